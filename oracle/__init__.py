@@ -1,0 +1,366 @@
+"""Plain FP64 CPU oracle of the line-by-line + ray-march path of
+arXiv 2604.11856 (Sec. 2.1 populations, Sec. 2.2.1 line emission /
+absorption / Voigt shape, Sec. 2.2.3 march and flux integral).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the package smoke check and the
+benchmark's CPU-baseline leg may import this package; the product path never
+does.  It shares no code with the GPU library: it reads the same seeded
+inputs (paper_2604_11856_amd.synth) and nothing else.
+
+The arithmetic lives in oracle.c (plain loops in double precision); this file
+only marshals arrays and lays out the geometry (rays, quadrature weights),
+citing the passage each step follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
+                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Species(C.Structure):
+    _fields_ = [("n_species", C.c_int), ("kind", _ip), ("mass", _dp),
+                ("lev_off", _i64p), ("lev_E", _dp), ("lev_g", _dp),
+                ("el_off", _i64p), ("el_T", _dp), ("el_g", _dp), ("el_Jmax", _ip),
+                ("vib_off", _i64p), ("vib_G", _dp), ("vib_B", _dp), ("vib_D", _dp)]
+
+
+class _Lines(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nu0", _dp), ("A", _dp), ("Eu_ev", _dp), ("Eu_rot", _dp),
+                ("El_ev", _dp), ("El_rot", _dp), ("gu", _dp), ("gl", _dp), ("species", _i32p)]
+
+
+class _Cells(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_species", C.c_int), ("T_tr", _dp), ("T_v", _dp),
+                ("N", _dp), ("n_e", _dp)]
+
+
+class _Pair(C.Structure):
+    _fields_ = [("Nu", C.c_double), ("Nl", C.c_double), ("S_eta", C.c_double),
+                ("B_line", C.c_double), ("gG", C.c_double), ("gL", C.c_double),
+                ("gV", C.c_double), ("klo", C.c_int64), ("khi", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        d, i64 = C.c_double, C.c_int64
+        sig = {
+            "orc_c2": (d, []),
+            "orc_partition_atom": (d, [i64, _dp, _dp, d]),
+            "orc_partition": (d, [C.POINTER(_Species), C.c_int, d, d]),
+            "orc_level_population": (d, [d, d, d, d, d, d, d]),
+            "orc_doppler_hwhm": (d, [d, d, d]),
+            "orc_lorentz_hwhm": (d, [d, d]),
+            "orc_voigt_hwhm": (d, [d, d]),
+            "orc_voigt_profile": (d, [d, d, d]),
+            "orc_window": (None, [d, d, d, d, i64, _i64p, _i64p]),
+            "orc_grid_offset": (d, [d, d, i64, d]),
+            "orc_planck": (d, [d, d]),
+            "orc_line_pair": (None, [C.POINTER(_Species), C.POINTER(_Lines), i64, d, d, d, d, d,
+                                     d, d, i64, C.POINTER(_Pair)]),
+            "orc_coeffs": (i64, [C.POINTER(_Species), C.POINTER(_Lines), C.POINTER(_Cells),
+                                 d, d, i64, i64, _i64p, _dp, _dp, C.c_int]),
+            "orc_coeffs_bruteforce": (None, [C.POINTER(_Species), C.POINTER(_Lines),
+                                             C.POINTER(_Cells), d, d, i64, _dp, _dp]),
+            "orc_march": (None, [i64, _i64p, _dp, i64, _dp, _dp, _dp, _dp]),
+            "orc_axi_segments": (i64, [C.c_int, C.c_int, d, d, d, d, d, i64, _i64p, _dp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+# ---------------------------------------------------------------------------
+# marshalling of the seeded inputs
+# ---------------------------------------------------------------------------
+
+class SpeciesTable:
+    """Flattened level tables of a species list (keeps the arrays alive)."""
+
+    def __init__(self, species):
+        S = len(species)
+        self.kind = np.array([s.kind for s in species], np.int32)
+        self.mass = np.array([s.mass for s in species], np.float64)
+        lev_E, lev_g, lev_off = [], [], [0]
+        el_T, el_g, el_J, el_off = [], [], [], [0]
+        vib_G, vib_B, vib_D, vib_off = [], [], [], [0]
+        for s in species:
+            lev_E.append(np.asarray(s.level_E, np.float64))
+            lev_g.append(np.asarray(s.level_g, np.float64))
+            lev_off.append(lev_off[-1] + len(s.level_E))
+            pos = 0
+            for e in range(len(s.el_T)):
+                nv = int(s.el_nv[e])
+                el_T.append(s.el_T[e]); el_g.append(s.el_g[e]); el_J.append(int(s.el_Jmax[e]))
+                vib_G.append(s.vib_G[pos:pos + nv]); vib_B.append(s.vib_B[pos:pos + nv])
+                vib_D.append(s.vib_D[pos:pos + nv])
+                vib_off.append(vib_off[-1] + nv)
+                pos += nv
+            el_off.append(el_off[-1] + len(s.el_T))
+        cat = lambda xs: np.ascontiguousarray(np.concatenate(xs) if xs else np.zeros(1), np.float64)
+        self.lev_E, self.lev_g = cat(lev_E + [np.zeros(1)]), cat(lev_g + [np.zeros(1)])
+        self.lev_off = np.array(lev_off, np.int64)
+        self.el_T = np.array(el_T + [0.0], np.float64)
+        self.el_g = np.array(el_g + [0.0], np.float64)
+        self.el_J = np.array(el_J + [0], np.int32)
+        self.el_off = np.array(el_off, np.int64)
+        self.vib_G = cat(vib_G + [np.zeros(1)])
+        self.vib_B = cat(vib_B + [np.zeros(1)])
+        self.vib_D = cat(vib_D + [np.zeros(1)])
+        self.vib_off = np.array(vib_off, np.int64)
+        self.s = _Species(S, _p(self.kind, _ip), _p(self.mass), _p(self.lev_off, _i64p),
+                          _p(self.lev_E), _p(self.lev_g), _p(self.el_off, _i64p), _p(self.el_T),
+                          _p(self.el_g), _p(self.el_J, _ip), _p(self.vib_off, _i64p),
+                          _p(self.vib_G), _p(self.vib_B), _p(self.vib_D))
+
+
+class LineTable:
+    def __init__(self, lines):
+        if lines.n > 1 and np.any(np.diff(lines.nu0) < 0):
+            raise ValueError("oracle expects lines sorted by nu0")
+        self.a = {f: np.ascontiguousarray(getattr(lines, f), np.float64)
+                  for f in ("nu0", "A", "Eu_ev", "Eu_rot", "El_ev", "El_rot", "gu", "gl")}
+        self.sp = np.ascontiguousarray(lines.species, np.int32)
+        a = self.a
+        self.s = _Lines(lines.n, _p(a["nu0"]), _p(a["A"]), _p(a["Eu_ev"]), _p(a["Eu_rot"]),
+                        _p(a["El_ev"]), _p(a["El_rot"]), _p(a["gu"]), _p(a["gl"]),
+                        _p(self.sp, _i32p))
+
+
+class CellTable:
+    def __init__(self, cells):
+        self.T_tr = np.ascontiguousarray(cells.T_tr, np.float64)
+        self.T_v = np.ascontiguousarray(cells.T_v, np.float64)
+        self.N = np.ascontiguousarray(cells.N, np.float64)
+        self.n_e = np.ascontiguousarray(cells.n_e, np.float64)
+        self.s = _Cells(self.T_tr.shape[0], self.N.shape[1], _p(self.T_tr), _p(self.T_v),
+                        _p(self.N), _p(self.n_e))
+
+
+# ---------------------------------------------------------------------------
+# scalar functions (Sec. 2.1, 2.2.1)
+# ---------------------------------------------------------------------------
+
+def c2() -> float:
+    return lib().orc_c2()
+
+
+def partition(species, s: int, Tv: float, Ttr: float) -> float:
+    t = SpeciesTable(species)
+    return lib().orc_partition(C.byref(t.s), s, Tv, Ttr)
+
+
+def level_population(N, Q, g, E_ev, E_rot, Tv, Ttr) -> float:
+    return lib().orc_level_population(N, Q, g, E_ev, E_rot, Tv, Ttr)
+
+
+def doppler_hwhm(nu0, Ttr, M) -> float:
+    return lib().orc_doppler_hwhm(nu0, Ttr, M)
+
+
+def lorentz_hwhm(ne, Tv) -> float:
+    return lib().orc_lorentz_hwhm(ne, Tv)
+
+
+def voigt_hwhm(gL, gG) -> float:
+    return lib().orc_voigt_hwhm(gL, gG)
+
+
+def voigt_profile(delta, gV, gL):
+    f = lib().orc_voigt_profile
+    d = np.atleast_1d(np.asarray(delta, np.float64))
+    return np.array([f(float(x), gV, gL) for x in d]) if d.size > 1 else f(float(d[0]), gV, gL)
+
+
+def window(nu0, gV, nu_min, h, n_points) -> Tuple[int, int]:
+    lo, hi = C.c_int64(), C.c_int64()
+    lib().orc_window(nu0, gV, nu_min, h, n_points, C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
+
+
+def grid_offset(nu_min, h, k, nu0) -> float:
+    return lib().orc_grid_offset(nu_min, h, int(k), nu0)
+
+
+def planck(nu, T) -> float:
+    return lib().orc_planck(nu, T)
+
+
+def line_pair(species, lines, i, Ttr, Tv, ne, N_s, Q_s, grid):
+    """Per-(cell, line) quantities: populations, S_eta, B_line, widths, window."""
+    st, lt = SpeciesTable(species), LineTable(lines)
+    p = _Pair()
+    h = grid_step(grid)
+    lib().orc_line_pair(C.byref(st.s), C.byref(lt.s), int(i), Ttr, Tv, ne, N_s, Q_s,
+                        grid.nu_min, h, grid.n_points, C.byref(p))
+    return {f: getattr(p, f) for f, _ in _Pair._fields_}
+
+
+def grid_step(grid) -> float:
+    return (grid.nu_max - grid.nu_min) / (grid.n_points - 1)
+
+
+# ---------------------------------------------------------------------------
+# eta / kappa (Sec. 2.2.1) for all cells at grid indices ks
+# ---------------------------------------------------------------------------
+
+def coeffs(species, lines, cells, grid, ks: Optional[np.ndarray] = None, threads: int = 0):
+    """Returns (eta [n_cells, n_k], kappa [n_cells, n_k], n_terms)."""
+    if ks is None:
+        ks = np.arange(grid.n_points, dtype=np.int64)
+    ks = np.ascontiguousarray(ks, np.int64)
+    st, lt, ct = SpeciesTable(species), LineTable(lines), CellTable(cells)
+    eta = np.zeros((cells.n, ks.size))
+    kap = np.zeros((cells.n, ks.size))
+    n = lib().orc_coeffs(C.byref(st.s), C.byref(lt.s), C.byref(ct.s), grid.nu_min, grid.nu_max,
+                         grid.n_points, ks.size, _p(ks, _i64p), _p(eta), _p(kap), int(threads))
+    return eta, kap, n
+
+
+def coeffs_bruteforce(species, lines, cells, grid):
+    st, lt, ct = SpeciesTable(species), LineTable(lines), CellTable(cells)
+    eta = np.zeros((cells.n, grid.n_points))
+    kap = np.zeros((cells.n, grid.n_points))
+    lib().orc_coeffs_bruteforce(C.byref(st.s), C.byref(lt.s), C.byref(ct.s), grid.nu_min,
+                                grid.nu_max, grid.n_points, _p(eta), _p(kap))
+    return eta, kap
+
+
+# ---------------------------------------------------------------------------
+# rays and quadrature (Sec. 2.2.3)
+# ---------------------------------------------------------------------------
+
+def gauss_legendre_01(n: int):
+    """Gauss-Legendre nodes and weights on [0, 1] (weights sum to 1)."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def slab_rays(geom):
+    """Rays of a 1-D slab seen from the wall: the wall-normal ray, then one
+    ray per Gauss-Legendre node mu_i (path length dx / mu_i per cell).
+    Returns (list of (cells, ds), mu, W) with cells ordered far -> wall."""
+    n = geom.dx.shape[0]
+    cells = np.arange(n, dtype=np.int64)
+    rays = [(cells, np.asarray(geom.dx, np.float64).copy())]
+    mu, W = (np.zeros(0), np.zeros(0))
+    if geom.n_mu > 0:
+        mu, W = gauss_legendre_01(geom.n_mu)
+        for m in mu:
+            rays.append((cells, np.asarray(geom.dx, np.float64) / m))
+    return rays, mu, W
+
+
+def axi_ray(geom, rw: float, mu: float, phi: float):
+    cap = geom.nx + 2 * geom.nr + 8
+    cell = np.zeros(cap, np.int64)
+    ds = np.zeros(cap)
+    n = lib().orc_axi_segments(geom.nx, geom.nr, geom.Lx, geom.R, rw, mu, phi, cap,
+                               _p(cell, _i64p), _p(ds))
+    if n < 0:
+        raise RuntimeError("segment capacity exceeded")
+    return cell[:n].copy(), ds[:n].copy()
+
+
+def axi_rays(geom, wall_index: int):
+    """Rays of one wall point: mu_i Gauss-Legendre on [0, 1] (outer),
+    phi_j = (j + 1/2) 2 pi / n_phi (inner).  Returns (rays, weights) with
+    weight W_i mu_i 2 pi / n_phi for the flux integral of I cos(theta) dOmega."""
+    mu, W = gauss_legendre_01(geom.n_mu)
+    rw = float(geom.wall_r[wall_index])
+    rays, wts = [], []
+    for i in range(geom.n_mu):
+        for j in range(geom.n_phi):
+            phi = (j + 0.5) * 2.0 * np.pi / geom.n_phi
+            rays.append(axi_ray(geom, rw, mu[i], phi))
+            wts.append(W[i] * mu[i] * 2.0 * np.pi / geom.n_phi)
+    return rays, np.array(wts)
+
+
+def march(cells_idx, ds, eta, kappa, I_far=None):
+    """I at the target for every column of eta/kappa [n_cells, n_k]."""
+    eta = np.ascontiguousarray(eta, np.float64)
+    kappa = np.ascontiguousarray(kappa, np.float64)
+    cells_idx = np.ascontiguousarray(cells_idx, np.int64)
+    ds = np.ascontiguousarray(ds, np.float64)
+    nk = eta.shape[1]
+    out = np.zeros(nk)
+    far = None if I_far is None else _p(np.ascontiguousarray(I_far, np.float64))
+    lib().orc_march(cells_idx.size, _p(cells_idx, _i64p), _p(ds), nk, _p(eta), _p(kappa),
+                    far, _p(out))
+    return out
+
+
+def trapezoid_weights(grid, ks=None):
+    """Spectral trapezoid weights by global grid index: h/2 at both ends, h inside."""
+    h = grid_step(grid)
+    ks = np.arange(grid.n_points) if ks is None else np.asarray(ks)
+    w = np.full(ks.shape, h)
+    w[(ks == 0) | (ks == grid.n_points - 1)] = 0.5 * h
+    return w
+
+
+def solve_slab(wl, ks=None, threads: int = 0):
+    """Whole path for a slab workload: eta/kappa at ks, I per ray, spectral
+    integral per ray (trapezoid over ks; exact when ks is the full grid) and
+    the tangent-slab flux q = 2 pi sum_i W_i mu_i I_int(mu_i)."""
+    eta, kap, n_terms = coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks, threads)
+    rays, mu, W = slab_rays(wl.geometry)
+    I = np.stack([march(c, d, eta, kap) for c, d in rays])
+    w = trapezoid_weights(wl.grid, ks)
+    I_int = I @ w
+    q = 2.0 * np.pi * float(np.sum(W * mu * I_int[1:])) if len(mu) else None
+    return dict(eta=eta, kappa=kap, I=I, I_int=I_int, q=q, n_terms=n_terms)
+
+
+def solve_axi(wl, wall_indices: Sequence[int], ks=None, threads: int = 0):
+    """Axisymmetric workload at the given wall points: per-point spectral
+    flux q_k = sum_rays w_ray I_ray(k) and, over ks, q = sum_k w_k q_k."""
+    eta, kap, n_terms = coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks, threads)
+    w = trapezoid_weights(wl.grid, ks)
+    out = []
+    for wi in wall_indices:
+        rays, wts = axi_rays(wl.geometry, wi)
+        qk = np.zeros(eta.shape[1])
+        I_int = []
+        for (c, d), wt in zip(rays, wts):
+            I = march(c, d, eta, kap)
+            qk += wt * I
+            I_int.append(float(I @ w))
+        out.append(dict(q_k=qk, q=float(qk @ w), I_int=np.array(I_int)))
+    return dict(eta=eta, kappa=kap, walls=out, n_terms=n_terms)

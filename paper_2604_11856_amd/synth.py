@@ -1,0 +1,498 @@
+"""Seeded synthetic inputs: species tables, line lists, cell states, spectral
+grids and ray geometry shaped like the workloads of the line-by-line +
+ray-tracing radiation method (arXiv 2604.11856, Sec. 2.2 and Sec. 3.2).
+
+This module draws random numbers and lays out data; it holds none of the
+method's arithmetic (no populations, widths, profiles, march or quadrature).
+The level energies of the synthetic rovibronic systems follow the term-value
+forms of Sec. 2.2.2 (vibrational ladder, rigid-rotor J(J+1) rotation) because
+those define what the synthetic line list *is*; the partition functions built
+from these tables are computed elsewhere.
+
+Both the oracle tests and the GPU path read inputs from here and nothing else
+is shared between them.
+
+Units: wavenumbers and energies in cm^-1, temperatures in K, number densities
+in cm^-3, lengths in cm, masses in g/mol.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional
+
+import numpy as np
+
+EV_CM = 8065.543937  # 1 eV in cm^-1 (CODATA)
+
+# Species order used by every multi-species workload (11-species air).
+AIR11 = ["N2", "O2", "NO", "N", "O", "N2+", "O2+", "NO+", "N+", "O+", "e-"]
+AIR11_MASS = {"N2": 28.0, "O2": 32.0, "NO": 30.0, "N": 14.0, "O": 16.0,
+              "N2+": 28.0, "O2+": 32.0, "NO+": 30.0, "N+": 14.0, "O+": 16.0,
+              "e-": 5.48579909e-4}
+ION_SPECIES = ["N2+", "O2+", "NO+", "N+", "O+"]
+
+KIND_NONE, KIND_ATOM, KIND_MOLECULE = 0, 1, 2
+
+
+@dataclasses.dataclass
+class Species:
+    """One species' level table.
+
+    kind: KIND_ATOM (electronic levels only), KIND_MOLECULE (electronic x
+    vibrational x rotational ladder) or KIND_NONE (no radiating levels).
+    Atoms: level_E[n], level_g[n].
+    Molecules: per electronic state e: el_T[e], el_g[e], el_nv[e] vibrational
+    levels with term values vib_G and rotational constants vib_B, vib_D
+    (concatenated over e, el_nv[e] entries each), J = 0..el_Jmax[e].
+    """
+    name: str
+    kind: int
+    mass: float
+    level_E: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
+    level_g: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
+    el_T: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
+    el_g: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
+    el_nv: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0, np.int32))
+    el_Jmax: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0, np.int32))
+    vib_G: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
+    vib_B: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
+    vib_D: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
+
+
+@dataclasses.dataclass
+class Lines:
+    """Line list, SoA, sorted by nu0 ascending (stable)."""
+    nu0: np.ndarray
+    A: np.ndarray
+    Eu_ev: np.ndarray
+    Eu_rot: np.ndarray
+    El_ev: np.ndarray
+    El_rot: np.ndarray
+    gu: np.ndarray
+    gl: np.ndarray
+    species: np.ndarray  # int32 index into the species table
+
+    @property
+    def n(self) -> int:
+        return int(self.nu0.shape[0])
+
+    def subset(self, idx) -> "Lines":
+        return Lines(*(getattr(self, f.name)[idx] for f in dataclasses.fields(self)))
+
+
+@dataclasses.dataclass
+class Cells:
+    T_tr: np.ndarray      # [n_cells]
+    T_v: np.ndarray       # [n_cells]  (electron-electronic = vibrational temperature)
+    N: np.ndarray         # [n_cells, n_species]
+    n_e: np.ndarray       # [n_cells]
+
+    @property
+    def n(self) -> int:
+        return int(self.T_tr.shape[0])
+
+
+@dataclasses.dataclass
+class Grid:
+    nu_min: float
+    nu_max: float
+    n_points: int
+    band_points: int
+
+    @property
+    def n_bands(self) -> int:
+        return (self.n_points + self.band_points - 1) // self.band_points
+
+
+@dataclasses.dataclass
+class SlabGeometry:
+    """1-D slab: cells ordered from the far (free) boundary to the wall."""
+    dx: np.ndarray
+    n_mu: int          # 0: only the wall-normal ray; else normal ray + n_mu Gauss-Legendre rays
+
+
+@dataclasses.dataclass
+class AxiGeometry:
+    """Axisymmetric structured grid x in [0, Lx], r in [0, R], nx x nr uniform
+    cells, cell index c = ix * nr + ir.  Wall is the plane x = 0, wall points at
+    radii wall_r; rays leave the wall into x > 0."""
+    nx: int
+    nr: int
+    Lx: float
+    R: float
+    wall_r: np.ndarray
+    n_mu: int
+    n_phi: int
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    species: List[Species]
+    lines: Lines
+    cells: Cells
+    grid: Grid
+    geometry: object
+    meta: Dict = dataclasses.field(default_factory=dict)
+
+
+# --------------------------------------------------------------------------
+# building blocks
+# --------------------------------------------------------------------------
+
+def _log_uniform(rng, lo, hi, size):
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), size))
+
+
+def atom_species(rng, name: str, n_levels: int = 20) -> Species:
+    """Atom with a seeded level table: level 0 is the ground state (E = 0);
+    the others have E ~ U(0.1, 14) eV.  Degeneracies g ~ U{2..12}."""
+    E = np.empty(n_levels)
+    E[0] = 0.0
+    E[1:] = np.sort(rng.uniform(0.1, 14.0, n_levels - 1)) * EV_CM
+    g = rng.integers(2, 13, n_levels).astype(np.float64)
+    return Species(name, KIND_ATOM, AIR11_MASS.get(name, 14.0), level_E=E, level_g=g)
+
+
+def none_species(name: str) -> Species:
+    return Species(name, KIND_NONE, AIR11_MASS.get(name, 1.0))
+
+
+def _vib_ladder(omega, omega_x, nv):
+    v = np.arange(nv, dtype=np.float64)
+    return omega * (v + 0.5) - omega_x * (v + 0.5) ** 2
+
+
+def molecule_species(rng, name: str, n_v: int, J_max: int = 151) -> Species:
+    """Diatomic with two electronic states (ground 'X' and one excited upper
+    state), each with an n_v-level anharmonic vibrational ladder and one
+    rigid-rotor constant B ~ U(1.5, 2.0) cm^-1 (D = 0)."""
+    g_ground = {"N2": 1.0, "N2+": 2.0, "NO": 4.0, "O2": 3.0}.get(name, 1.0)
+    T_up = rng.uniform(20000.0, 60000.0)
+    g_up = float(rng.integers(1, 7))
+    om = rng.uniform(1000.0, 2500.0, 2)
+    G_lo = _vib_ladder(om[0], om[0] / 200.0, n_v)
+    G_up = _vib_ladder(om[1], om[1] / 200.0, n_v)
+    B = rng.uniform(1.5, 2.0, 2)
+    return Species(
+        name, KIND_MOLECULE, AIR11_MASS.get(name, 28.0),
+        el_T=np.array([0.0, T_up]), el_g=np.array([g_ground, g_up]),
+        el_nv=np.array([n_v, n_v], np.int32), el_Jmax=np.array([J_max, J_max], np.int32),
+        vib_G=np.concatenate([G_lo, G_up]),
+        vib_B=np.concatenate([np.full(n_v, B[0]), np.full(n_v, B[1])]),
+        vib_D=np.zeros(2 * n_v))
+
+
+def atomic_lines(rng, sp_index: int, n: int, nu_lo: float, nu_hi: float,
+                 Eu_lo_ev: float = 10.0, Eu_hi_ev: float = 14.0) -> Dict[str, np.ndarray]:
+    """n synthetic atomic lines: nu0 ~ U(nu_lo, nu_hi), A ~ logU(1e4, 1e9),
+    E_u ~ U(10, 14) eV, E_l = E_u - nu0, g_u, g_l ~ U{2..12}.  A line whose
+    E_l would be negative has its E_u redrawn from U(nu0, 14 eV)."""
+    nu0 = rng.uniform(nu_lo, nu_hi, n)
+    A = _log_uniform(rng, 1e4, 1e9, n)
+    Eu = rng.uniform(Eu_lo_ev, Eu_hi_ev, n) * EV_CM
+    bad = Eu - nu0 < 0.0
+    if bad.any():
+        Eu[bad] = rng.uniform(nu0[bad], Eu_hi_ev * EV_CM)
+    El = Eu - nu0
+    gu = rng.integers(2, 13, n).astype(np.float64)
+    gl = rng.integers(2, 13, n).astype(np.float64)
+    z = np.zeros(n)
+    return dict(nu0=nu0, A=A, Eu_ev=Eu, Eu_rot=z.copy(), El_ev=El, El_rot=z.copy(),
+                gu=gu, gl=gl, species=np.full(n, sp_index, np.int32))
+
+
+def rovib_lines(rng, sp: Species, sp_index: int, n_target: int,
+                nu_min: float, nu_max: float) -> Dict[str, np.ndarray]:
+    """Synthetic rovibronic system upper(e=1) -> lower(e=0): P and R branches,
+    J'' = 0..150, nu = nu_band(v', v'') + B'J'(J'+1) - B''J''(J''+1),
+    A = A_band S / (2J'+1) with S_P = J'+1, S_R = J' (Sigma-Sigma column of
+    the Hund (a) Hoenl-London table), A_band ~ logU(1e5, 1e8),
+    g = g_el (2J+1).  Lines outside [nu_min, nu_max] are rejected; (v', v'')
+    bands are added in a seeded order until n_target lines are collected."""
+    nv = int(sp.el_nv[0])
+    G_lo, G_up = sp.vib_G[:nv], sp.vib_G[nv:2 * nv]
+    B_lo, B_up = float(sp.vib_B[0]), float(sp.vib_B[nv])
+    T_up, g_lo_el, g_up_el = float(sp.el_T[1]), float(sp.el_g[0]), float(sp.el_g[1])
+    Jpp = np.arange(0, 151)
+    # P branch: J' = J'' - 1 (J'' >= 1); R branch: J' = J'' + 1
+    Jl = np.concatenate([Jpp[1:], Jpp]).astype(np.float64)
+    Ju = np.concatenate([Jpp[1:] - 1, Jpp + 1]).astype(np.float64)
+    n_P = Jpp.size - 1
+    S = np.where(np.arange(Ju.size) < n_P, Ju + 1.0, Ju)                 # P: J'+1 ; R: J'
+    Eu_rot = B_up * Ju * (Ju + 1.0)
+    El_rot = B_lo * Jl * (Jl + 1.0)
+    out = {k: [] for k in ("nu0", "A", "Eu_ev", "Eu_rot", "El_ev", "El_rot", "gu", "gl")}
+    pairs = [(a, b) for a in range(nv) for b in range(nv)]
+    order = rng.permutation(len(pairs))
+    count = 0
+    for pi in order:
+        vu, vl = pairs[pi]
+        Eu_ev = T_up + G_up[vu]
+        El_ev = G_lo[vl]
+        nu0 = (Eu_ev - El_ev) + (Eu_rot - El_rot)
+        keep = (nu0 >= nu_min) & (nu0 <= nu_max)
+        m = int(keep.sum())
+        if m == 0:
+            continue
+        A_band = _log_uniform(rng, 1e5, 1e8, 1)[0]
+        out["nu0"].append(nu0[keep])
+        out["A"].append(A_band * S[keep] / (2.0 * Ju[keep] + 1.0))
+        out["Eu_ev"].append(np.full(m, Eu_ev))
+        out["Eu_rot"].append(Eu_rot[keep])
+        out["El_ev"].append(np.full(m, El_ev))
+        out["El_rot"].append(El_rot[keep])
+        out["gu"].append(g_up_el * (2.0 * Ju[keep] + 1.0))
+        out["gl"].append(g_lo_el * (2.0 * Jl[keep] + 1.0))
+        count += m
+        if count >= n_target:
+            break
+    d = {k: np.concatenate(v)[:n_target] for k, v in out.items()}
+    d["species"] = np.full(d["nu0"].shape[0], sp_index, np.int32)
+    return d
+
+
+def merge_sorted(parts: List[Dict[str, np.ndarray]]) -> Lines:
+    d = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+    order = np.argsort(d["nu0"], kind="stable")
+    return Lines(**{k: np.ascontiguousarray(v[order]) for k, v in d.items()})
+
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+
+def slab_equilibrium(n_cells=64, dx=0.05, n_lines_per_species=1000, n_points=200_000,
+                     nu_min=5000.0, nu_max=80000.0, band_points=None, seed=11856,
+                     identical_cells=False, n_mu=0) -> Workload:
+    """Plain method, single 1-D tangent-slab line of sight: T_e = T_v = T_tr
+    ~ U(6000, 12000) K per cell, N and O atoms logU(1e15, 1e17) cm^-3, n_e
+    logU(1e15, 1e16) cm^-3; N and O lines with nu0 ~ U(5000, 80000) cm^-1;
+    uniform grid; one wall-normal ray."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    species = [atom_species(rng, "N"), atom_species(rng, "O")]
+    lines = merge_sorted([
+        atomic_lines(rng, 0, n_lines_per_species, nu_min, nu_max),
+        atomic_lines(rng, 1, n_lines_per_species, nu_min, nu_max)])
+    nc = 1 if identical_cells else n_cells
+    T = rng.uniform(6000.0, 12000.0, nc)
+    N = _log_uniform(rng, 1e15, 1e17, (nc, 2))
+    ne = _log_uniform(rng, 1e15, 1e16, nc)
+    if identical_cells:
+        T, N, ne = np.repeat(T, n_cells), np.repeat(N, n_cells, 0), np.repeat(ne, n_cells)
+    cells = Cells(T_tr=T.copy(), T_v=T.copy(), N=np.ascontiguousarray(N), n_e=ne)
+    grid = Grid(nu_min, nu_max, n_points, band_points or n_points)
+    geom = SlabGeometry(dx=np.full(n_cells, dx), n_mu=n_mu)
+    return Workload("slab-equilibrium", species, lines, cells, grid, geom,
+                    dict(seed=seed))
+
+
+def _air_species(rng, n_v: int, radiators=("N", "O", "N2", "N2+", "NO", "O2")) -> List[Species]:
+    sp = []
+    for name in AIR11:
+        if name in ("N", "O") and name in radiators:
+            sp.append(atom_species(rng, name))
+        elif name in ("N2", "N2+", "NO", "O2") and name in radiators:
+            sp.append(molecule_species(rng, name, n_v))
+        else:
+            sp.append(none_species(name))
+    return sp
+
+
+def _air_lines(rng, species, n_atomic, n_rovib, nu_min, nu_max) -> Lines:
+    parts = []
+    iN, iO = AIR11.index("N"), AIR11.index("O")
+    parts.append(atomic_lines(rng, iN, n_atomic // 2, nu_min, nu_max))
+    parts.append(atomic_lines(rng, iO, n_atomic - n_atomic // 2, nu_min, nu_max))
+    mols = ["N2", "N2+", "NO", "O2"]
+    for j, name in enumerate(mols):
+        n_t = n_rovib // 4 + (1 if j < n_rovib % 4 else 0)
+        if n_t:
+            idx = AIR11.index(name)
+            parts.append(rovib_lines(rng, species[idx], idx, n_t, nu_min, nu_max))
+    return merge_sorted(parts)
+
+
+def _fractions_to_N(f_mol, f_ion, N_tot):
+    """Split total density into the 11 species from molecule / ion fractions."""
+    n = f_mol.shape[0]
+    N = np.zeros((n, 11))
+    mol_split = {"N2": 0.70, "O2": 0.15, "NO": 0.12, "N2+": 0.02, "O2+": 0.005, "NO+": 0.005}
+    ion_split = {"N+": 0.7, "O+": 0.3}
+    f_atom = 1.0 - f_mol - f_ion
+    for k, w in mol_split.items():
+        N[:, AIR11.index(k)] = w * f_mol * N_tot
+    for k, w in ion_split.items():
+        N[:, AIR11.index(k)] = w * f_ion * N_tot
+    N[:, AIR11.index("N")] = 0.78 * f_atom * N_tot
+    N[:, AIR11.index("O")] = 0.22 * f_atom * N_tot
+    ne = sum(N[:, AIR11.index(k)] for k in ION_SPECIES)
+    N[:, AIR11.index("e-")] = ne
+    return N, ne
+
+
+def stagnation_line(n_cells=400, length=4.0, n_atomic=200_000, n_rovib=2_000_000,
+                    n_points=1 << 21, nu_min=1000.0, nu_max=100000.0, band_points=None,
+                    n_mu=16, n_v=41, seed=11857) -> Workload:
+    """1-D stagnation-line nonequilibrium case: shock at x = 0 (far, free
+    boundary), wall at x = length; T_tr = 1e4 + 2e4 exp(-x/0.4) relaxing,
+    T_v = max(500, 1e4 - 9500 exp(-x/0.6)) lagging, +-1% seeded noise;
+    11 species with molecules decaying and atoms/ions rising along x,
+    N_tot 2e16..8e16; n_e = sum of ion densities."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    species = _air_species(rng, n_v)
+    lines = _air_lines(rng, species, n_atomic, n_rovib, nu_min, nu_max)
+    dx = length / n_cells
+    x = (np.arange(n_cells) + 0.5) * dx * (4.0 / length)   # profile shape in 4 cm units
+    noise = lambda: 1.0 + rng.uniform(-0.01, 0.01, n_cells)
+    T_tr = (1e4 + 2e4 * np.exp(-x / 0.4)) * noise()
+    T_v = np.maximum(500.0, 1e4 - 9500.0 * np.exp(-x / 0.6)) * noise()
+    N_tot = 2e16 + 6e16 * (1.0 - np.exp(-x / 1.5))
+    f_mol = 0.7 * np.exp(-x / 0.3) + 0.005
+    f_ion = 1e-3 + 0.05 * (1.0 - np.exp(-x / 0.5))
+    N, ne = _fractions_to_N(f_mol, f_ion, N_tot)
+    cells = Cells(T_tr=T_tr, T_v=T_v, N=np.ascontiguousarray(N), n_e=ne)
+    grid = Grid(nu_min, nu_max, n_points, band_points or n_points)
+    geom = SlabGeometry(dx=np.full(n_cells, dx), n_mu=n_mu)
+    return Workload("stagnation-line", species, lines, cells, grid, geom, dict(seed=seed))
+
+
+def _smooth_field(rng, X, Rr, Lx, R, n_bumps=6):
+    """Seeded smooth field in [0, 1] on the (x, r) plane: normalised sum of
+    Gaussian bumps."""
+    f = np.zeros_like(X)
+    for _ in range(n_bumps):
+        x0, r0 = rng.uniform(0, Lx), rng.uniform(0, R)
+        sx, sr = rng.uniform(0.15, 0.5) * Lx, rng.uniform(0.15, 0.5) * R
+        f += rng.uniform(0.3, 1.0) * np.exp(-((X - x0) / sx) ** 2 - ((Rr - r0) / sr) ** 2)
+    f -= f.min()
+    return f / max(f.max(), 1e-300)
+
+
+def axisymmetric(nx=256, nr=128, Lx=100.0, R=50.0, n_atomic=250_000, n_rovib=750_000,
+                 n_points=1 << 20, nu_min=1000.0, nu_max=100000.0, band_points=65536,
+                 n_wall=64, wall_R=30.0, n_mu=16, n_phi=16, n_v=41, seed=11858) -> Workload:
+    """2-D axisymmetric afterbody: structured nx x nr cells over
+    [0, Lx] x [0, R] cm with smooth seeded T_tr in 3000..10000 K,
+    T_v = T_tr (1 + 0.3 h) with smooth h in [0, 1] (T_v > T_tr in the wake),
+    N, O 1e14..1e16, molecules 1e13..1e16, ions / e- 1e11..1e15 cm^-3."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    species = _air_species(rng, n_v)
+    lines = _air_lines(rng, species, n_atomic, n_rovib, nu_min, nu_max)
+    xc = (np.arange(nx) + 0.5) * Lx / nx
+    rc = (np.arange(nr) + 0.5) * R / nr
+    X, Rr = np.meshgrid(xc, rc, indexing="ij")
+    s1 = _smooth_field(rng, X, Rr, Lx, R)
+    h = _smooth_field(rng, X, Rr, Lx, R)
+    T_tr = 3000.0 + 7000.0 * s1
+    T_v = T_tr * (1.0 + 0.3 * h)
+    fa = _smooth_field(rng, X, Rr, Lx, R)
+    fm = _smooth_field(rng, X, Rr, Lx, R)
+    fi = _smooth_field(rng, X, Rr, Lx, R)
+    N = np.zeros((nx * nr, 11))
+    atoms = 10.0 ** (14.0 + 2.0 * fa.ravel())
+    mols = 10.0 ** (13.0 + 3.0 * fm.ravel())
+    ions = 10.0 ** (11.0 + 4.0 * fi.ravel())
+    N[:, AIR11.index("N")] = 0.78 * atoms
+    N[:, AIR11.index("O")] = 0.22 * atoms
+    for k, w in {"N2": 0.6, "O2": 0.15, "NO": 0.2, "N2+": 0.05}.items():
+        N[:, AIR11.index(k)] = w * mols
+    for k, w in {"O2+": 0.05, "NO+": 0.15, "N+": 0.5, "O+": 0.3}.items():
+        N[:, AIR11.index(k)] = w * ions
+    ne = sum(N[:, AIR11.index(k)] for k in ION_SPECIES)
+    N[:, AIR11.index("e-")] = ne
+    cells = Cells(T_tr=T_tr.ravel().copy(), T_v=T_v.ravel().copy(),
+                  N=np.ascontiguousarray(N), n_e=ne.copy())
+    grid = Grid(nu_min, nu_max, n_points, band_points)
+    wall_r = (np.arange(n_wall) + 0.5) * wall_R / n_wall
+    geom = AxiGeometry(nx, nr, Lx, R, wall_r, n_mu, n_phi)
+    return Workload("axisymmetric", species, lines, cells, grid, geom, dict(seed=seed))
+
+
+# Named workloads at full size -------------------------------------------------
+
+def config_slab() -> Workload:
+    return slab_equilibrium()
+
+
+def config_stagnation() -> Workload:
+    return stagnation_line()
+
+
+def config_axi() -> Workload:
+    return axisymmetric()
+
+
+def config_axi_large() -> Workload:
+    return axisymmetric(nx=512, nr=256, n_atomic=1_000_000, n_rovib=3_000_000,
+                        n_points=1 << 22, band_points=131072, n_wall=256,
+                        n_mu=32, n_phi=32, seed=11860)
+
+
+# Serving requests -------------------------------------------------------------
+
+@dataclasses.dataclass
+class LosRequest:
+    cells: Cells
+    ds: np.ndarray           # per-cell path length, far -> observer order
+    k_first: int             # first grid index of the spectral window
+    n_window: int            # number of grid points in the window
+    species_mask: int        # bit s set: species s radiates in this request
+    arrival: float = 0.0     # seconds from stream start
+
+
+def serving_requests(n_requests: int, n_points: int, rate_hz: float = 0.0,
+                     min_cells=16, max_cells=2048, min_win=10_000, max_win=1_000_000,
+                     seed=11859) -> List[LosRequest]:
+    """Line-of-sight requests: cell count logU[16, 2048], ds ~ U(0.01, 0.1) cm,
+    T_tr ~ U(3000, 30000) and T_v ~ U(3000, 15000) K varying smoothly along the
+    LOS, 11 species, a random non-empty radiating subset of
+    {N, O, N2, O2, NO, N2+}, window length logU[1e4, 1e6] points at a uniform
+    start; Poisson arrivals at rate_hz (0: all at t = 0)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    reqs = []
+    t = 0.0
+    cand = [AIR11.index(s) for s in ("N", "O", "N2", "O2", "NO", "N2+")]
+    for _ in range(n_requests):
+        nc = int(np.round(_log_uniform(rng, min_cells, max_cells, 1)[0]))
+        nw = int(np.round(_log_uniform(rng, min_win, max_win, 1)[0]))
+        nw = min(nw, n_points)
+        k0 = int(rng.integers(0, n_points - nw + 1))
+        u = np.linspace(0.0, 1.0, nc)
+        def smooth(lo, hi):
+            a = rng.uniform(lo, hi, 3)
+            return a[0] + (a[1] - a[0]) * u + (a[2] - 0.5 * (a[0] + a[1])) * 4 * u * (1 - u)
+        T_tr = np.clip(smooth(3000.0, 30000.0), 3000.0, 30000.0)
+        T_v = np.clip(smooth(3000.0, 15000.0), 3000.0, 15000.0)
+        f_mol = np.clip(smooth(0.0, 0.7), 0.0, 0.7)
+        f_ion = np.clip(smooth(1e-4, 0.05), 1e-4, 0.05)
+        N_tot = np.clip(smooth(1e16, 1e17), 1e16, 1e17)
+        N, ne = _fractions_to_N(f_mol, f_ion, N_tot)
+        mask = 0
+        while mask == 0:
+            pick = rng.random(len(cand)) < 0.5
+            for s, p in zip(cand, pick):
+                if p:
+                    mask |= 1 << s
+        if rate_hz > 0:
+            t += rng.exponential(1.0 / rate_hz)
+        reqs.append(LosRequest(Cells(T_tr, T_v, np.ascontiguousarray(N), ne),
+                               rng.uniform(0.01, 0.1, nc), k0, nw, mask, t))
+    return reqs
+
+
+def sample_points(grid: Grid, lines: Lines, n: int, seed: int = 7, cluster: int = 32) -> np.ndarray:
+    """Seeded sorted unique grid indices for sampled comparisons: half in
+    uniformly placed clusters of `cluster` consecutive points, half in
+    clusters centred on the strongest (largest A) line centres."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = (grid.nu_max - grid.nu_min) / (grid.n_points - 1)
+    n_cl = max(1, n // cluster)
+    starts = list(rng.integers(0, max(1, grid.n_points - cluster), (n_cl + 1) // 2))
+    strong = np.argsort(lines.A)[::-1][: max(1, n_cl // 2) * 4]
+    pick = rng.choice(strong, size=n_cl // 2, replace=False) if n_cl // 2 else []
+    for i in pick:
+        kc = int(round((lines.nu0[i] - grid.nu_min) / h))
+        starts.append(min(max(0, kc - cluster // 2), max(0, grid.n_points - cluster)))
+    ks = np.unique(np.concatenate([np.arange(s, s + cluster) for s in starts]))
+    return ks[(ks >= 0) & (ks < grid.n_points)].astype(np.int64)

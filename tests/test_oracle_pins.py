@@ -1,0 +1,528 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks one oracle function against something other than itself:
+a limit that reduces to a textbook profile, a closed form, an invariant, a
+physical law written independently, or brute force on tiny inputs.  Together
+they are meant to catch a dropped term, a wrong sign, index or operand
+anywhere in the oracle's chain (populations -> widths -> profile -> window ->
+sum -> march -> quadrature -> geometry).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.optimize as so
+import scipy.special as ss
+
+import oracle as O
+from paper_2604_11856_amd import synth
+
+# Textbook constants, written here independently of the oracle (CODATA, CGS)
+H = 6.62607015e-27
+CL = 2.99792458e10
+KB = 1.380649e-16
+AMU = 1.66053906660e-24
+SIGMA_SB = 5.670374419e-5  # erg cm^-2 s^-1 K^-4
+
+
+def planck_textbook(nu, T):
+    """Planck spectral radiance per cm^-1, W cm^-2 sr^-1 (cm^-1)^-1."""
+    return 1e-7 * 2 * H * CL**2 * nu**3 / math.expm1(H * CL * nu / (KB * T))
+
+
+# ----------------------------------------------------------------------------
+# Voigt line shape (Sec. 2.2.1, Whiting profile and Olivero width)
+# ----------------------------------------------------------------------------
+
+def test_voigt_lorentz_limit():
+    """gamma_G = 0: width fit returns gamma_L and the profile is the exact
+    Lorentzian times pi/3.14 (the fit's 1.065+0.447+0.058 = 1.57)."""
+    gL = 0.7
+    gV = O.voigt_hwhm(gL, 0.0)
+    assert gV == pytest.approx(gL, rel=1e-15)
+    for d in [0.0, 0.3, 1.7, 25.0, 69.0]:
+        L = gL / math.pi / (gL**2 + d**2)
+        assert O.voigt_profile(d, gV, gL) / L == pytest.approx(math.pi / 3.14, rel=1e-13)
+
+
+def test_voigt_gauss_limit():
+    """gamma_L = 0: width fit returns gamma_G and the profile is the
+    Gaussian of HWHM gamma_G to the fit's own constants (2.772 ~ 4 ln 2,
+    1.065 ~ sqrt(pi/ln 2)/2): ratio within [0.99949, 1.00083] inside 3 HWHM."""
+    gG = 0.4
+    gV = O.voigt_hwhm(0.0, gG)
+    assert gV == pytest.approx(gG, rel=1e-15)
+    r = []
+    for d in np.linspace(0, 3 * gG, 301):
+        G = math.sqrt(math.log(2) / math.pi) / gG * math.exp(-math.log(2) * d * d / gG**2)
+        r.append(O.voigt_profile(d, gV, 0.0) / G)
+    assert 0.99949 < min(r) and max(r) < 1.00083
+
+
+def _exact_voigt_hwhm(gL, gG):
+    sigma = gG / math.sqrt(2 * math.log(2))
+    f0 = ss.voigt_profile(0.0, sigma, gL)
+    return so.brentq(lambda x: ss.voigt_profile(x, sigma, gL) - f0 / 2, 1e-12, 10 * (gL + gG),
+                     xtol=1e-15, rtol=1e-14)
+
+
+def test_voigt_width_fit_vs_exact_voigt():
+    """The Olivero-type width fit matches the exact Voigt HWHM (Faddeeva
+    profile, scipy) to 2e-4 across the Gauss-Lorentz range."""
+    for t in np.linspace(0.01, 0.99, 25):
+        gL, gG = 2.0 * t, 2.0 * (1 - t)
+        assert O.voigt_hwhm(gL, gG) / _exact_voigt_hwhm(gL, gG) - 1 == pytest.approx(0, abs=2e-4)
+
+
+def test_voigt_width_bracket_at_most_one():
+    """gamma_V <= gamma_L + gamma_G on the whole range (the oracle's line-skip
+    bound relies on it); equality at the pure limits."""
+    for d in np.linspace(-1, 1, 4001):
+        gL, gG = 0.5 * (1 + d), 0.5 * (1 - d)
+        assert O.voigt_hwhm(gL, gG) <= (gL + gG) * (1 + 1e-15)
+
+
+def _norm(r, cut=None):
+    gV, gL = 1.0, r
+    f = lambda d: O.voigt_profile(d, gV, gL)
+    if cut is None:
+        return 2 * (si.quad(f, 0, 50, limit=500)[0] + si.quad(f, 50, np.inf, limit=500)[0])
+    return 2 * si.quad(f, 0, cut, limit=2000, points=[1, 5, 20])[0]
+
+
+def test_voigt_normalisation():
+    """The profile integrates to ~1 over the whole line (the fit's own
+    accuracy, [0.995, 1.0006]) and to [0.9915, 0.9997] within +-100 HWHM;
+    a sign flip of the 0.016 r(1-r) term moves it above 1.02."""
+    for r in np.linspace(0, 1, 11):
+        assert 0.995 < _norm(r) < 1.0006
+        assert 0.9915 < _norm(r, 100.0) < 0.9997
+
+
+def test_voigt_vs_exact_voigt():
+    """Within 5 HWHM the empirical profile is within 6% of the exact Voigt
+    profile of the same Gaussian and Lorentz widths."""
+    worst = 0.0
+    for t in np.linspace(0.05, 0.95, 10):
+        gL, gG = t, 1 - t
+        gV = O.voigt_hwhm(gL, gG)
+        sigma = gG / math.sqrt(2 * math.log(2))
+        for d in np.linspace(0, 5 * gV, 41):
+            worst = max(worst, abs(O.voigt_profile(d, gV, gL) / ss.voigt_profile(d, sigma, gL) - 1))
+    assert worst < 0.06
+
+
+def test_doppler_constant():
+    """(7.16233e-7/2) nu0 sqrt(T/M) is the Doppler HWHM
+    nu0 sqrt(2 k T ln2 / (m c^2)) with m = M amu, to the printed precision."""
+    for nu0, T, M in [(5000.0, 6000.0, 14.0), (80000.0, 30000.0, 16.0), (1e5, 500.0, 28.0)]:
+        exact = nu0 * math.sqrt(2 * KB * T * math.log(2) / (M * AMU * CL**2))
+        assert O.doppler_hwhm(nu0, T, M) == pytest.approx(exact, rel=1e-6)
+
+
+def test_lorentz_law():
+    """Stark law with a 1 cm^-1 reference width at N_e = 1e16, T = 1e4 K:
+    linear in N_e, T^0.33."""
+    assert O.lorentz_hwhm(1e16, 1e4) == pytest.approx(1.0, rel=1e-15)
+    assert O.lorentz_hwhm(3e15, 1e4) == pytest.approx(0.3, rel=1e-15)
+    assert O.lorentz_hwhm(1e16, 2e4) == pytest.approx(2**0.33, rel=1e-15)
+
+
+# ----------------------------------------------------------------------------
+# Populations (Sec. 2.1)
+# ----------------------------------------------------------------------------
+
+def _atom():
+    rng = np.random.Generator(np.random.PCG64(3))
+    return synth.atom_species(rng, "N")
+
+
+def test_partition_atom_limits_and_closure():
+    sp = _atom()
+    # T -> 0: only the ground state survives
+    assert O.partition([sp], 0, 50.0, 50.0) == pytest.approx(sp.level_g[0], rel=1e-12)
+    # T -> infinity: sum of degeneracies
+    assert O.partition([sp], 0, 1e12, 1e12) == pytest.approx(sp.level_g.sum(), rel=1e-5)
+    # populations of all levels add up to the species density
+    for T in [3000.0, 9000.0, 30000.0]:
+        Q = O.partition([sp], 0, T, T)
+        tot = sum(O.level_population(1e16, Q, g, E, 0.0, T, T) for E, g in zip(sp.level_E, sp.level_g))
+        assert tot == pytest.approx(1e16, rel=1e-13)
+
+
+def _molecule(nv=400, Jmax=4000, omega=1500.0, B=1.7, g=(1.0,), T_el=(0.0,), harmonic=True):
+    n_el = len(g)
+    G = np.concatenate([omega * (np.arange(nv) + 0.5)] * n_el)
+    if not harmonic:
+        G = G - np.concatenate([omega / 200 * (np.arange(nv) + 0.5)**2] * n_el)
+    return synth.Species("M", synth.KIND_MOLECULE, 28.0, el_T=np.array(T_el, float),
+                         el_g=np.array(g, float), el_nv=np.full(n_el, nv, np.int32),
+                         el_Jmax=np.full(n_el, Jmax, np.int32), vib_G=G,
+                         vib_B=np.full(nv * n_el, B), vib_D=np.zeros(nv * n_el))
+
+
+def test_partition_molecule_closed_forms():
+    """Harmonic ladder: sum_v exp(-b w (v+1/2)) = e^{-bw/2}/(1-e^{-bw});
+    rigid rotor: sum_J (2J+1) e^{-bBJ(J+1)} = 1/(bB) + 1/3 + bB/15 + ...
+    (Mulholland); electronic states add with their g exp(-b T_e)."""
+    c2 = H * CL / KB
+    Tv, Ttr = 8000.0, 5000.0
+    sp = _molecule(nv=200, Jmax=3000)
+    bv, br = c2 / Tv, c2 / Ttr
+    qv = math.exp(-bv * 1500.0 / 2) / (-math.expm1(-bv * 1500.0))
+    x = br * 1.7
+    qr = 1 / x + 1 / 3 + x / 15 + 4 * x * x / 315
+    assert O.partition([sp], 0, Tv, Ttr) == pytest.approx(qv * qr, rel=1e-9)
+    # two electronic states
+    sp2 = _molecule(nv=200, Jmax=3000, g=(1.0, 3.0), T_el=(0.0, 9000.0))
+    assert O.partition([sp2], 0, Tv, Ttr) == pytest.approx(
+        qv * qr * (1 + 3 * math.exp(-bv * 9000.0)), rel=1e-9)
+    # temperatures enter where they belong: rotation only via T_tr
+    sp_r = _molecule(nv=1, Jmax=3000)
+    assert O.partition([sp_r], 0, 100.0, Ttr) == pytest.approx(
+        math.exp(-c2 * 750.0 / 100.0) * qr, rel=1e-9)
+
+
+def test_molecule_populations_close():
+    """Level populations over every (e, v, J) of a small molecule add up to N."""
+    sp = _molecule(nv=5, Jmax=30, g=(2.0, 3.0), T_el=(0.0, 20000.0), harmonic=False)
+    Tv, Ttr = 9000.0, 4000.0
+    Q = O.partition([sp], 0, Tv, Ttr)
+    tot = 0.0
+    for e in range(2):
+        for v in range(5):
+            G = sp.vib_G[e * 5 + v]
+            for J in range(31):
+                tot += O.level_population(1e15, Q, sp.el_g[e] * (2 * J + 1), sp.el_T[e] + G,
+                                          sp.vib_B[e * 5 + v] * J * (J + 1), Tv, Ttr)
+    assert tot == pytest.approx(1e15, rel=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Emission and absorption of one line (Sec. 2.2.1)
+# ----------------------------------------------------------------------------
+
+def _one_line_workload(nu0=20000.0, T=9000.0, Tv=None, N=1e16, ne=3e15, A=1e8, gu=4.0, gl=2.0,
+                       Eu=11.0 * synth.EV_CM, n_points=40001, span=60.0, Eu_rot=0.0, El_rot=0.0,
+                       kind="atom"):
+    rng = np.random.Generator(np.random.PCG64(5))
+    sp = synth.atom_species(rng, "N")
+    El = Eu - nu0 if kind == "atom" else Eu + Eu_rot - El_rot - nu0
+    lines = synth.Lines(np.array([nu0]), np.array([A]), np.array([Eu]), np.array([Eu_rot]),
+                        np.array([El]), np.array([El_rot]), np.array([gu]), np.array([gl]),
+                        np.array([0], np.int32))
+    Tv = T if Tv is None else Tv
+    cells = synth.Cells(np.array([T]), np.array([Tv]), np.array([[N]]), np.array([ne]))
+    grid = synth.Grid(nu0 - span, nu0 + span, n_points, n_points)
+    return sp, lines, cells, grid
+
+
+def test_kirchhoff_per_line():
+    """At T_tr = T_v, eta_i / kappa_i = Planck(nu0, T) at every grid point
+    (line-centre prefactors), Planck written independently."""
+    for T, nu0 in [(6000.0, 20000.0), (12000.0, 70000.0), (30000.0, 1500.0)]:
+        sp, lines, cells, grid = _one_line_workload(nu0=nu0, T=T)
+        eta, kap, n = O.coeffs([sp], lines, cells, grid)
+        m = eta[0] > 0
+        assert m.sum() > 100
+        np.testing.assert_allclose(eta[0][m] / kap[0][m], planck_textbook(nu0, T), rtol=2e-14)
+
+
+def test_line_strengths_textbook():
+    """Integrated line: int eta dnu = N_u A h c nu0 / 4pi (Einstein A, W) and
+    int kappa dnu = A g_u N_l (1 - e^{-hc nu0/kT}) / (8 pi c nu0^2 g_l),
+    times the profile's area inside the cut."""
+    nu0, T, N, A, gu, gl, Eu = 20000.0, 9000.0, 1e16, 1e8, 4.0, 2.0, 11.0 * synth.EV_CM
+    sp, lines, cells, grid = _one_line_workload(nu0=nu0, T=T, N=N, A=A, gu=gu, gl=gl, Eu=Eu,
+                                                n_points=400001, span=400.0)
+    eta, kap, _ = O.coeffs([sp], lines, cells, grid)
+    h = (grid.nu_max - grid.nu_min) / (grid.n_points - 1)
+    Q = sum(g * math.exp(-H * CL * E / (KB * T)) for E, g in zip(sp.level_E, sp.level_g))
+    Nu = N * gu * math.exp(-H * CL * Eu / (KB * T)) / Q
+    Nl = N * gl * math.exp(-H * CL * (Eu - nu0) / (KB * T)) / Q
+    gG = nu0 * math.sqrt(2 * KB * T * math.log(2) / (14.0 * AMU * CL**2))
+    gL = 1e-16 * 3e15 * (T / 1e4) ** 0.33
+    gV = O.voigt_hwhm(gL, gG)
+    area = 2 * si.quad(lambda d: O.voigt_profile(d, gV, gL), 0, 100 * gV, limit=2000,
+                       points=[gV, 5 * gV, 20 * gV])[0]
+    e_exp = 1e-7 * Nu * A * H * CL * nu0 / (4 * math.pi) * area
+    k_exp = A * gu * Nl * (-math.expm1(-H * CL * nu0 / (KB * T))) / (8 * math.pi * CL * nu0**2 * gl) * area
+    assert eta[0].sum() * h == pytest.approx(e_exp, rel=2e-5)
+    assert kap[0].sum() * h == pytest.approx(k_exp, rel=2e-5)
+
+
+def test_population_ratio_two_temperature():
+    """Upper/lower population ratio: N_u g_l / (N_l g_u) = exp(-x),
+    x = c2 (dE_ev / T_v + dE_rot / T_tr): rotation at T_tr, the rest at T_v."""
+    sp, lines, cells, grid = _one_line_workload()
+    c2 = H * CL / KB
+    for (Eu_ev, Eu_rot, El_ev, El_rot, Tv, Ttr) in [(50000.0, 3000.0, 20000.0, 4000.0, 7000.0, 12000.0),
+                                                     (30000.0, 0.0, 0.0, 500.0, 15000.0, 3000.0)]:
+        Nu = O.level_population(1e15, 7.0, 5.0, Eu_ev, Eu_rot, Tv, Ttr)
+        Nl = O.level_population(1e15, 7.0, 3.0, El_ev, El_rot, Tv, Ttr)
+        x = c2 * ((Eu_ev - El_ev) / Tv + (Eu_rot - El_rot) / Ttr)
+        assert Nu * 3.0 / (Nl * 5.0) == pytest.approx(math.exp(-x), rel=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# Window and sum (Sec. 2.2.1, +-100 Voigt HWHM cut)
+# ----------------------------------------------------------------------------
+
+def _tiny(seed, n_lines=5, n_cells=3, n_points=200, lo=20000.0, hi=20060.0):
+    """Tiny two-temperature case: lines inside, near and outside both grid
+    edges, mixed atoms and molecules of different masses."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    species = [synth.atom_species(rng, "N"), synth.atom_species(rng, "O"),
+               synth.molecule_species(rng, "N2", n_v=4)]
+    nu0 = np.sort(rng.uniform(lo - 40.0, hi + 40.0, n_lines))
+    sp_idx = rng.integers(0, 3, n_lines).astype(np.int32)
+    Eu_ev = rng.uniform(80000.0, 110000.0, n_lines)
+    Eu_rot = np.where(sp_idx == 2, rng.uniform(0, 4000.0, n_lines), 0.0)
+    El_rot = np.where(sp_idx == 2, rng.uniform(0, 4000.0, n_lines), 0.0)
+    El_ev = Eu_ev + Eu_rot - El_rot - nu0
+    lines = synth.Lines(nu0, 10 ** rng.uniform(4, 9, n_lines), Eu_ev, Eu_rot, El_ev, El_rot,
+                        rng.integers(2, 13, n_lines).astype(float),
+                        rng.integers(2, 13, n_lines).astype(float), sp_idx)
+    cells = synth.Cells(rng.uniform(3000, 30000, n_cells), rng.uniform(3000, 15000, n_cells),
+                        10 ** rng.uniform(14, 17, (n_cells, 3)), 10 ** rng.uniform(14, 17, n_cells))
+    return species, lines, cells, synth.Grid(lo, hi, n_points, n_points)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_window_and_sum_vs_bruteforce(seed):
+    """Integer windows + skipped lines == every line tested at every point
+    with |nu_k - nu0| <= 100 gamma_V (bitwise: same terms, same order)."""
+    species, lines, cells, grid = _tiny(seed)
+    eta, kap, _ = O.coeffs(species, lines, cells, grid)
+    eb, kb = O.coeffs_bruteforce(species, lines, cells, grid)
+    np.testing.assert_array_equal(eta, eb)
+    np.testing.assert_array_equal(kap, kb)
+
+
+def test_window_against_exact_rationals():
+    """Integer window bounds equal the set {k : |nu_min + k h - nu0| <= W}
+    evaluated in exact rational arithmetic (away from knife edges)."""
+    from fractions import Fraction as Fr
+    rng = np.random.Generator(np.random.PCG64(11))
+    nu_min, h, n = 1000.0, 0.0472, 5000
+    for _ in range(200):
+        nu0 = float(rng.uniform(nu_min - 20, nu_min + n * h + 20))
+        gV = float(rng.uniform(0.01, 0.5))
+        lo, hi = O.window(nu0, gV, nu_min, h, n)
+        W = Fr(100.0 * gV)
+        inside = [k for k in range(max(0, lo - 3), min(n, hi + 4))
+                  if abs(Fr(nu_min) + k * Fr(h) - Fr(nu0)) <= W]
+        if lo <= hi:
+            assert inside == list(range(lo, hi + 1))
+        else:
+            assert inside == []
+
+
+def test_superposition_of_lines():
+    """eta of a line list = sum of eta of each single line (no line dropped,
+    no index mixed up)."""
+    species, lines, cells, grid = _tiny(21, n_lines=8)
+    eta, kap, _ = O.coeffs(species, lines, cells, grid)
+    es = np.zeros_like(eta)
+    ks = np.zeros_like(kap)
+    for i in range(lines.n):
+        e1, k1, _ = O.coeffs(species, lines.subset([i]), cells, grid)
+        es += e1
+        ks += k1
+    np.testing.assert_allclose(eta, es, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(kap, ks, rtol=1e-13, atol=1e-300)
+
+
+def test_sampled_points_equal_dense():
+    """Evaluating at a sparse set of grid indices gives exactly the dense
+    values at those indices."""
+    wl = synth.slab_equilibrium(n_cells=4, n_lines_per_species=300, n_points=20000, seed=3)
+    eta, kap, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
+    ks = np.unique(np.random.default_rng(0).integers(0, wl.grid.n_points, 700))
+    es, kss, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks)
+    np.testing.assert_array_equal(es, eta[:, ks])
+    np.testing.assert_array_equal(kss, kap[:, ks])
+
+
+def test_grid_offset_correctly_rounded():
+    from fractions import Fraction as Fr
+    rng = np.random.Generator(np.random.PCG64(2))
+    for _ in range(200):
+        nu_min, h = 1000.0, 99000.0 / (2**21 - 1)
+        k = int(rng.integers(0, 2**21))
+        nu0 = float(nu_min + k * h + rng.uniform(-300, 300))
+        exact = Fr(nu_min) + k * Fr(h) - Fr(nu0)
+        assert O.grid_offset(nu_min, h, k, nu0) == float(exact)
+
+
+# ----------------------------------------------------------------------------
+# March along a line of sight (Sec. 2.2.3)
+# ----------------------------------------------------------------------------
+
+def test_uniform_slab_closed_form():
+    """Identical cells compose exactly: I = (eta/kappa)(1 - exp(-kappa L))."""
+    wl = synth.slab_equilibrium(n_cells=37, n_lines_per_species=200, n_points=30000,
+                                identical_cells=True, seed=5)
+    r = O.solve_slab(wl)
+    eta, kap = r["eta"][0], r["kappa"][0]
+    L = wl.geometry.dx.sum()
+    m = kap > 0
+    expect = eta[m] / kap[m] * -np.expm1(-kap[m] * L)
+    np.testing.assert_allclose(r["I"][0][m], expect, rtol=1e-12)
+    assert np.all(r["I"][0][~m] == 0)
+
+
+def test_single_line_thick_slab_is_blackbody():
+    """One strong line, optically thick: I at line centre -> Planck(nu0, T)."""
+    T, nu0 = 9000.0, 20000.0
+    sp, lines, cells, grid = _one_line_workload(nu0=nu0, T=T, N=1e18, A=1e9, Eu=10.0 * synth.EV_CM,
+                                                n_points=2001, span=5.0)
+    eta, kap, _ = O.coeffs([sp], lines, cells, grid)
+    k0 = np.argmax(eta[0])
+    I = O.march(np.zeros(50, np.int64), np.full(50, 10.0), eta, kap)
+    assert kap[0, k0] * 500.0 > 60
+    assert I[k0] == pytest.approx(planck_textbook(nu0, T), rel=1e-13)
+
+
+def test_optically_thin_limit():
+    """Scale every density by eps: I / eps -> sum_m eta_m ds_m / eps with
+    relative deviation O(tau)."""
+    wl = synth.slab_equilibrium(n_cells=10, n_lines_per_species=100, n_points=20000, seed=8)
+    ks = np.arange(0, 20000, 7)
+    eps = 1e-9
+    wl.cells.N *= eps
+    eta, kap, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks)
+    cells = np.arange(10)
+    I = O.march(cells, wl.geometry.dx, eta, kap)
+    thin = (eta * wl.geometry.dx[:, None]).sum(0)
+    tau = (kap * wl.geometry.dx[:, None]).sum(0)
+    m = thin > 0
+    assert tau.max() < 1e-6
+    np.testing.assert_allclose(I[m], thin[m], rtol=2 * tau.max() + 1e-13)
+
+
+def test_march_order_far_to_wall():
+    """Two cells: the far cell's emission is attenuated by the near cell:
+    I = S2 (1 - e^-t2) + S1 (1 - e^-t1) e^-t2, with 1 = far, 2 = near."""
+    eta = np.array([[3.0, 0.5], [1.0, 2.0]])
+    kap = np.array([[2.0, 0.1], [0.5, 4.0]])
+    ds = np.array([0.3, 0.7])
+    I = O.march(np.array([0, 1]), ds, eta, kap)
+    for k in range(2):
+        S1, t1 = eta[0, k] / kap[0, k], kap[0, k] * ds[0]
+        S2, t2 = eta[1, k] / kap[1, k], kap[1, k] * ds[1]
+        assert I[k] == pytest.approx(S2 * -math.expm1(-t2) + S1 * -math.expm1(-t1) * math.exp(-t2),
+                                     rel=1e-14)
+
+
+def test_march_zero_and_negative_kappa():
+    """kappa = 0: I = eta ds exactly; kappa < 0 (inversion):
+    I = eta (exp(|kappa| ds) - 1) / |kappa|."""
+    eta = np.array([[2.0, 2.0]])
+    kap = np.array([[0.0, -3.0]])
+    I = O.march(np.array([0]), np.array([0.25]), eta, kap)
+    assert I[0] == 0.5
+    assert I[1] == pytest.approx(2.0 * math.expm1(0.75) / 3.0, rel=1e-15)
+
+
+def test_march_with_far_boundary_intensity():
+    eta = np.array([[1.0]])
+    kap = np.array([[2.0]])
+    I = O.march(np.array([0]), np.array([0.5]), eta, kap, I_far=np.array([7.0]))
+    assert I[0] == pytest.approx(7.0 * math.exp(-1.0) + 0.5 * -math.expm1(-1.0), rel=1e-15)
+
+
+# ----------------------------------------------------------------------------
+# Quadrature (Sec. 2.2.3 flux integral)
+# ----------------------------------------------------------------------------
+
+def test_trapezoid_exact_for_linear():
+    g = synth.Grid(1000.0, 1100.0, 1001, 1001)
+    w = O.trapezoid_weights(g)
+    nu = g.nu_min + np.arange(g.n_points) * O.grid_step(g)
+    assert w @ (3.0 + 0.5 * nu) == pytest.approx(3.0 * 100 + 0.25 * (1100.0**2 - 1000.0**2), rel=1e-13)
+
+
+def test_gauss_legendre_isotropic_flux():
+    """Isotropic I0 gives q = pi I0 with GL in mu x uniform phi, and the
+    slab form 2 pi sum W mu I0."""
+    mu, W = O.gauss_legendre_01(16)
+    assert 2 * math.pi * np.sum(W * mu) == pytest.approx(math.pi, rel=1e-14)
+    geom = synth.AxiGeometry(8, 4, 10.0, 5.0, np.array([1.0]), 16, 16)
+    _, wts = O.axi_rays(geom, 0)
+    assert wts.sum() == pytest.approx(math.pi, rel=1e-14)
+
+
+def test_plane_slab_E3_flux():
+    """Uniform slab of optical thickness tau at the wall with unbounded lateral
+    extent: the ray sum equals 2 pi sum W mu S (1 - e^{-tau/mu}) exactly, and
+    the continuous flux pi S (1 - 2 E3(tau)) within the 16-point GL error."""
+    S, L = 2.5, 1.0
+    geom = synth.AxiGeometry(4, 2, L, 1e7, np.array([0.3]), 16, 4)
+    rays, wts = O.axi_rays(geom, 0)
+    for tau, tol in [(1e-2, 2e-4), (0.1, 1e-5), (1.0, 1e-8)]:
+        kap = tau / L
+        eta = np.full((geom.nx * geom.nr, 1), S * kap)
+        kk = np.full((geom.nx * geom.nr, 1), kap)
+        q = sum(w * O.march(c, d, eta, kk)[0] for (c, d), w in zip(rays, wts))
+        mu, W = O.gauss_legendre_01(16)
+        assert q == pytest.approx(2 * math.pi * np.sum(W * mu * S * -np.expm1(-tau / mu)), rel=1e-12)
+        assert q == pytest.approx(math.pi * S * (1 - 2 * ss.expn(3, tau)), rel=tol)
+
+
+def test_stefan_boltzmann():
+    """int Planck dnu = sigma T^4 / pi (pins the oracle's Planck function)."""
+    T = 8000.0
+    g = synth.Grid(1.0, 60 * T, 400001, 400001)
+    nu = g.nu_min + np.arange(g.n_points) * O.grid_step(g)
+    B = np.array([O.planck(x, T) for x in nu[::1]])
+    val = O.trapezoid_weights(g) @ B
+    assert val == pytest.approx(1e-7 * SIGMA_SB * T**4 / math.pi, rel=1e-6)
+
+
+# ----------------------------------------------------------------------------
+# Axisymmetric geometry (Sec. 2.2.3 rays through the cells)
+# ----------------------------------------------------------------------------
+
+def test_axi_segments_geometry():
+    """Segment lengths add up to the analytic exit distance, every segment
+    midpoint lies in its cell, and there are at most nx + 2 nr segments."""
+    nx, nr, Lx, R = 16, 8, 10.0, 5.0
+    geom = synth.AxiGeometry(nx, nr, Lx, R, np.array([0.7, 2.9]), 6, 6)
+    rng = np.random.Generator(np.random.PCG64(1))
+    for _ in range(300):
+        rw = float(rng.uniform(0, 4.9))
+        mu = float(rng.uniform(0.02, 0.999))
+        phi = float(rng.uniform(0, 2 * math.pi))
+        cell, ds = O.axi_ray(geom, rw, mu, phi)
+        st = math.sqrt(1 - mu * mu)
+        a, b = st * math.cos(phi), st * math.sin(phi)
+        sR = (-rw * a + math.sqrt(rw * rw * a * a - st * st * (rw * rw - R * R))) / (st * st)
+        s_exit = min(Lx / mu, sR)
+        assert ds.sum() == pytest.approx(s_exit, rel=1e-12)
+        assert len(ds) <= nx + 2 * nr and np.all(ds > 0)
+        s_end = np.cumsum(ds[::-1])          # wall -> far
+        s_beg = s_end - ds[::-1]
+
+        def cell_at(s):
+            x, y, z = s * mu, rw + s * a, s * b
+            rho = math.hypot(y, z)
+            return min(int(x // (Lx / nx)), nx - 1) * nr + min(int(rho // (R / nr)), nr - 1)
+
+        # both ends (pulled inside by a hair) and the midpoint lie in the cell:
+        # no segment straddles a cell face
+        for s0, s1, c in zip(s_beg, s_end, cell[::-1]):
+            e = 1e-9 * (s1 - s0)
+            assert cell_at(0.5 * (s0 + s1)) == c
+            assert cell_at(s0 + e) == c and cell_at(s1 - e) == c
+
+
+def test_axi_uniform_medium_matches_path_length():
+    """Uniform medium: each ray's intensity is S (1 - exp(-kappa s_exit))."""
+    geom = synth.AxiGeometry(10, 6, 8.0, 4.0, np.array([1.5]), 4, 6)
+    rays, _ = O.axi_rays(geom, 0)
+    eta = np.full((60, 1), 0.6)
+    kap = np.full((60, 1), 0.3)
+    for c, d in rays:
+        assert O.march(c, d, eta, kap)[0] == pytest.approx(2.0 * -math.expm1(-0.3 * d.sum()), rel=1e-13)
