@@ -1,0 +1,166 @@
+"""Benchmark of the line-by-line + ray-march hot path on one MI355X.
+
+One step = the whole path over one batch of resident synthetic input:
+per-cell populations and scales, per-(cell, line) setup, line-to-grid Voigt
+accumulation of eta/kappa for every cell, march of every ray and the spectral
++ angular quadrature to the wall flux (lrt_solve).  Default workload: the 1-D
+stagnation line with 400 cells, 11 species, 200k atomic + 2M rovibronic lines,
+a 2^21-point grid over 1000-100000 cm^-1 and 17 rays (wall normal + 16
+Gauss-Legendre directions), in the compensated single-precision form.  The
+double-precision form is timed beside it for the speedup and the error.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Voigt line-pt evals/s + q_rad solves/s (FP32-comp vs FP64, 1 GPU); p99 latency"
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz -> non-packed FP32 VALU lane-op issue rate
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# Issue slots of one profile evaluation in its minimal form: 16 FP32 VALU ops
+# (offset, |x|, x^2, 3 exponent scalings, 4 for the two rational terms over one
+# reciprocal, 2 combines, 2 accumulating FMAs, 2 for the mask/window test) +
+# 5 transcendentals (3 exp2, 1 log2, 1 rcp) at 4 slots each (quarter rate).
+SLOTS_PER_EVAL = 16 + 5 * 4
+HBM_PEAK = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--workload", default="stagnation", choices=["stagnation", "slab", "axi"])
+    ap.add_argument("--cpu-points", type=int, default=512, help="grid points of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def workload(name):
+    from paper_2604_11856_amd import synth
+    if name == "stagnation":
+        wl = synth.config_stagnation()
+        desc = ("stagnation-line: 400 cells x 0.01 cm, 11 species, 200k atomic + 2M rovibronic "
+                "lines, 2^21-point grid 1000-100000 cm^-1, 17 rays (wall normal + 16 GL)")
+    elif name == "slab":
+        wl = synth.config_slab()
+        desc = "slab: 64 cells x 0.05 cm, 2000 N/O lines, 200,000-point grid 5000-80000 cm^-1, 1 ray"
+    else:
+        wl = synth.config_axi()
+        desc = ("axisymmetric: 256x128 cells, 11 species, 1M lines, 2^20-point grid in 16 bands, "
+                "64 wall points x (16 GL x 16 azimuth) rays")
+    return wl, desc
+
+
+def cpu_baseline(wl, n_points):
+    import oracle as O
+    from paper_2604_11856_amd import synth
+    threads = min(os.cpu_count() or 1, 16)
+    ks = synth.sample_points(wl.grid, wl.lines, n_points, seed=1)
+    t = time.perf_counter()
+    _, _, n_terms = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks, threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": n_terms / dt, "unit": "Voigt line-pt evals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "all %d cells x %d grid points (%d-point clusters), all %d lines: %d terms in %.2f s"
+                      % (wl.cells.n, ks.size, 32, wl.lines.n, n_terms, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2604_11856_amd import lrt
+
+    wl, desc = workload(args.workload)
+    ctx = lrt.Context(0).load(wl)
+    sz = ctx.sizes()
+    n_terms = sum(ctx.count_terms(b) for b in range(sz["n_bands"]))
+    seg_pts = sum(len(ctx.ray(r)[0]) for r in range(sz["n_rays"])) * sz["n_points"]
+
+    def run(prec, steps, warmup):
+        for _ in range(warmup):
+            ctx.solve(prec)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = None
+        for _ in range(steps):
+            out = ctx.solve(prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        prof = {k: ctx.profile_read(k) for k in lrt.KERNELS}
+        ctx.profile(False)
+        return dt, out, prof
+
+    dt32, (q32, I32, _), prof32 = run(lrt.LRT_FP32_COMP, args.steps, args.warmup)
+    res = {}
+    if args.fp64_steps > 0:
+        dt64, (q64, I64, _), prof64 = run(lrt.LRT_FP64, args.fp64_steps, 0)
+        res = {"ms_per_step": dt64 * 1e3, "evals_per_s": n_terms / dt64,
+               "accum_ms_per_launch": prof64["accum"][0] / max(1, prof64["accum"][1]),
+               "speedup_fp32c_over_fp64": dt64 / dt32,
+               "rel_err_fp32c_vs_fp64": {
+                   "I_int_max": float(np.max(np.abs(I32 - I64) / np.maximum(np.abs(I64), 1e-300))),
+                   "q": [float(abs(a - b) / abs(b)) if b != 0 else 0.0 for a, b in zip(q32, q64)]}}
+
+    acc_ms, acc_n = prof32["accum"]
+    acc_s = acc_ms / 1e3 / max(1, acc_n)
+    terms_per_launch = n_terms / sz["n_bands"]
+    achieved = terms_per_launch * SLOTS_PER_EVAL / acc_s
+    mar_ms, mar_n = prof32["march"]
+    mar_s = mar_ms / 1e3 / max(1, mar_n)
+    march_bytes = seg_pts * 8 / sz["n_bands"]
+
+    line = {
+        "metric": METRIC,
+        "value": n_terms / dt32,
+        "unit": "Voigt line-pt evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt32 * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": desc, "precision": "fp32-compensated (Kahan per point); populations, "
+                   "widths, windows, march state and quadrature in f64",
+                   "cells": sz["n_cells"], "lines": wl.lines.n, "grid_points": sz["n_points"],
+                   "bands": sz["n_bands"], "rays": sz["n_rays"], "wall_points": sz["n_wall"],
+                   "voigt_terms_per_step": n_terms},
+        "q_rad_solves_per_s": sz["n_wall"] / dt32,
+        "los_solves_per_s": sz["n_rays"] / dt32,
+        "q_rad_W_cm2": [float(x) for x in q32],
+        "fp64": res,
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()},
+        "roofline": {"bound": "alu", "kernel": "accum_f32",
+                     "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "T lane-op/s (FP32 VALU issue slots, transcendental = 4)",
+                     "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "evals_per_launch": terms_per_launch, "slots_per_eval": SLOTS_PER_EVAL,
+                     "avg_launch_ms": acc_s * 1e3},
+        "march_roofline": {"bound": "hbm", "kernel": "march_f32", "achieved": march_bytes / mar_s / 1e9,
+                           "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                           "frac": march_bytes / mar_s / HBM_PEAK, "avg_launch_ms": mar_s * 1e3,
+                           "bytes_per_launch": march_bytes},
+        "p50_latency_ms": None, "p99_latency_ms": None,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_points)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

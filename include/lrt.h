@@ -1,0 +1,252 @@
+/*
+ * lrt.h -- C ABI of liblrt, an MI355X (gfx950) implementation of the
+ * line-by-line + ray-tracing radiation hot path of arXiv 2604.11856:
+ *
+ *   per-cell Boltzmann populations (Sec. 2.1)
+ *     -> per-(cell, line) emission / absorption strengths, Doppler, Lorentz
+ *        and Voigt widths (Sec. 2.2.1)
+ *     -> line-to-grid accumulation of the Whiting-Voigt profile into the
+ *        spectral emission coefficient eta and absorption coefficient kappa
+ *        of every cell (Sec. 2.2.1)
+ *     -> march of the radiative transfer equation along rays, far boundary
+ *        to wall, with piecewise-constant cells (Sec. 2.2.3)
+ *     -> spectral (trapezoid) and angular (Gauss-Legendre polar x uniform
+ *        azimuth) quadrature to the wall radiative heat flux (Sec. 2.2.3).
+ *
+ * Conventions for every call:
+ *   - Units: wavenumber and level energies in cm^-1, temperatures in K,
+ *     number densities in cm^-3, lengths in cm.  eta in W cm^-3 sr^-1
+ *     (cm^-1)^-1, kappa in cm^-1, intensity in W cm^-2 sr^-1 (cm^-1)^-1,
+ *     spectrally integrated intensity in W cm^-2 sr^-1, flux in W cm^-2.
+ *   - Every entry returns an lrt_status; nothing throws or aborts across the
+ *     ABI.  Arguments are validated before any device work; on error nothing
+ *     has been launched and lrt_last_error() describes the failure.
+ *   - Host pointers are read during the call only and never retained.  The
+ *     library owns the context and the device copies of species, lines,
+ *     grid, cells and rays.  The caller owns every output buffer.
+ *   - "stream" is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls that write only device buffers are stream-ordered and return
+ *     before the work is done; calls that write host buffers synchronise.
+ *   - One context is used by one host thread at a time.
+ */
+#ifndef LRT_H
+#define LRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lrt_ctx lrt_ctx;
+
+typedef enum {
+    LRT_OK = 0,
+    LRT_E_ARG = 1,        /* invalid argument (value, size, pointer) */
+    LRT_E_OOM = 2,        /* device or host allocation failed */
+    LRT_E_DEVICE = 3,     /* HIP runtime error (message in lrt_last_error) */
+    LRT_E_BUDGET = 4,     /* request larger than the configured memory budget */
+    LRT_E_NOT_READY = 5,  /* result not available yet */
+    LRT_E_STATE = 6       /* call made in the wrong state (missing set_* call) */
+} lrt_status;
+
+typedef enum {
+    LRT_FP64 = 0,       /* every step in double precision */
+    LRT_FP32_COMP = 1   /* populations, widths, windows and quadrature in double;
+                           profile evaluation in single precision with
+                           compensated (Kahan) sums per grid point; eta/kappa
+                           stored as float with a per-cell power-of-two scale */
+} lrt_precision;
+
+enum { LRT_KIND_NONE = 0, LRT_KIND_ATOM = 1, LRT_KIND_MOLECULE = 2 };
+
+/* Level table of one species (Sec. 2.1).
+ * kind == LRT_KIND_ATOM: n_levels electronic levels (energy level_E, degeneracy
+ *   level_g); Q = sum_j g_j exp(-c2 E_j / T_v).
+ * kind == LRT_KIND_MOLECULE: n_el electronic states (term el_T, degeneracy el_g)
+ *   with el_nv[e] vibrational levels each (term values vib_G, rotational
+ *   constants vib_B, vib_D, concatenated over e) and J = 0..el_Jmax[e];
+ *   Q = sum_e g_e exp(-c2 T_e/T_v) sum_v exp(-c2 G_v/T_v)
+ *       sum_J (2J+1) exp(-c2 (B_v J(J+1) - D_v J^2(J+1)^2) / T_tr).
+ *   Symmetry number and line-alternation factor are taken as 1.
+ * kind == LRT_KIND_NONE: species that carries no lines (number density only).
+ * mass: molar mass in g/mol (Doppler width). */
+typedef struct {
+    int kind;
+    double mass;
+    int n_levels;
+    const double *level_E, *level_g;
+    int n_el;
+    const double *el_T, *el_g;
+    const int *el_nv, *el_Jmax;
+    const double *vib_G, *vib_B, *vib_D;
+} lrt_species;
+
+/* Line list, structure of arrays, host pointers, any order (Sec. 2.2.1-2.2.2).
+ * nu0 > 0 line centre; A >= 0 Einstein coefficient (s^-1); upper / lower level
+ * energy split into an electronic+vibrational part (populated at T_v) and a
+ * rotational part (populated at T_tr; 0 for atoms); gu, gl >= 1 level
+ * degeneracies; species indexes the species table. */
+typedef struct {
+    int64_t n;
+    const double *nu0, *A, *Eu_ev, *Eu_rot, *El_ev, *El_rot, *gu, *gl;
+    const int32_t *species;
+} lrt_lines;
+
+/* Flowfield cell states, host pointers (Sec. 2.3 flowfield interface):
+ * T_tr translational-rotational temperature, T_v vibrational =
+ * electron-electronic temperature, N[c * n_species + s] number densities,
+ * n_e electron number density (Lorentz width). */
+typedef struct {
+    int64_t n_cells;
+    int n_species;
+    const double *T_tr, *T_v, *N, *n_e;
+} lrt_cells;
+
+/* Library version as "major.minor.patch". */
+const char *lrt_version(void);
+
+/* Text of a status code (static storage). */
+const char *lrt_status_string(lrt_status s);
+
+/* Create a context on HIP device `device`.  *out receives the context, or NULL
+ * on failure.  Errors: LRT_E_ARG (bad device or out == NULL), LRT_E_DEVICE. */
+lrt_status lrt_create(int device, lrt_ctx **out);
+
+/* Destroy a context and free its device memory.  NULL is accepted. */
+void lrt_destroy(lrt_ctx *ctx);
+
+/* Message of the last failed call on this context ("" if none); valid until
+ * the next call on the context.  NULL ctx returns the last lrt_create error. */
+const char *lrt_last_error(const lrt_ctx *ctx);
+
+/* Species level tables (copied).  Must precede lrt_set_lines/lrt_set_cells.
+ * Errors: LRT_E_ARG on n_species < 1, non-positive mass, unknown kind, a
+ * molecule / atom without levels, non-finite values. */
+lrt_status lrt_set_species(lrt_ctx *ctx, int n_species, const lrt_species *species);
+
+/* Line list (copied to device memory, sorted by nu0 there, kept resident).
+ * Errors: LRT_E_ARG (nu0 <= 0, A < 0, g < 1, non-finite energy, species index
+ * out of range or pointing to a species of kind NONE), LRT_E_STATE (no
+ * species), LRT_E_OOM. */
+lrt_status lrt_set_lines(lrt_ctx *ctx, const lrt_lines *lines);
+
+/* Uniform spectral grid nu_k = nu_min + k h, h = (nu_max - nu_min) /
+ * (n_points - 1), both ends included, processed in bands of band_points
+ * points (the last band may be shorter).  Errors: LRT_E_ARG (n_points < 2,
+ * nu_max <= nu_min, nu_min <= 0, band_points < 1, n_points >= 2^31). */
+lrt_status lrt_set_grid(lrt_ctx *ctx, double nu_min, double nu_max, int64_t n_points,
+                        int64_t band_points);
+
+/* Cell states (copied to device memory, resident).  Errors: LRT_E_ARG
+ * (n_species differs from the species table, T <= 0 or non-finite, N < 0,
+ * n_e < 0), LRT_E_STATE (no species). */
+lrt_status lrt_set_cells(lrt_ctx *ctx, const lrt_cells *cells);
+
+/* Rays of a 1-D slab seen from the wall (Sec. 2.2.3 with a tangent-slab
+ * geometry): cells 0..n_cells-1 ordered from the far (free) boundary to the
+ * wall with thicknesses dx (host).  Ray 0 is the wall normal; if n_mu > 0,
+ * rays 1..n_mu follow the Gauss-Legendre nodes mu_i on [0, 1] with path
+ * length dx/mu_i per cell and flux weight 2 pi W_i mu_i (ray 0 has weight 0).
+ * One wall point.  Errors: LRT_E_ARG (n_cells < 1, dx <= 0, n_mu < 0). */
+lrt_status lrt_set_rays_slab(lrt_ctx *ctx, int64_t n_cells, const double *dx, int n_mu);
+
+/* Rays of an axisymmetric structured grid (Sec. 2.2.3, LOS through the
+ * flowfield): nx x nr uniform cells over x in [0, Lx], r in [0, R], cell index
+ * c = ix * nr + ir.  The wall is the plane x = 0; wall point w sits at radius
+ * wall_r[w] (host) and sees rays of direction (mu_i, sin cos phi_j, sin sin
+ * phi_j) with mu_i Gauss-Legendre on [0, 1] and phi_j = (j + 1/2) 2 pi / n_phi,
+ * flux weight W_i mu_i 2 pi / n_phi.  Rays end at x = Lx or r = R (free
+ * boundary, I = 0); the axis is transparent.  Segments are built on the host
+ * in double precision by cell-to-cell traversal.
+ * Errors: LRT_E_ARG (non-positive sizes, wall_r outside [0, R), n_mu or
+ * n_phi < 1). */
+lrt_status lrt_set_rays_axi(lrt_ctx *ctx, int nx, int nr, double Lx, double R, int n_wall,
+                            const double *wall_r, int n_mu, int n_phi);
+
+/* Host-only (no device, no context): segments of one ray of the axisymmetric
+ * geometry of lrt_set_rays_axi, from wall radius rw along (mu, sqrt(1-mu^2)
+ * cos phi, sqrt(1-mu^2) sin phi), far -> wall order, at most cap entries.
+ * *n receives the count.  Errors: LRT_E_ARG (bad sizes, mu not in (0, 1],
+ * rw outside [0, R), cap too small). */
+lrt_status lrt_trace_axi_ray(int nx, int nr, double Lx, double R, double rw, double mu, double phi,
+                             int64_t cap, int32_t *cell, double *ds, int64_t *n);
+
+/* Sizes of the current state: cells, rays, wall points, grid points, bands,
+ * band length.  Any pointer may be NULL. */
+lrt_status lrt_get_sizes(const lrt_ctx *ctx, int64_t *n_cells, int64_t *n_rays, int64_t *n_wall,
+                         int64_t *n_points, int64_t *n_bands, int64_t *band_points);
+
+/* Copy ray r's segments to host: up to cap entries of cell index and path
+ * length, far -> wall order; *n receives the segment count, *weight the flux
+ * weight and *wall the wall point of the ray.  Errors: LRT_E_ARG (r out of
+ * range, cap < count). */
+lrt_status lrt_get_ray(const lrt_ctx *ctx, int64_t r, int64_t cap, int32_t *cell, double *ds,
+                       int64_t *n, double *weight, int64_t *wall);
+
+/* Emission and absorption coefficients of every cell on band `band`
+ * (grid indices [band * band_points, min(n_points, (band+1) * band_points)))
+ * (Sec. 2.1 populations, Sec. 2.2.1 bound-bound emission, absorption and
+ * Voigt profile, cut at +-100 Voigt HWHM).  eta and kappa are device buffers
+ * of [n_cells][band_len] doubles (LRT_FP64) or floats (LRT_FP32_COMP).  For
+ * LRT_FP32_COMP, escale (device, [n_cells][2] int32) receives per cell the
+ * power-of-two scale of eta and of kappa: value = stored * 2^escale (0 when
+ * the cell is representable unscaled); escale may be NULL for LRT_FP64.
+ * Stream-ordered.  Errors: LRT_E_STATE (species, lines, grid or cells
+ * missing), LRT_E_ARG (band out of range, NULL buffer, unknown precision). */
+lrt_status lrt_coeffs(lrt_ctx *ctx, int64_t band, lrt_precision prec, void *eta, void *kappa,
+                      int32_t *escale, void *stream);
+
+/* March every ray through eta / kappa of band `band` (as written by
+ * lrt_coeffs with the same precision) and integrate over the band's grid
+ * points (Sec. 2.2.3): per ray and point, starting from I = 0 at the far end,
+ * I <- I exp(-tau) + eta ds F(tau), tau = kappa ds, F(t) = (1 - e^-t)/t,
+ * F(0) = 1.  I_out (device, [n_rays][band_len] doubles) receives the wall
+ * intensity, or pass NULL; I_int_out (device, [n_rays] doubles) receives the
+ * band's trapezoid sum with global-index weights (h/2 at grid ends, h inside).
+ * Stream-ordered.  Errors: LRT_E_STATE (no rays, cells/rays mismatch),
+ * LRT_E_ARG. */
+lrt_status lrt_march(lrt_ctx *ctx, int64_t band, lrt_precision prec, const void *eta,
+                     const void *kappa, const int32_t *escale, double *I_out, double *I_int_out,
+                     void *stream);
+
+/* The whole path over bands first_band..n_bands-1: per-cell populations and
+ * scales (recomputed on every call), coefficients, march, spectral and angular
+ * quadrature.  Outputs (host, may be NULL): q[n_wall]
+ * wall flux summed over the processed bands, I_int[n_rays] spectrally
+ * integrated intensity per ray, q_band[n_wall][n_bands] per-band flux (bands
+ * before first_band are left untouched, so a run resumed at first_band fills
+ * in the rest).  Workspace is allocated by the library and kept for reuse.
+ * Synchronises the stream.  Errors: as lrt_coeffs and lrt_march, LRT_E_OOM. */
+lrt_status lrt_solve(lrt_ctx *ctx, lrt_precision prec, int64_t first_band, double *q,
+                     double *I_int, double *q_band, void *stream);
+
+/* Number of in-window (cell, line, grid point) terms of band `band`, i.e. the
+ * Voigt evaluations the accumulation performs usefully.  Synchronises. */
+lrt_status lrt_count_terms(lrt_ctx *ctx, int64_t band, int64_t *count, void *stream);
+
+/* Kernel families timed by the profiler. */
+typedef enum {
+    LRT_K_THERMO = 0,   /* partition functions, per-cell constants */
+    LRT_K_SCALE = 1,    /* per-cell power-of-two scale (single-precision form) */
+    LRT_K_RANGES = 2,   /* candidate line ranges per tile */
+    LRT_K_ACCUM = 3,    /* line-to-grid Voigt accumulation */
+    LRT_K_MARCH = 4,    /* ray march + spectral trapezoid */
+    LRT_K_COUNT = 5
+} lrt_kernel;
+
+/* enable != 0: from now on every kernel launch of the context is bracketed by
+ * HIP events recorded on the stream it is launched on; any earlier record is
+ * discarded.  enable == 0: stop recording and discard. */
+lrt_status lrt_profile(lrt_ctx *ctx, int enable);
+
+/* Total device time (ms, from the event pairs) and number of launches of one
+ * kernel family since profiling was enabled.  Waits for the recorded events. */
+lrt_status lrt_profile_read(lrt_ctx *ctx, int kernel, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRT_H */

@@ -92,6 +92,8 @@ def lib():
                                              C.POINTER(_Cells), d, d, i64, _dp, _dp]),
             "orc_march": (None, [i64, _i64p, _dp, i64, _dp, _dp, _dp, _dp]),
             "orc_axi_segments": (i64, [C.c_int, C.c_int, d, d, d, d, d, i64, _i64p, _dp]),
+            "orc_knife_edges": (i64, [C.POINTER(_Species), C.POINTER(_Lines), C.POINTER(_Cells),
+                                      d, d, i64, d, i64, _i64p, _i64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -250,6 +252,20 @@ def coeffs(species, lines, cells, grid, ks: Optional[np.ndarray] = None, threads
     n = lib().orc_coeffs(C.byref(st.s), C.byref(lt.s), C.byref(ct.s), grid.nu_min, grid.nu_max,
                          grid.n_points, ks.size, _p(ks, _i64p), _p(eta), _p(kap), int(threads))
     return eta, kap, n
+
+
+def knife_edges(species, lines, cells, grid, tol: float = 1e-9):
+    """(cell, k) grid points next to a window bound that lies within tol
+    (relative) of an integer grid index: a last-bit difference in the Voigt
+    width may move such a bound by one point."""
+    st, lt, ct = SpeciesTable(species), LineTable(lines), CellTable(cells)
+    cap = 1 << 16
+    cc = np.zeros(cap, np.int64)
+    kk = np.zeros(cap, np.int64)
+    n = lib().orc_knife_edges(C.byref(st.s), C.byref(lt.s), C.byref(ct.s), grid.nu_min,
+                              grid.nu_max, grid.n_points, tol, cap, _p(cc, _i64p), _p(kk, _i64p))
+    n = min(n, cap)
+    return cc[:n].copy(), kk[:n].copy()
 
 
 def coeffs_bruteforce(species, lines, cells, grid):

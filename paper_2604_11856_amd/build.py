@@ -1,0 +1,41 @@
+"""Compile liblrt.so (HIP for gfx950) in the package directory."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "liblrt.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+ARCH = ["--offload-arch=gfx950"]
+# packed FP32 instructions are disabled for every HIP translation unit
+NO_PK = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("build failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+
+
+def build_library(out: str = LIB) -> str:
+    """Always recompiles (the caller decides when to build)."""
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    k_obj = os.path.join(bdir, "lrt_kernels.o")
+    h_obj = os.path.join(bdir, "lrt_host.o")
+    _run([HIPCC, *ARCH, *COMMON, *NO_PK, "-c", os.path.join(CSRC, "lrt_kernels.hip"), "-o", k_obj])
+    # host code: no FP contraction, so the two-sum / two-product grid offsets stay exact
+    _run([HIPCC, *ARCH, *COMMON, "-ffp-contract=off", "-x", "hip", *NO_PK, "-c",
+          os.path.join(CSRC, "lrt_host.cpp"), "-o", h_obj])
+    tmp = out + ".tmp%d" % os.getpid()
+    _run([HIPCC, *ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, h_obj])
+    os.replace(tmp, out)
+    return out
+
+
+if __name__ == "__main__":
+    print(build_library())

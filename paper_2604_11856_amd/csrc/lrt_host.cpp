@@ -1,0 +1,953 @@
+// Host side of liblrt: context, validation, uploads, line preparation, ray
+// geometry (Sec. 2.2.3) and the band loop that drives the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/lrt.h"
+#include "lrt_internal.h"
+
+using namespace lrt;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// Device buffer owned by the context.
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+}  // namespace
+
+struct lrt_ctx {
+    int device = 0;
+    std::string err;
+
+    // species
+    int n_species = 0;
+    std::vector<int32_t> sp_kind;
+    std::vector<double> sp_mass;
+    DBuf d_kind, d_mass, d_lev_off, d_lev_E, d_lev_g, d_el_off, d_el_T, d_el_g, d_el_J,
+        d_vib_off, d_vib_G, d_vib_B, d_vib_D;
+    DevSpecies sp{};
+    double M_min = 0.0;
+
+    // lines (sorted by nu0 on the host, resident on the device)
+    int64_t n_lines = -1;
+    std::vector<double> h_nu0;   // sorted centres, host copy for k0/frac0
+    DBuf d_nu0, d_A, d_Eu_ev, d_Eu_rot, d_El_ev, d_El_rot, d_lngu, d_species, d_k0, d_frac0;
+    bool lines_grid_ready = false;
+
+    // grid
+    bool have_grid = false;
+    double nu_min = 0, nu_max = 0, h = 0;
+    int64_t n_points = 0, band_points = 0;
+
+    // cells
+    int64_t n_cells = -1;
+    DBuf d_T_tr, d_T_v, d_N, d_n_e;
+    DBuf d_cc, d_cs;
+    bool thermo_ready = false;
+    DBuf d_emax, d_escale;
+    bool scale_ready = false;
+
+    // rays
+    int64_t n_rays = -1, n_wall = 0;
+    int64_t rays_cells = 0;   // number of cells the geometry expects
+    std::vector<int64_t> h_off;
+    std::vector<int32_t> h_cell;
+    std::vector<double> h_ds, h_weight;
+    std::vector<int64_t> h_wall_off, h_ray_wall;
+    DBuf d_off, d_cell, d_ds, d_weight, d_wall_off;
+
+    // workspace
+    DBuf w_ranges, w_eta, w_kappa, w_partials, w_Iband, w_Itot, w_qband, w_count;
+
+    // profiler: event pairs per kernel family
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[LRT_K_COUNT];
+
+    void clear_events()
+    {
+        for (auto &v : ev) {
+            for (auto &p : v) {
+                (void)hipEventDestroy(p.first);
+                (void)hipEventDestroy(p.second);
+            }
+            v.clear();
+        }
+    }
+    ~lrt_ctx() { clear_events(); }
+};
+
+namespace {
+
+lrt_status fail(lrt_ctx *c, lrt_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf; else g_create_error = buf;
+    return s;
+}
+
+#define LRT_HIP(ctx, call)                                                                     \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((ctx), LRT_E_DEVICE, "%s: %s (%s:%d)", #call, hipGetErrorString(e_),   \
+                        __FILE__, __LINE__);                                                   \
+    } while (0)
+
+// Launch `fn` (returning hipError_t) on stream st, bracketed by events when
+// the context profiles.
+template <class F>
+hipError_t timed(lrt_ctx *c, int kernel, hipStream_t st, F fn)
+{
+    if (!c->prof) return fn();
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventCreate(&b)) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return e;
+    }
+    (void)hipEventRecord(a, st);
+    e = fn();
+    (void)hipEventRecord(b, st);
+    c->ev[kernel].push_back({a, b});
+    return e;
+}
+
+lrt_status upload(lrt_ctx *c, DBuf &b, const void *src, size_t bytes)
+{
+    b.release();
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail(c, LRT_E_OOM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    if (src) {
+        e = hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(c, LRT_E_DEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+    }
+    return LRT_OK;
+}
+
+template <class T>
+lrt_status upload_vec(lrt_ctx *c, DBuf &b, const std::vector<T> &v)
+{
+    return upload(c, b, v.empty() ? nullptr : v.data(), v.size() * sizeof(T));
+}
+
+// grow-only workspace
+lrt_status ensure(lrt_ctx *c, DBuf &b, size_t bytes)
+{
+    if (b.bytes >= bytes && b.p) return LRT_OK;
+    return upload(c, b, nullptr, bytes);
+}
+
+bool finite_all(const double *p, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Gauss-Legendre nodes and weights on [0, 1] (Newton on P_n).
+void gauss_legendre_01(int n, std::vector<double> &mu, std::vector<double> &w)
+{
+    mu.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double x = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = x; p0 = 1.0; }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = x; p0 = 1.0; }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+        }
+        // node on [-1, 1] -> [0, 1]
+        mu[i] = 0.5 * (x + 1.0);
+        w[i] = 0.5 * 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    // ascending order
+    std::vector<int> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return mu[a] < mu[b]; });
+    std::vector<double> m2(n), w2(n);
+    for (int i = 0; i < n; ++i) { m2[i] = mu[idx[i]]; w2[i] = w[idx[i]]; }
+    mu.swap(m2);
+    w.swap(w2);
+}
+
+// Roots of A2 s^2 + 2 B s + C = 0 (A2 > 0), smaller and larger; false if none.
+bool quad_roots(double A2, double B, double C, double &lo, double &hi)
+{
+    const double disc = B * B - A2 * C;
+    if (disc < 0.0) return false;
+    const double sq = std::sqrt(disc);
+    const double q = (B >= 0.0) ? -(B + sq) : (-B + sq);
+    if (q == 0.0) {
+        lo = hi = 0.0;
+        return true;
+    }
+    double r1 = q / A2, r2 = C / q;
+    lo = std::min(r1, r2);
+    hi = std::max(r1, r2);
+    return true;
+}
+
+// Cell-to-cell traversal of one ray from the wall point (0, rw, 0) along
+// (mu, st cos phi, st sin phi) through the nx x nr grid.  Appends segments in
+// wall -> far order.  Returns false if the traversal does not terminate.
+bool traverse_axi(int nx, int nr, double Lx, double R, double rw, double mu, double phi,
+                  std::vector<int32_t> &cell, std::vector<double> &ds)
+{
+    const double dx = Lx / nx, dr = R / nr;
+    const double st = std::sqrt(std::max(0.0, 1.0 - mu * mu));
+    const double a = st * std::cos(phi);
+    const double A2 = st * st;          // rho^2(s) = rw^2 + 2 B s + A2 s^2
+    const double B = rw * a;
+    int ix = 0;
+    int ir = std::min((int)std::floor(rw / dr), nr - 1);
+    double s = 0.0;
+    const int max_steps = 4 * (nx + 2 * nr) + 16;
+    for (int step = 0; step < max_steps; ++step) {
+        const double s_x = (ix + 1) * dx / mu;
+        double s_r = INFINITY;
+        int dir = 0;
+        if (A2 > 0.0) {
+            double lo, hi;
+            if (ir > 0) {
+                // inward crossing of the inner face: ahead of s, or at s when the
+                // ray starts on that face heading inward (d rho^2/ds < 0).  A
+                // tangency (lo == hi) touches the face without entering.
+                const double rj = ir * dr;
+                const bool inward = B + A2 * s < 0.0;
+                if (quad_roots(A2, B, (rw - rj) * (rw + rj), lo, hi) && lo < hi &&
+                    (lo > s || (lo == s && inward))) {
+                    s_r = lo;
+                    dir = -1;
+                }
+            }
+            if (dir == 0) {
+                const double rj = (ir + 1) * dr;
+                if (quad_roots(A2, B, (rw - rj) * (rw + rj), lo, hi) && hi > s) {
+                    s_r = hi;
+                    dir = +1;
+                }
+            }
+        }
+        const double s_next = std::min(s_x, s_r);
+        if (s_next > s) {
+            cell.push_back((int32_t)((int64_t)ix * nr + ir));
+            ds.push_back(s_next - s);
+        }
+        s = s_next;
+        // an x-plane and an r-face crossed at the same s are both taken, since
+        // a root equal to s is not found again on the next step
+        const bool cross_x = s_x <= s_r, cross_r = s_r <= s_x;
+        if (cross_x && ++ix >= nx) return true;
+        if (cross_r) {
+            ir += dir;
+            if (ir >= nr) return true;
+            if (ir < 0) ir = 0;
+        }
+    }
+    return false;
+}
+
+}  // namespace
+
+// ===========================================================================
+// public API
+// ===========================================================================
+
+extern "C" {
+
+const char *lrt_version(void) { return "0.1.0"; }
+
+const char *lrt_status_string(lrt_status s)
+{
+    switch (s) {
+    case LRT_OK: return "ok";
+    case LRT_E_ARG: return "invalid argument";
+    case LRT_E_OOM: return "out of memory";
+    case LRT_E_DEVICE: return "device error";
+    case LRT_E_BUDGET: return "over budget";
+    case LRT_E_NOT_READY: return "not ready";
+    case LRT_E_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+lrt_status lrt_create(int device, lrt_ctx **out)
+{
+    if (!out) return fail(nullptr, LRT_E_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return fail(nullptr, LRT_E_DEVICE, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (device < 0 || device >= n) return fail(nullptr, LRT_E_ARG, "device %d out of range (%d devices)", device, n);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, LRT_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    lrt_ctx *c = new (std::nothrow) lrt_ctx();
+    if (!c) return fail(nullptr, LRT_E_OOM, "context allocation failed");
+    c->device = device;
+    *out = c;
+    return LRT_OK;
+}
+
+void lrt_destroy(lrt_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    delete ctx;
+}
+
+const char *lrt_last_error(const lrt_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+lrt_status lrt_set_species(lrt_ctx *c, int n, const lrt_species *sp)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (n < 1 || !sp) return fail(c, LRT_E_ARG, "n_species must be >= 1 and species non-NULL");
+    std::vector<int32_t> kind(n), el_J;
+    std::vector<double> mass(n), lev_E, lev_g, el_T, el_g, vib_G, vib_B, vib_D;
+    std::vector<int64_t> lev_off(1, 0), el_off(1, 0), vib_off(1, 0);
+    double M_min = INFINITY;
+    for (int s = 0; s < n; ++s) {
+        const lrt_species &x = sp[s];
+        if (x.kind != LRT_KIND_NONE && x.kind != LRT_KIND_ATOM && x.kind != LRT_KIND_MOLECULE)
+            return fail(c, LRT_E_ARG, "species %d: unknown kind %d", s, x.kind);
+        if (!(x.mass > 0.0) || !std::isfinite(x.mass))
+            return fail(c, LRT_E_ARG, "species %d: mass must be positive", s);
+        kind[s] = x.kind;
+        mass[s] = x.mass;
+        if (x.kind == LRT_KIND_ATOM) {
+            if (x.n_levels < 1 || !x.level_E || !x.level_g)
+                return fail(c, LRT_E_ARG, "species %d: atom needs levels", s);
+            for (int j = 0; j < x.n_levels; ++j) {
+                if (!std::isfinite(x.level_E[j]) || !(x.level_g[j] > 0.0) || !std::isfinite(x.level_g[j]))
+                    return fail(c, LRT_E_ARG, "species %d level %d: bad energy or degeneracy", s, j);
+                lev_E.push_back(x.level_E[j]);
+                lev_g.push_back(x.level_g[j]);
+            }
+        }
+        if (x.kind == LRT_KIND_MOLECULE) {
+            if (x.n_el < 1 || !x.el_T || !x.el_g || !x.el_nv || !x.el_Jmax || !x.vib_G || !x.vib_B || !x.vib_D)
+                return fail(c, LRT_E_ARG, "species %d: molecule needs electronic / vibrational tables", s);
+            int64_t pos = 0;
+            for (int e = 0; e < x.n_el; ++e) {
+                if (x.el_nv[e] < 1 || x.el_Jmax[e] < 0 || !std::isfinite(x.el_T[e]) || !(x.el_g[e] > 0.0))
+                    return fail(c, LRT_E_ARG, "species %d state %d: bad electronic entry", s, e);
+                el_T.push_back(x.el_T[e]);
+                el_g.push_back(x.el_g[e]);
+                el_J.push_back(x.el_Jmax[e]);
+                for (int v = 0; v < x.el_nv[e]; ++v, ++pos) {
+                    if (!std::isfinite(x.vib_G[pos]) || !std::isfinite(x.vib_B[pos]) || !std::isfinite(x.vib_D[pos]))
+                        return fail(c, LRT_E_ARG, "species %d: non-finite vibrational entry", s);
+                    vib_G.push_back(x.vib_G[pos]);
+                    vib_B.push_back(x.vib_B[pos]);
+                    vib_D.push_back(x.vib_D[pos]);
+                }
+                vib_off.push_back((int64_t)vib_G.size());
+            }
+        }
+        lev_off.push_back((int64_t)lev_E.size());
+        el_off.push_back((int64_t)el_T.size());
+        if (x.kind != LRT_KIND_NONE) M_min = std::min(M_min, x.mass);
+    }
+    lrt_status st;
+    if ((st = upload_vec(c, c->d_kind, kind)) || (st = upload_vec(c, c->d_mass, mass)) ||
+        (st = upload_vec(c, c->d_lev_off, lev_off)) || (st = upload_vec(c, c->d_lev_E, lev_E)) ||
+        (st = upload_vec(c, c->d_lev_g, lev_g)) || (st = upload_vec(c, c->d_el_off, el_off)) ||
+        (st = upload_vec(c, c->d_el_T, el_T)) || (st = upload_vec(c, c->d_el_g, el_g)) ||
+        (st = upload_vec(c, c->d_el_J, el_J)) || (st = upload_vec(c, c->d_vib_off, vib_off)) ||
+        (st = upload_vec(c, c->d_vib_G, vib_G)) || (st = upload_vec(c, c->d_vib_B, vib_B)) ||
+        (st = upload_vec(c, c->d_vib_D, vib_D)))
+        return st;
+    c->n_species = n;
+    c->sp_kind = kind;
+    c->sp_mass = mass;
+    c->M_min = std::isfinite(M_min) ? M_min : 1.0;
+    c->sp = DevSpecies{n, c->d_kind.as<int32_t>(), c->d_mass.as<double>(), c->d_lev_off.as<int64_t>(),
+                       c->d_lev_E.as<double>(), c->d_lev_g.as<double>(), c->d_el_off.as<int64_t>(),
+                       c->d_el_T.as<double>(), c->d_el_g.as<double>(), c->d_el_J.as<int32_t>(),
+                       c->d_vib_off.as<int64_t>(), c->d_vib_G.as<double>(), c->d_vib_B.as<double>(),
+                       c->d_vib_D.as<double>()};
+    c->thermo_ready = c->scale_ready = false;
+    c->n_lines = -1;   // lines refer to species indices: must be set again
+    c->n_cells = -1;
+    return LRT_OK;
+}
+
+lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *L)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (c->n_species < 1) return fail(c, LRT_E_STATE, "set species before lines");
+    if (!L || L->n < 0) return fail(c, LRT_E_ARG, "lines NULL or negative count");
+    if (L->n >= INT_MAX) return fail(c, LRT_E_ARG, "at most 2^31-2 lines");
+    const int64_t n = L->n;
+    if (n > 0 && (!L->nu0 || !L->A || !L->Eu_ev || !L->Eu_rot || !L->El_ev || !L->El_rot || !L->gu ||
+                  !L->gl || !L->species))
+        return fail(c, LRT_E_ARG, "line arrays must be non-NULL");
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(L->nu0[i] > 0.0) || !std::isfinite(L->nu0[i]))
+            return fail(c, LRT_E_ARG, "line %lld: nu0 must be positive and finite", (long long)i);
+        if (!(L->A[i] >= 0.0) || !std::isfinite(L->A[i]))
+            return fail(c, LRT_E_ARG, "line %lld: A must be >= 0", (long long)i);
+        if (!(L->gu[i] >= 1.0) || !(L->gl[i] >= 1.0) || !std::isfinite(L->gu[i]) || !std::isfinite(L->gl[i]))
+            return fail(c, LRT_E_ARG, "line %lld: degeneracies must be >= 1", (long long)i);
+        if (!std::isfinite(L->Eu_ev[i]) || !std::isfinite(L->Eu_rot[i]) || !std::isfinite(L->El_ev[i]) ||
+            !std::isfinite(L->El_rot[i]))
+            return fail(c, LRT_E_ARG, "line %lld: non-finite level energy", (long long)i);
+        const int s = L->species[i];
+        if (s < 0 || s >= c->n_species || c->sp_kind[s] == LRT_KIND_NONE)
+            return fail(c, LRT_E_ARG, "line %lld: species %d is not a radiating species", (long long)i, s);
+    }
+    std::vector<int64_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return L->nu0[a] < L->nu0[b]; });
+    std::vector<double> nu0(n), A(n), Eue(n), Eur(n), Ele(n), Elr(n), lngu(n);
+    std::vector<int32_t> spc(n);
+    for (int64_t j = 0; j < n; ++j) {
+        const int64_t i = idx[j];
+        nu0[j] = L->nu0[i];
+        A[j] = L->A[i];
+        Eue[j] = L->Eu_ev[i];
+        Eur[j] = L->Eu_rot[i];
+        Ele[j] = L->El_ev[i];
+        Elr[j] = L->El_rot[i];
+        lngu[j] = std::log(L->gu[i]);
+        spc[j] = L->species[i];
+    }
+    lrt_status st;
+    if ((st = upload_vec(c, c->d_nu0, nu0)) || (st = upload_vec(c, c->d_A, A)) ||
+        (st = upload_vec(c, c->d_Eu_ev, Eue)) || (st = upload_vec(c, c->d_Eu_rot, Eur)) ||
+        (st = upload_vec(c, c->d_El_ev, Ele)) || (st = upload_vec(c, c->d_El_rot, Elr)) ||
+        (st = upload_vec(c, c->d_lngu, lngu)) || (st = upload_vec(c, c->d_species, spc)))
+        return st;
+    c->h_nu0.swap(nu0);
+    c->n_lines = n;
+    c->lines_grid_ready = false;
+    c->scale_ready = false;
+    return LRT_OK;
+}
+
+lrt_status lrt_set_grid(lrt_ctx *c, double nu_min, double nu_max, int64_t n_points, int64_t band_points)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (!(nu_min > 0.0) || !(nu_max > nu_min) || !std::isfinite(nu_max))
+        return fail(c, LRT_E_ARG, "grid needs 0 < nu_min < nu_max");
+    if (n_points < 2 || n_points >= ((int64_t)1 << 31))
+        return fail(c, LRT_E_ARG, "n_points must be in [2, 2^31)");
+    if (band_points < 1) return fail(c, LRT_E_ARG, "band_points must be >= 1");
+    c->nu_min = nu_min;
+    c->nu_max = nu_max;
+    c->n_points = n_points;
+    c->band_points = std::min(band_points, n_points);
+    c->h = (nu_max - nu_min) / (double)(n_points - 1);
+    c->have_grid = true;
+    c->lines_grid_ready = false;
+    c->scale_ready = false;
+    return LRT_OK;
+}
+
+lrt_status lrt_set_cells(lrt_ctx *c, const lrt_cells *x)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (c->n_species < 1) return fail(c, LRT_E_STATE, "set species before cells");
+    if (!x || x->n_cells < 1) return fail(c, LRT_E_ARG, "cells NULL or empty");
+    if (x->n_cells >= INT_MAX) return fail(c, LRT_E_ARG, "too many cells");
+    if (x->n_species != c->n_species)
+        return fail(c, LRT_E_ARG, "cells have %d species, table has %d", x->n_species, c->n_species);
+    if (!x->T_tr || !x->T_v || !x->N || !x->n_e) return fail(c, LRT_E_ARG, "cell arrays must be non-NULL");
+    const int64_t nc = x->n_cells, S = x->n_species;
+    for (int64_t i = 0; i < nc; ++i) {
+        if (!(x->T_tr[i] > 0.0) || !(x->T_v[i] > 0.0) || !std::isfinite(x->T_tr[i]) || !std::isfinite(x->T_v[i]))
+            return fail(c, LRT_E_ARG, "cell %lld: temperatures must be positive and finite", (long long)i);
+        if (!(x->n_e[i] >= 0.0) || !std::isfinite(x->n_e[i]))
+            return fail(c, LRT_E_ARG, "cell %lld: n_e must be >= 0", (long long)i);
+        for (int64_t s = 0; s < S; ++s)
+            if (!(x->N[i * S + s] >= 0.0) || !std::isfinite(x->N[i * S + s]))
+                return fail(c, LRT_E_ARG, "cell %lld species %lld: N must be >= 0", (long long)i, (long long)s);
+    }
+    lrt_status st;
+    if ((st = upload(c, c->d_T_tr, x->T_tr, nc * 8)) || (st = upload(c, c->d_T_v, x->T_v, nc * 8)) ||
+        (st = upload(c, c->d_N, x->N, nc * S * 8)) || (st = upload(c, c->d_n_e, x->n_e, nc * 8)) ||
+        (st = upload(c, c->d_cc, nullptr, nc * sizeof(CellConst))) ||
+        (st = upload(c, c->d_cs, nullptr, nc * S * sizeof(CellSpecies))) ||
+        (st = upload(c, c->d_emax, nullptr, nc * 2 * sizeof(int32_t))) ||
+        (st = upload(c, c->d_escale, nullptr, nc * 2 * sizeof(int32_t))))
+        return st;
+    c->n_cells = nc;
+    c->thermo_ready = false;
+    c->scale_ready = false;
+    return LRT_OK;
+}
+
+static lrt_status upload_rays(lrt_ctx *c)
+{
+    lrt_status st;
+    if ((st = upload_vec(c, c->d_off, c->h_off)) || (st = upload_vec(c, c->d_cell, c->h_cell)) ||
+        (st = upload_vec(c, c->d_ds, c->h_ds)) || (st = upload_vec(c, c->d_weight, c->h_weight)) ||
+        (st = upload_vec(c, c->d_wall_off, c->h_wall_off)))
+        return st;
+    return LRT_OK;
+}
+
+lrt_status lrt_set_rays_slab(lrt_ctx *c, int64_t n_cells, const double *dx, int n_mu)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (n_cells < 1 || n_cells >= INT_MAX || !dx || n_mu < 0)
+        return fail(c, LRT_E_ARG, "slab needs n_cells >= 1, dx, n_mu >= 0");
+    for (int64_t i = 0; i < n_cells; ++i)
+        if (!(dx[i] > 0.0) || !std::isfinite(dx[i])) return fail(c, LRT_E_ARG, "dx[%lld] must be positive", (long long)i);
+    std::vector<double> mu, w;
+    if (n_mu > 0) gauss_legendre_01(n_mu, mu, w);
+    c->h_off.assign(1, 0);
+    c->h_cell.clear();
+    c->h_ds.clear();
+    c->h_weight.clear();
+    c->h_ray_wall.clear();
+    for (int r = 0; r <= n_mu; ++r) {
+        const double m = (r == 0) ? 1.0 : mu[r - 1];
+        for (int64_t i = 0; i < n_cells; ++i) {
+            c->h_cell.push_back((int32_t)i);
+            c->h_ds.push_back(r == 0 ? dx[i] : dx[i] / m);
+        }
+        c->h_off.push_back((int64_t)c->h_cell.size());
+        c->h_weight.push_back(r == 0 ? 0.0 : 2.0 * kPi * w[r - 1] * mu[r - 1]);
+        c->h_ray_wall.push_back(0);
+    }
+    c->h_wall_off = {0, (int64_t)n_mu + 1};
+    lrt_status st = upload_rays(c);
+    if (st) return st;
+    c->n_rays = n_mu + 1;
+    c->n_wall = 1;
+    c->rays_cells = n_cells;
+    return LRT_OK;
+}
+
+lrt_status lrt_set_rays_axi(lrt_ctx *c, int nx, int nr, double Lx, double R, int n_wall,
+                            const double *wall_r, int n_mu, int n_phi)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (nx < 1 || nr < 1 || !(Lx > 0.0) || !(R > 0.0) || n_wall < 1 || !wall_r || n_mu < 1 || n_phi < 1)
+        return fail(c, LRT_E_ARG, "axisymmetric rays need positive sizes");
+    if ((int64_t)nx * nr >= INT_MAX) return fail(c, LRT_E_ARG, "grid too large");
+    for (int w = 0; w < n_wall; ++w)
+        if (!(wall_r[w] >= 0.0) || !(wall_r[w] < R)) return fail(c, LRT_E_ARG, "wall_r[%d] outside [0, R)", w);
+    std::vector<double> mu, W;
+    gauss_legendre_01(n_mu, mu, W);
+    c->h_off.assign(1, 0);
+    c->h_cell.clear();
+    c->h_ds.clear();
+    c->h_weight.clear();
+    c->h_ray_wall.clear();
+    c->h_wall_off.assign(1, 0);
+    std::vector<int32_t> cell;
+    std::vector<double> ds;
+    // phi_j and 2 pi - phi_j = phi_{n_phi-1-j} give identical segment lists
+    // (rho(s) depends on cos phi and sin^2 phi): trace j < n_phi/2 with twice
+    // the weight, plus the self-symmetric middle azimuth when n_phi is odd.
+    const int n_half = (n_phi + 1) / 2;
+    for (int w = 0; w < n_wall; ++w) {
+        for (int i = 0; i < n_mu; ++i) {
+            for (int j = 0; j < n_half; ++j) {
+                const double phi = (j + 0.5) * 2.0 * kPi / n_phi;
+                const double mult = (2 * j + 1 == n_phi) ? 1.0 : 2.0;
+                cell.clear();
+                ds.clear();
+                if (!traverse_axi(nx, nr, Lx, R, wall_r[w], mu[i], phi, cell, ds))
+                    return fail(c, LRT_E_ARG, "ray traversal did not terminate (wall %d, mu %d, phi %d)", w, i, j);
+                for (int64_t m = (int64_t)cell.size() - 1; m >= 0; --m) {   // far -> wall
+                    c->h_cell.push_back(cell[m]);
+                    c->h_ds.push_back(ds[m]);
+                }
+                c->h_off.push_back((int64_t)c->h_cell.size());
+                c->h_weight.push_back(mult * W[i] * mu[i] * 2.0 * kPi / n_phi);
+                c->h_ray_wall.push_back(w);
+            }
+        }
+        c->h_wall_off.push_back((int64_t)c->h_weight.size());
+    }
+    lrt_status st = upload_rays(c);
+    if (st) return st;
+    c->n_rays = (int64_t)c->h_weight.size();
+    c->n_wall = n_wall;
+    c->rays_cells = (int64_t)nx * nr;
+    return LRT_OK;
+}
+
+lrt_status lrt_trace_axi_ray(int nx, int nr, double Lx, double R, double rw, double mu, double phi,
+                             int64_t cap, int32_t *cell, double *ds, int64_t *n)
+{
+    if (nx < 1 || nr < 1 || !(Lx > 0.0) || !(R > 0.0) || !(rw >= 0.0) || !(rw < R) || !(mu > 0.0) ||
+        !(mu <= 1.0) || !std::isfinite(phi) || !n || (cap > 0 && (!cell || !ds)))
+        return fail(nullptr, LRT_E_ARG, "trace: invalid geometry or direction");
+    std::vector<int32_t> cv;
+    std::vector<double> dv;
+    if (!traverse_axi(nx, nr, Lx, R, rw, mu, phi, cv, dv))
+        return fail(nullptr, LRT_E_ARG, "trace: traversal did not terminate");
+    const int64_t m = (int64_t)cv.size();
+    *n = m;
+    if (cap < m) return fail(nullptr, LRT_E_ARG, "trace: capacity %lld < %lld", (long long)cap, (long long)m);
+    for (int64_t i = 0; i < m; ++i) {   // far -> wall
+        cell[i] = cv[m - 1 - i];
+        ds[i] = dv[m - 1 - i];
+    }
+    return LRT_OK;
+}
+
+lrt_status lrt_get_sizes(const lrt_ctx *c, int64_t *n_cells, int64_t *n_rays, int64_t *n_wall,
+                         int64_t *n_points, int64_t *n_bands, int64_t *band_points)
+{
+    if (!c) return LRT_E_ARG;
+    if (n_cells) *n_cells = c->n_cells;
+    if (n_rays) *n_rays = c->n_rays;
+    if (n_wall) *n_wall = c->n_wall;
+    if (n_points) *n_points = c->have_grid ? c->n_points : 0;
+    if (band_points) *band_points = c->have_grid ? c->band_points : 0;
+    if (n_bands) *n_bands = c->have_grid ? (c->n_points + c->band_points - 1) / c->band_points : 0;
+    return LRT_OK;
+}
+
+lrt_status lrt_get_ray(const lrt_ctx *cc, int64_t r, int64_t cap, int32_t *cell, double *ds, int64_t *n,
+                       double *weight, int64_t *wall)
+{
+    lrt_ctx *c = const_cast<lrt_ctx *>(cc);
+    if (!c) return LRT_E_ARG;
+    if (r < 0 || r >= c->n_rays) return fail(c, LRT_E_ARG, "ray %lld out of range", (long long)r);
+    const int64_t a = c->h_off[r], b = c->h_off[r + 1];
+    if (n) *n = b - a;
+    if (weight) *weight = c->h_weight[r];
+    if (wall) *wall = c->h_ray_wall[r];
+    if (cell || ds) {
+        if (cap < b - a) return fail(c, LRT_E_ARG, "capacity %lld < %lld segments", (long long)cap, (long long)(b - a));
+        for (int64_t m = a; m < b; ++m) {
+            if (cell) cell[m - a] = c->h_cell[m];
+            if (ds) ds[m - a] = c->h_ds[m];
+        }
+    }
+    return LRT_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// preparation and the compute entry points
+// ===========================================================================
+
+namespace {
+
+lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force = false)
+{
+    if (force) {
+        c->thermo_ready = false;
+        c->scale_ready = false;
+    }
+    if (c->n_species < 1) return fail(c, LRT_E_STATE, "species not set");
+    if (c->n_lines < 0) return fail(c, LRT_E_STATE, "lines not set");
+    if (!c->have_grid) return fail(c, LRT_E_STATE, "grid not set");
+    if (c->n_cells < 1) return fail(c, LRT_E_STATE, "cells not set");
+    if (!c->lines_grid_ready) {
+        // nu0 = nu_min + k0 h + frac0 with frac0 correctly rounded: k0 h and
+        // nu_min + k0 h are carried as unevaluated sums (two-product by fma,
+        // two-sum), so frac0 is the difference of nu0 and the exact grid point.
+        const int64_t n = c->n_lines;
+        std::vector<int32_t> k0(n);
+        std::vector<double> fr(n);
+        for (int64_t i = 0; i < n; ++i) {
+            const double nu0 = c->h_nu0[i];
+            double kk = std::nearbyint((nu0 - c->nu_min) / c->h);
+            kk = std::max(-16777216.0, std::min(16777216.0, kk));
+            const double p = kk * c->h;
+            const double pe = std::fma(kk, c->h, -p);
+            const double s = c->nu_min + p;
+            const double bb = s - c->nu_min;
+            const double se = (c->nu_min - (s - bb)) + (p - bb);
+            fr[i] = (nu0 - s) - (se + pe);
+            k0[i] = (int32_t)kk;
+        }
+        lrt_status r;
+        if ((r = upload_vec(c, c->d_k0, k0)) || (r = upload_vec(c, c->d_frac0, fr))) return r;
+        c->lines_grid_ready = true;
+    }
+    if (!c->thermo_ready) {
+        DevCells cells{(int32_t)c->n_cells, c->n_species, c->d_T_tr.as<double>(), c->d_T_v.as<double>(),
+                       c->d_N.as<double>(), c->d_n_e.as<double>()};
+        LRT_HIP(c, timed(c, LRT_K_THERMO, st, [&] {
+                    return launch_thermo(c->sp, cells, c->M_min, c->d_cc.as<CellConst>(),
+                                         c->d_cs.as<CellSpecies>(), st);
+                }));
+        c->thermo_ready = true;
+    }
+    if (need_scale && !c->scale_ready) {
+        DevLines L{c->n_lines, c->d_nu0.as<double>(), c->d_A.as<double>(), c->d_Eu_ev.as<double>(),
+                   c->d_Eu_rot.as<double>(), c->d_El_ev.as<double>(), c->d_El_rot.as<double>(),
+                   c->d_lngu.as<double>(), c->d_species.as<int32_t>(), c->d_k0.as<int32_t>(),
+                   c->d_frac0.as<double>()};
+        DevGrid g{c->nu_min, c->h, (int32_t)c->n_points};
+        LRT_HIP(c, launch_fill_i32(c->d_emax.as<int32_t>(), INT_MIN, 2 * c->n_cells, st));
+        LRT_HIP(c, timed(c, LRT_K_SCALE, st, [&] {
+                    return launch_scale(L, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
+                                        (int32_t)c->n_cells, c->n_species, c->d_emax.as<int32_t>(),
+                                        c->d_escale.as<int32_t>(), st);
+                }));
+        c->scale_ready = true;
+    }
+    return LRT_OK;
+}
+
+DevLines dev_lines(const lrt_ctx *c)
+{
+    return DevLines{c->n_lines, c->d_nu0.as<double>(), c->d_A.as<double>(), c->d_Eu_ev.as<double>(),
+                    c->d_Eu_rot.as<double>(), c->d_El_ev.as<double>(), c->d_El_rot.as<double>(),
+                    c->d_lngu.as<double>(), c->d_species.as<int32_t>(), c->d_k0.as<int32_t>(),
+                    c->d_frac0.as<double>()};
+}
+
+lrt_status band_range(lrt_ctx *c, int64_t band, int32_t &k_first, int32_t &n_band)
+{
+    const int64_t nb = (c->n_points + c->band_points - 1) / c->band_points;
+    if (band < 0 || band >= nb) return fail(c, LRT_E_ARG, "band %lld out of range [0, %lld)", (long long)band, (long long)nb);
+    k_first = (int32_t)(band * c->band_points);
+    n_band = (int32_t)std::min<int64_t>(c->band_points, c->n_points - k_first);
+    return LRT_OK;
+}
+
+lrt_status coeffs_impl(lrt_ctx *c, int64_t band, lrt_precision prec, void *eta, void *kappa,
+                       int32_t *escale, hipStream_t st)
+{
+    if (prec != LRT_FP64 && prec != LRT_FP32_COMP) return fail(c, LRT_E_ARG, "unknown precision %d", (int)prec);
+    if (!eta || !kappa) return fail(c, LRT_E_ARG, "eta and kappa must be non-NULL");
+    lrt_status r;
+    if ((r = prepare(c, st, prec == LRT_FP32_COMP))) return r;
+    int32_t k_first, n_band;
+    if ((r = band_range(c, band, k_first, n_band))) return r;
+    const int32_t n_tiles = (n_band + kTilePoints - 1) / kTilePoints;
+    if ((r = ensure(c, c->w_ranges, (size_t)c->n_cells * n_tiles * sizeof(int2)))) return r;
+    const DevLines L = dev_lines(c);
+    const DevGrid g{c->nu_min, c->h, (int32_t)c->n_points};
+    const int32_t nc = (int32_t)c->n_cells;
+    LRT_HIP(c, timed(c, LRT_K_RANGES, st, [&] {
+                return launch_ranges(L, g, c->d_cc.as<CellConst>(), nc, k_first, n_band, kTilePoints,
+                                     c->w_ranges.as<int2>(), st);
+            }));
+    if (prec == LRT_FP32_COMP) {
+        LRT_HIP(c, timed(c, LRT_K_ACCUM, st, [&] {
+                    return launch_accum_f32(L, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
+                                            c->d_escale.as<int32_t>(), c->w_ranges.as<int2>(), nc,
+                                            c->n_species, k_first, n_band, (float *)eta, (float *)kappa, st);
+                }));
+        if (escale)
+            LRT_HIP(c, hipMemcpyAsync(escale, c->d_escale.p, (size_t)nc * 2 * sizeof(int32_t),
+                                      hipMemcpyDeviceToDevice, st));
+    } else {
+        LRT_HIP(c, timed(c, LRT_K_ACCUM, st, [&] {
+                    return launch_accum_f64(L, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
+                                            c->w_ranges.as<int2>(), nc, c->n_species, k_first, n_band,
+                                            (double *)eta, (double *)kappa, st);
+                }));
+    }
+    return LRT_OK;
+}
+
+lrt_status march_impl(lrt_ctx *c, int64_t band, lrt_precision prec, const void *eta, const void *kappa,
+                      const int32_t *escale, double *I_out, double *I_int_out, hipStream_t st)
+{
+    if (prec != LRT_FP64 && prec != LRT_FP32_COMP) return fail(c, LRT_E_ARG, "unknown precision %d", (int)prec);
+    if (!eta || !kappa || !I_int_out) return fail(c, LRT_E_ARG, "eta, kappa and I_int_out must be non-NULL");
+    if (prec == LRT_FP32_COMP && !escale) return fail(c, LRT_E_ARG, "escale required for LRT_FP32_COMP");
+    if (c->n_rays < 1) return fail(c, LRT_E_STATE, "rays not set");
+    if (!c->have_grid) return fail(c, LRT_E_STATE, "grid not set");
+    if (c->n_cells < 1) return fail(c, LRT_E_STATE, "cells not set");
+    if (c->rays_cells != c->n_cells)
+        return fail(c, LRT_E_STATE, "rays expect %lld cells, %lld set", (long long)c->rays_cells, (long long)c->n_cells);
+    int32_t k_first, n_band;
+    lrt_status r;
+    if ((r = band_range(c, band, k_first, n_band))) return r;
+    const int32_t n_chunks = (n_band + kMarchPoints - 1) / kMarchPoints;
+    if ((r = ensure(c, c->w_partials, (size_t)c->n_rays * n_chunks * sizeof(double)))) return r;
+    const DevRays rays{(int32_t)c->n_rays, c->d_off.as<int64_t>(), c->d_cell.as<int32_t>(), c->d_ds.as<double>()};
+    const DevGrid g{c->nu_min, c->h, (int32_t)c->n_points};
+    LRT_HIP(c, timed(c, LRT_K_MARCH, st, [&] {
+                return launch_march(prec == LRT_FP32_COMP, rays, g, k_first, n_band, eta, kappa, escale,
+                                    I_out, c->w_partials.as<double>(), n_chunks, st);
+            }));
+    LRT_HIP(c, launch_reduce_rows(c->w_partials.as<double>(), (int32_t)c->n_rays, n_chunks, I_int_out, st));
+    return LRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lrt_status lrt_coeffs(lrt_ctx *c, int64_t band, lrt_precision prec, void *eta, void *kappa,
+                      int32_t *escale, void *stream)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    return coeffs_impl(c, band, prec, eta, kappa, escale, (hipStream_t)stream);
+}
+
+lrt_status lrt_march(lrt_ctx *c, int64_t band, lrt_precision prec, const void *eta, const void *kappa,
+                     const int32_t *escale, double *I_out, double *I_int_out, void *stream)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    return march_impl(c, band, prec, eta, kappa, escale, I_out, I_int_out, (hipStream_t)stream);
+}
+
+lrt_status lrt_solve(lrt_ctx *c, lrt_precision prec, int64_t first_band, double *q, double *I_int,
+                     double *q_band, void *stream)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    hipStream_t st = (hipStream_t)stream;
+    if (prec != LRT_FP64 && prec != LRT_FP32_COMP) return fail(c, LRT_E_ARG, "unknown precision %d", (int)prec);
+    if (!c->have_grid) return fail(c, LRT_E_STATE, "grid not set");
+    if (c->n_rays < 1) return fail(c, LRT_E_STATE, "rays not set");
+    const int64_t nb = (c->n_points + c->band_points - 1) / c->band_points;
+    if (first_band < 0 || first_band >= nb) return fail(c, LRT_E_ARG, "first_band out of range");
+    const size_t esz = prec == LRT_FP64 ? 8 : 4;
+    const size_t plane = (size_t)std::max<int64_t>(c->n_cells, 1) * c->band_points * esz;
+    lrt_status r;
+    if ((r = ensure(c, c->w_eta, plane)) || (r = ensure(c, c->w_kappa, plane)) ||
+        (r = ensure(c, c->w_Iband, (size_t)c->n_rays * 8)) || (r = ensure(c, c->w_Itot, (size_t)c->n_rays * 8)) ||
+        (r = ensure(c, c->w_qband, (size_t)c->n_wall * nb * 8)))
+        return r;
+    // zero the accumulators (all-zero bits are +0.0)
+    LRT_HIP(c, launch_fill_u64(c->w_Itot.as<unsigned long long>(), 0ull, c->n_rays, st));
+    LRT_HIP(c, launch_fill_u64(c->w_qband.as<unsigned long long>(), 0ull, c->n_wall * nb, st));
+    int32_t *esc = (prec == LRT_FP32_COMP) ? c->d_escale.as<int32_t>() : nullptr;
+    // populations and scales belong to the path: recompute them on every call
+    if ((r = prepare(c, st, prec == LRT_FP32_COMP, true))) return r;
+    for (int64_t b = first_band; b < nb; ++b) {
+        if ((r = coeffs_impl(c, b, prec, c->w_eta.p, c->w_kappa.p, nullptr, st))) return r;
+        if ((r = march_impl(c, b, prec, c->w_eta.p, c->w_kappa.p, esc, nullptr, c->w_Iband.as<double>(), st)))
+            return r;
+        LRT_HIP(c, launch_add(c->w_Itot.as<double>(), c->w_Iband.as<double>(), (int32_t)c->n_rays, st));
+        // per-band wall flux into row b of the [n_bands][n_wall] staging array
+        LRT_HIP(c, launch_wall_sum(c->w_Iband.as<double>(), c->d_weight.as<double>(), c->d_wall_off.as<int64_t>(),
+                                   (int32_t)c->n_wall, c->w_qband.as<double>() + b * c->n_wall, st));
+    }
+    std::vector<double> qb((size_t)c->n_wall * nb), it((size_t)c->n_rays);
+    LRT_HIP(c, hipMemcpyAsync(qb.data(), c->w_qband.p, qb.size() * 8, hipMemcpyDeviceToHost, st));
+    LRT_HIP(c, hipMemcpyAsync(it.data(), c->w_Itot.p, it.size() * 8, hipMemcpyDeviceToHost, st));
+    LRT_HIP(c, hipStreamSynchronize(st));
+    for (int64_t w = 0; w < c->n_wall; ++w) {
+        double s = 0.0;
+        for (int64_t b = first_band; b < nb; ++b) {
+            s += qb[b * c->n_wall + w];
+            if (q_band) q_band[w * nb + b] = qb[b * c->n_wall + w];
+        }
+        if (q) q[w] = s;
+    }
+    if (I_int) std::copy(it.begin(), it.end(), I_int);
+    return LRT_OK;
+}
+
+lrt_status lrt_count_terms(lrt_ctx *c, int64_t band, int64_t *count, void *stream)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (!count) return fail(c, LRT_E_ARG, "count must be non-NULL");
+    hipStream_t st = (hipStream_t)stream;
+    lrt_status r;
+    if ((r = prepare(c, st, false))) return r;
+    int32_t k_first, n_band;
+    if ((r = band_range(c, band, k_first, n_band))) return r;
+    if ((r = ensure(c, c->w_count, 8))) return r;
+    LRT_HIP(c, launch_fill_u64(c->w_count.as<unsigned long long>(), 0ull, 1, st));
+    const DevGrid g{c->nu_min, c->h, (int32_t)c->n_points};
+    LRT_HIP(c, launch_count(dev_lines(c), g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
+                            (int32_t)c->n_cells, c->n_species, k_first, n_band,
+                            c->w_count.as<unsigned long long>(), st));
+    unsigned long long v = 0;
+    LRT_HIP(c, hipMemcpyAsync(&v, c->w_count.p, 8, hipMemcpyDeviceToHost, st));
+    LRT_HIP(c, hipStreamSynchronize(st));
+    *count = (int64_t)v;
+    return LRT_OK;
+}
+
+lrt_status lrt_profile(lrt_ctx *c, int enable)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    LRT_HIP(c, hipDeviceSynchronize());
+    c->clear_events();
+    c->prof = enable != 0;
+    return LRT_OK;
+}
+
+lrt_status lrt_profile_read(lrt_ctx *c, int kernel, double *ms, int64_t *launches)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (kernel < 0 || kernel >= LRT_K_COUNT) return fail(c, LRT_E_ARG, "unknown kernel id %d", kernel);
+    double tot = 0.0;
+    for (auto &p : c->ev[kernel]) {
+        LRT_HIP(c, hipEventSynchronize(p.second));
+        float t = 0.0f;
+        LRT_HIP(c, hipEventElapsedTime(&t, p.first, p.second));
+        tot += t;
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = (int64_t)c->ev[kernel].size();
+    return LRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// Internal declarations shared by the host side (lrt_host.cpp) and the
+// gfx950 kernels (lrt_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lrt {
+
+// CODATA exact constants in CGS units.
+constexpr double kPlanck = 6.62607015e-27;  // erg s
+constexpr double kLight = 2.99792458e10;    // cm s^-1
+constexpr double kBoltz = 1.380649e-16;     // erg K^-1
+constexpr double kC2 = kPlanck * kLight / kBoltz;  // second radiation constant, cm K
+constexpr double kPi = 3.14159265358979323846;
+
+// Accumulation tile: 4 waves of 64 lanes, each lane owns kPPL grid points,
+// one workgroup owns 256 * kPPL consecutive points of one cell.
+constexpr int kAccumThreads = 256;
+constexpr int kPPL = 4;
+constexpr int kTilePoints = kAccumThreads * kPPL;
+// Line records staged in LDS per round.
+constexpr int kStage = 256;
+
+// March tile: 256 threads x 4 points.
+constexpr int kMarchThreads = 256;
+constexpr int kMarchPPT = 4;
+constexpr int kMarchPoints = kMarchThreads * kMarchPPT;
+
+// Species level tables on the device (flattened).
+struct DevSpecies {
+    int n;
+    const int32_t *kind;
+    const double *mass;
+    const int64_t *lev_off;   // [n+1]
+    const double *lev_E, *lev_g;
+    const int64_t *el_off;    // [n+1]
+    const double *el_T, *el_g;
+    const int32_t *el_Jmax;
+    const int64_t *vib_off;   // [n_el_total+1]
+    const double *vib_G, *vib_B, *vib_D;
+};
+
+// Line list on the device, sorted by nu0, structure of arrays.
+struct DevLines {
+    int64_t n;
+    const double *nu0, *A, *Eu_ev, *Eu_rot, *El_ev, *El_rot, *lngu;
+    const int32_t *species;
+    // grid-relative centre: nu0 = nu_min + k0 h + frac0 (frac0 exact to a
+    // few units of its last place)
+    const int32_t *k0;
+    const double *frac0;
+};
+
+struct DevGrid {
+    double nu_min, h;
+    int32_t n_points;
+};
+
+struct DevCells {
+    int32_t n_cells, n_species;
+    const double *T_tr, *T_v, *N, *n_e;
+};
+
+// Per-cell constants written by the thermo kernel.
+struct CellConst {
+    double beta_v, beta_tr;  // c2 / T_v, c2 / T_tr
+    double gL;               // Lorentz HWHM, cm^-1
+    double cand_G, cand_A;   // line-skip bound: |nu - nu0| <= cand_G + cand_A nu0
+};
+
+// Per (cell, species) constants written by the thermo kernel.
+struct CellSpecies {
+    double lnNQ;   // ln(N_s / Q_s), -inf when the species carries no population
+    double dop;    // Doppler HWHM per unit nu0: (7.16233e-7/2) sqrt(T_tr / M_s)
+};
+
+// Rays on the device.
+struct DevRays {
+    int32_t n_rays;
+    const int64_t *off;     // [n_rays+1] into cell / ds
+    const int32_t *cell;
+    const double *ds;
+};
+
+// ---- kernel launchers (lrt_kernels.hip) ----
+hipError_t launch_thermo(const DevSpecies &sp, const DevCells &cells, double M_min,
+                         CellConst *cc, CellSpecies *cs, hipStream_t st);
+
+hipError_t launch_ranges(const DevLines &L, const DevGrid &g, const CellConst *cc,
+                         int32_t n_cells, int32_t k_first, int32_t n_band, int32_t tile_points,
+                         int2 *ranges, hipStream_t st);
+
+hipError_t launch_scale(const DevLines &L, const DevGrid &g, const CellConst *cc,
+                        const CellSpecies *cs, int32_t n_cells, int32_t n_species,
+                        int32_t *emax, int32_t *escale, hipStream_t st);
+
+hipError_t launch_accum_f32(const DevLines &L, const DevGrid &g, const CellConst *cc,
+                            const CellSpecies *cs, const int32_t *escale, const int2 *ranges,
+                            int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band,
+                            float *eta, float *kappa, hipStream_t st);
+
+hipError_t launch_accum_f64(const DevLines &L, const DevGrid &g, const CellConst *cc,
+                            const CellSpecies *cs, const int2 *ranges, int32_t n_cells,
+                            int32_t n_species, int32_t k_first, int32_t n_band, double *eta,
+                            double *kappa, hipStream_t st);
+
+hipError_t launch_count(const DevLines &L, const DevGrid &g, const CellConst *cc,
+                        const CellSpecies *cs, int32_t n_cells, int32_t n_species,
+                        int32_t k_first, int32_t n_band, unsigned long long *count,
+                        hipStream_t st);
+
+hipError_t launch_march(bool fp32, const DevRays &rays, const DevGrid &g, int32_t k_first,
+                        int32_t n_band, const void *eta, const void *kappa,
+                        const int32_t *escale, double *I_out, double *partials,
+                        int32_t n_chunks, hipStream_t st);
+
+hipError_t launch_reduce_rows(const double *partials, int32_t n_rows, int32_t n_cols,
+                              double *out, hipStream_t st);
+
+hipError_t launch_wall_sum(const double *I_int, const double *weight, const int64_t *wall_off,
+                           int32_t n_wall, double *q, hipStream_t st);
+
+hipError_t launch_add(double *acc, const double *x, int32_t n, hipStream_t st);
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st);
+
+}  // namespace lrt

@@ -1,0 +1,700 @@
+// gfx950 kernels of the line-by-line + ray-march path (arXiv 2604.11856).
+//
+//   thermo      per (cell, species): partition function, ln(N/Q), Doppler
+//               coefficient; per cell: beta's, Lorentz HWHM, line-skip bound
+//               (Sec. 2.1 Boltzmann populations, Sec. 2.2.1 widths)
+//   ranges      per (cell, tile): index range of the nu0-sorted lines that
+//               can reach the tile
+//   scale       per cell: power-of-two scale of the single-precision eta/kappa
+//   accum_*     per (cell, tile): stage per-(cell, line) setups in LDS (FP64),
+//               then every lane accumulates the Whiting-Voigt profile of each
+//               staged line at its own grid points (Sec. 2.2.1)
+//   march       per (ray, spectral chunk): cell-constant RTE march far -> wall
+//               with the spectral trapezoid fused in (Sec. 2.2.3)
+//   reduce/wall deterministic sums of per-block partials and of ray fluxes
+//
+// Everything is output-stationary: each output element has one owner, so no
+// atomics touch eta, kappa, I or the flux; sums run in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+#include "lrt_internal.h"
+
+namespace lrt {
+
+namespace {
+
+constexpr double kLog2e = 1.4426950408889634;
+
+// ---------------------------------------------------------------------------
+// a1: partition functions and per-cell constants (FP64)
+// ---------------------------------------------------------------------------
+
+__global__ void thermo_kernel(DevSpecies sp, DevCells cells, double M_min, CellConst *cc,
+                              CellSpecies *cs)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int S = cells.n_species;
+    if (t >= (int64_t)cells.n_cells * S) return;
+    const int c = (int)(t / S), s = (int)(t % S);
+    const double Tv = cells.T_v[c], Ttr = cells.T_tr[c];
+    const double bv = kC2 / Tv, br = kC2 / Ttr;
+    const int kind = sp.kind[s];
+    double Q = 0.0;
+    if (kind == 1) {
+        for (int64_t j = sp.lev_off[s]; j < sp.lev_off[s + 1]; ++j)
+            Q += sp.lev_g[j] * exp(-bv * sp.lev_E[j]);
+    } else if (kind == 2) {
+        for (int64_t e = sp.el_off[s]; e < sp.el_off[s + 1]; ++e) {
+            double qvr = 0.0;
+            for (int64_t v = sp.vib_off[e]; v < sp.vib_off[e + 1]; ++v) {
+                const double B = sp.vib_B[v], D = sp.vib_D[v];
+                double qr = 0.0;
+                for (int J = 0; J <= sp.el_Jmax[e]; ++J) {
+                    const double jj = (double)J * (J + 1.0);
+                    qr += (2.0 * J + 1.0) * exp(-br * (B * jj - D * jj * jj));
+                }
+                qvr += exp(-bv * sp.vib_G[v]) * qr;
+            }
+            Q += sp.el_g[e] * exp(-bv * sp.el_T[e]) * qvr;
+        }
+    }
+    const double N = cells.N[(int64_t)c * S + s];
+    CellSpecies o;
+    o.lnNQ = (kind != 0 && N > 0.0 && Q > 0.0) ? log(N) - log(Q) : -INFINITY;
+    o.dop = 7.16233e-7 / 2.0 * sqrt(Ttr / sp.mass[s]);
+    cs[t] = o;
+    if (s == 0) {
+        CellConst k;
+        k.beta_v = bv;
+        k.beta_tr = br;
+        k.gL = 1e-16 * cells.n_e[c] * pow(Tv / 1e4, 0.33);
+        // Voigt HWHM <= gL + gG, gG = dop(M) nu0 <= dop(M_min) nu0; widened.
+        k.cand_G = 100.0 * k.gL * (1.0 + 1e-6);
+        k.cand_A = 100.0 * (7.16233e-7 / 2.0) * sqrt(Ttr / M_min) * (1.0 + 1e-6);
+        cc[c] = k;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a2: one (cell, line) pair in FP64
+// ---------------------------------------------------------------------------
+
+struct PairF64 {
+    double se, sk;        // eta and kappa per unit profile shape (strength * norm)
+    double inv2g, r;      // 1 / (2 gamma_V), gamma_L / gamma_V
+    int32_t klo, khi;     // inclusive window, klo > khi when empty
+};
+
+__device__ __forceinline__ bool pair_setup(const DevLines &L, const DevGrid &g, const CellConst &k,
+                                           const CellSpecies *csc, int64_t i, PairF64 &p)
+{
+    const int s = L.species[i];
+    const CellSpecies q = csc[s];
+    if (!(q.lnNQ > -INFINITY)) {
+        p.klo = 1;
+        p.khi = 0;
+        p.se = p.sk = p.inv2g = p.r = 0.0;
+        return false;
+    }
+    const double nu0 = L.nu0[i], A = L.A[i];
+    const double Eu_ev = L.Eu_ev[i], Eu_rot = L.Eu_rot[i];
+    const double El_ev = L.El_ev[i], El_rot = L.El_rot[i];
+    const double base = q.lnNQ + L.lngu[i];
+    // N_u = N g_u e^{-E_u}/Q ; N_l g_u / g_l = N g_u e^{-E_l}/Q
+    const double Nu = exp(base - k.beta_v * Eu_ev - k.beta_tr * Eu_rot);
+    const double Nlg = exp(base - k.beta_v * El_ev - k.beta_tr * El_rot);
+    const double x = k.beta_v * (Eu_ev - El_ev) + k.beta_tr * (Eu_rot - El_rot);
+    // eta_i = (hc/4pi) N_u A nu0 phi (W); kappa_i = eta_i / B_line
+    //       = A (N_l g_u/g_l) (1 - e^{-x}) phi / (8 pi c nu0^2)
+    const double Seta = (1e-7 * kPlanck * kLight / (4.0 * kPi)) * nu0 * A * Nu;
+    const double Skap = A * Nlg * (-expm1(-x)) / ((8.0 * kPi * kLight) * nu0 * nu0);
+    // widths (Sec. 2.2.1): Doppler, Lorentz, Voigt (Olivero fit)
+    const double gG = q.dop * nu0;
+    const double gL = k.gL;
+    const double sum = gL + gG;
+    const double d = (gL - gG) / sum;
+    const double gV = (1.0 - 0.18121 * (1.0 - d * d)
+                       - (0.023665 * exp(0.6 * d) + 0.00418 * exp(-1.9 * d)) * sin(kPi * d)) * sum;
+    const double r = gL / gV;
+    const double norm = 1.0 / (2.0 * gV * (1.065 + 0.447 * r + 0.058 * r * r));
+    // window |nu_k - nu0| <= 100 gamma_V; rounding-exact operation order
+    const double W = __dmul_rn(100.0, gV);
+    double lo = ceil(__ddiv_rn(__dsub_rn(__dsub_rn(nu0, W), g.nu_min), g.h));
+    double hi = floor(__ddiv_rn(__dsub_rn(__dadd_rn(nu0, W), g.nu_min), g.h));
+    lo = fmax(lo, 0.0);
+    hi = fmin(hi, (double)(g.n_points - 1));
+    if (lo > hi) {
+        p.klo = 1;
+        p.khi = 0;
+    } else {
+        p.klo = (int32_t)lo;
+        p.khi = (int32_t)hi;
+    }
+    p.se = Seta * norm;
+    p.sk = Skap * norm;
+    p.inv2g = 1.0 / (2.0 * gV);
+    p.r = r;
+    return p.klo <= p.khi;
+}
+
+// ---------------------------------------------------------------------------
+// candidate line ranges per (cell, tile)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t lower_bound_dev(const double *a, int64_t n, double v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t m = lo + ((hi - lo) >> 1);
+        if (a[m] < v) lo = m + 1; else hi = m;
+    }
+    return lo;
+}
+
+__global__ void ranges_kernel(DevLines L, DevGrid g, const CellConst *cc, int32_t n_cells,
+                              int32_t k_first, int32_t n_band, int32_t tile_points,
+                              int32_t n_tiles, int2 *ranges)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_cells * n_tiles) return;
+    const int c = (int)(t / n_tiles), tile = (int)(t % n_tiles);
+    const CellConst k = cc[c];
+    const int32_t ka = k_first + tile * tile_points;
+    const int32_t kb = min(k_first + n_band, ka + tile_points) - 1;
+    const double nu_a = g.nu_min + (double)ka * g.h - g.h;
+    const double nu_b = g.nu_min + (double)kb * g.h + g.h;
+    const double lo = (nu_a - k.cand_G) / (1.0 + k.cand_A);
+    const double hi = (nu_b + k.cand_G) / (1.0 - k.cand_A);
+    int2 r;
+    r.x = (int)lower_bound_dev(L.nu0, L.n, lo);
+    r.y = (int)lower_bound_dev(L.nu0, L.n, hi);
+    ranges[t] = r;
+}
+
+// ---------------------------------------------------------------------------
+// per-cell power-of-two scale for the single-precision form
+// ---------------------------------------------------------------------------
+
+__global__ void scale_kernel(DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs,
+                             int32_t n_cells, int32_t n_species, int32_t *emax)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int c = blockIdx.y; c < n_cells; c += gridDim.y) {
+        int ee = INT_MIN, ek = INT_MIN;
+        if (i < L.n) {
+            PairF64 p;
+            if (pair_setup(L, g, cc[c], cs + (int64_t)c * n_species, i, p)) {
+                if (p.se != 0.0) ee = ilogb(p.se) + 1;
+                if (p.sk != 0.0) ek = ilogb(fabs(p.sk)) + 1;
+            }
+        }
+        // wave max, then one atomic per wave (max is order independent)
+        for (int o = 32; o > 0; o >>= 1) {
+            ee = max(ee, __shfl_xor(ee, o));
+            ek = max(ek, __shfl_xor(ek, o));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (ee != INT_MIN) atomicMax(&emax[2 * c + 0], ee);
+            if (ek != INT_MIN) atomicMax(&emax[2 * c + 1], ek);
+        }
+    }
+}
+
+__global__ void scale_finish_kernel(const int32_t *emax, int32_t n, int32_t *escale)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int e = emax[t];
+    // keep values unscaled while the largest line peak stays within 2^+-60
+    escale[t] = (e == INT_MIN || (e >= -60 && e <= 60)) ? 0 : e;
+}
+
+// ---------------------------------------------------------------------------
+// a3: line-to-grid accumulation
+// ---------------------------------------------------------------------------
+
+struct __align__(16) RecF32 {
+    int32_t klo, khi;
+    float k0f, hs, fs, r, se, sk;
+};
+
+struct __align__(16) RecF64 {
+    int32_t klo, khi, k0, pad;
+    double frac0, inv2g, r, se, sk, pad2;
+};
+
+// Profile shape P(x) of the Whiting form with x = |dk h - frac0| / (2 gamma_V):
+// (1-r) e^{-2.772 x^2} + r/(1+4x^2) + 0.016 r(1-r)[e^{-0.4 x^2.25} - 1/(1+0.1 x^2.25)],
+// the two rational terms over one reciprocal.
+__device__ __forceinline__ float shape_f32(float x, float r)
+{
+    const float u = x * x;
+    const float g = __builtin_amdgcn_exp2f(u * (float)(-2.772 * kLog2e));
+    const float p = __builtin_amdgcn_exp2f(2.25f * __builtin_amdgcn_logf(x));
+    const float e = __builtin_amdgcn_exp2f(p * (float)(-0.4 * kLog2e));
+    const float d1 = fmaf(4.0f, u, 1.0f);
+    const float d2 = fmaf(0.1f, p, 1.0f);
+    const float aG = 1.0f - r;
+    const float aW = 0.016f * r * aG;
+    const float num = fmaf(r, d2, -aW * d1);
+    const float rat = num * __builtin_amdgcn_rcpf(d1 * d2);
+    return fmaf(aG, g, fmaf(aW, e, rat));
+}
+
+__device__ __forceinline__ double shape_f64(double x, double r)
+{
+    const double u = x * x;
+    const double gs = exp(-2.772 * u);
+    const double p = u * sqrt(sqrt(x));
+    const double e = exp(-0.4 * p);
+    return (1.0 - r) * gs + r / (1.0 + 4.0 * u) + 0.016 * r * (1.0 - r) * (e - 1.0 / (1.0 + 0.1 * p));
+}
+
+__global__ __launch_bounds__(kAccumThreads) void accum_f32_kernel(
+    DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int32_t *escale,
+    const int2 *ranges, int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles,
+    float *eta, float *kappa)
+{
+    __shared__ RecF32 rec[kStage];
+    const int tile = (int)(blockIdx.x % n_tiles), c = (int)(blockIdx.x / n_tiles);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t kt = k_first + tile * kTilePoints;            // first point of the tile
+    const int32_t kw = kt + wave * 64 * kPPL;                   // first point of the wave
+    const int32_t kend = k_first + n_band;                      // exclusive
+    const CellConst k = cc[c];
+    const CellSpecies *csc = cs + (int64_t)c * n_species;
+    const int ese = escale[2 * c + 0], esk = escale[2 * c + 1];
+    const int2 rg = ranges[(int64_t)c * n_tiles + tile];
+
+    float kf[kPPL], se[kPPL], ce[kPPL], sk[kPPL], ck[kPPL];
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        kf[j] = (float)(kw + 64 * j + lane);
+        se[j] = ce[j] = sk[j] = ck[j] = 0.0f;
+    }
+    const int32_t kw_last = kw + 64 * kPPL - 1;
+
+    for (int base = rg.x; base < rg.y; base += kStage) {
+        const int64_t i = (int64_t)base + threadIdx.x;
+        RecF32 rr;
+        rr.klo = 1;
+        rr.khi = 0;
+        rr.k0f = rr.hs = rr.fs = rr.r = rr.se = rr.sk = 0.0f;
+        if (i < rg.y) {
+            PairF64 p;
+            if (pair_setup(L, g, k, csc, i, p)) {
+                rr.klo = p.klo;
+                rr.khi = p.khi;
+                rr.k0f = (float)L.k0[i];
+                rr.hs = (float)(g.h * p.inv2g);
+                rr.fs = (float)(L.frac0[i] * p.inv2g);
+                rr.r = (float)p.r;
+                rr.se = (float)ldexp(p.se, -ese);
+                rr.sk = (float)ldexp(p.sk, -esk);
+            }
+        }
+        rec[threadIdx.x] = rr;
+        __syncthreads();
+        const int n = min(kStage, rg.y - base);
+        for (int l = 0; l < n; ++l) {
+            const RecF32 q = rec[l];
+            if (q.khi < kw || q.klo > kw_last) continue;
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                const int32_t k0j = kw + 64 * j;
+                if (q.khi < k0j || q.klo > k0j + 63) continue;
+                const float x = fabsf(fmaf(kf[j] - q.k0f, q.hs, -q.fs));
+                const float P = shape_f32(x, q.r);
+                const int32_t kk = k0j + lane;
+                const float v = (kk >= q.klo && kk <= q.khi) ? P : 0.0f;
+                // Kahan: s + v with the running compensation c
+                const float ye = fmaf(v, q.se, -ce[j]);
+                const float te = se[j] + ye;
+                ce[j] = (te - se[j]) - ye;
+                se[j] = te;
+                const float yk = fmaf(v, q.sk, -ck[j]);
+                const float tk = sk[j] + yk;
+                ck[j] = (tk - sk[j]) - yk;
+                sk[j] = tk;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        const int32_t kk = kw + 64 * j + lane;
+        if (kk < kend) {
+            const int64_t o = (int64_t)c * n_band + (kk - k_first);
+            eta[o] = se[j] - ce[j];
+            kappa[o] = sk[j] - ck[j];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
+    DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int2 *ranges,
+    int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles, double *eta,
+    double *kappa)
+{
+    __shared__ RecF64 rec[kStage];
+    const int tile = (int)(blockIdx.x % n_tiles), c = (int)(blockIdx.x / n_tiles);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t kt = k_first + tile * kTilePoints;
+    const int32_t kw = kt + wave * 64 * kPPL;
+    const int32_t kend = k_first + n_band;
+    const CellConst k = cc[c];
+    const CellSpecies *csc = cs + (int64_t)c * n_species;
+    const int2 rg = ranges[(int64_t)c * n_tiles + tile];
+
+    double se[kPPL], sk[kPPL];
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) se[j] = sk[j] = 0.0;
+    const int32_t kw_last = kw + 64 * kPPL - 1;
+
+    for (int base = rg.x; base < rg.y; base += kStage) {
+        const int64_t i = (int64_t)base + threadIdx.x;
+        RecF64 rr;
+        rr.klo = 1;
+        rr.khi = 0;
+        rr.k0 = 0;
+        rr.pad = 0;
+        rr.frac0 = rr.inv2g = rr.r = rr.se = rr.sk = rr.pad2 = 0.0;
+        if (i < rg.y) {
+            PairF64 p;
+            if (pair_setup(L, g, k, csc, i, p)) {
+                rr.klo = p.klo;
+                rr.khi = p.khi;
+                rr.k0 = L.k0[i];
+                rr.frac0 = L.frac0[i];
+                rr.inv2g = p.inv2g;
+                rr.r = p.r;
+                rr.se = p.se;
+                rr.sk = p.sk;
+            }
+        }
+        rec[threadIdx.x] = rr;
+        __syncthreads();
+        const int n = min(kStage, rg.y - base);
+        for (int l = 0; l < n; ++l) {
+            const RecF64 q = rec[l];
+            if (q.khi < kw || q.klo > kw_last) continue;
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                const int32_t k0j = kw + 64 * j;
+                if (q.khi < k0j || q.klo > k0j + 63) continue;
+                const int32_t kk = k0j + lane;
+                if (kk >= q.klo && kk <= q.khi) {
+                    const double delta = fma((double)(kk - q.k0), g.h, -q.frac0);
+                    const double x = fabs(delta) * q.inv2g;
+                    const double P = shape_f64(x, q.r);
+                    se[j] += q.se * P;
+                    sk[j] += q.sk * P;
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        const int32_t kk = kw + 64 * j + lane;
+        if (kk < kend) {
+            const int64_t o = (int64_t)c * n_band + (kk - k_first);
+            eta[o] = se[j];
+            kappa[o] = sk[j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// in-window term count (the evaluation count of the metric)
+// ---------------------------------------------------------------------------
+
+__global__ void count_kernel(DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs,
+                             int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band,
+                             unsigned long long *count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long n = 0;
+    for (int c = blockIdx.y; c < n_cells; c += gridDim.y) {
+        if (i < L.n) {
+            PairF64 p;
+            if (pair_setup(L, g, cc[c], cs + (int64_t)c * n_species, i, p)) {
+                const int32_t a = max(p.klo, k_first), b = min(p.khi, k_first + n_band - 1);
+                if (b >= a) n += (unsigned long long)(b - a + 1);
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+    if ((threadIdx.x & 63) == 0 && n) atomicAdd(count, n);
+}
+
+// ---------------------------------------------------------------------------
+// a5 + a6: march and spectral trapezoid
+// ---------------------------------------------------------------------------
+
+// F(t) = (1 - e^-t)/t from e = e^-t; Taylor for |t| < 0.1 avoids the
+// cancellation in 1 - e (relative error of the direct form ~ 6e-8 / |t|).
+__device__ __forceinline__ float fexp_f32(float t, float e)
+{
+    const float poly = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, -1.0f / 720.0f, 1.0f / 120.0f),
+                                                   -1.0f / 24.0f), 1.0f / 6.0f), -0.5f), 1.0f);
+    const float direct = (1.0f - e) * __builtin_amdgcn_rcpf(t);
+    return fabsf(t) < 0.1f ? poly : direct;
+}
+
+template <bool FP32>
+__global__ __launch_bounds__(kMarchThreads) void march_kernel(
+    DevRays rays, DevGrid g, int32_t k_first, int32_t n_band, const void *eta_v,
+    const void *kappa_v, const int32_t *escale, double *I_out, double *partials, int32_t n_chunks,
+    int32_t aligned16)
+{
+    const int ray = blockIdx.x, chunk = blockIdx.y;
+    const int32_t kb = chunk * kMarchPoints + threadIdx.x * kMarchPPT;   // band-relative
+    const int64_t m0 = rays.off[ray], m1 = rays.off[ray + 1];
+    double I[kMarchPPT];
+#pragma unroll
+    for (int j = 0; j < kMarchPPT; ++j) I[j] = 0.0;
+    // float4 loads only when every row start is 16-byte aligned
+    const bool vec = aligned16 && (kb + kMarchPPT <= n_band) && (n_band % kMarchPPT) == 0;
+
+    for (int64_t m = m0; m < m1; ++m) {
+        const int32_t c = rays.cell[m];
+        const double ds = rays.ds[m];
+        const int64_t row = (int64_t)c * n_band + kb;
+        if constexpr (FP32) {
+            const float *eta = (const float *)eta_v;
+            const float *kap = (const float *)kappa_v;
+            const double dse = ldexp(ds, escale[2 * c + 0]);
+            const double dsk_d = ldexp(ds, escale[2 * c + 1]);
+            const float dsk = (float)fmin(dsk_d, 3.0e38);
+            float ev[kMarchPPT], kv[kMarchPPT];
+            if (vec) {
+                const float4 a = *(const float4 *)(eta + row);
+                const float4 b = *(const float4 *)(kap + row);
+                ev[0] = a.x; ev[1] = a.y; ev[2] = a.z; ev[3] = a.w;
+                kv[0] = b.x; kv[1] = b.y; kv[2] = b.z; kv[3] = b.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < kMarchPPT; ++j) {
+                    const bool ok = kb + j < n_band;
+                    ev[j] = ok ? eta[row + j] : 0.0f;
+                    kv[j] = ok ? kap[row + j] : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kMarchPPT; ++j) {
+                const float tau = kv[j] * dsk;
+                const float e = __builtin_amdgcn_exp2f(tau * (float)(-kLog2e));
+                const float F = fexp_f32(tau, e);
+                const float src = ev[j] * F;
+                I[j] = fma((double)src, dse, I[j] * (double)e);
+            }
+        } else {
+            const double *eta = (const double *)eta_v;
+            const double *kap = (const double *)kappa_v;
+#pragma unroll
+            for (int j = 0; j < kMarchPPT; ++j) {
+                if (kb + j < n_band) {
+                    const double tau = kap[row + j] * ds;
+                    const double em = expm1(-tau);
+                    const double F = (tau == 0.0) ? 1.0 : -em / tau;
+                    I[j] = I[j] * (1.0 + em) + eta[row + j] * ds * F;
+                }
+            }
+        }
+    }
+    // outputs: I and the trapezoid partial with global-index weights
+    double part = 0.0;
+#pragma unroll
+    for (int j = 0; j < kMarchPPT; ++j) {
+        const int32_t kl = kb + j;
+        if (kl < n_band) {
+            const int32_t kg = k_first + kl;
+            const double w = (kg == 0 || kg == g.n_points - 1) ? 0.5 * g.h : g.h;
+            part += w * I[j];
+            if (I_out) I_out[(int64_t)ray * n_band + kl] = I[j];
+        }
+    }
+    // block sum in a fixed order: waves reduce by xor-shuffles, then wave 0
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    __shared__ double wsum[kMarchThreads / 64];
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kMarchThreads / 64; ++w) s += wsum[w];
+        partials[(int64_t)ray * n_chunks + chunk] = s;
+    }
+}
+
+__global__ void reduce_rows_kernel(const double *p, int32_t n_rows, int32_t n_cols, double *out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    double s = 0.0;
+    for (int j = 0; j < n_cols; ++j) s += p[(int64_t)r * n_cols + j];
+    out[r] = s;
+}
+
+__global__ void wall_sum_kernel(const double *I_int, const double *weight, const int64_t *wall_off,
+                                int32_t n_wall, double *q)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n_wall) return;
+    double s = 0.0;
+    for (int64_t r = wall_off[w]; r < wall_off[w + 1]; ++r) s += weight[r] * I_int[r];
+    q[w] = s;
+}
+
+__global__ void add_kernel(double *acc, const double *x, int32_t n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) acc[t] += x[t];
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_thermo(const DevSpecies &sp, const DevCells &cells, double M_min, CellConst *cc,
+                         CellSpecies *cs, hipStream_t st)
+{
+    const int64_t n = (int64_t)cells.n_cells * cells.n_species;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(thermo_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, st, sp, cells, M_min,
+                       cc, cs);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(const DevLines &L, const DevGrid &g, const CellConst *cc, int32_t n_cells,
+                         int32_t k_first, int32_t n_band, int32_t tile_points, int2 *ranges,
+                         hipStream_t st)
+{
+    const int32_t n_tiles = (n_band + tile_points - 1) / tile_points;
+    const int64_t n = (int64_t)n_cells * n_tiles;
+    hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, L, g, cc,
+                       n_cells, k_first, n_band, tile_points, n_tiles, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const DevLines &L, const DevGrid &g, const CellConst *cc,
+                        const CellSpecies *cs, int32_t n_cells, int32_t n_species, int32_t *emax,
+                        int32_t *escale, hipStream_t st)
+{
+    // emax must hold INT_MIN on entry (set by a fill kernel of the caller)
+    if (L.n > 0) {
+        hipLaunchKernelGGL(scale_kernel, dim3(blocks_for(L.n, 256), min(n_cells, 65535)),
+                           dim3(256), 0, st, L, g, cc, cs, n_cells, n_species, emax);
+    }
+    hipLaunchKernelGGL(scale_finish_kernel, dim3(blocks_for(2 * n_cells, 256)), dim3(256), 0, st,
+                       emax, 2 * n_cells, escale);
+    return hipGetLastError();
+}
+
+hipError_t launch_accum_f32(const DevLines &L, const DevGrid &g, const CellConst *cc,
+                            const CellSpecies *cs, const int32_t *escale, const int2 *ranges,
+                            int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band,
+                            float *eta, float *kappa, hipStream_t st)
+{
+    const int32_t n_tiles = (n_band + kTilePoints - 1) / kTilePoints;
+    hipLaunchKernelGGL(accum_f32_kernel, dim3((unsigned)((int64_t)n_tiles * n_cells)), dim3(kAccumThreads), 0, st, L, g,
+                       cc, cs, escale, ranges, n_species, k_first, n_band, n_tiles, eta, kappa);
+    return hipGetLastError();
+}
+
+hipError_t launch_accum_f64(const DevLines &L, const DevGrid &g, const CellConst *cc,
+                            const CellSpecies *cs, const int2 *ranges, int32_t n_cells,
+                            int32_t n_species, int32_t k_first, int32_t n_band, double *eta,
+                            double *kappa, hipStream_t st)
+{
+    const int32_t n_tiles = (n_band + kTilePoints - 1) / kTilePoints;
+    hipLaunchKernelGGL(accum_f64_kernel, dim3((unsigned)((int64_t)n_tiles * n_cells)), dim3(kAccumThreads), 0, st, L, g,
+                       cc, cs, ranges, n_species, k_first, n_band, n_tiles, eta, kappa);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const DevLines &L, const DevGrid &g, const CellConst *cc,
+                        const CellSpecies *cs, int32_t n_cells, int32_t n_species, int32_t k_first,
+                        int32_t n_band, unsigned long long *count, hipStream_t st)
+{
+    if (L.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(count_kernel, dim3(blocks_for(L.n, 256), min(n_cells, 65535)), dim3(256),
+                       0, st, L, g, cc, cs, n_cells, n_species, k_first, n_band, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_march(bool fp32, const DevRays &rays, const DevGrid &g, int32_t k_first,
+                        int32_t n_band, const void *eta, const void *kappa, const int32_t *escale,
+                        double *I_out, double *partials, int32_t n_chunks, hipStream_t st)
+{
+    if (rays.n_rays == 0) return hipSuccess;
+    dim3 grid(rays.n_rays, n_chunks);
+    const int32_t al = ((((uintptr_t)eta) | ((uintptr_t)kappa)) & 15) == 0;
+    if (fp32)
+        hipLaunchKernelGGL(march_kernel<true>, grid, dim3(kMarchThreads), 0, st, rays, g, k_first,
+                           n_band, eta, kappa, escale, I_out, partials, n_chunks, al);
+    else
+        hipLaunchKernelGGL(march_kernel<false>, grid, dim3(kMarchThreads), 0, st, rays, g, k_first,
+                           n_band, eta, kappa, escale, I_out, partials, n_chunks, al);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_rows(const double *partials, int32_t n_rows, int32_t n_cols, double *out,
+                              hipStream_t st)
+{
+    if (n_rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(n_rows, 64)), dim3(64), 0, st, partials,
+                       n_rows, n_cols, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_sum(const double *I_int, const double *weight, const int64_t *wall_off,
+                           int32_t n_wall, double *q, hipStream_t st)
+{
+    if (n_wall == 0) return hipSuccess;
+    hipLaunchKernelGGL(wall_sum_kernel, dim3(blocks_for(n_wall, 64)), dim3(64), 0, st, I_int,
+                       weight, wall_off, n_wall, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(double *acc, const double *x, int32_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(add_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, acc, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace lrt

@@ -1,0 +1,289 @@
+"""ctypes binding of liblrt (include/lrt.h): argument marshalling only.
+
+Every step of the radiation path runs in the library's HIP kernels; this module
+converts the seeded inputs (synth) to the C structures, passes torch device
+buffers by pointer and raises LrtError on any non-OK status.  It refuses to
+work without the built library: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import synth
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblrt.so")
+
+LRT_FP64 = 0
+LRT_FP32_COMP = 1
+PRECISIONS = {"fp64": LRT_FP64, "fp32c": LRT_FP32_COMP}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_vp = C.c_void_p
+
+EXPORTS = ["lrt_version", "lrt_status_string", "lrt_create", "lrt_destroy", "lrt_last_error",
+           "lrt_set_species", "lrt_set_lines", "lrt_set_grid", "lrt_set_cells",
+           "lrt_set_rays_slab", "lrt_set_rays_axi", "lrt_trace_axi_ray", "lrt_get_sizes", "lrt_get_ray",
+           "lrt_coeffs", "lrt_march", "lrt_solve", "lrt_count_terms", "lrt_profile",
+           "lrt_profile_read"]
+
+KERNELS = {"thermo": 0, "scale": 1, "ranges": 2, "accum": 3, "march": 4}
+
+
+class LrtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("lrt status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Species(C.Structure):
+    _fields_ = [("kind", C.c_int), ("mass", C.c_double), ("n_levels", C.c_int),
+                ("level_E", _dp), ("level_g", _dp), ("n_el", C.c_int), ("el_T", _dp),
+                ("el_g", _dp), ("el_nv", _ip), ("el_Jmax", _ip), ("vib_G", _dp),
+                ("vib_B", _dp), ("vib_D", _dp)]
+
+
+class _Lines(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nu0", _dp), ("A", _dp), ("Eu_ev", _dp), ("Eu_rot", _dp),
+                ("El_ev", _dp), ("El_rot", _dp), ("gu", _dp), ("gl", _dp), ("species", _i32p)]
+
+
+class _Cells(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_species", C.c_int), ("T_tr", _dp), ("T_v", _dp),
+                ("N", _dp), ("n_e", _dp)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblrt.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblrt.so not built: run __graft_entry__.build() "
+                              "(python -m paper_2604_11856_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int
+        sig = {
+            "lrt_version": (C.c_char_p, []),
+            "lrt_status_string": (C.c_char_p, [st]),
+            "lrt_create": (st, [C.c_int, C.POINTER(_vp)]),
+            "lrt_destroy": (None, [_vp]),
+            "lrt_last_error": (C.c_char_p, [_vp]),
+            "lrt_set_species": (st, [_vp, C.c_int, C.POINTER(_Species)]),
+            "lrt_set_lines": (st, [_vp, C.POINTER(_Lines)]),
+            "lrt_set_grid": (st, [_vp, C.c_double, C.c_double, C.c_int64, C.c_int64]),
+            "lrt_set_cells": (st, [_vp, C.POINTER(_Cells)]),
+            "lrt_set_rays_slab": (st, [_vp, C.c_int64, _dp, C.c_int]),
+            "lrt_set_rays_axi": (st, [_vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
+                                      _dp, C.c_int, C.c_int]),
+            "lrt_trace_axi_ray": (st, [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, C.c_double, C.c_int64, _i32p, _dp, _i64p]),
+            "lrt_get_sizes": (st, [_vp, _i64p, _i64p, _i64p, _i64p, _i64p, _i64p]),
+            "lrt_get_ray": (st, [_vp, C.c_int64, C.c_int64, _i32p, _dp, _i64p, _dp, _i64p]),
+            "lrt_coeffs": (st, [_vp, C.c_int64, C.c_int, _vp, _vp, _vp, _vp]),
+            "lrt_march": (st, [_vp, C.c_int64, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "lrt_solve": (st, [_vp, C.c_int, C.c_int64, _dp, _dp, _dp, _vp]),
+            "lrt_count_terms": (st, [_vp, C.c_int64, _i64p, _vp]),
+            "lrt_profile": (st, [_vp, C.c_int]),
+            "lrt_profile_read": (st, [_vp, C.c_int, _dp, _i64p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream) or None
+    return int(getattr(stream, "cuda_stream", stream)) or None
+
+
+class Context:
+    """One liblrt context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._L = lib()
+        h = _vp()
+        s = self._L.lrt_create(device, C.byref(h))
+        if s != 0:
+            raise LrtError(s, self._L.lrt_last_error(None).decode())
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.lrt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, s):
+        if s != 0:
+            raise LrtError(s, self._L.lrt_last_error(self.h).decode())
+
+    # -- state ---------------------------------------------------------------
+    def set_species(self, species):
+        arr = (_Species * len(species))()
+        keep = []
+        for i, sp in enumerate(species):
+            f = lambda x, t=np.float64: np.ascontiguousarray(x, t)
+            lE, lg = f(sp.level_E), f(sp.level_g)
+            eT, eg = f(sp.el_T), f(sp.el_g)
+            env, eJ = f(sp.el_nv, np.int32), f(sp.el_Jmax, np.int32)
+            vG, vB, vD = f(sp.vib_G), f(sp.vib_B), f(sp.vib_D)
+            keep += [lE, lg, eT, eg, env, eJ, vG, vB, vD]
+            arr[i] = _Species(sp.kind, sp.mass, lE.size, _p(lE), _p(lg), eT.size, _p(eT), _p(eg),
+                              _p(env, _ip), _p(eJ, _ip), _p(vG), _p(vB), _p(vD))
+        self._chk(self._L.lrt_set_species(self.h, len(species), arr))
+
+    def set_lines(self, lines):
+        a = {k: np.ascontiguousarray(getattr(lines, k), np.float64)
+             for k in ("nu0", "A", "Eu_ev", "Eu_rot", "El_ev", "El_rot", "gu", "gl")}
+        sp = np.ascontiguousarray(lines.species, np.int32)
+        s = _Lines(lines.n, _p(a["nu0"]), _p(a["A"]), _p(a["Eu_ev"]), _p(a["Eu_rot"]),
+                   _p(a["El_ev"]), _p(a["El_rot"]), _p(a["gu"]), _p(a["gl"]), _p(sp, _i32p))
+        self._chk(self._L.lrt_set_lines(self.h, C.byref(s)))
+
+    def set_grid(self, grid):
+        self._chk(self._L.lrt_set_grid(self.h, float(grid.nu_min), float(grid.nu_max),
+                                       int(grid.n_points), int(grid.band_points)))
+
+    def set_cells(self, cells):
+        T_tr = np.ascontiguousarray(cells.T_tr, np.float64)
+        T_v = np.ascontiguousarray(cells.T_v, np.float64)
+        N = np.ascontiguousarray(cells.N, np.float64)
+        ne = np.ascontiguousarray(cells.n_e, np.float64)
+        s = _Cells(T_tr.shape[0], N.shape[1], _p(T_tr), _p(T_v), _p(N), _p(ne))
+        self._chk(self._L.lrt_set_cells(self.h, C.byref(s)))
+
+    def set_rays(self, geom):
+        if isinstance(geom, synth.SlabGeometry):
+            dx = np.ascontiguousarray(geom.dx, np.float64)
+            self._chk(self._L.lrt_set_rays_slab(self.h, dx.size, _p(dx), int(geom.n_mu)))
+        elif isinstance(geom, synth.AxiGeometry):
+            wr = np.ascontiguousarray(geom.wall_r, np.float64)
+            self._chk(self._L.lrt_set_rays_axi(self.h, geom.nx, geom.nr, float(geom.Lx),
+                                               float(geom.R), wr.size, _p(wr), int(geom.n_mu),
+                                               int(geom.n_phi)))
+        else:
+            raise TypeError("unknown geometry %r" % type(geom))
+
+    def load(self, wl):
+        """Species, lines, grid, cells and rays of a synth.Workload."""
+        self.set_species(wl.species)
+        self.set_lines(wl.lines)
+        self.set_grid(wl.grid)
+        self.set_cells(wl.cells)
+        self.set_rays(wl.geometry)
+        return self
+
+    def sizes(self):
+        v = [C.c_int64() for _ in range(6)]
+        self._chk(self._L.lrt_get_sizes(self.h, *[C.byref(x) for x in v]))
+        keys = ("n_cells", "n_rays", "n_wall", "n_points", "n_bands", "band_points")
+        return {k: x.value for k, x in zip(keys, v)}
+
+    def band_len(self, band: int) -> int:
+        s = self.sizes()
+        return min(s["band_points"], s["n_points"] - band * s["band_points"])
+
+    def ray(self, r: int):
+        n, w, wall = C.c_int64(), C.c_double(), C.c_int64()
+        self._chk(self._L.lrt_get_ray(self.h, r, 0, None, None, C.byref(n), C.byref(w), C.byref(wall)))
+        cell = np.zeros(n.value, np.int32)
+        ds = np.zeros(n.value)
+        self._chk(self._L.lrt_get_ray(self.h, r, n.value, _p(cell, _i32p), _p(ds), C.byref(n),
+                                      C.byref(w), C.byref(wall)))
+        return cell, ds, w.value, wall.value
+
+    # -- compute ---------------------------------------------------------------
+    def coeffs(self, band: int, precision: int, eta, kappa, escale=None, stream=None):
+        self._chk(self._L.lrt_coeffs(self.h, band, precision, _ptr(eta), _ptr(kappa),
+                                     _ptr(escale), _stream(stream)))
+
+    def march(self, band: int, precision: int, eta, kappa, escale, I_out, I_int_out, stream=None):
+        self._chk(self._L.lrt_march(self.h, band, precision, _ptr(eta), _ptr(kappa),
+                                    _ptr(escale), _ptr(I_out), _ptr(I_int_out), _stream(stream)))
+
+    def solve(self, precision: int, first_band: int = 0, stream=None):
+        s = self.sizes()
+        q = np.zeros(s["n_wall"])
+        I_int = np.zeros(s["n_rays"])
+        qb = np.zeros((s["n_wall"], s["n_bands"]))
+        self._chk(self._L.lrt_solve(self.h, precision, first_band, _p(q), _p(I_int), _p(qb),
+                                    _stream(stream)))
+        return q, I_int, qb
+
+    def count_terms(self, band: int, stream=None) -> int:
+        n = C.c_int64()
+        self._chk(self._L.lrt_count_terms(self.h, band, C.byref(n), _stream(stream)))
+        return n.value
+
+    def profile(self, enable: bool = True):
+        self._chk(self._L.lrt_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self, kernel: str):
+        """(total ms, launches) of one kernel family since profile(True)."""
+        ms, n = C.c_double(), C.c_int64()
+        self._chk(self._L.lrt_profile_read(self.h, KERNELS[kernel], C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    # -- conveniences over torch buffers --------------------------------------
+    def coeffs_torch(self, band: int, precision: int, device="cuda:0"):
+        """Allocate eta/kappa(/escale) on the device and run lrt_coeffs."""
+        import torch
+        nc = self.sizes()["n_cells"]
+        nb = self.band_len(band)
+        dt = torch.float64 if precision == LRT_FP64 else torch.float32
+        eta = torch.empty((nc, nb), dtype=dt, device=device)
+        kap = torch.empty((nc, nb), dtype=dt, device=device)
+        esc = torch.zeros((nc, 2), dtype=torch.int32, device=device)
+        self.coeffs(band, precision, eta, kap, esc if precision == LRT_FP32_COMP else None)
+        return eta, kap, esc
+
+
+def trace_axi_ray(nx, nr, Lx, R, rw, mu, phi):
+    """Segments (cell, ds), far -> wall, of one axisymmetric ray (host only)."""
+    L = lib()
+    cap = 4 * (nx + 2 * nr) + 16
+    cell = np.zeros(cap, np.int32)
+    ds = np.zeros(cap)
+    n = C.c_int64()
+    s = L.lrt_trace_axi_ray(nx, nr, Lx, R, rw, mu, phi, cap, _p(cell, _i32p), _p(ds), C.byref(n))
+    if s != 0:
+        raise LrtError(s, L.lrt_last_error(None).decode())
+    return cell[:n.value].copy(), ds[:n.value].copy()
+
+
+def scaled_to_f64(eta, kappa, escale):
+    """Host FP64 values of a single-precision result: stored * 2^escale."""
+    e = eta.double().cpu().numpy()
+    k = kappa.double().cpu().numpy()
+    s = escale.cpu().numpy().astype(np.int64)
+    return np.ldexp(e, s[:, :1]), np.ldexp(k, s[:, 1:2])

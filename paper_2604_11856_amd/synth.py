@@ -333,7 +333,7 @@ def _fractions_to_N(f_mol, f_ion, N_tot):
 
 def stagnation_line(n_cells=400, length=4.0, n_atomic=200_000, n_rovib=2_000_000,
                     n_points=1 << 21, nu_min=1000.0, nu_max=100000.0, band_points=None,
-                    n_mu=16, n_v=41, seed=11857) -> Workload:
+                    n_mu=16, n_v=50, seed=11857) -> Workload:
     """1-D stagnation-line nonequilibrium case: shock at x = 0 (far, free
     boundary), wall at x = length; T_tr = 1e4 + 2e4 exp(-x/0.4) relaxing,
     T_v = max(500, 1e4 - 9500 exp(-x/0.6)) lagging, +-1% seeded noise;
@@ -371,7 +371,7 @@ def _smooth_field(rng, X, Rr, Lx, R, n_bumps=6):
 
 def axisymmetric(nx=256, nr=128, Lx=100.0, R=50.0, n_atomic=250_000, n_rovib=750_000,
                  n_points=1 << 20, nu_min=1000.0, nu_max=100000.0, band_points=65536,
-                 n_wall=64, wall_R=30.0, n_mu=16, n_phi=16, n_v=41, seed=11858) -> Workload:
+                 n_wall=64, wall_R=30.0, n_mu=16, n_phi=16, n_v=50, seed=11858) -> Workload:
     """2-D axisymmetric afterbody: structured nx x nr cells over
     [0, Lx] x [0, R] cm with smooth seeded T_tr in 3000..10000 K,
     T_v = T_tr (1 + 0.3 h) with smooth h in [0, 1] (T_v > T_tr in the wake),

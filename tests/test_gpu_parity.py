@@ -1,0 +1,367 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: LRT_FP64 within 1e-12 and LRT_FP32_COMP within 1e-5, relative and
+normwise per cell (eta, kappa) or per ray (I); scalar integrals (I_int, q)
+relative.  Window bounds that sit within 1e-9 of an integer grid index
+(knife edges, where a last-bit difference in the Voigt width between two
+correct libms moves the bound) are excluded and counted.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2604_11856_amd import lrt, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {lrt.LRT_FP64: 1e-12, lrt.LRT_FP32_COMP: 1e-5}
+PRECS = [lrt.LRT_FP64, lrt.LRT_FP32_COMP]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def normwise(got, ref, mask=None):
+    """max over rows of max|got - ref| / max|ref| (rows where ref == 0
+    must be exactly zero)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    d = np.abs(got - ref)
+    if mask is not None:
+        d = np.where(mask, 0.0, d)
+    den = np.max(np.abs(ref), axis=-1)
+    num = np.max(d, axis=-1)
+    zero = den == 0
+    assert np.all(num[zero] == 0), "nonzero values where the oracle has none"
+    return float(np.max(num[~zero] / den[~zero])) if np.any(~zero) else 0.0
+
+
+def gpu_coeffs(ctx, band, prec, torch):
+    eta, kap, esc = ctx.coeffs_torch(band, prec)
+    torch.cuda.synchronize()
+    if prec == lrt.LRT_FP32_COMP:
+        return lrt.scaled_to_f64(eta, kap, esc)
+    return eta.cpu().numpy(), kap.cpu().numpy()
+
+
+def edge_mask(wl, k_first, n):
+    cc, kk = O.knife_edges(wl.species, wl.lines, wl.cells, wl.grid)
+    m = np.zeros((wl.cells.n, n), bool)
+    sel = (kk >= k_first) & (kk < k_first + n)
+    m[cc[sel], kk[sel] - k_first] = True
+    return m
+
+
+def check_all_bands(wl, torch, precs=PRECS):
+    ctx = lrt.Context(0).load(wl)
+    eta_ref, kap_ref, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
+    nb = ctx.sizes()["n_bands"]
+    worst = {}
+    for prec in precs:
+        we = wk = 0.0
+        for b in range(nb):
+            say("  band %d/%d prec %d" % (b, nb, prec))
+            e, k = gpu_coeffs(ctx, b, prec, torch)
+            k0 = b * wl.grid.band_points
+            sl = slice(k0, k0 + e.shape[1])
+            m = edge_mask(wl, k0, e.shape[1])
+            we = max(we, normwise(e, eta_ref[:, sl], m))
+            wk = max(wk, normwise(k, kap_ref[:, sl], m))
+        say("  prec %d: eta %.3e kappa %.3e" % (prec, we, wk))
+        assert we <= TOL[prec] and wk <= TOL[prec], (prec, we, wk)
+        worst[prec] = (we, wk)
+    ctx.close()
+    return worst
+
+
+def _tiny(seed, n_lines=6, n_cells=3, n_points=211, band=53):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    species = [synth.atom_species(rng, "N"), synth.atom_species(rng, "O"),
+               synth.molecule_species(rng, "N2", n_v=4), synth.none_species("e-")]
+    lo, hi = 20000.0, 20000.0 + 0.31 * (n_points - 1)
+    nu0 = np.sort(rng.uniform(lo - 40.0, hi + 40.0, n_lines))
+    sp_idx = rng.integers(0, 3, n_lines).astype(np.int32)
+    Eu_ev = rng.uniform(80000.0, 110000.0, n_lines)
+    Eu_rot = np.where(sp_idx == 2, rng.uniform(0, 4000.0, n_lines), 0.0)
+    El_rot = np.where(sp_idx == 2, rng.uniform(0, 4000.0, n_lines), 0.0)
+    El_ev = Eu_ev + Eu_rot - El_rot - nu0
+    lines = synth.Lines(nu0, 10 ** rng.uniform(4, 9, n_lines), Eu_ev, Eu_rot, El_ev, El_rot,
+                        rng.integers(2, 13, n_lines).astype(float),
+                        rng.integers(2, 13, n_lines).astype(float), sp_idx)
+    N = 10 ** rng.uniform(14, 17, (n_cells, 4))
+    cells = synth.Cells(rng.uniform(3000, 30000, n_cells), rng.uniform(3000, 15000, n_cells),
+                        N, 10 ** rng.uniform(14, 17, n_cells))
+    return synth.Workload("tiny", species, lines, cells, synth.Grid(lo, hi, n_points, band),
+                          synth.SlabGeometry(np.full(n_cells, 0.1), 2))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tiny_cases_all_bands(seed, torch_dev):
+    say("tiny seed", seed)
+    check_all_bands(_tiny(seed), torch_dev)
+
+
+def test_slab_full_size(torch_dev):
+    """64 cells x 0.05 cm, 2000 N/O lines, 200,000 points over 5000-80000 cm^-1:
+    eta, kappa, the wall intensity and its spectral integral."""
+    torch = torch_dev
+    wl = synth.slab_equilibrium()
+    say("slab full: oracle")
+    ref = O.solve_slab(wl)
+    ctx = lrt.Context(0).load(wl)
+    n = wl.grid.n_points
+    m = edge_mask(wl, 0, n)
+    for prec in PRECS:
+        say("slab full prec", prec)
+        eta, kap, esc = ctx.coeffs_torch(0, prec)
+        I = torch.zeros((1, n), dtype=torch.float64, device="cuda:0")
+        Ii = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        ctx.march(0, prec, eta, kap, esc, I, Ii)
+        torch.cuda.synchronize()
+        e, k = (lrt.scaled_to_f64(eta, kap, esc) if prec == lrt.LRT_FP32_COMP
+                else (eta.cpu().numpy(), kap.cpu().numpy()))
+        ee, ek = normwise(e, ref["eta"], m), normwise(k, ref["kappa"], m)
+        eI = normwise(I.cpu().numpy(), ref["I"][:1])
+        eIi = abs(Ii.item() - ref["I_int"][0]) / abs(ref["I_int"][0])
+        say("  eta %.3e kappa %.3e I %.3e I_int %.3e" % (ee, ek, eI, eIi))
+        assert max(ee, ek, eI, eIi) <= TOL[prec]
+    ctx.close()
+
+
+@pytest.mark.parametrize("band_points", [200_000, 65_536, 4099])
+def test_slab_solve_bands(band_points, torch_dev):
+    """Whole path (lrt_solve) with ragged bands and GL rays: I_int per ray and
+    the tangent-slab flux."""
+    wl = synth.slab_equilibrium(n_cells=20, n_lines_per_species=400, n_points=50_001,
+                                band_points=band_points, n_mu=8, seed=99)
+    ref = O.solve_slab(wl)
+    ctx = lrt.Context(0).load(wl)
+    for prec in PRECS:
+        say("slab solve band_points", band_points, "prec", prec)
+        q, I_int, qb = ctx.solve(prec)
+        eI = np.max(np.abs(I_int - ref["I_int"]) / np.abs(ref["I_int"]))
+        eq = abs(q[0] - ref["q"]) / abs(ref["q"])
+        say("  I_int %.3e q %.3e" % (eI, eq))
+        assert eI <= TOL[prec] and eq <= TOL[prec]
+        assert qb.sum() == pytest.approx(q[0], rel=1e-14)
+    ctx.close()
+
+
+def test_stagnation_small(torch_dev):
+    """Two-temperature stagnation-line shape with atomic and rovibronic lines,
+    several ragged bands."""
+    wl = synth.stagnation_line(n_cells=24, n_atomic=4000, n_rovib=16000, n_points=1 << 16,
+                               band_points=20000, n_mu=4)
+    say("stagnation small coeffs")
+    check_all_bands(wl, torch_dev)
+    ref = O.solve_slab(wl)
+    ctx = lrt.Context(0).load(wl)
+    for prec in PRECS:
+        q, I_int, _ = ctx.solve(prec)
+        eI = np.max(np.abs(I_int - ref["I_int"]) / np.abs(ref["I_int"]))
+        eq = abs(q[0] - ref["q"]) / abs(ref["q"])
+        say("  stagnation solve prec %d: I_int %.3e q %.3e" % (prec, eI, eq))
+        assert eI <= TOL[prec] and eq <= TOL[prec]
+    ctx.close()
+
+
+def test_axisymmetric_small(torch_dev):
+    """Axisymmetric grid, several wall points, GL x azimuth rays: q per wall
+    point against the oracle's plain ray sum (every azimuth traced)."""
+    wl = synth.axisymmetric(nx=12, nr=6, n_atomic=1500, n_rovib=3000, n_points=8192,
+                            band_points=3000, n_wall=3, n_mu=3, n_phi=5)
+    say("axi small: oracle")
+    ref = O.solve_axi(wl, range(3))
+    ctx = lrt.Context(0).load(wl)
+    for prec in PRECS:
+        q, _, _ = ctx.solve(prec)
+        for w in range(3):
+            e = abs(q[w] - ref["walls"][w]["q"]) / abs(ref["walls"][w]["q"])
+            say("  axi prec %d wall %d: q %.6e ref %.6e rel %.3e" % (prec, w, q[w], ref["walls"][w]["q"], e))
+            assert e <= TOL[prec]
+    ctx.close()
+
+
+def test_axi_segments_match_oracle(torch_dev):
+    """Library traversal vs the oracle's sorted crossings: same cells, same
+    lengths (mirror azimuths are traced once with twice the weight)."""
+    # wall points on the axis, inside cells and exactly on radial cell faces
+    geom = synth.AxiGeometry(20, 8, 7.0, 4.0, np.array([0.0, 0.4, 1.0, 1.1, 2.0, 3.95]), 5, 6)
+    wl = synth.axisymmetric(nx=20, nr=8, Lx=7.0, R=4.0, n_atomic=10, n_rovib=0, n_points=64,
+                            band_points=64, n_wall=6)
+    wl.geometry = geom
+    ctx = lrt.Context(0).load(wl)
+    mu, W = O.gauss_legendre_01(5)
+    r = 0
+    for w, rw in enumerate(geom.wall_r):
+        for i in range(5):
+            for j in range(3):
+                cell, ds, wt, wall = ctx.ray(r)
+                oc, od = O.axi_ray(geom, rw, mu[i], (j + 0.5) * 2 * np.pi / 6)
+                assert wall == w
+                assert wt == pytest.approx(2 * W[i] * mu[i] * 2 * np.pi / 6, rel=1e-13)
+                # A near-tangent graze of a radial face makes a chord of length
+                # ~ sqrt(disc), conditioned like sqrt(eps) r: two correct
+                # traversals may disagree on a sliver below 1e-7 R.  Compare the
+                # path length per cell and the cell sequence without slivers.
+                tol = 1e-7 * geom.R
+                assert ds.sum() == pytest.approx(od.sum(), rel=1e-13)
+                per_lib = np.bincount(cell, weights=ds, minlength=geom.nx * geom.nr)
+                per_orc = np.bincount(oc, weights=od, minlength=geom.nx * geom.nr)
+                np.testing.assert_allclose(per_lib, per_orc, rtol=1e-10, atol=2 * tol)
+
+                def seq(cs, dd):
+                    out = []
+                    for c_, d_ in zip(cs, dd):
+                        if d_ > tol and (not out or out[-1] != c_):
+                            out.append(int(c_))
+                    return out
+                assert seq(cell, ds) == seq(oc, od)
+                r += 1
+    assert r == ctx.sizes()["n_rays"]
+    ctx.close()
+
+
+def test_count_terms_exact(torch_dev):
+    wl = synth.stagnation_line(n_cells=10, n_atomic=2000, n_rovib=4000, n_points=40000,
+                               band_points=15000, n_mu=0)
+    _, _, n_ref = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
+    ctx = lrt.Context(0).load(wl)
+    n = sum(ctx.count_terms(b) for b in range(ctx.sizes()["n_bands"]))
+    cc, _ = O.knife_edges(wl.species, wl.lines, wl.cells, wl.grid)
+    say("terms gpu %d oracle %d knife-edge points %d" % (n, n_ref, cc.size))
+    assert abs(n - n_ref) <= cc.size
+    ctx.close()
+
+
+def test_cold_cell_scaled_single_precision(torch_dev):
+    """A cell at T_v = 500 K has eta ~1e-130: the single-precision form keeps
+    it in range with a per-cell power-of-two scale."""
+    wl = synth.slab_equilibrium(n_cells=3, n_lines_per_species=200, n_points=20000, seed=4)
+    wl.cells.T_v[1] = 500.0
+    wl.cells.T_tr[1] = 30000.0
+    e_ref, k_ref, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
+    assert 0 < e_ref[1].max() < 1e-100
+    ctx = lrt.Context(0).load(wl)
+    eta, kap, esc = ctx.coeffs_torch(0, lrt.LRT_FP32_COMP)
+    e, k = lrt.scaled_to_f64(eta, kap, esc)
+    s = esc.cpu().numpy()
+    say("escale", s.tolist())
+    assert s[1, 0] < -300 and s[0, 0] == 0
+    m = edge_mask(wl, 0, wl.grid.n_points)
+    assert normwise(e, e_ref, m) <= 1e-5 and normwise(k, k_ref, m) <= 1e-5
+    ctx.close()
+
+
+def test_edge_cases(torch_dev):
+    """Empty line list, lines entirely outside the grid, a cell without
+    radiators, n_e = 0 (pure Doppler), a two-point grid, one-point bands."""
+    torch = torch_dev
+    base = synth.slab_equilibrium(n_cells=4, n_lines_per_species=50, n_points=3000, seed=6)
+    # 1) lines outside the grid (centres 1e6 cm^-1 away) and empty list
+    for lines in (base.lines.subset(np.arange(0)),
+                  synth.Lines(*(np.asarray(getattr(base.lines, f)) for f in
+                                ("nu0", "A", "Eu_ev", "Eu_rot", "El_ev", "El_rot", "gu", "gl", "species")))):
+        wl = synth.Workload("edge", base.species, lines, base.cells, base.grid, base.geometry)
+        if lines.n:
+            wl.lines.nu0 = wl.lines.nu0 + 1e6
+            wl.lines.Eu_ev = wl.lines.Eu_ev + 1e6
+        ctx = lrt.Context(0).load(wl)
+        for prec in PRECS:
+            eta, kap, esc = ctx.coeffs_torch(0, prec)
+            torch.cuda.synchronize()
+            assert float(eta.abs().max()) == 0.0 and float(kap.abs().max()) == 0.0
+            q, I_int, _ = ctx.solve(prec)
+            assert np.all(I_int == 0.0)
+        ctx.close()
+    # 2) zero densities in one cell, n_e = 0 in another, two-point grid and
+    #    one-point bands
+    wl = synth.slab_equilibrium(n_cells=4, n_lines_per_species=50, n_points=3000, seed=6)
+    wl.cells.N[1] = 0.0
+    wl.cells.n_e[2] = 0.0
+    check_all_bands(wl, torch)
+    wl.grid = synth.Grid(wl.lines.nu0[10] - 0.01, wl.lines.nu0[10] + 0.02, 2, 1)
+    check_all_bands(wl, torch)
+
+
+def test_invalid_arguments(torch_dev):
+    wl = synth.slab_equilibrium(n_cells=4, n_lines_per_species=20, n_points=1000, seed=2)
+    ctx = lrt.Context(0)
+    with pytest.raises(lrt.LrtError) as e:
+        ctx.set_lines(wl.lines)            # species first
+    assert e.value.status == 6
+    ctx.set_species(wl.species)
+    bad = wl.lines.subset(np.arange(wl.lines.n))
+    bad.nu0 = bad.nu0.copy()
+    bad.nu0[3] = -1.0
+    with pytest.raises(lrt.LrtError) as e:
+        ctx.set_lines(bad)
+    assert e.value.status == 1
+    ctx.set_lines(wl.lines)
+    with pytest.raises(lrt.LrtError):
+        ctx.set_grid(synth.Grid(100.0, 50.0, 10, 10))
+    with pytest.raises(lrt.LrtError):
+        ctx.set_grid(synth.Grid(100.0, 200.0, 1, 10))
+    ctx.set_grid(wl.grid)
+    cells = synth.Cells(wl.cells.T_tr.copy(), wl.cells.T_v.copy(), wl.cells.N.copy(), wl.cells.n_e.copy())
+    cells.T_v[0] = np.nan
+    with pytest.raises(lrt.LrtError):
+        ctx.set_cells(cells)
+    cells.T_v[0] = 5000.0
+    cells.N[1, 0] = -1.0
+    with pytest.raises(lrt.LrtError):
+        ctx.set_cells(cells)
+    ctx.set_cells(wl.cells)
+    import torch
+    eta = torch.zeros((4, 1000), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(lrt.LrtError) as e:
+        ctx.coeffs(5, lrt.LRT_FP64, eta, eta)       # band out of range
+    assert e.value.status == 1
+    with pytest.raises(lrt.LrtError):
+        ctx.coeffs(0, 7, eta, eta)                   # unknown precision
+    with pytest.raises(lrt.LrtError) as e:
+        ctx.solve(lrt.LRT_FP64)                      # no rays
+    assert e.value.status == 6
+    ctx.close()
+
+
+def test_stagnation_full_size_sampled(torch_dev):
+    """400 cells, 2.2M lines (200k atomic + 2M rovibronic), 2^21 points, the
+    launch configuration the benchmark times: eta/kappa of every cell at 512
+    sampled grid points against the oracle evaluated point by point."""
+    torch = torch_dev
+    wl = synth.stagnation_line()
+    ks = synth.sample_points(wl.grid, wl.lines, 512, seed=5)
+    say("stagnation full: oracle at %d points" % ks.size)
+    e_ref, k_ref, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks)
+    cc, kk = O.knife_edges(wl.species, wl.lines, wl.cells, wl.grid)
+    pos = {int(k): j for j, k in enumerate(ks)}
+    m = np.zeros(e_ref.shape, bool)
+    for c, k in zip(cc, kk):
+        if int(k) in pos:
+            m[c, pos[int(k)]] = True
+    ctx = lrt.Context(0).load(wl)
+    kt = torch.as_tensor(ks, device="cuda:0")
+    for prec in PRECS:
+        say("stagnation full prec", prec)
+        eta, kap, esc = ctx.coeffs_torch(0, prec)
+        es, ksmp = eta[:, kt], kap[:, kt]
+        del eta, kap
+        torch.cuda.synchronize()
+        if prec == lrt.LRT_FP32_COMP:
+            e, k = lrt.scaled_to_f64(es, ksmp, esc)
+        else:
+            e, k = es.cpu().numpy(), ksmp.cpu().numpy()
+        ee, ek = normwise(e, e_ref, m), normwise(k, k_ref, m)
+        say("  eta %.3e kappa %.3e (knife-edge points excluded: %d)" % (ee, ek, int(m.sum())))
+        assert ee <= TOL[prec] and ek <= TOL[prec]
+        torch.cuda.empty_cache()
+    ctx.close()
