@@ -54,9 +54,10 @@ typedef enum {
 typedef enum {
     LRT_FP64 = 0,       /* every step in double precision */
     LRT_FP32_COMP = 1   /* populations, widths, windows and quadrature in double;
-                           profile evaluation in single precision with
-                           compensated (Kahan) sums per grid point; eta/kappa
-                           stored as float with a per-cell power-of-two scale */
+                           profile evaluation in single precision; at each grid
+                           point lines are summed in blocks of 32 whose partials
+                           are merged with Kahan's compensation; eta/kappa stored
+                           as float with a per-cell power-of-two scale */
 } lrt_precision;
 
 enum { LRT_KIND_NONE = 0, LRT_KIND_ATOM = 1, LRT_KIND_MOLECULE = 2 };
@@ -174,7 +175,7 @@ lrt_status lrt_trace_axi_ray(int nx, int nr, double Lx, double R, double rw, dou
                              int64_t cap, int32_t *cell, double *ds, int64_t *n);
 
 /* Sizes of the current state: cells, rays, wall points, grid points, bands,
- * band length.  Any pointer may be NULL. */
+ * band length (0 for what is not set).  Any pointer may be NULL. */
 lrt_status lrt_get_sizes(const lrt_ctx *ctx, int64_t *n_cells, int64_t *n_rays, int64_t *n_wall,
                          int64_t *n_points, int64_t *n_bands, int64_t *band_points);
 
@@ -223,8 +224,12 @@ lrt_status lrt_solve(lrt_ctx *ctx, lrt_precision prec, int64_t first_band, doubl
                      double *I_int, double *q_band, void *stream);
 
 /* Number of in-window (cell, line, grid point) terms of band `band`, i.e. the
- * Voigt evaluations the accumulation performs usefully.  Synchronises. */
-lrt_status lrt_count_terms(lrt_ctx *ctx, int64_t band, int64_t *count, void *stream);
+ * Voigt evaluations the accumulation performs usefully, and (core_count, may
+ * be NULL) how many of them lie within 25 Voigt HWHM of the line centre, where
+ * the profile's two exponential terms are not negligible in single precision.
+ * Synchronises. */
+lrt_status lrt_count_terms(lrt_ctx *ctx, int64_t band, int64_t *count, int64_t *core_count,
+                           void *stream);
 
 /* Kernel families timed by the profiler. */
 typedef enum {

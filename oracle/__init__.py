@@ -92,8 +92,8 @@ def lib():
                                              C.POINTER(_Cells), d, d, i64, _dp, _dp]),
             "orc_march": (None, [i64, _i64p, _dp, i64, _dp, _dp, _dp, _dp]),
             "orc_axi_segments": (i64, [C.c_int, C.c_int, d, d, d, d, d, i64, _i64p, _dp]),
-            "orc_knife_edges": (i64, [C.POINTER(_Species), C.POINTER(_Lines), C.POINTER(_Cells),
-                                      d, d, i64, d, i64, _i64p, _i64p]),
+            "orc_knife_edges": (None, [C.POINTER(_Species), C.POINTER(_Lines), C.POINTER(_Cells),
+                                       d, d, i64, d, i64, _i64p, _i64p, _i64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -254,18 +254,30 @@ def coeffs(species, lines, cells, grid, ks: Optional[np.ndarray] = None, threads
     return eta, kap, n
 
 
-def knife_edges(species, lines, cells, grid, tol: float = 1e-9):
-    """(cell, k) grid points next to a window bound that lies within tol
-    (relative) of an integer grid index: a last-bit difference in the Voigt
-    width may move such a bound by one point."""
+def knife_edges(species, lines, cells, grid, tol: float = 1e-9, near=None):
+    """(cell, k) grid points next to a window bound that lies within tol grid
+    steps of an integer grid index: a last-bit difference in the Voigt
+    width may move such a bound by one point.  near: optional sorted grid
+    indices; only lines within 1000 cm^-1 of one of them are scanned."""
+    if near is not None and lines.n:
+        h = grid_step(grid)
+        nu = grid.nu_min + np.asarray(near, np.float64) * h
+        lo = np.searchsorted(lines.nu0, nu - 1000.0)
+        hi = np.searchsorted(lines.nu0, nu + 1000.0)
+        keep = np.zeros(lines.n + 1, np.int64)
+        np.add.at(keep, lo, 1)
+        np.add.at(keep, hi, -1)
+        lines = lines.subset(np.nonzero(np.cumsum(keep)[:-1] > 0)[0])
     st, lt, ct = SpeciesTable(species), LineTable(lines), CellTable(cells)
-    cap = 1 << 16
-    cc = np.zeros(cap, np.int64)
-    kk = np.zeros(cap, np.int64)
-    n = lib().orc_knife_edges(C.byref(st.s), C.byref(lt.s), C.byref(ct.s), grid.nu_min,
-                              grid.nu_max, grid.n_points, tol, cap, _p(cc, _i64p), _p(kk, _i64p))
-    n = min(n, cap)
-    return cc[:n].copy(), kk[:n].copy()
+    cap = 4096
+    cc = np.zeros(cells.n * cap, np.int64)
+    kk = np.zeros(cells.n * cap, np.int64)
+    cnt = np.zeros(cells.n, np.int64)
+    lib().orc_knife_edges(C.byref(st.s), C.byref(lt.s), C.byref(ct.s), grid.nu_min, grid.nu_max,
+                          grid.n_points, tol, cap, _p(cc, _i64p), _p(kk, _i64p), _p(cnt, _i64p))
+    sel = np.concatenate([np.arange(c * cap, c * cap + cnt[c]) for c in range(cells.n)]) \
+        if cells.n else np.zeros(0, np.int64)
+    return cc[sel].copy(), kk[sel].copy()
 
 
 def coeffs_bruteforce(species, lines, cells, grid):

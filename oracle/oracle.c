@@ -461,17 +461,23 @@ int64_t orc_axi_segments(int nx, int nr, double Lx, double R, double rw,
 }
 
 /* Knife edges: (cell, grid index) of window bounds whose real-valued position
- * (nu0 -+ 100 gV - nu_min)/h lies within tol of an integer.  At such a point
+ * (nu0 -+ 100 gV - nu_min)/h lies within tol (grid steps) of an integer.  At such a point
  * a one-ulp difference in gV between two correct implementations moves the
- * bound, so comparisons exclude it.  Returns the count (<= cap entries). */
-int64_t orc_knife_edges(const orc_species *sp, const orc_lines *L, const orc_cells *C,
-                        double nu_min, double nu_max, int64_t n_points, double tol,
-                        int64_t cap, int64_t *cell_out, int64_t *k_out)
+ * bound, so comparisons exclude it.  Cells are scanned in parallel; cell c
+ * writes at most cap_per_cell entries at cell_out/k_out + c * cap_per_cell and
+ * its count to count_out[c]. */
+void orc_knife_edges(const orc_species *sp, const orc_lines *L, const orc_cells *C,
+                     double nu_min, double nu_max, int64_t n_points, double tol,
+                     int64_t cap_per_cell, int64_t *cell_out, int64_t *k_out, int64_t *count_out)
 {
     const double h = (nu_max - nu_min) / (double)(n_points - 1);
     const int S = C->n_species;
-    int64_t n = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
     for (int64_t c = 0; c < C->n_cells; ++c) {
+        int64_t n = 0;
+        int64_t *co = cell_out + c * cap_per_cell, *ko = k_out + c * cap_per_cell;
         for (int64_t i = 0; i < L->n; ++i) {
             int s = L->species[i];
             double Ns = C->N[c * S + s];
@@ -482,16 +488,16 @@ int64_t orc_knife_edges(const orc_species *sp, const orc_lines *L, const orc_cel
             double b[2] = {(L->nu0[i] - W - nu_min) / h, (L->nu0[i] + W - nu_min) / h};
             for (int e = 0; e < 2; ++e) {
                 double r = nearbyint(b[e]);
-                if (fabs(b[e] - r) <= tol * fmax(1.0, fabs(b[e])) && r >= -1 && r <= (double)n_points) {
+                if (fabs(b[e] - r) <= tol && r >= -1 && r <= (double)n_points) {
                     for (int64_t d = -1; d <= 1; ++d) {
                         int64_t k = (int64_t)r + d;
                         if (k < 0 || k >= n_points) continue;
-                        if (n < cap) { cell_out[n] = c; k_out[n] = k; }
+                        if (n < cap_per_cell) { co[n] = c; ko[n] = k; }
                         ++n;
                     }
                 }
             }
         }
+        count_out[c] = n < cap_per_cell ? n : cap_per_cell;
     }
-    return n;
 }

@@ -655,8 +655,8 @@ lrt_status lrt_get_sizes(const lrt_ctx *c, int64_t *n_cells, int64_t *n_rays, in
                          int64_t *n_points, int64_t *n_bands, int64_t *band_points)
 {
     if (!c) return LRT_E_ARG;
-    if (n_cells) *n_cells = c->n_cells;
-    if (n_rays) *n_rays = c->n_rays;
+    if (n_cells) *n_cells = std::max<int64_t>(c->n_cells, 0);
+    if (n_rays) *n_rays = std::max<int64_t>(c->n_rays, 0);
     if (n_wall) *n_wall = c->n_wall;
     if (n_points) *n_points = c->have_grid ? c->n_points : 0;
     if (band_points) *band_points = c->have_grid ? c->band_points : 0;
@@ -900,7 +900,7 @@ lrt_status lrt_solve(lrt_ctx *c, lrt_precision prec, int64_t first_band, double 
     return LRT_OK;
 }
 
-lrt_status lrt_count_terms(lrt_ctx *c, int64_t band, int64_t *count, void *stream)
+lrt_status lrt_count_terms(lrt_ctx *c, int64_t band, int64_t *count, int64_t *core_count, void *stream)
 {
     if (!c) return LRT_E_ARG;
     c->err.clear();
@@ -910,16 +910,17 @@ lrt_status lrt_count_terms(lrt_ctx *c, int64_t band, int64_t *count, void *strea
     if ((r = prepare(c, st, false))) return r;
     int32_t k_first, n_band;
     if ((r = band_range(c, band, k_first, n_band))) return r;
-    if ((r = ensure(c, c->w_count, 8))) return r;
-    LRT_HIP(c, launch_fill_u64(c->w_count.as<unsigned long long>(), 0ull, 1, st));
+    if ((r = ensure(c, c->w_count, 16))) return r;
+    LRT_HIP(c, launch_fill_u64(c->w_count.as<unsigned long long>(), 0ull, 2, st));
     const DevGrid g{c->nu_min, c->h, (int32_t)c->n_points};
     LRT_HIP(c, launch_count(dev_lines(c), g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
                             (int32_t)c->n_cells, c->n_species, k_first, n_band,
                             c->w_count.as<unsigned long long>(), st));
-    unsigned long long v = 0;
-    LRT_HIP(c, hipMemcpyAsync(&v, c->w_count.p, 8, hipMemcpyDeviceToHost, st));
+    unsigned long long v[2] = {0, 0};
+    LRT_HIP(c, hipMemcpyAsync(v, c->w_count.p, 16, hipMemcpyDeviceToHost, st));
     LRT_HIP(c, hipStreamSynchronize(st));
-    *count = (int64_t)v;
+    *count = (int64_t)v[0];
+    if (core_count) *core_count = (int64_t)v[1];
     return LRT_OK;
 }
 

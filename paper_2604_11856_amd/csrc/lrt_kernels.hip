@@ -86,7 +86,14 @@ struct PairF64 {
     double se, sk;        // eta and kappa per unit profile shape (strength * norm)
     double inv2g, r;      // 1 / (2 gamma_V), gamma_L / gamma_V
     int32_t klo, khi;     // inclusive window, klo > khi when empty
+    int32_t kclo, kchi;   // core: points with |nu_k - nu0| <= 25 gamma_V (x <= 12.5)
 };
+
+// Half-width of the core in units of gamma_V.  Beyond it x = |dnu|/(2 gamma_V)
+// > 12.5, where e^{-2.772 x^2} (< 2^-620) and e^{-0.4 x^2.25} (< 2^-169) are
+// exactly zero in single precision, so the profile reduces to its two
+// rational terms.
+constexpr double kCoreHalfWidth = 25.0;
 
 __device__ __forceinline__ bool pair_setup(const DevLines &L, const DevGrid &g, const CellConst &k,
                                            const CellSpecies *csc, int64_t i, PairF64 &p)
@@ -94,8 +101,8 @@ __device__ __forceinline__ bool pair_setup(const DevLines &L, const DevGrid &g, 
     const int s = L.species[i];
     const CellSpecies q = csc[s];
     if (!(q.lnNQ > -INFINITY)) {
-        p.klo = 1;
-        p.khi = 0;
+        p.klo = p.kclo = 1;
+        p.khi = p.kchi = 0;
         p.se = p.sk = p.inv2g = p.r = 0.0;
         return false;
     }
@@ -132,6 +139,18 @@ __device__ __forceinline__ bool pair_setup(const DevLines &L, const DevGrid &g, 
     } else {
         p.klo = (int32_t)lo;
         p.khi = (int32_t)hi;
+    }
+    {
+        const double Wc = kCoreHalfWidth * gV;
+        double clo = fmax(ceil((nu0 - Wc - g.nu_min) / g.h), lo);
+        double chi = fmin(floor((nu0 + Wc - g.nu_min) / g.h), hi);
+        if (clo > chi) {
+            p.kclo = 1;
+            p.kchi = 0;
+        } else {
+            p.kclo = (int32_t)clo;
+            p.kchi = (int32_t)chi;
+        }
     }
     p.se = Seta * norm;
     p.sk = Skap * norm;
@@ -216,9 +235,13 @@ __global__ void scale_finish_kernel(const int32_t *emax, int32_t n, int32_t *esc
 // a3: line-to-grid accumulation
 // ---------------------------------------------------------------------------
 
+// Single-precision line record staged in LDS.  Grid indices inside the
+// kernel are relative to the tile start, so every float index is a small
+// exact integer whatever the grid size.
 struct __align__(16) RecF32 {
-    int32_t klo, khi;
-    float k0f, hs, fs, r, se, sk;
+    int32_t klo, khi, kclo, kchi;   // window and core window, tile-relative
+    float k0f, hs, fs, r;           // centre index, h/(2 gV), frac0/(2 gV), gL/gV
+    float aG, aW, se, sk;           // 1-r, 0.016 r (1-r), scaled strengths
 };
 
 struct __align__(16) RecF64 {
@@ -226,22 +249,37 @@ struct __align__(16) RecF64 {
     double frac0, inv2g, r, se, sk, pad2;
 };
 
-// Profile shape P(x) of the Whiting form with x = |dk h - frac0| / (2 gamma_V):
-// (1-r) e^{-2.772 x^2} + r/(1+4x^2) + 0.016 r(1-r)[e^{-0.4 x^2.25} - 1/(1+0.1 x^2.25)],
-// the two rational terms over one reciprocal.
-__device__ __forceinline__ float shape_f32(float x, float r)
+// Rational part of the Whiting profile at x = |dk h - frac0| / (2 gamma_V):
+// r/(1+4x^2) - 0.016 r(1-r)/(1+0.1 x^2.25) over one reciprocal; also returns
+// x^2 and x^2.25 for the exponential part.
+__device__ __forceinline__ float shape_rational_f32(float kf, const RecF32 &q, float &u, float &p)
 {
-    const float u = x * x;
-    const float g = __builtin_amdgcn_exp2f(u * (float)(-2.772 * kLog2e));
-    const float p = __builtin_amdgcn_exp2f(2.25f * __builtin_amdgcn_logf(x));
-    const float e = __builtin_amdgcn_exp2f(p * (float)(-0.4 * kLog2e));
+    const float x = fabsf(fmaf(kf - q.k0f, q.hs, -q.fs));
+    u = x * x;
+    p = __builtin_amdgcn_exp2f(2.25f * __builtin_amdgcn_logf(x));
     const float d1 = fmaf(4.0f, u, 1.0f);
     const float d2 = fmaf(0.1f, p, 1.0f);
-    const float aG = 1.0f - r;
-    const float aW = 0.016f * r * aG;
-    const float num = fmaf(r, d2, -aW * d1);
-    const float rat = num * __builtin_amdgcn_rcpf(d1 * d2);
-    return fmaf(aG, g, fmaf(aW, e, rat));
+    const float num = fmaf(q.r, d2, -(q.aW * d1));
+    return num * __builtin_amdgcn_rcpf(d1 * d2);
+}
+
+// Exponential part: (1-r) e^{-2.772 x^2} + 0.016 r(1-r) e^{-0.4 x^2.25} added to P.
+__device__ __forceinline__ float shape_exp_f32(const RecF32 &q, float u, float p, float P)
+{
+    const float gs = __builtin_amdgcn_exp2f(u * (float)(-2.772 * kLog2e));
+    const float e = __builtin_amdgcn_exp2f(p * (float)(-0.4 * kLog2e));
+    return fmaf(q.aG, gs, fmaf(q.aW, e, P));
+}
+
+__device__ __forceinline__ int32_t uniform_i(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Compensated (Kahan) addition of a block partial v into (s, c).
+__device__ __forceinline__ void kahan_add(float &s, float &c, float v)
+{
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
 }
 
 __device__ __forceinline__ double shape_f64(double x, double r)
@@ -253,6 +291,10 @@ __device__ __forceinline__ double shape_f64(double x, double r)
     return (1.0 - r) * gs + r / (1.0 + 4.0 * u) + 0.016 * r * (1.0 - r) * (e - 1.0 / (1.0 + 0.1 * p));
 }
 
+// Lines per compensated block: partials of at most kBlock terms are added
+// plainly, blocks are merged with Kahan's compensation.
+constexpr int kBlock = 32;
+
 __global__ __launch_bounds__(kAccumThreads) void accum_f32_kernel(
     DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int32_t *escale,
     const int2 *ranges, int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles,
@@ -260,38 +302,42 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f32_kernel(
 {
     __shared__ RecF32 rec[kStage];
     const int tile = (int)(blockIdx.x % n_tiles), c = (int)(blockIdx.x / n_tiles);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int32_t kt = k_first + tile * kTilePoints;            // first point of the tile
-    const int32_t kw = kt + wave * 64 * kPPL;                   // first point of the wave
-    const int32_t kend = k_first + n_band;                      // exclusive
+    // the wave index is uniform across the wave: keep it (and every bound
+    // derived from it) in scalar registers so slice tests are scalar branches
+    const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
+    const int32_t kt = k_first + tile * kTilePoints;   // first (global) point of the tile
+    const int32_t kw = wave * 64 * kPPL;               // first point of the wave, tile-relative
+    const int32_t kw_last = kw + 64 * kPPL - 1;
+    const int32_t kend = k_first + n_band;             // exclusive, global
     const CellConst k = cc[c];
     const CellSpecies *csc = cs + (int64_t)c * n_species;
     const int ese = escale[2 * c + 0], esk = escale[2 * c + 1];
     const int2 rg = ranges[(int64_t)c * n_tiles + tile];
 
-    float kf[kPPL], se[kPPL], ce[kPPL], sk[kPPL], ck[kPPL];
+    float se[kPPL], ce[kPPL], sk[kPPL], ck[kPPL], ae[kPPL], ak[kPPL];
 #pragma unroll
-    for (int j = 0; j < kPPL; ++j) {
-        kf[j] = (float)(kw + 64 * j + lane);
-        se[j] = ce[j] = sk[j] = ck[j] = 0.0f;
-    }
-    const int32_t kw_last = kw + 64 * kPPL - 1;
+    for (int j = 0; j < kPPL; ++j) se[j] = ce[j] = sk[j] = ck[j] = ae[j] = ak[j] = 0.0f;
 
     for (int base = rg.x; base < rg.y; base += kStage) {
+        // stage: one (cell, line) setup per thread, in double precision
         const int64_t i = (int64_t)base + threadIdx.x;
         RecF32 rr;
-        rr.klo = 1;
-        rr.khi = 0;
-        rr.k0f = rr.hs = rr.fs = rr.r = rr.se = rr.sk = 0.0f;
+        rr.klo = rr.kclo = 1;
+        rr.khi = rr.kchi = 0;
+        rr.k0f = rr.hs = rr.fs = rr.r = rr.aG = rr.aW = rr.se = rr.sk = 0.0f;
         if (i < rg.y) {
             PairF64 p;
             if (pair_setup(L, g, k, csc, i, p)) {
-                rr.klo = p.klo;
-                rr.khi = p.khi;
-                rr.k0f = (float)L.k0[i];
+                rr.klo = p.klo - kt;
+                rr.khi = p.khi - kt;
+                rr.kclo = p.kclo - kt;
+                rr.kchi = p.kchi - kt;
+                rr.k0f = (float)(L.k0[i] - kt);
                 rr.hs = (float)(g.h * p.inv2g);
                 rr.fs = (float)(L.frac0[i] * p.inv2g);
                 rr.r = (float)p.r;
+                rr.aG = (float)(1.0 - p.r);
+                rr.aW = (float)(0.016 * p.r * (1.0 - p.r));
                 rr.se = (float)ldexp(p.se, -ese);
                 rr.sk = (float)ldexp(p.sk, -esk);
             }
@@ -299,33 +345,49 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f32_kernel(
         rec[threadIdx.x] = rr;
         __syncthreads();
         const int n = min(kStage, rg.y - base);
-        for (int l = 0; l < n; ++l) {
-            const RecF32 q = rec[l];
-            if (q.khi < kw || q.klo > kw_last) continue;
+        for (int l0 = 0; l0 < n; l0 += kBlock) {
+            const int l1 = min(l0 + kBlock, n);
+            for (int l = l0; l < l1; ++l) {
+                const RecF32 q = rec[l];
+                const int32_t klo = uniform_i(q.klo), khi = uniform_i(q.khi);
+                if (khi < kw || klo > kw_last) continue;
+                const int32_t kclo = uniform_i(q.kclo), kchi = uniform_i(q.kchi);
+#pragma unroll
+                for (int j = 0; j < kPPL; ++j) {
+                    const int32_t a = kw + 64 * j, b = a + 63;
+                    if (khi < a || klo > b) continue;          // slice outside the window
+                    const int32_t kk = a + lane;
+                    float u, pw;
+                    float P = shape_rational_f32((float)kk, q, u, pw);
+                    // Within 25 HWHM of the centre the exponentials contribute;
+                    // beyond it they are exactly zero in single precision.  Both
+                    // conditions are wave-uniform; the empty asm keeps them real
+                    // scalar branches instead of computing both sides and selecting.
+                    if (!(kchi < a || kclo > b)) {
+                        asm volatile("");
+                        P = shape_exp_f32(q, u, pw, P);
+                    }
+                    // slice crossing a window edge: mask the lanes outside
+                    if (!(klo <= a && khi >= b)) {
+                        asm volatile("");
+                        P = (kk >= klo && kk <= khi) ? P : 0.0f;
+                    }
+                    ae[j] = fmaf(P, q.se, ae[j]);
+                    ak[j] = fmaf(P, q.sk, ak[j]);
+                }
+            }
 #pragma unroll
             for (int j = 0; j < kPPL; ++j) {
-                const int32_t k0j = kw + 64 * j;
-                if (q.khi < k0j || q.klo > k0j + 63) continue;
-                const float x = fabsf(fmaf(kf[j] - q.k0f, q.hs, -q.fs));
-                const float P = shape_f32(x, q.r);
-                const int32_t kk = k0j + lane;
-                const float v = (kk >= q.klo && kk <= q.khi) ? P : 0.0f;
-                // Kahan: s + v with the running compensation c
-                const float ye = fmaf(v, q.se, -ce[j]);
-                const float te = se[j] + ye;
-                ce[j] = (te - se[j]) - ye;
-                se[j] = te;
-                const float yk = fmaf(v, q.sk, -ck[j]);
-                const float tk = sk[j] + yk;
-                ck[j] = (tk - sk[j]) - yk;
-                sk[j] = tk;
+                kahan_add(se[j], ce[j], ae[j]);
+                kahan_add(sk[j], ck[j], ak[j]);
+                ae[j] = ak[j] = 0.0f;
             }
         }
         __syncthreads();
     }
 #pragma unroll
     for (int j = 0; j < kPPL; ++j) {
-        const int32_t kk = kw + 64 * j + lane;
+        const int32_t kk = kt + kw + 64 * j + lane;
         if (kk < kend) {
             const int64_t o = (int64_t)c * n_band + (kk - k_first);
             eta[o] = se[j] - ce[j];
@@ -417,18 +479,26 @@ __global__ void count_kernel(DevLines L, DevGrid g, const CellConst *cc, const C
                              unsigned long long *count)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long n = 0;
+    unsigned long long n = 0, nc = 0;
     for (int c = blockIdx.y; c < n_cells; c += gridDim.y) {
         if (i < L.n) {
             PairF64 p;
             if (pair_setup(L, g, cc[c], cs + (int64_t)c * n_species, i, p)) {
                 const int32_t a = max(p.klo, k_first), b = min(p.khi, k_first + n_band - 1);
                 if (b >= a) n += (unsigned long long)(b - a + 1);
+                const int32_t ca = max(p.kclo, k_first), cb = min(p.kchi, k_first + n_band - 1);
+                if (cb >= ca) nc += (unsigned long long)(cb - ca + 1);
             }
         }
     }
-    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
-    if ((threadIdx.x & 63) == 0 && n) atomicAdd(count, n);
+    for (int o = 32; o > 0; o >>= 1) {
+        n += __shfl_xor(n, o);
+        nc += __shfl_xor(nc, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (n) atomicAdd(&count[0], n);
+        if (nc) atomicAdd(&count[1], nc);
+    }
 }
 
 // ---------------------------------------------------------------------------

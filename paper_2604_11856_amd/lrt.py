@@ -92,7 +92,7 @@ def lib():
             "lrt_coeffs": (st, [_vp, C.c_int64, C.c_int, _vp, _vp, _vp, _vp]),
             "lrt_march": (st, [_vp, C.c_int64, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]),
             "lrt_solve": (st, [_vp, C.c_int, C.c_int64, _dp, _dp, _dp, _vp]),
-            "lrt_count_terms": (st, [_vp, C.c_int64, _i64p, _vp]),
+            "lrt_count_terms": (st, [_vp, C.c_int64, _i64p, _i64p, _vp]),
             "lrt_profile": (st, [_vp, C.c_int]),
             "lrt_profile_read": (st, [_vp, C.c_int, _dp, _i64p]),
         }
@@ -240,10 +240,12 @@ class Context:
                                     _stream(stream)))
         return q, I_int, qb
 
-    def count_terms(self, band: int, stream=None) -> int:
-        n = C.c_int64()
-        self._chk(self._L.lrt_count_terms(self.h, band, C.byref(n), _stream(stream)))
-        return n.value
+    def count_terms(self, band: int, stream=None, core: bool = False):
+        """In-window terms of a band; with core=True also those within 25
+        Voigt HWHM of their line centre: (total, core)."""
+        n, nc = C.c_int64(), C.c_int64()
+        self._chk(self._L.lrt_count_terms(self.h, band, C.byref(n), C.byref(nc), _stream(stream)))
+        return (n.value, nc.value) if core else n.value
 
     def profile(self, enable: bool = True):
         self._chk(self._L.lrt_profile(self.h, 1 if enable else 0))

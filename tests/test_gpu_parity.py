@@ -2,7 +2,7 @@
 
 Bars: LRT_FP64 within 1e-12 and LRT_FP32_COMP within 1e-5, relative and
 normwise per cell (eta, kappa) or per ray (I); scalar integrals (I_int, q)
-relative.  Window bounds that sit within 1e-9 of an integer grid index
+relative.  Window bounds that sit within 1e-9 grid steps of an integer index
 (knife edges, where a last-bit difference in the Voigt width between two
 correct libms moves the bound) are excluded and counted.
 """
@@ -249,7 +249,7 @@ def test_cold_cell_scaled_single_precision(torch_dev):
     wl.cells.T_v[1] = 500.0
     wl.cells.T_tr[1] = 30000.0
     e_ref, k_ref, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
-    assert 0 < e_ref[1].max() < 1e-100
+    assert 0 < e_ref[1].max() < 1e-80
     ctx = lrt.Context(0).load(wl)
     eta, kap, esc = ctx.coeffs_torch(0, lrt.LRT_FP32_COMP)
     e, k = lrt.scaled_to_f64(eta, kap, esc)
@@ -342,7 +342,7 @@ def test_stagnation_full_size_sampled(torch_dev):
     ks = synth.sample_points(wl.grid, wl.lines, 512, seed=5)
     say("stagnation full: oracle at %d points" % ks.size)
     e_ref, k_ref, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks)
-    cc, kk = O.knife_edges(wl.species, wl.lines, wl.cells, wl.grid)
+    cc, kk = O.knife_edges(wl.species, wl.lines, wl.cells, wl.grid, near=ks)
     pos = {int(k): j for j, k in enumerate(ks)}
     m = np.zeros(e_ref.shape, bool)
     for c, k in zip(cc, kk):
