@@ -250,6 +250,80 @@ lrt_status lrt_profile(lrt_ctx *ctx, int enable);
  * kernel family since profiling was enabled.  Waits for the recorded events. */
 lrt_status lrt_profile_read(lrt_ctx *ctx, int kernel, double *ms, int64_t *launches);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of line-of-sight requests                     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct lrt_server lrt_server;
+
+/* One line of sight from a coupled flow solver: cells ordered from the far
+ * (free) boundary to the observer with path length ds[c] (cm), cell states as
+ * in lrt_cells (host pointers, copied at submit), a window of n_window grid
+ * points starting at k_first on the context's resident grid, and the species
+ * that radiate (bit s of species_mask; 0 = every species with lines).
+ * keep_spectrum != 0 keeps I over the window for lrt_poll / lrt_wait. */
+typedef struct {
+    int64_t n_cells;
+    int n_species;
+    const double *T_tr, *T_v, *N, *n_e, *ds;
+    int64_t k_first, n_window;
+    uint64_t species_mask;
+    int keep_spectrum;
+} lrt_los_request;
+
+/* Result of one request: status (LRT_OK, or the error that ended it;
+ * LRT_E_STATE for a cancelled request), the spectral integral of the observer
+ * intensity over the window (trapezoid, h/2 at both window ends; W cm^-2
+ * sr^-1), the window length, and host-clock times from submission to
+ * admission and to the result being available (ms). */
+typedef struct {
+    lrt_status status;
+    double I_int;
+    int64_t n_window;
+    double queue_ms, latency_ms;
+} lrt_los_result;
+
+/* Start the serving loop on ctx, whose species, lines and grid must be set
+ * (ctx cells and rays are not used; ctx must not be used for other calls until
+ * lrt_server_stop).  hbm_budget_bytes of device memory are allocated once and
+ * shared by admitted requests; at most max_slots requests are admitted at a
+ * time.  Each request is computed by fused kernels (populations, setups,
+ * accumulation and march per spectral tile and chunk of cells, then the
+ * chunks composed in order), single-precision compensated profile sums, FP64
+ * march state and quadrature; no eta/kappa array is stored.  Errors:
+ * LRT_E_ARG (max_slots < 1, budget < 1 MiB), LRT_E_STATE (missing set_*),
+ * LRT_E_OOM, LRT_E_DEVICE. */
+lrt_status lrt_server_start(lrt_ctx *ctx, size_t hbm_budget_bytes, int max_slots, lrt_server **out);
+
+/* Copy a request in and queue it; never waits for the GPU.  *ticket receives
+ * its handle.  Errors: LRT_E_ARG (invalid cells, ds <= 0, window outside the
+ * grid, species count), LRT_E_BUDGET (the request could never fit the budget),
+ * LRT_E_STATE (server stopping), LRT_E_DEVICE (server failed). */
+lrt_status lrt_submit(lrt_server *s, const lrt_los_request *req, uint64_t *ticket);
+
+/* LRT_E_NOT_READY until the request is finished; then fills *out (and the
+ * n_window doubles of spectrum, if non-NULL and the request kept it), forgets
+ * the ticket and returns LRT_OK.  LRT_E_ARG for an unknown ticket. */
+lrt_status lrt_poll(lrt_server *s, uint64_t ticket, lrt_los_result *out, double *spectrum);
+
+/* As lrt_poll, waiting up to timeout_ms (negative: no limit). */
+lrt_status lrt_wait(lrt_server *s, uint64_t ticket, double timeout_ms, lrt_los_result *out,
+                    double *spectrum);
+
+/* Withdraw a request that has not been admitted yet (its result then reports
+ * LRT_E_STATE).  LRT_E_STATE if it is already admitted, LRT_E_ARG if unknown. */
+lrt_status lrt_cancel(lrt_server *s, uint64_t ticket);
+
+/* Counters: requests waiting for admission, admitted and not finished,
+ * completed so far, epochs launched, arena bytes in use.  Any pointer may be
+ * NULL. */
+lrt_status lrt_server_info(lrt_server *s, int64_t *pending, int64_t *admitted, int64_t *completed,
+                           int64_t *epochs, size_t *bytes_in_use);
+
+/* Finish every queued and admitted request, then free the server.  Results
+ * not yet taken are dropped.  NULL is accepted. */
+lrt_status lrt_server_stop(lrt_server *s);
+
 #ifdef __cplusplus
 }
 #endif

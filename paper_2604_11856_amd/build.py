@@ -26,13 +26,16 @@ def build_library(out: str = LIB) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     k_obj = os.path.join(bdir, "lrt_kernels.o")
-    h_obj = os.path.join(bdir, "lrt_host.o")
+    objs = [k_obj]
     _run([HIPCC, *ARCH, *COMMON, *NO_PK, "-c", os.path.join(CSRC, "lrt_kernels.hip"), "-o", k_obj])
     # host code: no FP contraction, so the two-sum / two-product grid offsets stay exact
-    _run([HIPCC, *ARCH, *COMMON, "-ffp-contract=off", "-x", "hip", *NO_PK, "-c",
-          os.path.join(CSRC, "lrt_host.cpp"), "-o", h_obj])
+    for name in ("lrt_host", "lrt_serve"):
+        obj = os.path.join(bdir, name + ".o")
+        _run([HIPCC, *ARCH, *COMMON, "-ffp-contract=off", "-x", "hip", *NO_PK, "-c",
+              os.path.join(CSRC, name + ".cpp"), "-o", obj])
+        objs.append(obj)
     tmp = out + ".tmp%d" % os.getpid()
-    _run([HIPCC, *ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, h_obj])
+    _run([HIPCC, *ARCH, "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, out)
     return out
 

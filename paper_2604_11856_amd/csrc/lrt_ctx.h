@@ -1,0 +1,123 @@
+// Host-side context of liblrt, shared by lrt_host.cpp and lrt_serve.cpp.
+// Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/lrt.h"
+#include "lrt_internal.h"
+
+namespace lrt {
+
+// Device buffer owned by the context (hipFree on release).
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+}  // namespace lrt
+
+struct lrt_ctx {
+    using DBuf = lrt::DBuf;
+    using DevSpecies = lrt::DevSpecies;
+    int device = 0;
+    std::string err;
+
+    // species
+    int n_species = 0;
+    std::vector<int32_t> sp_kind;
+    std::vector<double> sp_mass;
+    DBuf d_kind, d_mass, d_lev_off, d_lev_E, d_lev_g, d_el_off, d_el_T, d_el_g, d_el_J,
+        d_vib_off, d_vib_G, d_vib_B, d_vib_D;
+    DevSpecies sp{};
+    double M_min = 0.0;
+
+    // lines (sorted by nu0 on the host, resident on the device)
+    int64_t n_lines = -1;
+    std::vector<double> h_nu0;   // sorted centres, host copy for k0/frac0
+    DBuf d_nu0, d_A, d_Eu_ev, d_Eu_rot, d_El_ev, d_El_rot, d_lngu, d_species, d_k0, d_frac0;
+    bool lines_grid_ready = false;
+
+    // grid
+    bool have_grid = false;
+    double nu_min = 0, nu_max = 0, h = 0;
+    int64_t n_points = 0, band_points = 0;
+
+    // cells
+    int64_t n_cells = -1;
+    DBuf d_T_tr, d_T_v, d_N, d_n_e;
+    DBuf d_cc, d_cs;
+    bool thermo_ready = false;
+    DBuf d_emax, d_escale;
+    bool scale_ready = false;
+
+    // rays
+    int64_t n_rays = -1, n_wall = 0;
+    int64_t rays_cells = 0;   // number of cells the geometry expects
+    std::vector<int64_t> h_off;
+    std::vector<int32_t> h_cell;
+    std::vector<double> h_ds, h_weight;
+    std::vector<int64_t> h_wall_off, h_ray_wall;
+    DBuf d_off, d_cell, d_ds, d_weight, d_wall_off;
+
+    // workspace
+    DBuf w_ranges, w_eta, w_kappa, w_partials, w_Iband, w_Itot, w_qband, w_count;
+
+    // profiler: event pairs per kernel family
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[LRT_K_COUNT];
+
+    void clear_events()
+    {
+        for (auto &v : ev) {
+            for (auto &p : v) {
+                (void)hipEventDestroy(p.first);
+                (void)hipEventDestroy(p.second);
+            }
+            v.clear();
+        }
+    }
+    ~lrt_ctx() { clear_events(); }
+};
+
+namespace lrt {
+
+// Record the message and return the status (ctx == NULL: the thread's
+// create-time message).
+lrt_status fail(lrt_ctx *c, lrt_status s, const char *fmt, ...);
+// Allocate (and fill from src, if not NULL) a device buffer.
+lrt_status upload(lrt_ctx *c, DBuf &b, const void *src, size_t bytes);
+// Grow-only workspace.
+lrt_status ensure(lrt_ctx *c, DBuf &b, size_t bytes);
+// Lines placed on the grid (k0, frac0).
+lrt_status prepare_lines(lrt_ctx *c);
+// Lines on the grid, per-cell constants (and scales when need_scale).
+lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force = false);
+DevLines dev_lines(const lrt_ctx *c);
+
+}  // namespace lrt
+
+#define LRT_HIP(ctx, call)                                                                     \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return ::lrt::fail((ctx), LRT_E_DEVICE, "%s: %s (%s:%d)", #call,                   \
+                               hipGetErrorString(e_), __FILE__, __LINE__);                     \
+    } while (0)

@@ -13,93 +13,18 @@
 #include <vector>
 
 #include "../../include/lrt.h"
+#include "lrt_ctx.h"
 #include "lrt_internal.h"
 
 using namespace lrt;
 
 namespace {
-
 thread_local std::string g_create_error;
-
-// Device buffer owned by the context.
-struct DBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    ~DBuf() { release(); }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <class T>
-    T *as() const { return static_cast<T *>(p); }
-};
-
 }  // namespace
 
-struct lrt_ctx {
-    int device = 0;
-    std::string err;
 
-    // species
-    int n_species = 0;
-    std::vector<int32_t> sp_kind;
-    std::vector<double> sp_mass;
-    DBuf d_kind, d_mass, d_lev_off, d_lev_E, d_lev_g, d_el_off, d_el_T, d_el_g, d_el_J,
-        d_vib_off, d_vib_G, d_vib_B, d_vib_D;
-    DevSpecies sp{};
-    double M_min = 0.0;
 
-    // lines (sorted by nu0 on the host, resident on the device)
-    int64_t n_lines = -1;
-    std::vector<double> h_nu0;   // sorted centres, host copy for k0/frac0
-    DBuf d_nu0, d_A, d_Eu_ev, d_Eu_rot, d_El_ev, d_El_rot, d_lngu, d_species, d_k0, d_frac0;
-    bool lines_grid_ready = false;
-
-    // grid
-    bool have_grid = false;
-    double nu_min = 0, nu_max = 0, h = 0;
-    int64_t n_points = 0, band_points = 0;
-
-    // cells
-    int64_t n_cells = -1;
-    DBuf d_T_tr, d_T_v, d_N, d_n_e;
-    DBuf d_cc, d_cs;
-    bool thermo_ready = false;
-    DBuf d_emax, d_escale;
-    bool scale_ready = false;
-
-    // rays
-    int64_t n_rays = -1, n_wall = 0;
-    int64_t rays_cells = 0;   // number of cells the geometry expects
-    std::vector<int64_t> h_off;
-    std::vector<int32_t> h_cell;
-    std::vector<double> h_ds, h_weight;
-    std::vector<int64_t> h_wall_off, h_ray_wall;
-    DBuf d_off, d_cell, d_ds, d_weight, d_wall_off;
-
-    // workspace
-    DBuf w_ranges, w_eta, w_kappa, w_partials, w_Iband, w_Itot, w_qband, w_count;
-
-    // profiler: event pairs per kernel family
-    bool prof = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[LRT_K_COUNT];
-
-    void clear_events()
-    {
-        for (auto &v : ev) {
-            for (auto &p : v) {
-                (void)hipEventDestroy(p.first);
-                (void)hipEventDestroy(p.second);
-            }
-            v.clear();
-        }
-    }
-    ~lrt_ctx() { clear_events(); }
-};
-
-namespace {
+namespace lrt {
 
 lrt_status fail(lrt_ctx *c, lrt_status s, const char *fmt, ...)
 {
@@ -112,13 +37,7 @@ lrt_status fail(lrt_ctx *c, lrt_status s, const char *fmt, ...)
     return s;
 }
 
-#define LRT_HIP(ctx, call)                                                                     \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return fail((ctx), LRT_E_DEVICE, "%s: %s (%s:%d)", #call, hipGetErrorString(e_),   \
-                        __FILE__, __LINE__);                                                   \
-    } while (0)
+
 
 // Launch `fn` (returning hipError_t) on stream st, bracketed by events when
 // the context profiles.
@@ -169,6 +88,10 @@ lrt_status ensure(lrt_ctx *c, DBuf &b, size_t bytes)
     if (b.bytes >= bytes && b.p) return LRT_OK;
     return upload(c, b, nullptr, bytes);
 }
+
+}  // namespace lrt
+
+namespace {
 
 bool finite_all(const double *p, int64_t n)
 {
@@ -690,18 +613,13 @@ lrt_status lrt_get_ray(const lrt_ctx *cc, int64_t r, int64_t cap, int32_t *cell,
 // preparation and the compute entry points
 // ===========================================================================
 
-namespace {
+namespace lrt {
 
-lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force = false)
+lrt_status prepare_lines(lrt_ctx *c)
 {
-    if (force) {
-        c->thermo_ready = false;
-        c->scale_ready = false;
-    }
     if (c->n_species < 1) return fail(c, LRT_E_STATE, "species not set");
     if (c->n_lines < 0) return fail(c, LRT_E_STATE, "lines not set");
     if (!c->have_grid) return fail(c, LRT_E_STATE, "grid not set");
-    if (c->n_cells < 1) return fail(c, LRT_E_STATE, "cells not set");
     if (!c->lines_grid_ready) {
         // nu0 = nu_min + k0 h + frac0 with frac0 correctly rounded: k0 h and
         // nu_min + k0 h are carried as unevaluated sums (two-product by fma,
@@ -725,11 +643,23 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force = fal
         if ((r = upload_vec(c, c->d_k0, k0)) || (r = upload_vec(c, c->d_frac0, fr))) return r;
         c->lines_grid_ready = true;
     }
+    return LRT_OK;
+}
+
+lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
+{
+    if (force) {
+        c->thermo_ready = false;
+        c->scale_ready = false;
+    }
+    lrt_status r0 = prepare_lines(c);
+    if (r0) return r0;
+    if (c->n_cells < 1) return fail(c, LRT_E_STATE, "cells not set");
     if (!c->thermo_ready) {
         DevCells cells{(int32_t)c->n_cells, c->n_species, c->d_T_tr.as<double>(), c->d_T_v.as<double>(),
                        c->d_N.as<double>(), c->d_n_e.as<double>()};
         LRT_HIP(c, timed(c, LRT_K_THERMO, st, [&] {
-                    return launch_thermo(c->sp, cells, c->M_min, c->d_cc.as<CellConst>(),
+                    return launch_thermo(c->sp, cells, c->M_min, 0, c->d_cc.as<CellConst>(),
                                          c->d_cs.as<CellSpecies>(), st);
                 }));
         c->thermo_ready = true;
@@ -742,7 +672,7 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force = fal
         DevGrid g{c->nu_min, c->h, (int32_t)c->n_points};
         LRT_HIP(c, launch_fill_i32(c->d_emax.as<int32_t>(), INT_MIN, 2 * c->n_cells, st));
         LRT_HIP(c, timed(c, LRT_K_SCALE, st, [&] {
-                    return launch_scale(L, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
+                    return launch_scale(L, 0, L.n, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
                                         (int32_t)c->n_cells, c->n_species, c->d_emax.as<int32_t>(),
                                         c->d_escale.as<int32_t>(), st);
                 }));
@@ -831,7 +761,7 @@ lrt_status march_impl(lrt_ctx *c, int64_t band, lrt_precision prec, const void *
     return LRT_OK;
 }
 
-}  // namespace
+}  // namespace lrt
 
 extern "C" {
 

@@ -84,17 +84,36 @@ struct DevRays {
     const double *ds;
 };
 
+// One admitted line-of-sight request as the serving kernels see it.
+struct ServeReq {
+    int32_t n_cells, k_first, n_window, n_tiles, n_chunks, chunk_cells;
+    const CellConst *cc;
+    const CellSpecies *cs;
+    const int32_t *escale;   // [cell][2]
+    const double *ds;        // [cell], far -> observer
+    const int2 *ranges;      // [cell][tile]
+    double *TS;              // [tile][chunk][2][kTilePoints]: transmittance, source
+    double *I_out;           // [n_window]
+    double *partials;        // [ceil(n_window / 256)]
+    double *I_int;           // [1]
+};
+
+// One unit of serving work: the cells of one chunk on one tile of a request.
+struct ServeItem {
+    int32_t req, tile, chunk;
+};
+
 // ---- kernel launchers (lrt_kernels.hip) ----
 hipError_t launch_thermo(const DevSpecies &sp, const DevCells &cells, double M_min,
-                         CellConst *cc, CellSpecies *cs, hipStream_t st);
+                         uint64_t species_mask, CellConst *cc, CellSpecies *cs, hipStream_t st);
 
 hipError_t launch_ranges(const DevLines &L, const DevGrid &g, const CellConst *cc,
                          int32_t n_cells, int32_t k_first, int32_t n_band, int32_t tile_points,
                          int2 *ranges, hipStream_t st);
 
-hipError_t launch_scale(const DevLines &L, const DevGrid &g, const CellConst *cc,
-                        const CellSpecies *cs, int32_t n_cells, int32_t n_species,
-                        int32_t *emax, int32_t *escale, hipStream_t st);
+hipError_t launch_scale(const DevLines &L, int64_t i0, int64_t i1, const DevGrid &g,
+                        const CellConst *cc, const CellSpecies *cs, int32_t n_cells,
+                        int32_t n_species, int32_t *emax, int32_t *escale, hipStream_t st);
 
 hipError_t launch_accum_f32(const DevLines &L, const DevGrid &g, const CellConst *cc,
                             const CellSpecies *cs, const int32_t *escale, const int2 *ranges,
@@ -125,6 +144,12 @@ hipError_t launch_wall_sum(const double *I_int, const double *weight, const int6
 hipError_t launch_add(double *acc, const double *x, int32_t n, hipStream_t st);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+
+hipError_t launch_serve(const DevLines &L, const DevGrid &g, const ServeReq *reqs,
+                        const ServeItem *items, int32_t n_items, int32_t *counter,
+                        int32_t n_species, int32_t n_groups, hipStream_t st);
+
+hipError_t launch_serve_combine(const ServeReq &req_host, const DevGrid &g, hipStream_t st);
 
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st);
 

@@ -32,8 +32,8 @@ constexpr double kLog2e = 1.4426950408889634;
 // a1: partition functions and per-cell constants (FP64)
 // ---------------------------------------------------------------------------
 
-__global__ void thermo_kernel(DevSpecies sp, DevCells cells, double M_min, CellConst *cc,
-                              CellSpecies *cs)
+__global__ void thermo_kernel(DevSpecies sp, DevCells cells, double M_min, uint64_t mask,
+                              CellConst *cc, CellSpecies *cs)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int S = cells.n_species;
@@ -63,7 +63,9 @@ __global__ void thermo_kernel(DevSpecies sp, DevCells cells, double M_min, CellC
     }
     const double N = cells.N[(int64_t)c * S + s];
     CellSpecies o;
-    o.lnNQ = (kind != 0 && N > 0.0 && Q > 0.0) ? log(N) - log(Q) : -INFINITY;
+    // species outside a non-zero mask carry no lines (bit s of mask)
+    const bool on = mask == 0 || (s < 64 && ((mask >> s) & 1ull));
+    o.lnNQ = (on && kind != 0 && N > 0.0 && Q > 0.0) ? log(N) - log(Q) : -INFINITY;
     o.dop = 7.16233e-7 / 2.0 * sqrt(Ttr / sp.mass[s]);
     cs[t] = o;
     if (s == 0) {
@@ -197,13 +199,14 @@ __global__ void ranges_kernel(DevLines L, DevGrid g, const CellConst *cc, int32_
 // per-cell power-of-two scale for the single-precision form
 // ---------------------------------------------------------------------------
 
-__global__ void scale_kernel(DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs,
-                             int32_t n_cells, int32_t n_species, int32_t *emax)
+__global__ void scale_kernel(DevLines L, int64_t i0, int64_t i1, DevGrid g, const CellConst *cc,
+                             const CellSpecies *cs, int32_t n_cells, int32_t n_species,
+                             int32_t *emax)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = i0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int c = blockIdx.y; c < n_cells; c += gridDim.y) {
         int ee = INT_MIN, ek = INT_MIN;
-        if (i < L.n) {
+        if (i < i1) {
             PairF64 p;
             if (pair_setup(L, g, cc[c], cs + (int64_t)c * n_species, i, p)) {
                 if (p.se != 0.0) ee = ilogb(p.se) + 1;
@@ -295,25 +298,19 @@ __device__ __forceinline__ double shape_f64(double x, double r)
 // plainly, blocks are merged with Kahan's compensation.
 constexpr int kBlock = 32;
 
-__global__ __launch_bounds__(kAccumThreads) void accum_f32_kernel(
-    DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int32_t *escale,
-    const int2 *ranges, int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles,
-    float *eta, float *kappa)
+// eta and kappa of one cell on one tile (kTilePoints points starting at the
+// global index kt) in single precision: every round stages kStage candidate
+// lines (one FP64 setup per thread) into `rec`, then each wave evaluates the
+// staged lines on its 4 slices of 64 points.  Lanes hold the compensated sums;
+// the function returns eta[j], kappa[j] of point kt + kw + 64 j + lane (scaled
+// by 2^-ese, 2^-esk).  Must be called by the whole workgroup.
+__device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines &L, const DevGrid &g,
+                                                    const CellConst &k, const CellSpecies *csc,
+                                                    int ese, int esk, int2 rg, int32_t kt,
+                                                    int32_t kw, int lane, float (&eta)[kPPL],
+                                                    float (&kap)[kPPL])
 {
-    __shared__ RecF32 rec[kStage];
-    const int tile = (int)(blockIdx.x % n_tiles), c = (int)(blockIdx.x / n_tiles);
-    // the wave index is uniform across the wave: keep it (and every bound
-    // derived from it) in scalar registers so slice tests are scalar branches
-    const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
-    const int32_t kt = k_first + tile * kTilePoints;   // first (global) point of the tile
-    const int32_t kw = wave * 64 * kPPL;               // first point of the wave, tile-relative
     const int32_t kw_last = kw + 64 * kPPL - 1;
-    const int32_t kend = k_first + n_band;             // exclusive, global
-    const CellConst k = cc[c];
-    const CellSpecies *csc = cs + (int64_t)c * n_species;
-    const int ese = escale[2 * c + 0], esk = escale[2 * c + 1];
-    const int2 rg = ranges[(int64_t)c * n_tiles + tile];
-
     float se[kPPL], ce[kPPL], sk[kPPL], ck[kPPL], ae[kPPL], ak[kPPL];
 #pragma unroll
     for (int j = 0; j < kPPL; ++j) se[j] = ce[j] = sk[j] = ck[j] = ae[j] = ak[j] = 0.0f;
@@ -387,11 +384,34 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f32_kernel(
     }
 #pragma unroll
     for (int j = 0; j < kPPL; ++j) {
+        eta[j] = se[j] - ce[j];
+        kap[j] = sk[j] - ck[j];
+    }
+}
+
+__global__ __launch_bounds__(kAccumThreads) void accum_f32_kernel(
+    DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int32_t *escale,
+    const int2 *ranges, int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles,
+    float *eta, float *kappa)
+{
+    __shared__ RecF32 rec[kStage];
+    const int tile = (int)(blockIdx.x % n_tiles), c = (int)(blockIdx.x / n_tiles);
+    // the wave index is uniform across the wave: keep it (and every bound
+    // derived from it) in scalar registers so slice tests are scalar branches
+    const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
+    const int32_t kt = k_first + tile * kTilePoints;   // first (global) point of the tile
+    const int32_t kw = wave * 64 * kPPL;               // first point of the wave, tile-relative
+    const int32_t kend = k_first + n_band;             // exclusive, global
+    float e[kPPL], kp[kPPL];
+    accum_cell_tile_f32(rec, L, g, cc[c], cs + (int64_t)c * n_species, escale[2 * c + 0],
+                        escale[2 * c + 1], ranges[(int64_t)c * n_tiles + tile], kt, kw, lane, e, kp);
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
         const int32_t kk = kt + kw + 64 * j + lane;
         if (kk < kend) {
             const int64_t o = (int64_t)c * n_band + (kk - k_first);
-            eta[o] = se[j] - ce[j];
-            kappa[o] = sk[j] - ck[j];
+            eta[o] = e[j];
+            kappa[o] = kp[j];
         }
     }
 }
@@ -515,6 +535,20 @@ __device__ __forceinline__ float fexp_f32(float t, float e)
     return fabsf(t) < 0.1f ? poly : direct;
 }
 
+// One cell-constant segment on scaled single-precision coefficients:
+// tau = kappa ds; returns e^-tau (as the attenuation factor) and the emitted
+// term eta ds F(tau) in double precision.  dsk = ds 2^esk (as float),
+// dse = ds 2^ese.
+__device__ __forceinline__ void segment_f32(float eta_s, float kap_s, float dsk, double dse,
+                                            double &atten, double &emit)
+{
+    const float tau = kap_s * dsk;
+    const float e = __builtin_amdgcn_exp2f(tau * (float)(-kLog2e));
+    const float F = fexp_f32(tau, e);
+    atten = (double)e;
+    emit = (double)(eta_s * F) * dse;
+}
+
 template <bool FP32>
 __global__ __launch_bounds__(kMarchThreads) void march_kernel(
     DevRays rays, DevGrid g, int32_t k_first, int32_t n_band, const void *eta_v,
@@ -556,11 +590,9 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
             }
 #pragma unroll
             for (int j = 0; j < kMarchPPT; ++j) {
-                const float tau = kv[j] * dsk;
-                const float e = __builtin_amdgcn_exp2f(tau * (float)(-kLog2e));
-                const float F = fexp_f32(tau, e);
-                const float src = ev[j] * F;
-                I[j] = fma((double)src, dse, I[j] * (double)e);
+                double at, em;
+                segment_f32(ev[j], kv[j], dsk, dse, at, em);
+                I[j] = fma(I[j], at, em);
             }
         } else {
             const double *eta = (const double *)eta_v;
@@ -637,6 +669,93 @@ __global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, int
     if (t < n) p[t] = v;
 }
 
+// ---------------------------------------------------------------------------
+// a7: serving.  A persistent workgroup pulls (request, tile, chunk) items from
+// an epoch's list through an atomic counter until the list is exhausted; every
+// workgroup exits then.  An item accumulates eta/kappa of each cell of its
+// chunk on its tile (in LDS / registers, never stored) and marches through them
+// at once, producing the chunk's transmittance T and source S per point:
+// I_out = I_in T + S.  The combine kernel then composes the chunks far ->
+// observer in a fixed order.  Nothing depends on what else shares the epoch.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kAccumThreads) void serve_kernel(DevLines L, DevGrid g,
+                                                              const ServeReq *reqs,
+                                                              const ServeItem *items,
+                                                              int32_t n_items, int32_t *counter,
+                                                              int32_t n_species)
+{
+    __shared__ RecF32 rec[kStage];
+    __shared__ int32_t s_item;
+    const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
+    const int32_t kw = wave * 64 * kPPL;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t it = s_item;
+        __syncthreads();   // every thread has read s_item before it is overwritten
+        if (it >= n_items) break;
+        const ServeItem w = items[it];
+        const ServeReq R = reqs[w.req];
+        const int32_t kt = R.k_first + w.tile * kTilePoints;
+        const int32_t c0 = w.chunk * R.chunk_cells;
+        const int32_t c1 = min(R.n_cells, c0 + R.chunk_cells);
+        double T[kPPL], S[kPPL];
+#pragma unroll
+        for (int j = 0; j < kPPL; ++j) {
+            T[j] = 1.0;
+            S[j] = 0.0;
+        }
+        for (int32_t c = c0; c < c1; ++c) {
+            float e[kPPL], kp[kPPL];
+            const int ese = R.escale[2 * c + 0], esk = R.escale[2 * c + 1];
+            accum_cell_tile_f32(rec, L, g, R.cc[c], R.cs + (int64_t)c * n_species, ese, esk,
+                                R.ranges[(int64_t)c * R.n_tiles + w.tile], kt, kw, lane, e, kp);
+            const double ds = R.ds[c];
+            const double dse = ldexp(ds, ese);
+            const float dsk = (float)fmin(ldexp(ds, esk), 3.0e38);
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                double at, em;
+                segment_f32(e[j], kp[j], dsk, dse, at, em);
+                T[j] *= at;
+                S[j] = fma(S[j], at, em);
+            }
+        }
+        double *ts = R.TS + ((int64_t)w.tile * R.n_chunks + w.chunk) * 2 * kTilePoints;
+#pragma unroll
+        for (int j = 0; j < kPPL; ++j) {
+            const int32_t loc = kw + 64 * j + lane;
+            ts[loc] = T[j];
+            ts[kTilePoints + loc] = S[j];
+        }
+    }
+}
+
+// Compose the chunks of every window point far -> observer, write I and the
+// window's trapezoid partials (h/2 at both window ends).
+__global__ __launch_bounds__(256) void serve_combine_kernel(ServeReq R, DevGrid g)
+{
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    double part = 0.0;
+    if (t < R.n_window) {
+        const int32_t tile = t / kTilePoints, loc = t % kTilePoints;
+        double I = 0.0;
+        for (int32_t m = 0; m < R.n_chunks; ++m) {
+            const double *ts = R.TS + ((int64_t)tile * R.n_chunks + m) * 2 * kTilePoints;
+            I = fma(I, ts[loc], ts[kTilePoints + loc]);
+        }
+        R.I_out[t] = I;
+        const double w = (t == 0 || t == R.n_window - 1) ? 0.5 * g.h : g.h;
+        part = w * I;
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    __shared__ double wsum[4];
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) R.partials[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+}
+
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -645,13 +764,13 @@ inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t
 // launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_thermo(const DevSpecies &sp, const DevCells &cells, double M_min, CellConst *cc,
-                         CellSpecies *cs, hipStream_t st)
+hipError_t launch_thermo(const DevSpecies &sp, const DevCells &cells, double M_min,
+                         uint64_t species_mask, CellConst *cc, CellSpecies *cs, hipStream_t st)
 {
     const int64_t n = (int64_t)cells.n_cells * cells.n_species;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(thermo_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, st, sp, cells, M_min,
-                       cc, cs);
+                       species_mask, cc, cs);
     return hipGetLastError();
 }
 
@@ -666,14 +785,15 @@ hipError_t launch_ranges(const DevLines &L, const DevGrid &g, const CellConst *c
     return hipGetLastError();
 }
 
-hipError_t launch_scale(const DevLines &L, const DevGrid &g, const CellConst *cc,
-                        const CellSpecies *cs, int32_t n_cells, int32_t n_species, int32_t *emax,
-                        int32_t *escale, hipStream_t st)
+hipError_t launch_scale(const DevLines &L, int64_t i0, int64_t i1, const DevGrid &g,
+                        const CellConst *cc, const CellSpecies *cs, int32_t n_cells,
+                        int32_t n_species, int32_t *emax, int32_t *escale, hipStream_t st)
 {
-    // emax must hold INT_MIN on entry (set by a fill kernel of the caller)
-    if (L.n > 0) {
-        hipLaunchKernelGGL(scale_kernel, dim3(blocks_for(L.n, 256), min(n_cells, 65535)),
-                           dim3(256), 0, st, L, g, cc, cs, n_cells, n_species, emax);
+    // emax must hold INT_MIN on entry (set by a fill kernel of the caller);
+    // lines i0 <= i < i1 are scanned
+    if (i1 > i0) {
+        hipLaunchKernelGGL(scale_kernel, dim3(blocks_for(i1 - i0, 256), min(n_cells, 65535)),
+                           dim3(256), 0, st, L, i0, i1, g, cc, cs, n_cells, n_species, emax);
     }
     hipLaunchKernelGGL(scale_finish_kernel, dim3(blocks_for(2 * n_cells, 256)), dim3(256), 0, st,
                        emax, 2 * n_cells, escale);
@@ -765,6 +885,28 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, v, n);
     return hipGetLastError();
+}
+
+
+hipError_t launch_serve(const DevLines &L, const DevGrid &g, const ServeReq *reqs,
+                        const ServeItem *items, int32_t n_items, int32_t *counter,
+                        int32_t n_species, int32_t n_groups, hipStream_t st)
+{
+    // counter must hold 0 on entry; every workgroup leaves once it draws an
+    // index >= n_items
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(serve_kernel, dim3((unsigned)max(1, min(n_groups, n_items))),
+                       dim3(kAccumThreads), 0, st, L, g, reqs, items, n_items, counter, n_species);
+    return hipGetLastError();
+}
+
+hipError_t launch_serve_combine(const ServeReq &R, const DevGrid &g, hipStream_t st)
+{
+    const unsigned nb = blocks_for(R.n_window, 256);
+    hipLaunchKernelGGL(serve_combine_kernel, dim3(nb), dim3(256), 0, st, R, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce_rows(R.partials, 1, (int32_t)nb, R.I_int, st);
 }
 
 }  // namespace lrt

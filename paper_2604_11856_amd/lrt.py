@@ -32,7 +32,8 @@ EXPORTS = ["lrt_version", "lrt_status_string", "lrt_create", "lrt_destroy", "lrt
            "lrt_set_species", "lrt_set_lines", "lrt_set_grid", "lrt_set_cells",
            "lrt_set_rays_slab", "lrt_set_rays_axi", "lrt_trace_axi_ray", "lrt_get_sizes", "lrt_get_ray",
            "lrt_coeffs", "lrt_march", "lrt_solve", "lrt_count_terms", "lrt_profile",
-           "lrt_profile_read"]
+           "lrt_profile_read", "lrt_server_start", "lrt_submit", "lrt_poll", "lrt_wait",
+           "lrt_cancel", "lrt_server_info", "lrt_server_stop"]
 
 KERNELS = {"thermo": 0, "scale": 1, "ranges": 2, "accum": 3, "march": 4}
 
@@ -58,6 +59,17 @@ class _Lines(C.Structure):
 class _Cells(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_species", C.c_int), ("T_tr", _dp), ("T_v", _dp),
                 ("N", _dp), ("n_e", _dp)]
+
+
+class _LosRequest(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_species", C.c_int), ("T_tr", _dp), ("T_v", _dp),
+                ("N", _dp), ("n_e", _dp), ("ds", _dp), ("k_first", C.c_int64),
+                ("n_window", C.c_int64), ("species_mask", C.c_uint64), ("keep_spectrum", C.c_int)]
+
+
+class _LosResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("I_int", C.c_double), ("n_window", C.c_int64),
+                ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
 
 
 _lib = None
@@ -95,6 +107,13 @@ def lib():
             "lrt_count_terms": (st, [_vp, C.c_int64, _i64p, _i64p, _vp]),
             "lrt_profile": (st, [_vp, C.c_int]),
             "lrt_profile_read": (st, [_vp, C.c_int, _dp, _i64p]),
+            "lrt_server_start": (st, [_vp, C.c_size_t, C.c_int, C.POINTER(_vp)]),
+            "lrt_submit": (st, [_vp, C.POINTER(_LosRequest), C.POINTER(C.c_uint64)]),
+            "lrt_poll": (st, [_vp, C.c_uint64, C.POINTER(_LosResult), _dp]),
+            "lrt_wait": (st, [_vp, C.c_uint64, C.c_double, C.POINTER(_LosResult), _dp]),
+            "lrt_cancel": (st, [_vp, C.c_uint64]),
+            "lrt_server_info": (st, [_vp, _i64p, _i64p, _i64p, _i64p, C.POINTER(C.c_size_t)]),
+            "lrt_server_stop": (st, [_vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -268,6 +287,87 @@ class Context:
         esc = torch.zeros((nc, 2), dtype=torch.int32, device=device)
         self.coeffs(band, precision, eta, kap, esc if precision == LRT_FP32_COMP else None)
         return eta, kap, esc
+
+
+LRT_E_NOT_READY = 5
+
+
+class Server:
+    """Serving loop on a context whose species, lines and grid are set."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_slots: int = 64):
+        self._L = lib()
+        self.ctx = ctx
+        h = _vp()
+        s = self._L.lrt_server_start(ctx.h, int(budget_bytes), int(max_slots), C.byref(h))
+        if s != 0:
+            raise LrtError(s, self._L.lrt_last_error(ctx.h).decode())
+        self.h = h
+        self._windows = {}
+
+    def _err(self, s):
+        raise LrtError(s, self._L.lrt_last_error(None).decode())
+
+    def submit(self, req, keep_spectrum: bool = False) -> int:
+        """req: synth.LosRequest.  Returns the ticket."""
+        c = req.cells
+        a = [np.ascontiguousarray(x, np.float64) for x in (c.T_tr, c.T_v, c.N, c.n_e, req.ds)]
+        q = _LosRequest(a[0].shape[0], a[2].shape[1], _p(a[0]), _p(a[1]), _p(a[2]), _p(a[3]),
+                        _p(a[4]), int(req.k_first), int(req.n_window), int(req.species_mask),
+                        1 if keep_spectrum else 0)
+        t = C.c_uint64()
+        s = self._L.lrt_submit(self.h, C.byref(q), C.byref(t))
+        if s != 0:
+            self._err(s)
+        self._windows[t.value] = int(req.n_window) if keep_spectrum else 0
+        return t.value
+
+    def _result(self, fn, ticket, *extra):
+        n = self._windows.get(ticket, 0)
+        spec = np.zeros(n) if n else None
+        r = _LosResult()
+        s = fn(self.h, C.c_uint64(ticket), *extra, C.byref(r), _p(spec) if spec is not None else None)
+        if s == LRT_E_NOT_READY:
+            return None
+        if s != 0:
+            self._err(s)
+        self._windows.pop(ticket, None)
+        return {"status": r.status, "I_int": r.I_int, "n_window": r.n_window,
+                "queue_ms": r.queue_ms, "latency_ms": r.latency_ms, "spectrum": spec}
+
+    def poll(self, ticket: int):
+        """None while running, else the result dict."""
+        return self._result(self._L.lrt_poll, ticket)
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0):
+        return self._result(self._L.lrt_wait, ticket, C.c_double(timeout_ms))
+
+    def cancel(self, ticket: int):
+        s = self._L.lrt_cancel(self.h, C.c_uint64(ticket))
+        if s != 0:
+            self._err(s)
+
+    def info(self):
+        v = [C.c_int64() for _ in range(4)]
+        b = C.c_size_t()
+        s = self._L.lrt_server_info(self.h, *[C.byref(x) for x in v], C.byref(b))
+        if s != 0:
+            self._err(s)
+        return {"pending": v[0].value, "admitted": v[1].value, "completed": v[2].value,
+                "epochs": v[3].value, "bytes_in_use": b.value}
+
+    def stop(self):
+        if getattr(self, "h", None):
+            s = self._L.lrt_server_stop(self.h)
+            self.h = None
+            if s != 0:
+                self._err(s)
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
 
 
 def trace_axi_ray(nx, nr, Lx, R, rw, mu, phi):
