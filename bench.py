@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--workload", default="stagnation", choices=["stagnation", "slab", "axi"])
     ap.add_argument("--cpu-points", type=int, default=512, help="grid points of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=48,
+                    help="requests per serving phase (closed loop, then open loop); 0 skips")
     return ap.parse_args()
 
 
@@ -64,6 +66,53 @@ def workload(name):
         desc = ("axisymmetric: 256x128 cells, 11 species, 1M lines, 2^20-point grid in 16 bands, "
                 "64 wall points x (16 GL x 16 azimuth) rays")
     return wl, desc
+
+
+def serving(n_closed, n_open, budget_gb=64, slots=64):
+    """Serving stream on the resident 1M-line list and 2^20-point grid:
+    closed-loop saturation (all requests at t = 0), then Poisson arrivals at
+    half that rate; latency = submit -> result on the host."""
+    from paper_2604_11856_amd import lrt, synth
+    wl = synth.config_axi()
+    ctx = lrt.Context(0)
+    ctx.set_species(wl.species)
+    ctx.set_lines(wl.lines)
+    ctx.set_grid(wl.grid)
+    srv = lrt.Server(ctx, budget_gb << 30, slots)
+    # warm the kernels with one small request
+    srv.wait(srv.submit(synth.serving_requests(1, wl.grid.n_points, max_cells=32, max_win=20000,
+                                               seed=1)[0]))
+    reqs = synth.serving_requests(n_closed, wl.grid.n_points, seed=11859)
+    t0 = time.perf_counter()
+    res = [srv.wait(t) for t in [srv.submit(r) for r in reqs]]
+    t_closed = time.perf_counter() - t0
+    x_sat = n_closed / t_closed
+    rate = 0.5 * x_sat
+    reqs = synth.serving_requests(n_open, wl.grid.n_points, rate_hz=rate, seed=11861)
+    t0 = time.perf_counter()
+    tickets = []
+    for r in reqs:
+        dt = t0 + r.arrival - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(r))
+    res = [srv.wait(t) for t in tickets]
+    t_open = time.perf_counter() - t0
+    ok = all(x["status"] == 0 for x in res)
+    lat = np.array([x["latency_ms"] for x in res])
+    info = srv.info()
+    srv.stop()
+    ctx.close()
+    return {"resident": "1M lines (250k atomic + 750k rovibronic), 2^20-point grid 1000-100000 cm^-1",
+            "requests": "cells logU[16, 2048], window logU[1e4, 1e6] points, mixed species subsets",
+            "budget_GB": budget_gb, "slots": slots, "all_ok": ok,
+            "closed_loop": {"requests": n_closed, "seconds": t_closed, "solves_per_s": x_sat},
+            "open_loop": {"requests": n_open, "rate_hz": rate, "seconds": t_open,
+                          "solves_per_s": n_open / t_open,
+                          "p50_latency_ms": float(np.percentile(lat, 50)),
+                          "p99_latency_ms": float(np.percentile(lat, 99)),
+                          "max_latency_ms": float(lat.max())},
+            "epochs": info["epochs"]}
 
 
 def cpu_baseline(wl, n_points):
@@ -166,9 +215,17 @@ def main():
                            "bytes_per_launch": march_bytes},
         "p50_latency_ms": None, "p99_latency_ms": None,
     }
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    if args.serving_requests > 0:
+        sv = serving(args.serving_requests, args.serving_requests)
+        line["serving"] = sv
+        line["p50_latency_ms"] = sv["open_loop"]["p50_latency_ms"]
+        line["p99_latency_ms"] = sv["open_loop"]["p99_latency_ms"]
+        line["serving_solves_per_s"] = sv["open_loop"]["solves_per_s"]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_points)
-    ctx.close()
     print(json.dumps(line), flush=True)
 
 

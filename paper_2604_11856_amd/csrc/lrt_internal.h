@@ -16,9 +16,23 @@ constexpr double kC2 = kPlanck * kLight / kBoltz;  // second radiation constant,
 constexpr double kPi = 3.14159265358979323846;
 
 // Accumulation tile: 4 waves of 64 lanes, each lane owns kPPL grid points,
-// one workgroup owns 256 * kPPL consecutive points of one cell.
+// one workgroup owns 256 * kPPL consecutive points of one cell.  The
+// accumulation kernels are compiled for LRT_ACCUM_WAVES waves per SIMD
+// (register budget 512 / waves per lane).  Measured on the 400-cell, 2.2M-line
+// stagnation case: 2 points per lane at 8 waves per SIMD beats 4 points at 4
+// waves by 22% (1385 ms vs 1785 ms per launch) although the staging code then
+// spills a few registers around each round.
+#ifndef LRT_ACCUM_PPL
+#define LRT_ACCUM_PPL 2
+#endif
+#ifndef LRT_ACCUM_WAVES
+#define LRT_ACCUM_WAVES 8
+#endif
+#ifndef LRT_SERVE_WAVES
+#define LRT_SERVE_WAVES 8
+#endif
 constexpr int kAccumThreads = 256;
-constexpr int kPPL = 4;
+constexpr int kPPL = LRT_ACCUM_PPL;
 constexpr int kTilePoints = kAccumThreads * kPPL;
 // Line records staged in LDS per round.
 constexpr int kStage = 256;

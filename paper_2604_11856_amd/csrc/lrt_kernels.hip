@@ -389,7 +389,8 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
     }
 }
 
-__global__ __launch_bounds__(kAccumThreads) void accum_f32_kernel(
+__global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(LRT_ACCUM_WAVES)))
+void accum_f32_kernel(
     DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int32_t *escale,
     const int2 *ranges, int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles,
     float *eta, float *kappa)
@@ -679,7 +680,8 @@ __global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, int
 // observer in a fixed order.  Nothing depends on what else shares the epoch.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kAccumThreads) void serve_kernel(DevLines L, DevGrid g,
+__global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(LRT_SERVE_WAVES)))
+void serve_kernel(DevLines L, DevGrid g,
                                                               const ServeReq *reqs,
                                                               const ServeItem *items,
                                                               int32_t n_items, int32_t *counter,
