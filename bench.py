@@ -68,6 +68,29 @@ def workload(name):
     return wl, desc
 
 
+def counter_traffic(workload_name):
+    """HBM bytes per accumulation launch from the committed counter summary, if
+    it was taken on the stagnation workload with the current kernel sources;
+    otherwise None."""
+    import hashlib
+    if workload_name != "stagnation":
+        return None
+    path = os.path.join(ROOT, "profiles", "accum_f32_stagnation_pmc.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for ln in open(path):
+        if ":" in ln:
+            k, v = ln.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("lrt_kernels.hip", "lrt_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2604_11856_amd", "csrc", f), "rb").read())
+    if fields.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def serving(n_closed, n_open, budget_gb=64, slots=64):
     """Serving stream on the resident 1M-line list and 2^20-point grid:
     closed-loop saturation (all requests at t = 0), then Poisson arrivals at
@@ -204,7 +227,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "accum_f32",
                      "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "T lane-op/s (FP32 VALU issue slots, transcendental = 2)",
-                     "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "frac": achieved / PEAK_LANE_OPS, "traffic": counter_traffic(args.workload),
                      "evals_per_launch": terms_per_launch,
                      "core_fraction": n_core / max(1, n_terms),
                      "slots_per_eval": slots_per_launch / max(1.0, terms_per_launch),

@@ -276,6 +276,49 @@ __device__ __forceinline__ float shape_exp_f32(const RecF32 &q, float u, float p
 
 __device__ __forceinline__ int32_t uniform_i(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Block -> (tile, cell) order of the accumulation grid.
+//   0: tile fastest (consecutive workgroups sweep one cell's spectrum)
+//   1: workgroups are dispatched round-robin over the 8 XCDs (workgroup b on
+//      XCD b % 8, each with its own L2); XCD x walks a contiguous block of the
+//      tile-major, cell-minor order
+//   2: tile-major, cell-minor, no XCD remap
+//   3: groups of 8 tiles x all cells; within a group XCD x takes tile 8g + x
+//      for every cell, so the cells of one tile share their candidate lines in
+//      one L2 while tiles stay interleaved across XCDs
+#ifndef LRT_BLOCK_MAP
+#define LRT_BLOCK_MAP 3
+#endif
+constexpr int kXCDs = 8;
+__device__ __forceinline__ void block_tile_cell(uint32_t b, uint32_t n_blocks, int32_t n_cells,
+                                                int32_t n_tiles, int &tile, int &cell)
+{
+#if LRT_BLOCK_MAP == 0
+    tile = (int)(b % (uint32_t)n_tiles);
+    cell = (int)(b / (uint32_t)n_tiles);
+#elif LRT_BLOCK_MAP == 1
+    const uint32_t per = n_blocks / kXCDs, rem = n_blocks % kXCDs;
+    const uint32_t x = b % kXCDs, i = b / kXCDs;
+    const uint32_t logical = x * per + min(x, rem) + i;
+    tile = (int)(logical / (uint32_t)n_cells);
+    cell = (int)(logical % (uint32_t)n_cells);
+#elif LRT_BLOCK_MAP == 2
+    tile = (int)(b / (uint32_t)n_cells);
+    cell = (int)(b % (uint32_t)n_cells);
+#else
+    const uint32_t gsz = (uint32_t)kXCDs * (uint32_t)n_cells;
+    const uint32_t g = b / gsz, r = b % gsz;
+    const uint32_t full = (uint32_t)n_tiles / kXCDs;
+    if (g < full) {
+        tile = (int)(g * kXCDs + r % kXCDs);
+        cell = (int)(r / kXCDs);
+    } else {   // last partial group of tiles
+        tile = (int)(g * kXCDs + r / (uint32_t)n_cells);
+        cell = (int)(r % (uint32_t)n_cells);
+    }
+#endif
+    (void)n_blocks;
+}
+
 // Compensated (Kahan) addition of a block partial v into (s, c).
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v)
 {
@@ -392,11 +435,12 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
 __global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(LRT_ACCUM_WAVES)))
 void accum_f32_kernel(
     DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int32_t *escale,
-    const int2 *ranges, int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles,
-    float *eta, float *kappa)
+    const int2 *ranges, int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band,
+    int32_t n_tiles, float *eta, float *kappa)
 {
     __shared__ RecF32 rec[kStage];
-    const int tile = (int)(blockIdx.x % n_tiles), c = (int)(blockIdx.x / n_tiles);
+    int tile, c;
+    block_tile_cell(blockIdx.x, gridDim.x, n_cells, n_tiles, tile, c);
     // the wave index is uniform across the wave: keep it (and every bound
     // derived from it) in scalar registers so slice tests are scalar branches
     const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
@@ -419,11 +463,12 @@ void accum_f32_kernel(
 
 __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
     DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int2 *ranges,
-    int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles, double *eta,
-    double *kappa)
+    int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles,
+    double *eta, double *kappa)
 {
     __shared__ RecF64 rec[kStage];
-    const int tile = (int)(blockIdx.x % n_tiles), c = (int)(blockIdx.x / n_tiles);
+    int tile, c;
+    block_tile_cell(blockIdx.x, gridDim.x, n_cells, n_tiles, tile, c);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t kt = k_first + tile * kTilePoints;
     const int32_t kw = kt + wave * 64 * kPPL;
@@ -808,8 +853,9 @@ hipError_t launch_accum_f32(const DevLines &L, const DevGrid &g, const CellConst
                             float *eta, float *kappa, hipStream_t st)
 {
     const int32_t n_tiles = (n_band + kTilePoints - 1) / kTilePoints;
-    hipLaunchKernelGGL(accum_f32_kernel, dim3((unsigned)((int64_t)n_tiles * n_cells)), dim3(kAccumThreads), 0, st, L, g,
-                       cc, cs, escale, ranges, n_species, k_first, n_band, n_tiles, eta, kappa);
+    hipLaunchKernelGGL(accum_f32_kernel, dim3((unsigned)((int64_t)n_tiles * n_cells)),
+                       dim3(kAccumThreads), 0, st, L, g, cc, cs, escale, ranges, n_cells, n_species,
+                       k_first, n_band, n_tiles, eta, kappa);
     return hipGetLastError();
 }
 
@@ -819,8 +865,9 @@ hipError_t launch_accum_f64(const DevLines &L, const DevGrid &g, const CellConst
                             double *kappa, hipStream_t st)
 {
     const int32_t n_tiles = (n_band + kTilePoints - 1) / kTilePoints;
-    hipLaunchKernelGGL(accum_f64_kernel, dim3((unsigned)((int64_t)n_tiles * n_cells)), dim3(kAccumThreads), 0, st, L, g,
-                       cc, cs, ranges, n_species, k_first, n_band, n_tiles, eta, kappa);
+    hipLaunchKernelGGL(accum_f64_kernel, dim3((unsigned)((int64_t)n_tiles * n_cells)),
+                       dim3(kAccumThreads), 0, st, L, g, cc, cs, ranges, n_cells, n_species, k_first,
+                       n_band, n_tiles, eta, kappa);
     return hipGetLastError();
 }
 
