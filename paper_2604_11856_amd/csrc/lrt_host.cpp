@@ -840,10 +840,15 @@ lrt_status lrt_count_terms(lrt_ctx *c, int64_t band, int64_t *count, int64_t *co
     if ((r = prepare(c, st, false))) return r;
     int32_t k_first, n_band;
     if ((r = band_range(c, band, k_first, n_band))) return r;
-    if ((r = ensure(c, c->w_count, 16))) return r;
+    if ((r = ensure(c, c->w_count, 16)) || (r = ensure(c, c->w_ranges, (size_t)c->n_cells * sizeof(int2))))
+        return r;
     LRT_HIP(c, launch_fill_u64(c->w_count.as<unsigned long long>(), 0ull, 2, st));
     const DevGrid g{c->nu_min, c->h, (int32_t)c->n_points};
-    LRT_HIP(c, launch_count(dev_lines(c), g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
+    const DevLines L = dev_lines(c);
+    // candidate lines of each cell for the whole band (one tile spanning it)
+    LRT_HIP(c, launch_ranges(L, g, c->d_cc.as<CellConst>(), (int32_t)c->n_cells, k_first, n_band, n_band,
+                             c->w_ranges.as<int2>(), st));
+    LRT_HIP(c, launch_count(L, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(), c->w_ranges.as<int2>(),
                             (int32_t)c->n_cells, c->n_species, k_first, n_band,
                             c->w_count.as<unsigned long long>(), st));
     unsigned long long v[2] = {0, 0};

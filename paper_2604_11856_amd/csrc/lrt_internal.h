@@ -140,9 +140,9 @@ hipError_t launch_accum_f64(const DevLines &L, const DevGrid &g, const CellConst
                             double *kappa, hipStream_t st);
 
 hipError_t launch_count(const DevLines &L, const DevGrid &g, const CellConst *cc,
-                        const CellSpecies *cs, int32_t n_cells, int32_t n_species,
-                        int32_t k_first, int32_t n_band, unsigned long long *count,
-                        hipStream_t st);
+                        const CellSpecies *cs, const int2 *band_ranges, int32_t n_cells,
+                        int32_t n_species, int32_t k_first, int32_t n_band,
+                        unsigned long long *count, hipStream_t st);
 
 hipError_t launch_march(bool fp32, const DevRays &rays, const DevGrid &g, int32_t k_first,
                         int32_t n_band, const void *eta, const void *kappa,

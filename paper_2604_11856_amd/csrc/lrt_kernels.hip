@@ -541,13 +541,15 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
 // ---------------------------------------------------------------------------
 
 __global__ void count_kernel(DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs,
-                             int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band,
-                             unsigned long long *count)
+                             const int2 *band_ranges, int32_t n_cells, int32_t n_species,
+                             int32_t k_first, int32_t n_band, unsigned long long *count)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // lines i in the cell's candidate range for the band, grid-stride in x
     unsigned long long n = 0, nc = 0;
     for (int c = blockIdx.y; c < n_cells; c += gridDim.y) {
-        if (i < L.n) {
+        const int2 rg = band_ranges[c];
+        for (int64_t i = (int64_t)rg.x + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rg.y;
+             i += (int64_t)gridDim.x * blockDim.x) {
             PairF64 p;
             if (pair_setup(L, g, cc[c], cs + (int64_t)c * n_species, i, p)) {
                 const int32_t a = max(p.klo, k_first), b = min(p.khi, k_first + n_band - 1);
@@ -872,12 +874,13 @@ hipError_t launch_accum_f64(const DevLines &L, const DevGrid &g, const CellConst
 }
 
 hipError_t launch_count(const DevLines &L, const DevGrid &g, const CellConst *cc,
-                        const CellSpecies *cs, int32_t n_cells, int32_t n_species, int32_t k_first,
-                        int32_t n_band, unsigned long long *count, hipStream_t st)
+                        const CellSpecies *cs, const int2 *band_ranges, int32_t n_cells,
+                        int32_t n_species, int32_t k_first, int32_t n_band,
+                        unsigned long long *count, hipStream_t st)
 {
     if (L.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(count_kernel, dim3(blocks_for(L.n, 256), min(n_cells, 65535)), dim3(256),
-                       0, st, L, g, cc, cs, n_cells, n_species, k_first, n_band, count);
+    hipLaunchKernelGGL(count_kernel, dim3(64, min(n_cells, 65535)), dim3(256), 0, st, L, g, cc, cs,
+                       band_ranges, n_cells, n_species, k_first, n_band, count);
     return hipGetLastError();
 }
 
