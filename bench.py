@@ -24,17 +24,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Voigt line-pt evals/s + q_rad solves/s (FP32-comp vs FP64, 1 GPU); p99 latency"
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz -> non-packed FP32 VALU lane-op issue rate
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz -> non-packed FP32 VALU lane-op
+# issue rate (one wave64 instruction per SIMD every 4 cycles).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# Issue slots of one profile evaluation in its minimal form.  On gfx950 the
-# transcendentals (v_exp/v_log/v_rcp_f32) issue at half the FMA rate, so each
-# costs 2 slots.  Core point (|dnu| <= 25 HWHM): 16 VALU ops (offset, |x|,
-# x^2, 3 exponent scalings, 2 denominators, 3 for the rational pair over one
-# reciprocal, 2 combines, 2 accumulating FMAs) + 5 transcendentals (3 exp2,
-# 1 log2, 1 rcp) = 26 slots.  Wing point: the two exponentials are exactly
-# zero in single precision: 12 VALU ops + 3 transcendentals = 18 slots.
-SLOTS_CORE = 16 + 5 * 2
-SLOTS_WING = 12 + 3 * 2
+# Issue slots of one profile evaluation in the form the kernel evaluates, one
+# slot per VALU instruction, transcendentals included (v_exp/v_log/v_rcp issue
+# in one slot; the transcendental unit behind them runs at half rate, which
+# instruction counters show overlapping with other VALU issue rather than
+# adding a second slot).  In y = (nu - nu0)/gamma_V:
+#   wing point (|dnu| > 25 HWHM, both exponentials exactly zero in single
+#   precision): offset 2 (sub, fma), 1 + y^2 1, |y|^2.25 3 (log, scale, exp),
+#   1 + 0.1 x^2.25 1, reciprocal of the product 2, numerator 2, product 1,
+#   two accumulating FMAs 2 = 14;
+#   core point: + exponent and exp for each of the two exponentials (4) and
+#   their two FMAs = 20.
+SLOTS_CORE = 20
+SLOTS_WING = 14
 HBM_PEAK = 8.0e12
 
 
@@ -226,7 +231,7 @@ def main():
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()},
         "roofline": {"bound": "alu", "kernel": "accum_f32",
                      "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "T lane-op/s (FP32 VALU issue slots, transcendental = 2)",
+                     "unit": "T lane-op/s (FP32 VALU issue slots, one per instruction)",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": counter_traffic(args.workload),
                      "evals_per_launch": terms_per_launch,
                      "core_fraction": n_core / max(1, n_terms),

@@ -241,36 +241,73 @@ __global__ void scale_finish_kernel(const int32_t *emax, int32_t n, int32_t *esc
 // Single-precision line record staged in LDS.  Grid indices inside the
 // kernel are relative to the tile start, so every float index is a small
 // exact integer whatever the grid size.
+//
+// `mode` holds, for every 64-point slice of the tile, what evaluating the
+// line there takes, decided once at staging: byte w belongs to wave w, and
+// within it bits 3j, 3j+1, 3j+2 of the wave's slice j say "window reaches the
+// slice", "window edge inside the slice (mask lanes)" and "core window
+// reaches the slice (exponential terms)".  A wave turns the bytes of a block
+// of lines into scalar bit masks and needs no vector work for control flow.
 struct __align__(16) RecF32 {
-    int32_t klo, khi, kclo, kchi;   // window and core window, tile-relative
-    float k0f, hs, fs, r;           // centre index, h/(2 gV), frac0/(2 gV), gL/gV
-    float aG, aW, se, sk;           // 1-r, 0.016 r (1-r), scaled strengths
+    uint32_t mode;
+    float klo, khi;                 // window, tile-relative, clamped to [-1, tile] (edge masks)
+    float k0f;                      // centre index, tile-relative
+    float hg, fg, r, aG;            // h/gV, frac0/gV, gL/gV, 1-r
+    float aW, se, sk, pad;          // 0.016 r (1-r), scaled strengths
 };
+static_assert(kPPL >= 1 && kPPL <= 2, "mode word holds 8 bits per wave: at most 2 slices per lane");
+
+enum : uint32_t { kSliceIn = 1u, kSliceEdge = 2u, kSliceCore = 4u };
+
+// Mode bits of a window [klo, khi] with core window [kclo, kchi] (tile-relative).
+__device__ __forceinline__ uint32_t slice_modes(int32_t klo, int32_t khi, int32_t kclo, int32_t kchi)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int w = 0; w < kAccumThreads / 64; ++w) {
+#pragma unroll
+        for (int j = 0; j < kPPL; ++j) {
+            const int32_t a = (w * kPPL + j) * 64, b = a + 63;
+            if (khi < a || klo > b) continue;
+            uint32_t bits = kSliceIn;
+            if (!(klo <= a && khi >= b)) bits |= kSliceEdge;
+            if (!(kchi < a || kclo > b)) bits |= kSliceCore;
+            m |= bits << (8 * w + 3 * j);
+        }
+    }
+    return m;
+}
 
 struct __align__(16) RecF64 {
     int32_t klo, khi, k0, pad;
     double frac0, inv2g, r, se, sk, pad2;
 };
 
-// Rational part of the Whiting profile at x = |dk h - frac0| / (2 gamma_V):
-// r/(1+4x^2) - 0.016 r(1-r)/(1+0.1 x^2.25) over one reciprocal; also returns
-// x^2 and x^2.25 for the exponential part.
-__device__ __forceinline__ float shape_rational_f32(float kf, const RecF32 &q, float &u, float &p)
+// The Whiting profile is evaluated in y = (nu_k - nu0) / gamma_V = +-2x, so that
+// 1 + 4x^2 = 1 + y^2 is one FMA and x^2.25 = 2^-2.25 |y|^2.25.
+constexpr double kTwoM225 = 0.21022410381342863;   // 2^-2.25
+
+// Rational part r/(1+4x^2) - 0.016 r(1-r)/(1+0.1 x^2.25) over one reciprocal;
+// also returns 1 + y^2 and |y|^2.25 for the exponential part.  (Two
+// reciprocals save two instructions but measured 4 % slower: the
+// transcendental pipe, not the instruction count, then sets the pace.)
+__device__ __forceinline__ float shape_rational_f32(float kf, const RecF32 &q, float &d1, float &p)
 {
-    const float x = fabsf(fmaf(kf - q.k0f, q.hs, -q.fs));
-    u = x * x;
-    p = __builtin_amdgcn_exp2f(2.25f * __builtin_amdgcn_logf(x));
-    const float d1 = fmaf(4.0f, u, 1.0f);
-    const float d2 = fmaf(0.1f, p, 1.0f);
+    const float y = fmaf(kf - q.k0f, q.hg, -q.fg);
+    d1 = fmaf(y, y, 1.0f);
+    p = __builtin_amdgcn_exp2f(2.25f * __builtin_amdgcn_logf(fabsf(y)));
+    const float d2 = fmaf(p, (float)(0.1 * kTwoM225), 1.0f);
     const float num = fmaf(q.r, d2, -(q.aW * d1));
     return num * __builtin_amdgcn_rcpf(d1 * d2);
 }
 
-// Exponential part: (1-r) e^{-2.772 x^2} + 0.016 r(1-r) e^{-0.4 x^2.25} added to P.
-__device__ __forceinline__ float shape_exp_f32(const RecF32 &q, float u, float p, float P)
+// Exponential part (1-r) e^{-2.772 x^2} + 0.016 r(1-r) e^{-0.4 x^2.25} added to
+// P, with x^2 = (d1 - 1)/4 folded into the exponent's FMA.
+__device__ __forceinline__ float shape_exp_f32(const RecF32 &q, float d1, float p, float P)
 {
-    const float gs = __builtin_amdgcn_exp2f(u * (float)(-2.772 * kLog2e));
-    const float e = __builtin_amdgcn_exp2f(p * (float)(-0.4 * kLog2e));
+    constexpr float c1 = (float)(-2.772 / 4.0 * kLog2e);
+    const float gs = __builtin_amdgcn_exp2f(fmaf(d1, c1, -c1));
+    const float e = __builtin_amdgcn_exp2f(p * (float)(-0.4 * kTwoM225 * kLog2e));
     return fmaf(q.aG, gs, fmaf(q.aW, e, P));
 }
 
@@ -344,7 +381,7 @@ constexpr int kBlock = 32;
 // eta and kappa of one cell on one tile (kTilePoints points starting at the
 // global index kt) in single precision: every round stages kStage candidate
 // lines (one FP64 setup per thread) into `rec`, then each wave evaluates the
-// staged lines on its 4 slices of 64 points.  Lanes hold the compensated sums;
+// staged lines on its kPPL slices of 64 points.  Lanes hold the compensated sums;
 // the function returns eta[j], kappa[j] of point kt + kw + 64 j + lane (scaled
 // by 2^-ese, 2^-esk).  Must be called by the whole workgroup.
 __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines &L, const DevGrid &g,
@@ -353,28 +390,36 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
                                                     int32_t kw, int lane, float (&eta)[kPPL],
                                                     float (&kap)[kPPL])
 {
-    const int32_t kw_last = kw + 64 * kPPL - 1;
+    // byte of the mode word that belongs to this wave (kw = wave * 64 * kPPL)
+    const uint32_t wshift = (uint32_t)(kw / (64 * kPPL)) * 8u;
+    float kf[kPPL];
     float se[kPPL], ce[kPPL], sk[kPPL], ck[kPPL], ae[kPPL], ak[kPPL];
 #pragma unroll
-    for (int j = 0; j < kPPL; ++j) se[j] = ce[j] = sk[j] = ck[j] = ae[j] = ak[j] = 0.0f;
+    for (int j = 0; j < kPPL; ++j) {
+        kf[j] = (float)(kw + 64 * j + lane);
+        asm volatile("" : "+v"(kf[j]));   // keep the float index in a register
+        se[j] = ce[j] = sk[j] = ck[j] = ae[j] = ak[j] = 0.0f;
+    }
 
     for (int base = rg.x; base < rg.y; base += kStage) {
         // stage: one (cell, line) setup per thread, in double precision
         const int64_t i = (int64_t)base + threadIdx.x;
         RecF32 rr;
-        rr.klo = rr.kclo = 1;
-        rr.khi = rr.kchi = 0;
-        rr.k0f = rr.hs = rr.fs = rr.r = rr.aG = rr.aW = rr.se = rr.sk = 0.0f;
+        rr.mode = 0;
+        rr.klo = 1.0f;
+        rr.khi = 0.0f;
+        rr.k0f = rr.hg = rr.fg = rr.r = rr.aG = rr.aW = rr.se = rr.sk = rr.pad = 0.0f;
         if (i < rg.y) {
             PairF64 p;
             if (pair_setup(L, g, k, csc, i, p)) {
-                rr.klo = p.klo - kt;
-                rr.khi = p.khi - kt;
-                rr.kclo = p.kclo - kt;
-                rr.kchi = p.kchi - kt;
+                const int32_t lo = p.klo - kt, hi = p.khi - kt;
+                rr.mode = slice_modes(lo, hi, p.kclo - kt, p.kchi - kt);
+                // small exact integers in float: the lanes compare their float index
+                rr.klo = (float)max(lo, -1);
+                rr.khi = (float)min(hi, kTilePoints);
                 rr.k0f = (float)(L.k0[i] - kt);
-                rr.hs = (float)(g.h * p.inv2g);
-                rr.fs = (float)(L.frac0[i] * p.inv2g);
+                rr.hg = (float)(2.0 * g.h * p.inv2g);
+                rr.fg = (float)(2.0 * L.frac0[i] * p.inv2g);
                 rr.r = (float)p.r;
                 rr.aG = (float)(1.0 - p.r);
                 rr.aW = (float)(0.016 * p.r * (1.0 - p.r));
@@ -386,31 +431,41 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
         __syncthreads();
         const int n = min(kStage, rg.y - base);
         for (int l0 = 0; l0 < n; l0 += kBlock) {
-            const int l1 = min(l0 + kBlock, n);
-            for (int l = l0; l < l1; ++l) {
-                const RecF32 q = rec[l];
-                const int32_t klo = uniform_i(q.klo), khi = uniform_i(q.khi);
-                if (khi < kw || klo > kw_last) continue;
-                const int32_t kclo = uniform_i(q.kclo), kchi = uniform_i(q.kchi);
+            // Control of the block's lines on this wave, as bit masks over the
+            // block in scalar registers: lane t < kBlock reads line l0 + t's
+            // mode byte, one ballot per (slice, flag).  The loop then visits
+            // only the lines that reach this wave, in line order.
+            uint32_t mb = 0;
+            if (lane < kBlock && l0 + lane < n) mb = (rec[l0 + lane].mode >> wshift) & 0xffu;
+            uint32_t todo = (uint32_t)__ballot(mb != 0);
+            uint32_t m_in[kPPL], m_edge[kPPL], m_core[kPPL];
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                m_in[j] = (uint32_t)__ballot(mb & (kSliceIn << (3 * j)));
+                m_edge[j] = (uint32_t)__ballot(mb & (kSliceEdge << (3 * j)));
+                m_core[j] = (uint32_t)__ballot(mb & (kSliceCore << (3 * j)));
+            }
+            while (todo) {
+                const int t = __builtin_ctz(todo);
+                todo &= todo - 1;
+                const RecF32 q = rec[l0 + t];
 #pragma unroll
                 for (int j = 0; j < kPPL; ++j) {
-                    const int32_t a = kw + 64 * j, b = a + 63;
-                    if (khi < a || klo > b) continue;          // slice outside the window
-                    const int32_t kk = a + lane;
-                    float u, pw;
-                    float P = shape_rational_f32((float)kk, q, u, pw);
+                    if (!((m_in[j] >> t) & 1u)) continue;      // slice outside the window
+                    float d1, pw;
+                    float P = shape_rational_f32(kf[j], q, d1, pw);
                     // Within 25 HWHM of the centre the exponentials contribute;
                     // beyond it they are exactly zero in single precision.  Both
                     // conditions are wave-uniform; the empty asm keeps them real
                     // scalar branches instead of computing both sides and selecting.
-                    if (!(kchi < a || kclo > b)) {
+                    if ((m_core[j] >> t) & 1u) {
                         asm volatile("");
-                        P = shape_exp_f32(q, u, pw, P);
+                        P = shape_exp_f32(q, d1, pw, P);
                     }
                     // slice crossing a window edge: mask the lanes outside
-                    if (!(klo <= a && khi >= b)) {
+                    if ((m_edge[j] >> t) & 1u) {
                         asm volatile("");
-                        P = (kk >= klo && kk <= khi) ? P : 0.0f;
+                        P = (kf[j] >= q.klo && kf[j] <= q.khi) ? P : 0.0f;
                     }
                     ae[j] = fmaf(P, q.se, ae[j]);
                     ak[j] = fmaf(P, q.sk, ak[j]);
