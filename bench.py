@@ -218,7 +218,7 @@ def main():
         "ms_per_step": dt32 * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": desc, "precision": "fp32 profile evaluation, per-point sums over 32-line "
+        "config": {"workload": desc, "precision": "fp32 profile evaluation, per-point sums over 64-line "
                    "blocks merged with Kahan compensation; populations, widths, windows, march "
                    "state and quadrature in f64",
                    "cells": sz["n_cells"], "lines": wl.lines.n, "grid_points": sz["n_points"],

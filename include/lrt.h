@@ -225,9 +225,10 @@ lrt_status lrt_solve(lrt_ctx *ctx, lrt_precision prec, int64_t first_band, doubl
 
 /* Number of in-window (cell, line, grid point) terms of band `band`, i.e. the
  * Voigt evaluations the accumulation performs usefully, and (core_count, may
- * be NULL) how many of them lie within 25 Voigt HWHM of the line centre, where
- * the profile's two exponential terms are not negligible in single precision.
- * Synchronises. */
+ * be NULL) how many of them the single-precision form evaluates with the
+ * profile's two exponential terms: every point within 25 Voigt HWHM of the
+ * line centre (beyond it both terms are exactly zero in single precision)
+ * plus at most one point of margin on each side.  Synchronises. */
 lrt_status lrt_count_terms(lrt_ctx *ctx, int64_t band, int64_t *count, int64_t *core_count,
                            void *stream);
 

@@ -52,7 +52,7 @@ struct lrt_ctx {
     // lines (sorted by nu0 on the host, resident on the device)
     int64_t n_lines = -1;
     std::vector<double> h_nu0;   // sorted centres, host copy for k0/frac0
-    DBuf d_nu0, d_A, d_Eu_ev, d_Eu_rot, d_El_ev, d_El_rot, d_lngu, d_species, d_k0, d_frac0;
+    DBuf d_nu0, d_seta0, d_skap0, d_Eu_ev, d_Eu_rot, d_El_ev, d_El_rot, d_lngu, d_species, d_k0, d_frac0;
     bool lines_grid_ready = false;
 
     // grid
@@ -111,6 +111,10 @@ lrt_status prepare_lines(lrt_ctx *c);
 // Lines on the grid, per-cell constants (and scales when need_scale).
 lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force = false);
 DevLines dev_lines(const lrt_ctx *c);
+inline DevGrid dev_grid(const lrt_ctx *c)
+{
+    return DevGrid{c->nu_min, c->h, (int32_t)c->n_points, 1.0 / c->h};
+}
 
 }  // namespace lrt
 

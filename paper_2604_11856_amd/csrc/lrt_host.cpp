@@ -378,12 +378,15 @@ lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *L)
     std::vector<int64_t> idx(n);
     std::iota(idx.begin(), idx.end(), 0);
     std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return L->nu0[a] < L->nu0[b]; });
-    std::vector<double> nu0(n), A(n), Eue(n), Eur(n), Ele(n), Elr(n), lngu(n);
+    std::vector<double> nu0(n), seta0(n), skap0(n), Eue(n), Eur(n), Ele(n), Elr(n), lngu(n);
     std::vector<int32_t> spc(n);
     for (int64_t j = 0; j < n; ++j) {
         const int64_t i = idx[j];
         nu0[j] = L->nu0[i];
-        A[j] = L->A[i];
+        // eta_i = (hc/4pi) N_u A nu0 phi (W after the 1e-7);
+        // kappa_i = A (N_l g_u/g_l)(1 - e^{-x}) phi / (8 pi c nu0^2)
+        seta0[j] = (1e-7 * kPlanck * kLight / (4.0 * kPi)) * L->nu0[i] * L->A[i];
+        skap0[j] = L->A[i] / ((8.0 * kPi * kLight) * L->nu0[i] * L->nu0[i]);
         Eue[j] = L->Eu_ev[i];
         Eur[j] = L->Eu_rot[i];
         Ele[j] = L->El_ev[i];
@@ -392,7 +395,8 @@ lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *L)
         spc[j] = L->species[i];
     }
     lrt_status st;
-    if ((st = upload_vec(c, c->d_nu0, nu0)) || (st = upload_vec(c, c->d_A, A)) ||
+    if ((st = upload_vec(c, c->d_nu0, nu0)) || (st = upload_vec(c, c->d_seta0, seta0)) ||
+        (st = upload_vec(c, c->d_skap0, skap0)) ||
         (st = upload_vec(c, c->d_Eu_ev, Eue)) || (st = upload_vec(c, c->d_Eu_rot, Eur)) ||
         (st = upload_vec(c, c->d_El_ev, Ele)) || (st = upload_vec(c, c->d_El_rot, Elr)) ||
         (st = upload_vec(c, c->d_lngu, lngu)) || (st = upload_vec(c, c->d_species, spc)))
@@ -665,11 +669,11 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
         c->thermo_ready = true;
     }
     if (need_scale && !c->scale_ready) {
-        DevLines L{c->n_lines, c->d_nu0.as<double>(), c->d_A.as<double>(), c->d_Eu_ev.as<double>(),
+        DevLines L{c->n_lines, c->d_nu0.as<double>(), c->d_Eu_ev.as<double>(),
                    c->d_Eu_rot.as<double>(), c->d_El_ev.as<double>(), c->d_El_rot.as<double>(),
-                   c->d_lngu.as<double>(), c->d_species.as<int32_t>(), c->d_k0.as<int32_t>(),
-                   c->d_frac0.as<double>()};
-        DevGrid g{c->nu_min, c->h, (int32_t)c->n_points};
+                   c->d_lngu.as<double>(), c->d_seta0.as<double>(), c->d_skap0.as<double>(),
+                   c->d_species.as<int32_t>(), c->d_k0.as<int32_t>(), c->d_frac0.as<double>()};
+        DevGrid g = dev_grid(c);
         LRT_HIP(c, launch_fill_i32(c->d_emax.as<int32_t>(), INT_MIN, 2 * c->n_cells, st));
         LRT_HIP(c, timed(c, LRT_K_SCALE, st, [&] {
                     return launch_scale(L, 0, L.n, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
@@ -683,10 +687,10 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
 
 DevLines dev_lines(const lrt_ctx *c)
 {
-    return DevLines{c->n_lines, c->d_nu0.as<double>(), c->d_A.as<double>(), c->d_Eu_ev.as<double>(),
+    return DevLines{c->n_lines, c->d_nu0.as<double>(), c->d_Eu_ev.as<double>(),
                     c->d_Eu_rot.as<double>(), c->d_El_ev.as<double>(), c->d_El_rot.as<double>(),
-                    c->d_lngu.as<double>(), c->d_species.as<int32_t>(), c->d_k0.as<int32_t>(),
-                    c->d_frac0.as<double>()};
+                    c->d_lngu.as<double>(), c->d_seta0.as<double>(), c->d_skap0.as<double>(),
+                    c->d_species.as<int32_t>(), c->d_k0.as<int32_t>(), c->d_frac0.as<double>()};
 }
 
 lrt_status band_range(lrt_ctx *c, int64_t band, int32_t &k_first, int32_t &n_band)
@@ -710,7 +714,7 @@ lrt_status coeffs_impl(lrt_ctx *c, int64_t band, lrt_precision prec, void *eta, 
     const int32_t n_tiles = (n_band + kTilePoints - 1) / kTilePoints;
     if ((r = ensure(c, c->w_ranges, (size_t)c->n_cells * n_tiles * sizeof(int2)))) return r;
     const DevLines L = dev_lines(c);
-    const DevGrid g{c->nu_min, c->h, (int32_t)c->n_points};
+    const DevGrid g = dev_grid(c);
     const int32_t nc = (int32_t)c->n_cells;
     LRT_HIP(c, timed(c, LRT_K_RANGES, st, [&] {
                 return launch_ranges(L, g, c->d_cc.as<CellConst>(), nc, k_first, n_band, kTilePoints,
@@ -752,7 +756,7 @@ lrt_status march_impl(lrt_ctx *c, int64_t band, lrt_precision prec, const void *
     const int32_t n_chunks = (n_band + kMarchPoints - 1) / kMarchPoints;
     if ((r = ensure(c, c->w_partials, (size_t)c->n_rays * n_chunks * sizeof(double)))) return r;
     const DevRays rays{(int32_t)c->n_rays, c->d_off.as<int64_t>(), c->d_cell.as<int32_t>(), c->d_ds.as<double>()};
-    const DevGrid g{c->nu_min, c->h, (int32_t)c->n_points};
+    const DevGrid g = dev_grid(c);
     LRT_HIP(c, timed(c, LRT_K_MARCH, st, [&] {
                 return launch_march(prec == LRT_FP32_COMP, rays, g, k_first, n_band, eta, kappa, escale,
                                     I_out, c->w_partials.as<double>(), n_chunks, st);
@@ -843,7 +847,7 @@ lrt_status lrt_count_terms(lrt_ctx *c, int64_t band, int64_t *count, int64_t *co
     if ((r = ensure(c, c->w_count, 16)) || (r = ensure(c, c->w_ranges, (size_t)c->n_cells * sizeof(int2))))
         return r;
     LRT_HIP(c, launch_fill_u64(c->w_count.as<unsigned long long>(), 0ull, 2, st));
-    const DevGrid g{c->nu_min, c->h, (int32_t)c->n_points};
+    const DevGrid g = dev_grid(c);
     const DevLines L = dev_lines(c);
     // candidate lines of each cell for the whole band (one tile spanning it)
     LRT_HIP(c, launch_ranges(L, g, c->d_cc.as<CellConst>(), (int32_t)c->n_cells, k_first, n_band, n_band,

@@ -31,11 +31,14 @@ constexpr double kPi = 3.14159265358979323846;
 #ifndef LRT_SERVE_WAVES
 #define LRT_SERVE_WAVES 8
 #endif
-constexpr int kAccumThreads = 256;
+#ifndef LRT_ACCUM_THREADS
+#define LRT_ACCUM_THREADS 256
+#endif
+constexpr int kAccumThreads = LRT_ACCUM_THREADS;
 constexpr int kPPL = LRT_ACCUM_PPL;
 constexpr int kTilePoints = kAccumThreads * kPPL;
-// Line records staged in LDS per round.
-constexpr int kStage = 256;
+// Line records staged in LDS per round: one per thread.
+constexpr int kStage = kAccumThreads;
 
 // March tile: 256 threads x 4 points.
 constexpr int kMarchThreads = 256;
@@ -59,7 +62,10 @@ struct DevSpecies {
 // Line list on the device, sorted by nu0, structure of arrays.
 struct DevLines {
     int64_t n;
-    const double *nu0, *A, *Eu_ev, *Eu_rot, *El_ev, *El_rot, *lngu;
+    const double *nu0, *Eu_ev, *Eu_rot, *El_ev, *El_rot, *lngu;
+    // cell-independent strength factors: seta0 = 1e-7 (hc/4pi) nu0 A (W cm),
+    // skap0 = A / (8 pi c nu0^2) (cm^2 s^-1 ... per unit population)
+    const double *seta0, *skap0;
     const int32_t *species;
     // grid-relative centre: nu0 = nu_min + k0 h + frac0 (frac0 exact to a
     // few units of its last place)
@@ -70,6 +76,7 @@ struct DevLines {
 struct DevGrid {
     double nu_min, h;
     int32_t n_points;
+    double inv_h;   // 1/h (approximate bounds only; exact windows divide by h)
 };
 
 struct DevCells {

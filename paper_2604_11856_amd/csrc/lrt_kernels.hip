@@ -19,6 +19,7 @@
 
 #include <climits>
 #include <cmath>
+#include <type_traits>
 
 #include "lrt_internal.h"
 
@@ -108,27 +109,30 @@ __device__ __forceinline__ bool pair_setup(const DevLines &L, const DevGrid &g, 
         p.se = p.sk = p.inv2g = p.r = 0.0;
         return false;
     }
-    const double nu0 = L.nu0[i], A = L.A[i];
+    const double nu0 = L.nu0[i];
     const double Eu_ev = L.Eu_ev[i], Eu_rot = L.Eu_rot[i];
     const double El_ev = L.El_ev[i], El_rot = L.El_rot[i];
     const double base = q.lnNQ + L.lngu[i];
-    // N_u = N g_u e^{-E_u}/Q ; N_l g_u / g_l = N g_u e^{-E_l}/Q
-    const double Nu = exp(base - k.beta_v * Eu_ev - k.beta_tr * Eu_rot);
-    const double Nlg = exp(base - k.beta_v * El_ev - k.beta_tr * El_rot);
+    // N_u = N g_u e^{-E_u}/Q, and N_l g_u/g_l = N_u e^{x} with x the line's
+    // reduced energy, so N_l (g_u/g_l)(1 - e^{-x}) = N_u (e^{x} - 1)
+    const double lnNu = base - k.beta_v * Eu_ev - k.beta_tr * Eu_rot;
     const double x = k.beta_v * (Eu_ev - El_ev) + k.beta_tr * (Eu_rot - El_rot);
-    // eta_i = (hc/4pi) N_u A nu0 phi (W); kappa_i = eta_i / B_line
-    //       = A (N_l g_u/g_l) (1 - e^{-x}) phi / (8 pi c nu0^2)
-    const double Seta = (1e-7 * kPlanck * kLight / (4.0 * kPi)) * nu0 * A * Nu;
-    const double Skap = A * Nlg * (-expm1(-x)) / ((8.0 * kPi * kLight) * nu0 * nu0);
+    const double Nu = exp(lnNu);
+    // (the two-factor form only while N_u e^{x} stays representable)
+    const double Nlx = (lnNu > -700.0 && x < 700.0) ? Nu * expm1(x)
+                                                    : exp(lnNu + x) * (-expm1(-x));
+    const double Seta = L.seta0[i] * Nu;
+    const double Skap = L.skap0[i] * Nlx;
     // widths (Sec. 2.2.1): Doppler, Lorentz, Voigt (Olivero fit)
     const double gG = q.dop * nu0;
     const double gL = k.gL;
     const double sum = gL + gG;
     const double d = (gL - gG) / sum;
     const double gV = (1.0 - 0.18121 * (1.0 - d * d)
-                       - (0.023665 * exp(0.6 * d) + 0.00418 * exp(-1.9 * d)) * sin(kPi * d)) * sum;
-    const double r = gL / gV;
-    const double norm = 1.0 / (2.0 * gV * (1.065 + 0.447 * r + 0.058 * r * r));
+                       - (0.023665 * exp(0.6 * d) + 0.00418 * exp(-1.9 * d)) * sinpi(d)) * sum;
+    const double inv_gV = 1.0 / gV;
+    const double r = gL * inv_gV;
+    const double norm = (0.5 * inv_gV) / (1.065 + 0.447 * r + 0.058 * r * r);
     // window |nu_k - nu0| <= 100 gamma_V; rounding-exact operation order
     const double W = __dmul_rn(100.0, gV);
     double lo = ceil(__ddiv_rn(__dsub_rn(__dsub_rn(nu0, W), g.nu_min), g.h));
@@ -143,9 +147,11 @@ __device__ __forceinline__ bool pair_setup(const DevLines &L, const DevGrid &g, 
         p.khi = (int32_t)hi;
     }
     {
+        // core: a superset of the points within 25 gamma_V (one point of
+        // margin on each side covers the rounding of the product by 1/h)
         const double Wc = kCoreHalfWidth * gV;
-        double clo = fmax(ceil((nu0 - Wc - g.nu_min) / g.h), lo);
-        double chi = fmin(floor((nu0 + Wc - g.nu_min) / g.h), hi);
+        double clo = fmax(ceil((nu0 - Wc - g.nu_min) * g.inv_h) - 1.0, lo);
+        double chi = fmin(floor((nu0 + Wc - g.nu_min) * g.inv_h) + 1.0, hi);
         if (clo > chi) {
             p.kclo = 1;
             p.kchi = 0;
@@ -156,7 +162,7 @@ __device__ __forceinline__ bool pair_setup(const DevLines &L, const DevGrid &g, 
     }
     p.se = Seta * norm;
     p.sk = Skap * norm;
-    p.inv2g = 1.0 / (2.0 * gV);
+    p.inv2g = 0.5 * inv_gV;
     p.r = r;
     return p.klo <= p.khi;
 }
@@ -249,20 +255,21 @@ __global__ void scale_finish_kernel(const int32_t *emax, int32_t n, int32_t *esc
 // reaches the slice (exponential terms)".  A wave turns the bytes of a block
 // of lines into scalar bit masks and needs no vector work for control flow.
 struct __align__(16) RecF32 {
-    uint32_t mode;
+    uint64_t mode;
     float klo, khi;                 // window, tile-relative, clamped to [-1, tile] (edge masks)
     float k0f;                      // centre index, tile-relative
     float hg, fg, r, aG;            // h/gV, frac0/gV, gL/gV, 1-r
-    float aW, se, sk, pad;          // 0.016 r (1-r), scaled strengths
+    float aW, se, sk;               // 0.016 r (1-r), scaled strengths
 };
-static_assert(kPPL >= 1 && kPPL <= 2, "mode word holds 8 bits per wave: at most 2 slices per lane");
+static_assert(kPPL >= 1 && kPPL <= 2 && kAccumThreads / 64 <= 8,
+              "mode word holds 8 bits per wave (at most 2 slices per lane) and 8 waves");
 
 enum : uint32_t { kSliceIn = 1u, kSliceEdge = 2u, kSliceCore = 4u };
 
 // Mode bits of a window [klo, khi] with core window [kclo, kchi] (tile-relative).
-__device__ __forceinline__ uint32_t slice_modes(int32_t klo, int32_t khi, int32_t kclo, int32_t kchi)
+__device__ __forceinline__ uint64_t slice_modes(int32_t klo, int32_t khi, int32_t kclo, int32_t kchi)
 {
-    uint32_t m = 0;
+    uint64_t m = 0;
 #pragma unroll
     for (int w = 0; w < kAccumThreads / 64; ++w) {
 #pragma unroll
@@ -272,7 +279,7 @@ __device__ __forceinline__ uint32_t slice_modes(int32_t klo, int32_t khi, int32_
             uint32_t bits = kSliceIn;
             if (!(klo <= a && khi >= b)) bits |= kSliceEdge;
             if (!(kchi < a || kclo > b)) bits |= kSliceCore;
-            m |= bits << (8 * w + 3 * j);
+            m |= (uint64_t)bits << (8 * w + 3 * j);
         }
     }
     return m;
@@ -376,7 +383,15 @@ __device__ __forceinline__ double shape_f64(double x, double r)
 
 // Lines per compensated block: partials of at most kBlock terms are added
 // plainly, blocks are merged with Kahan's compensation.
-constexpr int kBlock = 32;
+#ifndef LRT_ACCUM_BLOCK
+#define LRT_ACCUM_BLOCK 64
+#endif
+constexpr int kBlock = LRT_ACCUM_BLOCK;
+static_assert(kBlock == 32 || kBlock == 64, "a block is one ballot mask");
+// Bit mask over the lines of one block, one bit per line.
+using BlockMask = std::conditional_t<(kBlock > 32), uint64_t, uint32_t>;
+__device__ __forceinline__ int lowest_bit(uint32_t m) { return __builtin_ctz(m); }
+__device__ __forceinline__ int lowest_bit(uint64_t m) { return __builtin_ctzll(m); }
 
 // eta and kappa of one cell on one tile (kTilePoints points starting at the
 // global index kt) in single precision: every round stages kStage candidate
@@ -408,7 +423,7 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
         rr.mode = 0;
         rr.klo = 1.0f;
         rr.khi = 0.0f;
-        rr.k0f = rr.hg = rr.fg = rr.r = rr.aG = rr.aW = rr.se = rr.sk = rr.pad = 0.0f;
+        rr.k0f = rr.hg = rr.fg = rr.r = rr.aG = rr.aW = rr.se = rr.sk = 0.0f;
         if (i < rg.y) {
             PairF64 p;
             if (pair_setup(L, g, k, csc, i, p)) {
@@ -436,17 +451,17 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
             // mode byte, one ballot per (slice, flag).  The loop then visits
             // only the lines that reach this wave, in line order.
             uint32_t mb = 0;
-            if (lane < kBlock && l0 + lane < n) mb = (rec[l0 + lane].mode >> wshift) & 0xffu;
-            uint32_t todo = (uint32_t)__ballot(mb != 0);
-            uint32_t m_in[kPPL], m_edge[kPPL], m_core[kPPL];
+            if (lane < kBlock && l0 + lane < n) mb = (uint32_t)(rec[l0 + lane].mode >> wshift) & 0xffu;
+            BlockMask todo = (BlockMask)__ballot(mb != 0);
+            BlockMask m_in[kPPL], m_edge[kPPL], m_core[kPPL];
 #pragma unroll
             for (int j = 0; j < kPPL; ++j) {
-                m_in[j] = (uint32_t)__ballot(mb & (kSliceIn << (3 * j)));
-                m_edge[j] = (uint32_t)__ballot(mb & (kSliceEdge << (3 * j)));
-                m_core[j] = (uint32_t)__ballot(mb & (kSliceCore << (3 * j)));
+                m_in[j] = (BlockMask)__ballot(mb & (kSliceIn << (3 * j)));
+                m_edge[j] = (BlockMask)__ballot(mb & (kSliceEdge << (3 * j)));
+                m_core[j] = (BlockMask)__ballot(mb & (kSliceCore << (3 * j)));
             }
             while (todo) {
-                const int t = __builtin_ctz(todo);
+                const int t = lowest_bit(todo);
                 todo &= todo - 1;
                 const RecF32 q = rec[l0 + t];
 #pragma unroll

@@ -251,7 +251,7 @@ bool lrt_server::admit(Req &r)
         !ok(hipMemcpyAsync(N, r.N.data(), (size_t)nc * S * 8, hipMemcpyHostToDevice, st), "upload"))
         return true;   // failed and released; counts as handled
     const DevLines L = dev_lines(ctx);
-    const DevGrid g{ctx->nu_min, ctx->h, (int32_t)ctx->n_points};
+    const DevGrid g = dev_grid(ctx);
     const DevCells cells{(int32_t)nc, S, T_tr, T_v, N, n_e};
     if (!ok(launch_thermo(ctx->sp, cells, ctx->M_min, r.mask, cc, cs, st), "thermo") ||
         !ok(launch_ranges(L, g, cc, (int32_t)nc, r.k_first, r.n_window, kTilePoints, ranges, st), "ranges"))
@@ -326,7 +326,7 @@ bool lrt_server::launch_epoch(Epoch &e)
         }
     }
     const DevLines L = dev_lines(ctx);
-    const DevGrid g{ctx->nu_min, ctx->h, (int32_t)ctx->n_points};
+    const DevGrid g = dev_grid(ctx);
     hipError_t err = hipMemcpyAsync(e.d_items.p, e.h_items, (size_t)n * sizeof(ServeItem),
                                     hipMemcpyHostToDevice, e.stream);
     if (err == hipSuccess) err = launch_fill_i32(e.d_counter.as<int32_t>(), 0, 1, e.stream);
@@ -368,7 +368,7 @@ void lrt_server::run()
         for (uint64_t t : admitted) {
             Req &r = *reqs[t];
             if (r.state != ST_ADMITTED || r.items_done < r.items_total) continue;
-            const DevGrid g{ctx->nu_min, ctx->h, (int32_t)ctx->n_points};
+            const DevGrid g = dev_grid(ctx);
             hipError_t err = launch_serve_combine(r.dev, g, admit_stream);
             if (err == hipSuccess) err = hipEventCreateWithFlags(&r.comb_ev, hipEventDisableTiming);
             if (err == hipSuccess) err = hipEventRecord(r.comb_ev, admit_stream);
