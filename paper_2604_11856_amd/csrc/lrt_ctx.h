@@ -66,6 +66,8 @@ struct lrt_ctx {
     DBuf d_cc, d_cs;
     bool thermo_ready = false;
     DBuf d_emax, d_escale;
+    DBuf d_bin_sp, d_bin_Ev, d_bin_Er, d_bin_aeta, d_bin_akap;
+    int64_t n_bins = 0;
     bool scale_ready = false;
 
     // rays

@@ -8,7 +8,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <numeric>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -394,7 +396,52 @@ lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *L)
         lngu[j] = std::log(L->gu[i]);
         spc[j] = L->species[i];
     }
+    // level-energy bins for the per-cell scale bound (1000 cm^-1 wide; the
+    // bound then exceeds the true peak by at most e^{(beta_v + beta_tr) 1000})
+    std::vector<int32_t> b_sp;
+    std::vector<double> b_Ev, b_Er, b_aeta, b_akap;
+    {
+        constexpr double kBinE = 1000.0;
+        std::unordered_map<uint64_t, int64_t> slot;
+        slot.reserve(4096);
+        // key: (species, upper/lower, E_ev bin, E_rot bin), bins offset to be non-negative
+        auto bin = [&](int32_t s, int lower, double Ev, double Er, double aeta, double akap) {
+            const double fe = std::floor(Ev / kBinE) + 8388608.0, fr = std::floor(Er / kBinE) + 8388608.0;
+            if (!(fe >= 0.0 && fe < 16777216.0 && fr >= 0.0 && fr < 16777216.0)) return false;
+            const uint64_t key = ((uint64_t)(2 * s + lower) << 48) | ((uint64_t)fe << 24) | (uint64_t)fr;
+            auto it = slot.find(key);
+            if (it == slot.end()) {
+                slot.emplace(key, (int64_t)b_sp.size());
+                b_sp.push_back(s);
+                b_Ev.push_back(Ev);
+                b_Er.push_back(Er);
+                b_aeta.push_back(aeta);
+                b_akap.push_back(akap);
+            } else {
+                const int64_t k = it->second;
+                b_Ev[k] = std::min(b_Ev[k], Ev);
+                b_Er[k] = std::min(b_Er[k], Er);
+                b_aeta[k] = std::max(b_aeta[k], aeta);
+                b_akap[k] = std::max(b_akap[k], akap);
+            }
+            return true;
+        };
+        const double ninf = -std::numeric_limits<double>::infinity();
+        for (int64_t j = 0; j < n; ++j) {
+            if (!(seta0[j] > 0.0)) continue;   // A = 0: the line has no strength
+            const double ln_nu = std::log(nu0[j]);
+            const double ae = std::log(seta0[j]) + lngu[j] - ln_nu;
+            const double ak = std::log(skap0[j]) + lngu[j] - ln_nu;
+            if (!bin(spc[j], 0, Eue[j], Eur[j], ae, ak) || !bin(spc[j], 1, Ele[j], Elr[j], ninf, ak))
+                return fail(c, LRT_E_ARG, "line %lld: level energy beyond +-8e9 cm^-1", (long long)j);
+        }
+    }
     lrt_status st;
+    if ((st = upload_vec(c, c->d_bin_sp, b_sp)) || (st = upload_vec(c, c->d_bin_Ev, b_Ev)) ||
+        (st = upload_vec(c, c->d_bin_Er, b_Er)) || (st = upload_vec(c, c->d_bin_aeta, b_aeta)) ||
+        (st = upload_vec(c, c->d_bin_akap, b_akap)))
+        return st;
+    c->n_bins = (int64_t)b_sp.size();
     if ((st = upload_vec(c, c->d_nu0, nu0)) || (st = upload_vec(c, c->d_seta0, seta0)) ||
         (st = upload_vec(c, c->d_skap0, skap0)) ||
         (st = upload_vec(c, c->d_Eu_ev, Eue)) || (st = upload_vec(c, c->d_Eu_rot, Eur)) ||
@@ -674,11 +721,12 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
                    c->d_lngu.as<double>(), c->d_seta0.as<double>(), c->d_skap0.as<double>(),
                    c->d_species.as<int32_t>(), c->d_k0.as<int32_t>(), c->d_frac0.as<double>()};
         DevGrid g = dev_grid(c);
-        LRT_HIP(c, launch_fill_i32(c->d_emax.as<int32_t>(), INT_MIN, 2 * c->n_cells, st));
+        const DevBins B{(int32_t)c->n_bins, c->d_bin_sp.as<int32_t>(), c->d_bin_Ev.as<double>(),
+                        c->d_bin_Er.as<double>(), c->d_bin_aeta.as<double>(), c->d_bin_akap.as<double>()};
         LRT_HIP(c, timed(c, LRT_K_SCALE, st, [&] {
-                    return launch_scale(L, 0, L.n, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
-                                        (int32_t)c->n_cells, c->n_species, c->d_emax.as<int32_t>(),
-                                        c->d_escale.as<int32_t>(), st);
+                    return launch_scale_bound(B, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
+                                              (int32_t)c->n_cells, c->n_species, c->d_escale.as<int32_t>(),
+                                              st);
                 }));
         c->scale_ready = true;
     }

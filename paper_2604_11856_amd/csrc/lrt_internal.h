@@ -73,6 +73,18 @@ struct DevLines {
     const double *frac0;
 };
 
+// Upper bounds of the line peaks for the per-cell scale, from level-energy
+// bins of the line list (one entry per (species, E_ev bin, E_rot bin) of the
+// upper levels and one per bin of the lower levels).  For every line i in a
+// bin, with Ev <= E_ev,i and Er <= E_rot,i:
+//   ln(seta0_i g_u,i / nu0_i) <= a_eta,  ln(skap0_i g_u,i / nu0_i) <= a_kap
+// (a_eta = -inf for lower-level bins).
+struct DevBins {
+    int32_t n;
+    const int32_t *species;
+    const double *Ev, *Er, *a_eta, *a_kap;
+};
+
 struct DevGrid {
     double nu_min, h;
     int32_t n_points;
@@ -132,6 +144,8 @@ hipError_t launch_ranges(const DevLines &L, const DevGrid &g, const CellConst *c
                          int32_t n_cells, int32_t k_first, int32_t n_band, int32_t tile_points,
                          int2 *ranges, hipStream_t st);
 
+hipError_t launch_scale_bound(const DevBins &B, const CellConst *cc, const CellSpecies *cs,
+                              int32_t n_cells, int32_t n_species, int32_t *escale, hipStream_t st);
 hipError_t launch_scale(const DevLines &L, int64_t i0, int64_t i1, const DevGrid &g,
                         const CellConst *cc, const CellSpecies *cs, int32_t n_cells,
                         int32_t n_species, int32_t *emax, int32_t *escale, hipStream_t st);

@@ -231,6 +231,48 @@ __global__ void scale_kernel(DevLines L, int64_t i0, int64_t i1, DevGrid g, cons
     }
 }
 
+// Per-cell scale from the level-energy bins: one wave per cell takes the
+// largest upper bound of ln(eta peak) and ln(|kappa peak|) over the bins.
+// Peak of line i: strength * norm with norm = 1/(2 gV (1.065 + ...)) and
+// gV >= 0.9 gG (the Voigt width is at least the Doppler one; 0.9 leaves room
+// for the fit), gG = dop_s nu0; |kappa| <= skap0 max(N_u, N_l g_u/g_l).  The
+// bound exceeds the true peak by a modest factor (bin width, Lorentz part of
+// the width), which the power-of-two scale absorbs.
+__global__ void scale_bound_kernel(DevBins B, const CellConst *cc, const CellSpecies *cs,
+                                   int32_t n_cells, int32_t n_species, int32_t *escale)
+{
+    const int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= n_cells) return;
+    const CellConst k = cc[c];
+    const double ln_norm = -log(2.0 * 1.065 * 0.9);
+    double ve = -INFINITY, vk = -INFINITY;
+    for (int b = lane; b < B.n; b += 64) {
+        const CellSpecies q = cs[(int64_t)c * n_species + B.species[b]];
+        if (!(q.lnNQ > -INFINITY)) continue;
+        const double v = q.lnNQ + ln_norm - log(q.dop) - k.beta_v * B.Ev[b] - k.beta_tr * B.Er[b];
+        ve = fmax(ve, B.a_eta[b] + v);
+        vk = fmax(vk, B.a_kap[b] + v);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ve = fmax(ve, __shfl_xor(ve, o));
+        vk = fmax(vk, __shfl_xor(vk, o));
+    }
+    if (lane == 0) {
+        // peak < 2^e; stay unscaled while e is within 2^+-60
+        const double v2[2] = {ve, vk};
+        for (int j = 0; j < 2; ++j) {
+            int e = 0;
+            if (v2[j] > -INFINITY) {
+                const double t = ceil(v2[j] * kLog2e) + 1.0;
+                e = (int)fmax(-2000.0, fmin(2000.0, t));
+                if (e >= -60 && e <= 60) e = 0;
+            }
+            escale[2 * c + j] = e;
+        }
+    }
+}
+
 __global__ void scale_finish_kernel(const int32_t *emax, int32_t n, int32_t *escale)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -901,6 +943,15 @@ hipError_t launch_ranges(const DevLines &L, const DevGrid &g, const CellConst *c
     const int64_t n = (int64_t)n_cells * n_tiles;
     hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, L, g, cc,
                        n_cells, k_first, n_band, tile_points, n_tiles, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_bound(const DevBins &B, const CellConst *cc, const CellSpecies *cs,
+                              int32_t n_cells, int32_t n_species, int32_t *escale, hipStream_t st)
+{
+    if (n_cells == 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_bound_kernel, dim3(blocks_for(n_cells, 4)), dim3(256), 0, st, B, cc, cs,
+                       n_cells, n_species, escale);
     return hipGetLastError();
 }
 

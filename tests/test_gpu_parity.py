@@ -256,6 +256,11 @@ def test_cold_cell_scaled_single_precision(torch_dev):
     s = esc.cpu().numpy()
     say("escale", s.tolist())
     assert s[1, 0] < -300 and s[0, 0] == 0
+    # the scale comes from an upper bound of the line peaks: stored values
+    # stay well inside the single-precision range
+    for a in (eta, kap):
+        m_ = a.abs().amax(dim=1).double().cpu().numpy()
+        assert np.all(m_ > 0) and np.all(np.log2(m_) > -100) and np.all(np.log2(m_) < 64)
     m = edge_mask(wl, 0, wl.grid.n_points)
     assert normwise(e, e_ref, m) <= 1e-5 and normwise(k, k_ref, m) <= 1e-5
     ctx.close()
