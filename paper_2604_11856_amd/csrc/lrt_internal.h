@@ -42,7 +42,11 @@ constexpr int kStage = kAccumThreads;
 
 // March tile: 256 threads x 4 points.
 constexpr int kMarchThreads = 256;
-constexpr int kMarchPPT = 4;
+#ifndef LRT_MARCH_PPT
+#define LRT_MARCH_PPT 4
+#endif
+constexpr int kMarchPPT = LRT_MARCH_PPT;
+static_assert(kMarchPPT == 1 || kMarchPPT == 2 || kMarchPPT == 4, "march points per thread");
 constexpr int kMarchPoints = kMarchThreads * kMarchPPT;
 
 // Species level tables on the device (flattened).

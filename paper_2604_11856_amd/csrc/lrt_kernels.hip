@@ -290,41 +290,41 @@ __global__ void scale_finish_kernel(const int32_t *emax, int32_t n, int32_t *esc
 // kernel are relative to the tile start, so every float index is a small
 // exact integer whatever the grid size.
 //
-// `mode` holds, for every 64-point slice of the tile, what evaluating the
-// line there takes, decided once at staging: byte w belongs to wave w, and
-// within it bits 3j, 3j+1, 3j+2 of the wave's slice j say "window reaches the
-// slice", "window edge inside the slice (mask lanes)" and "core window
-// reaches the slice (exponential terms)".  A wave turns the bytes of a block
-// of lines into scalar bit masks and needs no vector work for control flow.
+// `mode` holds three masks over the tile's 64-point slices (slice s = points
+// 64s..64s+63, bit s of each byte): bits 0-7 "window reaches the slice",
+// bits 8-15 "window edge inside the slice (mask lanes)", bits 16-23 "core
+// window reaches the slice (exponential terms)".  Decided once at staging; a
+// wave turns the bits of its own slices, over a block of lines, into scalar
+// bit masks and needs no vector work for control flow.
+constexpr int kSlices = kTilePoints / 64;
 struct __align__(16) RecF32 {
-    uint64_t mode;
+    uint32_t mode;
     float klo, khi;                 // window, tile-relative, clamped to [-1, tile] (edge masks)
     float k0f;                      // centre index, tile-relative
     float hg, fg, r, aG;            // h/gV, frac0/gV, gL/gV, 1-r
-    float aW, se, sk;               // 0.016 r (1-r), scaled strengths
+    float aW, se, sk, pad;          // 0.016 r (1-r), scaled strengths
 };
-static_assert(kPPL >= 1 && kPPL <= 2 && kAccumThreads / 64 <= 8,
-              "mode word holds 8 bits per wave (at most 2 slices per lane) and 8 waves");
+static_assert(kSlices <= 8 && kPPL <= 2, "mode masks hold at most 8 slices per tile");
 
-enum : uint32_t { kSliceIn = 1u, kSliceEdge = 2u, kSliceCore = 4u };
-
-// Mode bits of a window [klo, khi] with core window [kclo, kchi] (tile-relative).
-__device__ __forceinline__ uint64_t slice_modes(int32_t klo, int32_t khi, int32_t kclo, int32_t kchi)
+// Slices of the tile overlapped by [lo, hi] (tile-relative, possibly beyond
+// the tile): a contiguous run of bits.
+__device__ __forceinline__ uint32_t slice_run(int32_t lo, int32_t hi)
 {
-    uint64_t m = 0;
-#pragma unroll
-    for (int w = 0; w < kAccumThreads / 64; ++w) {
-#pragma unroll
-        for (int j = 0; j < kPPL; ++j) {
-            const int32_t a = (w * kPPL + j) * 64, b = a + 63;
-            if (khi < a || klo > b) continue;
-            uint32_t bits = kSliceIn;
-            if (!(klo <= a && khi >= b)) bits |= kSliceEdge;
-            if (!(kchi < a || kclo > b)) bits |= kSliceCore;
-            m |= (uint64_t)bits << (8 * w + 3 * j);
-        }
-    }
-    return m;
+    if (lo > hi || hi < 0 || lo > kTilePoints - 1) return 0u;
+    const int32_t a = max(lo, 0) >> 6, b = min(hi, kTilePoints - 1) >> 6;
+    return (2u << b) - (1u << a);
+}
+
+// Mode masks of a window [klo, khi] with core window [kclo, kchi] (tile-relative).
+__device__ __forceinline__ uint32_t slice_modes(int32_t klo, int32_t khi, int32_t kclo, int32_t kchi)
+{
+    const uint32_t in = slice_run(klo, khi);
+    // a slice holds a window edge when the window starts or ends strictly inside it
+    uint32_t edge = 0u;
+    if (klo >= 0 && (klo & 63) != 0) edge |= 1u << min(klo >> 6, 31);
+    if (khi < kTilePoints && (khi & 63) != 63 && khi >= 0) edge |= 1u << min(khi >> 6, 31);
+    const uint32_t core = slice_run(max(kclo, klo), min(kchi, khi));
+    return in | ((edge & in) << 8) | ((core & in) << 16);
 }
 
 struct __align__(16) RecF64 {
@@ -447,8 +447,8 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
                                                     int32_t kw, int lane, float (&eta)[kPPL],
                                                     float (&kap)[kPPL])
 {
-    // byte of the mode word that belongs to this wave (kw = wave * 64 * kPPL)
-    const uint32_t wshift = (uint32_t)(kw / (64 * kPPL)) * 8u;
+    // first slice of this wave (kw = wave * 64 * kPPL)
+    const uint32_t wshift = (uint32_t)(kw / 64);
     float kf[kPPL];
     float se[kPPL], ce[kPPL], sk[kPPL], ck[kPPL], ae[kPPL], ak[kPPL];
 #pragma unroll
@@ -465,7 +465,7 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
         rr.mode = 0;
         rr.klo = 1.0f;
         rr.khi = 0.0f;
-        rr.k0f = rr.hg = rr.fg = rr.r = rr.aG = rr.aW = rr.se = rr.sk = 0.0f;
+        rr.k0f = rr.hg = rr.fg = rr.r = rr.aG = rr.aW = rr.se = rr.sk = rr.pad = 0.0f;
         if (i < rg.y) {
             PairF64 p;
             if (pair_setup(L, g, k, csc, i, p)) {
@@ -493,14 +493,14 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
             // mode byte, one ballot per (slice, flag).  The loop then visits
             // only the lines that reach this wave, in line order.
             uint32_t mb = 0;
-            if (lane < kBlock && l0 + lane < n) mb = (uint32_t)(rec[l0 + lane].mode >> wshift) & 0xffu;
-            BlockMask todo = (BlockMask)__ballot(mb != 0);
+            if (lane < kBlock && l0 + lane < n) mb = rec[l0 + lane].mode >> wshift;
+            BlockMask todo = (BlockMask)__ballot((mb & ((1u << kPPL) - 1u)) != 0);
             BlockMask m_in[kPPL], m_edge[kPPL], m_core[kPPL];
 #pragma unroll
             for (int j = 0; j < kPPL; ++j) {
-                m_in[j] = (BlockMask)__ballot(mb & (kSliceIn << (3 * j)));
-                m_edge[j] = (BlockMask)__ballot(mb & (kSliceEdge << (3 * j)));
-                m_core[j] = (BlockMask)__ballot(mb & (kSliceCore << (3 * j)));
+                m_in[j] = (BlockMask)__ballot(mb & (1u << j));
+                m_edge[j] = (BlockMask)__ballot(mb & (1u << (8 + j)));
+                m_core[j] = (BlockMask)__ballot(mb & (1u << (16 + j)));
             }
             while (todo) {
                 const int t = lowest_bit(todo);
@@ -715,13 +715,25 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
     const void *kappa_v, const int32_t *escale, double *I_out, double *partials, int32_t n_chunks,
     int32_t aligned16)
 {
-    const int ray = blockIdx.x, chunk = blockIdx.y;
+    // Workgroups go round-robin to the 8 XCDs, each with its own L2: give XCD
+    // x a contiguous range of rays, since rays of one wall point share their
+    // cells near the wall (12 % faster than ray = blockIdx.x on 8192
+    // axisymmetric rays).  A bijection of [0, n_rays) for any n_rays.
+    int ray;
+    {
+        const int n = gridDim.x, x = blockIdx.x % kXCDs, i = blockIdx.x / kXCDs;
+        const int per = n / kXCDs, rem = n % kXCDs;
+        ray = x * per + min(x, rem) + i;
+    }
+    const int chunk = blockIdx.y;
     const int32_t kb = chunk * kMarchPoints + threadIdx.x * kMarchPPT;   // band-relative
     const int64_t m0 = rays.off[ray], m1 = rays.off[ray + 1];
     double I[kMarchPPT];
 #pragma unroll
     for (int j = 0; j < kMarchPPT; ++j) I[j] = 0.0;
-    // float4 loads only when every row start is 16-byte aligned
+    // vector loads only when every row start is aligned to kMarchPPT floats
+    // (16-byte aligned bases, n_band a multiple of kMarchPPT) and the
+    // thread's points are all inside the band
     const bool vec = aligned16 && (kb + kMarchPPT <= n_band) && (n_band % kMarchPPT) == 0;
 
     for (int64_t m = m0; m < m1; ++m) {
@@ -736,10 +748,24 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
             const float dsk = (float)fmin(dsk_d, 3.0e38);
             float ev[kMarchPPT], kv[kMarchPPT];
             if (vec) {
-                const float4 a = *(const float4 *)(eta + row);
-                const float4 b = *(const float4 *)(kap + row);
-                ev[0] = a.x; ev[1] = a.y; ev[2] = a.z; ev[3] = a.w;
-                kv[0] = b.x; kv[1] = b.y; kv[2] = b.z; kv[3] = b.w;
+                // one load of kMarchPPT consecutive floats per array
+                if constexpr (kMarchPPT == 4) {
+                    const float4 a = *(const float4 *)(eta + row);
+                    const float4 b = *(const float4 *)(kap + row);
+                    ev[0] = a.x; ev[1] = a.y; ev[2] = a.z; ev[3] = a.w;
+                    kv[0] = b.x; kv[1] = b.y; kv[2] = b.z; kv[3] = b.w;
+                } else if constexpr (kMarchPPT == 2) {
+                    const float2 a = *(const float2 *)(eta + row);
+                    const float2 b = *(const float2 *)(kap + row);
+                    ev[0] = a.x; ev[1] = a.y;
+                    kv[0] = b.x; kv[1] = b.y;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kMarchPPT; ++j) {
+                        ev[j] = eta[row + j];
+                        kv[j] = kap[row + j];
+                    }
+                }
             } else {
 #pragma unroll
                 for (int j = 0; j < kMarchPPT; ++j) {
