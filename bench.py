@@ -54,7 +54,23 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=48,
                     help="requests per serving phase (closed loop, then open loop); 0 skips")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy 3 times (the reference kernel that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = (2 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read_per_copy": a.numel() * 4,
+                      "bytes_written_per_copy": a.numel() * 4, "copies": 3}), flush=True)
 
 
 def workload(name):
@@ -159,6 +175,9 @@ def cpu_baseline(wl, n_points):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
