@@ -91,6 +91,8 @@ def lib():
             "orc_coeffs_bruteforce": (None, [C.POINTER(_Species), C.POINTER(_Lines),
                                              C.POINTER(_Cells), d, d, i64, _dp, _dp]),
             "orc_march": (None, [i64, _i64p, _dp, i64, _dp, _dp, _dp, _dp]),
+            "orc_linear_j_weights": (None, [d, _dp, _dp]),
+            "orc_march_nodes": (None, [i64, _i64p, _dp, i64, _dp, _dp, _dp, _dp]),
             "orc_axi_segments": (i64, [C.c_int, C.c_int, d, d, d, d, d, i64, _i64p, _dp]),
             "orc_knife_edges": (None, [C.POINTER(_Species), C.POINTER(_Lines), C.POINTER(_Cells),
                                        d, d, i64, d, i64, _i64p, _i64p, _i64p]),
@@ -352,6 +354,106 @@ def march(cells_idx, ds, eta, kappa, I_far=None):
     lib().orc_march(cells_idx.size, _p(cells_idx, _i64p), _p(ds), nk, _p(eta), _p(kappa),
                     far, _p(out))
     return out
+
+
+def linear_j_weights(t: float):
+    """(W_far, W_near) of the linear-j segment (Sec. 2.2.3): the segment adds
+    ds (W_far j_far + W_near j_near) to the attenuated intensity."""
+    a, b = C.c_double(), C.c_double()
+    lib().orc_linear_j_weights(float(t), C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def midpoint_nodes(cells_idx, ds):
+    """LOS nodes of a ray given as cell segments far -> target, for the
+    linear-j march: the far end, the midpoint of every segment, the target.
+    A node takes the state of the cell that contains it; spacings are
+    ds_0/2, (ds_m + ds_m+1)/2, ..., ds_M-1/2."""
+    cells_idx = np.asarray(cells_idx, np.int64)
+    ds = np.asarray(ds, np.float64)
+    node_cell = np.concatenate([cells_idx[:1], cells_idx, cells_idx[-1:]])
+    dsn = np.concatenate([ds[:1] * 0.5, 0.5 * (ds[:-1] + ds[1:]), ds[-1:] * 0.5])
+    return node_cell, dsn
+
+
+def march_nodes(node_cell, dsn, eta, kappa, I_far=None):
+    """Linear-j march over explicit nodes (Sec. 2.2.3): I at the last node for
+    every column of eta/kappa [n_cells, n_k]."""
+    eta = np.ascontiguousarray(eta, np.float64)
+    kappa = np.ascontiguousarray(kappa, np.float64)
+    node_cell = np.ascontiguousarray(node_cell, np.int64)
+    dsn = np.ascontiguousarray(dsn, np.float64)
+    nk = eta.shape[1]
+    out = np.zeros(nk)
+    far = None if I_far is None else _p(np.ascontiguousarray(I_far, np.float64))
+    lib().orc_march_nodes(node_cell.size, _p(node_cell, _i64p), _p(dsn), nk, _p(eta), _p(kappa),
+                          far, _p(out))
+    return out
+
+
+def march_linear(cells_idx, ds, eta, kappa, I_far=None):
+    """Linear-j march of a cell-segment ray through its midpoint nodes."""
+    nc, dsn = midpoint_nodes(cells_idx, ds)
+    return march_nodes(nc, dsn, eta, kappa, I_far)
+
+
+def planck_spectrum(grid, ks, T: float):
+    """Blackbody intensity B(nu_k, T) (W cm^-2 sr^-1 per cm^-1) at grid points ks."""
+    h = grid_step(grid)
+    return np.array([lib().orc_planck(grid.nu_min + float(k) * h, float(T)) for k in ks])
+
+
+def fibonacci_directions(n: int):
+    """Fibonacci-sphere LOS directions (Sec. 2.2.3): for i = 1..n,
+    w = 1 - 2 (i-1)/(n-1), r = sqrt(1 - w^2), a = (i-1)(sqrt 5 - 1) pi and the
+    unit vector (r cos a, w, r sin a).  Returned in the wall frame: the polar
+    component w along the wall normal (first coordinate), then (r cos a,
+    r sin a)."""
+    i = np.arange(1, n + 1, dtype=np.float64)
+    w = 1.0 - 2.0 * (i - 1.0) / (n - 1.0)
+    r = np.sqrt(np.maximum(0.0, 1.0 - w * w))
+    a = (i - 1.0) * (np.sqrt(5.0) - 1.0) * np.pi
+    return np.stack([w, r * np.cos(a), r * np.sin(a)], axis=1)
+
+
+def fibonacci_quadrature(n_los: int, n_polar: int, n_azim: int):
+    """Flux quadrature over the Fibonacci LOS seen from a wall (Sec. 2.2.3
+    heat-flux sum): the LOS results are carried to the nodes of a uniform
+    grid in polar angle phi_p = p (pi/2)/n_polar (from the wall normal) and
+    azimuth theta_t = t 2 pi/n_azim by taking the nearest LOS direction, and
+    every grid cell contributes the mean of its four corners times
+    int sin(phi) cos(phi) dphi over the cell = (sin^2 phi_p+1 - sin^2 phi_p)/2,
+    times the azimuth step.  Because the rule is linear in the LOS results it
+    is a weight per LOS.  Returns (directions [m, 3] with positive normal
+    component, weights [m])."""
+    d = fibonacci_directions(n_los)
+    keep = np.nonzero(d[:, 0] > 0.0)[0]
+    d = d[keep]
+    w = np.zeros(len(keep))
+    phi = np.arange(n_polar + 1) * (0.5 * np.pi / n_polar)
+    th = np.arange(n_azim + 1) * (2.0 * np.pi / n_azim)
+    near = np.zeros((n_polar + 1, n_azim + 1), np.int64)
+    for p in range(n_polar + 1):
+        for t in range(n_azim + 1):
+            nx_, ny_, nz_ = np.cos(phi[p]), np.sin(phi[p]) * np.cos(th[t]), np.sin(phi[p]) * np.sin(th[t])
+            dots = d[:, 0] * nx_ + d[:, 1] * ny_ + d[:, 2] * nz_
+            near[p, t] = int(np.argmax(dots))
+    for p in range(n_polar):
+        wp = 0.5 * (np.sin(phi[p + 1]) ** 2 - np.sin(phi[p]) ** 2)
+        for t in range(n_azim):
+            wc = 0.25 * wp * (th[t + 1] - th[t])
+            for pp, tt in ((p, t), (p + 1, t), (p, t + 1), (p + 1, t + 1)):
+                w[near[pp, tt]] += wc
+    return d, w
+
+
+def axi_rays_fibonacci(geom, wall_index: int, n_los: int, n_polar: int, n_azim: int):
+    """Rays of one wall point along the Fibonacci LOS with a positive normal
+    component, and their flux weights."""
+    d, w = fibonacci_quadrature(n_los, n_polar, n_azim)
+    rw = float(geom.wall_r[wall_index])
+    rays = [axi_ray(geom, rw, float(v[0]), float(np.arctan2(v[2], v[1]))) for v in d]
+    return rays, w
 
 
 def trapezoid_weights(grid, ks=None):

@@ -386,6 +386,60 @@ void orc_march(int64_t n_seg, const int64_t *cell, const double *ds,
     }
 }
 
+/* Sec. 2.2.3, Johnston-Mazaheri segment with linear j: over [s_i, s_{i+1}]
+ * kappa is the far node's value and j varies linearly.  Integrating the
+ * transfer equation over the segment (the derivation printed with the scheme)
+ * gives, with t = kappa ds and f(t) = (1 - e^{-t}) / t,
+ *   I_{i+1} = I_i e^{-t} + ds [ W_far(t) j_i + W_near(t) j_{i+1} ],
+ *   W_near(t) = (1 - f(t)) / t,   W_far(t) = (f(t) - e^{-t}) / t.
+ * (The closing formula of the scheme pairs these two coefficients with the
+ * other node; its own derivation, and the limit t -> infinity where only the
+ * node next to the target can matter, fix the pairing used here.)
+ * Where t is small both differences cancel, so there the weights come from
+ * their Taylor series (the paper's thin-layer branch, carried to double
+ * precision):  W_near(t) = sum_{n>=0} (-t)^n / (n+2)!,
+ *              W_far(t)  = sum_{n>=0} (-1)^n (n+1) t^n / (n+2)!.            */
+void orc_linear_j_weights(double t, double *w_far, double *w_near)
+{
+    if (fabs(t) >= 0.05) {
+        double e = exp(-t);
+        double f = -expm1(-t) / t;
+        *w_near = (1.0 - f) / t;
+        *w_far = (f - e) / t;
+        return;
+    }
+    double a = 0.0, b = 0.0, fact = 2.0, tn = 1.0;   /* fact = (n+2)!, tn = (-t)^n */
+    for (int n = 0; n < 20; ++n) {
+        a += tn / fact;
+        b += (n + 1) * tn / fact;
+        tn *= -t;
+        fact *= (double)(n + 3);
+    }
+    *w_near = a;
+    *w_far = b;
+}
+
+/* March over nodes 0..n_node-1 (far -> target): node i carries the cell
+ * node_cell[i] whose eta/kappa it takes, dsn[i] is the distance from node i
+ * to node i+1.  I starts from I_far (NULL: 0) at node 0. */
+void orc_march_nodes(int64_t n_node, const int64_t *node_cell, const double *dsn,
+                     int64_t n_k, const double *eta, const double *kappa,
+                     const double *I_far, double *I_out)
+{
+    for (int64_t k = 0; k < n_k; ++k) {
+        double I = I_far ? I_far[k] : 0.0;
+        for (int64_t i = 0; i + 1 < n_node; ++i) {
+            double kap = kappa[node_cell[i] * n_k + k];
+            double j_far = eta[node_cell[i] * n_k + k];
+            double j_near = eta[node_cell[i + 1] * n_k + k];
+            double wf, wn;
+            orc_linear_j_weights(kap * dsn[i], &wf, &wn);
+            I = I * exp(-kap * dsn[i]) + dsn[i] * (wf * j_far + wn * j_near);
+        }
+        I_out[k] = I;
+    }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Sec. 2.2.3 ray geometry: axisymmetric cell traversal                      */
 /* ---------------------------------------------------------------------- */

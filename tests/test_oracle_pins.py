@@ -526,3 +526,156 @@ def test_axi_uniform_medium_matches_path_length():
     kap = np.full((60, 1), 0.3)
     for c, d in rays:
         assert O.march(c, d, eta, kap)[0] == pytest.approx(2.0 * -math.expm1(-0.3 * d.sum()), rel=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# Linear-j segment scheme, far blackbody boundary, Fibonacci LOS (Sec. 2.2.3)
+# ----------------------------------------------------------------------------
+
+def test_linear_j_weights_known_values():
+    """t -> 0: both weights 1/2 (trapezoid); t = 1: W_far = f(1) - 1/e = 1 - 2/e
+    and W_near = 1 - f(1) = 1/e; W_far + W_near = f(t) = (1 - e^-t)/t for
+    every t; for large t the node next to the target dominates."""
+    assert O.linear_j_weights(0.0) == (0.5, 0.5)
+    wf, wn = O.linear_j_weights(1.0)
+    assert abs(wn - math.exp(-1.0)) < 1e-15 and abs(wf - (1.0 - 2.0 * math.exp(-1.0))) < 1e-15
+    for t in (-3.0, -0.2, -0.05, -1e-3, 1e-9, 1e-3, 0.0499, 0.05, 0.3, 2.0, 40.0, 700.0):
+        wf, wn = O.linear_j_weights(t)
+        f = -math.expm1(-t) / t
+        assert abs((wf + wn) - f) <= 1e-14 * abs(f), t
+    wf, wn = O.linear_j_weights(50.0)
+    assert wn > 40 * wf
+
+
+def test_linear_j_weights_against_quadrature():
+    """Unit segment, target at u = 1: W_far = int_0^1 (1-u) e^{-t(1-u)} du and
+    W_near = int_0^1 u e^{-t(1-u)} du, by adaptive quadrature."""
+    for t in (-2.0, -0.04, 1e-6, 0.01, 0.049, 0.051, 0.7, 5.0, 60.0):
+        wf, wn = O.linear_j_weights(t)
+        fq = si.quad(lambda u: (1 - u) * math.exp(-t * (1 - u)), 0, 1, epsabs=0, epsrel=2e-14)[0]
+        nq = si.quad(lambda u: u * math.exp(-t * (1 - u)), 0, 1, epsabs=0, epsrel=2e-14)[0]
+        assert abs(wf - fq) <= 2e-13 * abs(fq) and abs(wn - nq) <= 2e-13 * abs(nq), t
+
+
+def test_march_nodes_exact_for_linear_emission():
+    """Constant kappa and j(s) = a + b s along the ray: the scheme is exact for
+    any node placement, I(L) = a (1-e^{-kL})/k + b (L/k - (1-e^{-kL})/k^2)."""
+    rng = np.random.default_rng(5)
+    for kap in (1e-8, 0.3, 4.0):
+        s = np.concatenate([[0.0], np.sort(rng.uniform(0.0, 2.5, 9)), [2.5]])
+        a, b = 0.7, 1.9
+        j = a + b * s
+        eta = j[:, None]
+        kappa = np.full((s.size, 1), kap)
+        I = O.march_nodes(np.arange(s.size), np.diff(s), eta, kappa)[0]
+        L = s[-1]
+        x = kap * L
+        E = -math.expm1(-x)
+        # L/k - E/k^2 = L^2 g(x), g(x) = (x - 1 + e^-x)/x^2, summed as a series
+        # where the difference cancels
+        g = (x - E) / x**2 if x > 0.1 else sum((-x)**n / math.factorial(n + 2) for n in range(30))
+        ref = a * E / kap + b * L * L * g
+        assert abs(I - ref) <= 1e-11 * abs(ref), kap
+
+
+def test_march_nodes_far_node_kappa_bruteforce():
+    """Varying kappa: on [s_i, s_i+1] kappa is the far node's value and j is
+    linear; a fine explicit integration of dI/ds = j - kappa I with exact
+    per-substep attenuation converges to the scheme."""
+    rng = np.random.default_rng(9)
+    n = 6
+    dsn = rng.uniform(0.05, 0.4, n - 1)
+    eta = rng.uniform(0.5, 2.0, (n, 1))
+    kappa = rng.uniform(0.1, 3.0, (n, 1))
+    I_s = O.march_nodes(np.arange(n), dsn, eta, kappa)[0]
+    I = 0.0
+    m = 4000
+    for i in range(n - 1):
+        h = dsn[i] / m
+        for q in range(m):
+            u = (q + 0.5) / m
+            jj = eta[i, 0] * (1 - u) + eta[i + 1, 0] * u
+            e = math.exp(-kappa[i, 0] * h)
+            I = I * e + jj * (1 - e) / kappa[i, 0]
+    assert abs(I - I_s) <= 1e-7 * abs(I_s)
+
+
+def test_march_nodes_transparent_is_trapezoid():
+    """kappa = 0: I = sum ds_i (j_i + j_i+1)/2 exactly."""
+    rng = np.random.default_rng(2)
+    j = rng.uniform(0, 3, 7)
+    dsn = rng.uniform(0.1, 1, 6)
+    I = O.march_nodes(np.arange(7), dsn, j[:, None], np.zeros((7, 1)))[0]
+    assert abs(I - float(np.sum(dsn * 0.5 * (j[:-1] + j[1:])))) <= 1e-14 * I
+
+
+def test_midpoint_nodes_uniform_medium():
+    """Uniform medium through midpoint nodes: the constant-source closed form
+    (eta/kappa)(1 - e^{-kappa L}), equal to the cell-constant march."""
+    cells = np.array([0, 1, 2, 3])
+    ds = np.array([0.2, 0.05, 0.3, 0.15])
+    eta = np.full((4, 2), 2.0)
+    kappa = np.array([[0.5, 1e-9]] * 4)
+    I = O.march_linear(cells, ds, eta, kappa)
+    L = ds.sum()
+    ref = np.array([2.0 / 0.5 * -math.expm1(-0.5 * L), 2.0 / 1e-9 * -math.expm1(-1e-9 * L)])
+    assert np.allclose(I, ref, rtol=1e-13, atol=0)
+    assert np.allclose(I, O.march(cells, ds, eta, kappa), rtol=1e-13, atol=0)
+    nc, dsn = O.midpoint_nodes(cells, ds)
+    assert list(nc) == [0, 0, 1, 2, 3, 3] and abs(dsn.sum() - L) < 1e-15
+
+
+def test_far_blackbody_in_equilibrium_medium():
+    """Far boundary at T and every cell in LTE at T (eta = kappa B(T)): the
+    intensity stays B(T) along any path.  The cell-constant march keeps this for
+    any kappa; the linear-j march (kappa from the far node, j linear) keeps it
+    where kappa is uniform along the ray."""
+    class G:
+        nu_min, nu_max, n_points = 1000.0, 50000.0, 3
+    ks = np.array([0, 1, 2])
+    T = 7000.0
+    B = O.planck_spectrum(G, ks, T)
+    for k, Bk in zip(ks, B):
+        nu = G.nu_min + k * (G.nu_max - G.nu_min) / (G.n_points - 1)
+        assert abs(Bk - planck_textbook(nu, T)) <= 1e-14 * Bk
+    cells = np.arange(5)
+    ds = np.array([0.3, 0.01, 1.2, 0.5, 0.05])
+    kappa = np.array([[0.2, 3.0, 1e-4]] * 5) * np.arange(1, 6)[:, None]
+    eta = kappa * B[None, :]
+    I = O.march(cells, ds, eta, kappa, I_far=B)
+    assert np.allclose(I, B, rtol=1e-13, atol=0)
+    kappa_u = np.repeat(kappa[2:3], 5, axis=0)
+    I = O.march_linear(cells, ds, kappa_u * B[None, :], kappa_u, I_far=B)
+    assert np.allclose(I, B, rtol=1e-13, atol=0)
+    # and without the far boundary the linear-j ray falls short of B by B e^{-tau}
+    I0 = O.march_linear(cells, ds, kappa_u * B[None, :], kappa_u)
+    assert np.allclose(I0, B * -np.expm1(-kappa_u[0] * ds.sum()), rtol=1e-12, atol=0)
+
+
+def test_fibonacci_directions():
+    """Unit vectors; the first is the wall normal; the polar component steps
+    uniformly from 1 to -1 and the azimuth by the golden angle."""
+    d = O.fibonacci_directions(400)
+    assert np.allclose(np.linalg.norm(d, axis=1), 1.0, atol=1e-15)
+    assert np.allclose(d[0], [1.0, 0.0, 0.0]) and np.allclose(d[-1, 0], -1.0)
+    assert np.allclose(np.diff(d[:, 0]), -2.0 / 399)
+    a = np.arctan2(d[1:, 2], d[1:, 1])
+    da = np.mod(np.diff(a), 2 * np.pi)
+    assert np.allclose(da[1:-1], np.mod((math.sqrt(5) - 1) * math.pi, 2 * math.pi), atol=1e-9)
+    # nearly uniform: the mean direction over the sphere is ~0
+    assert np.linalg.norm(d.mean(axis=0)) < 1e-2
+
+
+def test_fibonacci_quadrature_flux_integrals():
+    """Weights integrate I cos(phi) over the outgoing hemisphere: isotropic
+    I = 1 gives pi exactly; I = cos(phi) gives 2 pi/3 and I = cos^2(phi)
+    gives pi/2 within the grid's discretisation error, which shrinks as the
+    LOS set and grid are refined."""
+    errs = []
+    for n_los, n_p, n_a in ((100, 8, 16), (400, 16, 32), (1600, 32, 64)):
+        d, w = O.fibonacci_quadrature(n_los, n_p, n_a)
+        assert abs(w.sum() - math.pi) < 1e-12 and np.all(w >= 0) and np.all(d[:, 0] > 0)
+        e1 = abs(float(w @ d[:, 0]) - 2 * math.pi / 3) / (2 * math.pi / 3)
+        e2 = abs(float(w @ d[:, 0] ** 2) - math.pi / 2) / (math.pi / 2)
+        errs.append(max(e1, e2))
+    assert errs[-1] < 0.02 and errs[-1] < errs[0]
