@@ -481,14 +481,18 @@ int64_t orc_axi_segments(int nx, int nr, double Lx, double R, double rw,
         if (mu > 0.0 && s > 0.0 && s < s_exit) bp[nb++] = s;
     }
     if (A2 > 0.0) {
+        /* A wall point on a radial face gives a root at s = 0 that rounding can
+         * move to ~1e-15: a crossing within 1e-12 of the domain size of the
+         * wall point is the wall point itself, not the start of a segment. */
+        double s_min = 1e-12 * (Lx + R);
         for (int j = 1; j < nr; ++j) {
             double rj = j * dr;
             double disc = rw * rw * a * a - A2 * (rw * rw - rj * rj);
             if (disc < 0.0) continue;
             double sq = sqrt(disc);
             double r1 = (-rw * a - sq) / A2, r2 = (-rw * a + sq) / A2;
-            if (r1 > 0.0 && r1 < s_exit) bp[nb++] = r1;
-            if (r2 > 0.0 && r2 < s_exit && r2 != r1) bp[nb++] = r2;
+            if (r1 > s_min && r1 < s_exit) bp[nb++] = r1;
+            if (r2 > s_min && r2 < s_exit && r2 != r1) bp[nb++] = r2;
         }
     }
     qsort(bp, (size_t)nb, sizeof(double), cmp_double);
