@@ -166,6 +166,50 @@ lrt_status lrt_set_rays_slab(lrt_ctx *ctx, int64_t n_cells, const double *dx, in
 lrt_status lrt_set_rays_axi(lrt_ctx *ctx, int nx, int nr, double Lx, double R, int n_wall,
                             const double *wall_r, int n_mu, int n_phi);
 
+/* Rays of the axisymmetric grid of lrt_set_rays_axi along Fibonacci-sphere
+ * lines of sight (Sec. 2.2.3): of n_los directions i = 1..n_los with polar
+ * component w = 1 - 2(i-1)/(n_los-1) along the wall normal (+x) and azimuth
+ * (i-1)(sqrt 5 - 1) pi, those with w > 0 are traced from every wall point.
+ * Flux weights: the LOS results are carried to the nodes of a uniform grid of
+ * n_polar polar intervals on [0, pi/2] and n_azim azimuth intervals on
+ * [0, 2 pi] (each node takes its nearest LOS), and each grid cell adds the mean
+ * of its four corners times its integral of sin(phi) cos(phi) dphi dtheta;
+ * the weights of a wall point sum to pi.  All symmetry is ignored: every
+ * direction is traced.  Errors: LRT_E_ARG (non-positive sizes, n_los < 3,
+ * wall_r outside [0, R)). */
+lrt_status lrt_set_rays_axi_fibonacci(lrt_ctx *ctx, int nx, int nr, double Lx, double R, int n_wall,
+                                      const double *wall_r, int n_los, int n_polar, int n_azim);
+
+/* Host-only (no device, no context): the directions (dirs[3*i..3*i+2], unit,
+ * normal component first) and flux weights of lrt_set_rays_axi_fibonacci's
+ * angular rule; *n receives the number of directions with a positive normal
+ * component, at most cap are written.  Errors: LRT_E_ARG (bad sizes, cap too
+ * small). */
+lrt_status lrt_fibonacci_quadrature(int n_los, int n_polar, int n_azim, int64_t cap, double *dirs,
+                                    double *weights, int64_t *n);
+
+/* March scheme used by lrt_march and lrt_solve (Sec. 2.2.3).
+ *   LRT_MARCH_CELL: piecewise-constant cells along each segment,
+ *     I <- I e^{-tau} + eta ds F(tau) (the default).
+ *   LRT_MARCH_LINEAR_J: the Johnston-Mazaheri segment with kappa from the far
+ *     node and j linear between LOS nodes, placed at the far end of each ray,
+ *     the midpoint of every cell segment and the target (a node takes the
+ *     state of its cell); I <- I e^{-kappa_f L} + L (W_far j_f + W_near j_n),
+ *     W_near = (1 - f)/tau, W_far = (f - e^{-tau})/tau, f = (1 - e^{-tau})/tau,
+ *     with a Taylor branch for thin segments. */
+typedef enum { LRT_MARCH_CELL = 0, LRT_MARCH_LINEAR_J = 1 } lrt_march_scheme;
+
+/* Select the march scheme (kept until changed).  Errors: LRT_E_ARG. */
+lrt_status lrt_set_march(lrt_ctx *ctx, lrt_march_scheme scheme);
+
+/* Far boundary of every ray (Sec. 2.2.3): a solid surface at temperature
+ * T_far starts the march with the blackbody intensity B(nu, T_far); 0 means a
+ * free boundary (I = 0).  n = 1 applies T_far[0] to every ray, n = n_rays
+ * gives one value per ray (host array), n = 0 makes every ray free again.
+ * Setting new rays resets all rays to free.  Errors: LRT_E_STATE (no rays),
+ * LRT_E_ARG (n not 0, 1 or n_rays; T < 0 or non-finite). */
+lrt_status lrt_set_far_temperature(lrt_ctx *ctx, const double *T_far, int64_t n);
+
 /* Host-only (no device, no context): segments of one ray of the axisymmetric
  * geometry of lrt_set_rays_axi, from wall radius rw along (mu, sqrt(1-mu^2)
  * cos phi, sqrt(1-mu^2) sin phi), far -> wall order, at most cap entries.
@@ -201,9 +245,10 @@ lrt_status lrt_coeffs(lrt_ctx *ctx, int64_t band, lrt_precision prec, void *eta,
 
 /* March every ray through eta / kappa of band `band` (as written by
  * lrt_coeffs with the same precision) and integrate over the band's grid
- * points (Sec. 2.2.3): per ray and point, starting from I = 0 at the far end,
- * I <- I exp(-tau) + eta ds F(tau), tau = kappa ds, F(t) = (1 - e^-t)/t,
- * F(0) = 1.  I_out (device, [n_rays][band_len] doubles) receives the wall
+ * points (Sec. 2.2.3): per ray and point, starting from the far boundary's
+ * intensity (0, or B(nu, T_far) of lrt_set_far_temperature), with the scheme
+ * of lrt_set_march; by default I <- I exp(-tau) + eta ds F(tau),
+ * tau = kappa ds, F(t) = (1 - e^-t)/t, F(0) = 1.  I_out (device, [n_rays][band_len] doubles) receives the wall
  * intensity, or pass NULL; I_int_out (device, [n_rays] doubles) receives the
  * band's trapezoid sum with global-index weights (h/2 at grid ends, h inside).
  * Stream-ordered.  Errors: LRT_E_STATE (no rays, cells/rays mismatch),

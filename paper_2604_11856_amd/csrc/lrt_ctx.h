@@ -78,6 +78,9 @@ struct lrt_ctx {
     std::vector<double> h_ds, h_weight;
     std::vector<int64_t> h_wall_off, h_ray_wall;
     DBuf d_off, d_cell, d_ds, d_weight, d_wall_off;
+    DBuf d_Tfar;              // per-ray far-boundary temperature (valid when have_Tfar)
+    bool have_Tfar = false;
+    int march_scheme = 0;     // lrt_march_scheme
 
     // workspace
     DBuf w_ranges, w_eta, w_kappa, w_partials, w_Iband, w_Itot, w_qband, w_count;

@@ -511,6 +511,7 @@ lrt_status lrt_set_cells(lrt_ctx *c, const lrt_cells *x)
 
 static lrt_status upload_rays(lrt_ctx *c)
 {
+    c->have_Tfar = false;   // a new ray set starts with free far boundaries
     lrt_status st;
     if ((st = upload_vec(c, c->d_off, c->h_off)) || (st = upload_vec(c, c->d_cell, c->h_cell)) ||
         (st = upload_vec(c, c->d_ds, c->h_ds)) || (st = upload_vec(c, c->d_weight, c->h_weight)) ||
@@ -602,6 +603,156 @@ lrt_status lrt_set_rays_axi(lrt_ctx *c, int nx, int nr, double Lx, double R, int
     c->n_rays = (int64_t)c->h_weight.size();
     c->n_wall = n_wall;
     c->rays_cells = (int64_t)nx * nr;
+    return LRT_OK;
+}
+
+// Fibonacci-sphere LOS seen from a wall with normal along +x, and the flux
+// weight of each (Sec. 2.2.3): direction i (1-based) of n has polar component
+// w = 1 - 2(i-1)/(n-1) along the normal and azimuth a = (i-1)(sqrt 5 - 1) pi;
+// those with w > 0 look into the gas.  The interpolated angular rule carries
+// the LOS results to the nodes of a uniform (polar phi, azimuth theta) grid,
+// each node taking its nearest LOS, and sums over the grid cells the mean of
+// the four corners times the cell's int sin(phi) cos(phi) dphi dtheta.  The
+// rule is linear in the LOS results, so it reduces to one weight per LOS.
+static void fibonacci_rule(int n_los, int n_polar, int n_azim, std::vector<double> &dir,
+                           std::vector<double> &wt)
+{
+    dir.clear();
+    wt.clear();
+    for (int i = 0; i < n_los; ++i) {
+        const double w = 1.0 - 2.0 * (double)i / (double)(n_los - 1);
+        if (!(w > 0.0)) continue;
+        const double r = std::sqrt(std::max(0.0, 1.0 - w * w));
+        const double a = ((double)i * (std::sqrt(5.0) - 1.0)) * kPi;
+        dir.push_back(w);
+        dir.push_back(r * std::cos(a));
+        dir.push_back(r * std::sin(a));
+    }
+    const int m = (int)(dir.size() / 3);
+    wt.assign(m, 0.0);
+    std::vector<int> near((size_t)(n_polar + 1) * (n_azim + 1));
+    const double dphi = 0.5 * kPi / n_polar, dth = 2.0 * kPi / n_azim;
+    for (int p = 0; p <= n_polar; ++p) {
+        const double ph = p * dphi;
+        for (int t = 0; t <= n_azim; ++t) {
+            const double th = t * dth;
+            const double nx_ = std::cos(ph), ny_ = std::sin(ph) * std::cos(th), nz_ = std::sin(ph) * std::sin(th);
+            int best = 0;
+            double bd = -2.0;
+            for (int q = 0; q < m; ++q) {
+                const double dd = dir[3 * q] * nx_ + dir[3 * q + 1] * ny_ + dir[3 * q + 2] * nz_;
+                if (dd > bd) {
+                    bd = dd;
+                    best = q;
+                }
+            }
+            near[(size_t)p * (n_azim + 1) + t] = best;
+        }
+    }
+    for (int p = 0; p < n_polar; ++p) {
+        const double s0 = std::sin(p * dphi), s1 = std::sin((p + 1) * dphi);
+        const double band = 0.5 * (s1 * s1 - s0 * s0);
+        for (int t = 0; t < n_azim; ++t) {
+            const double quarter = 0.25 * band * (((t + 1) * dth) - (t * dth));
+            wt[near[(size_t)p * (n_azim + 1) + t]] += quarter;
+            wt[near[(size_t)(p + 1) * (n_azim + 1) + t]] += quarter;
+            wt[near[(size_t)p * (n_azim + 1) + t + 1]] += quarter;
+            wt[near[(size_t)(p + 1) * (n_azim + 1) + t + 1]] += quarter;
+        }
+    }
+}
+
+lrt_status lrt_set_rays_axi_fibonacci(lrt_ctx *c, int nx, int nr, double Lx, double R, int n_wall,
+                                      const double *wall_r, int n_los, int n_polar, int n_azim)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (nx < 1 || nr < 1 || !(Lx > 0.0) || !(R > 0.0) || n_wall < 1 || !wall_r || n_los < 3 || n_polar < 1 ||
+        n_azim < 1)
+        return fail(c, LRT_E_ARG, "Fibonacci rays need positive sizes and n_los >= 3");
+    if ((int64_t)nx * nr >= INT_MAX) return fail(c, LRT_E_ARG, "grid too large");
+    for (int w = 0; w < n_wall; ++w)
+        if (!(wall_r[w] >= 0.0) || !(wall_r[w] < R)) return fail(c, LRT_E_ARG, "wall_r[%d] outside [0, R)", w);
+    std::vector<double> dir, wt;
+    fibonacci_rule(n_los, n_polar, n_azim, dir, wt);
+    c->h_off.assign(1, 0);
+    c->h_cell.clear();
+    c->h_ds.clear();
+    c->h_weight.clear();
+    c->h_ray_wall.clear();
+    c->h_wall_off.assign(1, 0);
+    std::vector<int32_t> cell;
+    std::vector<double> ds;
+    for (int w = 0; w < n_wall; ++w) {
+        for (size_t q = 0; q < wt.size(); ++q) {
+            const double mu = std::min(1.0, dir[3 * q]);
+            const double phi = std::atan2(dir[3 * q + 2], dir[3 * q + 1]);
+            cell.clear();
+            ds.clear();
+            if (!traverse_axi(nx, nr, Lx, R, wall_r[w], mu, phi, cell, ds))
+                return fail(c, LRT_E_ARG, "ray traversal did not terminate (wall %d, LOS %zu)", w, q);
+            for (int64_t m = (int64_t)cell.size() - 1; m >= 0; --m) {   // far -> wall
+                c->h_cell.push_back(cell[m]);
+                c->h_ds.push_back(ds[m]);
+            }
+            c->h_off.push_back((int64_t)c->h_cell.size());
+            c->h_weight.push_back(wt[q]);
+            c->h_ray_wall.push_back(w);
+        }
+        c->h_wall_off.push_back((int64_t)c->h_weight.size());
+    }
+    lrt_status st = upload_rays(c);
+    if (st) return st;
+    c->n_rays = (int64_t)c->h_weight.size();
+    c->n_wall = n_wall;
+    c->rays_cells = (int64_t)nx * nr;
+    return LRT_OK;
+}
+
+lrt_status lrt_fibonacci_quadrature(int n_los, int n_polar, int n_azim, int64_t cap, double *dirs,
+                                    double *weights, int64_t *n)
+{
+    if (n_los < 3 || n_polar < 1 || n_azim < 1 || !n || (cap > 0 && (!dirs || !weights)))
+        return fail(nullptr, LRT_E_ARG, "fibonacci: invalid sizes");
+    std::vector<double> dir, wt;
+    fibonacci_rule(n_los, n_polar, n_azim, dir, wt);
+    *n = (int64_t)wt.size();
+    if (cap < *n) return fail(nullptr, LRT_E_ARG, "fibonacci: capacity %lld < %lld", (long long)cap, (long long)*n);
+    std::copy(dir.begin(), dir.end(), dirs);
+    std::copy(wt.begin(), wt.end(), weights);
+    return LRT_OK;
+}
+
+lrt_status lrt_set_march(lrt_ctx *c, lrt_march_scheme scheme)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (scheme != LRT_MARCH_CELL && scheme != LRT_MARCH_LINEAR_J)
+        return fail(c, LRT_E_ARG, "unknown march scheme %d", (int)scheme);
+    c->march_scheme = (int)scheme;
+    return LRT_OK;
+}
+
+lrt_status lrt_set_far_temperature(lrt_ctx *c, const double *T_far, int64_t n)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (c->n_rays < 1) return fail(c, LRT_E_STATE, "rays not set");
+    if (n == 0) {
+        c->have_Tfar = false;
+        return LRT_OK;
+    }
+    if (!T_far || (n != 1 && n != c->n_rays))
+        return fail(c, LRT_E_ARG, "T_far needs 1 or n_rays = %lld values", (long long)c->n_rays);
+    std::vector<double> t((size_t)c->n_rays);
+    for (int64_t r = 0; r < c->n_rays; ++r) {
+        const double v = T_far[n == 1 ? 0 : r];
+        if (!(v >= 0.0) || !std::isfinite(v)) return fail(c, LRT_E_ARG, "T_far[%lld] must be >= 0", (long long)r);
+        t[(size_t)r] = v;
+    }
+    lrt_status st = upload_vec(c, c->d_Tfar, t);
+    if (st) return st;
+    c->have_Tfar = true;
     return LRT_OK;
 }
 
@@ -806,8 +957,10 @@ lrt_status march_impl(lrt_ctx *c, int64_t band, lrt_precision prec, const void *
     const DevRays rays{(int32_t)c->n_rays, c->d_off.as<int64_t>(), c->d_cell.as<int32_t>(), c->d_ds.as<double>()};
     const DevGrid g = dev_grid(c);
     LRT_HIP(c, timed(c, LRT_K_MARCH, st, [&] {
-                return launch_march(prec == LRT_FP32_COMP, rays, g, k_first, n_band, eta, kappa, escale,
-                                    I_out, c->w_partials.as<double>(), n_chunks, st);
+                return launch_march(prec == LRT_FP32_COMP, c->march_scheme == LRT_MARCH_LINEAR_J, rays, g,
+                                    k_first, n_band, eta, kappa, escale,
+                                    c->have_Tfar ? c->d_Tfar.as<double>() : nullptr, I_out,
+                                    c->w_partials.as<double>(), n_chunks, st);
             }));
     LRT_HIP(c, launch_reduce_rows(c->w_partials.as<double>(), (int32_t)c->n_rays, n_chunks, I_int_out, st));
     return LRT_OK;

@@ -169,10 +169,10 @@ hipError_t launch_count(const DevLines &L, const DevGrid &g, const CellConst *cc
                         int32_t n_species, int32_t k_first, int32_t n_band,
                         unsigned long long *count, hipStream_t st);
 
-hipError_t launch_march(bool fp32, const DevRays &rays, const DevGrid &g, int32_t k_first,
-                        int32_t n_band, const void *eta, const void *kappa,
-                        const int32_t *escale, double *I_out, double *partials,
-                        int32_t n_chunks, hipStream_t st);
+hipError_t launch_march(bool fp32, bool linear, const DevRays &rays, const DevGrid &g,
+                        int32_t k_first, int32_t n_band, const void *eta, const void *kappa,
+                        const int32_t *escale, const double *T_far, double *I_out,
+                        double *partials, int32_t n_chunks, hipStream_t st);
 
 hipError_t launch_reduce_rows(const double *partials, int32_t n_rows, int32_t n_cols,
                               double *out, hipStream_t st);

@@ -30,7 +30,8 @@ _vp = C.c_void_p
 
 EXPORTS = ["lrt_version", "lrt_status_string", "lrt_create", "lrt_destroy", "lrt_last_error",
            "lrt_set_species", "lrt_set_lines", "lrt_set_grid", "lrt_set_cells",
-           "lrt_set_rays_slab", "lrt_set_rays_axi", "lrt_trace_axi_ray", "lrt_get_sizes", "lrt_get_ray",
+           "lrt_set_rays_slab", "lrt_set_rays_axi", "lrt_set_rays_axi_fibonacci",
+           "lrt_fibonacci_quadrature", "lrt_set_march", "lrt_set_far_temperature", "lrt_trace_axi_ray", "lrt_get_sizes", "lrt_get_ray",
            "lrt_coeffs", "lrt_march", "lrt_solve", "lrt_count_terms", "lrt_profile",
            "lrt_profile_read", "lrt_server_start", "lrt_submit", "lrt_poll", "lrt_wait",
            "lrt_cancel", "lrt_server_info", "lrt_server_stop"]
@@ -97,6 +98,11 @@ def lib():
             "lrt_set_rays_slab": (st, [_vp, C.c_int64, _dp, C.c_int]),
             "lrt_set_rays_axi": (st, [_vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
                                       _dp, C.c_int, C.c_int]),
+            "lrt_set_rays_axi_fibonacci": (st, [_vp, C.c_int, C.c_int, C.c_double, C.c_double,
+                                                C.c_int, _dp, C.c_int, C.c_int, C.c_int]),
+            "lrt_fibonacci_quadrature": (st, [C.c_int, C.c_int, C.c_int, C.c_int64, _dp, _dp, _i64p]),
+            "lrt_set_march": (st, [_vp, C.c_int]),
+            "lrt_set_far_temperature": (st, [_vp, _dp, C.c_int64]),
             "lrt_trace_axi_ray": (st, [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_double, C.c_int64, _i32p, _dp, _i64p]),
             "lrt_get_sizes": (st, [_vp, _i64p, _i64p, _i64p, _i64p, _i64p, _i64p]),
@@ -205,6 +211,11 @@ class Context:
         if isinstance(geom, synth.SlabGeometry):
             dx = np.ascontiguousarray(geom.dx, np.float64)
             self._chk(self._L.lrt_set_rays_slab(self.h, dx.size, _p(dx), int(geom.n_mu)))
+        elif isinstance(geom, synth.AxiGeometry) and geom.fib_los > 0:
+            wr = np.ascontiguousarray(geom.wall_r, np.float64)
+            self._chk(self._L.lrt_set_rays_axi_fibonacci(
+                self.h, geom.nx, geom.nr, float(geom.Lx), float(geom.R), wr.size, _p(wr),
+                int(geom.fib_los), int(geom.fib_polar), int(geom.fib_azim)))
         elif isinstance(geom, synth.AxiGeometry):
             wr = np.ascontiguousarray(geom.wall_r, np.float64)
             self._chk(self._L.lrt_set_rays_axi(self.h, geom.nx, geom.nr, float(geom.Lx),
@@ -212,6 +223,17 @@ class Context:
                                                int(geom.n_phi)))
         else:
             raise TypeError("unknown geometry %r" % type(geom))
+
+    def set_march(self, scheme: int):
+        self._chk(self._L.lrt_set_march(self.h, int(scheme)))
+
+    def set_far_temperature(self, T_far):
+        """Scalar (every ray), per-ray array, or None (all free)."""
+        if T_far is None:
+            self._chk(self._L.lrt_set_far_temperature(self.h, None, 0))
+            return
+        t = np.ascontiguousarray(np.atleast_1d(np.asarray(T_far, np.float64)))
+        self._chk(self._L.lrt_set_far_temperature(self.h, _p(t), t.size))
 
     def load(self, wl):
         """Species, lines, grid, cells and rays of a synth.Workload."""
@@ -368,6 +390,22 @@ class Server:
             self.stop()
         except Exception:
             pass
+
+
+LRT_MARCH_CELL, LRT_MARCH_LINEAR_J = 0, 1
+
+
+def fibonacci_quadrature(n_los: int, n_polar: int, n_azim: int):
+    """Directions [m, 3] and flux weights [m] of the Fibonacci-LOS angular
+    rule (host only)."""
+    L = lib()
+    dirs = np.zeros((n_los, 3))
+    w = np.zeros(n_los)
+    n = C.c_int64()
+    s = L.lrt_fibonacci_quadrature(n_los, n_polar, n_azim, n_los, _p(dirs), _p(w), C.byref(n))
+    if s != 0:
+        raise LrtError(s, L.lrt_last_error(None).decode())
+    return dirs[:n.value].copy(), w[:n.value].copy()
 
 
 def trace_axi_ray(nx, nr, Lx, R, rw, mu, phi):

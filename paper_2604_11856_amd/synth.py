@@ -115,7 +115,10 @@ class SlabGeometry:
 class AxiGeometry:
     """Axisymmetric structured grid x in [0, Lx], r in [0, R], nx x nr uniform
     cells, cell index c = ix * nr + ir.  Wall is the plane x = 0, wall points at
-    radii wall_r; rays leave the wall into x > 0."""
+    radii wall_r; rays leave the wall into x > 0.  Directions: n_mu
+    Gauss-Legendre polar nodes x n_phi azimuths, or, when fib_los > 0, the
+    Fibonacci-sphere LOS set of fib_los directions with its (fib_polar x
+    fib_azim)-interval angular grid."""
     nx: int
     nr: int
     Lx: float
@@ -123,6 +126,9 @@ class AxiGeometry:
     wall_r: np.ndarray
     n_mu: int
     n_phi: int
+    fib_los: int = 0
+    fib_polar: int = 0
+    fib_azim: int = 0
 
 
 @dataclasses.dataclass

@@ -54,3 +54,15 @@ def test_trace_rejects_bad_arguments():
         lrt.trace_axi_ray(4, 4, 1.0, 1.0, 2.0, 0.5, 0.0)     # rw outside [0, R)
     with pytest.raises(lrt.LrtError):
         lrt.trace_axi_ray(4, 4, 1.0, 1.0, 0.5, 0.0, 0.0)     # mu = 0 never leaves the wall
+
+
+def test_fibonacci_rule_matches_oracle():
+    """The library's Fibonacci LOS directions and flux weights (host-only
+    entry point) equal the oracle's, written independently from the same
+    passage."""
+    for n, p, a in ((400, 20, 40), (100, 8, 16), (1600, 32, 64), (7, 3, 5), (61, 6, 12)):
+        d1, w1 = lrt.fibonacci_quadrature(n, p, a)
+        d0, w0 = O.fibonacci_quadrature(n, p, a)
+        assert d1.shape == d0.shape
+        np.testing.assert_allclose(d1, d0, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(w1, w0, rtol=1e-14, atol=0)

@@ -1,0 +1,159 @@
+"""Parity of the paper's march variants (Sec. 2.2.3) through the C ABI:
+the linear-j segment scheme over LOS nodes, a blackbody far boundary, and
+Fibonacci-sphere lines of sight with the interpolated angular rule.
+
+Bars as for the main path: LRT_FP64 within 1e-12 and LRT_FP32_COMP within
+1e-5 of the FP64 oracle, normwise per ray for spectra, relative for integrals
+and fluxes.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2604_11856_amd import lrt, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {lrt.LRT_FP64: 1e-12, lrt.LRT_FP32_COMP: 1e-5}
+PRECS = [lrt.LRT_FP64, lrt.LRT_FP32_COMP]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def normwise(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return float(np.max(np.max(np.abs(got - ref), axis=-1) / np.max(np.abs(ref), axis=-1)))
+
+
+def march_all(ctx, wl, prec, torch):
+    """eta/kappa and the march of every ray over the whole (single-band) grid."""
+    eta, kap, esc = ctx.coeffs_torch(0, prec)
+    s = ctx.sizes()
+    n = ctx.band_len(0)
+    I = torch.zeros((s["n_rays"], n), dtype=torch.float64, device="cuda:0")
+    Ii = torch.zeros(s["n_rays"], dtype=torch.float64, device="cuda:0")
+    ctx.march(0, prec, eta, kap, esc, I, Ii)
+    torch.cuda.synchronize()
+    return I.cpu().numpy(), Ii.cpu().numpy()
+
+
+@pytest.mark.parametrize("T_far", [0.0, 6500.0])
+def test_slab_linear_j_and_far_boundary(T_far, torch_dev):
+    """Slab with a wall-normal ray and 6 GL rays, both schemes, with a free or
+    a blackbody far boundary: I per ray and its spectral integral."""
+    torch = torch_dev
+    wl = synth.slab_equilibrium(n_cells=16, n_lines_per_species=300, n_points=30_011,
+                                band_points=30_011, n_mu=6, seed=21)
+    ks = np.arange(wl.grid.n_points)
+    eta, kap, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
+    rays, mu, W = O.slab_rays(wl.geometry)
+    I_far = O.planck_spectrum(wl.grid, ks, T_far) if T_far > 0 else None
+    wts = O.trapezoid_weights(wl.grid)
+    ctx = lrt.Context(0).load(wl)
+    if T_far > 0:
+        ctx.set_far_temperature(T_far)
+    for scheme, f in ((lrt.LRT_MARCH_CELL, O.march), (lrt.LRT_MARCH_LINEAR_J, O.march_linear)):
+        ref = np.stack([f(c, d, eta, kap, I_far) for c, d in rays])
+        ctx.set_march(scheme)
+        for prec in PRECS:
+            I, Ii = march_all(ctx, wl, prec, torch)
+            eI = normwise(I, ref)
+            eIi = float(np.max(np.abs(Ii - ref @ wts) / np.abs(ref @ wts)))
+            say("slab T_far %g scheme %d prec %d: I %.3e I_int %.3e" % (T_far, scheme, prec, eI, eIi))
+            assert eI <= TOL[prec] and eIi <= TOL[prec]
+    # the two schemes differ where j changes between cells
+    ctx.set_march(lrt.LRT_MARCH_CELL)
+    a = march_all(ctx, wl, lrt.LRT_FP64, torch)[1]
+    ctx.set_march(lrt.LRT_MARCH_LINEAR_J)
+    b = march_all(ctx, wl, lrt.LRT_FP64, torch)[1]
+    assert np.max(np.abs(a - b) / np.abs(a)) > 1e-6
+    ctx.close()
+
+
+def test_axi_fibonacci_both_schemes(torch_dev):
+    """Axisymmetric grid, Fibonacci LOS (every direction traced) and the
+    interpolated angular rule: q per wall point, both schemes, against the
+    oracle's own rays, weights and march."""
+    wl = synth.axisymmetric(nx=12, nr=6, n_atomic=1500, n_rovib=3000, n_points=8192,
+                            band_points=3000, n_wall=3, n_mu=3, n_phi=5)
+    g = wl.geometry
+    wl.geometry = synth.AxiGeometry(g.nx, g.nr, g.Lx, g.R, g.wall_r, 0, 0, fib_los=60,
+                                    fib_polar=6, fib_azim=12)
+    say("axi fibonacci: oracle")
+    eta, kap, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
+    wts = O.trapezoid_weights(wl.grid)
+    ctx = lrt.Context(0).load(wl)
+    assert ctx.sizes()["n_rays"] == 3 * 30
+    for scheme, f in ((lrt.LRT_MARCH_CELL, O.march), (lrt.LRT_MARCH_LINEAR_J, O.march_linear)):
+        qref = []
+        for w in range(3):
+            rays, wr = O.axi_rays_fibonacci(wl.geometry, w, 60, 6, 12)
+            qref.append(sum(wt * float(f(c, d, eta, kap) @ wts) for (c, d), wt in zip(rays, wr)))
+        ctx.set_march(scheme)
+        for prec in PRECS:
+            q, _, _ = ctx.solve(prec)
+            for w in range(3):
+                e = abs(q[w] - qref[w]) / abs(qref[w])
+                say("  fib scheme %d prec %d wall %d: q %.6e ref %.6e rel %.3e" % (scheme, prec, w, q[w], qref[w], e))
+                assert e <= TOL[prec]
+    ctx.close()
+
+
+def test_axi_gl_linear_j_with_far_wall(torch_dev):
+    """GL x azimuth rays (mirror azimuths traced once), linear-j scheme, a
+    per-ray far temperature: q per wall point against the oracle's plain sum
+    over every azimuth."""
+    wl = synth.axisymmetric(nx=10, nr=5, n_atomic=1200, n_rovib=2400, n_points=6000,
+                            band_points=6000, n_wall=2, n_mu=3, n_phi=4, seed=31)
+    ks = np.arange(wl.grid.n_points)
+    eta, kap, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
+    wts = O.trapezoid_weights(wl.grid)
+    T = 4000.0
+    B = O.planck_spectrum(wl.grid, ks, T)
+    ctx = lrt.Context(0).load(wl)
+    ctx.set_march(lrt.LRT_MARCH_LINEAR_J)
+    ctx.set_far_temperature(T)
+    qref = []
+    for w in range(2):
+        rays, wr = O.axi_rays(wl.geometry, w)
+        qref.append(sum(wt * float(O.march_linear(c, d, eta, kap, B) @ wts) for (c, d), wt in zip(rays, wr)))
+    for prec in PRECS:
+        q, _, _ = ctx.solve(prec)
+        for w in range(2):
+            e = abs(q[w] - qref[w]) / abs(qref[w])
+            say("  GL linear-j far wall prec %d wall %d: rel %.3e" % (prec, w, e))
+            assert e <= TOL[prec]
+    # back to free boundaries and the default scheme: the original result
+    ctx.set_far_temperature(None)
+    ctx.set_march(lrt.LRT_MARCH_CELL)
+    ref0 = O.solve_axi(wl, range(2))
+    q, _, _ = ctx.solve(lrt.LRT_FP64)
+    for w in range(2):
+        assert abs(q[w] - ref0["walls"][w]["q"]) <= 1e-12 * abs(ref0["walls"][w]["q"])
+    ctx.close()
+
+
+def test_march_variant_arguments(torch_dev):
+    wl = synth.slab_equilibrium(n_cells=4, n_lines_per_species=20, n_points=1000, seed=3)
+    ctx = lrt.Context(0)
+    with pytest.raises(lrt.LrtError) as e:
+        ctx.set_far_temperature(5000.0)          # no rays yet
+    assert e.value.status == 6
+    ctx.load(wl)
+    with pytest.raises(lrt.LrtError):
+        ctx.set_march(7)
+    with pytest.raises(lrt.LrtError):
+        ctx.set_far_temperature([1.0, 2.0, 3.0])  # neither 1 nor n_rays values
+    with pytest.raises(lrt.LrtError):
+        ctx.set_far_temperature(-1.0)
+    ctx.close()
