@@ -89,6 +89,11 @@ def workload(name):
     return wl, desc
 
 
+# Sources of the accumulation kernel; the committed counter summary records
+# their sha256 (in this order).
+ACCUM_SOURCES = ("lrt_accum.hip", "lrt_device.h", "lrt_internal.h")
+
+
 def counter_traffic(workload_name):
     """HBM bytes per accumulation launch from the committed counter summary, if
     it was taken on the stagnation workload with the current kernel sources;
@@ -105,7 +110,7 @@ def counter_traffic(workload_name):
             k, v = ln.split(":", 1)
             fields[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for f in ("lrt_kernels.hip", "lrt_internal.h"):
+    for f in ACCUM_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2604_11856_amd", "csrc", f), "rb").read())
     if fields.get("kernel_source_sha256") != h.hexdigest():
         return None
@@ -157,6 +162,35 @@ def serving(n_closed, n_open, budget_gb=64, slots=64):
                           "p99_latency_ms": float(np.percentile(lat, 99)),
                           "max_latency_ms": float(lat.max())},
             "epochs": info["epochs"]}
+
+
+def compare_march_schemes(ctx, lrt, torch, sz, reps=3):
+    """Band 0 in single precision: the march (a5 + a6) with the cell-constant
+    scheme and with the linear-j segment scheme over LOS nodes, on the same
+    eta/kappa; per-launch time from HIP events and the spread of I_int."""
+    eta, kap, esc = ctx.coeffs_torch(0, lrt.LRT_FP32_COMP)
+    Ii = torch.zeros(sz["n_rays"], dtype=torch.float64, device="cuda:0")
+    out = {}
+    res = {}
+    for name, scheme in (("cell", lrt.LRT_MARCH_CELL), ("linear_j", lrt.LRT_MARCH_LINEAR_J)):
+        ctx.set_march(scheme)
+        ctx.march(0, lrt.LRT_FP32_COMP, eta, kap, esc, None, Ii)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(reps):
+            ctx.march(0, lrt.LRT_FP32_COMP, eta, kap, esc, None, Ii)
+        torch.cuda.synchronize()
+        ms, n = ctx.profile_read("march")
+        ctx.profile(False)
+        out[name + "_ms_per_launch"] = ms / max(1, n)
+        res[name] = Ii.cpu().numpy().copy()
+    ctx.set_march(lrt.LRT_MARCH_CELL)
+    out["band"] = 0
+    out["I_int_rel_diff_linear_vs_cell_max"] = float(np.max(np.abs(res["linear_j"] - res["cell"]) /
+                                                           np.abs(res["cell"])))
+    del eta, kap, esc
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(wl, n_points):
@@ -220,6 +254,8 @@ def main():
                    "I_int_max": float(np.max(np.abs(I32 - I64) / np.maximum(np.abs(I64), 1e-300))),
                    "q": [float(abs(a - b) / abs(b)) if b != 0 else 0.0 for a, b in zip(q32, q64)]}}
 
+    march_schemes = compare_march_schemes(ctx, lrt, torch, sz)
+
     acc_ms, acc_n = prof32["accum"]
     acc_s = acc_ms / 1e3 / max(1, acc_n)
     terms_per_launch = n_terms / sz["n_bands"]
@@ -256,6 +292,7 @@ def main():
                      "core_fraction": n_core / max(1, n_terms),
                      "slots_per_eval": slots_per_launch / max(1.0, terms_per_launch),
                      "avg_launch_ms": acc_s * 1e3},
+        "march_schemes": march_schemes,
         "march_roofline": {"bound": "hbm", "kernel": "march_f32", "achieved": march_bytes / mar_s / 1e9,
                            "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                            "frac": march_bytes / mar_s / HBM_PEAK, "avg_launch_ms": mar_s * 1e3,

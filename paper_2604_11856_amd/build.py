@@ -25,9 +25,11 @@ def build_library(out: str = LIB) -> str:
     """Always recompiles (the caller decides when to build)."""
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    k_obj = os.path.join(bdir, "lrt_kernels.o")
-    objs = [k_obj]
-    _run([HIPCC, *ARCH, *COMMON, *NO_PK, "-c", os.path.join(CSRC, "lrt_kernels.hip"), "-o", k_obj])
+    objs = []
+    for name in ("lrt_accum", "lrt_march"):
+        obj = os.path.join(bdir, name + ".o")
+        _run([HIPCC, *ARCH, *COMMON, *NO_PK, "-c", os.path.join(CSRC, name + ".hip"), "-o", obj])
+        objs.append(obj)
     # host code: no FP contraction, so the two-sum / two-product grid offsets stay exact
     for name in ("lrt_host", "lrt_serve"):
         obj = os.path.join(bdir, name + ".o")

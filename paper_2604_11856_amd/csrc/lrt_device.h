@@ -1,0 +1,42 @@
+// Device helpers shared by the accumulation and march translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lrt {
+
+constexpr double kLog2e = 1.4426950408889634;
+// XCDs of the chip: workgroup ids go round-robin over them, each has its own L2.
+constexpr int kXCDs = 8;
+
+__device__ __forceinline__ int32_t uniform_i(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// F(t) = (1 - e^-t)/t from e = e^-t; Taylor for |t| < 0.1 avoids the
+// cancellation in 1 - e (relative error of the direct form ~ 6e-8 / |t|).
+static __device__ __forceinline__ float fexp_f32(float t, float e)
+{
+    const float poly = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, -1.0f / 720.0f, 1.0f / 120.0f),
+                                                   -1.0f / 24.0f), 1.0f / 6.0f), -0.5f), 1.0f);
+    const float direct = (1.0f - e) * __builtin_amdgcn_rcpf(t);
+    return fabsf(t) < 0.1f ? poly : direct;
+}
+
+// One cell-constant segment on scaled single-precision coefficients:
+// tau = kappa ds; returns e^-tau (as the attenuation factor) and the emitted
+// term eta ds F(tau) in double precision.  dsk = ds 2^esk (as float),
+// dse = ds 2^ese.
+static __device__ __forceinline__ void segment_f32(float eta_s, float kap_s, float dsk, double dse,
+                                            double &atten, double &emit)
+{
+    const float tau = kap_s * dsk;
+    const float e = __builtin_amdgcn_exp2f(tau * (float)(-kLog2e));
+    const float F = fexp_f32(tau, e);
+    atten = (double)e;
+    emit = (double)(eta_s * F) * dse;
+}
+
+}  // namespace lrt

@@ -1,5 +1,5 @@
 // Internal declarations shared by the host side (lrt_host.cpp) and the
-// gfx950 kernels (lrt_kernels.hip).  Not part of the public ABI.
+// gfx950 kernels (lrt_accum.hip, lrt_march.hip).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -140,7 +140,7 @@ struct ServeItem {
     int32_t req, tile, chunk;
 };
 
-// ---- kernel launchers (lrt_kernels.hip) ----
+// ---- kernel launchers (lrt_accum.hip, lrt_march.hip) ----
 hipError_t launch_thermo(const DevSpecies &sp, const DevCells &cells, double M_min,
                          uint64_t species_mask, CellConst *cc, CellSpecies *cs, hipStream_t st);
 

@@ -1,0 +1,319 @@
+// gfx950 kernels of the ray march (arXiv 2604.11856, Sec. 2.2.3): per (ray,
+// spectral chunk) the RTE march far -> target with the spectral trapezoid
+// fused in, in the cell-constant or the linear-j segment scheme, and the
+// deterministic sums of per-block partials and of ray fluxes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "lrt_device.h"
+#include "lrt_internal.h"
+
+namespace lrt {
+
+namespace {
+
+// Weights per unit length of the two nodes of a linear-j segment (Sec. 2.2.3:
+// kappa from the far node, j linear between the nodes) at optical thickness
+// t with e = e^-t: W_near = (1 - f)/t, W_far = (f - e)/t, f = (1 - e)/t, which
+// integrate the transfer equation over the segment.  (The pairing follows the
+// scheme's derivation; as t grows only the node next to the target counts.)
+// For |t| < 0.1 both differences cancel; there the weights come from their
+// Taylor series, W_near = sum (-t)^n/(n+2)!, W_far = sum (-1)^n (n+1) t^n/(n+2)!,
+// whose first omitted terms are below 3e-11.
+__device__ __forceinline__ void linear_j_weights_f32(float t, float e, float &wf, float &wn)
+{
+    const float sn = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, -1.0f / 5040.0f, 1.0f / 720.0f),
+                                                   -1.0f / 120.0f), 1.0f / 24.0f), -1.0f / 6.0f), 0.5f);
+    const float sf = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, -1.0f / 840.0f, 1.0f / 144.0f),
+                                                   -1.0f / 30.0f), 1.0f / 8.0f), -1.0f / 3.0f), 0.5f);
+    const float r = __builtin_amdgcn_rcpf(t);
+    const float f = (1.0f - e) * r;
+    const bool thin = fabsf(t) < 0.1f;
+    wn = thin ? sn : (1.0f - f) * r;
+    wf = thin ? sf : (f - e) * r;
+}
+
+__device__ __forceinline__ void linear_j_weights_f64(double t, double &e, double &wf, double &wn)
+{
+    e = exp(-t);
+    if (fabs(t) >= 0.05) {
+        const double f = -expm1(-t) / t;
+        wn = (1.0 - f) / t;
+        wf = (f - e) / t;
+        return;
+    }
+    // Horner over n = 17..0 of c_n t^n with c_n = (-1)^n/(n+2)! and (n+1) c_n
+    double inv_fact[18];
+    double fct = 2.0;
+    for (int n = 0; n < 18; ++n) {
+        inv_fact[n] = 1.0 / fct;
+        fct *= (double)(n + 3);
+    }
+    double a = 0.0, b = 0.0;
+    for (int n = 17; n >= 0; --n) {
+        const double c = (n & 1) ? -inv_fact[n] : inv_fact[n];
+        a = fma(a, t, c);
+        b = fma(b, t, (double)(n + 1) * c);
+    }
+    wn = a;
+    wf = b;
+}
+
+// Blackbody intensity B(nu, T) in W cm^-2 sr^-1 per cm^-1 (CGS x 1e-7).
+__device__ __forceinline__ double planck_f64(double nu, double T)
+{
+    return 1e-7 * 2.0 * kPlanck * kLight * kLight * nu * nu * nu / expm1(kC2 * nu / T);
+}
+
+// One row (kMarchPPT consecutive points of a cell) of eta and kappa.
+template <typename T>
+__device__ __forceinline__ void load_row(const T *eta, const T *kap, int64_t row, int32_t kb,
+                                         int32_t n_band, bool vec, T (&ev)[kMarchPPT],
+                                         T (&kv)[kMarchPPT])
+{
+    if constexpr (sizeof(T) == 4) {
+        if (vec) {
+            // one load of kMarchPPT consecutive floats per array
+            if constexpr (kMarchPPT == 4) {
+                const float4 a = *(const float4 *)(eta + row);
+                const float4 b = *(const float4 *)(kap + row);
+                ev[0] = a.x; ev[1] = a.y; ev[2] = a.z; ev[3] = a.w;
+                kv[0] = b.x; kv[1] = b.y; kv[2] = b.z; kv[3] = b.w;
+                return;
+            } else if constexpr (kMarchPPT == 2) {
+                const float2 a = *(const float2 *)(eta + row);
+                const float2 b = *(const float2 *)(kap + row);
+                ev[0] = a.x; ev[1] = a.y;
+                kv[0] = b.x; kv[1] = b.y;
+                return;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kMarchPPT; ++j) {
+        const bool ok = kb + j < n_band;
+        ev[j] = ok ? eta[row + j] : (T)0;
+        kv[j] = ok ? kap[row + j] : (T)0;
+    }
+}
+
+// March of one (ray, chunk of kMarchPoints points), far -> target.
+//   LINEAR = false: cell-constant segments, I <- I e^-tau + eta ds F(tau).
+//   LINEAR = true: linear-j segments between LOS nodes at the far end of the
+//     ray, the midpoint of every cell segment and the target; a node takes its
+//     cell's state, so the node spacings are ds_0/2, (ds_m-1 + ds_m)/2, ...,
+//     ds_M-1/2, and each segment uses the far node's kappa.
+// T_far (NULL: all free) gives per ray the temperature of a solid far
+// boundary (0: free), whose blackbody intensity starts the march.
+template <bool FP32, bool LINEAR>
+__global__ __launch_bounds__(kMarchThreads) void march_kernel(
+    DevRays rays, DevGrid g, int32_t k_first, int32_t n_band, const void *eta_v,
+    const void *kappa_v, const int32_t *escale, const double *T_far, double *I_out,
+    double *partials, int32_t n_chunks, int32_t aligned16)
+{
+    // Workgroups go round-robin to the 8 XCDs, each with its own L2: give XCD
+    // x a contiguous range of rays, since rays of one wall point share their
+    // cells near the wall (12 % faster than ray = blockIdx.x on 8192
+    // axisymmetric rays).  A bijection of [0, n_rays) for any n_rays.
+    int ray;
+    {
+        const int n = gridDim.x, x = blockIdx.x % kXCDs, i = blockIdx.x / kXCDs;
+        const int per = n / kXCDs, rem = n % kXCDs;
+        ray = x * per + min(x, rem) + i;
+    }
+    const int chunk = blockIdx.y;
+    const int32_t kb = chunk * kMarchPoints + threadIdx.x * kMarchPPT;   // band-relative
+    const int64_t m0 = rays.off[ray], m1 = rays.off[ray + 1];
+    double I[kMarchPPT];
+    const double Tw = T_far ? T_far[ray] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kMarchPPT; ++j) {
+        I[j] = 0.0;
+        if (Tw > 0.0 && kb + j < n_band) I[j] = planck_f64(g.nu_min + (double)(k_first + kb + j) * g.h, Tw);
+    }
+    // vector loads only when every row start is aligned to kMarchPPT floats
+    // (16-byte aligned bases, n_band a multiple of kMarchPPT) and the
+    // thread's points are all inside the band
+    const bool vec = aligned16 && (kb + kMarchPPT <= n_band) && (n_band % kMarchPPT) == 0;
+    using T = std::conditional_t<FP32, float, double>;
+    const T *eta = (const T *)eta_v;
+    const T *kap = (const T *)kappa_v;
+
+    if constexpr (!LINEAR) {
+        for (int64_t m = m0; m < m1; ++m) {
+            const int32_t c = rays.cell[m];
+            const double ds = rays.ds[m];
+            const int64_t row = (int64_t)c * n_band + kb;
+            T ev[kMarchPPT], kv[kMarchPPT];
+            load_row<T>(eta, kap, row, kb, n_band, vec, ev, kv);
+            if constexpr (FP32) {
+                const double dse = ldexp(ds, escale[2 * c + 0]);
+                const float dsk = (float)fmin(ldexp(ds, escale[2 * c + 1]), 3.0e38);
+#pragma unroll
+                for (int j = 0; j < kMarchPPT; ++j) {
+                    double at, em;
+                    segment_f32(ev[j], kv[j], dsk, dse, at, em);
+                    I[j] = fma(I[j], at, em);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < kMarchPPT; ++j) {
+                    if (kb + j < n_band) {
+                        const double tau = kv[j] * ds;
+                        const double em = expm1(-tau);
+                        const double F = (tau == 0.0) ? 1.0 : -em / tau;
+                        I[j] = I[j] * (1.0 + em) + ev[j] * ds * F;
+                    }
+                }
+            }
+        }
+    } else {
+        // previous node (the far node of the next segment)
+        T pe[kMarchPPT], pk[kMarchPPT];
+        int32_t pee = 0, pek = 0;
+        double pds = 0.0;
+        // one linear-j segment of length L from node (fe, fk) to node (ne_)
+        auto segment = [&](const T (&fe)[kMarchPPT], const T (&fk)[kMarchPPT], int32_t fee,
+                           int32_t fek, const T (&ne_)[kMarchPPT], int32_t nee, double L) {
+            if constexpr (FP32) {
+                const double Lf = ldexp(L, fee), Ln = ldexp(L, nee);
+                const float Lk = (float)fmin(ldexp(L, fek), 3.0e38);
+#pragma unroll
+                for (int j = 0; j < kMarchPPT; ++j) {
+                    const float t = fk[j] * Lk;
+                    const float e = __builtin_amdgcn_exp2f(t * (float)(-kLog2e));
+                    float wf, wn;
+                    linear_j_weights_f32(t, e, wf, wn);
+                    I[j] = fma(I[j], (double)e, (double)(wf * fe[j]) * Lf + (double)(wn * ne_[j]) * Ln);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < kMarchPPT; ++j) {
+                    if (kb + j < n_band) {
+                        double e, wf, wn;
+                        linear_j_weights_f64(fk[j] * L, e, wf, wn);
+                        I[j] = I[j] * e + L * (wf * fe[j] + wn * ne_[j]);
+                    }
+                }
+            }
+        };
+        for (int64_t m = m0; m < m1; ++m) {
+            const int32_t c = rays.cell[m];
+            const double ds = rays.ds[m];
+            T ev[kMarchPPT], kv[kMarchPPT];
+            load_row<T>(eta, kap, (int64_t)c * n_band + kb, kb, n_band, vec, ev, kv);
+            const int32_t ee = FP32 ? escale[2 * c + 0] : 0, ek = FP32 ? escale[2 * c + 1] : 0;
+            if (m == m0)
+                segment(ev, kv, ee, ek, ev, ee, 0.5 * ds);             // far end -> first midpoint
+            else
+                segment(pe, pk, pee, pek, ev, ee, 0.5 * (pds + ds));   // midpoint -> midpoint
+#pragma unroll
+            for (int j = 0; j < kMarchPPT; ++j) {
+                pe[j] = ev[j];
+                pk[j] = kv[j];
+            }
+            pee = ee;
+            pek = ek;
+            pds = ds;
+        }
+        if (m1 > m0) segment(pe, pk, pee, pek, pe, pee, 0.5 * pds);     // last midpoint -> target
+    }
+    // outputs: I and the trapezoid partial with global-index weights
+    double part = 0.0;
+#pragma unroll
+    for (int j = 0; j < kMarchPPT; ++j) {
+        const int32_t kl = kb + j;
+        if (kl < n_band) {
+            const int32_t kg = k_first + kl;
+            const double w = (kg == 0 || kg == g.n_points - 1) ? 0.5 * g.h : g.h;
+            part += w * I[j];
+            if (I_out) I_out[(int64_t)ray * n_band + kl] = I[j];
+        }
+    }
+    // block sum in a fixed order: waves reduce by xor-shuffles, then wave 0
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    __shared__ double wsum[kMarchThreads / 64];
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kMarchThreads / 64; ++w) s += wsum[w];
+        partials[(int64_t)ray * n_chunks + chunk] = s;
+    }
+}
+
+__global__ void reduce_rows_kernel(const double *p, int32_t n_rows, int32_t n_cols, double *out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    double s = 0.0;
+    for (int j = 0; j < n_cols; ++j) s += p[(int64_t)r * n_cols + j];
+    out[r] = s;
+}
+
+__global__ void wall_sum_kernel(const double *I_int, const double *weight, const int64_t *wall_off,
+                                int32_t n_wall, double *q)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n_wall) return;
+    double s = 0.0;
+    for (int64_t r = wall_off[w]; r < wall_off[w + 1]; ++r) s += weight[r] * I_int[r];
+    q[w] = s;
+}
+
+__global__ void add_kernel(double *acc, const double *x, int32_t n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) acc[t] += x[t];
+}
+
+}  // namespace
+
+hipError_t launch_march(bool fp32, bool linear, const DevRays &rays, const DevGrid &g,
+                        int32_t k_first, int32_t n_band, const void *eta, const void *kappa,
+                        const int32_t *escale, const double *T_far, double *I_out,
+                        double *partials, int32_t n_chunks, hipStream_t st)
+{
+    if (rays.n_rays == 0) return hipSuccess;
+    dim3 grid(rays.n_rays, n_chunks);
+    const int32_t al = ((((uintptr_t)eta) | ((uintptr_t)kappa)) & 15) == 0;
+#define LRT_MARCH(F, LIN)                                                                          \
+    hipLaunchKernelGGL((march_kernel<F, LIN>), grid, dim3(kMarchThreads), 0, st, rays, g, k_first, \
+                       n_band, eta, kappa, escale, T_far, I_out, partials, n_chunks, al)
+    if (fp32) {
+        if (linear) LRT_MARCH(true, true); else LRT_MARCH(true, false);
+    } else {
+        if (linear) LRT_MARCH(false, true); else LRT_MARCH(false, false);
+    }
+#undef LRT_MARCH
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_rows(const double *partials, int32_t n_rows, int32_t n_cols, double *out,
+                              hipStream_t st)
+{
+    if (n_rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(n_rows, 64)), dim3(64), 0, st, partials,
+                       n_rows, n_cols, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_sum(const double *I_int, const double *weight, const int64_t *wall_off,
+                           int32_t n_wall, double *q, hipStream_t st)
+{
+    if (n_wall == 0) return hipSuccess;
+    hipLaunchKernelGGL(wall_sum_kernel, dim3(blocks_for(n_wall, 64)), dim3(64), 0, st, I_int,
+                       weight, wall_off, n_wall, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(double *acc, const double *x, int32_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(add_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, acc, x, n);
+    return hipGetLastError();
+}
+
+}  // namespace lrt
