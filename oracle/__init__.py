@@ -52,6 +52,11 @@ class _Lines(C.Structure):
                 ("El_ev", _dp), ("El_rot", _dp), ("gu", _dp), ("gl", _dp), ("species", _i32p)]
 
 
+class _Cont(C.Structure):
+    _fields_ = [("species", C.c_int), ("ion", C.c_int), ("E_ion", C.c_double),
+                ("Q_ion", C.c_double), ("sigma0", _dp), ("peach", _dp), ("z", C.c_double)]
+
+
 class _Cells(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_species", C.c_int), ("T_tr", _dp), ("T_v", _dp),
                 ("N", _dp), ("n_e", _dp)]
@@ -92,6 +97,10 @@ def lib():
                                              C.POINTER(_Cells), d, d, i64, _dp, _dp]),
             "orc_march": (None, [i64, _i64p, _dp, i64, _dp, _dp, _dp, _dp]),
             "orc_linear_j_weights": (None, [d, _dp, _dp]),
+            "orc_saha_volume": (d, [d]),
+            "orc_peach_ff": (d, [_dp, d, d, d]),
+            "orc_continuum": (None, [C.POINTER(_Species), C.POINTER(_Cells), C.c_int,
+                                     C.POINTER(_Cont), d, d, i64, _i64p, _dp, _dp]),
             "orc_march_nodes": (None, [i64, _i64p, _dp, i64, _dp, _dp, _dp, _dp]),
             "orc_axi_segments": (i64, [C.c_int, C.c_int, d, d, d, d, d, i64, _i64p, _dp]),
             "orc_knife_edges": (None, [C.POINTER(_Species), C.POINTER(_Lines), C.POINTER(_Cells),
@@ -280,6 +289,35 @@ def knife_edges(species, lines, cells, grid, tol: float = 1e-9, near=None):
     sel = np.concatenate([np.arange(c * cap, c * cap + cnt[c]) for c in range(cells.n)]) \
         if cells.n else np.zeros(0, np.int64)
     return cc[sel].copy(), kk[sel].copy()
+
+
+def saha_volume(T: float) -> float:
+    return lib().orc_saha_volume(float(T))
+
+
+def peach_ff(c, z: float, s: float, T: float) -> float:
+    c = np.ascontiguousarray(c, np.float64)
+    return lib().orc_peach_ff(_p(c), float(z), float(s), float(T))
+
+
+def continuum(species, cells, grid, cont, ks: Optional[np.ndarray] = None):
+    """Atomic continuum (Sec. 2.2.1 bound-free and free-free) eta and kappa
+    [n_cells, n_k] at grid points ks (default: all)."""
+    if ks is None:
+        ks = np.arange(grid.n_points, dtype=np.int64)
+    ks = np.ascontiguousarray(ks, np.int64)
+    st, ct = SpeciesTable(species), CellTable(cells)
+    keep = [(np.ascontiguousarray(r.sigma0, np.float64), np.ascontiguousarray(r.peach, np.float64))
+            for r in cont]
+    arr = (_Cont * max(1, len(cont)))()
+    for j, (r, (s0, pc)) in enumerate(zip(cont, keep)):
+        arr[j] = _Cont(int(r.species), int(r.ion), float(r.E_ion), float(r.Q_ion), _p(s0), _p(pc),
+                       float(r.z))
+    eta = np.zeros((cells.n, ks.size))
+    kap = np.zeros((cells.n, ks.size))
+    lib().orc_continuum(C.byref(st.s), C.byref(ct.s), len(cont), arr, float(grid.nu_min),
+                        grid_step(grid), ks.size, _p(ks, _i64p), _p(eta), _p(kap))
+    return eta, kap
 
 
 def coeffs_bruteforce(species, lines, cells, grid):

@@ -386,6 +386,86 @@ void orc_march(int64_t n_seg, const int64_t *cell, const double *ds,
     }
 }
 
+/* ---------------------------------------------------------------------- */
+/* Sec. 2.2.1 atomic continuum: bound-free and free-free                    */
+/* ---------------------------------------------------------------------- */
+
+#define ORC_ME 9.1093837015e-28   /* electron mass, g */
+
+/* Saha-Boltzmann volume (h^2 / (2 pi m_e k T))^{3/2}, cm^3: the printed
+ * factor with its SI-to-CGS conversions (1e6, 1e-3) carried out. */
+double orc_saha_volume(double T)
+{
+    return pow(ORC_H * ORC_H / (2.0 * ORC_PI * ORC_ME * ORC_KB * T), 1.5);
+}
+
+/* Hydrogenic free-free cross section per (ion, electron) pair, cm^5, from
+ * the fit z^4 s^3 sigma 1e40 = A1(T)/s + A2(T), A1 = c1 + c2 e^{-c3 T},
+ * A2 = c4 + c5 e^{-c6 T} + c7 e^{-c8 T}, with s = lambda_H / lambda the
+ * dimensionless wavelength parameter (lambda_H = 91.1267 nm). */
+double orc_peach_ff(const double *c, double z, double s, double T)
+{
+    double A1 = c[0] + c[1] * exp(-c[2] * T);
+    double A2 = c[3] + c[4] * exp(-c[5] * T) + c[6] * exp(-c[7] * T);
+    return (A1 / s + A2) * 1e-40 / (z * z * z * z * s * s * s);
+}
+
+typedef struct {
+    int species, ion;
+    double E_ion, Q_ion;
+    const double *sigma0;   /* [levels of the atom] */
+    const double *peach;    /* c1..c8 */
+    double z;
+} orc_cont;
+
+/* Continuum eta and kappa of every cell at grid points ks (added to eta /
+ * kappa [n_cells][n_k]).  Per atom a with ion +: T = T_ee = T_v;
+ *   bound-free from level i (threshold nu_i = E_ion - E_i, nu >= nu_i):
+ *     kappa = N_i sigma_i(nu), N_i = N_a g_i e^{-c2 E_i/T} / Q_a,
+ *     eta = B(nu, T) sigma_i(nu) N_+ n_e V(T) g_i e^{c2 (E_ion - E_i)/T} / (2 Q_+)
+ *     (the LTE population per ion-electron pair in Kirchhoff's law), with the
+ *     synthetic hydrogenic shape sigma_i(nu) = sigma0_i (nu_i / nu)^3;
+ *   free-free: kappa = N_+ n_e sigma_H(s, T) (1 + D), D = 0 (the normalization
+ *     table is not available), eta = B(nu, T) kappa. */
+void orc_continuum(const orc_species *sp, const orc_cells *C, int n_cont, const orc_cont *cont,
+                   double nu_min, double h, int64_t n_k, const int64_t *ks, double *eta, double *kappa)
+{
+    const double c2 = orc_c2();
+    const double nu_H = 1e7 / 91.1267;
+    for (int64_t c = 0; c < C->n_cells; ++c) {
+        double T = C->T_v[c];
+        for (int r = 0; r < n_cont; ++r) {
+            const orc_cont *q = &cont[r];
+            int a = q->species;
+            double Na = C->N[c * C->n_species + a];
+            double Np = C->N[c * C->n_species + q->ion];
+            double ne = C->n_e[c];
+            double Qa = orc_partition(sp, a, C->T_v[c], C->T_tr[c]);
+            for (int64_t t = 0; t < n_k; ++t) {
+                double nu = nu_min + (double)ks[t] * h;
+                double B = orc_planck(nu, T);
+                double kap = 0.0, em = 0.0;
+                for (int64_t i = sp->lev_off[a]; i < sp->lev_off[a + 1]; ++i) {
+                    int64_t li = i - sp->lev_off[a];
+                    double Ei = sp->lev_E[i], gi = sp->lev_g[i];
+                    double nui = q->E_ion - Ei;
+                    if (q->sigma0[li] == 0.0 || !(nui > 0.0) || nu < nui) continue;
+                    double sig = q->sigma0[li] * pow(nui / nu, 3.0);
+                    double Ni = (Qa > 0.0) ? Na * gi * exp(-c2 * Ei / T) / Qa : 0.0;
+                    kap += Ni * sig;
+                    em += B * sig * Np * ne * orc_saha_volume(T) * gi * exp(c2 * (q->E_ion - Ei) / T)
+                          / (2.0 * q->Q_ion);
+                }
+                double ff = Np * ne * orc_peach_ff(q->peach, q->z, nu / nu_H, T);
+                kap += ff;
+                em += B * ff;
+                kappa[c * n_k + t] += kap;
+                eta[c * n_k + t] += em;
+            }
+        }
+    }
+}
+
 /* Sec. 2.2.3, Johnston-Mazaheri segment with linear j: over [s_i, s_{i+1}]
  * kappa is the far node's value and j varies linearly.  Integrating the
  * transfer equation over the segment (the derivation printed with the scheme)

@@ -132,6 +132,23 @@ class AxiGeometry:
 
 
 @dataclasses.dataclass
+class Continuum:
+    """Atomic continuum data of one atom: bound-free absorption from each of
+    its levels into the ground state of its singly charged ion, and free-free
+    absorption of electrons in the field of that ion.
+    sigma0[i]: photoionization cross section of level i at its threshold
+    (E_ion - E_i), cm^2 (0: no bound-free from that level); peach: c1..c8 of
+    the hydrogenic free-free fit, cm^5 (all 0: no free-free); z: ion charge."""
+    species: int
+    ion: int
+    E_ion: float
+    Q_ion: float
+    sigma0: np.ndarray
+    peach: np.ndarray
+    z: float = 1.0
+
+
+@dataclasses.dataclass
 class Workload:
     name: str
     species: List[Species]
@@ -140,6 +157,7 @@ class Workload:
     grid: Grid
     geometry: object
     meta: Dict = dataclasses.field(default_factory=dict)
+    continuum: Optional[List[Continuum]] = None
 
 
 # --------------------------------------------------------------------------
@@ -158,6 +176,39 @@ def atom_species(rng, name: str, n_levels: int = 20) -> Species:
     E[1:] = np.sort(rng.uniform(0.1, 14.0, n_levels - 1)) * EV_CM
     g = rng.integers(2, 13, n_levels).astype(np.float64)
     return Species(name, KIND_ATOM, AIR11_MASS.get(name, 14.0), level_E=E, level_g=g)
+
+
+# Ionization energies of the ground states (cm^-1) and the ground-term
+# degeneracies of the singly charged ions, used as their partition functions.
+ION_ENERGY_CM = {"N": 117225.7, "O": 109837.02}
+ION_Q = {"N+": 9.0, "O+": 4.0}
+# Coefficients c1..c8 (cm^5) of the hydrogenic free-free fit for N and O, as
+# printed in the paper's table of fitting parameters.
+PEACH_FF = {"N": [0.006805, -0.00934, 0.000116, 0.508, 1.046, 5.77e-5, 1.85, 0.000343],
+            "O": [0.001905, -0.005105, 8.176e-5, 0.4554, 1.0238, 5.329e-5, 1.7587, 0.003121]}
+
+
+def air_continuum(species: List[Species], seed: int = 11862) -> List[Continuum]:
+    """Continuum records of the radiating atoms N and O of a species list that
+    also holds their ions N+ and O+ (found by name).  The photoionization cross
+    sections are synthetic (the level-resolved data are not available):
+    sigma0 ~ logU(1e-19, 1e-17) cm^2 per level, 0 for levels at or above the
+    ionization energy."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    names = [sp.name for sp in species]
+    out = []
+    for atom in ("N", "O"):
+        if atom not in names or atom + "+" not in names:
+            continue
+        a = names.index(atom)
+        sp = species[a]
+        if sp.kind != KIND_ATOM:
+            continue
+        s0 = 10.0 ** rng.uniform(-19.0, -17.0, sp.level_E.size)
+        s0[sp.level_E >= ION_ENERGY_CM[atom]] = 0.0
+        out.append(Continuum(a, names.index(atom + "+"), ION_ENERGY_CM[atom], ION_Q[atom + "+"],
+                             s0, np.array(PEACH_FF[atom], np.float64), 1.0))
+    return out
 
 
 def none_species(name: str) -> Species:

@@ -679,3 +679,156 @@ def test_fibonacci_quadrature_flux_integrals():
         e2 = abs(float(w @ d[:, 0] ** 2) - math.pi / 2) / (math.pi / 2)
         errs.append(max(e1, e2))
     assert errs[-1] < 0.02 and errs[-1] < errs[0]
+
+
+# ----------------------------------------------------------------------------
+# Atomic continuum (Sec. 2.2.1 bound-free and free-free)
+# ----------------------------------------------------------------------------
+
+ME = 9.1093837015e-28
+
+
+def test_saha_volume_textbook_constant():
+    """(2 pi m_e k T / h^2)^{3/2} = 2.4147e15 T^{3/2} cm^-3, the Saha constant
+    of the textbooks; the oracle's volume is its inverse."""
+    for T in (500.0, 1e4, 3e4):
+        assert abs(O.saha_volume(T) * 2.4147e15 * T**1.5 - 1.0) < 1e-4
+
+
+def test_peach_free_free_against_kramers():
+    """The hydrogenic free-free fit (z = 1) stays within a factor of two of
+    Kramers' semi-classical cross section 3.692e8 z^2 T^{-1/2} nu_Hz^{-3} cm^5
+    (Gaunt factor 1) for both atoms over the wavelength and temperature
+    ranges of the workloads."""
+    nu_H = 1e7 / 91.1267
+    for atom in ("N", "O"):
+        c = synth.PEACH_FF[atom]
+        for T in (5000.0, 1e4, 2e4, 3e4):
+            for s in (0.03, 0.1, 0.3, 0.9):
+                nu_hz = s * nu_H * CL
+                kram = 3.692e8 / math.sqrt(T) / nu_hz**3
+                ratio = O.peach_ff(c, 1.0, s, T) / kram
+                assert 0.5 < ratio < 2.0, (atom, T, s, ratio)
+        # z^4 s^3 scaling of the fit
+        a = O.peach_ff(c, 1.0, 0.2, 1e4)
+        assert abs(O.peach_ff(c, 2.0, 0.2, 1e4) * 16.0 / a - 1.0) < 1e-14
+
+
+def _continuum_case(T, Np_ne_factor=1.0):
+    """One cell of N atoms and N+ ions with the level table of a synthetic atom;
+    Np_ne_factor scales N+ n_e away from its Saha equilibrium value."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    sp = [synth.atom_species(rng, "N"), synth.none_species("N+"), synth.none_species("e-")]
+    Na = 1e16
+    Qa = O.partition(sp, 0, T, T)
+    E_ion, Qp = synth.ION_ENERGY_CM["N"], synth.ION_Q["N+"]
+    # Saha: N+ n_e / N_a = 2 Q+ / Q_a e^{-c2 E_ion/T} / V(T)
+    NpNe = Na * 2.0 * Qp / Qa * math.exp(-O.c2() * E_ion / T) / O.saha_volume(T) * Np_ne_factor
+    ne = math.sqrt(NpNe)
+    cells = synth.Cells(np.array([T]), np.array([T]), np.array([[Na, ne, ne]]), np.array([ne]))
+    s0 = np.full(sp[0].level_E.size, 3e-18)
+    cont = [synth.Continuum(0, 1, E_ion, Qp, s0, np.array(synth.PEACH_FF["N"]), 1.0)]
+    grid = synth.Grid(2000.0, 120000.0, 4001, 4001)
+    return sp, cells, grid, cont
+
+
+def test_continuum_kirchhoff_in_lte():
+    """With N+ n_e at its Saha value for the cell's T, bound-free emission from
+    the Saha-Boltzmann populations equals B(nu, T) times the absorption of the
+    Boltzmann populations, level by level, so eta = B kappa at every point;
+    away from equilibrium it does not."""
+    for T in (6000.0, 12000.0):
+        sp, cells, grid, cont = _continuum_case(T)
+        ks = np.arange(0, 4001, 7)
+        eta, kap = O.continuum(sp, cells, grid, cont, ks)
+        B = O.planck_spectrum(grid, ks, T)
+        np.testing.assert_allclose(eta[0], B * kap[0], rtol=1e-12, atol=0)
+        sp, cells, grid, cont = _continuum_case(T, 3.0)
+        eta, kap = O.continuum(sp, cells, grid, cont, ks)
+        assert np.max(np.abs(eta[0] / (B * kap[0]) - 1.0)) > 0.5
+
+
+def test_continuum_thresholds_and_cube_law():
+    """kappa jumps by N_i sigma0_i at each level's threshold E_ion - E_i and
+    falls as nu^-3 between thresholds (with free-free removed: n_e -> the
+    bound-free part scales as the atom density only)."""
+    T = 9000.0
+    sp, cells, grid, cont = _continuum_case(T)
+    cont[0].peach = np.zeros(8)
+    E = sp[0].level_E
+    g = sp[0].level_g
+    Qa = O.partition(sp, 0, T, T)
+    h = (grid.nu_max - grid.nu_min) / (grid.n_points - 1)
+    thr = cont[0].E_ion - E
+    # the ground-level threshold lies beyond the grid; pick the first excited one inside it
+    i = int(np.argmax((thr > grid.nu_min + 10 * h) & (thr < grid.nu_max - 10 * h)))
+    k_thr = int(math.ceil((thr[i] - grid.nu_min) / h))
+    ks = np.array([k_thr - 1, k_thr])
+    _, kap = O.continuum(sp, cells, grid, cont, ks)
+    Ni = cells.N[0, 0] * g[i] * math.exp(-O.c2() * E[i] / T) / Qa
+    nu1 = grid.nu_min + k_thr * h
+    jump = kap[0, 1] - kap[0, 0] * ((grid.nu_min + (k_thr - 1) * h) / nu1) ** 3
+    assert abs(jump - Ni * 3e-18 * (thr[i] / nu1) ** 3) <= 1e-9 * jump
+    # between thresholds: nu^-3
+    others = np.sort(thr[(thr > grid.nu_min) & (thr < grid.nu_max)])
+    lo_k = int(math.ceil((others[-1] - grid.nu_min) / h)) + 1
+    ks = np.array([lo_k, lo_k + 5])
+    _, kap = O.continuum(sp, cells, grid, cont, ks)
+    nu = grid.nu_min + ks * h
+    assert abs(kap[0, 1] / kap[0, 0] - (nu[0] / nu[1]) ** 3) < 1e-13
+
+
+def test_free_free_scales_with_ion_electron_pairs():
+    """Free-free kappa is linear in N+ n_e and vanishes without electrons; its
+    emission is B kappa."""
+    T = 15000.0
+    sp, cells, grid, cont = _continuum_case(T)
+    cont[0].sigma0 = np.zeros_like(cont[0].sigma0)
+    ks = np.arange(0, 4001, 400)
+    e1, k1 = O.continuum(sp, cells, grid, cont, ks)
+    c2 = synth.Cells(cells.T_tr, cells.T_v, cells.N * np.array([1.0, 2.0, 1.0]), cells.n_e * 3.0)
+    e2, k2 = O.continuum(sp, c2, grid, cont, ks)
+    np.testing.assert_allclose(k2, 6.0 * k1, rtol=1e-14)
+    np.testing.assert_allclose(e1, O.planck_spectrum(grid, ks, T) * k1, rtol=1e-13)
+    c0 = synth.Cells(cells.T_tr, cells.T_v, cells.N, np.zeros(1))
+    _, k0 = O.continuum(sp, c0, grid, cont, ks)
+    assert np.all(k0 == 0.0)
+
+
+def test_peach_fit_limits_and_decay_rates():
+    """Structure of the free-free fit against the paper's table: at T -> inf
+    the exponentials vanish, 1e40 s^3 sigma = c1/s + c4; at T = 0 they are 1,
+    (c1+c2)/s + c4+c5+c7; the 1/s part decays towards c1 at rate c3, and the
+    two decaying terms of the constant part at rates c6 and c8."""
+    for atom in ("N", "O"):
+        c = synth.PEACH_FF[atom]
+        f = lambda s, T: O.peach_ff(c, 1.0, s, T) * 1e40 * s**3
+        for s in (0.05, 0.4):
+            assert abs(f(s, 1e12) - (c[0] / s + c[3])) < 1e-12 * abs(c[0] / s + c[3])
+            assert abs(f(s, 0.0) - ((c[0] + c[1]) / s + c[3] + c[4] + c[6])) < 1e-12
+        # 1/s slope minus c1 decays at rate c3
+        A1 = lambda T: (f(0.05, T) - f(0.5, T)) / (1 / 0.05 - 1 / 0.5)
+        T1, T2 = 2000.0, 6000.0
+        rate = -math.log((A1(T2) - c[0]) / (A1(T1) - c[0])) / (T2 - T1)
+        assert abs(rate / c[2] - 1) < 1e-9
+        # intercept: c4 + c5 e^{-c6 T} + c7 e^{-c8 T}; with the c5 term removed
+        # using c6, the remainder decays at rate c8
+        A2 = lambda T: f(0.05, T) - A1(T) / 0.05
+        R = lambda T: A2(T) - c[3] - c[4] * math.exp(-c[5] * T)
+        rate8 = -math.log(R(T2) / R(T1)) / (T2 - T1)
+        assert abs(rate8 / c[7] - 1) < 1e-7
+
+
+def test_continuum_depends_on_electron_temperature_only():
+    """Bound-free and free-free depend on T_ee = T_v (populations, Saha factor,
+    Planck function, fit); changing T_tr leaves them unchanged for an atom."""
+    sp, cells, grid, cont = _continuum_case(9000.0)
+    ks = np.arange(0, 4001, 50)
+    e1, k1 = O.continuum(sp, cells, grid, cont, ks)
+    c2 = synth.Cells(np.array([25000.0]), cells.T_v, cells.N, cells.n_e)
+    e2, k2 = O.continuum(sp, c2, grid, cont, ks)
+    np.testing.assert_array_equal(e1, e2)
+    np.testing.assert_array_equal(k1, k2)
+    c3 = synth.Cells(cells.T_tr, np.array([9500.0]), cells.N, cells.n_e)
+    e3, _ = O.continuum(sp, c3, grid, cont, ks)
+    assert np.max(np.abs(e3 / e1 - 1)) > 1e-3
