@@ -145,6 +145,37 @@ lrt_status lrt_set_grid(lrt_ctx *ctx, double nu_min, double nu_max, int64_t n_po
  * n_e < 0), LRT_E_STATE (no species). */
 lrt_status lrt_set_cells(lrt_ctx *ctx, const lrt_cells *cells);
 
+/* Atomic continuum of one atom (Sec. 2.2.1 bound-free and free-free), added
+ * to eta and kappa of every cell and grid point by lrt_coeffs and lrt_solve.
+ * With T = T_v (the electron temperature), N_a, N_+ the cell's densities of
+ * `species` and `ion`, n_e its electron density and nu in cm^-1:
+ *   bound-free from level i of the atom (threshold nu_i = E_ion - E_i,
+ *   nu >= nu_i, cross section sigma0[i] (nu_i/nu)^3):
+ *     kappa += N_a g_i e^{-c2 E_i/T} / Q_a  sigma_i(nu),
+ *     eta   += B(nu, T) sigma_i(nu) N_+ n_e V(T) g_i e^{c2 (E_ion - E_i)/T} / (2 Q_ion),
+ *     V(T) = (h^2 / (2 pi m_e k T))^{3/2} (the LTE population per ion-electron
+ *     pair, so that eta = B kappa in Saha equilibrium);
+ *   free-free (hydrogenic fit, s = nu / (1e7 / 91.1267 cm^-1)):
+ *     kappa += N_+ n_e 1e-40 (A1/s + A2) / (z^4 s^3),
+ *     A1 = c1 + c2 e^{-c3 T}, A2 = c4 + c5 e^{-c6 T} + c7 e^{-c8 T},
+ *     eta += B(nu, T) times that (the fit's normalisation factor D is 0).
+ * sigma0 has one entry per level of the atom (0: no bound-free from it); all
+ * c zero: no free-free.  The serving path does not add the continuum. */
+typedef struct {
+    int32_t species;       /* the atom (an LRT_KIND_ATOM species) */
+    int32_t ion;           /* species index of its singly charged ion */
+    double E_ion;          /* ionization energy from the ground level, cm^-1 */
+    double Q_ion;          /* partition function of the ion, held constant */
+    const double *sigma0;  /* [levels of the atom], cm^2, host */
+    double peach[8];       /* c1..c8 of the free-free fit, cm^5 */
+    double z;              /* ion charge in the free-free fit */
+} lrt_continuum;
+
+/* Set (n > 0) or clear (n = 0) the continuum records; copied.  Errors:
+ * LRT_E_STATE (no species), LRT_E_ARG (species not an atom, index out of
+ * range, E_ion, Q_ion or z <= 0, negative or non-finite sigma0). */
+lrt_status lrt_set_continuum(lrt_ctx *ctx, int n, const lrt_continuum *cont);
+
 /* Rays of a 1-D slab seen from the wall (Sec. 2.2.3 with a tangent-slab
  * geometry): cells 0..n_cells-1 ordered from the far (free) boundary to the
  * wall with thicknesses dx (host).  Ray 0 is the wall normal; if n_mu > 0,

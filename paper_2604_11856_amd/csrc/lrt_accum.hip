@@ -170,6 +170,83 @@ __device__ __forceinline__ bool pair_setup(const DevLines &L, const DevGrid &g, 
 }
 
 // ---------------------------------------------------------------------------
+// atomic continuum (Sec. 2.2.1 bound-free and free-free)
+// ---------------------------------------------------------------------------
+
+constexpr double kElectronMass = 9.1093837015e-28;   // g
+
+// Per cell: prefix sums over the sorted thresholds of the bound-free
+// absorption and emission weights (times nu_thr^3), the two free-free
+// coefficients, and ln upper bounds of eta_c and kappa_c over [nu_lo, nu_hi]
+// for the power-of-two scale.
+__global__ void cont_cells_kernel(const ContThr *thr, int32_t n_thr, const ContRec *rec,
+                                  int32_t n_rec, DevCells cells, const CellSpecies *cs,
+                                  double nu_lo, double nu_hi, double *cum, double *ff, double *lnb)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells.n_cells) return;
+    const int ns = cells.n_species;
+    const double T = cells.T_v[c], ne = cells.n_e[c];
+    // Saha-Boltzmann volume (h^2 / (2 pi m_e k T))^{3/2}
+    const double V = pow(kPlanck * kPlanck / (2.0 * kPi * kElectronMass * kBoltz * T), 1.5);
+    double *cA = cum + (int64_t)c * 2 * (n_thr + 1), *cB = cA + (n_thr + 1);
+    double a = 0.0, b = 0.0, ka = 0.0, eb = 0.0;
+    cA[0] = cB[0] = 0.0;
+    const double twohc2 = 1e-7 * 2.0 * kPlanck * kLight * kLight;
+    for (int j = 0; j < n_thr; ++j) {
+        const ContThr t = thr[j];
+        const ContRec r = rec[t.rec];
+        const double NQ = exp(cs[(int64_t)c * ns + r.species].lnNQ);   // N_a / Q_a
+        const double Np = cells.N[(int64_t)c * ns + r.ion];
+        const double aj = NQ * t.g * exp(-kC2 * t.E / T) * t.s3;
+        const double bj = Np * ne * V * t.g / (2.0 * r.Q_ion) * t.s3;   // without e^{c2 nu_j / T}
+        a += aj;
+        b += bj * exp(kC2 * t.nu / T);
+        cA[j + 1] = a;
+        cB[j + 1] = b;
+        // bounds: at nu >= max(nu_j, nu_lo), aj / nu^3 <= aj / max(nu_j, nu_lo)^3 and
+        // B(nu) bj e^{c2 nu_j/T} / nu^3 <= 2hc^2 bj / (1 - e^{-c2 max(nu_j, nu_lo)/T})
+        const double nm = fmax(t.nu, nu_lo);
+        ka += aj / (nm * nm * nm);
+        eb += twohc2 * bj / -expm1(-kC2 * nm / T);
+    }
+    double f0 = 0.0, f1 = 0.0;
+    for (int q = 0; q < n_rec; ++q) {
+        const ContRec r = rec[q];
+        const double w = cells.N[(int64_t)c * ns + r.ion] * ne * 1e-40 * r.z4inv;
+        f0 += w * (r.peach[0] + r.peach[1] * exp(-r.peach[2] * T));
+        f1 += w * (r.peach[3] + r.peach[4] * exp(-r.peach[5] * T) + r.peach[6] * exp(-r.peach[7] * T));
+    }
+    ff[2 * c + 0] = f0;
+    ff[2 * c + 1] = f1;
+    // free-free falls with nu on the grid; its emission carries the Planck
+    // factor, whose maximum over [nu_lo, nu_hi] is at nu_p = 2.8214 T / c2 or
+    // the nearer end
+    const double inv3 = 1.0 / (nu_lo * nu_lo * nu_lo);
+    const double kff = (fabs(f0) * kNuH / nu_lo + fabs(f1)) * kNuH * kNuH * kNuH * inv3;
+    const double nu_p = fmin(fmax(2.8214393721220787 * T / kC2, nu_lo), nu_hi);
+    const double km = ka + kff, em = eb + planck_f64(nu_p, T) * kff;
+    lnb[2 * c + 0] = em > 0.0 ? log(em) : -INFINITY;
+    lnb[2 * c + 1] = km > 0.0 ? log(km) : -INFINITY;
+}
+
+// Continuum eta and kappa of cell c at nu (double precision).
+__device__ __forceinline__ void continuum_point(const DevCont &ct, int c, double nu, double &eta,
+                                                double &kap)
+{
+    int lo = 0, hi = ct.n_thr;   // m = number of thresholds <= nu
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ct.thr[mid].nu <= nu) lo = mid + 1; else hi = mid;
+    }
+    const double *cA = ct.cum + (int64_t)c * 2 * (ct.n_thr + 1);
+    const double inv3 = 1.0 / (nu * nu * nu);
+    const double kff = (ct.ff[2 * c] * (kNuH / nu) + ct.ff[2 * c + 1]) * (kNuH * kNuH * kNuH) * inv3;
+    kap = cA[lo] * inv3 + kff;
+    eta = planck_f64(nu, ct.T_v[c]) * (cA[ct.n_thr + 1 + lo] * inv3 + kff);
+}
+
+// ---------------------------------------------------------------------------
 // candidate line ranges per (cell, tile)
 // ---------------------------------------------------------------------------
 
@@ -241,7 +318,8 @@ __global__ void scale_kernel(DevLines L, int64_t i0, int64_t i1, DevGrid g, cons
 // bound exceeds the true peak by a modest factor (bin width, Lorentz part of
 // the width), which the power-of-two scale absorbs.
 __global__ void scale_bound_kernel(DevBins B, const CellConst *cc, const CellSpecies *cs,
-                                   int32_t n_cells, int32_t n_species, int32_t *escale)
+                                   const double *cont_lnb, int32_t n_cells, int32_t n_species,
+                                   int32_t *escale)
 {
     const int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -259,6 +337,10 @@ __global__ void scale_bound_kernel(DevBins B, const CellConst *cc, const CellSpe
     for (int o = 32; o > 0; o >>= 1) {
         ve = fmax(ve, __shfl_xor(ve, o));
         vk = fmax(vk, __shfl_xor(vk, o));
+    }
+    if (cont_lnb) {   // the atomic continuum's own bound
+        ve = fmax(ve, cont_lnb[2 * c + 0]);
+        vk = fmax(vk, cont_lnb[2 * c + 1]);
     }
     if (lane == 0) {
         // peak < 2^e; stay unscaled while e is within 2^+-60
@@ -548,7 +630,7 @@ __global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(L
 void accum_f32_kernel(
     DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int32_t *escale,
     const int2 *ranges, int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band,
-    int32_t n_tiles, float *eta, float *kappa)
+    int32_t n_tiles, DevCont ct, float *eta, float *kappa)
 {
     __shared__ RecF32 rec[kStage];
     int tile, c;
@@ -567,6 +649,13 @@ void accum_f32_kernel(
         const int32_t kk = kt + kw + 64 * j + lane;
         if (kk < kend) {
             const int64_t o = (int64_t)c * n_band + (kk - k_first);
+            if (ct.n_thr >= 0) {
+                // atomic continuum, added in double precision and rounded once
+                double ce, ck;
+                continuum_point(ct, c, g.nu_min + (double)kk * g.h, ce, ck);
+                e[j] = (float)((double)e[j] + ldexp(ce, -escale[2 * c + 0]));
+                kp[j] = (float)((double)kp[j] + ldexp(ck, -escale[2 * c + 1]));
+            }
             eta[o] = e[j];
             kappa[o] = kp[j];
         }
@@ -576,7 +665,7 @@ void accum_f32_kernel(
 __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
     DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int2 *ranges,
     int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles,
-    double *eta, double *kappa)
+    DevCont ct, double *eta, double *kappa)
 {
     __shared__ RecF64 rec[kStage];
     int tile, c;
@@ -642,6 +731,12 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
         const int32_t kk = kw + 64 * j + lane;
         if (kk < kend) {
             const int64_t o = (int64_t)c * n_band + (kk - k_first);
+            if (ct.n_thr >= 0) {   // atomic continuum
+                double ce, ck;
+                continuum_point(ct, c, g.nu_min + (double)kk * g.h, ce, ck);
+                se[j] += ce;
+                sk[j] += ck;
+            }
             eta[o] = se[j];
             kappa[o] = sk[j];
         }
@@ -810,11 +905,22 @@ hipError_t launch_ranges(const DevLines &L, const DevGrid &g, const CellConst *c
 }
 
 hipError_t launch_scale_bound(const DevBins &B, const CellConst *cc, const CellSpecies *cs,
-                              int32_t n_cells, int32_t n_species, int32_t *escale, hipStream_t st)
+                              const double *cont_lnb, int32_t n_cells, int32_t n_species,
+                              int32_t *escale, hipStream_t st)
 {
     if (n_cells == 0) return hipSuccess;
     hipLaunchKernelGGL(scale_bound_kernel, dim3(blocks_for(n_cells, 4)), dim3(256), 0, st, B, cc, cs,
-                       n_cells, n_species, escale);
+                       cont_lnb, n_cells, n_species, escale);
+    return hipGetLastError();
+}
+
+hipError_t launch_cont_cells(const ContThr *thr, int32_t n_thr, const ContRec *rec, int32_t n_rec,
+                             const DevCells &cells, const CellSpecies *cs, double nu_lo,
+                             double nu_hi, double *cum, double *ff, double *lnb, hipStream_t st)
+{
+    if (cells.n_cells == 0) return hipSuccess;
+    hipLaunchKernelGGL(cont_cells_kernel, dim3(blocks_for(cells.n_cells, 64)), dim3(64), 0, st, thr,
+                       n_thr, rec, n_rec, cells, cs, nu_lo, nu_hi, cum, ff, lnb);
     return hipGetLastError();
 }
 
@@ -836,24 +942,24 @@ hipError_t launch_scale(const DevLines &L, int64_t i0, int64_t i1, const DevGrid
 hipError_t launch_accum_f32(const DevLines &L, const DevGrid &g, const CellConst *cc,
                             const CellSpecies *cs, const int32_t *escale, const int2 *ranges,
                             int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band,
-                            float *eta, float *kappa, hipStream_t st)
+                            const DevCont &ct, float *eta, float *kappa, hipStream_t st)
 {
     const int32_t n_tiles = (n_band + kTilePoints - 1) / kTilePoints;
     hipLaunchKernelGGL(accum_f32_kernel, dim3((unsigned)((int64_t)n_tiles * n_cells)),
                        dim3(kAccumThreads), 0, st, L, g, cc, cs, escale, ranges, n_cells, n_species,
-                       k_first, n_band, n_tiles, eta, kappa);
+                       k_first, n_band, n_tiles, ct, eta, kappa);
     return hipGetLastError();
 }
 
 hipError_t launch_accum_f64(const DevLines &L, const DevGrid &g, const CellConst *cc,
                             const CellSpecies *cs, const int2 *ranges, int32_t n_cells,
-                            int32_t n_species, int32_t k_first, int32_t n_band, double *eta,
-                            double *kappa, hipStream_t st)
+                            int32_t n_species, int32_t k_first, int32_t n_band, const DevCont &ct,
+                            double *eta, double *kappa, hipStream_t st)
 {
     const int32_t n_tiles = (n_band + kTilePoints - 1) / kTilePoints;
     hipLaunchKernelGGL(accum_f64_kernel, dim3((unsigned)((int64_t)n_tiles * n_cells)),
                        dim3(kAccumThreads), 0, st, L, g, cc, cs, ranges, n_cells, n_species, k_first,
-                       n_band, n_tiles, eta, kappa);
+                       n_band, n_tiles, ct, eta, kappa);
     return hipGetLastError();
 }
 

@@ -48,6 +48,13 @@ struct lrt_ctx {
         d_vib_off, d_vib_G, d_vib_B, d_vib_D;
     DevSpecies sp{};
     double M_min = 0.0;
+    std::vector<int64_t> h_lev_off;      // host copies of the atomic level tables
+    std::vector<double> h_lev_E, h_lev_g;
+
+    // atomic continuum: thresholds sorted by nu, records, per-cell sums
+    int n_cont_rec = 0, n_cont_thr = 0;
+    DBuf d_cont_thr, d_cont_rec;         // ContThr[n_thr], ContRec[n_rec]
+    DBuf d_cont_cum, d_cont_ff, d_cont_lnb;   // per cell: [2][n_thr+1], [2], [2]
 
     // lines (sorted by nu0 on the host, resident on the device)
     int64_t n_lines = -1;

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "lrt_internal.h"
+
 namespace lrt {
 
 constexpr double kLog2e = 1.4426950408889634;
@@ -14,6 +16,12 @@ constexpr int kXCDs = 8;
 __device__ __forceinline__ int32_t uniform_i(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// Blackbody intensity B(nu, T) in W cm^-2 sr^-1 per cm^-1 (CGS x 1e-7).
+static __device__ __forceinline__ double planck_f64(double nu, double T)
+{
+    return 1e-7 * 2.0 * kPlanck * kLight * kLight * nu * nu * nu / expm1(kC2 * nu / T);
+}
 
 // F(t) = (1 - e^-t)/t from e = e^-t; Taylor for |t| < 0.1 avoids the
 // cancellation in 1 - e (relative error of the direct form ~ 6e-8 / |t|).

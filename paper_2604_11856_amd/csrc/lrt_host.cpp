@@ -340,6 +340,10 @@ lrt_status lrt_set_species(lrt_ctx *c, int n, const lrt_species *sp)
     c->n_species = n;
     c->sp_kind = kind;
     c->sp_mass = mass;
+    c->h_lev_off = lev_off;
+    c->h_lev_E = lev_E;
+    c->h_lev_g = lev_g;
+    c->n_cont_rec = c->n_cont_thr = 0;   // continuum records refer to the old table
     c->M_min = std::isfinite(M_min) ? M_min : 1.0;
     c->sp = DevSpecies{n, c->d_kind.as<int32_t>(), c->d_mass.as<double>(), c->d_lev_off.as<int64_t>(),
                        c->d_lev_E.as<double>(), c->d_lev_g.as<double>(), c->d_el_off.as<int64_t>(),
@@ -452,6 +456,52 @@ lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *L)
     c->n_lines = n;
     c->lines_grid_ready = false;
     c->scale_ready = false;
+    return LRT_OK;
+}
+
+lrt_status lrt_set_continuum(lrt_ctx *c, int n, const lrt_continuum *cont)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (c->n_species < 1) return fail(c, LRT_E_STATE, "set species before the continuum");
+    if (n < 0 || (n > 0 && !cont)) return fail(c, LRT_E_ARG, "n must be >= 0 and cont non-NULL");
+    std::vector<ContThr> thr;
+    std::vector<ContRec> rec(n);
+    for (int q = 0; q < n; ++q) {
+        const lrt_continuum &x = cont[q];
+        if (x.species < 0 || x.species >= c->n_species || c->sp_kind[x.species] != LRT_KIND_ATOM)
+            return fail(c, LRT_E_ARG, "continuum %d: species %d is not an atom", q, x.species);
+        if (x.ion < 0 || x.ion >= c->n_species) return fail(c, LRT_E_ARG, "continuum %d: ion out of range", q);
+        if (!(x.E_ion > 0.0) || !(x.Q_ion > 0.0) || !(x.z > 0.0) || !std::isfinite(x.E_ion) ||
+            !std::isfinite(x.Q_ion) || !std::isfinite(x.z))
+            return fail(c, LRT_E_ARG, "continuum %d: E_ion, Q_ion and z must be positive", q);
+        for (int j = 0; j < 8; ++j)
+            if (!std::isfinite(x.peach[j])) return fail(c, LRT_E_ARG, "continuum %d: non-finite fit coefficient", q);
+        rec[q].species = x.species;
+        rec[q].ion = x.ion;
+        rec[q].E_ion = x.E_ion;
+        rec[q].Q_ion = x.Q_ion;
+        rec[q].z4inv = 1.0 / (x.z * x.z * x.z * x.z);
+        std::copy(x.peach, x.peach + 8, rec[q].peach);
+        const int64_t l0 = c->h_lev_off[x.species], l1 = c->h_lev_off[x.species + 1];
+        if (l1 > l0 && !x.sigma0) return fail(c, LRT_E_ARG, "continuum %d: sigma0 NULL", q);
+        for (int64_t i = l0; i < l1; ++i) {
+            const double s0 = x.sigma0[i - l0];
+            if (!(s0 >= 0.0) || !std::isfinite(s0))
+                return fail(c, LRT_E_ARG, "continuum %d level %lld: sigma0 must be >= 0", q, (long long)(i - l0));
+            const double nu = x.E_ion - c->h_lev_E[i];
+            if (s0 == 0.0 || !(nu > 0.0)) continue;   // no bound-free from this level
+            thr.push_back(ContThr{nu, c->h_lev_E[i], c->h_lev_g[i], s0 * nu * nu * nu, q, 0});
+        }
+    }
+    std::stable_sort(thr.begin(), thr.end(), [](const ContThr &a, const ContThr &b) { return a.nu < b.nu; });
+    lrt_status st;
+    if (n > 0 && ((st = upload(c, c->d_cont_rec, rec.data(), rec.size() * sizeof(ContRec))) ||
+                  (st = upload(c, c->d_cont_thr, thr.empty() ? nullptr : thr.data(), thr.size() * sizeof(ContThr)))))
+        return st;
+    c->n_cont_rec = n;
+    c->n_cont_thr = (int)thr.size();
+    c->thermo_ready = c->scale_ready = false;
     return LRT_OK;
 }
 
@@ -864,6 +914,18 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
                     return launch_thermo(c->sp, cells, c->M_min, 0, c->d_cc.as<CellConst>(),
                                          c->d_cs.as<CellSpecies>(), st);
                 }));
+        if (c->n_cont_rec > 0) {
+            lrt_status r;
+            const size_t nc = (size_t)c->n_cells;
+            if ((r = ensure(c, c->d_cont_cum, nc * 2 * (c->n_cont_thr + 1) * sizeof(double))) ||
+                (r = ensure(c, c->d_cont_ff, nc * 2 * sizeof(double))) ||
+                (r = ensure(c, c->d_cont_lnb, nc * 2 * sizeof(double))))
+                return r;
+            LRT_HIP(c, launch_cont_cells(c->d_cont_thr.as<ContThr>(), c->n_cont_thr, c->d_cont_rec.as<ContRec>(),
+                                         c->n_cont_rec, cells, c->d_cs.as<CellSpecies>(), c->nu_min,
+                                         c->nu_max, c->d_cont_cum.as<double>(), c->d_cont_ff.as<double>(),
+                                         c->d_cont_lnb.as<double>(), st));
+        }
         c->thermo_ready = true;
     }
     if (need_scale && !c->scale_ready) {
@@ -876,6 +938,7 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
                         c->d_bin_Er.as<double>(), c->d_bin_aeta.as<double>(), c->d_bin_akap.as<double>()};
         LRT_HIP(c, timed(c, LRT_K_SCALE, st, [&] {
                     return launch_scale_bound(B, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
+                                              c->n_cont_rec > 0 ? c->d_cont_lnb.as<double>() : nullptr,
                                               (int32_t)c->n_cells, c->n_species, c->d_escale.as<int32_t>(),
                                               st);
                 }));
@@ -919,11 +982,16 @@ lrt_status coeffs_impl(lrt_ctx *c, int64_t band, lrt_precision prec, void *eta, 
                 return launch_ranges(L, g, c->d_cc.as<CellConst>(), nc, k_first, n_band, kTilePoints,
                                      c->w_ranges.as<int2>(), st);
             }));
+    DevCont ct{-1, nullptr, nullptr, nullptr, nullptr};
+    if (c->n_cont_rec > 0)
+        ct = DevCont{c->n_cont_thr, c->d_cont_thr.as<ContThr>(), c->d_cont_cum.as<double>(),
+                     c->d_cont_ff.as<double>(), c->d_T_v.as<double>()};
     if (prec == LRT_FP32_COMP) {
         LRT_HIP(c, timed(c, LRT_K_ACCUM, st, [&] {
                     return launch_accum_f32(L, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
                                             c->d_escale.as<int32_t>(), c->w_ranges.as<int2>(), nc,
-                                            c->n_species, k_first, n_band, (float *)eta, (float *)kappa, st);
+                                            c->n_species, k_first, n_band, ct, (float *)eta, (float *)kappa,
+                                            st);
                 }));
         if (escale)
             LRT_HIP(c, hipMemcpyAsync(escale, c->d_escale.p, (size_t)nc * 2 * sizeof(int32_t),
@@ -931,7 +999,7 @@ lrt_status coeffs_impl(lrt_ctx *c, int64_t band, lrt_precision prec, void *eta, 
     } else {
         LRT_HIP(c, timed(c, LRT_K_ACCUM, st, [&] {
                     return launch_accum_f64(L, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
-                                            c->w_ranges.as<int2>(), nc, c->n_species, k_first, n_band,
+                                            c->w_ranges.as<int2>(), nc, c->n_species, k_first, n_band, ct,
                                             (double *)eta, (double *)kappa, st);
                 }));
     }

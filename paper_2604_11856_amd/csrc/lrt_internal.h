@@ -77,6 +77,29 @@ struct DevLines {
     const double *frac0;
 };
 
+// Atomic continuum.  A bound-free threshold (sorted by nu over all records)
+// and its level; s3 = sigma0 nu_thr^3 (the cross section is s3 / nu^3 above).
+struct ContThr {
+    double nu, E, g, s3;
+    int32_t rec, pad;
+};
+struct ContRec {
+    int32_t species, ion;
+    double E_ion, Q_ion, z4inv;   // z4inv = 1/z^4
+    double peach[8];
+};
+// What the accumulation needs per cell: with m = number of thresholds <= nu,
+//   kappa_c = cum[0][m] / nu^3 + kff(nu), eta_c = B(nu, T_v) (cum[1][m] / nu^3 + kff(nu)),
+//   kff(nu) = (ff[0] nu_H / nu + ff[1]) nu_H^3 / nu^3.
+struct DevCont {
+    int32_t n_thr;          // < 0: no continuum
+    const ContThr *thr;
+    const double *cum;      // [n_cells][2][n_thr+1]
+    const double *ff;       // [n_cells][2]
+    const double *T_v;      // [n_cells]
+};
+constexpr double kNuH = 1e7 / 91.1267;   // hydrogen ground-state threshold, cm^-1
+
 // Upper bounds of the line peaks for the per-cell scale, from level-energy
 // bins of the line list (one entry per (species, E_ev bin, E_rot bin) of the
 // upper levels and one per bin of the lower levels).  For every line i in a
@@ -149,7 +172,11 @@ hipError_t launch_ranges(const DevLines &L, const DevGrid &g, const CellConst *c
                          int2 *ranges, hipStream_t st);
 
 hipError_t launch_scale_bound(const DevBins &B, const CellConst *cc, const CellSpecies *cs,
-                              int32_t n_cells, int32_t n_species, int32_t *escale, hipStream_t st);
+                              const double *cont_lnb, int32_t n_cells, int32_t n_species,
+                              int32_t *escale, hipStream_t st);
+hipError_t launch_cont_cells(const ContThr *thr, int32_t n_thr, const ContRec *rec, int32_t n_rec,
+                             const DevCells &cells, const CellSpecies *cs, double nu_lo,
+                             double nu_hi, double *cum, double *ff, double *lnb, hipStream_t st);
 hipError_t launch_scale(const DevLines &L, int64_t i0, int64_t i1, const DevGrid &g,
                         const CellConst *cc, const CellSpecies *cs, int32_t n_cells,
                         int32_t n_species, int32_t *emax, int32_t *escale, hipStream_t st);
@@ -157,12 +184,12 @@ hipError_t launch_scale(const DevLines &L, int64_t i0, int64_t i1, const DevGrid
 hipError_t launch_accum_f32(const DevLines &L, const DevGrid &g, const CellConst *cc,
                             const CellSpecies *cs, const int32_t *escale, const int2 *ranges,
                             int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band,
-                            float *eta, float *kappa, hipStream_t st);
+                            const DevCont &ct, float *eta, float *kappa, hipStream_t st);
 
 hipError_t launch_accum_f64(const DevLines &L, const DevGrid &g, const CellConst *cc,
                             const CellSpecies *cs, const int2 *ranges, int32_t n_cells,
-                            int32_t n_species, int32_t k_first, int32_t n_band, double *eta,
-                            double *kappa, hipStream_t st);
+                            int32_t n_species, int32_t k_first, int32_t n_band, const DevCont &ct,
+                            double *eta, double *kappa, hipStream_t st);
 
 hipError_t launch_count(const DevLines &L, const DevGrid &g, const CellConst *cc,
                         const CellSpecies *cs, const int2 *band_ranges, int32_t n_cells,

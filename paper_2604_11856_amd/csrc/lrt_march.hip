@@ -61,12 +61,6 @@ __device__ __forceinline__ void linear_j_weights_f64(double t, double &e, double
     wf = b;
 }
 
-// Blackbody intensity B(nu, T) in W cm^-2 sr^-1 per cm^-1 (CGS x 1e-7).
-__device__ __forceinline__ double planck_f64(double nu, double T)
-{
-    return 1e-7 * 2.0 * kPlanck * kLight * kLight * nu * nu * nu / expm1(kC2 * nu / T);
-}
-
 // One row (kMarchPPT consecutive points of a cell) of eta and kappa.
 template <typename T>
 __device__ __forceinline__ void load_row(const T *eta, const T *kap, int64_t row, int32_t kb,

@@ -29,7 +29,7 @@ _i64p = C.POINTER(C.c_int64)
 _vp = C.c_void_p
 
 EXPORTS = ["lrt_version", "lrt_status_string", "lrt_create", "lrt_destroy", "lrt_last_error",
-           "lrt_set_species", "lrt_set_lines", "lrt_set_grid", "lrt_set_cells",
+           "lrt_set_species", "lrt_set_lines", "lrt_set_grid", "lrt_set_cells", "lrt_set_continuum",
            "lrt_set_rays_slab", "lrt_set_rays_axi", "lrt_set_rays_axi_fibonacci",
            "lrt_fibonacci_quadrature", "lrt_set_march", "lrt_set_far_temperature", "lrt_trace_axi_ray", "lrt_get_sizes", "lrt_get_ray",
            "lrt_coeffs", "lrt_march", "lrt_solve", "lrt_count_terms", "lrt_profile",
@@ -55,6 +55,11 @@ class _Species(C.Structure):
 class _Lines(C.Structure):
     _fields_ = [("n", C.c_int64), ("nu0", _dp), ("A", _dp), ("Eu_ev", _dp), ("Eu_rot", _dp),
                 ("El_ev", _dp), ("El_rot", _dp), ("gu", _dp), ("gl", _dp), ("species", _i32p)]
+
+
+class _Continuum(C.Structure):
+    _fields_ = [("species", C.c_int32), ("ion", C.c_int32), ("E_ion", C.c_double),
+                ("Q_ion", C.c_double), ("sigma0", _dp), ("peach", C.c_double * 8), ("z", C.c_double)]
 
 
 class _Cells(C.Structure):
@@ -95,6 +100,7 @@ def lib():
             "lrt_set_lines": (st, [_vp, C.POINTER(_Lines)]),
             "lrt_set_grid": (st, [_vp, C.c_double, C.c_double, C.c_int64, C.c_int64]),
             "lrt_set_cells": (st, [_vp, C.POINTER(_Cells)]),
+            "lrt_set_continuum": (st, [_vp, C.c_int, C.POINTER(_Continuum)]),
             "lrt_set_rays_slab": (st, [_vp, C.c_int64, _dp, C.c_int]),
             "lrt_set_rays_axi": (st, [_vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
                                       _dp, C.c_int, C.c_int]),
@@ -224,6 +230,16 @@ class Context:
         else:
             raise TypeError("unknown geometry %r" % type(geom))
 
+    def set_continuum(self, records):
+        """Atomic continuum records (synth.Continuum), or None / [] for none."""
+        records = records or []
+        keep = [np.ascontiguousarray(r.sigma0, np.float64) for r in records]
+        arr = (_Continuum * max(1, len(records)))()
+        for j, (r, s0) in enumerate(zip(records, keep)):
+            arr[j] = _Continuum(int(r.species), int(r.ion), float(r.E_ion), float(r.Q_ion), _p(s0),
+                                (C.c_double * 8)(*[float(v) for v in r.peach]), float(r.z))
+        self._chk(self._L.lrt_set_continuum(self.h, len(records), arr))
+
     def set_march(self, scheme: int):
         self._chk(self._L.lrt_set_march(self.h, int(scheme)))
 
@@ -242,6 +258,8 @@ class Context:
         self.set_grid(wl.grid)
         self.set_cells(wl.cells)
         self.set_rays(wl.geometry)
+        if getattr(wl, "continuum", None):
+            self.set_continuum(wl.continuum)
         return self
 
     def sizes(self):

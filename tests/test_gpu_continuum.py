@@ -1,0 +1,141 @@
+"""Parity of the atomic continuum (Sec. 2.2.1 bound-free and free-free,
+added to eta and kappa) through the C ABI with the FP64 oracle.  Bars as for
+the line path: LRT_FP64 within 1e-12 and LRT_FP32_COMP within 1e-5, normwise
+per cell, relative for integrals and fluxes; knife-edge window bounds of the
+lines are excluded as there."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2604_11856_amd import lrt, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {lrt.LRT_FP64: 1e-12, lrt.LRT_FP32_COMP: 1e-5}
+PRECS = [lrt.LRT_FP64, lrt.LRT_FP32_COMP]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def normwise(got, ref, mask=None):
+    d = np.abs(np.asarray(got, np.float64) - np.asarray(ref, np.float64))
+    if mask is not None:
+        d = np.where(mask, 0.0, d)
+    return float(np.max(np.max(d, axis=1) / np.max(np.abs(ref), axis=1)))
+
+
+def gpu_coeffs(ctx, band, prec, torch):
+    eta, kap, esc = ctx.coeffs_torch(band, prec)
+    torch.cuda.synchronize()
+    if prec == lrt.LRT_FP32_COMP:
+        return lrt.scaled_to_f64(eta, kap, esc)
+    return eta.cpu().numpy(), kap.cpu().numpy()
+
+
+def edge_mask(wl, k_first, n):
+    cc, kk = O.knife_edges(wl.species, wl.lines, wl.cells, wl.grid)
+    m = np.zeros((wl.cells.n, n), bool)
+    sel = (kk >= k_first) & (kk < k_first + n)
+    m[cc[sel], kk[sel] - k_first] = True
+    return m
+
+
+def test_continuum_coeffs_all_bands(torch_dev):
+    """Stagnation-line cells with lines and continuum over ragged bands: eta
+    and kappa equal the oracle's lines plus continuum."""
+    wl = synth.stagnation_line(n_cells=12, n_atomic=2000, n_rovib=6000, n_points=30_000,
+                               band_points=11_000, n_mu=2)
+    wl.continuum = synth.air_continuum(wl.species)
+    e_l, k_l, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
+    e_c, k_c = O.continuum(wl.species, wl.cells, wl.grid, wl.continuum)
+    assert np.max(k_c) > 0 and np.max(e_c) > 0
+    ctx = lrt.Context(0).load(wl)
+    nb = ctx.sizes()["n_bands"]
+    for prec in PRECS:
+        we = wk = 0.0
+        for b in range(nb):
+            e, k = gpu_coeffs(ctx, b, prec, torch_dev)
+            k0 = b * wl.grid.band_points
+            sl = slice(k0, k0 + e.shape[1])
+            m = edge_mask(wl, k0, e.shape[1])
+            we = max(we, normwise(e, e_l[:, sl] + e_c[:, sl], m))
+            wk = max(wk, normwise(k, k_l[:, sl] + k_c[:, sl], m))
+        say("continuum coeffs prec %d: eta %.3e kappa %.3e" % (prec, we, wk))
+        assert we <= TOL[prec] and wk <= TOL[prec]
+    # clearing the continuum gives the line-only coefficients back
+    ctx.set_continuum(None)
+    e, k = gpu_coeffs(ctx, 0, lrt.LRT_FP64, torch_dev)
+    m = edge_mask(wl, 0, e.shape[1])
+    assert normwise(e, e_l[:, :e.shape[1]], m) <= 1e-12
+    ctx.close()
+
+
+def test_continuum_only_and_cold_cell(torch_dev):
+    """No lines at all: the continuum alone, in cells from 600 K to 30,000 K
+    (the power-of-two scale then comes from the continuum's own bound)."""
+    wl = synth.stagnation_line(n_cells=6, n_atomic=0, n_rovib=0, n_points=20_000,
+                               band_points=20_000, n_mu=0)
+    wl.cells.T_v[:] = [600.0, 3000.0, 8000.0, 12000.0, 20000.0, 30000.0]
+    wl.continuum = synth.air_continuum(wl.species)
+    e_c, k_c = O.continuum(wl.species, wl.cells, wl.grid, wl.continuum)
+    ctx = lrt.Context(0).load(wl)
+    for prec in PRECS:
+        e, k = gpu_coeffs(ctx, 0, prec, torch_dev)
+        we, wk = normwise(e, e_c), normwise(k, k_c)
+        say("continuum only prec %d: eta %.3e kappa %.3e" % (prec, we, wk))
+        assert we <= TOL[prec] and wk <= TOL[prec]
+    ctx.close()
+
+
+def test_continuum_solve_slab(torch_dev):
+    """Whole path with the continuum: wall intensities and tangent-slab flux."""
+    wl = synth.stagnation_line(n_cells=16, n_atomic=1500, n_rovib=3000, n_points=16_384,
+                               band_points=5000, n_mu=4)
+    wl.continuum = synth.air_continuum(wl.species)
+    e_l, k_l, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
+    e_c, k_c = O.continuum(wl.species, wl.cells, wl.grid, wl.continuum)
+    eta, kap = e_l + e_c, k_l + k_c
+    rays, mu, W = O.slab_rays(wl.geometry)
+    w = O.trapezoid_weights(wl.grid)
+    I_int = np.array([float(O.march(c, d, eta, kap) @ w) for c, d in rays])
+    q_ref = 2 * np.pi * float(np.sum(W * mu * I_int[1:]))
+    ctx = lrt.Context(0).load(wl)
+    for prec in PRECS:
+        q, Ii, _ = ctx.solve(prec)
+        eI = float(np.max(np.abs(Ii - I_int) / np.abs(I_int)))
+        eq = abs(q[0] - q_ref) / abs(q_ref)
+        say("continuum solve prec %d: I_int %.3e q %.3e" % (prec, eI, eq))
+        assert eI <= TOL[prec] and eq <= TOL[prec]
+    ctx.close()
+
+
+def test_continuum_arguments(torch_dev):
+    wl = synth.stagnation_line(n_cells=2, n_atomic=10, n_rovib=10, n_points=1000, band_points=1000)
+    cont = synth.air_continuum(wl.species)
+    ctx = lrt.Context(0)
+    with pytest.raises(lrt.LrtError) as e:
+        ctx.set_continuum(cont)                  # no species yet
+    assert e.value.status == 6
+    ctx.set_species(wl.species)
+    bad = [synth.Continuum(0, cont[0].ion, cont[0].E_ion, cont[0].Q_ion, np.zeros(1), cont[0].peach)]
+    with pytest.raises(lrt.LrtError):
+        ctx.set_continuum(bad)                   # species 0 (N2) is not an atom
+    bad = [synth.Continuum(cont[0].species, cont[0].ion, -1.0, cont[0].Q_ion, cont[0].sigma0, cont[0].peach)]
+    with pytest.raises(lrt.LrtError):
+        ctx.set_continuum(bad)
+    s0 = cont[0].sigma0.copy()
+    s0[3] = -1.0
+    bad = [synth.Continuum(cont[0].species, cont[0].ion, cont[0].E_ion, cont[0].Q_ion, s0, cont[0].peach)]
+    with pytest.raises(lrt.LrtError):
+        ctx.set_continuum(bad)
+    ctx.set_continuum(cont)
+    ctx.close()
