@@ -193,6 +193,34 @@ def compare_march_schemes(ctx, lrt, torch, sz, reps=3):
     return out
 
 
+def continuum_cost(ctx, wl, lrt, torch, reps=2):
+    """Band 0 in single precision: accumulation time without and with the
+    atomic continuum (bound-free + free-free of N and O, added per point in the
+    accumulation's epilogue)."""
+    from paper_2604_11856_amd import synth
+    cont = synth.air_continuum(wl.species)
+    if not cont:
+        return None
+    out = {}
+    for name, rec in (("lines_only", None), ("with_continuum", cont)):
+        ctx.set_continuum(rec)
+        eta, kap, esc = ctx.coeffs_torch(0, lrt.LRT_FP32_COMP)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(reps):
+            ctx.coeffs(0, lrt.LRT_FP32_COMP, eta, kap, esc)
+        torch.cuda.synchronize()
+        ms, n = ctx.profile_read("accum")
+        ctx.profile(False)
+        out[name + "_accum_ms"] = ms / max(1, n)
+        del eta, kap, esc
+    ctx.set_continuum(None)
+    torch.cuda.empty_cache()
+    out["band"] = 0
+    out["thresholds"] = int(sum(int((r.sigma0 > 0).sum()) for r in cont))
+    return out
+
+
 def cpu_baseline(wl, n_points):
     import oracle as O
     from paper_2604_11856_amd import synth
@@ -255,6 +283,7 @@ def main():
                    "q": [float(abs(a - b) / abs(b)) if b != 0 else 0.0 for a, b in zip(q32, q64)]}}
 
     march_schemes = compare_march_schemes(ctx, lrt, torch, sz)
+    continuum = continuum_cost(ctx, wl, lrt, torch)
 
     acc_ms, acc_n = prof32["accum"]
     acc_s = acc_ms / 1e3 / max(1, acc_n)
@@ -293,6 +322,7 @@ def main():
                      "slots_per_eval": slots_per_launch / max(1.0, terms_per_launch),
                      "avg_launch_ms": acc_s * 1e3},
         "march_schemes": march_schemes,
+        "continuum": continuum,
         "march_roofline": {"bound": "hbm", "kernel": "march_f32", "achieved": march_bytes / mar_s / 1e9,
                            "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                            "frac": march_bytes / mar_s / HBM_PEAK, "avg_launch_ms": mar_s * 1e3,
