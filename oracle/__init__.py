@@ -44,7 +44,8 @@ class _Species(C.Structure):
     _fields_ = [("n_species", C.c_int), ("kind", _ip), ("mass", _dp),
                 ("lev_off", _i64p), ("lev_E", _dp), ("lev_g", _dp),
                 ("el_off", _i64p), ("el_T", _dp), ("el_g", _dp), ("el_Jmax", _ip),
-                ("vib_off", _i64p), ("vib_G", _dp), ("vib_B", _dp), ("vib_D", _dp)]
+                ("vib_off", _i64p), ("vib_G", _dp), ("vib_B", _dp), ("vib_D", _dp),
+                ("E_ion", _dp)]
 
 
 class _Lines(C.Structure):
@@ -89,8 +90,10 @@ def lib():
             "orc_window": (None, [d, d, d, d, i64, _i64p, _i64p]),
             "orc_grid_offset": (d, [d, d, i64, d]),
             "orc_planck": (d, [d, d]),
-            "orc_line_pair": (None, [C.POINTER(_Species), C.POINTER(_Lines), i64, d, d, d, d, d,
-                                     d, d, i64, C.POINTER(_Pair)]),
+            "orc_line_pair": (None, [C.POINTER(_Species), C.POINTER(_Lines), i64, d, d, d, _dp,
+                                     C.c_int, d, d, d, d, i64, C.POINTER(_Pair)]),
+            "orc_lorentz_line": (d, [C.POINTER(_Species), C.POINTER(_Lines), i64, d, d, d, _dp,
+                                     C.c_int]),
             "orc_coeffs": (i64, [C.POINTER(_Species), C.POINTER(_Lines), C.POINTER(_Cells),
                                  d, d, i64, i64, _i64p, _dp, _dp, C.c_int]),
             "orc_coeffs_bruteforce": (None, [C.POINTER(_Species), C.POINTER(_Lines),
@@ -125,8 +128,11 @@ def _p(a, t=_dp):
 class SpeciesTable:
     """Flattened level tables of a species list (keeps the arrays alive)."""
 
-    def __init__(self, species):
+    def __init__(self, species, E_ion=None):
+        """E_ion: per-species ionization energies (cm^-1) that switch atomic
+        lines to the full Lorentz width, or None (uniform Stark law)."""
         S = len(species)
+        self.E_ion = None if E_ion is None else np.ascontiguousarray(E_ion, np.float64)
         self.kind = np.array([s.kind for s in species], np.int32)
         self.mass = np.array([s.mass for s in species], np.float64)
         lev_E, lev_g, lev_off = [], [], [0]
@@ -159,7 +165,8 @@ class SpeciesTable:
         self.s = _Species(S, _p(self.kind, _ip), _p(self.mass), _p(self.lev_off, _i64p),
                           _p(self.lev_E), _p(self.lev_g), _p(self.el_off, _i64p), _p(self.el_T),
                           _p(self.el_g), _p(self.el_J, _ip), _p(self.vib_off, _i64p),
-                          _p(self.vib_G), _p(self.vib_B), _p(self.vib_D))
+                          _p(self.vib_G), _p(self.vib_B), _p(self.vib_D),
+                          None if self.E_ion is None else _p(self.E_ion))
 
 
 class LineTable:
@@ -234,13 +241,16 @@ def planck(nu, T) -> float:
     return lib().orc_planck(nu, T)
 
 
-def line_pair(species, lines, i, Ttr, Tv, ne, N_s, Q_s, grid):
-    """Per-(cell, line) quantities: populations, S_eta, B_line, widths, window."""
-    st, lt = SpeciesTable(species), LineTable(lines)
+def line_pair(species, lines, i, Ttr, Tv, ne, N_s, Q_s, grid, N_cell=None, E_ion=None):
+    """Per-(cell, line) quantities: populations, S_eta, B_line, widths, window.
+    N_cell (all species densities of the cell) and E_ion matter only for the
+    full Lorentz width."""
+    st, lt = SpeciesTable(species, E_ion), LineTable(lines)
     p = _Pair()
     h = grid_step(grid)
-    lib().orc_line_pair(C.byref(st.s), C.byref(lt.s), int(i), Ttr, Tv, ne, N_s, Q_s,
-                        grid.nu_min, h, grid.n_points, C.byref(p))
+    Nc = np.ascontiguousarray(np.zeros(len(species)) if N_cell is None else N_cell, np.float64)
+    lib().orc_line_pair(C.byref(st.s), C.byref(lt.s), int(i), Ttr, Tv, ne, _p(Nc), len(species),
+                        N_s, Q_s, grid.nu_min, h, grid.n_points, C.byref(p))
     return {f: getattr(p, f) for f, _ in _Pair._fields_}
 
 
@@ -252,12 +262,13 @@ def grid_step(grid) -> float:
 # eta / kappa (Sec. 2.2.1) for all cells at grid indices ks
 # ---------------------------------------------------------------------------
 
-def coeffs(species, lines, cells, grid, ks: Optional[np.ndarray] = None, threads: int = 0):
+def coeffs(species, lines, cells, grid, ks: Optional[np.ndarray] = None, threads: int = 0,
+           E_ion=None):
     """Returns (eta [n_cells, n_k], kappa [n_cells, n_k], n_terms)."""
     if ks is None:
         ks = np.arange(grid.n_points, dtype=np.int64)
     ks = np.ascontiguousarray(ks, np.int64)
-    st, lt, ct = SpeciesTable(species), LineTable(lines), CellTable(cells)
+    st, lt, ct = SpeciesTable(species, E_ion), LineTable(lines), CellTable(cells)
     eta = np.zeros((cells.n, ks.size))
     kap = np.zeros((cells.n, ks.size))
     n = lib().orc_coeffs(C.byref(st.s), C.byref(lt.s), C.byref(ct.s), grid.nu_min, grid.nu_max,
@@ -265,7 +276,7 @@ def coeffs(species, lines, cells, grid, ks: Optional[np.ndarray] = None, threads
     return eta, kap, n
 
 
-def knife_edges(species, lines, cells, grid, tol: float = 1e-9, near=None):
+def knife_edges(species, lines, cells, grid, tol: float = 1e-9, near=None, E_ion=None):
     """(cell, k) grid points next to a window bound that lies within tol grid
     steps of an integer grid index: a last-bit difference in the Voigt
     width may move such a bound by one point.  near: optional sorted grid
@@ -279,7 +290,7 @@ def knife_edges(species, lines, cells, grid, tol: float = 1e-9, near=None):
         np.add.at(keep, lo, 1)
         np.add.at(keep, hi, -1)
         lines = lines.subset(np.nonzero(np.cumsum(keep)[:-1] > 0)[0])
-    st, lt, ct = SpeciesTable(species), LineTable(lines), CellTable(cells)
+    st, lt, ct = SpeciesTable(species, E_ion), LineTable(lines), CellTable(cells)
     cap = 4096
     cc = np.zeros(cells.n * cap, np.int64)
     kk = np.zeros(cells.n * cap, np.int64)
@@ -320,8 +331,8 @@ def continuum(species, cells, grid, cont, ks: Optional[np.ndarray] = None):
     return eta, kap
 
 
-def coeffs_bruteforce(species, lines, cells, grid):
-    st, lt, ct = SpeciesTable(species), LineTable(lines), CellTable(cells)
+def coeffs_bruteforce(species, lines, cells, grid, E_ion=None):
+    st, lt, ct = SpeciesTable(species, E_ion), LineTable(lines), CellTable(cells)
     eta = np.zeros((cells.n, grid.n_points))
     kap = np.zeros((cells.n, grid.n_points))
     lib().orc_coeffs_bruteforce(C.byref(st.s), C.byref(lt.s), C.byref(ct.s), grid.nu_min,
@@ -507,7 +518,8 @@ def solve_slab(wl, ks=None, threads: int = 0):
     """Whole path for a slab workload: eta/kappa at ks, I per ray, spectral
     integral per ray (trapezoid over ks; exact when ks is the full grid) and
     the tangent-slab flux q = 2 pi sum_i W_i mu_i I_int(mu_i)."""
-    eta, kap, n_terms = coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks, threads)
+    eta, kap, n_terms = coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks, threads,
+                               getattr(wl, "lorentz_E_ion", None))
     rays, mu, W = slab_rays(wl.geometry)
     I = np.stack([march(c, d, eta, kap) for c, d in rays])
     w = trapezoid_weights(wl.grid, ks)
@@ -519,7 +531,8 @@ def solve_slab(wl, ks=None, threads: int = 0):
 def solve_axi(wl, wall_indices: Sequence[int], ks=None, threads: int = 0):
     """Axisymmetric workload at the given wall points: per-point spectral
     flux q_k = sum_rays w_ray I_ray(k) and, over ks, q = sum_k w_k q_k."""
-    eta, kap, n_terms = coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks, threads)
+    eta, kap, n_terms = coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks, threads,
+                               getattr(wl, "lorentz_E_ion", None))
     w = trapezoid_weights(wl.grid, ks)
     out = []
     for wi in wall_indices:

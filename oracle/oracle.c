@@ -52,6 +52,9 @@ typedef struct {
     /* vibrational levels of electronic state e: vib_off[e] .. vib_off[e+1]-1 */
     const int64_t *vib_off;
     const double *vib_G, *vib_B, *vib_D;
+    /* ionization energies, cm^-1, per species: an atom with E_ion > 0 gives
+     * its lines the full Lorentz width (NULL: the uniform Stark law for all) */
+    const double *E_ion;
 } orc_species;
 
 typedef struct {
@@ -153,6 +156,39 @@ double orc_lorentz_hwhm(double ne, double Tv)
     return 1e-16 * ne * pow(Tv / 1e4, 0.33);
 }
 
+/* Lorentz HWHM of line i in a cell with the per-species densities N_cell
+ * (Sec. 2.2.1 pressure broadening).  An atom with an ionization energy gets
+ * the sum of natural (5.9e-6 nm), Stark
+ * (1.69e3 lambda^2 / dE^2.623 (T_ee/1e4)^0.33 (N_e/1e16), dE = max(E_ion - E_u,
+ * E_ion(H)/25)) and van der Waals (lambda^2 [6.65e-29 N (2 T_t/M)^0.5 +
+ * 2.925e-29 N_others (2 T_t/M_others)^0.5]) widths in nm at lambda = 1e7/nu0 nm,
+ * converted to cm^-1 by dnu = 1e7 dlambda / lambda^2; resonance broadening is
+ * left out.  N_others: every other species but the electrons (M < 0.01 g/mol),
+ * M_others their density-weighted mean molar mass.  Other lines: the uniform
+ * Stark law. */
+#define ORC_E_H 109678.77   /* ionization energy of hydrogen, cm^-1 */
+double orc_lorentz_line(const orc_species *sp, const orc_lines *L, int64_t i, double Ttr,
+                        double Tv, double ne, const double *N_cell, int S)
+{
+    int s = L->species[i];
+    if (!sp->E_ion || !(sp->E_ion[s] > 0.0) || sp->kind[s] != 1) return orc_lorentz_hwhm(ne, Tv);
+    double lam = 1e7 / L->nu0[i];   /* nm */
+    double dl_N = 5.9e-6;
+    double Eu = L->Eu_ev[i] + L->Eu_rot[i];
+    double dE = fmax(sp->E_ion[s] - Eu, ORC_E_H / 25.0);
+    double dl_S = 1.69e3 * lam * lam / pow(dE, 2.623) * pow(Tv / 1e4, 0.33) * (ne / 1e16);
+    double Noth = 0.0, NMoth = 0.0;
+    for (int t = 0; t < S; ++t) {
+        if (t == s || sp->mass[t] < 0.01) continue;
+        Noth += N_cell[t];
+        NMoth += N_cell[t] * sp->mass[t];
+    }
+    double lw0 = 6.65e-29 * N_cell[s] * sqrt(2.0 * Ttr / sp->mass[s]);
+    if (Noth > 0.0) lw0 += 2.925e-29 * Noth * sqrt(2.0 * Ttr / (NMoth / Noth));
+    double dl_W = lw0 * lam * lam;
+    return 1e7 * (dl_N + dl_S + dl_W) / (lam * lam);
+}
+
 /* Voigt HWHM (Olivero-type fit) from the Lorentz and Doppler HWHMs. */
 double orc_voigt_hwhm(double gL, double gG)
 {
@@ -207,8 +243,8 @@ double orc_planck(double nu, double T)
 /* ---------------------------------------------------------------------- */
 
 void orc_line_pair(const orc_species *sp, const orc_lines *L, int64_t i,
-                   double Ttr, double Tv, double ne, double N_s, double Q_s,
-                   double nu_min, double h, int64_t n_points, orc_pair *p)
+                   double Ttr, double Tv, double ne, const double *N_cell, int S, double N_s,
+                   double Q_s, double nu_min, double h, int64_t n_points, orc_pair *p)
 {
     int s = L->species[i];
     double nu0 = L->nu0[i];
@@ -220,7 +256,7 @@ void orc_line_pair(const orc_species *sp, const orc_lines *L, int64_t i,
     p->B_line = 1e-7 * 2.0 * ORC_H * ORC_C * ORC_C * nu0 * nu0 * nu0
                 / (p->Nl * L->gu[i] / (p->Nu * L->gl[i]) - 1.0);
     p->gG = orc_doppler_hwhm(nu0, Ttr, sp->mass[s]);
-    p->gL = orc_lorentz_hwhm(ne, Tv);
+    p->gL = orc_lorentz_line(sp, L, i, Ttr, Tv, ne, N_cell, S);
     p->gV = orc_voigt_hwhm(p->gL, p->gG);
     orc_window(nu0, p->gV, nu_min, h, n_points, &p->klo, &p->khi);
 }
@@ -269,8 +305,14 @@ int64_t orc_cell_coeffs(const orc_species *sp, const orc_lines *L, const orc_cel
     if (n_k == 0 || L->n == 0) { free(Q); return 0; }
 
     /* Skip bound: a line reaches nu only if |nu - nu0| <= 100 (gL + b nu0),
-     * b = Doppler coefficient at the lightest radiator. Widened by 1e-6. */
-    const double gL = orc_lorentz_hwhm(ne, Tv);
+     * gL the largest Lorentz HWHM of any line in this cell, b = Doppler
+     * coefficient at the lightest radiator. Widened by 1e-6. */
+    double gL = orc_lorentz_hwhm(ne, Tv);
+    if (sp->E_ion)
+        for (int64_t i = 0; i < L->n; ++i) {
+            double gi = orc_lorentz_line(sp, L, i, Ttr, Tv, ne, N, S);
+            if (gi > gL) gL = gi;
+        }
     const double b = 7.16233e-7 / 2.0 * sqrt(Ttr / Mmin) * (1.0 + 1e-6);
     const double g = 100.0 * gL * (1.0 + 1e-6) + h;
     const double a = 100.0 * b;
@@ -296,7 +338,7 @@ int64_t orc_cell_coeffs(const orc_species *sp, const orc_lines *L, const orc_cel
             int s = L->species[i];
             if (sp->kind[s] == 0 || N[s] <= 0.0) continue;
             orc_pair p;
-            orc_line_pair(sp, L, i, Ttr, Tv, ne, N[s], Q[s], nu_min, h, n_points, &p);
+            orc_line_pair(sp, L, i, Ttr, Tv, ne, N, S, N[s], Q[s], nu_min, h, n_points, &p);
             if (p.klo > p.khi) continue;
             int64_t a0 = lower_bound_i(ks, n_k, p.klo);
             for (int64_t t = a0; t < n_k && ks[t] <= p.khi; ++t) {
@@ -348,7 +390,8 @@ void orc_coeffs_bruteforce(const orc_species *sp, const orc_lines *L, const orc_
             if (sp->kind[s] == 0 || Ns <= 0.0) continue;
             double Q = orc_partition(sp, s, C->T_v[c], C->T_tr[c]);
             orc_pair p;
-            orc_line_pair(sp, L, i, C->T_tr[c], C->T_v[c], C->n_e[c], Ns, Q, nu_min, h, n_points, &p);
+            orc_line_pair(sp, L, i, C->T_tr[c], C->T_v[c], C->n_e[c], C->N + c * S, S, Ns, Q, nu_min, h,
+                          n_points, &p);
             for (int64_t k = 0; k < n_points; ++k) {
                 double delta = orc_grid_offset(nu_min, h, k, L->nu0[i]);
                 if (fabs(delta) > 100.0 * p.gV) continue;
@@ -621,7 +664,7 @@ void orc_knife_edges(const orc_species *sp, const orc_lines *L, const orc_cells 
             double Ns = C->N[c * S + s];
             if (sp->kind[s] == 0 || Ns <= 0.0) continue;
             double gG = orc_doppler_hwhm(L->nu0[i], C->T_tr[c], sp->mass[s]);
-            double gL = orc_lorentz_hwhm(C->n_e[c], C->T_v[c]);
+            double gL = orc_lorentz_line(sp, L, i, C->T_tr[c], C->T_v[c], C->n_e[c], C->N + c * S, S);
             double W = 100.0 * orc_voigt_hwhm(gL, gG);
             double b[2] = {(L->nu0[i] - W - nu_min) / h, (L->nu0[i] + W - nu_min) / h};
             for (int e = 0; e < 2; ++e) {

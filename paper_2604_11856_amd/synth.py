@@ -158,6 +158,10 @@ class Workload:
     geometry: object
     meta: Dict = dataclasses.field(default_factory=dict)
     continuum: Optional[List[Continuum]] = None
+    # per-species ionization energies (cm^-1) giving atomic lines the full
+    # Lorentz width (natural + per-line Stark + van der Waals); None: the
+    # uniform Stark law for every line
+    lorentz_E_ion: Optional[np.ndarray] = None
 
 
 # --------------------------------------------------------------------------
@@ -209,6 +213,13 @@ def air_continuum(species: List[Species], seed: int = 11862) -> List[Continuum]:
         out.append(Continuum(a, names.index(atom + "+"), ION_ENERGY_CM[atom], ION_Q[atom + "+"],
                              s0, np.array(PEACH_FF[atom], np.float64), 1.0))
     return out
+
+
+def air_ionization_energies(species: List[Species]) -> np.ndarray:
+    """Per-species ionization energies for the full Lorentz width: the textbook
+    values for the atoms N and O, 0 for every other species."""
+    return np.array([ION_ENERGY_CM.get(sp.name, 0.0) if sp.kind == KIND_ATOM else 0.0
+                     for sp in species], np.float64)
 
 
 def none_species(name: str) -> Species:

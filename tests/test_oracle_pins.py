@@ -832,3 +832,100 @@ def test_continuum_depends_on_electron_temperature_only():
     c3 = synth.Cells(cells.T_tr, np.array([9500.0]), cells.N, cells.n_e)
     e3, _ = O.continuum(sp, c3, grid, cont, ks)
     assert np.max(np.abs(e3 / e1 - 1)) > 1e-3
+
+
+# ----------------------------------------------------------------------------
+# Full Lorentz width of atomic lines (Sec. 2.2.1 pressure broadening)
+# ----------------------------------------------------------------------------
+
+E_H = 109678.77
+
+
+def _lorentz(species, lines, i, Ttr, Tv, ne, N_cell, E_ion):
+    grid = synth.Grid(1000.0, 100000.0, 1001, 1001)
+    return O.line_pair(species, lines, i, Ttr, Tv, ne, N_cell[lines.species[i]], 1.0, grid,
+                       N_cell=N_cell, E_ion=E_ion)["gL"]
+
+
+def _atom_lines():
+    rng = np.random.Generator(np.random.PCG64(8))
+    sp = [synth.atom_species(rng, "N"), synth.molecule_species(rng, "N2", 4), synth.none_species("e-")]
+    nu0 = np.array([15000.0, 20000.0, 30000.0, 40000.0])
+    Eu = np.array([95000.0, 95000.0, 114000.0, 30000.0])
+    spc = np.array([0, 0, 0, 1], np.int32)
+    lines = synth.Lines(nu0, np.full(4, 1e7), Eu, np.zeros(4), Eu - nu0, np.zeros(4),
+                        np.full(4, 4.0), np.full(4, 2.0), spc)
+    E_ion = np.array([117225.7, 0.0, 0.0])
+    return sp, lines, E_ion
+
+
+def test_lorentz_natural_width():
+    """No electrons and no perturbers: the natural width 5.9e-6 nm, i.e.
+    5.9e-6 * 1e7 / lambda^2 = 5.9e-13 nu0^2 cm^-1."""
+    sp, lines, E_ion = _atom_lines()
+    for i in range(3):
+        g = _lorentz(sp, lines, i, 8000.0, 8000.0, 0.0, np.zeros(3), E_ion)
+        assert abs(g - 5.9e-13 * lines.nu0[i] ** 2) <= 1e-14 * g
+
+
+def test_lorentz_stark_width():
+    """Stark part in cm^-1: the printed lambda^2 cancels against the nm -> cm^-1
+    conversion, leaving 1.69e10 / dE^2.623 (T/1e4)^0.33 (N_e/1e16) with
+    dE = max(E_ion - E_u, E_H/25): the same for two lines of one upper level,
+    linear in N_e, floored near the ionization limit."""
+    sp, lines, E_ion = _atom_lines()
+    nat = lambda i: 5.9e-13 * lines.nu0[i] ** 2
+    gs = [_lorentz(sp, lines, i, 9000.0, 12000.0, 3e16, np.zeros(3), E_ion) - nat(i) for i in range(3)]
+    dE = 117225.7 - 95000.0
+    ref = 1.69e10 / dE**2.623 * (12000.0 / 1e4) ** 0.33 * 3.0
+    assert abs(gs[0] - ref) <= 1e-12 * ref and abs(gs[1] - ref) <= 1e-12 * ref
+    ref2 = 1.69e10 / (E_H / 25.0) ** 2.623 * (12000.0 / 1e4) ** 0.33 * 3.0   # E_u above E_ion - E_H/25
+    assert abs(gs[2] - ref2) <= 1e-12 * ref2
+    g6 = _lorentz(sp, lines, 0, 9000.0, 12000.0, 6e16, np.zeros(3), E_ion) - nat(0)
+    assert abs(g6 / gs[0] - 2.0) < 1e-12
+    # the paper's comparison: at 10,000 K and 1.6e17 cm^-3 Stark dominates
+    N = np.array([1e17, 1e17, 1.6e17])
+    g = _lorentz(sp, lines, 0, 1e4, 1e4, 1.6e17, N, E_ion)
+    g0 = _lorentz(sp, lines, 0, 1e4, 1e4, 0.0, N, E_ion)
+    assert (g - g0) > 10.0 * g0
+
+
+def test_lorentz_van_der_waals_width():
+    """Van der Waals part: 1e7 [6.65e-29 N sqrt(2 T/M) + 2.925e-29 N_others
+    sqrt(2 T/M_others)] cm^-1, electrons not counted among the perturbers."""
+    sp, lines, E_ion = _atom_lines()
+    T = 7000.0
+    N = np.array([2e17, 5e16, 3e16])   # N atoms, N2, electrons
+    g = _lorentz(sp, lines, 1, T, 15000.0, 0.0, N, E_ion) - 5.9e-13 * lines.nu0[1] ** 2
+    ref = 1e7 * (6.65e-29 * 2e17 * math.sqrt(2 * T / 14.0) + 2.925e-29 * 5e16 * math.sqrt(2 * T / 28.0))
+    assert abs(g - ref) <= 1e-12 * ref
+
+
+def test_lorentz_uniform_law_elsewhere():
+    """Molecular lines, atoms without an ionization energy and E_ion = None keep
+    the uniform Stark law 1e-16 n_e (T_v/1e4)^0.33."""
+    sp, lines, E_ion = _atom_lines()
+    N = np.array([1e17, 1e17, 1e16])
+    u = 1e-16 * 1e16 * (11000.0 / 1e4) ** 0.33
+    assert abs(_lorentz(sp, lines, 3, 9000.0, 11000.0, 1e16, N, E_ion) - u) <= 1e-15 * u
+    assert abs(_lorentz(sp, lines, 0, 9000.0, 11000.0, 1e16, N, None) - u) <= 1e-15 * u
+    assert abs(_lorentz(sp, lines, 0, 9000.0, 11000.0, 1e16, N, np.zeros(3)) - u) <= 1e-15 * u
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_full_lorentz_sum_vs_bruteforce(seed):
+    """With per-line Lorentz widths the pruned sum (skip bound from the cell's
+    largest width) equals brute force over every (line, point) bitwise."""
+    wl = synth.stagnation_line(n_cells=3, n_atomic=300, n_rovib=300, n_points=3000,
+                               band_points=3000, n_mu=0, seed=seed)
+    wl.cells.n_e[:] = [3e17, 1e16, 2e18]   # Stark widths that dominate the windows
+    E_ion = synth.air_ionization_energies(wl.species)
+    e, k, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid, E_ion=E_ion)
+    eb, kb = O.coeffs_bruteforce(wl.species, wl.lines, wl.cells, wl.grid, E_ion=E_ion)
+    assert np.array_equal(e, eb) and np.array_equal(k, kb)
+    # isolated points: the skip bound alone decides which lines are visited
+    ks = np.arange(7, 3000, 397)
+    es, kss, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks, E_ion=E_ion)
+    assert np.array_equal(es, eb[:, ks]) and np.array_equal(kss, kb[:, ks])
+    e0, _, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
+    assert np.max(np.abs(e - e0)) > 0
