@@ -145,6 +145,20 @@ lrt_status lrt_set_grid(lrt_ctx *ctx, double nu_min, double nu_max, int64_t n_po
  * n_e < 0), LRT_E_STATE (no species). */
 lrt_status lrt_set_cells(lrt_ctx *ctx, const lrt_cells *cells);
 
+/* Lorentz width of atomic lines (Sec. 2.2.1 pressure broadening).  With
+ * E_ion == NULL (the default) every line has gamma_L = 1e-16 n_e (T_v/1e4)^0.33
+ * cm^-1.  With E_ion[s] > 0 (cm^-1, host, [n_species]) the lines of atom s get
+ * the sum of the natural width 5.9e-6 nm, the Stark width
+ * 1.69e3 lambda^2 / dE^2.623 (T_v/1e4)^0.33 (n_e/1e16) nm with
+ * dE = max(E_ion - E_u, E_ion(H)/25), and the van der Waals width
+ * lambda^2 [6.65e-29 N_s (2 T_tr/M_s)^0.5 + 2.925e-29 N_o (2 T_tr/M_o)^0.5] nm
+ * (N_o, M_o: the other species but electrons, density-weighted molar mass),
+ * each converted to cm^-1 by dnu = 1e7 dlambda / lambda^2 (lambda = 1e7/nu0
+ * nm); resonance broadening is left out.  Other lines keep the uniform law.
+ * Kept until changed; new species clear it.  Errors: LRT_E_STATE (no
+ * species), LRT_E_ARG (negative or non-finite E_ion). */
+lrt_status lrt_set_lorentz(lrt_ctx *ctx, const double *E_ion);
+
 /* Atomic continuum of one atom (Sec. 2.2.1 bound-free and free-free), added
  * to eta and kappa of every cell and grid point by lrt_coeffs and lrt_solve.
  * With T = T_v (the electron temperature), N_a, N_+ the cell's densities of

@@ -35,8 +35,27 @@ namespace {
 // a1: partition functions and per-cell constants (FP64)
 // ---------------------------------------------------------------------------
 
-__global__ void thermo_kernel(DevSpecies sp, DevCells cells, double M_min, uint64_t mask,
-                              CellConst *cc, CellSpecies *cs)
+// van der Waals HWHM (cm^-1) of the lines of atom s in cell c: the printed
+// lambda^2 [6.65e-29 N_s (2T/M_s)^0.5 + 2.925e-29 N_o (2T/M_o)^0.5] nm times
+// 1e7/lambda^2; N_o, M_o over the other species but electrons (M < 0.01).
+__device__ double vdw_width(const DevSpecies &sp, const DevCells &cells, int c, int s)
+{
+    const int S = cells.n_species;
+    const double Ttr = cells.T_tr[c];
+    double No = 0.0, NMo = 0.0;
+    for (int t = 0; t < S; ++t) {
+        if (t == s || sp.mass[t] < 0.01) continue;
+        const double n = cells.N[(int64_t)c * S + t];
+        No += n;
+        NMo += n * sp.mass[t];
+    }
+    double w = 6.65e-29 * cells.N[(int64_t)c * S + s] * sqrt(2.0 * Ttr / sp.mass[s]);
+    if (No > 0.0) w += 2.925e-29 * No * sqrt(2.0 * Ttr / (NMo / No));
+    return 1e7 * w;
+}
+
+__global__ void thermo_kernel(DevSpecies sp, DevCells cells, DevWidths wd, double M_min,
+                              uint64_t mask, CellConst *cc, CellSpecies *cs)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int S = cells.n_species;
@@ -70,6 +89,7 @@ __global__ void thermo_kernel(DevSpecies sp, DevCells cells, double M_min, uint6
     const bool on = mask == 0 || (s < 64 && ((mask >> s) & 1ull));
     o.lnNQ = (on && kind != 0 && N > 0.0 && Q > 0.0) ? log(N) - log(Q) : -INFINITY;
     o.dop = 7.16233e-7 / 2.0 * sqrt(Ttr / sp.mass[s]);
+    o.gW = (wd.E_ion && kind == 1 && wd.E_ion[s] > 0.0) ? vdw_width(sp, cells, c, s) : 0.0;
     cs[t] = o;
     if (s == 0) {
         CellConst k;
@@ -77,7 +97,12 @@ __global__ void thermo_kernel(DevSpecies sp, DevCells cells, double M_min, uint6
         k.beta_tr = br;
         k.gL = 1e-16 * cells.n_e[c] * pow(Tv / 1e4, 0.33);
         // Voigt HWHM <= gL + gG, gG = dop(M) nu0 <= dop(M_min) nu0; widened.
-        k.cand_G = 100.0 * k.gL * (1.0 + 1e-6);
+        // gL of any line <= gN_max + gS_max gL(c) + the largest van der Waals width.
+        double gWmax = 0.0;
+        if (wd.E_ion)
+            for (int s2 = 0; s2 < S; ++s2)
+                if (sp.kind[s2] == 1 && wd.E_ion[s2] > 0.0) gWmax = fmax(gWmax, vdw_width(sp, cells, c, s2));
+        k.cand_G = 100.0 * (wd.gN_max + wd.gS_max * k.gL + gWmax) * (1.0 + 1e-6);
         k.cand_A = 100.0 * (7.16233e-7 / 2.0) * sqrt(Ttr / M_min) * (1.0 + 1e-6);
         cc[c] = k;
     }
@@ -127,7 +152,7 @@ __device__ __forceinline__ bool pair_setup(const DevLines &L, const DevGrid &g, 
     const double Skap = L.skap0[i] * Nlx;
     // widths (Sec. 2.2.1): Doppler, Lorentz, Voigt (Olivero fit)
     const double gG = q.dop * nu0;
-    const double gL = k.gL;
+    const double gL = L.gN[i] + L.gS[i] * k.gL + q.gW;
     const double sum = gL + gG;
     const double d = (gL - gG) / sum;
     const double gV = (1.0 - 0.18121 * (1.0 - d * d)
@@ -883,12 +908,12 @@ __global__ __launch_bounds__(256) void serve_combine_kernel(ServeReq R, DevGrid 
 // launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_thermo(const DevSpecies &sp, const DevCells &cells, double M_min,
+hipError_t launch_thermo(const DevSpecies &sp, const DevCells &cells, const DevWidths &wd, double M_min,
                          uint64_t species_mask, CellConst *cc, CellSpecies *cs, hipStream_t st)
 {
     const int64_t n = (int64_t)cells.n_cells * cells.n_species;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(thermo_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, st, sp, cells, M_min,
+    hipLaunchKernelGGL(thermo_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, st, sp, cells, wd, M_min,
                        species_mask, cc, cs);
     return hipGetLastError();
 }

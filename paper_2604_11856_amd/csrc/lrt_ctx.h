@@ -60,6 +60,14 @@ struct lrt_ctx {
     int64_t n_lines = -1;
     std::vector<double> h_nu0;   // sorted centres, host copy for k0/frac0
     DBuf d_nu0, d_seta0, d_skap0, d_Eu_ev, d_Eu_rot, d_El_ev, d_El_rot, d_lngu, d_species, d_k0, d_frac0;
+    std::vector<int32_t> h_spc;   // sorted order: species and upper-level energy
+    std::vector<double> h_Eu;
+
+    // Lorentz widths: per-species ionization energies (empty: uniform law),
+    // per-line natural width and Stark coefficient
+    std::vector<double> h_Eion;
+    DBuf d_Eion, d_gN, d_gS;
+    double gN_max = 0.0, gS_max = 1.0;
     bool lines_grid_ready = false;
 
     // grid
@@ -123,6 +131,11 @@ lrt_status prepare_lines(lrt_ctx *c);
 // Lines on the grid, per-cell constants (and scales when need_scale).
 lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force = false);
 DevLines dev_lines(const lrt_ctx *c);
+inline DevWidths dev_widths(const lrt_ctx *c)
+{
+    return DevWidths{c->h_Eion.empty() ? nullptr : c->d_Eion.as<double>(), c->gN_max, c->gS_max};
+}
+lrt_status line_widths(lrt_ctx *c);
 inline DevGrid dev_grid(const lrt_ctx *c)
 {
     return DevGrid{c->nu_min, c->h, (int32_t)c->n_points, 1.0 / c->h};

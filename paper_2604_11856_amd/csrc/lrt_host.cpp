@@ -344,6 +344,7 @@ lrt_status lrt_set_species(lrt_ctx *c, int n, const lrt_species *sp)
     c->h_lev_E = lev_E;
     c->h_lev_g = lev_g;
     c->n_cont_rec = c->n_cont_thr = 0;   // continuum records refer to the old table
+    c->h_Eion.clear();                   // so does the Lorentz model
     c->M_min = std::isfinite(M_min) ? M_min : 1.0;
     c->sp = DevSpecies{n, c->d_kind.as<int32_t>(), c->d_mass.as<double>(), c->d_lev_off.as<int64_t>(),
                        c->d_lev_E.as<double>(), c->d_lev_g.as<double>(), c->d_el_off.as<int64_t>(),
@@ -453,10 +454,31 @@ lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *L)
         (st = upload_vec(c, c->d_lngu, lngu)) || (st = upload_vec(c, c->d_species, spc)))
         return st;
     c->h_nu0.swap(nu0);
+    c->h_spc = spc;
+    c->h_Eu.resize(n);
+    for (int64_t j = 0; j < n; ++j) c->h_Eu[j] = Eue[j] + Eur[j];
     c->n_lines = n;
     c->lines_grid_ready = false;
     c->scale_ready = false;
-    return LRT_OK;
+    c->thermo_ready = false;
+    return line_widths(c);
+}
+
+lrt_status lrt_set_lorentz(lrt_ctx *c, const double *E_ion)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (c->n_species < 1) return fail(c, LRT_E_STATE, "set species before the Lorentz model");
+    std::vector<double> e;
+    if (E_ion) {
+        e.assign(E_ion, E_ion + c->n_species);
+        for (int s = 0; s < c->n_species; ++s)
+            if (!(e[s] >= 0.0) || !std::isfinite(e[s])) return fail(c, LRT_E_ARG, "E_ion[%d] must be >= 0", s);
+        lrt_status st = upload_vec(c, c->d_Eion, e);
+        if (st) return st;
+    }
+    c->h_Eion.swap(e);
+    return c->n_lines >= 0 ? line_widths(c) : LRT_OK;
 }
 
 lrt_status lrt_set_continuum(lrt_ctx *c, int n, const lrt_continuum *cont)
@@ -911,7 +933,7 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
         DevCells cells{(int32_t)c->n_cells, c->n_species, c->d_T_tr.as<double>(), c->d_T_v.as<double>(),
                        c->d_N.as<double>(), c->d_n_e.as<double>()};
         LRT_HIP(c, timed(c, LRT_K_THERMO, st, [&] {
-                    return launch_thermo(c->sp, cells, c->M_min, 0, c->d_cc.as<CellConst>(),
+                    return launch_thermo(c->sp, cells, dev_widths(c), c->M_min, 0, c->d_cc.as<CellConst>(),
                                          c->d_cs.as<CellSpecies>(), st);
                 }));
         if (c->n_cont_rec > 0) {
@@ -932,7 +954,8 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
         DevLines L{c->n_lines, c->d_nu0.as<double>(), c->d_Eu_ev.as<double>(),
                    c->d_Eu_rot.as<double>(), c->d_El_ev.as<double>(), c->d_El_rot.as<double>(),
                    c->d_lngu.as<double>(), c->d_seta0.as<double>(), c->d_skap0.as<double>(),
-                   c->d_species.as<int32_t>(), c->d_k0.as<int32_t>(), c->d_frac0.as<double>()};
+                   c->d_gN.as<double>(), c->d_gS.as<double>(), c->d_species.as<int32_t>(),
+                   c->d_k0.as<int32_t>(), c->d_frac0.as<double>()};
         DevGrid g = dev_grid(c);
         const DevBins B{(int32_t)c->n_bins, c->d_bin_sp.as<int32_t>(), c->d_bin_Ev.as<double>(),
                         c->d_bin_Er.as<double>(), c->d_bin_aeta.as<double>(), c->d_bin_akap.as<double>()};
@@ -947,12 +970,43 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
     return LRT_OK;
 }
 
+// Per-line natural width and Stark coefficient in cm^-1 (Sec. 2.2.1): for an
+// atom with an ionization energy, gN = 1e7 * 5.9e-6 nm / lambda^2 =
+// 5.9e-13 nu0^2 and gS = 1e7 * 1.69e3 / dE^2.623 (the lambda^2 of the nm-form
+// coefficient cancels against 1e7 / lambda^2), dE = max(E_ion - E_u, E_H/25);
+// every other line gN = 0, gS = 1 (the uniform law).
+lrt_status line_widths(lrt_ctx *c)
+{
+    const int64_t n = std::max<int64_t>(c->n_lines, 0);
+    constexpr double kEH = 109678.77;   // ionization energy of hydrogen, cm^-1
+    std::vector<double> gN(n, 0.0), gS(n, 1.0);
+    double gN_max = 0.0, gS_max = n > 0 ? 0.0 : 1.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int s = c->h_spc[i];
+        if (!c->h_Eion.empty() && c->sp_kind[s] == LRT_KIND_ATOM && c->h_Eion[s] > 0.0) {
+            const double nu0 = c->h_nu0[i];
+            const double dE = std::max(c->h_Eion[s] - c->h_Eu[i], kEH / 25.0);
+            gN[i] = 5.9e-13 * nu0 * nu0;
+            gS[i] = 1.69e10 / std::pow(dE, 2.623);
+        }
+        gN_max = std::max(gN_max, gN[i]);
+        gS_max = std::max(gS_max, gS[i]);
+    }
+    lrt_status st;
+    if ((st = upload_vec(c, c->d_gN, gN)) || (st = upload_vec(c, c->d_gS, gS))) return st;
+    c->gN_max = gN_max;
+    c->gS_max = gS_max;
+    c->thermo_ready = c->scale_ready = false;
+    return LRT_OK;
+}
+
 DevLines dev_lines(const lrt_ctx *c)
 {
     return DevLines{c->n_lines, c->d_nu0.as<double>(), c->d_Eu_ev.as<double>(),
                     c->d_Eu_rot.as<double>(), c->d_El_ev.as<double>(), c->d_El_rot.as<double>(),
                     c->d_lngu.as<double>(), c->d_seta0.as<double>(), c->d_skap0.as<double>(),
-                    c->d_species.as<int32_t>(), c->d_k0.as<int32_t>(), c->d_frac0.as<double>()};
+                    c->d_gN.as<double>(), c->d_gS.as<double>(), c->d_species.as<int32_t>(),
+                    c->d_k0.as<int32_t>(), c->d_frac0.as<double>()};
 }
 
 lrt_status band_range(lrt_ctx *c, int64_t band, int32_t &k_first, int32_t &n_band)

@@ -70,6 +70,9 @@ struct DevLines {
     // cell-independent strength factors: seta0 = 1e-7 (hc/4pi) nu0 A (W cm),
     // skap0 = A / (8 pi c nu0^2) (cm^2 s^-1 ... per unit population)
     const double *seta0, *skap0;
+    // Lorentz HWHM of line i in cell c: gN[i] + gS[i] gL(c) + gW(c, species),
+    // gL(c) = 1e-16 n_e (T_v/1e4)^0.33 (gN = 0, gS = 1, gW = 0: that law)
+    const double *gN, *gS;
     const int32_t *species;
     // grid-relative centre: nu0 = nu_min + k0 h + frac0 (frac0 exact to a
     // few units of its last place)
@@ -134,6 +137,14 @@ struct CellConst {
 struct CellSpecies {
     double lnNQ;   // ln(N_s / Q_s), -inf when the species carries no population
     double dop;    // Doppler HWHM per unit nu0: (7.16233e-7/2) sqrt(T_tr / M_s)
+    double gW;     // van der Waals HWHM of the species' lines, cm^-1 (0 unless full widths)
+};
+
+// Full Lorentz widths: per-species ionization energies (NULL: off) and the
+// largest per-line natural width and Stark coefficient (for the skip bound).
+struct DevWidths {
+    const double *E_ion;
+    double gN_max, gS_max;
 };
 
 // Rays on the device.
@@ -164,7 +175,7 @@ struct ServeItem {
 };
 
 // ---- kernel launchers (lrt_accum.hip, lrt_march.hip) ----
-hipError_t launch_thermo(const DevSpecies &sp, const DevCells &cells, double M_min,
+hipError_t launch_thermo(const DevSpecies &sp, const DevCells &cells, const DevWidths &wd, double M_min,
                          uint64_t species_mask, CellConst *cc, CellSpecies *cs, hipStream_t st);
 
 hipError_t launch_ranges(const DevLines &L, const DevGrid &g, const CellConst *cc,

@@ -253,7 +253,7 @@ bool lrt_server::admit(Req &r)
     const DevLines L = dev_lines(ctx);
     const DevGrid g = dev_grid(ctx);
     const DevCells cells{(int32_t)nc, S, T_tr, T_v, N, n_e};
-    if (!ok(launch_thermo(ctx->sp, cells, ctx->M_min, r.mask, cc, cs, st), "thermo") ||
+    if (!ok(launch_thermo(ctx->sp, cells, dev_widths(ctx), ctx->M_min, r.mask, cc, cs, st), "thermo") ||
         !ok(launch_ranges(L, g, cc, (int32_t)nc, r.k_first, r.n_window, kTilePoints, ranges, st), "ranges"))
         return true;
     // lines that can reach the window at all, for the per-cell scale

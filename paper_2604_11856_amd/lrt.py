@@ -29,7 +29,7 @@ _i64p = C.POINTER(C.c_int64)
 _vp = C.c_void_p
 
 EXPORTS = ["lrt_version", "lrt_status_string", "lrt_create", "lrt_destroy", "lrt_last_error",
-           "lrt_set_species", "lrt_set_lines", "lrt_set_grid", "lrt_set_cells", "lrt_set_continuum",
+           "lrt_set_species", "lrt_set_lines", "lrt_set_grid", "lrt_set_cells", "lrt_set_continuum", "lrt_set_lorentz",
            "lrt_set_rays_slab", "lrt_set_rays_axi", "lrt_set_rays_axi_fibonacci",
            "lrt_fibonacci_quadrature", "lrt_set_march", "lrt_set_far_temperature", "lrt_trace_axi_ray", "lrt_get_sizes", "lrt_get_ray",
            "lrt_coeffs", "lrt_march", "lrt_solve", "lrt_count_terms", "lrt_profile",
@@ -101,6 +101,7 @@ def lib():
             "lrt_set_grid": (st, [_vp, C.c_double, C.c_double, C.c_int64, C.c_int64]),
             "lrt_set_cells": (st, [_vp, C.POINTER(_Cells)]),
             "lrt_set_continuum": (st, [_vp, C.c_int, C.POINTER(_Continuum)]),
+            "lrt_set_lorentz": (st, [_vp, _dp]),
             "lrt_set_rays_slab": (st, [_vp, C.c_int64, _dp, C.c_int]),
             "lrt_set_rays_axi": (st, [_vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
                                       _dp, C.c_int, C.c_int]),
@@ -240,6 +241,15 @@ class Context:
                                 (C.c_double * 8)(*[float(v) for v in r.peach]), float(r.z))
         self._chk(self._L.lrt_set_continuum(self.h, len(records), arr))
 
+    def set_lorentz(self, E_ion):
+        """Per-species ionization energies (cm^-1) for the full Lorentz width of
+        atomic lines, or None for the uniform Stark law."""
+        if E_ion is None:
+            self._chk(self._L.lrt_set_lorentz(self.h, None))
+            return
+        e = np.ascontiguousarray(E_ion, np.float64)
+        self._chk(self._L.lrt_set_lorentz(self.h, _p(e)))
+
     def set_march(self, scheme: int):
         self._chk(self._L.lrt_set_march(self.h, int(scheme)))
 
@@ -254,6 +264,8 @@ class Context:
     def load(self, wl):
         """Species, lines, grid, cells and rays of a synth.Workload."""
         self.set_species(wl.species)
+        if getattr(wl, "lorentz_E_ion", None) is not None:
+            self.set_lorentz(wl.lorentz_E_ion)
         self.set_lines(wl.lines)
         self.set_grid(wl.grid)
         self.set_cells(wl.cells)
