@@ -1,6 +1,7 @@
 """Plain FP64 CPU oracle of the line-by-line + ray-march path of
-arXiv 2604.11856 (Sec. 2.1 populations, Sec. 2.2.1 line emission /
-absorption / Voigt shape, Sec. 2.2.3 march and flux integral).
+arXiv 2604.11856 (Sec. 2.1 populations, Boltzmann or QSS collisional-radiative,
+Sec. 2.2.1 line emission / absorption / Voigt shape and atomic continuum,
+Sec. 2.2.3 march and flux integral).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the package smoke check and the
 benchmark's CPU-baseline leg may import this package; the product path never
@@ -8,12 +9,14 @@ does.  It shares no code with the GPU library: it reads the same seeded
 inputs (paper_2604_11856_amd.synth) and nothing else.
 
 The arithmetic lives in oracle.c (plain loops in double precision); this file
-only marshals arrays and lays out the geometry (rays, quadrature weights),
-citing the passage each step follows.
+marshals arrays, lays out the geometry (rays, quadrature weights) and
+assembles the QSS collisional-radiative system of Sec. 2.1 in plain Python
+loops (solved by LAPACK's LU), citing the passage each step follows.
 """
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from typing import List, Optional, Sequence, Tuple
@@ -50,7 +53,8 @@ class _Species(C.Structure):
 
 class _Lines(C.Structure):
     _fields_ = [("n", C.c_int64), ("nu0", _dp), ("A", _dp), ("Eu_ev", _dp), ("Eu_rot", _dp),
-                ("El_ev", _dp), ("El_rot", _dp), ("gu", _dp), ("gl", _dp), ("species", _i32p)]
+                ("El_ev", _dp), ("El_rot", _dp), ("gu", _dp), ("gl", _dp), ("species", _i32p),
+                ("lev_u", _i32p), ("lev_l", _i32p)]
 
 
 class _Cont(C.Structure):
@@ -60,7 +64,7 @@ class _Cont(C.Structure):
 
 class _Cells(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_species", C.c_int), ("T_tr", _dp), ("T_v", _dp),
-                ("N", _dp), ("n_e", _dp)]
+                ("N", _dp), ("n_e", _dp), ("N_lev", _dp), ("lev_on", _ip)]
 
 
 class _Pair(C.Structure):
@@ -91,7 +95,7 @@ def lib():
             "orc_grid_offset": (d, [d, d, i64, d]),
             "orc_planck": (d, [d, d]),
             "orc_line_pair": (None, [C.POINTER(_Species), C.POINTER(_Lines), i64, d, d, d, _dp,
-                                     C.c_int, d, d, d, d, i64, C.POINTER(_Pair)]),
+                                     C.c_int, d, d, _dp, d, d, i64, C.POINTER(_Pair)]),
             "orc_lorentz_line": (d, [C.POINTER(_Species), C.POINTER(_Lines), i64, d, d, d, _dp,
                                      C.c_int]),
             "orc_coeffs": (i64, [C.POINTER(_Species), C.POINTER(_Lines), C.POINTER(_Cells),
@@ -170,26 +174,40 @@ class SpeciesTable:
 
 
 class LineTable:
-    def __init__(self, lines):
+    def __init__(self, lines, levels=None):
+        """levels: None, or [n_lines, 2] (upper, lower) level indices (-1: none)."""
         if lines.n > 1 and np.any(np.diff(lines.nu0) < 0):
             raise ValueError("oracle expects lines sorted by nu0")
         self.a = {f: np.ascontiguousarray(getattr(lines, f), np.float64)
                   for f in ("nu0", "A", "Eu_ev", "Eu_rot", "El_ev", "El_rot", "gu", "gl")}
         self.sp = np.ascontiguousarray(lines.species, np.int32)
+        self.lev = None
+        if levels is not None:
+            lev = np.asarray(levels, np.int32).reshape(lines.n, 2)
+            self.lev = (np.ascontiguousarray(lev[:, 0]), np.ascontiguousarray(lev[:, 1]))
         a = self.a
         self.s = _Lines(lines.n, _p(a["nu0"]), _p(a["A"]), _p(a["Eu_ev"]), _p(a["Eu_rot"]),
                         _p(a["El_ev"]), _p(a["El_rot"]), _p(a["gu"]), _p(a["gl"]),
-                        _p(self.sp, _i32p))
+                        _p(self.sp, _i32p),
+                        None if self.lev is None else _p(self.lev[0], _i32p),
+                        None if self.lev is None else _p(self.lev[1], _i32p))
 
 
 class CellTable:
-    def __init__(self, cells):
+    def __init__(self, cells, levels=None):
+        """levels: None, or (N_lev [n_cells, total levels], lev_on [n_species])."""
         self.T_tr = np.ascontiguousarray(cells.T_tr, np.float64)
         self.T_v = np.ascontiguousarray(cells.T_v, np.float64)
         self.N = np.ascontiguousarray(cells.N, np.float64)
         self.n_e = np.ascontiguousarray(cells.n_e, np.float64)
+        self.N_lev = self.lev_on = None
+        if levels is not None:
+            self.N_lev = np.ascontiguousarray(levels[0], np.float64)
+            self.lev_on = np.ascontiguousarray(levels[1], np.int32)
         self.s = _Cells(self.T_tr.shape[0], self.N.shape[1], _p(self.T_tr), _p(self.T_v),
-                        _p(self.N), _p(self.n_e))
+                        _p(self.N), _p(self.n_e),
+                        None if self.N_lev is None else _p(self.N_lev),
+                        None if self.lev_on is None else _p(self.lev_on, _ip))
 
 
 # ---------------------------------------------------------------------------
@@ -241,16 +259,21 @@ def planck(nu, T) -> float:
     return lib().orc_planck(nu, T)
 
 
-def line_pair(species, lines, i, Ttr, Tv, ne, N_s, Q_s, grid, N_cell=None, E_ion=None):
+def line_pair(species, lines, i, Ttr, Tv, ne, N_s, Q_s, grid, N_cell=None, E_ion=None,
+              line_levels=None, N_lev_s=None):
     """Per-(cell, line) quantities: populations, S_eta, B_line, widths, window.
     N_cell (all species densities of the cell) and E_ion matter only for the
-    full Lorentz width."""
-    st, lt = SpeciesTable(species, E_ion), LineTable(lines)
+    full Lorentz width; line_levels ([n_lines, 2]) with N_lev_s (the level
+    populations of the line's species in this cell) replace the Boltzmann
+    populations of a line that has levels."""
+    st, lt = SpeciesTable(species, E_ion), LineTable(lines, line_levels)
     p = _Pair()
     h = grid_step(grid)
     Nc = np.ascontiguousarray(np.zeros(len(species)) if N_cell is None else N_cell, np.float64)
+    Nl = None if N_lev_s is None else np.ascontiguousarray(N_lev_s, np.float64)
     lib().orc_line_pair(C.byref(st.s), C.byref(lt.s), int(i), Ttr, Tv, ne, _p(Nc), len(species),
-                        N_s, Q_s, grid.nu_min, h, grid.n_points, C.byref(p))
+                        N_s, Q_s, None if Nl is None else _p(Nl), grid.nu_min, h, grid.n_points,
+                        C.byref(p))
     return {f: getattr(p, f) for f, _ in _Pair._fields_}
 
 
@@ -259,16 +282,165 @@ def grid_step(grid) -> float:
 
 
 # ---------------------------------------------------------------------------
+# Sec. 2.1 collisional-radiative model, QSS form
+# ---------------------------------------------------------------------------
+
+N_AVOGADRO = 6.02214076e23   # mol^-1 (exact SI value)
+
+
+def arrhenius(C_a: float, n_a: float, E_a: float, T: float) -> float:
+    """Sec. 2.1 rate formula: k = C_a T^n_a exp(-E_a / T), E_a in K."""
+    return C_a * T ** n_a * math.exp(-E_a / T)
+
+
+def rate_temperature(a: float, T_tr: float, T_v: float) -> float:
+    """Characteristic temperature T_tr^a T_v^(1-a) of a rate."""
+    return T_tr ** a * T_v ** (1.0 - a)
+
+
+def state_partition(E: float, g: float, T: float) -> float:
+    """Partition function of one atomic state, g e^{-c2 E / T} (energy zero
+    at the atom's ground state)."""
+    return g * math.exp(-c2() * E / T)
+
+
+def cr_system(rec, species, T_tr: float, T_v: float, N_cell, n_e: float, collider_w):
+    """The QSS system R n = b of Sec. 2.1 for one atom (CR record rec) in one
+    cell, n = populations of levels 0..l-1 of its level table (level 0 the
+    ground state, l = rec.n_model).
+
+    Row 0 is the closure: the populations of all levels add up to the atom's
+    density, the levels p >= l standing in Boltzmann ratio Q_p/Q_(l-1) (at
+    T_v) with level l-1.  Row i >= 1 is the QSS balance of level i: R[i, i]
+    holds minus every loss rate of i (heavy-particle and electron impact
+    transitions to every other level, spontaneous emission to lower levels
+    with escape factor 0 above nu_cut and 1 below, electron impact
+    ionization, charge exchange with the partner ion), R[i, j] the rate of
+    every process taking level j to level i, and b[i] minus the sources from
+    outside the atom (three-body recombination of the ion, charge exchange
+    of the ion with the partner atom).  Two-body rates are the Arrhenius
+    coefficient over Avogadro's number times the collider density (heavy
+    colliders: sum_s collider_w[s] N_s); reverse rates follow the paper's
+    detailed-balance relation evaluated at the backward temperature, with
+    the state partition functions g e^{-c2 E/T}, the ion's Q_ion
+    e^{-c2 E_ion/T} and the free electron's 2 (2 pi m_e k T / h^2)^{3/2}."""
+    sp = species[rec.species]
+    E, g = np.asarray(sp.level_E, np.float64), np.asarray(sp.level_g, np.float64)
+    Lm, Ls = int(rec.n_model), E.size
+    NA = N_AVOGADRO
+    N_cell = np.asarray(N_cell, np.float64)
+    N_M = sum(float(collider_w[s]) * float(N_cell[s]) for s in range(N_cell.size))
+    N_ion = float(N_cell[rec.ion]) if rec.ion >= 0 else 0.0
+    Tm = [(rate_temperature(rec.texp[2 * m], T_tr, T_v),
+           rate_temperature(rec.texp[2 * m + 1], T_tr, T_v)) for m in range(4)]
+    Q = lambda i, T: state_partition(E[i], g[i], T)
+
+    def k_exc(table, m, i, j):
+        """rate coefficient of the transition i -> j of mechanism m (0 HPIE, 1 EIE)"""
+        T_f, T_b = Tm[m]
+        if j > i:
+            return arrhenius(*table[i, j], T_f)
+        return arrhenius(*table[j, i], T_b) * Q(j, T_b) / Q(i, T_b)
+
+    def escape(hi, lo):
+        return 0.0 if E[hi] - E[lo] > rec.nu_cut else 1.0
+
+    R = np.zeros((Lm, Lm))
+    b = np.zeros(Lm)
+    R[0, :] = 1.0
+    R[0, Lm - 1] = 1.0 + sum(Q(p, T_v) / Q(Lm - 1, T_v) for p in range(Lm, Ls))
+    b[0] = float(N_cell[rec.species])
+    for i in range(1, Lm):
+        loss = 0.0
+        for m in range(Lm):
+            if m != i:
+                loss += k_exc(rec.hpie, 0, i, m) / NA * N_M + k_exc(rec.eie, 1, i, m) / NA * n_e
+        for m in range(i):
+            loss += escape(i, m) * rec.A[i, m]
+        loss += arrhenius(*rec.eii[i], Tm[2][0]) / NA * n_e
+        if rec.partner >= 0:
+            loss += arrhenius(*rec.ce[i], Tm[3][0]) / NA * float(N_cell[rec.partner_ion])
+        R[i, i] = -loss
+        for j in range(Lm):
+            if j == i:
+                continue
+            gain = k_exc(rec.hpie, 0, j, i) / NA * N_M + k_exc(rec.eie, 1, j, i) / NA * n_e
+            if j > i:
+                gain += escape(j, i) * rec.A[j, i]
+            R[i, j] = gain
+        T_b = Tm[2][1]
+        k_rec = (arrhenius(*rec.eii[i], T_b) * Q(i, T_b)
+                 / (rec.Q_ion * math.exp(-c2() * rec.E_ion / T_b) * (2.0 / saha_volume(T_b))))
+        src = k_rec / NA * N_ion * n_e * n_e
+        if rec.partner >= 0:
+            T_b = Tm[3][1]
+            pb = species[rec.partner]
+            Q_B = sum(state_partition(pb.level_E[k], pb.level_g[k], T_b) for k in range(len(pb.level_E)))
+            Q_Bp = rec.partner_Q_ion * math.exp(-c2() * rec.partner_E_ion / T_b)
+            Q_Ap = rec.Q_ion * math.exp(-c2() * rec.E_ion / T_b)
+            k_b = arrhenius(*rec.ce[i], T_b) * Q(i, T_b) * Q_Bp / (Q_Ap * Q_B)
+            src += k_b / NA * N_ion * float(N_cell[rec.partner])
+        b[i] = -src
+    return R, b
+
+
+def cr_level_populations(rec, species, T_tr, T_v, N_cell, n_e, collider_w):
+    """Populations of every level of the atom's table in one cell: levels
+    0..l-1 from the LU solution of R n = b (LAPACK's partially pivoted LU),
+    the levels above from their Boltzmann ratio to level l-1 at T_v."""
+    R, b = cr_system(rec, species, T_tr, T_v, N_cell, n_e, collider_w)
+    n = np.linalg.solve(R, b)
+    sp = species[rec.species]
+    Lm = int(rec.n_model)
+    out = np.empty(len(sp.level_E))
+    out[:Lm] = n
+    q_top = state_partition(sp.level_E[Lm - 1], sp.level_g[Lm - 1], T_v)
+    for p in range(Lm, len(sp.level_E)):
+        out[p] = n[Lm - 1] * state_partition(sp.level_E[p], sp.level_g[p], T_v) / q_top
+    return out
+
+
+def cr_populations(cr, species, cells):
+    """Per CR record, the level populations [n_cells, n_levels] of its atom."""
+    out = []
+    for rec in cr.species:
+        out.append(np.stack([cr_level_populations(rec, species, float(cells.T_tr[c]),
+                                                  float(cells.T_v[c]), cells.N[c],
+                                                  float(cells.n_e[c]), cr.collider_w)
+                             for c in range(cells.n)]) if cells.n else
+                   np.zeros((0, len(species[rec.species].level_E))))
+    return out
+
+
+def cr_level_table(cr, species, cells):
+    """(N_lev [n_cells, total levels of all species], lev_on [n_species]) for
+    the coefficient routines, or None without a CR model."""
+    if cr is None:
+        return None
+    off = np.concatenate([[0], np.cumsum([len(s.level_E) for s in species])])
+    N_lev = np.zeros((cells.n, int(off[-1])))
+    lev_on = np.zeros(len(species), np.int32)
+    for rec, pop in zip(cr.species, cr_populations(cr, species, cells)):
+        N_lev[:, off[rec.species]:off[rec.species + 1]] = pop
+        lev_on[rec.species] = 1
+    return N_lev, lev_on
+
+
+# ---------------------------------------------------------------------------
 # eta / kappa (Sec. 2.2.1) for all cells at grid indices ks
 # ---------------------------------------------------------------------------
 
 def coeffs(species, lines, cells, grid, ks: Optional[np.ndarray] = None, threads: int = 0,
-           E_ion=None):
-    """Returns (eta [n_cells, n_k], kappa [n_cells, n_k], n_terms)."""
+           E_ion=None, cr=None, line_levels=None):
+    """Returns (eta [n_cells, n_k], kappa [n_cells, n_k], n_terms).  With a
+    CR model and line_levels, the lines with levels take their populations
+    from the QSS-CR solution."""
     if ks is None:
         ks = np.arange(grid.n_points, dtype=np.int64)
     ks = np.ascontiguousarray(ks, np.int64)
-    st, lt, ct = SpeciesTable(species, E_ion), LineTable(lines), CellTable(cells)
+    st = SpeciesTable(species, E_ion)
+    lt = LineTable(lines, line_levels if cr is not None else None)
+    ct = CellTable(cells, cr_level_table(cr, species, cells))
     eta = np.zeros((cells.n, ks.size))
     kap = np.zeros((cells.n, ks.size))
     n = lib().orc_coeffs(C.byref(st.s), C.byref(lt.s), C.byref(ct.s), grid.nu_min, grid.nu_max,
@@ -311,13 +483,14 @@ def peach_ff(c, z: float, s: float, T: float) -> float:
     return lib().orc_peach_ff(_p(c), float(z), float(s), float(T))
 
 
-def continuum(species, cells, grid, cont, ks: Optional[np.ndarray] = None):
+def continuum(species, cells, grid, cont, ks: Optional[np.ndarray] = None, cr=None):
     """Atomic continuum (Sec. 2.2.1 bound-free and free-free) eta and kappa
-    [n_cells, n_k] at grid points ks (default: all)."""
+    [n_cells, n_k] at grid points ks (default: all); with a CR model the
+    bound-free absorption of its atoms uses the QSS-CR level populations."""
     if ks is None:
         ks = np.arange(grid.n_points, dtype=np.int64)
     ks = np.ascontiguousarray(ks, np.int64)
-    st, ct = SpeciesTable(species), CellTable(cells)
+    st, ct = SpeciesTable(species), CellTable(cells, cr_level_table(cr, species, cells))
     keep = [(np.ascontiguousarray(r.sigma0, np.float64), np.ascontiguousarray(r.peach, np.float64))
             for r in cont]
     arr = (_Cont * max(1, len(cont)))()
@@ -331,8 +504,10 @@ def continuum(species, cells, grid, cont, ks: Optional[np.ndarray] = None):
     return eta, kap
 
 
-def coeffs_bruteforce(species, lines, cells, grid, E_ion=None):
-    st, lt, ct = SpeciesTable(species, E_ion), LineTable(lines), CellTable(cells)
+def coeffs_bruteforce(species, lines, cells, grid, E_ion=None, cr=None, line_levels=None):
+    st = SpeciesTable(species, E_ion)
+    lt = LineTable(lines, line_levels if cr is not None else None)
+    ct = CellTable(cells, cr_level_table(cr, species, cells))
     eta = np.zeros((cells.n, grid.n_points))
     kap = np.zeros((cells.n, grid.n_points))
     lib().orc_coeffs_bruteforce(C.byref(st.s), C.byref(lt.s), C.byref(ct.s), grid.nu_min,
@@ -519,7 +694,8 @@ def solve_slab(wl, ks=None, threads: int = 0):
     integral per ray (trapezoid over ks; exact when ks is the full grid) and
     the tangent-slab flux q = 2 pi sum_i W_i mu_i I_int(mu_i)."""
     eta, kap, n_terms = coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks, threads,
-                               getattr(wl, "lorentz_E_ion", None))
+                               getattr(wl, "lorentz_E_ion", None), getattr(wl, "cr", None),
+                               getattr(wl, "line_levels", None))
     rays, mu, W = slab_rays(wl.geometry)
     I = np.stack([march(c, d, eta, kap) for c, d in rays])
     w = trapezoid_weights(wl.grid, ks)
@@ -532,7 +708,8 @@ def solve_axi(wl, wall_indices: Sequence[int], ks=None, threads: int = 0):
     """Axisymmetric workload at the given wall points: per-point spectral
     flux q_k = sum_rays w_ray I_ray(k) and, over ks, q = sum_k w_k q_k."""
     eta, kap, n_terms = coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks, threads,
-                               getattr(wl, "lorentz_E_ion", None))
+                               getattr(wl, "lorentz_E_ion", None), getattr(wl, "cr", None),
+                               getattr(wl, "line_levels", None))
     w = trapezoid_weights(wl.grid, ks)
     out = []
     for wi in wall_indices:

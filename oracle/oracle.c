@@ -61,12 +61,19 @@ typedef struct {
     int64_t n;
     const double *nu0, *A, *Eu_ev, *Eu_rot, *El_ev, *El_rot, *gu, *gl;
     const int32_t *species;
+    /* optional (NULL: none): the line's upper and lower level in its atom's
+     * level table, -1 for a line without levels */
+    const int32_t *lev_u, *lev_l;
 } orc_lines;
 
 typedef struct {
     int64_t n_cells;
     int n_species;
     const double *T_tr, *T_v, *N, *n_e;   /* N is [n_cells][n_species] */
+    /* optional (NULL: none): level populations [n_cells][lev_off[n_species]]
+     * that replace the Boltzmann ones of the species with lev_on[s] != 0 */
+    const double *N_lev;
+    const int *lev_on;
 } orc_cells;
 
 /* Everything the method fixes for one (cell, line) pair. */
@@ -242,14 +249,37 @@ double orc_planck(double nu, double T)
 /* One (cell, line) pair: Sec. 2.2.1 emission, absorption and widths        */
 /* ---------------------------------------------------------------------- */
 
+/* Population of a line's level from the population Nlev of the table level
+ * (energy E_lev, degeneracy g_lev) it belongs to: the line's level takes its
+ * Boltzmann share g e^{-c2 (E_ev - E_lev)/T_v - c2 E_rot/T_tr} / g_lev. */
+static double orc_sublevel_population(double Nlev, double g_lev, double E_lev, double g,
+                                      double E_ev, double E_rot, double Tv, double Ttr)
+{
+    const double c2 = orc_c2();
+    return Nlev * (g / g_lev) * exp(-c2 * (E_ev - E_lev) / Tv - c2 * E_rot / Ttr);
+}
+
+/* Nlev: NULL, or the level populations of the line's species in this cell
+ * (Sec. 2.1 CR model); a line with levels then takes its populations from
+ * them instead of the Boltzmann relation. */
 void orc_line_pair(const orc_species *sp, const orc_lines *L, int64_t i,
                    double Ttr, double Tv, double ne, const double *N_cell, int S, double N_s,
-                   double Q_s, double nu_min, double h, int64_t n_points, orc_pair *p)
+                   double Q_s, const double *Nlev, double nu_min, double h, int64_t n_points,
+                   orc_pair *p)
 {
     int s = L->species[i];
     double nu0 = L->nu0[i];
-    p->Nu = orc_level_population(N_s, Q_s, L->gu[i], L->Eu_ev[i], L->Eu_rot[i], Tv, Ttr);
-    p->Nl = orc_level_population(N_s, Q_s, L->gl[i], L->El_ev[i], L->El_rot[i], Tv, Ttr);
+    if (Nlev && L->lev_u && L->lev_u[i] >= 0) {
+        const int64_t o = sp->lev_off[s];
+        const int u = L->lev_u[i], l = L->lev_l[i];
+        p->Nu = orc_sublevel_population(Nlev[u], sp->lev_g[o + u], sp->lev_E[o + u], L->gu[i],
+                                        L->Eu_ev[i], L->Eu_rot[i], Tv, Ttr);
+        p->Nl = orc_sublevel_population(Nlev[l], sp->lev_g[o + l], sp->lev_E[o + l], L->gl[i],
+                                        L->El_ev[i], L->El_rot[i], Tv, Ttr);
+    } else {
+        p->Nu = orc_level_population(N_s, Q_s, L->gu[i], L->Eu_ev[i], L->Eu_rot[i], Tv, Ttr);
+        p->Nl = orc_level_population(N_s, Q_s, L->gl[i], L->El_ev[i], L->El_rot[i], Tv, Ttr);
+    }
     /* j = (hc/4pi) N_u A_ul nu0 phi, nu0 the line centre (CGS -> W: 1e-7) */
     p->S_eta = 1e-7 * ORC_H * ORC_C * nu0 * p->Nu * L->A[i] / (4.0 * ORC_PI);
     /* kappa = j / B with exp(hc nu/kT) replaced by N_l g_u / (N_u g_l) */
@@ -259,6 +289,13 @@ void orc_line_pair(const orc_species *sp, const orc_lines *L, int64_t i,
     p->gL = orc_lorentz_line(sp, L, i, Ttr, Tv, ne, N_cell, S);
     p->gV = orc_voigt_hwhm(p->gL, p->gG);
     orc_window(nu0, p->gV, nu_min, h, n_points, &p->klo, &p->khi);
+}
+
+/* The level populations of species s in cell c, or NULL (Boltzmann). */
+static const double *orc_cell_levels(const orc_species *sp, const orc_cells *C, int64_t c, int s)
+{
+    if (!C->N_lev || !C->lev_on || !C->lev_on[s]) return NULL;
+    return C->N_lev + c * sp->lev_off[sp->n_species] + sp->lev_off[s];
 }
 
 /* first index with a[i] >= v in a sorted array */
@@ -338,7 +375,8 @@ int64_t orc_cell_coeffs(const orc_species *sp, const orc_lines *L, const orc_cel
             int s = L->species[i];
             if (sp->kind[s] == 0 || N[s] <= 0.0) continue;
             orc_pair p;
-            orc_line_pair(sp, L, i, Ttr, Tv, ne, N, S, N[s], Q[s], nu_min, h, n_points, &p);
+            orc_line_pair(sp, L, i, Ttr, Tv, ne, N, S, N[s], Q[s], orc_cell_levels(sp, C, c, s),
+                          nu_min, h, n_points, &p);
             if (p.klo > p.khi) continue;
             int64_t a0 = lower_bound_i(ks, n_k, p.klo);
             for (int64_t t = a0; t < n_k && ks[t] <= p.khi; ++t) {
@@ -390,8 +428,8 @@ void orc_coeffs_bruteforce(const orc_species *sp, const orc_lines *L, const orc_
             if (sp->kind[s] == 0 || Ns <= 0.0) continue;
             double Q = orc_partition(sp, s, C->T_v[c], C->T_tr[c]);
             orc_pair p;
-            orc_line_pair(sp, L, i, C->T_tr[c], C->T_v[c], C->n_e[c], C->N + c * S, S, Ns, Q, nu_min, h,
-                          n_points, &p);
+            orc_line_pair(sp, L, i, C->T_tr[c], C->T_v[c], C->n_e[c], C->N + c * S, S, Ns, Q,
+                          orc_cell_levels(sp, C, c, s), nu_min, h, n_points, &p);
             for (int64_t k = 0; k < n_points; ++k) {
                 double delta = orc_grid_offset(nu_min, h, k, L->nu0[i]);
                 if (fabs(delta) > 100.0 * p.gV) continue;
@@ -464,7 +502,8 @@ typedef struct {
 /* Continuum eta and kappa of every cell at grid points ks (added to eta /
  * kappa [n_cells][n_k]).  Per atom a with ion +: T = T_ee = T_v;
  *   bound-free from level i (threshold nu_i = E_ion - E_i, nu >= nu_i):
- *     kappa = N_i sigma_i(nu), N_i = N_a g_i e^{-c2 E_i/T} / Q_a,
+ *     kappa = N_i sigma_i(nu), N_i = N_a g_i e^{-c2 E_i/T} / Q_a (or the
+ *     cell's level population when the atom has them),
  *     eta = B(nu, T) sigma_i(nu) N_+ n_e V(T) g_i e^{c2 (E_ion - E_i)/T} / (2 Q_+)
  *     (the LTE population per ion-electron pair in Kirchhoff's law), with the
  *     synthetic hydrogenic shape sigma_i(nu) = sigma0_i (nu_i / nu)^3;
@@ -484,6 +523,7 @@ void orc_continuum(const orc_species *sp, const orc_cells *C, int n_cont, const 
             double Np = C->N[c * C->n_species + q->ion];
             double ne = C->n_e[c];
             double Qa = orc_partition(sp, a, C->T_v[c], C->T_tr[c]);
+            const double *Nlev = orc_cell_levels(sp, C, c, a);
             for (int64_t t = 0; t < n_k; ++t) {
                 double nu = nu_min + (double)ks[t] * h;
                 double B = orc_planck(nu, T);
@@ -494,7 +534,7 @@ void orc_continuum(const orc_species *sp, const orc_cells *C, int n_cont, const 
                     double nui = q->E_ion - Ei;
                     if (q->sigma0[li] == 0.0 || !(nui > 0.0) || nu < nui) continue;
                     double sig = q->sigma0[li] * pow(nui / nu, 3.0);
-                    double Ni = (Qa > 0.0) ? Na * gi * exp(-c2 * Ei / T) / Qa : 0.0;
+                    double Ni = Nlev ? Nlev[li] : (Qa > 0.0) ? Na * gi * exp(-c2 * Ei / T) / Qa : 0.0;
                     kap += Ni * sig;
                     em += B * sig * Np * ne * orc_saha_volume(T) * gi * exp(c2 * (q->E_ion - Ei) / T)
                           / (2.0 * q->Q_ion);

@@ -149,6 +149,52 @@ class Continuum:
 
 
 @dataclasses.dataclass
+class CRSpecies:
+    """Collisional-radiative data of one atom (Sec. 2.1 CR model): levels
+    0..n_model-1 of its level table are solved for, the levels above stay in
+    Boltzmann ratio (at T_v) with level n_model-1.  Rate coefficients are
+    Arrhenius triples (C in cm^3 mol^-1 s^-1 K^-n, n, E_a in K) of the
+    forward processes:
+      (ion < 0: the ion density is taken as 0)
+      hpie[lo, hi], eie[lo, hi]: heavy-particle / electron impact excitation
+        lo -> hi (lo < hi; other entries unused);
+      A[hi, lo]: spontaneous emission hi -> lo, s^-1 (lo < hi);
+      eii[i]: electron impact ionization of level i into the ion `ion`;
+      ce[i]: charge exchange  atom(i) + partner_ion -> ion + partner
+        (partner < 0: none).
+    Reverse rates follow from detailed balance.  texp[2m], texp[2m+1]: the
+    forward and backward rates of mechanism m (HPIE, EIE, EII, CE) are
+    taken at T = T_tr^a T_v^(1-a) with a the entry.  Transitions above
+    nu_cut (cm^-1, i.e. below 200 nm) are optically thick (no net
+    radiative rate)."""
+    species: int
+    ion: int
+    partner: int
+    partner_ion: int
+    n_model: int
+    E_ion: float
+    Q_ion: float
+    partner_E_ion: float
+    partner_Q_ion: float
+    hpie: np.ndarray
+    eie: np.ndarray
+    A: np.ndarray
+    eii: np.ndarray
+    ce: np.ndarray
+    texp: np.ndarray
+    nu_cut: float = 50000.0
+
+
+@dataclasses.dataclass
+class CRModel:
+    """QSS collisional-radiative populations for some atoms; collider_w[s]
+    is the weight of species s among the heavy collision partners M (0 for
+    electrons)."""
+    species: List[CRSpecies]
+    collider_w: np.ndarray
+
+
+@dataclasses.dataclass
 class Workload:
     name: str
     species: List[Species]
@@ -162,6 +208,11 @@ class Workload:
     # Lorentz width (natural + per-line Stark + van der Waals); None: the
     # uniform Stark law for every line
     lorentz_E_ion: Optional[np.ndarray] = None
+    # QSS collisional-radiative populations (None: Boltzmann for every level)
+    # and, per line in list order, its (upper, lower) level in its atom's
+    # level table (-1, -1: the line keeps Boltzmann populations)
+    cr: Optional[CRModel] = None
+    line_levels: Optional[np.ndarray] = None
 
 
 # --------------------------------------------------------------------------
@@ -220,6 +271,87 @@ def air_ionization_energies(species: List[Species]) -> np.ndarray:
     values for the atoms N and O, 0 for every other species."""
     return np.array([ION_ENERGY_CM.get(sp.name, 0.0) if sp.kind == KIND_ATOM else 0.0
                      for sp in species], np.float64)
+
+
+AVOGADRO = 6.02214076e23
+C2_CM_K = 6.62607015e-27 * 2.99792458e10 / 1.380649e-16   # second radiation constant
+
+
+def _arrhenius_triples(rng, n, k_lo, k_hi, n_lo, n_hi, Ea):
+    """n Arrhenius triples whose rate at 1e4 K is k ~ logU(k_lo, k_hi) cm^3/s,
+    with n ~ U(n_lo, n_hi) and the given activation temperatures."""
+    k = _log_uniform(rng, k_lo, k_hi, n)
+    ex = rng.uniform(n_lo, n_hi, n)
+    return np.stack([k * AVOGADRO * 1e4 ** (-ex), ex, np.asarray(Ea, np.float64)], axis=-1)
+
+
+def air_cr(species: List[Species], n_model: int = 18, seed: int = 11863) -> CRModel:
+    """Synthetic QSS-CR data for the atoms N and O of a species list (the
+    paper's rate mechanism is not available); an atom whose ion is not in the
+    list gets ion = -1 (no recombination source) and no charge exchange.  Per
+    level pair lo < hi of the first n_model levels, with dE = E_hi - E_lo:
+      EIE  k(1e4 K) ~ logU(1e-10, 1e-7) cm^3/s, n ~ U(-0.5, 0.5), E_a = c2 dE;
+      HPIE k(1e4 K) ~ logU(1e-14, 1e-11) cm^3/s, n ~ U(0, 1),  E_a = c2 dE;
+      A ~ logU(1e4, 1e8) s^-1 for half of the pairs (seeded), else 0;
+    per level i: EII k ~ logU(1e-10, 1e-8), n ~ U(0, 0.5),
+    E_a = c2 max(E_ion - E_i, 0); CE with the other atom (N(i) + O+ <-> N+ + O
+    and O(i) + N+ <-> O+ + N) k ~ logU(1e-12, 1e-10), n ~ U(0, 0.5),
+    E_a = c2 max(E_ion - E_i - E_ion', 0).  Temperatures: HPIE forward at
+    sqrt(T_tr T_v), backward at T_tr; EIE and EII at T_v (= T_e); CE at T_tr.
+    Heavy colliders: every species but e-, weight 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    names = [sp.name for sp in species]
+    recs = []
+    atoms = [a for a in ("N", "O") if a in names and species[names.index(a)].kind == KIND_ATOM]
+    ion_of = lambda a: names.index(a + "+") if a + "+" in names else -1
+    for a in atoms:
+        other = [b for b in atoms if b != a]
+        sp = species[names.index(a)]
+        L = min(n_model, sp.level_E.size)
+        E = sp.level_E[:L]
+        dE = C2_CM_K * np.maximum(E[None, :] - E[:, None], 0.0)
+        hpie = _arrhenius_triples(rng, L * L, 1e-14, 1e-11, 0.0, 1.0, dE.ravel()).reshape(L, L, 3)
+        eie = _arrhenius_triples(rng, L * L, 1e-10, 1e-7, -0.5, 0.5, dE.ravel()).reshape(L, L, 3)
+        A = np.zeros((L, L))
+        for hi in range(L):
+            for lo in range(hi):
+                if rng.uniform() < 0.5:
+                    A[hi, lo] = _log_uniform(rng, 1e4, 1e8, 1)[0]
+        Ei = ION_ENERGY_CM[a]
+        eii = _arrhenius_triples(rng, L, 1e-10, 1e-8, 0.0, 0.5, C2_CM_K * np.maximum(Ei - E, 0.0))
+        if other and ion_of(a) >= 0 and ion_of(other[0]) >= 0:
+            b = other[0]
+            Eb = ION_ENERGY_CM[b]
+            ce = _arrhenius_triples(rng, L, 1e-12, 1e-10, 0.0, 0.5,
+                                    C2_CM_K * np.maximum(Ei - E - Eb, 0.0))
+            partner, partner_ion, pE, pQ = names.index(b), ion_of(b), Eb, ION_Q[b + "+"]
+        else:
+            ce = np.zeros((L, 3))
+            partner, partner_ion, pE, pQ = -1, -1, 0.0, 1.0
+        recs.append(CRSpecies(names.index(a), ion_of(a), partner, partner_ion, L,
+                              Ei, ION_Q[a + "+"], pE, pQ, hpie, eie, A, eii, ce,
+                              np.array([0.5, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 1.0])))
+    w = np.array([0.0 if n == "e-" else 1.0 for n in names])
+    return CRModel(recs, w)
+
+
+def tie_lines_to_levels(lines: Lines, species: List[Species], cr: CRModel) -> np.ndarray:
+    """(upper, lower) level of every line of a CR atom: the level of its
+    atom nearest in energy to E_u and to E_l (ties: the lower level); -1 for
+    the lines of every other species.  [n_lines, 2] int32."""
+    out = np.full((lines.n, 2), -1, np.int32)
+    for rec in cr.species:
+        sel = np.nonzero(lines.species == rec.species)[0]
+        E = species[rec.species].level_E
+        for col, Ev in ((0, lines.Eu_ev[sel]), (1, lines.El_ev[sel])):
+            out[sel, col] = np.argmin(np.abs(Ev[:, None] - E[None, :]), axis=1)
+    return out
+
+
+def with_cr(wl: Workload, n_model: int = 18, seed: int = 11863) -> Workload:
+    """The same workload with QSS-CR populations for its atoms."""
+    cr = air_cr(wl.species, n_model, seed)
+    return dataclasses.replace(wl, cr=cr, line_levels=tie_lines_to_levels(wl.lines, wl.species, cr))
 
 
 def none_species(name: str) -> Species:
