@@ -221,6 +221,56 @@ def continuum_cost(ctx, wl, lrt, torch, reps=2):
     return out
 
 
+def cr_cost(ctx, wl, lrt, torch, q_boltzmann, reps=2, scale_cells=32768):
+    """QSS collisional-radiative populations of N and O (Sec. 2.1): whole
+    single-precision solves with the atoms' lines and bound-free absorption
+    taking their populations from the per-(cell, atom) CR solve, against the
+    Boltzmann solve; then the CR solve alone on scale_cells cells (one wave
+    per (cell, atom) system)."""
+    from paper_2604_11856_amd import synth
+    cr = synth.air_cr(wl.species)
+    if not cr.species:
+        return None
+    ctx.set_cr(cr)
+    ctx.set_line_levels(synth.tie_lines_to_levels(wl.lines, wl.species, cr))
+    ctx.solve(lrt.LRT_FP32_COMP)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        q, _, _ = ctx.solve(lrt.LRT_FP32_COMP)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    prof = {k: ctx.profile_read(k) for k in ("cr", "accum", "thermo")}
+    ctx.profile(False)
+    ctx.set_cr(None)
+    ctx.set_line_levels(None)
+    n_sys = wl.cells.n * len(cr.species)
+    out = {"atoms": [wl.species[r.species].name for r in cr.species],
+           "levels_solved": [int(r.n_model) for r in cr.species],
+           "systems": n_sys, "ms_per_step": dt * 1e3,
+           "cr_ms_per_solve": prof["cr"][0] / max(1, prof["cr"][1]),
+           "accum_ms_per_launch": prof["accum"][0] / max(1, prof["accum"][1]),
+           "q_rad_ratio_cr_over_boltzmann": [float(a / b) if b else None for a, b in zip(q, q_boltzmann)]}
+    # the CR solve alone at a larger cell count (the axisymmetric grid's)
+    sw = synth.with_cr(synth.stagnation_line(n_cells=scale_cells, n_atomic=64, n_rovib=0, n_points=4096,
+                                             n_mu=0))
+    c2 = lrt.Context(0).load(sw)
+    c2.solve(lrt.LRT_FP64)
+    torch.cuda.synchronize()
+    c2.profile(True)
+    for _ in range(reps):
+        c2.solve(lrt.LRT_FP64)
+    torch.cuda.synchronize()
+    ms, n = c2.profile_read("cr")
+    c2.profile(False)
+    c2.close()
+    t = ms / max(1, n)
+    out["scaled"] = {"cells": scale_cells, "systems": scale_cells * len(sw.cr.species), "cr_ms": t,
+                     "systems_per_s": scale_cells * len(sw.cr.species) / (t / 1e3)}
+    return out
+
+
 def cpu_baseline(wl, n_points):
     import oracle as O
     from paper_2604_11856_amd import synth
@@ -284,6 +334,7 @@ def main():
 
     march_schemes = compare_march_schemes(ctx, lrt, torch, sz)
     continuum = continuum_cost(ctx, wl, lrt, torch)
+    cr = cr_cost(ctx, wl, lrt, torch, q32) if args.workload == "stagnation" else None
 
     acc_ms, acc_n = prof32["accum"]
     acc_s = acc_ms / 1e3 / max(1, acc_n)
@@ -323,6 +374,7 @@ def main():
                      "avg_launch_ms": acc_s * 1e3},
         "march_schemes": march_schemes,
         "continuum": continuum,
+        "cr": cr,
         "march_roofline": {"bound": "hbm", "kernel": "march_f32", "achieved": march_bytes / mar_s / 1e9,
                            "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                            "frac": march_bytes / mar_s / HBM_PEAK, "avg_launch_ms": mar_s * 1e3,

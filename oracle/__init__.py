@@ -387,10 +387,13 @@ def cr_system(rec, species, T_tr: float, T_v: float, N_cell, n_e: float, collide
 def cr_level_populations(rec, species, T_tr, T_v, N_cell, n_e, collider_w):
     """Populations of every level of the atom's table in one cell: levels
     0..l-1 from the LU solution of R n = b (LAPACK's partially pivoted LU),
-    the levels above from their Boltzmann ratio to level l-1 at T_v."""
+    the levels above from their Boltzmann ratio to level l-1 at T_v; all zero
+    in a cell without the atom."""
+    sp = species[rec.species]
+    if not float(N_cell[rec.species]) > 0.0:
+        return np.zeros(len(sp.level_E))   # no atoms in the cell: no level populations
     R, b = cr_system(rec, species, T_tr, T_v, N_cell, n_e, collider_w)
     n = np.linalg.solve(R, b)
-    sp = species[rec.species]
     Lm = int(rec.n_model)
     out = np.empty(len(sp.level_E))
     out[:Lm] = n

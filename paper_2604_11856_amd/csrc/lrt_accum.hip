@@ -3,7 +3,9 @@
 //
 //   thermo      per (cell, species): partition function, ln(N/Q), Doppler
 //               coefficient; per cell: beta's, Lorentz HWHM, line-skip bound
-//               (Sec. 2.1 Boltzmann populations, Sec. 2.2.1 widths)
+//               (Sec. 2.1 Boltzmann populations, Sec. 2.2.1 widths); the
+//               QSS-CR populations of selected atoms come from lrt_cr.hip
+//               and enter the line setup as departures from Boltzmann
 //   ranges      per (cell, tile): index range of the nu0-sorted lines that
 //               can reach the tile
 //   scale       per cell: power-of-two scale of the single-precision eta/kappa
@@ -125,8 +127,16 @@ struct PairF64 {
 // rational terms.
 constexpr double kCoreHalfWidth = 25.0;
 
+// The cell's row of ln departures from Boltzmann (QSS-CR populations), or
+// NULL when no line has levels.
+__device__ __forceinline__ const double *cr_row(const DevLines &L, int c)
+{
+    return L.lev ? L.lnd + (int64_t)c * L.lnd_stride : nullptr;
+}
+
 __device__ __forceinline__ bool pair_setup(const DevLines &L, const DevGrid &g, const CellConst &k,
-                                           const CellSpecies *csc, int64_t i, PairF64 &p)
+                                           const CellSpecies *csc, const double *lnd_c, int64_t i,
+                                           PairF64 &p)
 {
     const int s = L.species[i];
     const CellSpecies q = csc[s];
@@ -144,10 +154,21 @@ __device__ __forceinline__ bool pair_setup(const DevLines &L, const DevGrid &g, 
     // reduced energy, so N_l (g_u/g_l)(1 - e^{-x}) = N_u (e^{x} - 1)
     const double lnNu = base - k.beta_v * Eu_ev - k.beta_tr * Eu_rot;
     const double x = k.beta_v * (Eu_ev - El_ev) + k.beta_tr * (Eu_rot - El_rot);
-    const double Nu = exp(lnNu);
-    // (the two-factor form only while N_u e^{x} stays representable)
-    const double Nlx = (lnNu > -700.0 && x < 700.0) ? Nu * expm1(x)
-                                                    : exp(lnNu + x) * (-expm1(-x));
+    const int32_t lv = lnd_c ? L.lev[i] : -1;
+    double Nu, Nlx;
+    if (lv < 0) {
+        Nu = exp(lnNu);
+        // (the two-factor form only while N_u e^{x} stays representable)
+        Nlx = (lnNu > -700.0 && x < 700.0) ? Nu * expm1(x) : exp(lnNu + x) * (-expm1(-x));
+    } else {
+        // QSS-CR populations: both levels carry their departure from
+        // Boltzmann, N_u = e^{lu}, N_l g_u/g_l = e^{ll}, and the absorption
+        // takes N_l g_u/g_l - N_u (negative for an inverted pair)
+        const double lu = lnNu + lnd_c[lv & 0xffff];
+        const double ll = lnNu + x + lnd_c[lv >> 16];
+        Nu = exp(lu);
+        Nlx = (ll >= lu) ? (ll > -INFINITY ? exp(ll) * -expm1(lu - ll) : 0.0) : -(Nu * -expm1(ll - lu));
+    }
     const double Seta = L.seta0[i] * Nu;
     const double Skap = L.skap0[i] * Nlx;
     // widths (Sec. 2.2.1): Doppler, Lorentz, Voigt (Olivero fit)
@@ -205,7 +226,7 @@ constexpr double kElectronMass = 9.1093837015e-28;   // g
 // coefficients, and ln upper bounds of eta_c and kappa_c over [nu_lo, nu_hi]
 // for the power-of-two scale.
 __global__ void cont_cells_kernel(const ContThr *thr, int32_t n_thr, const ContRec *rec,
-                                  int32_t n_rec, DevCells cells, const CellSpecies *cs,
+                                  int32_t n_rec, DevCells cells, const CellSpecies *cs, DevCR cr,
                                   double nu_lo, double nu_hi, double *cum, double *ff, double *lnb)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -221,9 +242,11 @@ __global__ void cont_cells_kernel(const ContThr *thr, int32_t n_thr, const ContR
     for (int j = 0; j < n_thr; ++j) {
         const ContThr t = thr[j];
         const ContRec r = rec[t.rec];
-        const double NQ = exp(cs[(int64_t)c * ns + r.species].lnNQ);   // N_a / Q_a
         const double Np = cells.N[(int64_t)c * ns + r.ion];
-        const double aj = NQ * t.g * exp(-kC2 * t.E / T) * t.s3;
+        const int slot = cr.n > 0 ? cr.slot[r.species] : -1;
+        // absorption from the level: its QSS-CR population, else Boltzmann
+        const double aj = slot >= 0 ? cr.pop[((int64_t)c * cr.n + slot) * cr.LS + t.lev] * t.s3
+                                    : exp(cs[(int64_t)c * ns + r.species].lnNQ) * t.g * exp(-kC2 * t.E / T) * t.s3;
         const double bj = Np * ne * V * t.g / (2.0 * r.Q_ion) * t.s3;   // without e^{c2 nu_j / T}
         a += aj;
         b += bj * exp(kC2 * t.nu / T);
@@ -318,7 +341,7 @@ __global__ void scale_kernel(DevLines L, int64_t i0, int64_t i1, DevGrid g, cons
         int ee = INT_MIN, ek = INT_MIN;
         if (i < i1) {
             PairF64 p;
-            if (pair_setup(L, g, cc[c], cs + (int64_t)c * n_species, i, p)) {
+            if (pair_setup(L, g, cc[c], cs + (int64_t)c * n_species, cr_row(L, c), i, p)) {
                 if (p.se != 0.0) ee = ilogb(p.se) + 1;
                 if (p.sk != 0.0) ek = ilogb(fabs(p.sk)) + 1;
             }
@@ -352,10 +375,20 @@ __global__ void scale_bound_kernel(DevBins B, const CellConst *cc, const CellSpe
     const CellConst k = cc[c];
     const double ln_norm = -log(2.0 * 1.065 * 0.9);
     double ve = -INFINITY, vk = -INFINITY;
+    const double *lnd_c = B.lev_off ? B.lnd + (int64_t)c * B.lnd_stride : nullptr;
     for (int b = lane; b < B.n; b += 64) {
         const CellSpecies q = cs[(int64_t)c * n_species + B.species[b]];
         if (!(q.lnNQ > -INFINITY)) continue;
-        const double v = q.lnNQ + ln_norm - log(q.dop) - k.beta_v * B.Ev[b] - k.beta_tr * B.Er[b];
+        double v = q.lnNQ + ln_norm - log(q.dop) - k.beta_v * B.Ev[b] - k.beta_tr * B.Er[b];
+        if (lnd_c) {
+            // QSS-CR: the largest departure from Boltzmann among the bin's levels
+            double d = -INFINITY;
+            for (int32_t j = B.lev_off[b]; j < B.lev_off[b + 1]; ++j) {
+                const int32_t o = B.lev[j];
+                d = fmax(d, o < 0 ? 0.0 : lnd_c[o]);
+            }
+            v += d;
+        }
         ve = fmax(ve, B.a_eta[b] + v);
         vk = fmax(vk, B.a_kap[b] + v);
     }
@@ -550,7 +583,7 @@ __device__ __forceinline__ int lowest_bit(uint64_t m) { return __builtin_ctzll(m
 // by 2^-ese, 2^-esk).  Must be called by the whole workgroup.
 __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines &L, const DevGrid &g,
                                                     const CellConst &k, const CellSpecies *csc,
-                                                    int ese, int esk, int2 rg, int32_t kt,
+                                                    const double *lnd_c, int ese, int esk, int2 rg, int32_t kt,
                                                     int32_t kw, int lane, float (&eta)[kPPL],
                                                     float (&kap)[kPPL])
 {
@@ -575,7 +608,7 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
         rr.k0f = rr.hg = rr.fg = rr.r = rr.aG = rr.aW = rr.se = rr.sk = rr.pad = 0.0f;
         if (i < rg.y) {
             PairF64 p;
-            if (pair_setup(L, g, k, csc, i, p)) {
+            if (pair_setup(L, g, k, csc, lnd_c, i, p)) {
                 const int32_t lo = p.klo - kt, hi = p.khi - kt;
                 rr.mode = slice_modes(lo, hi, p.kclo - kt, p.kchi - kt);
                 // small exact integers in float: the lanes compare their float index
@@ -667,7 +700,7 @@ void accum_f32_kernel(
     const int32_t kw = wave * 64 * kPPL;               // first point of the wave, tile-relative
     const int32_t kend = k_first + n_band;             // exclusive, global
     float e[kPPL], kp[kPPL];
-    accum_cell_tile_f32(rec, L, g, cc[c], cs + (int64_t)c * n_species, escale[2 * c + 0],
+    accum_cell_tile_f32(rec, L, g, cc[c], cs + (int64_t)c * n_species, cr_row(L, c), escale[2 * c + 0],
                         escale[2 * c + 1], ranges[(int64_t)c * n_tiles + tile], kt, kw, lane, e, kp);
 #pragma unroll
     for (int j = 0; j < kPPL; ++j) {
@@ -701,6 +734,7 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
     const int32_t kend = k_first + n_band;
     const CellConst k = cc[c];
     const CellSpecies *csc = cs + (int64_t)c * n_species;
+    const double *lnd_c = cr_row(L, c);
     const int2 rg = ranges[(int64_t)c * n_tiles + tile];
 
     double se[kPPL], sk[kPPL];
@@ -718,7 +752,7 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
         rr.frac0 = rr.inv2g = rr.r = rr.se = rr.sk = rr.pad2 = 0.0;
         if (i < rg.y) {
             PairF64 p;
-            if (pair_setup(L, g, k, csc, i, p)) {
+            if (pair_setup(L, g, k, csc, lnd_c, i, p)) {
                 rr.klo = p.klo;
                 rr.khi = p.khi;
                 rr.k0 = L.k0[i];
@@ -783,7 +817,7 @@ __global__ void count_kernel(DevLines L, DevGrid g, const CellConst *cc, const C
         for (int64_t i = (int64_t)rg.x + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rg.y;
              i += (int64_t)gridDim.x * blockDim.x) {
             PairF64 p;
-            if (pair_setup(L, g, cc[c], cs + (int64_t)c * n_species, i, p)) {
+            if (pair_setup(L, g, cc[c], cs + (int64_t)c * n_species, cr_row(L, c), i, p)) {
                 const int32_t a = max(p.klo, k_first), b = min(p.khi, k_first + n_band - 1);
                 if (b >= a) n += (unsigned long long)(b - a + 1);
                 const int32_t ca = max(p.kclo, k_first), cb = min(p.kchi, k_first + n_band - 1);
@@ -854,7 +888,7 @@ void serve_kernel(DevLines L, DevGrid g,
         for (int32_t c = c0; c < c1; ++c) {
             float e[kPPL], kp[kPPL];
             const int ese = R.escale[2 * c + 0], esk = R.escale[2 * c + 1];
-            accum_cell_tile_f32(rec, L, g, R.cc[c], R.cs + (int64_t)c * n_species, ese, esk,
+            accum_cell_tile_f32(rec, L, g, R.cc[c], R.cs + (int64_t)c * n_species, nullptr, ese, esk,
                                 R.ranges[(int64_t)c * R.n_tiles + w.tile], kt, kw, lane, e, kp);
             const double ds = R.ds[c];
             const double dse = ldexp(ds, ese);
@@ -940,12 +974,13 @@ hipError_t launch_scale_bound(const DevBins &B, const CellConst *cc, const CellS
 }
 
 hipError_t launch_cont_cells(const ContThr *thr, int32_t n_thr, const ContRec *rec, int32_t n_rec,
-                             const DevCells &cells, const CellSpecies *cs, double nu_lo,
-                             double nu_hi, double *cum, double *ff, double *lnb, hipStream_t st)
+                             const DevCells &cells, const CellSpecies *cs, const DevCR &cr,
+                             double nu_lo, double nu_hi, double *cum, double *ff, double *lnb,
+                             hipStream_t st)
 {
     if (cells.n_cells == 0) return hipSuccess;
     hipLaunchKernelGGL(cont_cells_kernel, dim3(blocks_for(cells.n_cells, 64)), dim3(64), 0, st, thr,
-                       n_thr, rec, n_rec, cells, cs, nu_lo, nu_hi, cum, ff, lnb);
+                       n_thr, rec, n_rec, cells, cs, cr, nu_lo, nu_hi, cum, ff, lnb);
     return hipGetLastError();
 }
 

@@ -56,8 +56,26 @@ struct lrt_ctx {
     DBuf d_cont_thr, d_cont_rec;         // ContThr[n_thr], ContRec[n_rec]
     DBuf d_cont_cum, d_cont_ff, d_cont_lnb;   // per cell: [2][n_thr+1], [2], [2]
 
+    // QSS-CR atoms: records (device pointers into d_cr_tab), per-species
+    // record index, collider weights, per-(cell, atom) populations and ln
+    // departures ([n_cells][n_cr][cr_LS])
+    int n_cr = 0, cr_LS = 0, cr_max_l = 0;
+    std::vector<int32_t> h_cr_slot, h_cr_nlev;
+    DBuf d_cr_rec, d_cr_tab, d_cr_slot, d_cr_w, d_cr_pop, d_cr_lnd;
+    // per line (sorted order) its upper / lower level (-1: none), and the packed
+    // offsets into a cell's departure row the line setup reads (built when both
+    // the levels and the CR atoms are set)
+    std::vector<int32_t> h_lev_u, h_lev_l;
+    DBuf d_line_lev;
+    // per scale bin the departure-row offsets of the levels of its lines
+    // (CSR; -1 for lines with Boltzmann populations)
+    DBuf d_bin_lev_off, d_bin_lev;
+    bool line_lev_ready = false;
+
     // lines (sorted by nu0 on the host, resident on the device)
     int64_t n_lines = -1;
+    std::vector<int64_t> h_line_order;   // sorted position -> caller's index
+    std::vector<int32_t> h_bin_u, h_bin_l;   // scale bin of each line's upper / lower level
     std::vector<double> h_nu0;   // sorted centres, host copy for k0/frac0
     DBuf d_nu0, d_seta0, d_skap0, d_Eu_ev, d_Eu_rot, d_El_ev, d_El_rot, d_lngu, d_species, d_k0, d_frac0;
     std::vector<int32_t> h_spc;   // sorted order: species and upper-level energy
@@ -131,6 +149,30 @@ lrt_status prepare_lines(lrt_ctx *c);
 // Lines on the grid, per-cell constants (and scales when need_scale).
 lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force = false);
 DevLines dev_lines(const lrt_ctx *c);
+// QSS-CR: device view, line-to-level packing, per-cell solve (after thermo).
+DevCR dev_cr(const lrt_ctx *c);
+lrt_status cr_build_line_levels(lrt_ctx *c);
+lrt_status cr_run(lrt_ctx *c, const DevCells &cells, hipStream_t st);
+
+// Launch `fn` (returning hipError_t) on stream st, bracketed by events when
+// the context profiles.
+template <class F>
+hipError_t timed(lrt_ctx *c, int kernel, hipStream_t st, F fn)
+{
+    if (!c->prof) return fn();
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventCreate(&b)) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return e;
+    }
+    (void)hipEventRecord(a, st);
+    e = fn();
+    (void)hipEventRecord(b, st);
+    c->ev[kernel].push_back({a, b});
+    return e;
+}
 inline DevWidths dev_widths(const lrt_ctx *c)
 {
     return DevWidths{c->h_Eion.empty() ? nullptr : c->d_Eion.as<double>(), c->gN_max, c->gS_max};

@@ -41,26 +41,6 @@ lrt_status fail(lrt_ctx *c, lrt_status s, const char *fmt, ...)
 
 
 
-// Launch `fn` (returning hipError_t) on stream st, bracketed by events when
-// the context profiles.
-template <class F>
-hipError_t timed(lrt_ctx *c, int kernel, hipStream_t st, F fn)
-{
-    if (!c->prof) return fn();
-    hipEvent_t a, b;
-    hipError_t e = hipEventCreate(&a);
-    if (e != hipSuccess) return e;
-    if ((e = hipEventCreate(&b)) != hipSuccess) {
-        (void)hipEventDestroy(a);
-        return e;
-    }
-    (void)hipEventRecord(a, st);
-    e = fn();
-    (void)hipEventRecord(b, st);
-    c->ev[kernel].push_back({a, b});
-    return e;
-}
-
 lrt_status upload(lrt_ctx *c, DBuf &b, const void *src, size_t bytes)
 {
     b.release();
@@ -345,6 +325,12 @@ lrt_status lrt_set_species(lrt_ctx *c, int n, const lrt_species *sp)
     c->h_lev_g = lev_g;
     c->n_cont_rec = c->n_cont_thr = 0;   // continuum records refer to the old table
     c->h_Eion.clear();                   // so does the Lorentz model
+    c->n_cr = 0;                         // and the QSS-CR atoms
+    c->h_cr_slot.clear();
+    c->h_cr_nlev.clear();
+    c->h_lev_u.clear();
+    c->h_lev_l.clear();
+    c->line_lev_ready = false;
     c->M_min = std::isfinite(M_min) ? M_min : 1.0;
     c->sp = DevSpecies{n, c->d_kind.as<int32_t>(), c->d_mass.as<double>(), c->d_lev_off.as<int64_t>(),
                        c->d_lev_E.as<double>(), c->d_lev_g.as<double>(), c->d_el_off.as<int64_t>(),
@@ -402,17 +388,19 @@ lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *L)
         spc[j] = L->species[i];
     }
     // level-energy bins for the per-cell scale bound (1000 cm^-1 wide; the
-    // bound then exceeds the true peak by at most e^{(beta_v + beta_tr) 1000})
-    std::vector<int32_t> b_sp;
+    // bound then exceeds the true peak by at most e^{(beta_v + beta_tr) 1000}),
+    // and each line's upper and lower bin
+    std::vector<int32_t> b_sp, bin_u, bin_l;
     std::vector<double> b_Ev, b_Er, b_aeta, b_akap;
     {
         constexpr double kBinE = 1000.0;
         std::unordered_map<uint64_t, int64_t> slot;
         slot.reserve(4096);
         // key: (species, upper/lower, E_ev bin, E_rot bin), bins offset to be non-negative
-        auto bin = [&](int32_t s, int lower, double Ev, double Er, double aeta, double akap) {
+        // returns the bin's index, -1 when the energies are out of range
+        auto bin = [&](int32_t s, int lower, double Ev, double Er, double aeta, double akap) -> int32_t {
             const double fe = std::floor(Ev / kBinE) + 8388608.0, fr = std::floor(Er / kBinE) + 8388608.0;
-            if (!(fe >= 0.0 && fe < 16777216.0 && fr >= 0.0 && fr < 16777216.0)) return false;
+            if (!(fe >= 0.0 && fe < 16777216.0 && fr >= 0.0 && fr < 16777216.0)) return -1;
             const uint64_t key = ((uint64_t)(2 * s + lower) << 48) | ((uint64_t)fe << 24) | (uint64_t)fr;
             auto it = slot.find(key);
             if (it == slot.end()) {
@@ -422,22 +410,26 @@ lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *L)
                 b_Er.push_back(Er);
                 b_aeta.push_back(aeta);
                 b_akap.push_back(akap);
-            } else {
-                const int64_t k = it->second;
-                b_Ev[k] = std::min(b_Ev[k], Ev);
-                b_Er[k] = std::min(b_Er[k], Er);
-                b_aeta[k] = std::max(b_aeta[k], aeta);
-                b_akap[k] = std::max(b_akap[k], akap);
+                return (int32_t)(b_sp.size() - 1);
             }
-            return true;
+            const int64_t k = it->second;
+            b_Ev[k] = std::min(b_Ev[k], Ev);
+            b_Er[k] = std::min(b_Er[k], Er);
+            b_aeta[k] = std::max(b_aeta[k], aeta);
+            b_akap[k] = std::max(b_akap[k], akap);
+            return (int32_t)k;
         };
         const double ninf = -std::numeric_limits<double>::infinity();
+        bin_u.assign(n, -1);
+        bin_l.assign(n, -1);
         for (int64_t j = 0; j < n; ++j) {
             if (!(seta0[j] > 0.0)) continue;   // A = 0: the line has no strength
             const double ln_nu = std::log(nu0[j]);
             const double ae = std::log(seta0[j]) + lngu[j] - ln_nu;
             const double ak = std::log(skap0[j]) + lngu[j] - ln_nu;
-            if (!bin(spc[j], 0, Eue[j], Eur[j], ae, ak) || !bin(spc[j], 1, Ele[j], Elr[j], ninf, ak))
+            bin_u[j] = bin(spc[j], 0, Eue[j], Eur[j], ae, ak);
+            bin_l[j] = bin(spc[j], 1, Ele[j], Elr[j], ninf, ak);
+            if (bin_u[j] < 0 || bin_l[j] < 0)
                 return fail(c, LRT_E_ARG, "line %lld: level energy beyond +-8e9 cm^-1", (long long)j);
         }
     }
@@ -455,6 +447,12 @@ lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *L)
         return st;
     c->h_nu0.swap(nu0);
     c->h_spc = spc;
+    c->h_line_order.swap(idx);
+    c->h_bin_u.swap(bin_u);
+    c->h_bin_l.swap(bin_l);
+    c->h_lev_u.clear();   // line levels refer to the old list
+    c->h_lev_l.clear();
+    c->line_lev_ready = false;
     c->h_Eu.resize(n);
     for (int64_t j = 0; j < n; ++j) c->h_Eu[j] = Eue[j] + Eur[j];
     c->n_lines = n;
@@ -513,7 +511,7 @@ lrt_status lrt_set_continuum(lrt_ctx *c, int n, const lrt_continuum *cont)
                 return fail(c, LRT_E_ARG, "continuum %d level %lld: sigma0 must be >= 0", q, (long long)(i - l0));
             const double nu = x.E_ion - c->h_lev_E[i];
             if (s0 == 0.0 || !(nu > 0.0)) continue;   // no bound-free from this level
-            thr.push_back(ContThr{nu, c->h_lev_E[i], c->h_lev_g[i], s0 * nu * nu * nu, q, 0});
+            thr.push_back(ContThr{nu, c->h_lev_E[i], c->h_lev_g[i], s0 * nu * nu * nu, q, (int32_t)(i - l0)});
         }
     }
     std::stable_sort(thr.begin(), thr.end(), [](const ContThr &a, const ContThr &b) { return a.nu < b.nu; });
@@ -936,6 +934,8 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
                     return launch_thermo(c->sp, cells, dev_widths(c), c->M_min, 0, c->d_cc.as<CellConst>(),
                                          c->d_cs.as<CellSpecies>(), st);
                 }));
+        lrt_status rc = cr_run(c, cells, st);   // QSS-CR populations (Sec. 2.1)
+        if (rc) return rc;
         if (c->n_cont_rec > 0) {
             lrt_status r;
             const size_t nc = (size_t)c->n_cells;
@@ -944,9 +944,9 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
                 (r = ensure(c, c->d_cont_lnb, nc * 2 * sizeof(double))))
                 return r;
             LRT_HIP(c, launch_cont_cells(c->d_cont_thr.as<ContThr>(), c->n_cont_thr, c->d_cont_rec.as<ContRec>(),
-                                         c->n_cont_rec, cells, c->d_cs.as<CellSpecies>(), c->nu_min,
-                                         c->nu_max, c->d_cont_cum.as<double>(), c->d_cont_ff.as<double>(),
-                                         c->d_cont_lnb.as<double>(), st));
+                                         c->n_cont_rec, cells, c->d_cs.as<CellSpecies>(), dev_cr(c),
+                                         c->nu_min, c->nu_max, c->d_cont_cum.as<double>(),
+                                         c->d_cont_ff.as<double>(), c->d_cont_lnb.as<double>(), st));
         }
         c->thermo_ready = true;
     }
@@ -957,8 +957,14 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
                    c->d_gN.as<double>(), c->d_gS.as<double>(), c->d_species.as<int32_t>(),
                    c->d_k0.as<int32_t>(), c->d_frac0.as<double>()};
         DevGrid g = dev_grid(c);
-        const DevBins B{(int32_t)c->n_bins, c->d_bin_sp.as<int32_t>(), c->d_bin_Ev.as<double>(),
-                        c->d_bin_Er.as<double>(), c->d_bin_aeta.as<double>(), c->d_bin_akap.as<double>()};
+        DevBins B{(int32_t)c->n_bins, c->d_bin_sp.as<int32_t>(), c->d_bin_Ev.as<double>(),
+                  c->d_bin_Er.as<double>(), c->d_bin_aeta.as<double>(), c->d_bin_akap.as<double>()};
+        if (c->n_cr > 0 && c->line_lev_ready) {
+            B.lev_off = c->d_bin_lev_off.as<int32_t>();
+            B.lev = c->d_bin_lev.as<int32_t>();
+            B.lnd = c->d_cr_lnd.as<double>();
+            B.lnd_stride = c->n_cr * c->cr_LS;
+        }
         LRT_HIP(c, timed(c, LRT_K_SCALE, st, [&] {
                     return launch_scale_bound(B, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(),
                                               c->n_cont_rec > 0 ? c->d_cont_lnb.as<double>() : nullptr,
@@ -1002,11 +1008,17 @@ lrt_status line_widths(lrt_ctx *c)
 
 DevLines dev_lines(const lrt_ctx *c)
 {
-    return DevLines{c->n_lines, c->d_nu0.as<double>(), c->d_Eu_ev.as<double>(),
-                    c->d_Eu_rot.as<double>(), c->d_El_ev.as<double>(), c->d_El_rot.as<double>(),
-                    c->d_lngu.as<double>(), c->d_seta0.as<double>(), c->d_skap0.as<double>(),
-                    c->d_gN.as<double>(), c->d_gS.as<double>(), c->d_species.as<int32_t>(),
-                    c->d_k0.as<int32_t>(), c->d_frac0.as<double>()};
+    DevLines L{c->n_lines, c->d_nu0.as<double>(), c->d_Eu_ev.as<double>(),
+               c->d_Eu_rot.as<double>(), c->d_El_ev.as<double>(), c->d_El_rot.as<double>(),
+               c->d_lngu.as<double>(), c->d_seta0.as<double>(), c->d_skap0.as<double>(),
+               c->d_gN.as<double>(), c->d_gS.as<double>(), c->d_species.as<int32_t>(),
+               c->d_k0.as<int32_t>(), c->d_frac0.as<double>()};
+    if (c->n_cr > 0 && c->line_lev_ready) {
+        L.lev = c->d_line_lev.as<int32_t>();
+        L.lnd = c->d_cr_lnd.as<double>();
+        L.lnd_stride = c->n_cr * c->cr_LS;
+    }
+    return L;
 }
 
 lrt_status band_range(lrt_ctx *c, int64_t band, int32_t &k_first, int32_t &n_band)

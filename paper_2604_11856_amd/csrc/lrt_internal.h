@@ -1,5 +1,6 @@
 // Internal declarations shared by the host side (lrt_host.cpp) and the
-// gfx950 kernels (lrt_accum.hip, lrt_march.hip).  Not part of the public ABI.
+// gfx950 kernels (lrt_accum.hip, lrt_march.hip, lrt_cr.hip).  Not part of
+// the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -78,13 +79,20 @@ struct DevLines {
     // few units of its last place)
     const int32_t *k0;
     const double *frac0;
+    // QSS-CR level populations (NULL: Boltzmann for every line): lev[i] = -1
+    // for a line without levels, else the offsets of its upper (low 16 bits)
+    // and lower (high 16 bits) level into a cell's row of lnd, the ln
+    // departures from Boltzmann, lnd_stride entries per cell
+    const int32_t *lev = nullptr;
+    const double *lnd = nullptr;
+    int32_t lnd_stride = 0;
 };
 
 // Atomic continuum.  A bound-free threshold (sorted by nu over all records)
 // and its level; s3 = sigma0 nu_thr^3 (the cross section is s3 / nu^3 above).
 struct ContThr {
     double nu, E, g, s3;
-    int32_t rec, pad;
+    int32_t rec, lev;   // record, level index in the atom's table
 };
 struct ContRec {
     int32_t species, ion;
@@ -103,16 +111,48 @@ struct DevCont {
 };
 constexpr double kNuH = 1e7 / 91.1267;   // hydrogen ground-state threshold, cm^-1
 
+// QSS collisional-radiative atoms (Sec. 2.1 CR model).  Levels 0..n_model-1
+// of the atom's table are solved for; levels n_model..n_lev-1 stay in
+// Boltzmann ratio (T_v) with level n_model-1.  Rate tables are Arrhenius
+// triples (C, n, E_a) of the forward processes: hpie/eie [l][l][3] at
+// [lo][hi] for lo -> hi, A [l][l] at [hi][lo], eii/ce [l][3] per level.
+// texp[2m], texp[2m+1]: forward / backward temperature T_tr^a T_v^(1-a) of
+// mechanism m (HPIE, EIE, EII, CE).
+constexpr int kCRMaxLevels = 64;   // one lane per level
+struct CRRec {
+    int32_t species, ion, partner, partner_ion;
+    int32_t n_model, n_lev, pn_lev, pad;
+    int64_t lev0, plev0;   // first level of the atom / the partner in the species tables
+    double E_ion, Q_ion, pE_ion, pQ_ion, nu_cut;
+    double texp[8];
+    const double *hpie, *eie, *A, *eii, *ce;
+};
+struct DevCR {
+    int32_t n;                 // atoms (0: off)
+    int32_t LS;                // entries per (cell, atom) row of pop / lnd
+    const CRRec *rec;
+    const int32_t *slot;       // per species: its atom record, or -1
+    const double *collider_w;  // per species: weight among the heavy colliders
+    double *pop;               // [n_cells][n][LS] level populations, cm^-3
+    double *lnd;               // [n_cells][n][LS] ln(population / Boltzmann population)
+};
+
 // Upper bounds of the line peaks for the per-cell scale, from level-energy
 // bins of the line list (one entry per (species, E_ev bin, E_rot bin) of the
 // upper levels and one per bin of the lower levels).  For every line i in a
 // bin, with Ev <= E_ev,i and Er <= E_rot,i:
 //   ln(seta0_i g_u,i / nu0_i) <= a_eta,  ln(skap0_i g_u,i / nu0_i) <= a_kap
-// (a_eta = -inf for lower-level bins).
+// (a_eta = -inf for lower-level bins).  With QSS-CR populations the bound of
+// bin b also takes the largest ln departure of the levels its lines belong to:
+// offsets lev[lev_off[b] .. lev_off[b+1]-1] into the cell's row of lnd (-1: a
+// line with Boltzmann populations); lev_off NULL: no departures.
 struct DevBins {
     int32_t n;
     const int32_t *species;
     const double *Ev, *Er, *a_eta, *a_kap;
+    const int32_t *lev_off = nullptr, *lev = nullptr;
+    const double *lnd = nullptr;
+    int32_t lnd_stride = 0;
 };
 
 struct DevGrid {
@@ -186,8 +226,14 @@ hipError_t launch_scale_bound(const DevBins &B, const CellConst *cc, const CellS
                               const double *cont_lnb, int32_t n_cells, int32_t n_species,
                               int32_t *escale, hipStream_t st);
 hipError_t launch_cont_cells(const ContThr *thr, int32_t n_thr, const ContRec *rec, int32_t n_rec,
-                             const DevCells &cells, const CellSpecies *cs, double nu_lo,
-                             double nu_hi, double *cum, double *ff, double *lnb, hipStream_t st);
+                             const DevCells &cells, const CellSpecies *cs, const DevCR &cr,
+                             double nu_lo, double nu_hi, double *cum, double *ff, double *lnb,
+                             hipStream_t st);
+
+// QSS-CR populations of every (cell, atom) (lrt_cr.hip); max_l / max_lev:
+// largest n_model / n_lev over the records.
+hipError_t launch_cr(const DevSpecies &sp, const DevCells &cells, const DevCR &cr, int32_t max_l,
+                     int32_t max_lev, const CellSpecies *cs, hipStream_t st);
 hipError_t launch_scale(const DevLines &L, int64_t i0, int64_t i1, const DevGrid &g,
                         const CellConst *cc, const CellSpecies *cs, int32_t n_cells,
                         int32_t n_species, int32_t *emax, int32_t *escale, hipStream_t st);

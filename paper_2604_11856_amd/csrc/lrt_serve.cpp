@@ -250,7 +250,8 @@ bool lrt_server::admit(Req &r)
         !ok(hipMemcpyAsync(ds, r.ds.data(), nc * 8, hipMemcpyHostToDevice, st), "upload") ||
         !ok(hipMemcpyAsync(N, r.N.data(), (size_t)nc * S * 8, hipMemcpyHostToDevice, st), "upload"))
         return true;   // failed and released; counts as handled
-    const DevLines L = dev_lines(ctx);
+    DevLines L = dev_lines(ctx);
+    L.lev = nullptr;   // a request's cells carry Boltzmann populations (no QSS-CR here)
     const DevGrid g = dev_grid(ctx);
     const DevCells cells{(int32_t)nc, S, T_tr, T_v, N, n_e};
     if (!ok(launch_thermo(ctx->sp, cells, dev_widths(ctx), ctx->M_min, r.mask, cc, cs, st), "thermo") ||
@@ -325,7 +326,8 @@ bool lrt_server::launch_epoch(Epoch &e)
             return false;
         }
     }
-    const DevLines L = dev_lines(ctx);
+    DevLines L = dev_lines(ctx);
+    L.lev = nullptr;   // Boltzmann populations in serving
     const DevGrid g = dev_grid(ctx);
     hipError_t err = hipMemcpyAsync(e.d_items.p, e.h_items, (size_t)n * sizeof(ServeItem),
                                     hipMemcpyHostToDevice, e.stream);

@@ -34,9 +34,10 @@ EXPORTS = ["lrt_version", "lrt_status_string", "lrt_create", "lrt_destroy", "lrt
            "lrt_fibonacci_quadrature", "lrt_set_march", "lrt_set_far_temperature", "lrt_trace_axi_ray", "lrt_get_sizes", "lrt_get_ray",
            "lrt_coeffs", "lrt_march", "lrt_solve", "lrt_count_terms", "lrt_profile",
            "lrt_profile_read", "lrt_server_start", "lrt_submit", "lrt_poll", "lrt_wait",
-           "lrt_cancel", "lrt_server_info", "lrt_server_stop"]
+           "lrt_cancel", "lrt_server_info", "lrt_server_stop", "lrt_set_cr", "lrt_set_line_levels",
+           "lrt_cr_populations"]
 
-KERNELS = {"thermo": 0, "scale": 1, "ranges": 2, "accum": 3, "march": 4}
+KERNELS = {"thermo": 0, "scale": 1, "ranges": 2, "accum": 3, "march": 4, "cr": 5}
 
 
 class LrtError(RuntimeError):
@@ -60,6 +61,14 @@ class _Lines(C.Structure):
 class _Continuum(C.Structure):
     _fields_ = [("species", C.c_int32), ("ion", C.c_int32), ("E_ion", C.c_double),
                 ("Q_ion", C.c_double), ("sigma0", _dp), ("peach", C.c_double * 8), ("z", C.c_double)]
+
+
+class _CRAtom(C.Structure):
+    _fields_ = [("species", C.c_int32), ("ion", C.c_int32), ("partner", C.c_int32),
+                ("partner_ion", C.c_int32), ("n_model", C.c_int32), ("E_ion", C.c_double),
+                ("Q_ion", C.c_double), ("partner_E_ion", C.c_double), ("partner_Q_ion", C.c_double),
+                ("nu_cut", C.c_double), ("texp", C.c_double * 8), ("hpie", _dp), ("eie", _dp),
+                ("A", _dp), ("eii", _dp), ("ce", _dp)]
 
 
 class _Cells(C.Structure):
@@ -127,6 +136,9 @@ def lib():
             "lrt_cancel": (st, [_vp, C.c_uint64]),
             "lrt_server_info": (st, [_vp, _i64p, _i64p, _i64p, _i64p, C.POINTER(C.c_size_t)]),
             "lrt_server_stop": (st, [_vp]),
+            "lrt_set_cr": (st, [_vp, C.c_int, C.POINTER(_CRAtom), _dp]),
+            "lrt_set_line_levels": (st, [_vp, _i32p, _i32p, C.c_int64]),
+            "lrt_cr_populations": (st, [_vp, C.c_int, _dp, _vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -250,6 +262,38 @@ class Context:
         e = np.ascontiguousarray(E_ion, np.float64)
         self._chk(self._L.lrt_set_lorentz(self.h, _p(e)))
 
+    def set_cr(self, cr):
+        """QSS collisional-radiative atoms (synth.CRModel), or None for none."""
+        if cr is None or not cr.species:
+            self._chk(self._L.lrt_set_cr(self.h, 0, None, None))
+            return
+        keep, arr = [], (_CRAtom * len(cr.species))()
+        for j, r in enumerate(cr.species):
+            t = [np.ascontiguousarray(a, np.float64) for a in (r.hpie, r.eie, r.A, r.eii, r.ce)]
+            keep.append(t)
+            arr[j] = _CRAtom(int(r.species), int(r.ion), int(r.partner), int(r.partner_ion),
+                             int(r.n_model), float(r.E_ion), float(r.Q_ion), float(r.partner_E_ion),
+                             float(r.partner_Q_ion), float(r.nu_cut),
+                             (C.c_double * 8)(*[float(v) for v in r.texp]), *[_p(a) for a in t])
+        w = np.ascontiguousarray(cr.collider_w, np.float64)
+        self._chk(self._L.lrt_set_cr(self.h, len(cr.species), arr, _p(w)))
+
+    def set_line_levels(self, levels):
+        """[n_lines, 2] (upper, lower) level per line (-1: none), or None."""
+        if levels is None:
+            self._chk(self._L.lrt_set_line_levels(self.h, None, None, 0))
+            return
+        lev = np.asarray(levels, np.int32)
+        u, l = np.ascontiguousarray(lev[:, 0]), np.ascontiguousarray(lev[:, 1])
+        self._chk(self._L.lrt_set_line_levels(self.h, _p(u, _i32p), _p(l, _i32p), lev.shape[0]))
+
+    def cr_populations(self, atom: int, n_levels: int, stream=None):
+        """Level populations [n_cells, n_levels] of QSS-CR record `atom`."""
+        nc = max(self.sizes()["n_cells"], 0)
+        out = np.zeros((nc, n_levels))
+        self._chk(self._L.lrt_cr_populations(self.h, int(atom), _p(out), _stream(stream)))
+        return out
+
     def set_march(self, scheme: int):
         self._chk(self._L.lrt_set_march(self.h, int(scheme)))
 
@@ -272,6 +316,10 @@ class Context:
         self.set_rays(wl.geometry)
         if getattr(wl, "continuum", None):
             self.set_continuum(wl.continuum)
+        if getattr(wl, "cr", None) is not None:
+            self.set_cr(wl.cr)
+            if getattr(wl, "line_levels", None) is not None:
+                self.set_line_levels(wl.line_levels)
         return self
 
     def sizes(self):
