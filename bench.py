@@ -251,7 +251,8 @@ def cr_cost(ctx, wl, lrt, torch, q_boltzmann, reps=2, scale_cells=32768):
            "systems": n_sys, "ms_per_step": dt * 1e3,
            "cr_ms_per_solve": prof["cr"][0] / max(1, prof["cr"][1]),
            "accum_ms_per_launch": prof["accum"][0] / max(1, prof["accum"][1]),
-           "q_rad_ratio_cr_over_boltzmann": [float(a / b) if b else None for a, b in zip(q, q_boltzmann)]}
+           "q_rad_ratio_cr_over_boltzmann": [float(a / b) if b and np.isfinite(a / b) else None
+                                             for a, b in zip(q, q_boltzmann)]}
     # the CR solve alone at a larger cell count (the axisymmetric grid's)
     sw = synth.with_cr(synth.stagnation_line(n_cells=scale_cells, n_atomic=64, n_rovib=0, n_points=4096,
                                              n_mu=0))

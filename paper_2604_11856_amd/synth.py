@@ -297,8 +297,11 @@ def air_cr(species: List[Species], n_model: int = 18, seed: int = 11863) -> CRMo
     E_a = c2 max(E_ion - E_i, 0); CE with the other atom (N(i) + O+ <-> N+ + O
     and O(i) + N+ <-> O+ + N) k ~ logU(1e-12, 1e-10), n ~ U(0, 0.5),
     E_a = c2 max(E_ion - E_i - E_ion', 0).  Temperatures: HPIE forward at
-    sqrt(T_tr T_v), backward at T_tr; EIE and EII at T_v (= T_e); CE at T_tr.
-    Heavy colliders: every species but e-, weight 1."""
+    sqrt(T_tr T_v), backward at T_tr; EIE and EII at T_v (= T_e); CE at
+    sqrt(T_tr T_v) both ways (at T_tr, charge exchange fills the upper levels
+    of the cold-T_v cells behind the shock towards a 30,000 K distribution
+    while radiation drains the lower ones: inversions whose gain overflows
+    the grazing rays).  Heavy colliders: every species but e-, weight 1."""
     rng = np.random.Generator(np.random.PCG64(seed))
     names = [sp.name for sp in species]
     recs = []
@@ -330,7 +333,7 @@ def air_cr(species: List[Species], n_model: int = 18, seed: int = 11863) -> CRMo
             partner, partner_ion, pE, pQ = -1, -1, 0.0, 1.0
         recs.append(CRSpecies(names.index(a), ion_of(a), partner, partner_ion, L,
                               Ei, ION_Q[a + "+"], pE, pQ, hpie, eie, A, eii, ce,
-                              np.array([0.5, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 1.0])))
+                              np.array([0.5, 1.0, 0.0, 0.0, 0.0, 0.0, 0.5, 0.5])))
     w = np.array([0.0 if n == "e-" else 1.0 for n in names])
     return CRModel(recs, w)
 
