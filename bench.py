@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--workload", default="stagnation", choices=["stagnation", "slab", "axi"])
     ap.add_argument("--cpu-points", type=int, default=512, help="grid points of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the side measurements (march schemes, continuum, QSS-CR), so that a "
+                         "profiler sees only the timed steps")
     ap.add_argument("--serving-requests", type=int, default=48,
                     help="requests per serving phase (closed loop, then open loop); 0 skips")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -333,9 +336,11 @@ def main():
                    "I_int_max": float(np.max(np.abs(I32 - I64) / np.maximum(np.abs(I64), 1e-300))),
                    "q": [float(abs(a - b) / abs(b)) if b != 0 else 0.0 for a, b in zip(q32, q64)]}}
 
-    march_schemes = compare_march_schemes(ctx, lrt, torch, sz)
-    continuum = continuum_cost(ctx, wl, lrt, torch)
-    cr = cr_cost(ctx, wl, lrt, torch, q32) if args.workload == "stagnation" else None
+    march_schemes = continuum = cr = None
+    if not args.no_side:
+        march_schemes = compare_march_schemes(ctx, lrt, torch, sz)
+        continuum = continuum_cost(ctx, wl, lrt, torch)
+        cr = cr_cost(ctx, wl, lrt, torch, q32) if args.workload == "stagnation" else None
 
     acc_ms, acc_n = prof32["accum"]
     acc_s = acc_ms / 1e3 / max(1, acc_n)
