@@ -230,38 +230,47 @@ def continuum_cost(ctx, wl, lrt, torch, reps=2):
     return out
 
 
-def cr_cost(ctx, wl, lrt, torch, q_boltzmann, reps=2, scale_cells=32768):
-    """QSS collisional-radiative populations of N and O (Sec. 2.1): whole
-    single-precision solves with the atoms' lines and bound-free absorption
+def cr_cost(wl, lrt, torch, reps=2, scale_cells=32768):
+    """QSS collisional-radiative populations of N and O (Sec. 2.1) on the
+    workload with its atomic lines put on level pairs (synth.with_cr): whole
+    single-precision solves with those lines and the bound-free absorption
     taking their populations from the per-(cell, atom) CR solve, against the
-    Boltzmann solve; then the CR solve alone on scale_cells cells (one wave
-    per (cell, atom) system)."""
+    same line list with Boltzmann populations; then the CR solve alone on
+    scale_cells cells (one wave per (cell, atom) system)."""
     from paper_2604_11856_amd import synth
-    cr = synth.air_cr(wl.species)
-    if not cr.species:
+    cw = synth.with_cr(wl)
+    if not cw.cr.species:
         return None
-    ctx.set_cr(cr)
-    ctx.set_line_levels(synth.tie_lines_to_levels(wl.lines, wl.species, cr))
-    ctx.solve(lrt.LRT_FP32_COMP)
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        q, _, _ = ctx.solve(lrt.LRT_FP32_COMP)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    prof = {k: ctx.profile_read(k) for k in ("cr", "accum", "thermo")}
-    ctx.profile(False)
+    ctx = lrt.Context(0).load(cw)
+
+    def timed_solves():
+        ctx.solve(lrt.LRT_FP32_COMP)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            q, _, _ = ctx.solve(lrt.LRT_FP32_COMP)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        prof = {k: ctx.profile_read(k) for k in ("cr", "accum")}
+        ctx.profile(False)
+        return q, dt, prof
+
+    q_cr, dt_cr, p_cr = timed_solves()
     ctx.set_cr(None)
-    ctx.set_line_levels(None)
-    n_sys = wl.cells.n * len(cr.species)
-    out = {"atoms": [wl.species[r.species].name for r in cr.species],
-           "levels_solved": [int(r.n_model) for r in cr.species],
-           "systems": n_sys, "ms_per_step": dt * 1e3,
-           "cr_ms_per_solve": prof["cr"][0] / max(1, prof["cr"][1]),
-           "accum_ms_per_launch": prof["accum"][0] / max(1, prof["accum"][1]),
+    q_b, dt_b, p_b = timed_solves()
+    ctx.close()
+    torch.cuda.empty_cache()
+    out = {"atoms": [wl.species[r.species].name for r in cw.cr.species],
+           "levels_solved": [int(r.n_model) for r in cw.cr.species],
+           "lines_on_levels": int((cw.line_levels[:, 0] >= 0).sum()),
+           "systems": wl.cells.n * len(cw.cr.species),
+           "ms_per_step": dt_cr * 1e3, "ms_per_step_boltzmann": dt_b * 1e3,
+           "cr_ms_per_solve": p_cr["cr"][0] / max(1, p_cr["cr"][1]),
+           "accum_ms_per_launch": p_cr["accum"][0] / max(1, p_cr["accum"][1]),
+           "accum_ms_per_launch_boltzmann": p_b["accum"][0] / max(1, p_b["accum"][1]),
            "q_rad_ratio_cr_over_boltzmann": [float(a / b) if b and np.isfinite(a / b) else None
-                                             for a, b in zip(q, q_boltzmann)]}
+                                             for a, b in zip(q_cr, q_b)]}
     # the CR solve alone at a larger cell count (the axisymmetric grid's)
     sw = synth.with_cr(synth.stagnation_line(n_cells=scale_cells, n_atomic=64, n_rovib=0, n_points=4096,
                                              n_mu=0))
@@ -346,7 +355,7 @@ def main():
     if not args.no_side:
         march_schemes = compare_march_schemes(ctx, lrt, torch, sz)
         continuum = continuum_cost(ctx, wl, lrt, torch)
-        cr = cr_cost(ctx, wl, lrt, torch, q32) if args.workload == "stagnation" else None
+        cr = cr_cost(wl, lrt, torch) if args.workload == "stagnation" else None
 
     acc_ms, acc_n = prof32["accum"]
     acc_s = acc_ms / 1e3 / max(1, acc_n)

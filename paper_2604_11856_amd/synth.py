@@ -297,11 +297,8 @@ def air_cr(species: List[Species], n_model: int = 18, seed: int = 11863) -> CRMo
     E_a = c2 max(E_ion - E_i, 0); CE with the other atom (N(i) + O+ <-> N+ + O
     and O(i) + N+ <-> O+ + N) k ~ logU(1e-12, 1e-10), n ~ U(0, 0.5),
     E_a = c2 max(E_ion - E_i - E_ion', 0).  Temperatures: HPIE forward at
-    sqrt(T_tr T_v), backward at T_tr; EIE and EII at T_v (= T_e); CE at
-    sqrt(T_tr T_v) both ways (at T_tr, charge exchange fills the upper levels
-    of the cold-T_v cells behind the shock towards a 30,000 K distribution
-    while radiation drains the lower ones: inversions whose gain overflows
-    the grazing rays).  Heavy colliders: every species but e-, weight 1."""
+    sqrt(T_tr T_v), backward at T_tr; EIE and EII at T_v (= T_e); CE at T_tr.
+    Heavy colliders: every species but e-, weight 1."""
     rng = np.random.Generator(np.random.PCG64(seed))
     names = [sp.name for sp in species]
     recs = []
@@ -333,7 +330,7 @@ def air_cr(species: List[Species], n_model: int = 18, seed: int = 11863) -> CRMo
             partner, partner_ion, pE, pQ = -1, -1, 0.0, 1.0
         recs.append(CRSpecies(names.index(a), ion_of(a), partner, partner_ion, L,
                               Ei, ION_Q[a + "+"], pE, pQ, hpie, eie, A, eii, ce,
-                              np.array([0.5, 1.0, 0.0, 0.0, 0.0, 0.0, 0.5, 0.5])))
+                              np.array([0.5, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 1.0])))
     w = np.array([0.0 if n == "e-" else 1.0 for n in names])
     return CRModel(recs, w)
 
@@ -351,10 +348,48 @@ def tie_lines_to_levels(lines: Lines, species: List[Species], cr: CRModel) -> np
     return out
 
 
+def lines_on_levels(lines: Lines, species: List[Species], cr: CRModel, grid: Grid,
+                    seed: int = 11864, offset: float = 20.0):
+    """Put the lines of the CR atoms on transitions between table levels: a
+    line keeps its A and takes the level pair nearest in energy to its drawn
+    E_u and E_l, with upper energy E_lev(u) + d_u, lower energy E_lev(l) + d_l
+    (d ~ U(-offset, offset) cm^-1, a seeded fine-structure spread), nu0 their
+    difference and the levels' degeneracies.  A line whose nearest pair is
+    not upper above lower, or whose new centre leaves the grid, keeps its
+    drawn values and no levels.  (A line far from the levels it is tied to
+    would take its Boltzmann share of each level at T_v, so that in the
+    cold-T_v cells behind the shock a line whose nu0 falls short of the gap
+    between its levels reads an inversion of order e^{c2 (gap - nu0)/T_v}
+    from populations that are not inverted.)  Returns the lines re-sorted by
+    nu0 and their [n_lines, 2] levels."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = {f.name: getattr(lines, f.name).copy() for f in dataclasses.fields(lines)}
+    lev = np.full((lines.n, 2), -1, np.int32)
+    for rec in cr.species:
+        sel = np.nonzero(lines.species == rec.species)[0]
+        E, g = species[rec.species].level_E, species[rec.species].level_g
+        u = np.argmin(np.abs(lines.Eu_ev[sel][:, None] - E[None, :]), axis=1)
+        l = np.argmin(np.abs(lines.El_ev[sel][:, None] - E[None, :]), axis=1)
+        eu = E[u] + rng.uniform(-offset, offset, sel.size)
+        el = E[l] + rng.uniform(-offset, offset, sel.size)
+        nu = eu - el
+        ok = (u > l) & (nu >= grid.nu_min) & (nu <= grid.nu_max)
+        t = sel[ok]
+        d["Eu_ev"][t], d["El_ev"][t], d["nu0"][t] = eu[ok], el[ok], nu[ok]
+        d["gu"][t], d["gl"][t] = g[u[ok]], g[l[ok]]
+        lev[t, 0], lev[t, 1] = u[ok], l[ok]
+    order = np.argsort(d["nu0"], kind="stable")
+    return (Lines(**{k: np.ascontiguousarray(v[order]) for k, v in d.items()}),
+            np.ascontiguousarray(lev[order]))
+
+
 def with_cr(wl: Workload, n_model: int = 18, seed: int = 11863) -> Workload:
-    """The same workload with QSS-CR populations for its atoms."""
+    """The workload with QSS-CR populations for its atoms N and O, whose
+    lines are put on transitions between their table levels
+    (lines_on_levels)."""
     cr = air_cr(wl.species, n_model, seed)
-    return dataclasses.replace(wl, cr=cr, line_levels=tie_lines_to_levels(wl.lines, wl.species, cr))
+    lines, lev = lines_on_levels(wl.lines, wl.species, cr, wl.grid)
+    return dataclasses.replace(wl, cr=cr, lines=lines, line_levels=lev)
 
 
 def none_species(name: str) -> Species:
