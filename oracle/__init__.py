@@ -86,6 +86,7 @@ def lib():
             "orc_c2": (d, []),
             "orc_partition_atom": (d, [i64, _dp, _dp, d]),
             "orc_partition": (d, [C.POINTER(_Species), C.c_int, d, d]),
+            "orc_state_partition": (d, [C.POINTER(_Species), C.c_int, i64, d, d]),
             "orc_level_population": (d, [d, d, d, d, d, d, d]),
             "orc_doppler_hwhm": (d, [d, d, d]),
             "orc_lorentz_hwhm": (d, [d, d]),
@@ -286,6 +287,8 @@ def grid_step(grid) -> float:
 # ---------------------------------------------------------------------------
 
 N_AVOGADRO = 6.02214076e23   # mol^-1 (exact SI value)
+H_CGS = 6.62607015e-27        # erg s
+KB_CGS = 1.380649e-16         # erg / K
 
 
 def arrhenius(C_a: float, n_a: float, E_a: float, T: float) -> float:
@@ -304,10 +307,30 @@ def state_partition(E: float, g: float, T: float) -> float:
     return g * math.exp(-c2() * E / T)
 
 
+M_PROTON_G = 1.0 / N_AVOGADRO   # g per (g/mol)
+KIND_ATOM = 1                   # species kind of an atom (2: diatomic molecule)
+
+
+def _cr_states(rec, species):
+    """State energies (level energies of an atom, electronic terms of a
+    molecule) and a partition-function callable q(i, T_v, T_tr) of one state
+    with the species' own energy zero."""
+    sp = species[rec.species]
+    if sp.kind == KIND_ATOM:
+        E, g = np.asarray(sp.level_E, np.float64), np.asarray(sp.level_g, np.float64)
+        return E, lambda i, Tv, Ttr: state_partition(E[i], g[i], Tv)
+    table = SpeciesTable(species)
+    keep = table   # keeps the arrays alive for the C calls
+    return (np.asarray(sp.el_T, np.float64),
+            lambda i, Tv, Ttr: lib().orc_state_partition(C.byref(keep.s), rec.species, int(i),
+                                                         float(Tv), float(Ttr)))
+
+
 def cr_system(rec, species, T_tr: float, T_v: float, N_cell, n_e: float, collider_w):
-    """The QSS system R n = b of Sec. 2.1 for one atom (CR record rec) in one
-    cell, n = populations of levels 0..l-1 of its level table (level 0 the
-    ground state, l = rec.n_model).
+    """The QSS system R n = b of Sec. 2.1 for one atom or molecule (CR record
+    rec) in one cell, n = populations of its states 0..l-1 (the atom's table
+    levels or the molecule's electronic states; state 0 the ground state,
+    l = rec.n_model).
 
     Row 0 is the closure: the populations of all levels add up to the atom's
     density, the levels p >= l standing in Boltzmann ratio Q_p/Q_(l-1) (at
@@ -322,18 +345,29 @@ def cr_system(rec, species, T_tr: float, T_v: float, N_cell, n_e: float, collide
     coefficient over Avogadro's number times the collider density (heavy
     colliders: sum_s collider_w[s] N_s); reverse rates follow the paper's
     detailed-balance relation evaluated at the backward temperature, with
-    the state partition functions g e^{-c2 E/T}, the ion's Q_ion
-    e^{-c2 E_ion/T} and the free electron's 2 (2 pi m_e k T / h^2)^{3/2}."""
+    the state partition functions (g e^{-c2 E/T} for an atomic level, g_e
+    e^{-c2 T_e/T} Q_vr(T) for a molecular electronic state, all modes at the
+    rate's temperature), the ion's Q_ion e^{-c2 E_ion/T} and the free
+    electron's 2 (2 pi m_e k T / h^2)^{3/2}.
+
+    A molecule's state i also dissociates into X + Y by heavy-particle and
+    electron impact (loss k_f N_M / N_A, k_f n_e / N_A), and X + Y recombine
+    into it (source k_b N_X N_Y N_M / N_A, k_b N_X N_Y n_e / N_A) with the
+    detailed-balance rate k_b = [k_f Q_i / (Q_X Q_Y)]_{T_b} (h^2 / (2 pi mu k
+    T_b))^{3/2} e^{c2 E_diss / T_b}: the translational partition function of
+    the pair (reduced mass mu) and the energy of X + Y above the molecule's
+    energy zero.  The closure's Boltzmann tail of a molecule takes the
+    state partition functions at (T_v, T_tr)."""
     sp = species[rec.species]
-    E, g = np.asarray(sp.level_E, np.float64), np.asarray(sp.level_g, np.float64)
+    E, q2 = _cr_states(rec, species)
     Lm, Ls = int(rec.n_model), E.size
     NA = N_AVOGADRO
     N_cell = np.asarray(N_cell, np.float64)
     N_M = sum(float(collider_w[s]) * float(N_cell[s]) for s in range(N_cell.size))
     N_ion = float(N_cell[rec.ion]) if rec.ion >= 0 else 0.0
     Tm = [(rate_temperature(rec.texp[2 * m], T_tr, T_v),
-           rate_temperature(rec.texp[2 * m + 1], T_tr, T_v)) for m in range(4)]
-    Q = lambda i, T: state_partition(E[i], g[i], T)
+           rate_temperature(rec.texp[2 * m + 1], T_tr, T_v)) for m in range(len(rec.texp) // 2)]
+    Q = lambda i, T: q2(i, T, T)
 
     def k_exc(table, m, i, j):
         """rate coefficient of the transition i -> j of mechanism m (0 HPIE, 1 EIE)"""
@@ -345,10 +379,21 @@ def cr_system(rec, species, T_tr: float, T_v: float, N_cell, n_e: float, collide
     def escape(hi, lo):
         return 0.0 if E[hi] - E[lo] > rec.nu_cut else 1.0
 
+    diss = getattr(rec, "diss_x", -1) >= 0
+    if diss:
+        def product_q(p, Qc, T):
+            ps = species[p]
+            if ps.kind == KIND_ATOM:
+                return sum(state_partition(ps.level_E[k], ps.level_g[k], T) for k in range(len(ps.level_E)))
+            return Qc
+        mX, mY = species[rec.diss_x].mass, species[rec.diss_y].mass
+        mu = mX * mY / (mX + mY) * M_PROTON_G
+        N_X, N_Y = float(N_cell[rec.diss_x]), float(N_cell[rec.diss_y])
+
     R = np.zeros((Lm, Lm))
     b = np.zeros(Lm)
     R[0, :] = 1.0
-    R[0, Lm - 1] = 1.0 + sum(Q(p, T_v) / Q(Lm - 1, T_v) for p in range(Lm, Ls))
+    R[0, Lm - 1] = 1.0 + sum(q2(p, T_v, T_tr) / q2(Lm - 1, T_v, T_tr) for p in range(Lm, Ls))
     b[0] = float(N_cell[rec.species])
     for i in range(1, Lm):
         loss = 0.0
@@ -357,9 +402,12 @@ def cr_system(rec, species, T_tr: float, T_v: float, N_cell, n_e: float, collide
                 loss += k_exc(rec.hpie, 0, i, m) / NA * N_M + k_exc(rec.eie, 1, i, m) / NA * n_e
         for m in range(i):
             loss += escape(i, m) * rec.A[i, m]
-        loss += arrhenius(*rec.eii[i], Tm[2][0]) / NA * n_e
-        if rec.partner >= 0:
-            loss += arrhenius(*rec.ce[i], Tm[3][0]) / NA * float(N_cell[rec.partner_ion])
+        if not diss:
+            loss += arrhenius(*rec.eii[i], Tm[2][0]) / NA * n_e
+            if rec.partner >= 0:
+                loss += arrhenius(*rec.ce[i], Tm[3][0]) / NA * float(N_cell[rec.partner_ion])
+        else:
+            loss += arrhenius(*rec.hpid[i], Tm[4][0]) / NA * N_M + arrhenius(*rec.eid[i], Tm[5][0]) / NA * n_e
         R[i, i] = -loss
         for j in range(Lm):
             if j == i:
@@ -368,6 +416,18 @@ def cr_system(rec, species, T_tr: float, T_v: float, N_cell, n_e: float, collide
             if j > i:
                 gain += escape(j, i) * rec.A[j, i]
             R[i, j] = gain
+        if diss:
+            src = 0.0
+            for m, coll in ((4, N_M), (5, n_e)):
+                T_b = Tm[m][1]
+                table = rec.hpid if m == 4 else rec.eid
+                Vmu = (H_CGS * H_CGS / (2.0 * math.pi * mu * KB_CGS * T_b)) ** 1.5
+                k_b = (arrhenius(*table[i], T_b) * Q(i, T_b)
+                       / (product_q(rec.diss_x, rec.Q_x, T_b) * product_q(rec.diss_y, rec.Q_y, T_b))
+                       * Vmu * math.exp(c2() * rec.E_diss / T_b))
+                src += k_b / NA * N_X * N_Y * coll
+            b[i] = -src
+            continue
         T_b = Tm[2][1]
         k_rec = (arrhenius(*rec.eii[i], T_b) * Q(i, T_b)
                  / (rec.Q_ion * math.exp(-c2() * rec.E_ion / T_b) * (2.0 / saha_volume(T_b))))
@@ -389,43 +449,49 @@ def cr_level_populations(rec, species, T_tr, T_v, N_cell, n_e, collider_w):
     0..l-1 from the LU solution of R n = b (LAPACK's partially pivoted LU),
     the levels above from their Boltzmann ratio to level l-1 at T_v; all zero
     in a cell without the atom."""
-    sp = species[rec.species]
+    E, q2 = _cr_states(rec, species)
     if not float(N_cell[rec.species]) > 0.0:
-        return np.zeros(len(sp.level_E))   # no atoms in the cell: no level populations
+        return np.zeros(E.size)   # none of the species in the cell: no state populations
     R, b = cr_system(rec, species, T_tr, T_v, N_cell, n_e, collider_w)
     n = np.linalg.solve(R, b)
     Lm = int(rec.n_model)
-    out = np.empty(len(sp.level_E))
+    out = np.empty(E.size)
     out[:Lm] = n
-    q_top = state_partition(sp.level_E[Lm - 1], sp.level_g[Lm - 1], T_v)
-    for p in range(Lm, len(sp.level_E)):
-        out[p] = n[Lm - 1] * state_partition(sp.level_E[p], sp.level_g[p], T_v) / q_top
+    q_top = q2(Lm - 1, T_v, T_tr)
+    for p in range(Lm, E.size):
+        out[p] = n[Lm - 1] * q2(p, T_v, T_tr) / q_top
     return out
 
 
 def cr_populations(cr, species, cells):
-    """Per CR record, the level populations [n_cells, n_levels] of its atom."""
+    """Per CR record, the state populations [n_cells, n_states] of its species."""
     out = []
     for rec in cr.species:
         out.append(np.stack([cr_level_populations(rec, species, float(cells.T_tr[c]),
                                                   float(cells.T_v[c]), cells.N[c],
                                                   float(cells.n_e[c]), cr.collider_w)
                              for c in range(cells.n)]) if cells.n else
-                   np.zeros((0, len(species[rec.species].level_E))))
+                   np.zeros((0, _cr_states(rec, species)[0].size)))
     return out
 
 
 def cr_level_table(cr, species, cells):
-    """(N_lev [n_cells, total levels of all species], lev_on [n_species]) for
-    the coefficient routines, or None without a CR model."""
+    """(N_lev [n_cells, atom levels of all species + molecular electronic
+    states of all species], lev_on [n_species]) for the coefficient
+    routines, or None without a CR model."""
     if cr is None:
         return None
     off = np.concatenate([[0], np.cumsum([len(s.level_E) for s in species])])
-    N_lev = np.zeros((cells.n, int(off[-1])))
+    eoff = off[-1] + np.concatenate([[0], np.cumsum([len(s.el_T) for s in species])])
+    N_lev = np.zeros((cells.n, int(eoff[-1])))
     lev_on = np.zeros(len(species), np.int32)
     for rec, pop in zip(cr.species, cr_populations(cr, species, cells)):
-        N_lev[:, off[rec.species]:off[rec.species + 1]] = pop
-        lev_on[rec.species] = 1
+        s = rec.species
+        if species[s].kind == KIND_ATOM:
+            N_lev[:, off[s]:off[s + 1]] = pop
+        else:
+            N_lev[:, eoff[s]:eoff[s + 1]] = pop
+        lev_on[s] = 1
     return N_lev, lev_on
 
 

@@ -70,7 +70,8 @@ typedef struct {
     int64_t n_cells;
     int n_species;
     const double *T_tr, *T_v, *N, *n_e;   /* N is [n_cells][n_species] */
-    /* optional (NULL: none): level populations [n_cells][lev_off[n_species]]
+    /* optional (NULL: none): state populations [n_cells][lev_off[n_species]
+     * + el_off[n_species]] (atom levels, then molecular electronic states)
      * that replace the Boltzmann ones of the species with lev_on[s] != 0 */
     const double *N_lev;
     const int *lev_on;
@@ -125,6 +126,31 @@ double orc_partition_molecule(const orc_species *sp, int s, double Tv, double Tt
         q += sp->el_g[e] * exp(-c2 * sp->el_T[e] / Tv) * qvr;
     }
     return q;
+}
+
+/* Partition function of one state of species s (energy zero as in the
+ * species' own partition function): an atom's level `state`,
+ * g e^{-c2 E/T_v}, or a molecule's electronic state `state`,
+ * g_e e^{-c2 T_e/T_v} Q_vr,e with Q_vr,e as above. */
+double orc_state_partition(const orc_species *sp, int s, int64_t state, double Tv, double Ttr)
+{
+    const double c2 = orc_c2();
+    if (sp->kind[s] == 1) {
+        int64_t j = sp->lev_off[s] + state;
+        return sp->lev_g[j] * exp(-c2 * sp->lev_E[j] / Tv);
+    }
+    int64_t e = sp->el_off[s] + state;
+    double qvr = 0.0;
+    for (int64_t v = sp->vib_off[e]; v < sp->vib_off[e + 1]; ++v) {
+        double qr = 0.0;
+        for (int J = 0; J <= sp->el_Jmax[e]; ++J) {
+            double jj = (double)J * (J + 1.0);
+            double F = sp->vib_B[v] * jj - sp->vib_D[v] * jj * jj;
+            qr += (2.0 * J + 1.0) * exp(-c2 * F / Ttr);
+        }
+        qvr += exp(-c2 * sp->vib_G[v] / Tv) * qr;
+    }
+    return sp->el_g[e] * exp(-c2 * sp->el_T[e] / Tv) * qvr;
 }
 
 double orc_partition(const orc_species *sp, int s, double Tv, double Ttr)
@@ -269,13 +295,22 @@ void orc_line_pair(const orc_species *sp, const orc_lines *L, int64_t i,
 {
     int s = L->species[i];
     double nu0 = L->nu0[i];
-    if (Nlev && L->lev_u && L->lev_u[i] >= 0) {
+    if (Nlev && L->lev_u && L->lev_u[i] >= 0 && sp->kind[s] == 1) {
         const int64_t o = sp->lev_off[s];
         const int u = L->lev_u[i], l = L->lev_l[i];
         p->Nu = orc_sublevel_population(Nlev[u], sp->lev_g[o + u], sp->lev_E[o + u], L->gu[i],
                                         L->Eu_ev[i], L->Eu_rot[i], Tv, Ttr);
         p->Nl = orc_sublevel_population(Nlev[l], sp->lev_g[o + l], sp->lev_E[o + l], L->gl[i],
                                         L->El_ev[i], L->El_rot[i], Tv, Ttr);
+    } else if (Nlev && L->lev_u && L->lev_u[i] >= 0) {
+        /* a molecule's rovibronic level takes its Boltzmann share of its
+         * electronic state: g e^{-c2 E_ev/T_v - c2 E_rot/T_tr} / Q_state */
+        const double c2 = orc_c2();
+        const int u = L->lev_u[i], l = L->lev_l[i];
+        p->Nu = Nlev[u] * L->gu[i] * exp(-c2 * L->Eu_ev[i] / Tv - c2 * L->Eu_rot[i] / Ttr)
+                / orc_state_partition(sp, s, u, Tv, Ttr);
+        p->Nl = Nlev[l] * L->gl[i] * exp(-c2 * L->El_ev[i] / Tv - c2 * L->El_rot[i] / Ttr)
+                / orc_state_partition(sp, s, l, Tv, Ttr);
     } else {
         p->Nu = orc_level_population(N_s, Q_s, L->gu[i], L->Eu_ev[i], L->Eu_rot[i], Tv, Ttr);
         p->Nl = orc_level_population(N_s, Q_s, L->gl[i], L->El_ev[i], L->El_rot[i], Tv, Ttr);
@@ -291,11 +326,15 @@ void orc_line_pair(const orc_species *sp, const orc_lines *L, int64_t i,
     orc_window(nu0, p->gV, nu_min, h, n_points, &p->klo, &p->khi);
 }
 
-/* The level populations of species s in cell c, or NULL (Boltzmann). */
+/* The state populations of species s in cell c, or NULL (Boltzmann).
+ * N_lev holds, per cell, the atoms' levels (lev_off) followed by the
+ * molecules' electronic states (el_off). */
 static const double *orc_cell_levels(const orc_species *sp, const orc_cells *C, int64_t c, int s)
 {
     if (!C->N_lev || !C->lev_on || !C->lev_on[s]) return NULL;
-    return C->N_lev + c * sp->lev_off[sp->n_species] + sp->lev_off[s];
+    const int64_t NL = sp->lev_off[sp->n_species], NE = sp->el_off[sp->n_species];
+    const double *row = C->N_lev + c * (NL + NE);
+    return sp->kind[s] == 2 ? row + NL + sp->el_off[s] : row + sp->lev_off[s];
 }
 
 /* first index with a[i] >= v in a sorted array */

@@ -150,22 +150,28 @@ class Continuum:
 
 @dataclasses.dataclass
 class CRSpecies:
-    """Collisional-radiative data of one atom (Sec. 2.1 CR model): levels
-    0..n_model-1 of its level table are solved for, the levels above stay in
-    Boltzmann ratio (at T_v) with level n_model-1.  Rate coefficients are
-    Arrhenius triples (C in cm^3 mol^-1 s^-1 K^-n, n, E_a in K) of the
-    forward processes:
-      (ion < 0: the ion density is taken as 0)
+    """Collisional-radiative data of one atom or diatomic molecule (Sec. 2.1
+    CR model).  The states are the atom's table levels or the molecule's
+    electronic states (energies E: level energies, electronic terms T_e);
+    states 0..n_model-1 are solved for, the states above stay in Boltzmann
+    ratio with state n_model-1.  Rate coefficients are Arrhenius triples
+    (C in cm^3 mol^-1 s^-1 K^-n, n, E_a in K) of the forward processes:
       hpie[lo, hi], eie[lo, hi]: heavy-particle / electron impact excitation
         lo -> hi (lo < hi; other entries unused);
       A[hi, lo]: spontaneous emission hi -> lo, s^-1 (lo < hi);
+    atoms only (ion < 0: the ion density is taken as 0):
       eii[i]: electron impact ionization of level i into the ion `ion`;
       ce[i]: charge exchange  atom(i) + partner_ion -> ion + partner
-        (partner < 0: none).
+        (partner < 0: none);
+    molecules only (diss_x < 0: none):
+      hpid[i], eid[i]: heavy-particle / electron impact dissociation of
+        state i into diss_x + diss_y, whose partition functions are the
+        level sums of an atom, else the constants Q_x, Q_y; E_diss (cm^-1):
+        energy of the separated products above the molecule's energy zero.
     Reverse rates follow from detailed balance.  texp[2m], texp[2m+1]: the
-    forward and backward rates of mechanism m (HPIE, EIE, EII, CE) are
-    taken at T = T_tr^a T_v^(1-a) with a the entry.  Transitions above
-    nu_cut (cm^-1, i.e. below 200 nm) are optically thick (no net
+    forward and backward rates of mechanism m (HPIE, EIE, EII, CE, HPID,
+    EID) are taken at T = T_tr^a T_v^(1-a) with a the entry.  Transitions
+    above nu_cut (cm^-1, i.e. below 200 nm) are optically thick (no net
     radiative rate)."""
     species: int
     ion: int
@@ -183,11 +189,18 @@ class CRSpecies:
     ce: np.ndarray
     texp: np.ndarray
     nu_cut: float = 50000.0
+    diss_x: int = -1
+    diss_y: int = -1
+    Q_x: float = 0.0
+    Q_y: float = 0.0
+    E_diss: float = 0.0
+    hpid: Optional[np.ndarray] = None
+    eid: Optional[np.ndarray] = None
 
 
 @dataclasses.dataclass
 class CRModel:
-    """QSS collisional-radiative populations for some atoms; collider_w[s]
+    """QSS collisional-radiative populations for some atoms and molecules; collider_w[s]
     is the weight of species s among the heavy collision partners M (0 for
     electrons)."""
     species: List[CRSpecies]
@@ -285,7 +298,14 @@ def _arrhenius_triples(rng, n, k_lo, k_hi, n_lo, n_hi, Ea):
     return np.stack([k * AVOGADRO * 1e4 ** (-ex), ex, np.asarray(Ea, np.float64)], axis=-1)
 
 
-def air_cr(species: List[Species], n_model: int = 18, seed: int = 11863) -> CRModel:
+# Dissociation energies D0 (cm^-1, from v = 0 of the ground state) of the
+# synthetic diatomics: the textbook values of N2, O2, NO and N2+.
+DISS_D0_CM = {"N2": 78714.0, "O2": 41260.0, "NO": 52400.0, "N2+": 70300.0}
+DISS_PRODUCTS = {"N2": ("N", "N"), "O2": ("O", "O"), "NO": ("N", "O"), "N2+": ("N", "N+")}
+
+
+def air_cr(species: List[Species], n_model: int = 18, seed: int = 11863,
+           molecules: bool = True) -> CRModel:
     """Synthetic QSS-CR data for the atoms N and O of a species list (the
     paper's rate mechanism is not available); an atom whose ion is not in the
     list gets ion = -1 (no recombination source) and no charge exchange.  Per
@@ -298,7 +318,15 @@ def air_cr(species: List[Species], n_model: int = 18, seed: int = 11863) -> CRMo
     and O(i) + N+ <-> O+ + N) k ~ logU(1e-12, 1e-10), n ~ U(0, 0.5),
     E_a = c2 max(E_ion - E_i - E_ion', 0).  Temperatures: HPIE forward at
     sqrt(T_tr T_v), backward at T_tr; EIE and EII at T_v (= T_e); CE at T_tr.
-    Heavy colliders: every species but e-, weight 1."""
+    With molecules, every electronic state of N2, O2, NO and N2+ (seed + 1):
+    HPIE and EIE between states as above with dE the term difference, the
+    band's A ~ logU(1e5, 1e8) s^-1, and per state dissociation into the
+    products of DISS_PRODUCTS (N+ with its ground-term degeneracy as partition
+    function): HPID C ~ logU(1e21, 1e22), n = -1.6, EID C ~ logU(1e23, 1e25),
+    n = -1.6, both with E_a = c2 (E_diss - T_e - G_e(0)) and E_diss = D0 +
+    G_X(0) (the energy zero of the molecule's partition function is the
+    bottom of the X well); HPID forward at sqrt(T_tr T_v), backward at T_tr,
+    EID at T_v.  Heavy colliders: every species but e-, weight 1."""
     rng = np.random.Generator(np.random.PCG64(seed))
     names = [sp.name for sp in species]
     recs = []
@@ -330,18 +358,53 @@ def air_cr(species: List[Species], n_model: int = 18, seed: int = 11863) -> CRMo
             partner, partner_ion, pE, pQ = -1, -1, 0.0, 1.0
         recs.append(CRSpecies(names.index(a), ion_of(a), partner, partner_ion, L,
                               Ei, ION_Q[a + "+"], pE, pQ, hpie, eie, A, eii, ce,
-                              np.array([0.5, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 1.0])))
+                              np.array([0.5, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 1.0,
+                                        0.5, 1.0, 0.0, 0.0])))
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    for m in (("N2", "O2", "NO", "N2+") if molecules else ()):
+        px, py = DISS_PRODUCTS[m]
+        if m not in names or px not in names or py not in names:
+            continue
+        sp = species[names.index(m)]
+        if sp.kind != KIND_MOLECULE:
+            continue
+        L = min(n_model, sp.el_T.size)
+        T = sp.el_T[:L]
+        dE = C2_CM_K * np.maximum(T[None, :] - T[:, None], 0.0)
+        hpie = _arrhenius_triples(rng, L * L, 1e-14, 1e-11, 0.0, 1.0, dE.ravel()).reshape(L, L, 3)
+        eie = _arrhenius_triples(rng, L * L, 1e-10, 1e-7, -0.5, 0.5, dE.ravel()).reshape(L, L, 3)
+        A = np.zeros((L, L))
+        for hi in range(1, L):
+            for lo in range(hi):
+                A[hi, lo] = _log_uniform(rng, 1e5, 1e8, 1)[0]
+        off = np.concatenate([[0], np.cumsum(sp.el_nv)])
+        G0 = np.array([sp.vib_G[off[e]] for e in range(sp.el_T.size)])
+        E_diss = DISS_D0_CM[m] + G0[0]
+        D = C2_CM_K * np.maximum(E_diss - T - G0[:L], 0.0)
+        hpid = np.stack([_log_uniform(rng, 1e21, 1e22, L), np.full(L, -1.6), D], axis=-1)
+        eid = np.stack([_log_uniform(rng, 1e23, 1e25, L), np.full(L, -1.6), D], axis=-1)
+        qc = lambda p: ION_Q.get(p, 1.0) if species[names.index(p)].kind != KIND_ATOM else 0.0
+        recs.append(CRSpecies(names.index(m), -1, -1, -1, L, 0.0, 0.0, 0.0, 0.0, hpie, eie, A,
+                              np.zeros((L, 3)), np.zeros((L, 3)),
+                              np.array([0.5, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0,
+                                        0.5, 1.0, 0.0, 0.0]),
+                              diss_x=names.index(px), diss_y=names.index(py), Q_x=qc(px),
+                              Q_y=qc(py), E_diss=E_diss, hpid=hpid, eid=eid))
     w = np.array([0.0 if n == "e-" else 1.0 for n in names])
     return CRModel(recs, w)
 
 
 def tie_lines_to_levels(lines: Lines, species: List[Species], cr: CRModel) -> np.ndarray:
     """(upper, lower) level of every line of a CR atom: the level of its
-    atom nearest in energy to E_u and to E_l (ties: the lower level); -1 for
-    the lines of every other species.  [n_lines, 2] int32."""
+    atom nearest in energy to E_u and to E_l (ties: the lower level); the
+    electronic states (1, 0) of the band system for the lines of a CR
+    molecule; -1 for the lines of every other species.  [n_lines, 2] int32."""
     out = np.full((lines.n, 2), -1, np.int32)
     for rec in cr.species:
         sel = np.nonzero(lines.species == rec.species)[0]
+        if species[rec.species].kind == KIND_MOLECULE:
+            out[sel] = (1, 0)   # the band system: upper electronic state 1, lower 0
+            continue
         E = species[rec.species].level_E
         for col, Ev in ((0, lines.Eu_ev[sel]), (1, lines.El_ev[sel])):
             out[sel, col] = np.argmin(np.abs(Ev[:, None] - E[None, :]), axis=1)
@@ -356,7 +419,8 @@ def lines_on_levels(lines: Lines, species: List[Species], cr: CRModel, grid: Gri
     (d ~ U(-offset, offset) cm^-1, a seeded fine-structure spread), nu0 their
     difference and the levels' degeneracies.  A line whose nearest pair is
     not upper above lower, or whose new centre leaves the grid, keeps its
-    drawn values and no levels.  (A line far from the levels it is tied to
+    drawn values and no levels.  The rovibronic lines of a CR molecule keep
+    their values and take the electronic states (1, 0) of their band system.  (A line far from the levels it is tied to
     would take its Boltzmann share of each level at T_v, so that in the
     cold-T_v cells behind the shock a line whose nu0 falls short of the gap
     between its levels reads an inversion of order e^{c2 (gap - nu0)/T_v}
@@ -367,6 +431,9 @@ def lines_on_levels(lines: Lines, species: List[Species], cr: CRModel, grid: Gri
     lev = np.full((lines.n, 2), -1, np.int32)
     for rec in cr.species:
         sel = np.nonzero(lines.species == rec.species)[0]
+        if species[rec.species].kind == KIND_MOLECULE:
+            lev[sel] = (1, 0)   # rovibronic lines of the band system 1 -> 0
+            continue
         E, g = species[rec.species].level_E, species[rec.species].level_g
         u = np.argmin(np.abs(lines.Eu_ev[sel][:, None] - E[None, :]), axis=1)
         l = np.argmin(np.abs(lines.El_ev[sel][:, None] - E[None, :]), axis=1)

@@ -70,36 +70,75 @@ def air_species(seed=5):
     return synth._air_species(rng, 8)
 
 
+def q_mol_state(sp, e, Tv, Ttr):
+    """Electronic state e of a synthetic diatomic: g_e e^{-c2 T_e/T_v} times
+    its vibrational (T_v) and rotational (T_tr) sums."""
+    off = np.concatenate([[0], np.cumsum(sp.el_nv)])
+    J = np.arange(int(sp.el_Jmax[e]) + 1, dtype=float)
+    jj = J * (J + 1.0)
+    q = 0.0
+    for v in range(off[e], off[e + 1]):
+        F = sp.vib_B[v] * jj - sp.vib_D[v] * jj * jj
+        q += math.exp(-C2 * sp.vib_G[v] / Tv) * float(np.sum((2 * J + 1) * np.exp(-C2 * F / Ttr)))
+    return sp.el_g[e] * math.exp(-C2 * sp.el_T[e] / Tv) * q
+
+
+def q_species(sp, T):
+    if sp.kind == synth.KIND_ATOM:
+        return sum(q_state(E, g, T) for E, g in zip(sp.level_E, sp.level_g))
+    return sum(q_mol_state(sp, e, T, T) for e in range(len(sp.el_T)))
+
+
 def saha_cell(species, T, N_atom, n_e):
-    """Cell densities with N+ and O+ at their Saha densities for N, O at T."""
+    """Cell densities at equilibrium at T: N and O at N_atom, N+ and O+ at
+    their Saha densities, and N2, O2, NO, N2+ at dissociation equilibrium
+    with their products (N_mol = N_X N_Y Q_mol / (Q_X Q_Y)
+    (h^2 / (2 pi mu k T))^{3/2} e^{c2 E_diss / T}, N+ with Q = 9, E_diss from
+    the CR records)."""
     names = [s.name for s in species]
     N = np.zeros(len(species))
     for a, Ei, Qi in (("N", 117225.7, 9.0), ("O", 109837.02, 4.0)):
         sp = species[names.index(a)]
-        Qa = sum(q_state(E, g, T) for E, g in zip(sp.level_E, sp.level_g))
+        Qa = q_species(sp, T)
         N[names.index(a)] = N_atom
         N[names.index(a + "+")] = N_atom * Qi * math.exp(-C2 * Ei / T) * q_electron(T) / (Qa * n_e)
-    N[names.index("N2")] = 3e16
+    for rec in synth.air_cr(species).species:
+        if rec.diss_x < 0:
+            continue
+        qx = q_species(species[rec.diss_x], T) if species[rec.diss_x].kind == synth.KIND_ATOM else rec.Q_x
+        qy = q_species(species[rec.diss_y], T) if species[rec.diss_y].kind == synth.KIND_ATOM else rec.Q_y
+        mx, my = species[rec.diss_x].mass, species[rec.diss_y].mass
+        mu = mx * my / (mx + my) / NA
+        V = (H * H / (2 * math.pi * mu * KB * T)) ** 1.5
+        N[rec.species] = (N[rec.diss_x] * N[rec.diss_y] * q_species(species[rec.species], T) / (qx * qy)
+                          * V * math.exp(C2 * rec.E_diss / T))
     N[names.index("e-")] = n_e
     return N
 
 
 def test_detailed_balance_gives_boltzmann_saha():
     """Every rate at one temperature, radiation optically thick everywhere
-    (nu_cut = 0), ions at their Saha densities: the QSS solution is the
-    Boltzmann distribution N_i = N g_i e^{-c2 E_i/T} / Q for every level,
-    tail levels included.  Catches a wrong reverse-rate ratio, a transposed
-    R, a wrong ion or electron partition function or a wrong closure."""
+    (nu_cut = 0), ions at their Saha densities and molecules at dissociation
+    equilibrium with their products: the QSS solution is the Boltzmann
+    distribution N_i = N Q_i / Q for every state, tail states included
+    (atomic levels g e^{-c2 E/T}, molecular electronic states with their
+    rovibrational sums).  Catches a wrong reverse-rate ratio, a transposed
+    R, a wrong ion, electron, product or pair partition function, a wrong
+    dissociation energy sign or a wrong closure."""
     species = air_species()
     cr = synth.air_cr(species, n_model=14)
     T = 9000.0
     N = saha_cell(species, T, 1e16, 2e15)
+    assert any(r.diss_x >= 0 for r in cr.species)
     for rec in cr.species:
         rec = dataclasses.replace(rec, nu_cut=0.0)
         sp = species[rec.species]
         pop = O.cr_level_populations(rec, species, T, T, N, 2e15, cr.collider_w)
-        Q = sum(q_state(E, g, T) for E, g in zip(sp.level_E, sp.level_g))
-        want = np.array([1e16 * q_state(E, g, T) / Q for E, g in zip(sp.level_E, sp.level_g)])
+        Q = q_species(sp, T)
+        if sp.kind == synth.KIND_ATOM:
+            want = np.array([N[rec.species] * q_state(E, g, T) / Q for E, g in zip(sp.level_E, sp.level_g)])
+        else:
+            want = np.array([N[rec.species] * q_mol_state(sp, e, T, T) / Q for e in range(len(sp.el_T))])
         np.testing.assert_allclose(pop, want, rtol=1e-12, atol=0)
 
 
@@ -235,6 +274,108 @@ def test_two_level_charge_exchange():
     np.testing.assert_allclose(pop, [N0, (a * N0 + s) / d], rtol=1e-12)
 
 
+def test_two_state_molecule_dissociation():
+    """A diatomic's two electronic states with EIE and a band A between them,
+    and dissociation of state 1 into N + N by heavy-particle impact (forward
+    at sqrt(T_tr T_v), reverse at T_tr) and electron impact (at T_v), with
+    three-body recombination from detailed balance, k_b = k_f Q_1 / Q_N^2
+    (h^2 / (2 pi mu k T))^{3/2} e^{c2 E_diss / T}: row 1 reads
+    a N0 - d N1 + s = 0 with a = k01 n_e/N_A, d = (k10 n_e + k_H N_M +
+    k_E n_e)/N_A + A10 and s = (k_bH N_M + k_bE n_e) N_N^2 / N_A."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    mol = synth.molecule_species(rng, "N2", n_v=6, J_max=40)
+    atom = synth.atom_species(rng, "N")
+    species = [mol, atom, synth.none_species("e-")]
+    Te = float(mol.el_T[1])
+    eie = np.zeros((2, 2, 3))
+    eie[0, 1] = (2e15, 0.2, C2 * Te)
+    A = np.zeros((2, 2))
+    A[1, 0] = 4e5
+    E_diss = 80000.0
+    hpid = np.array([[0.0, 0.0, 0.0], [3e21, -1.6, C2 * (E_diss - Te)]])
+    eid = np.array([[0.0, 0.0, 0.0], [5e24, -1.6, C2 * (E_diss - Te)]])
+    rec = dataclasses.replace(record(0, 2, eie=eie, A=A,
+                                     texp=(0.5, 1.0, 0, 0, 0, 0, 1, 1, 0.5, 1.0, 0.0, 0.0),
+                                     nu_cut=1e6),
+                              diss_x=1, diss_y=1, E_diss=E_diss, hpid=hpid, eid=eid)
+    Ttr, Tv, ne = 16000.0, 9000.0, 4e14
+    N = np.array([2e16, 3e17, ne])
+    w = np.array([1.0, 1.0, 0.0])
+    NM = 3.2e17
+    mu = 14.0 * 14.0 / 28.0 / NA
+    Tf, Tb = math.sqrt(Ttr * Tv), Ttr
+    QN = lambda T: sum(q_state(E, g, T) for E, g in zip(atom.level_E, atom.level_g))
+    q1 = lambda T: q_mol_state(mol, 1, T, T)
+    q0 = lambda T: q_mol_state(mol, 0, T, T)
+    kb = lambda t, T: (arr(t, T) * q1(T) / QN(T) ** 2 * (H * H / (2 * math.pi * mu * KB * T)) ** 1.5
+                       * math.exp(C2 * E_diss / T))
+    k01 = arr(eie[0, 1], Tv)
+    k10 = arr(eie[0, 1], Tv) * q0(Tv) / q1(Tv)
+    a = k01 * ne / NA
+    d = (k10 * ne + arr(hpid[1], Tf) * NM + arr(eid[1], Tv) * ne) / NA + 4e5
+    src = (kb(hpid[1], Tb) * NM + kb(eid[1], Tv) * ne) * 3e17 ** 2 / NA
+    assert src > 1e-2 * a * 2e16   # recombination matters
+    N0 = (2e16 - src / d) / (1.0 + a / d)
+    pop = O.cr_level_populations(rec, species, Ttr, Tv, N, ne, w)
+    np.testing.assert_allclose(pop, [N0, (a * N0 + src) / d], rtol=1e-12)
+
+
+def small_molecule(n_el=3, n_v=3, J_max=12):
+    """A diatomic with n_el electronic states (terms 0, 30000, 45000, ...),
+    n_v anharmonic vibrational levels each and rigid rotors."""
+    T_e = np.array([0.0, 30000.0, 45000.0, 52000.0][:n_el])
+    G = []
+    for e in range(n_el):
+        om = 1500.0 + 200.0 * e
+        v = np.arange(n_v) + 0.5
+        G.append(om * v - om / 200.0 * v * v)
+    return synth.Species("N2", synth.KIND_MOLECULE, 28.0, el_T=T_e,
+                         el_g=np.array([1.0, 3.0, 2.0, 6.0][:n_el]),
+                         el_nv=np.full(n_el, n_v, np.int32), el_Jmax=np.full(n_el, J_max, np.int32),
+                         vib_G=np.concatenate(G), vib_B=np.repeat(np.linspace(1.6, 1.9, n_el), n_v),
+                         vib_D=np.zeros(n_el * n_v))
+
+
+def test_molecule_tail_at_two_temperatures():
+    """States above n_model stay in the two-temperature Boltzmann ratio with
+    state n_model-1: electronic and vibrational energies at T_v, rotational
+    at T_tr."""
+    mol = small_molecule(3)
+    species = [mol, synth.none_species("e-")]
+    eie = np.zeros((2, 2, 3))
+    eie[0, 1] = (1e16, 0.0, C2 * 30000.0)
+    rec = record(0, 2, eie=eie)
+    Ttr, Tv = 14000.0, 5000.0
+    pop = O.cr_level_populations(rec, species, Ttr, Tv, np.array([1e16, 1e15]), 1e15, np.array([1.0, 0.0]))
+    want = q_mol_state(mol, 2, Tv, Ttr) / q_mol_state(mol, 1, Tv, Ttr)
+    assert pop[2] / pop[1] == pytest.approx(want, rel=1e-13)
+    assert pop.sum() == pytest.approx(1e16, rel=1e-14)
+
+
+def test_molecule_line_shares_add_up_to_the_state():
+    """A rovibronic line takes its two-temperature Boltzmann share of its
+    electronic state: over every (v, J) level of the state the upper-level
+    populations of lines that start there add up to the state population."""
+    mol = small_molecule(2, n_v=3, J_max=12)
+    n_v, Jm = 3, 12
+    Eu_ev, Eu_rot, gu = [], [], []
+    for v in range(n_v):
+        for J in range(Jm + 1):
+            Eu_ev.append(mol.el_T[1] + mol.vib_G[n_v + v])
+            Eu_rot.append(mol.vib_B[n_v + v] * J * (J + 1.0))
+            gu.append(mol.el_g[1] * (2 * J + 1.0))
+    n = len(gu)
+    nu0 = np.linspace(20000.0, 20100.0, n)
+    lines = synth.Lines(nu0, np.full(n, 1e6), np.array(Eu_ev), np.array(Eu_rot), np.array(Eu_ev) - nu0,
+                        np.zeros(n), np.array(gu), np.ones(n), np.zeros(n, np.int32))
+    lev = np.tile(np.array([1, 0], np.int32), (n, 1))
+    grid = synth.Grid(19990.0, 20110.0, 121, 121)
+    Ttr, Tv, N1 = 16000.0, 6000.0, 3.7e12
+    tot = sum(O.line_pair([mol], lines, i, Ttr, Tv, 1e14, 1e16, 1.0, grid, line_levels=lev,
+                          N_lev_s=np.array([1e16, N1]))["Nu"] for i in range(n))
+    assert tot == pytest.approx(N1, rel=1e-13)
+
+
 def stagnation_cells():
     wl = synth.stagnation_line(n_cells=24, n_atomic=20, n_rovib=20, n_points=64)
     return wl.species, wl.cells
@@ -312,8 +453,8 @@ def test_line_source_function_at_excitation_temperature():
 
 def test_coefficients_reduce_to_boltzmann_at_equilibrium():
     """With the CR populations at their equilibrium (detailed-balance setup)
-    the line and continuum coefficients of the tied lines equal the
-    Boltzmann ones."""
+    the line and continuum coefficients of the tied lines, atomic and
+    rovibronic, equal the Boltzmann ones (T_tr = T_v)."""
     species = air_species(7)
     names = [s.name for s in species]
     T = 8500.0
@@ -323,11 +464,17 @@ def test_coefficients_reduce_to_boltzmann_at_equilibrium():
     cr = dataclasses.replace(cr, species=[dataclasses.replace(r, nu_cut=0.0) for r in cr.species])
     rng = np.random.Generator(np.random.PCG64(3))
     parts = [synth.atomic_lines(rng, names.index(a), 30, 20000.0, 30000.0) for a in ("N", "O")]
+    for m in ("N2", "NO"):
+        i = names.index(m)
+        parts.append(synth.rovib_lines(rng, species[i], i, 60, 5000.0, 65000.0))
     lines = synth.merge_sorted(parts)
+    assert np.any(lines.species == names.index("N2"))
     lev = synth.tie_lines_to_levels(lines, species, cr)
-    grid = synth.Grid(20000.0, 30000.0, 3001, 3001)
+    grid = synth.Grid(5000.0, 65000.0, 120001, 120001)
     e0, k0, _ = O.coeffs(species, lines, cells, grid)
     e1, k1, _ = O.coeffs(species, lines, cells, grid, cr=cr, line_levels=lev)
+    mol = np.isin(lines.species, [names.index("N2"), names.index("NO")])
+    assert np.all(lev[mol] == (1, 0))
     assert np.max(e0) > 0
     np.testing.assert_allclose(e1, e0, rtol=1e-11, atol=1e-12 * np.max(e0))
     np.testing.assert_allclose(k1, k0, rtol=1e-11, atol=1e-12 * np.max(np.abs(k0)))
