@@ -190,18 +190,24 @@ typedef struct {
  * range, E_ion, Q_ion or z <= 0, negative or non-finite sigma0). */
 lrt_status lrt_set_continuum(lrt_ctx *ctx, int n, const lrt_continuum *cont);
 
-/* Quasi-steady-state collisional-radiative (QSS-CR) data of one atom
- * (Sec. 2.1 CR model, master equation in QSS form, ground-state closure,
- * R n = b solved by LU).  With l = n_model, levels 0..l-1 of the atom's level
- * table are solved for in every cell; the levels above stay in Boltzmann
- * ratio g e^{-c2 E/T_v} with level l-1 (the closure row sums all of them to
- * the atom's density N).  Row i >= 1 balances level i: its losses by heavy-
- * particle (HPIE) and electron impact (EIE) transitions to every other solved
- * level, spontaneous emission to lower levels, electron impact ionization
- * (EII) and charge exchange (CE) with the partner ion, against its gains by
- * the same transitions from the other levels and, as sources b, three-body
- * recombination of the ion and charge exchange of the ion with the partner
- * atom.  Two-body rates are k / N_A times the collider density (heavy
+/* Quasi-steady-state collisional-radiative (QSS-CR) data of one atom or
+ * diatomic molecule (Sec. 2.1 CR model, master equation in QSS form,
+ * ground-state closure, R n = b solved by LU).  The states are the atom's
+ * table levels (energies E_i, degeneracies g_i) or the molecule's electronic
+ * states (terms T_e, with their vibrational and rotational ladders).  With
+ * l = n_model, states 0..l-1 are solved for in every cell; the states above
+ * stay in Boltzmann ratio with state l-1 at (T_v, T_tr) (the closure row sums
+ * all of them to the species' density N).  Row i >= 1 balances state i: its
+ * losses by heavy-particle (HPIE) and electron impact (EIE) transitions to
+ * every other solved state, spontaneous emission to lower states, and
+ *   atoms: electron impact ionization (EII) and charge exchange (CE) with the
+ *   partner ion;
+ *   molecules: heavy-particle (HPID) and electron impact (EID) dissociation
+ *   into diss_x + diss_y;
+ * against its gains by the same transitions from the other states and, as
+ * sources b, three-body recombination of the ion, charge exchange of the ion
+ * with the partner atom, or three-body recombination of the dissociation
+ * products.  Two-body rates are k / N_A times the collider density (heavy
  * colliders: sum over species of collider_w[s] N_s; electrons: n_e).
  * Forward rate coefficients are Arrhenius triples (C, n, E_a): k = C T^n
  * e^{-E_a/T} (cm^3 mol^-1 s^-1, E_a in K); reverse rates follow detailed
@@ -209,59 +215,75 @@ lrt_status lrt_set_continuum(lrt_ctx *ctx, int n, const lrt_continuum *cont);
  *   de-excitation hi -> lo:  [k(lo -> hi) Q_lo / Q_hi]_{T_b},
  *   recombination into i:    [k_EII(i) Q_i / (Q_ion e^{-c2 E_ion/T} Q_e)]_{T_b},
  *   CE into i:               [k_CE(i) Q_i Q_B+ / (Q_A+ Q_B)]_{T_b},
- * with Q_i = g_i e^{-c2 E_i/T}, Q_A+ = Q_ion e^{-c2 E_ion/T}, Q_B+ likewise
- * for the partner, Q_B the partner's full partition function and Q_e =
- * 2 (2 pi m_e k T / h^2)^{3/2}.  Rates of mechanism m (0 HPIE, 1 EIE, 2 EII,
- * 3 CE) are taken at T = T_tr^a T_v^(1-a) with a = texp[2m] (forward) and
+ *   X + Y into i:            [k_D(i) Q_i / (Q_X Q_Y)]_{T_b} (h^2/(2 pi mu k T_b))^{3/2}
+ *                            e^{c2 E_diss / T_b},
+ * with Q_i = g_i e^{-c2 E_i/T} for an atomic level and g_e e^{-c2 T_e/T}
+ * Q_vr,e(T) for a molecular state (every mode at T), Q_A+ = Q_ion
+ * e^{-c2 E_ion/T}, Q_B+ likewise for the partner, Q_B the partner's full
+ * partition function, Q_e = 2 (2 pi m_e k T / h^2)^{3/2}, Q_X and Q_Y the
+ * level sums of atomic products (else the constants Q_x, Q_y), mu the pair's
+ * reduced mass.  Rates of mechanism m (0 HPIE, 1 EIE, 2 EII, 3 CE, 4 HPID,
+ * 5 EID) are taken at T = T_tr^a T_v^(1-a) with a = texp[2m] (forward) and
  * texp[2m+1] (backward).  The escape factor is 0 (optically thick) for
- * transitions above nu_cut cm^-1, 1 below; absorption of radiation is left
- * out.  The populations replace the Boltzmann ones for the lines given
- * levels by lrt_set_line_levels and for the atom's bound-free absorption.
+ * transitions above nu_cut cm^-1 (state energy difference), 1 below;
+ * absorption of radiation is left out.  The populations replace the
+ * Boltzmann ones for the lines given states by lrt_set_line_levels and for
+ * an atom's bound-free absorption.  T_v and T_tr must keep every partition
+ * function and e^{c2 E_diss/T} representable (T above a few hundred K).
  * Rate tables are host arrays (copied), row-major: */
 typedef struct {
-    int32_t species;        /* the atom (LRT_KIND_ATOM, at most 64 levels) */
-    int32_t ion;            /* species of its singly charged ion, or -1 (ion density 0) */
-    int32_t partner;        /* charge-exchange partner atom, or -1 (no charge exchange) */
+    int32_t species;        /* the atom or molecule (at most 64 levels / electronic states) */
+    int32_t ion;            /* atom: species of its singly charged ion, or -1 (ion density 0); molecule: -1 */
+    int32_t partner;        /* atom: charge-exchange partner atom, or -1; molecule: -1 */
     int32_t partner_ion;    /* the partner's ion (with a partner) */
-    int32_t n_model;        /* l: 2 <= l <= the atom's level count */
-    double E_ion, Q_ion;    /* ionization energy (cm^-1) and partition function of the ion */
+    int32_t n_model;        /* l: 2 <= l <= the species' state count */
+    int32_t diss_x, diss_y; /* molecule: dissociation products (species), or -1, -1 (none) */
+    double E_ion, Q_ion;    /* atom: ionization energy (cm^-1) and partition function of the ion */
     double partner_E_ion, partner_Q_ion;
+    double Q_x, Q_y;        /* partition function of a product that is not an atom (> 0) */
+    double E_diss;          /* cm^-1: products above the molecule's energy zero */
     double nu_cut;          /* optically thick above, cm^-1 (5e4: 200 nm) */
-    double texp[8];         /* temperature exponents, each in [0, 1] */
+    double texp[12];        /* temperature exponents, each in [0, 1] */
     const double *hpie;     /* [l][l][3]: HPIE lo -> hi at [lo][hi] (lo < hi; rest ignored) */
     const double *eie;      /* [l][l][3]: EIE likewise */
     const double *A;        /* [l][l]: spontaneous emission hi -> lo at [hi][lo], s^-1 */
-    const double *eii;      /* [l][3]: EII of each level (row 0 unused) */
-    const double *ce;       /* [l][3]: CE of each level (ignored without a partner) */
-} lrt_cr_atom;
+    const double *eii;      /* [l][3]: atom: EII of each level (row 0 unused) */
+    const double *ce;       /* [l][3]: atom: CE of each level (ignored without a partner) */
+    const double *hpid;     /* [l][3]: molecule: HPID of each state (row 0 unused) */
+    const double *eid;      /* [l][3]: molecule: EID of each state (row 0 unused) */
+} lrt_cr_species;
 
-/* Set (n > 0) or clear (n = 0) the QSS-CR atoms, at most one record per atom;
- * collider_w (host, [n_species]) weights the species as heavy colliders (0
- * for electrons).  Copied; kept until changed; new species clear it.  The
- * populations are recomputed with the other per-cell quantities.  Errors:
- * LRT_E_STATE (no species), LRT_E_ARG (species not an atom or with more than
- * 64 levels, index out of range, duplicate atom, l out of range, E_ion or
- * Q_ion <= 0, texp outside [0, 1], negative or non-finite rate data or
- * collider weight, NULL table). */
-lrt_status lrt_set_cr(lrt_ctx *ctx, int n, const lrt_cr_atom *atoms, const double *collider_w);
+/* Set (n > 0) or clear (n = 0) the QSS-CR species, at most one record per
+ * species; collider_w (host, [n_species]) weights the species as heavy
+ * colliders (0 for electrons).  Copied; kept until changed; new species clear
+ * it.  The populations are recomputed with the other per-cell quantities.
+ * Errors: LRT_E_STATE (no species), LRT_E_ARG (species neither atom nor
+ * molecule or with more than 64 states, index out of range, duplicate
+ * species, l out of range, an atom's E_ion or Q_ion <= 0, ionization or
+ * charge exchange given to a molecule, dissociation given to an atom, a
+ * non-atomic product without Q > 0, texp outside [0, 1], negative or
+ * non-finite rate data or collider weight, NULL table). */
+lrt_status lrt_set_cr(lrt_ctx *ctx, int n, const lrt_cr_species *sp, const double *collider_w);
 
-/* Upper and lower level of every line (host, [n_lines] each, in the order the
- * lines were given to lrt_set_lines) in its atom's level table, or -1 for
- * both: such a line keeps Boltzmann populations, as does every line of an
- * atom without QSS-CR data.  A line with levels takes N_u = N_CR(u) times its
- * Boltzmann share g e^{-c2 E/T_v} of the table level (1 when its E and g are
- * the level's), likewise N_l, and kappa from N_l g_u/g_l - N_u.  Both NULL:
- * clear.  Copied; new lines clear it.  Errors: LRT_E_STATE (no lines),
- * LRT_E_ARG (n != n_lines, one of the two levels -1, a level outside its
- * atom's table, levels given to a line of a molecule). */
+/* Upper and lower state of every line (host, [n_lines] each, in the order the
+ * lines were given to lrt_set_lines): a level of its atom's table, or an
+ * electronic state of its molecule; -1 for both: such a line keeps Boltzmann
+ * populations, as does every line of a species without QSS-CR data.  A line
+ * with states takes N_u = N_CR(u) times its Boltzmann share of that state
+ * (an atom's line g e^{-c2 (E - E_u)/T_v} g_u^-1, 1 when its E and g are the
+ * level's; a molecule's rovibronic level g e^{-c2 E_ev/T_v - c2 E_rot/T_tr}
+ * / Q_u(T_v, T_tr)), likewise N_l, and kappa from N_l g_u/g_l - N_u.  Both
+ * NULL: clear.  Copied; new lines clear it.  Errors: LRT_E_STATE (no lines),
+ * LRT_E_ARG (n != n_lines, one of the two states -1, a state outside its
+ * species' table). */
 lrt_status lrt_set_line_levels(lrt_ctx *ctx, const int32_t *lev_u, const int32_t *lev_l, int64_t n);
 
-/* The QSS-CR level populations (cm^-3) of record `atom` (as given to
- * lrt_set_cr) in every cell: pop (host, [n_cells][levels of the atom]).
+/* The QSS-CR state populations (cm^-3) of record `rec` (as given to
+ * lrt_set_cr) in every cell: pop (host, [n_cells][states of the species]).
  * Computes the per-cell quantities if they are not current.  A cell without
- * the atom has all zero; a singular system gives NaN.  Synchronises the
+ * the species has all zero; a singular system gives NaN.  Synchronises the
  * stream.  Errors: LRT_E_STATE (no QSS-CR data, cells missing), LRT_E_ARG. */
-lrt_status lrt_cr_populations(lrt_ctx *ctx, int atom, double *pop, void *stream);
+lrt_status lrt_cr_populations(lrt_ctx *ctx, int rec, double *pop, void *stream);
 
 /* Rays of a 1-D slab seen from the wall (Sec. 2.2.3 with a tangent-slab
  * geometry): cells 0..n_cells-1 ordered from the far (free) boundary to the

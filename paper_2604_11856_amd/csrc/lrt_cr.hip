@@ -1,7 +1,9 @@
 // gfx950 kernel of the quasi-steady-state collisional-radiative populations
-// (arXiv 2604.11856, Sec. 2.1 CR model): one wave per (cell, atom) assembles
-// the l x l system R n = b of the QSS balance with the ground-state closure in
-// LDS, one lane per row, and solves it by LU with partial pivoting.  The
+// (arXiv 2604.11856, Sec. 2.1 CR model): one wave per (cell, species)
+// assembles the l x l system R n = b of the QSS balance with the ground-state
+// closure in LDS, one lane per row, and solves it by LU with partial
+// pivoting.  The states are an atom's table levels or a diatomic molecule's
+// electronic states.  The
 // matrix is small (l <= 64) and every system is independent, so the work is a
 // batch of wave-sized dense solves, bound by VALU latency and LDS traffic, not
 // a contraction for the matrix cores.  Everything is FP64.
@@ -41,6 +43,43 @@ __device__ __forceinline__ double k_exc(const double *tab, int L, int i, int j, 
     return arrhenius(tab + 3 * (j * L + i), Tb) * Qb[j] / Qb[i];
 }
 
+// Sum over the wave of one value per lane, in a fixed order; every lane
+// receives the sum.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Partition function of electronic state e of a molecule at (Tv, Tr):
+// g_e e^{-c2 T_e/Tv} sum_v e^{-c2 G_v/Tv} sum_J (2J+1) e^{-c2 F_v(J)/Tr},
+// F = B J(J+1) - D J^2 (J+1)^2, the (v, J) terms spread over the lanes.
+// Called by the whole wave; every lane receives the value.
+__device__ double mol_state_q(const DevSpecies &sp, int64_t e, double Tv, double Tr, int lane)
+{
+    const int64_t v0 = sp.vib_off[e], nv = sp.vib_off[e + 1] - v0;
+    const int nJ = sp.el_Jmax[e] + 1;
+    double acc = 0.0;
+    for (int64_t t = lane; t < nv * nJ; t += 64) {
+        const int64_t v = v0 + t / nJ;
+        const double J = (double)(t % nJ), jj = J * (J + 1.0);
+        const double F = sp.vib_B[v] * jj - sp.vib_D[v] * jj * jj;
+        acc += exp(-kC2 * sp.vib_G[v] / Tv) * ((2.0 * J + 1.0) * exp(-kC2 * F / Tr));
+    }
+    return sp.el_g[e] * exp(-kC2 * sp.el_T[e] / Tv) * wave_sum(acc);
+}
+
+// Partition function of a dissociation product at T: an atom's level sum,
+// else the given constant.
+__device__ __forceinline__ double product_q(const DevSpecies &sp, int64_t lev0, int32_t n_lev, double Qc,
+                                            double T)
+{
+    if (n_lev == 0) return Qc;
+    double q = 0.0;
+    for (int32_t k = 0; k < n_lev; ++k) q += sp.lev_g[lev0 + k] * exp(-kC2 * sp.lev_E[lev0 + k] / T);
+    return q;
+}
+
 // LDS row stride of the augmented matrix [R | b] (L + 1 columns): odd, so the
 // lanes of a column walk hit distinct banks.
 __host__ __device__ constexpr int row_stride(int L) { return (L + 1) | 1; }
@@ -54,11 +93,15 @@ __global__ __launch_bounds__(64) void cr_kernel(DevSpecies sp, DevCells cells, D
     const CRRec R = cr.rec[r];
     const int L = R.n_model, NL = R.n_lev, S = cells.n_species;
     const int ld = row_stride(L);
+    const bool mol = R.kind == 2;
     double *M = lds;                 // [L][ld]: R, then b in column L
     double *QH = M + L * ld;         // [NL] state partition functions at the HPIE backward T
     double *QE = QH + NL;            // [NL] ... at the EIE backward T
-    double *Qv = QE + NL;            // [NL] ... at T_v (closure, Boltzmann tail)
-    double *xs = Qv + NL;            // [L] solution
+    double *Qv = QE + NL;            // [NL] ... at (T_v, T_tr) (closure, Boltzmann tail)
+    double *QDH = Qv + NL;           // [NL] ... at the HPID backward T (molecules)
+    double *QDE = QDH + NL;          // [NL] ... at the EID backward T (molecules)
+    double *sE = QDE + NL;           // [NL] state energies: level energies or electronic terms
+    double *xs = sE + NL;            // [L] solution
 
     const double Ttr = cells.T_tr[c], Tv = cells.T_v[c], ne = cells.n_e[c];
     const double *Nc = cells.N + (int64_t)c * S;
@@ -76,15 +119,38 @@ __global__ __launch_bounds__(64) void cr_kernel(DevSpecies sp, DevCells cells, D
     double NM = 0.0;   // heavy colliders
     for (int s = 0; s < S; ++s) NM += cr.collider_w[s] * Nc[s];
     const double Nion = R.ion >= 0 ? Nc[R.ion] : 0.0;
-    double Tm[8];
+    double Tm[12];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) Tm[k] = rate_temperature(R.texp[k], Ttr, Tv);
+    for (int k = 0; k < 12; ++k) Tm[k] = rate_temperature(R.texp[k], Ttr, Tv);
     const double *lE = sp.lev_E + R.lev0, *lg = sp.lev_g + R.lev0;
 
-    for (int j = lane; j < NL; j += 64) {
-        QH[j] = lg[j] * exp(-kC2 * lE[j] / Tm[1]);
-        QE[j] = lg[j] * exp(-kC2 * lE[j] / Tm[3]);
-        Qv[j] = lg[j] * exp(-kC2 * lE[j] / Tv);
+    if (!mol) {
+        for (int j = lane; j < NL; j += 64) {
+            QH[j] = lg[j] * exp(-kC2 * lE[j] / Tm[1]);
+            QE[j] = lg[j] * exp(-kC2 * lE[j] / Tm[3]);
+            Qv[j] = lg[j] * exp(-kC2 * lE[j] / Tv);
+            sE[j] = lE[j];
+        }
+    } else {
+        for (int j = 0; j < NL; ++j) {   // wave-uniform: the (v, J) sums use every lane
+            const int64_t e = R.e0 + j;
+            const double qh = mol_state_q(sp, e, Tm[1], Tm[1], lane);
+            const double qe = mol_state_q(sp, e, Tm[3], Tm[3], lane);
+            const double qv = mol_state_q(sp, e, Tv, Ttr, lane);
+            double qdh = 0.0, qde = 0.0;
+            if (R.diss_x >= 0) {
+                qdh = mol_state_q(sp, e, Tm[9], Tm[9], lane);
+                qde = mol_state_q(sp, e, Tm[11], Tm[11], lane);
+            }
+            if (lane == 0) {
+                QH[j] = qh;
+                QE[j] = qe;
+                Qv[j] = qv;
+                QDH[j] = qdh;
+                QDE[j] = qde;
+                sE[j] = sp.el_T[e];
+            }
+        }
     }
     __syncthreads();
 
@@ -107,10 +173,14 @@ __global__ __launch_bounds__(64) void cr_kernel(DevSpecies sp, DevCells cells, D
     if (i >= 1 && i < L) {
         for (int m = 0; m < L; ++m)
             if (m != i) loss += M[m * ld + i];
-        // spontaneous emission to lower levels, escape factor 0 above nu_cut
-        for (int m = 0; m < i; ++m) loss += (lE[i] - lE[m] > R.nu_cut ? 0.0 : 1.0) * R.A[i * L + m];
-        loss += arrhenius(R.eii + 3 * i, Tm[4]) / kAvogadro * ne;
-        if (R.partner >= 0) loss += arrhenius(R.ce + 3 * i, Tm[6]) / kAvogadro * Nc[R.partner_ion];
+        // spontaneous emission to lower states, escape factor 0 above nu_cut
+        for (int m = 0; m < i; ++m) loss += (sE[i] - sE[m] > R.nu_cut ? 0.0 : 1.0) * R.A[i * L + m];
+        if (!mol) {
+            loss += arrhenius(R.eii + 3 * i, Tm[4]) / kAvogadro * ne;
+            if (R.partner >= 0) loss += arrhenius(R.ce + 3 * i, Tm[6]) / kAvogadro * Nc[R.partner_ion];
+        } else if (R.diss_x >= 0) {
+            loss += arrhenius(R.hpid + 3 * i, Tm[8]) / kAvogadro * NM + arrhenius(R.eid + 3 * i, Tm[10]) / kAvogadro * ne;
+        }
     }
     __syncthreads();
     if (i == 0) {
@@ -125,7 +195,28 @@ __global__ __launch_bounds__(64) void cr_kernel(DevSpecies sp, DevCells cells, D
     } else if (i < L) {
         double *row = M + i * ld;
         row[i] = -loss;
-        for (int j = i + 1; j < L; ++j) row[j] += (lE[j] - lE[i] > R.nu_cut ? 0.0 : 1.0) * R.A[j * L + i];
+        for (int j = i + 1; j < L; ++j) row[j] += (sE[j] - sE[i] > R.nu_cut ? 0.0 : 1.0) * R.A[j * L + i];
+        if (mol) {
+            // three-body recombination of the dissociation products into the
+            // state, k_b = [k_D Q_i / (Q_X Q_Y)]_{T_b} (h^2/(2 pi mu k T_b))^{3/2}
+            // e^{c2 E_diss / T_b}, by heavy particles and by electrons
+            double src = 0.0;
+            if (R.diss_x >= 0) {
+                const double NXY[2] = {NM, ne};
+                for (int d = 0; d < 2; ++d) {
+                    const double Tb = Tm[9 + 2 * d];
+                    const double *tab = d == 0 ? R.hpid : R.eid;
+                    const double Qi = d == 0 ? QDH[i] : QDE[i];
+                    const double Vmu = pow(kPlanck * kPlanck / (2.0 * kPi * R.mu * kBoltz * Tb), 1.5);
+                    const double kb = arrhenius(tab + 3 * i, Tb) * Qi /
+                                      (product_q(sp, R.x_lev0, R.nx_lev, R.Q_x, Tb) *
+                                       product_q(sp, R.y_lev0, R.ny_lev, R.Q_y, Tb)) *
+                                      Vmu * exp(kC2 * R.E_diss / Tb);
+                    src += kb / kAvogadro * Nc[R.diss_x] * Nc[R.diss_y] * NXY[d];
+                }
+            }
+            row[L] = -src;
+        } else {
         // sources from outside the atom: three-body recombination of the ion,
         // k_rec = [k_EII Q_i / (Q_ion e^{-c2 E_ion/T} Q_e)]_{T_b}, Q_e the free
         // electron's 2 (2 pi m_e k T / h^2)^{3/2}; charge exchange of the ion with
@@ -146,6 +237,7 @@ __global__ __launch_bounds__(64) void cr_kernel(DevSpecies sp, DevCells cells, D
             src += kb / kAvogadro * Nion * Nc[R.partner];
         }
         row[L] = -src;
+        }
     }
     __syncthreads();
 
@@ -189,11 +281,13 @@ __global__ __launch_bounds__(64) void cr_kernel(DevSpecies sp, DevCells cells, D
     }
 
     // populations and their ln departures from the Boltzmann populations the
-    // line setup uses, ln(N/Q) + ln g - c2 E / T_v (-inf for a population <= 0)
+    // line setup uses: ln(N/Q) + ln g - c2 E / T_v for an atomic level,
+    // ln(N/Q) + ln Q_e(T_v, T_tr) for a molecular state (-inf for a
+    // population <= 0)
     const double bv = kC2 / Tv;
     for (int j = lane; j < NL; j += 64) {
         const double pj = j < L ? xs[j] : xs[L - 1] * Qv[j] / Qv[L - 1];
-        const double lnB = (q.lnNQ + log(lg[j])) - bv * lE[j];
+        const double lnB = mol ? q.lnNQ + log(Qv[j]) : (q.lnNQ + log(lg[j])) - bv * lE[j];
         cr.pop[orow + j] = pj;
         cr.lnd[orow + j] = pj > 0.0 ? log(pj) - lnB : (pj <= 0.0 ? -INFINITY : pj);
     }
@@ -205,7 +299,7 @@ hipError_t launch_cr(const DevSpecies &sp, const DevCells &cells, const DevCR &c
                      int32_t max_lev, const CellSpecies *cs, hipStream_t st)
 {
     if (cr.n < 1 || cells.n_cells < 1) return hipSuccess;
-    const size_t lds = ((size_t)max_l * row_stride(max_l) + 3 * (size_t)max_lev + max_l) * sizeof(double);
+    const size_t lds = ((size_t)max_l * row_stride(max_l) + 6 * (size_t)max_lev + max_l) * sizeof(double);
     hipLaunchKernelGGL(cr_kernel, dim3((unsigned)cells.n_cells * (unsigned)cr.n), dim3(64), lds, st, sp,
                        cells, cr, cs);
     return hipGetLastError();

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "../../include/lrt.h"
@@ -46,8 +47,8 @@ DevCR dev_cr(const lrt_ctx *c)
 
 // Pack the line levels into offsets of a cell's departure row:
 // (slot * LS + level) of the upper level in the low 16 bits, of the lower
-// level in the high 16 bits; -1 for a line without levels or whose atom has
-// no QSS-CR record.  Also list, per scale bin, the offsets of the levels its
+// level in the high 16 bits; -1 for a line without levels or whose species
+// has no QSS-CR record.  Also list, per scale bin, the offsets of the levels its
 // lines belong to (-1 for Boltzmann lines), so that the per-cell scale bound
 // takes each bin's own largest departure.
 lrt_status cr_build_line_levels(lrt_ctx *c)
@@ -91,7 +92,7 @@ lrt_status cr_build_line_levels(lrt_ctx *c)
     return LRT_OK;
 }
 
-// Populations of every (cell, atom), after the thermo kernel (they need its
+// Populations of every (cell, CR species), after the thermo kernel (they need its
 // ln(N/Q)).
 lrt_status cr_run(lrt_ctx *c, const DevCells &cells, hipStream_t st)
 {
@@ -113,78 +114,120 @@ lrt_status cr_run(lrt_ctx *c, const DevCells &cells, hipStream_t st)
 
 extern "C" {
 
-lrt_status lrt_set_cr(lrt_ctx *c, int n, const lrt_cr_atom *atoms, const double *collider_w)
+lrt_status lrt_set_cr(lrt_ctx *c, int n, const lrt_cr_species *recs, const double *collider_w)
 {
     if (!c) return LRT_E_ARG;
     c->err.clear();
-    if (c->n_species < 1) return fail(c, LRT_E_STATE, "set species before the QSS-CR atoms");
-    if (n < 0 || (n > 0 && (!atoms || !collider_w)))
-        return fail(c, LRT_E_ARG, "n must be >= 0, atoms and collider_w non-NULL");
+    if (c->n_species < 1) return fail(c, LRT_E_STATE, "set species before the QSS-CR species");
+    if (n < 0 || (n > 0 && (!recs || !collider_w)))
+        return fail(c, LRT_E_ARG, "n must be >= 0, records and collider_w non-NULL");
     const int S = c->n_species;
     if (n > 0 && !finite_nonneg(collider_w, S))
         return fail(c, LRT_E_ARG, "collider weights must be finite and >= 0");
     std::vector<int32_t> slot(S, -1), nlev(n);
     std::vector<CRRec> rec(n);
     std::vector<double> tab;
-    std::vector<size_t> off(n * 5);
+    constexpr int kTabs = 7;   // hpie, eie, A, eii, ce, hpid, eid
+    std::vector<size_t> off(n * kTabs);
     int LS = 0, max_l = 0;
     auto valid_sp = [&](int s) { return s >= 0 && s < S; };
+    auto n_levels = [&](int s) { return (int)(c->h_lev_off[s + 1] - c->h_lev_off[s]); };
     for (int q = 0; q < n; ++q) {
-        const lrt_cr_atom &x = atoms[q];
-        if (!valid_sp(x.species) || c->sp_kind[x.species] != LRT_KIND_ATOM)
-            return fail(c, LRT_E_ARG, "CR atom %d: species %d is not an atom", q, x.species);
-        if (slot[x.species] >= 0) return fail(c, LRT_E_ARG, "CR atom %d: species %d given twice", q, x.species);
-        const int NL = (int)(c->h_lev_off[x.species + 1] - c->h_lev_off[x.species]);
-        if (NL > kCRMaxLevels) return fail(c, LRT_E_ARG, "CR atom %d: more than %d levels", q, kCRMaxLevels);
+        const lrt_cr_species &x = recs[q];
+        if (!valid_sp(x.species) || (c->sp_kind[x.species] != LRT_KIND_ATOM && c->sp_kind[x.species] != LRT_KIND_MOLECULE))
+            return fail(c, LRT_E_ARG, "CR record %d: species %d is neither an atom nor a molecule", q, x.species);
+        if (slot[x.species] >= 0) return fail(c, LRT_E_ARG, "CR record %d: species %d given twice", q, x.species);
+        const bool mol = c->sp_kind[x.species] == LRT_KIND_MOLECULE;
+        const int NL = mol ? (int)(c->h_el_off[x.species + 1] - c->h_el_off[x.species]) : n_levels(x.species);
+        if (NL > kCRMaxLevels) return fail(c, LRT_E_ARG, "CR record %d: more than %d states", q, kCRMaxLevels);
         const int L = x.n_model;
-        if (L < 2 || L > NL) return fail(c, LRT_E_ARG, "CR atom %d: n_model %d outside [2, %d]", q, L, NL);
-        if (x.ion != -1 && !valid_sp(x.ion)) return fail(c, LRT_E_ARG, "CR atom %d: ion out of range", q);
-        if (x.partner != -1) {
-            if (!valid_sp(x.partner) || x.partner == x.species || c->sp_kind[x.partner] != LRT_KIND_ATOM)
-                return fail(c, LRT_E_ARG, "CR atom %d: partner must be another atom", q);
-            if (!valid_sp(x.partner_ion)) return fail(c, LRT_E_ARG, "CR atom %d: partner ion out of range", q);
-            if (x.ion < 0) return fail(c, LRT_E_ARG, "CR atom %d: charge exchange needs the atom's ion", q);
-            if (!(x.partner_E_ion > 0.0) || !(x.partner_Q_ion > 0.0) || !std::isfinite(x.partner_E_ion) ||
-                !std::isfinite(x.partner_Q_ion))
-                return fail(c, LRT_E_ARG, "CR atom %d: partner E_ion and Q_ion must be positive", q);
-        }
-        if (!(x.E_ion > 0.0) || !(x.Q_ion > 0.0) || !std::isfinite(x.E_ion) || !std::isfinite(x.Q_ion))
-            return fail(c, LRT_E_ARG, "CR atom %d: E_ion and Q_ion must be positive", q);
-        if (!(x.nu_cut >= 0.0) || std::isnan(x.nu_cut)) return fail(c, LRT_E_ARG, "CR atom %d: nu_cut must be >= 0", q);
-        for (int k = 0; k < 8; ++k)
+        if (L < 2 || L > NL) return fail(c, LRT_E_ARG, "CR record %d: n_model %d outside [2, %d]", q, L, NL);
+        if (!(x.nu_cut >= 0.0) || std::isnan(x.nu_cut)) return fail(c, LRT_E_ARG, "CR record %d: nu_cut must be >= 0", q);
+        for (int k = 0; k < 12; ++k)
             if (!(x.texp[k] >= 0.0 && x.texp[k] <= 1.0))
-                return fail(c, LRT_E_ARG, "CR atom %d: texp[%d] outside [0, 1]", q, k);
-        if (!x.hpie || !x.eie || !x.A || !x.eii || (x.partner >= 0 && !x.ce))
-            return fail(c, LRT_E_ARG, "CR atom %d: NULL rate table", q);
+                return fail(c, LRT_E_ARG, "CR record %d: texp[%d] outside [0, 1]", q, k);
+        if (!x.hpie || !x.eie || !x.A) return fail(c, LRT_E_ARG, "CR record %d: NULL rate table", q);
         const size_t LL = (size_t)L * L;
-        if (!triples_ok(x.hpie, LL) || !triples_ok(x.eie, LL) || !finite_nonneg(x.A, LL) ||
-            !triples_ok(x.eii, L) || (x.partner >= 0 && !triples_ok(x.ce, L)))
-            return fail(c, LRT_E_ARG, "CR atom %d: negative or non-finite rate data", q);
-        // tables concatenated: hpie, eie, A, eii, ce (zeros without a partner)
-        const double *src[5] = {x.hpie, x.eie, x.A, x.eii, x.partner >= 0 ? x.ce : nullptr};
-        const size_t len[5] = {3 * LL, 3 * LL, LL, 3 * (size_t)L, 3 * (size_t)L};
-        for (int t = 0; t < 5; ++t) {
-            off[5 * q + t] = tab.size();
+        if (!triples_ok(x.hpie, LL) || !triples_ok(x.eie, LL) || !finite_nonneg(x.A, LL))
+            return fail(c, LRT_E_ARG, "CR record %d: negative or non-finite rate data", q);
+        CRRec &R = rec[q];
+        std::memset(&R, 0, sizeof(CRRec));
+        R.species = x.species;
+        R.n_model = L;
+        R.n_lev = NL;
+        R.kind = mol ? 2 : 1;
+        R.nu_cut = x.nu_cut;
+        R.ion = R.partner = R.partner_ion = R.diss_x = R.diss_y = -1;
+        std::copy(x.texp, x.texp + 12, R.texp);
+        const double *src[kTabs] = {x.hpie, x.eie, x.A, nullptr, nullptr, nullptr, nullptr};
+        if (!mol) {
+            if (x.diss_x != -1 || x.diss_y != -1)
+                return fail(c, LRT_E_ARG, "CR record %d: dissociation given to an atom", q);
+            if (x.ion != -1 && !valid_sp(x.ion)) return fail(c, LRT_E_ARG, "CR record %d: ion out of range", q);
+            if (x.partner != -1) {
+                if (!valid_sp(x.partner) || x.partner == x.species || c->sp_kind[x.partner] != LRT_KIND_ATOM)
+                    return fail(c, LRT_E_ARG, "CR record %d: partner must be another atom", q);
+                if (!valid_sp(x.partner_ion)) return fail(c, LRT_E_ARG, "CR record %d: partner ion out of range", q);
+                if (x.ion < 0) return fail(c, LRT_E_ARG, "CR record %d: charge exchange needs the atom's ion", q);
+                if (!(x.partner_E_ion > 0.0) || !(x.partner_Q_ion > 0.0) || !std::isfinite(x.partner_E_ion) ||
+                    !std::isfinite(x.partner_Q_ion))
+                    return fail(c, LRT_E_ARG, "CR record %d: partner E_ion and Q_ion must be positive", q);
+            }
+            if (!(x.E_ion > 0.0) || !(x.Q_ion > 0.0) || !std::isfinite(x.E_ion) || !std::isfinite(x.Q_ion))
+                return fail(c, LRT_E_ARG, "CR record %d: E_ion and Q_ion must be positive", q);
+            if (!x.eii || (x.partner >= 0 && !x.ce)) return fail(c, LRT_E_ARG, "CR record %d: NULL rate table", q);
+            if (!triples_ok(x.eii, L) || (x.partner >= 0 && !triples_ok(x.ce, L)))
+                return fail(c, LRT_E_ARG, "CR record %d: negative or non-finite rate data", q);
+            src[3] = x.eii;
+            src[4] = x.partner >= 0 ? x.ce : nullptr;
+            R.ion = x.ion;
+            R.partner = x.partner;
+            R.partner_ion = x.partner >= 0 ? x.partner_ion : -1;
+            R.pn_lev = x.partner >= 0 ? n_levels(x.partner) : 0;
+            R.lev0 = c->h_lev_off[x.species];
+            R.plev0 = x.partner >= 0 ? c->h_lev_off[x.partner] : 0;
+            R.E_ion = x.E_ion;
+            R.Q_ion = x.Q_ion;
+            R.pE_ion = x.partner >= 0 ? x.partner_E_ion : 0.0;
+            R.pQ_ion = x.partner >= 0 ? x.partner_Q_ion : 1.0;
+        } else {
+            if (x.ion != -1 || x.partner != -1)
+                return fail(c, LRT_E_ARG, "CR record %d: ionization and charge exchange are for atoms", q);
+            R.e0 = c->h_el_off[x.species];
+            if (x.diss_x != -1 || x.diss_y != -1) {
+                if (!valid_sp(x.diss_x) || !valid_sp(x.diss_y))
+                    return fail(c, LRT_E_ARG, "CR record %d: dissociation product out of range", q);
+                if (!x.hpid || !x.eid) return fail(c, LRT_E_ARG, "CR record %d: NULL rate table", q);
+                if (!triples_ok(x.hpid, L) || !triples_ok(x.eid, L))
+                    return fail(c, LRT_E_ARG, "CR record %d: negative or non-finite rate data", q);
+                if (!std::isfinite(x.E_diss)) return fail(c, LRT_E_ARG, "CR record %d: non-finite E_diss", q);
+                const int p[2] = {x.diss_x, x.diss_y};
+                const double Qc[2] = {x.Q_x, x.Q_y};
+                for (int k = 0; k < 2; ++k)
+                    if (c->sp_kind[p[k]] != LRT_KIND_ATOM && !(Qc[k] > 0.0 && std::isfinite(Qc[k])))
+                        return fail(c, LRT_E_ARG, "CR record %d: product %d is not an atom and has no Q > 0", q, p[k]);
+                src[5] = x.hpid;
+                src[6] = x.eid;
+                R.diss_x = x.diss_x;
+                R.diss_y = x.diss_y;
+                R.nx_lev = c->sp_kind[x.diss_x] == LRT_KIND_ATOM ? n_levels(x.diss_x) : 0;
+                R.ny_lev = c->sp_kind[x.diss_y] == LRT_KIND_ATOM ? n_levels(x.diss_y) : 0;
+                R.x_lev0 = c->h_lev_off[x.diss_x];
+                R.y_lev0 = c->h_lev_off[x.diss_y];
+                R.Q_x = x.Q_x;
+                R.Q_y = x.Q_y;
+                R.E_diss = x.E_diss;
+                const double mx = c->sp_mass[x.diss_x], my = c->sp_mass[x.diss_y];
+                R.mu = mx * my / (mx + my) * (1.0 / 6.02214076e23);
+            }
+        }
+        // tables concatenated (zeros for the ones a record has no use for)
+        const size_t len[kTabs] = {3 * LL, 3 * LL, LL, 3 * (size_t)L, 3 * (size_t)L, 3 * (size_t)L, 3 * (size_t)L};
+        for (int t = 0; t < kTabs; ++t) {
+            off[kTabs * q + t] = tab.size();
             if (src[t]) tab.insert(tab.end(), src[t], src[t] + len[t]);
             else tab.insert(tab.end(), len[t], 0.0);
         }
-        CRRec &R = rec[q];
-        R.species = x.species;
-        R.ion = x.ion;
-        R.partner = x.partner;
-        R.partner_ion = x.partner >= 0 ? x.partner_ion : -1;
-        R.n_model = L;
-        R.n_lev = NL;
-        R.pn_lev = x.partner >= 0 ? (int32_t)(c->h_lev_off[x.partner + 1] - c->h_lev_off[x.partner]) : 0;
-        R.pad = 0;
-        R.lev0 = c->h_lev_off[x.species];
-        R.plev0 = x.partner >= 0 ? c->h_lev_off[x.partner] : 0;
-        R.E_ion = x.E_ion;
-        R.Q_ion = x.Q_ion;
-        R.pE_ion = x.partner >= 0 ? x.partner_E_ion : 0.0;
-        R.pQ_ion = x.partner >= 0 ? x.partner_Q_ion : 1.0;
-        R.nu_cut = x.nu_cut;
-        std::copy(x.texp, x.texp + 8, R.texp);
         slot[x.species] = q;
         nlev[q] = NL;
         LS = std::max(LS, NL);
@@ -195,11 +238,9 @@ lrt_status lrt_set_cr(lrt_ctx *c, int n, const lrt_cr_atom *atoms, const double 
         if ((st = upload(c, c->d_cr_tab, tab.data(), tab.size() * sizeof(double)))) return st;
         const double *base = c->d_cr_tab.as<double>();
         for (int q = 0; q < n; ++q) {
-            rec[q].hpie = base + off[5 * q + 0];
-            rec[q].eie = base + off[5 * q + 1];
-            rec[q].A = base + off[5 * q + 2];
-            rec[q].eii = base + off[5 * q + 3];
-            rec[q].ce = base + off[5 * q + 4];
+            const double **ptr[kTabs] = {&rec[q].hpie, &rec[q].eie, &rec[q].A, &rec[q].eii, &rec[q].ce,
+                                         &rec[q].hpid, &rec[q].eid};
+            for (int t = 0; t < kTabs; ++t) *ptr[t] = base + off[kTabs * q + t];
         }
         if ((st = upload(c, c->d_cr_rec, rec.data(), rec.size() * sizeof(CRRec))) ||
             (st = upload(c, c->d_cr_slot, slot.data(), slot.size() * sizeof(int32_t))) ||
@@ -238,12 +279,11 @@ lrt_status lrt_set_line_levels(lrt_ctx *c, const int32_t *lev_u, const int32_t *
             continue;
         }
         const int s = c->h_spc[j];
-        const int64_t NL = c->h_lev_off[s + 1] - c->h_lev_off[s];
-        if (c->sp_kind[s] != LRT_KIND_ATOM)
-            return fail(c, LRT_E_ARG, "line %lld: levels given to a line of a molecule", (long long)i);
+        const int64_t NL = c->sp_kind[s] == LRT_KIND_ATOM ? c->h_lev_off[s + 1] - c->h_lev_off[s]
+                                                           : c->h_el_off[s + 1] - c->h_el_off[s];
         if (a < 0 || b < 0 || a >= NL || b >= NL)
-            return fail(c, LRT_E_ARG, "line %lld: levels (%d, %d) outside the atom's %lld levels", (long long)i, a, b,
-                        (long long)NL);
+            return fail(c, LRT_E_ARG, "line %lld: states (%d, %d) outside the species' %lld states", (long long)i, a,
+                        b, (long long)NL);
         u[j] = a;
         l[j] = b;
     }
@@ -253,19 +293,19 @@ lrt_status lrt_set_line_levels(lrt_ctx *c, const int32_t *lev_u, const int32_t *
     return cr_build_line_levels(c);
 }
 
-lrt_status lrt_cr_populations(lrt_ctx *c, int atom, double *pop, void *stream)
+lrt_status lrt_cr_populations(lrt_ctx *c, int rec, double *pop, void *stream)
 {
     if (!c) return LRT_E_ARG;
     c->err.clear();
     if (c->n_cr < 1) return fail(c, LRT_E_STATE, "no QSS-CR atoms set");
-    if (atom < 0 || atom >= c->n_cr) return fail(c, LRT_E_ARG, "atom record %d out of range", atom);
+    if (rec < 0 || rec >= c->n_cr) return fail(c, LRT_E_ARG, "CR record %d out of range", rec);
     if (!pop) return fail(c, LRT_E_ARG, "pop must be non-NULL");
     hipStream_t st = (hipStream_t)stream;
     lrt_status r;
     if ((r = prepare(c, st, false))) return r;
-    const int NL = c->h_cr_nlev[atom];
+    const int NL = c->h_cr_nlev[rec];
     const size_t pitch = (size_t)c->n_cr * c->cr_LS * sizeof(double);
-    LRT_HIP(c, hipMemcpy2DAsync(pop, NL * sizeof(double), c->d_cr_pop.as<double>() + (size_t)atom * c->cr_LS, pitch,
+    LRT_HIP(c, hipMemcpy2DAsync(pop, NL * sizeof(double), c->d_cr_pop.as<double>() + (size_t)rec * c->cr_LS, pitch,
                                 NL * sizeof(double), (size_t)c->n_cells, hipMemcpyDeviceToHost, st));
     LRT_HIP(c, hipStreamSynchronize(st));
     return LRT_OK;

@@ -48,6 +48,7 @@ struct lrt_ctx {
         d_vib_off, d_vib_G, d_vib_B, d_vib_D;
     DevSpecies sp{};
     double M_min = 0.0;
+    std::vector<int64_t> h_el_off;       // host copy of the electronic-state offsets
     std::vector<int64_t> h_lev_off;      // host copies of the atomic level tables
     std::vector<double> h_lev_E, h_lev_g;
 

@@ -321,6 +321,7 @@ lrt_status lrt_set_species(lrt_ctx *c, int n, const lrt_species *sp)
     c->sp_kind = kind;
     c->sp_mass = mass;
     c->h_lev_off = lev_off;
+    c->h_el_off = el_off;
     c->h_lev_E = lev_E;
     c->h_lev_g = lev_g;
     c->n_cont_rec = c->n_cont_thr = 0;   // continuum records refer to the old table

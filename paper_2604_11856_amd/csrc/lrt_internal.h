@@ -111,21 +111,27 @@ struct DevCont {
 };
 constexpr double kNuH = 1e7 / 91.1267;   // hydrogen ground-state threshold, cm^-1
 
-// QSS collisional-radiative atoms (Sec. 2.1 CR model).  Levels 0..n_model-1
-// of the atom's table are solved for; levels n_model..n_lev-1 stay in
-// Boltzmann ratio (T_v) with level n_model-1.  Rate tables are Arrhenius
-// triples (C, n, E_a) of the forward processes: hpie/eie [l][l][3] at
-// [lo][hi] for lo -> hi, A [l][l] at [hi][lo], eii/ce [l][3] per level.
-// texp[2m], texp[2m+1]: forward / backward temperature T_tr^a T_v^(1-a) of
-// mechanism m (HPIE, EIE, EII, CE).
-constexpr int kCRMaxLevels = 64;   // one lane per level
+// QSS collisional-radiative species (Sec. 2.1 CR model): an atom's table
+// levels or a diatomic molecule's electronic states.  States 0..n_model-1
+// are solved for; states n_model..n_lev-1 stay in Boltzmann ratio
+// (T_v, T_tr) with state n_model-1.  Rate tables are Arrhenius triples
+// (C, n, E_a) of the forward processes: hpie/eie [l][l][3] at [lo][hi] for
+// lo -> hi, A [l][l] at [hi][lo], eii/ce (atoms) and hpid/eid (molecules)
+// [l][3] per state.  texp[2m], texp[2m+1]: forward / backward temperature
+// T_tr^a T_v^(1-a) of mechanism m (HPIE, EIE, EII, CE, HPID, EID).
+constexpr int kCRMaxLevels = 64;   // one lane per state
 struct CRRec {
     int32_t species, ion, partner, partner_ion;
-    int32_t n_model, n_lev, pn_lev, pad;
-    int64_t lev0, plev0;   // first level of the atom / the partner in the species tables
+    int32_t n_model, n_lev, pn_lev, kind;   // kind: 1 atom, 2 molecule
+    int32_t diss_x, diss_y;                 // molecule: products, -1 without dissociation
+    int32_t nx_lev, ny_lev;                 // level counts of atomic products (0: constant Q)
+    int64_t lev0, plev0;                    // atom: first level of the atom / its partner
+    int64_t e0;                             // molecule: first electronic state
+    int64_t x_lev0, y_lev0;                 // first levels of atomic products
     double E_ion, Q_ion, pE_ion, pQ_ion, nu_cut;
-    double texp[8];
-    const double *hpie, *eie, *A, *eii, *ce;
+    double Q_x, Q_y, E_diss, mu;            // mu: reduced mass of the products, g
+    double texp[12];
+    const double *hpie, *eie, *A, *eii, *ce, *hpid, *eid;
 };
 struct DevCR {
     int32_t n;                 // atoms (0: off)

@@ -63,12 +63,14 @@ class _Continuum(C.Structure):
                 ("Q_ion", C.c_double), ("sigma0", _dp), ("peach", C.c_double * 8), ("z", C.c_double)]
 
 
-class _CRAtom(C.Structure):
+class _CRSpecies(C.Structure):
     _fields_ = [("species", C.c_int32), ("ion", C.c_int32), ("partner", C.c_int32),
-                ("partner_ion", C.c_int32), ("n_model", C.c_int32), ("E_ion", C.c_double),
-                ("Q_ion", C.c_double), ("partner_E_ion", C.c_double), ("partner_Q_ion", C.c_double),
-                ("nu_cut", C.c_double), ("texp", C.c_double * 8), ("hpie", _dp), ("eie", _dp),
-                ("A", _dp), ("eii", _dp), ("ce", _dp)]
+                ("partner_ion", C.c_int32), ("n_model", C.c_int32), ("diss_x", C.c_int32),
+                ("diss_y", C.c_int32), ("E_ion", C.c_double), ("Q_ion", C.c_double),
+                ("partner_E_ion", C.c_double), ("partner_Q_ion", C.c_double), ("Q_x", C.c_double),
+                ("Q_y", C.c_double), ("E_diss", C.c_double), ("nu_cut", C.c_double),
+                ("texp", C.c_double * 12), ("hpie", _dp), ("eie", _dp), ("A", _dp), ("eii", _dp),
+                ("ce", _dp), ("hpid", _dp), ("eid", _dp)]
 
 
 class _Cells(C.Structure):
@@ -136,7 +138,7 @@ def lib():
             "lrt_cancel": (st, [_vp, C.c_uint64]),
             "lrt_server_info": (st, [_vp, _i64p, _i64p, _i64p, _i64p, C.POINTER(C.c_size_t)]),
             "lrt_server_stop": (st, [_vp]),
-            "lrt_set_cr": (st, [_vp, C.c_int, C.POINTER(_CRAtom), _dp]),
+            "lrt_set_cr": (st, [_vp, C.c_int, C.POINTER(_CRSpecies), _dp]),
             "lrt_set_line_levels": (st, [_vp, _i32p, _i32p, C.c_int64]),
             "lrt_cr_populations": (st, [_vp, C.c_int, _dp, _vp]),
         }
@@ -263,18 +265,26 @@ class Context:
         self._chk(self._L.lrt_set_lorentz(self.h, _p(e)))
 
     def set_cr(self, cr):
-        """QSS collisional-radiative atoms (synth.CRModel), or None for none."""
+        """QSS collisional-radiative atoms and molecules (synth.CRModel), or
+        None for none."""
         if cr is None or not cr.species:
             self._chk(self._L.lrt_set_cr(self.h, 0, None, None))
             return
-        keep, arr = [], (_CRAtom * len(cr.species))()
+        keep, arr = [], (_CRSpecies * len(cr.species))()
         for j, r in enumerate(cr.species):
-            t = [np.ascontiguousarray(a, np.float64) for a in (r.hpie, r.eie, r.A, r.eii, r.ce)]
+            L = int(r.n_model)
+            z = np.zeros((L, 3))
+            t = [np.ascontiguousarray(a, np.float64) for a in
+                 (r.hpie, r.eie, r.A, r.eii, r.ce,
+                  z if r.hpid is None else r.hpid, z if r.eid is None else r.eid)]
             keep.append(t)
-            arr[j] = _CRAtom(int(r.species), int(r.ion), int(r.partner), int(r.partner_ion),
-                             int(r.n_model), float(r.E_ion), float(r.Q_ion), float(r.partner_E_ion),
-                             float(r.partner_Q_ion), float(r.nu_cut),
-                             (C.c_double * 8)(*[float(v) for v in r.texp]), *[_p(a) for a in t])
+            texp = np.zeros(12)
+            texp[:len(r.texp)] = r.texp
+            arr[j] = _CRSpecies(int(r.species), int(r.ion), int(r.partner), int(r.partner_ion),
+                                L, int(r.diss_x), int(r.diss_y), float(r.E_ion), float(r.Q_ion),
+                                float(r.partner_E_ion), float(r.partner_Q_ion), float(r.Q_x),
+                                float(r.Q_y), float(r.E_diss), float(r.nu_cut),
+                                (C.c_double * 12)(*[float(v) for v in texp]), *[_p(a) for a in t])
         w = np.ascontiguousarray(cr.collider_w, np.float64)
         self._chk(self._L.lrt_set_cr(self.h, len(cr.species), arr, _p(w)))
 
@@ -287,11 +297,11 @@ class Context:
         u, l = np.ascontiguousarray(lev[:, 0]), np.ascontiguousarray(lev[:, 1])
         self._chk(self._L.lrt_set_line_levels(self.h, _p(u, _i32p), _p(l, _i32p), lev.shape[0]))
 
-    def cr_populations(self, atom: int, n_levels: int, stream=None):
-        """Level populations [n_cells, n_levels] of QSS-CR record `atom`."""
+    def cr_populations(self, rec: int, n_levels: int, stream=None):
+        """State populations [n_cells, n_levels] of QSS-CR record `rec`."""
         nc = max(self.sizes()["n_cells"], 0)
         out = np.zeros((nc, n_levels))
-        self._chk(self._L.lrt_cr_populations(self.h, int(atom), _p(out), _stream(stream)))
+        self._chk(self._L.lrt_cr_populations(self.h, int(rec), _p(out), _stream(stream)))
         return out
 
     def set_march(self, scheme: int):

@@ -115,6 +115,62 @@ def test_cr_populations_largest_atom_no_ion(torch_dev):
     ctx.close()
 
 
+def small_molecule(n_el, n_v=4, J_max=30):
+    T_e = np.array([0.0, 30000.0, 45000.0, 52000.0][:n_el])
+    G = []
+    for e in range(n_el):
+        om = 1500.0 + 200.0 * e
+        v = np.arange(n_v) + 0.5
+        G.append(om * v - om / 200.0 * v * v)
+    return synth.Species("N2", synth.KIND_MOLECULE, 28.0, el_T=T_e,
+                         el_g=np.array([1.0, 3.0, 2.0, 6.0][:n_el]),
+                         el_nv=np.full(n_el, n_v, np.int32), el_Jmax=np.full(n_el, J_max, np.int32),
+                         vib_G=np.concatenate(G), vib_B=np.repeat(np.linspace(1.6, 1.9, n_el), n_v),
+                         vib_D=np.zeros(n_el * n_v))
+
+
+def test_cr_molecule_with_tail_and_dissociation(torch_dev):
+    """A four-state diatomic with three states solved (one in the two-
+    temperature Boltzmann tail), dissociating into N + N, next to a CR atom;
+    populations, and eta / kappa of its rovibronic lines (band 1 -> 0) and
+    of the atom's lines, in nonequilibrium cells."""
+    rng = np.random.Generator(np.random.PCG64(41))
+    species = [small_molecule(4), synth.atom_species(rng, "N"), synth.none_species("N+"),
+               synth.none_species("e-")]
+    cr = synth.air_cr(species, n_model=3)
+    assert [r.species for r in cr.species] == [1, 0] and cr.species[1].n_model == 3
+    n_cells = 12
+    Ttr = rng.uniform(6000.0, 25000.0, n_cells)
+    Tv = rng.uniform(3000.0, 12000.0, n_cells)
+    N = np.stack([10 ** rng.uniform(15, 17, n_cells), 10 ** rng.uniform(15, 17, n_cells),
+                  10 ** rng.uniform(13, 15, n_cells), np.zeros(n_cells)], axis=1)
+    N[:, 3] = N[:, 2]
+    cells = synth.Cells(Ttr, Tv, N, N[:, 2].copy())
+    parts = [synth.atomic_lines(rng, 1, 300, 15000.0, 40000.0),
+             synth.rovib_lines(rng, species[0], 0, 600, 15000.0, 40000.0)]
+    lines = synth.merge_sorted(parts)
+    grid = synth.Grid(15000.0, 40000.0, 20001, 7000)
+    wl = synth.Workload("molecule", species, lines, cells, grid, synth.SlabGeometry(np.full(n_cells, 0.1), 0))
+    wl.cr = cr
+    wl.lines, wl.line_levels = synth.lines_on_levels(lines, species, cr, grid)
+    assert np.any(wl.line_levels[wl.lines.species == 0, 0] == 1)
+    ctx = lrt.Context(0).load(wl)
+    ref = check_populations(ctx, wl, "4-state molecule")
+    assert np.all(ref[1] > 0)
+    e_r, k_r, _ = O.coeffs(species, wl.lines, cells, grid, cr=cr, line_levels=wl.line_levels)
+    for prec in PRECS:
+        we = wk = 0.0
+        for b in range(ctx.sizes()["n_bands"]):
+            e, k = gpu_coeffs(ctx, b, prec, torch_dev)
+            k0 = b * grid.band_points
+            m = edge_mask(wl, k0, e.shape[1])
+            we = max(we, normwise(e, e_r[:, k0:k0 + e.shape[1]], m))
+            wk = max(wk, normwise(k, k_r[:, k0:k0 + e.shape[1]], m))
+        say("4-state molecule coeffs prec %d: eta %.3e kappa %.3e" % (prec, we, wk))
+        assert we <= TOL[prec] and wk <= TOL[prec]
+    ctx.close()
+
+
 def test_cr_coeffs_all_bands(torch_dev):
     """eta and kappa of the lines with levels (and the bound-free absorption)
     from the QSS-CR populations, over ragged bands, with and without the
@@ -201,6 +257,7 @@ def test_cr_full_size_stagnation(torch_dev):
 def test_cr_arguments(torch_dev):
     wl = cr_stagnation(n_cells=2, n_atomic=10, n_rovib=10, n_points=1000, band_points=1000)
     cr = wl.cr
+    names = [sp.name for sp in wl.species]
     ctx = lrt.Context(0)
     with pytest.raises(lrt.LrtError) as e:
         ctx.set_cr(cr)                           # no species yet
@@ -213,7 +270,19 @@ def test_cr_arguments(torch_dev):
             ctx.set_cr(dataclasses.replace(cr, species=[dataclasses.replace(r0, **kw)]))
         assert e.value.status == 1
 
-    bad(species=0)                               # N2 is not an atom
+    bad(species=0)                               # N2 is a molecule: no ionization for it
+    bad(diss_x=3, diss_y=3)                      # dissociation given to an atom
+    m0 = [r for r in cr.species if r.diss_x >= 0][0]
+
+    def bad_mol(**kw):
+        with pytest.raises(lrt.LrtError) as e:
+            ctx.set_cr(dataclasses.replace(cr, species=[dataclasses.replace(m0, **kw)]))
+        assert e.value.status == 1
+
+    bad_mol(diss_y=99)
+    bad_mol(diss_y=names.index("N+"), Q_y=0.0)   # a non-atomic product needs Q > 0
+    bad_mol(hpid=-m0.hpid)
+    bad_mol(ion=names.index("N2+"))
     bad(n_model=1)
     bad(n_model=21)                              # the atom has 20 levels
     bad(ion=99)
@@ -238,8 +307,9 @@ def test_cr_arguments(torch_dev):
     with pytest.raises(lrt.LrtError):
         ctx.set_line_levels(wl.line_levels[:-1])
     lev = wl.line_levels.copy()
-    mol = np.nonzero(lev[:, 0] < 0)[0][0]
-    lev[mol] = (0, 0)                            # levels on a molecule's line
+    names = [sp.name for sp in wl.species]
+    mol = np.nonzero(wl.lines.species == names.index("N2"))[0][0]
+    lev[mol] = (2, 0)                            # N2 has 2 electronic states
     with pytest.raises(lrt.LrtError):
         ctx.set_line_levels(lev)
     lev = wl.line_levels.copy()
