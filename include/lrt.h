@@ -70,7 +70,8 @@ enum { LRT_KIND_NONE = 0, LRT_KIND_ATOM = 1, LRT_KIND_MOLECULE = 2 };
  *   constants vib_B, vib_D, concatenated over e) and J = 0..el_Jmax[e];
  *   Q = sum_e g_e exp(-c2 T_e/T_v) sum_v exp(-c2 G_v/T_v)
  *       sum_J (2J+1) exp(-c2 (B_v J(J+1) - D_v J^2(J+1)^2) / T_tr).
- *   Symmetry number and line-alternation factor are taken as 1.
+ *   Symmetry number and line-alternation factor are taken as 1.  A state
+ *   has at most 2^30 (v, J) terms.
  * kind == LRT_KIND_NONE: species that carries no lines (number density only).
  * mass: molar mass in g/mol (Doppler width). */
 typedef struct {

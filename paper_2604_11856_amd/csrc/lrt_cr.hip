@@ -51,22 +51,37 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Partition function of electronic state e of a molecule at (Tv, Tr):
+// Partition functions of electronic state e of a molecule, in one pass over
+// its (v, J) terms spread over the lanes: out[0] at (Tv, Tr) and out[1 + k]
+// at T[k] (vibration and rotation alike, k < nT), each
 // g_e e^{-c2 T_e/Tv} sum_v e^{-c2 G_v/Tv} sum_J (2J+1) e^{-c2 F_v(J)/Tr},
-// F = B J(J+1) - D J^2 (J+1)^2, the (v, J) terms spread over the lanes.
-// Called by the whole wave; every lane receives the value.
-__device__ double mol_state_q(const DevSpecies &sp, int64_t e, double Tv, double Tr, int lane)
+// F = B J(J+1) - D J^2 (J+1)^2.  Called by the whole wave; every lane
+// receives the values.
+template <int nT>
+__device__ void mol_state_q(const DevSpecies &sp, int64_t e, double Tv, double Tr, const double *T, int lane,
+                            double *out)
 {
-    const int64_t v0 = sp.vib_off[e], nv = sp.vib_off[e + 1] - v0;
-    const int nJ = sp.el_Jmax[e] + 1;
-    double acc = 0.0;
-    for (int64_t t = lane; t < nv * nJ; t += 64) {
+    const int64_t v0 = sp.vib_off[e];
+    const int nv = (int)(sp.vib_off[e + 1] - v0), nJ = sp.el_Jmax[e] + 1;
+    double iT[nT];
+#pragma unroll
+    for (int k = 0; k < nT; ++k) iT[k] = 1.0 / T[k];
+    const double iTv = 1.0 / Tv, iTr = 1.0 / Tr;
+    double acc[nT + 1];
+#pragma unroll
+    for (int k = 0; k <= nT; ++k) acc[k] = 0.0;
+    for (int t = lane; t < nv * nJ; t += 64) {
         const int64_t v = v0 + t / nJ;
-        const double J = (double)(t % nJ), jj = J * (J + 1.0);
-        const double F = sp.vib_B[v] * jj - sp.vib_D[v] * jj * jj;
-        acc += exp(-kC2 * sp.vib_G[v] / Tv) * ((2.0 * J + 1.0) * exp(-kC2 * F / Tr));
+        const double J = (double)(t % nJ), jj = J * (J + 1.0), g = 2.0 * J + 1.0;
+        const double x = kC2 * sp.vib_G[v], y = kC2 * (sp.vib_B[v] * jj - sp.vib_D[v] * jj * jj);
+        acc[0] += g * exp(-x * iTv - y * iTr);
+#pragma unroll
+        for (int k = 0; k < nT; ++k) acc[1 + k] += g * exp(-(x + y) * iT[k]);
     }
-    return sp.el_g[e] * exp(-kC2 * sp.el_T[e] / Tv) * wave_sum(acc);
+    const double cT = kC2 * sp.el_T[e], ge = sp.el_g[e];
+    out[0] = ge * exp(-cT * iTv) * wave_sum(acc[0]);
+#pragma unroll
+    for (int k = 0; k < nT; ++k) out[1 + k] = ge * exp(-cT * iT[k]) * wave_sum(acc[1 + k]);
 }
 
 // Partition function of a dissociation product at T: an atom's level sum,
@@ -134,14 +149,15 @@ __global__ __launch_bounds__(64) void cr_kernel(DevSpecies sp, DevCells cells, D
     } else {
         for (int j = 0; j < NL; ++j) {   // wave-uniform: the (v, J) sums use every lane
             const int64_t e = R.e0 + j;
-            const double qh = mol_state_q(sp, e, Tm[1], Tm[1], lane);
-            const double qe = mol_state_q(sp, e, Tm[3], Tm[3], lane);
-            const double qv = mol_state_q(sp, e, Tv, Ttr, lane);
-            double qdh = 0.0, qde = 0.0;
+            double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             if (R.diss_x >= 0) {
-                qdh = mol_state_q(sp, e, Tm[9], Tm[9], lane);
-                qde = mol_state_q(sp, e, Tm[11], Tm[11], lane);
+                const double T4[4] = {Tm[1], Tm[3], Tm[9], Tm[11]};
+                mol_state_q<4>(sp, e, Tv, Ttr, T4, lane, o);
+            } else {
+                const double T2[2] = {Tm[1], Tm[3]};
+                mol_state_q<2>(sp, e, Tv, Ttr, T2, lane, o);
             }
+            const double qv = o[0], qh = o[1], qe = o[2], qdh = o[3], qde = o[4];
             if (lane == 0) {
                 QH[j] = qh;
                 QE[j] = qe;

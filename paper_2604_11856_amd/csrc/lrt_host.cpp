@@ -291,6 +291,8 @@ lrt_status lrt_set_species(lrt_ctx *c, int n, const lrt_species *sp)
             for (int e = 0; e < x.n_el; ++e) {
                 if (x.el_nv[e] < 1 || x.el_Jmax[e] < 0 || !std::isfinite(x.el_T[e]) || !(x.el_g[e] > 0.0))
                     return fail(c, LRT_E_ARG, "species %d state %d: bad electronic entry", s, e);
+                if ((int64_t)x.el_nv[e] * ((int64_t)x.el_Jmax[e] + 1) > (int64_t(1) << 30))
+                    return fail(c, LRT_E_ARG, "species %d state %d: more than 2^30 (v, J) terms", s, e);
                 el_T.push_back(x.el_T[e]);
                 el_g.push_back(x.el_g[e]);
                 el_J.push_back(x.el_Jmax[e]);
