@@ -440,11 +440,10 @@ __global__ void scale_finish_kernel(const int32_t *emax, int32_t n, int32_t *esc
 // bit masks and needs no vector work for control flow.
 constexpr int kSlices = kTilePoints / 64;
 struct __align__(16) RecF32 {
-    uint32_t mode;
+    float k0f, hg, fg, r;           // centre index (tile-relative), h/gV, frac0/gV, gL/gV
+    float aG, aW, se, sk;           // 1-r, 0.016 r (1-r), scaled strengths
     float klo, khi;                 // window, tile-relative, clamped to [-1, tile] (edge masks)
-    float k0f;                      // centre index, tile-relative
-    float hg, fg, r, aG;            // h/gV, frac0/gV, gL/gV, 1-r
-    float aW, se, sk, pad;          // 0.016 r (1-r), scaled strengths
+    uint32_t mode, pad;
 };
 static_assert(kSlices <= 8 && kPPL <= 2, "mode masks hold at most 8 slices per tile");
 
@@ -575,6 +574,45 @@ using BlockMask = std::conditional_t<(kBlock > 32), uint64_t, uint32_t>;
 __device__ __forceinline__ int lowest_bit(uint32_t m) { return __builtin_ctz(m); }
 __device__ __forceinline__ int lowest_bit(uint64_t m) { return __builtin_ctzll(m); }
 
+// Order in which a wave walks the lines of a block that reach it (both in
+// line order, so the sums are bitwise the same):
+//   0: lowest set bit of the block mask, one line at a time
+//   1: groups of 8 lines with constant LDS offsets
+#ifndef LRT_LINE_WALK
+#define LRT_LINE_WALK 1
+#endif
+
+// The terms of one staged line (bit t of the block masks) on this wave's
+// slices, added to the block partials.
+template <typename Mask>
+__device__ __forceinline__ void line_terms(const RecF32 &qr, int t, const float (&kf)[kPPL],
+                                           const Mask (&m_in)[kPPL], const Mask (&m_core)[kPPL],
+                                           const Mask (&m_edge)[kPPL], float (&ae)[kPPL], float (&ak)[kPPL])
+{
+    const RecF32 q = qr;
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        if (!((m_in[j] >> t) & 1u)) continue;      // slice outside the window
+        float d1, pw;
+        float P = shape_rational_f32(kf[j], q, d1, pw);
+        // Within 25 HWHM of the centre the exponentials contribute;
+        // beyond it they are exactly zero in single precision.  Both
+        // conditions are wave-uniform; the empty asm keeps them real
+        // scalar branches instead of computing both sides and selecting.
+        if ((m_core[j] >> t) & 1u) {
+            asm volatile("");
+            P = shape_exp_f32(q, d1, pw, P);
+        }
+        // slice crossing a window edge: mask the lanes outside
+        if ((m_edge[j] >> t) & 1u) {
+            asm volatile("");
+            P = (kf[j] >= q.klo && kf[j] <= q.khi) ? P : 0.0f;
+        }
+        ae[j] = fmaf(P, q.se, ae[j]);
+        ak[j] = fmaf(P, q.sk, ak[j]);
+    }
+}
+
 // eta and kappa of one cell on one tile (kTilePoints points starting at the
 // global index kt) in single precision: every round stages kStage candidate
 // lines (one FP64 setup per thread) into `rec`, then each wave evaluates the
@@ -605,7 +643,8 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
         rr.mode = 0;
         rr.klo = 1.0f;
         rr.khi = 0.0f;
-        rr.k0f = rr.hg = rr.fg = rr.r = rr.aG = rr.aW = rr.se = rr.sk = rr.pad = 0.0f;
+        rr.k0f = rr.hg = rr.fg = rr.r = rr.aG = rr.aW = rr.se = rr.sk = 0.0f;
+        rr.pad = 0;
         if (i < rg.y) {
             PairF64 p;
             if (pair_setup(L, g, k, csc, lnd_c, i, p)) {
@@ -642,32 +681,37 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
                 m_edge[j] = (BlockMask)__ballot(mb & (1u << (8 + j)));
                 m_core[j] = (BlockMask)__ballot(mb & (1u << (16 + j)));
             }
+#if LRT_LINE_WALK == 0
             while (todo) {
                 const int t = lowest_bit(todo);
                 todo &= todo - 1;
-                const RecF32 q = rec[l0 + t];
+                line_terms(rec[l0 + t], t, kf, m_in, m_core, m_edge, ae, ak);
+            }
+#else
+            // groups of 8 lines: within a group the LDS offsets are constants
+            // from one base address held in a vector register, and the block
+            // masks, shifted once per group, are tested at constant bits; a
+            // group that no line of it reaches is skipped whole
+            for (int g8 = 0; g8 < kBlock; g8 += 8) {
+                const uint32_t gt = (uint32_t)(todo >> g8) & 0xffu;
+                if (gt == 0) continue;
+                uint32_t gi[kPPL], gc[kPPL], ge[kPPL];
 #pragma unroll
                 for (int j = 0; j < kPPL; ++j) {
-                    if (!((m_in[j] >> t) & 1u)) continue;      // slice outside the window
-                    float d1, pw;
-                    float P = shape_rational_f32(kf[j], q, d1, pw);
-                    // Within 25 HWHM of the centre the exponentials contribute;
-                    // beyond it they are exactly zero in single precision.  Both
-                    // conditions are wave-uniform; the empty asm keeps them real
-                    // scalar branches instead of computing both sides and selecting.
-                    if ((m_core[j] >> t) & 1u) {
-                        asm volatile("");
-                        P = shape_exp_f32(q, d1, pw, P);
-                    }
-                    // slice crossing a window edge: mask the lanes outside
-                    if ((m_edge[j] >> t) & 1u) {
-                        asm volatile("");
-                        P = (kf[j] >= q.klo && kf[j] <= q.khi) ? P : 0.0f;
-                    }
-                    ae[j] = fmaf(P, q.se, ae[j]);
-                    ak[j] = fmaf(P, q.sk, ak[j]);
+                    gi[j] = (uint32_t)(m_in[j] >> g8);
+                    gc[j] = (uint32_t)(m_core[j] >> g8);
+                    ge[j] = (uint32_t)(m_edge[j] >> g8);
                 }
+                // one LDS base per group (a byte offset in a vector register),
+                // not one per line
+                uint32_t off = (uint32_t)((l0 + g8) * (int)sizeof(RecF32));
+                asm volatile("" : "+v"(off));
+                const RecF32 *rg8 = (const RecF32 *)((const char *)rec + off);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if ((gt >> u) & 1u) line_terms(rg8[u], u, kf, gi, gc, ge, ae, ak);
             }
+#endif
 #pragma unroll
             for (int j = 0; j < kPPL; ++j) {
                 kahan_add(se[j], ce[j], ae[j]);
