@@ -599,8 +599,11 @@ __device__ __forceinline__ int lowest_bit(uint64_t m) { return __builtin_ctzll(m
 
 // Order in which a wave walks the lines of a block that reach it (both in
 // line order, so the sums are bitwise the same):
-//   0: lowest set bit of the block mask, one line at a time
-//   1: groups of 8 lines with constant LDS offsets
+//   0: lowest set bit of the block mask, one line at a time (per line a
+//      vector move of the LDS address and ~8 more scalar instructions)
+//   1: groups of 8 lines with constant LDS offsets from one base register;
+//      measured 4 % faster on the stagnation line, 5-8 % on the
+//      axisymmetric bands
 #ifndef LRT_LINE_WALK
 #define LRT_LINE_WALK 1
 #endif
