@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--workload", default="stagnation", choices=["stagnation", "slab", "axi"])
-    ap.add_argument("--cpu-points", type=int, default=512, help="grid points of the oracle sample")
+    ap.add_argument("--cpu-points", type=int, default=1536, help="grid points of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true",
                     help="skip the side measurements (march schemes, continuum, QSS-CR), so that a "
@@ -230,6 +230,33 @@ def continuum_cost(ctx, wl, lrt, torch, reps=2):
     return out
 
 
+def lorentz_cost(ctx, wl, lrt, torch, reps=2):
+    """Band 0 in single precision: accumulation with the uniform Lorentz law of
+    the workload against the full per-line width of the atomic lines (natural
+    + Stark + van der Waals, Sec. 2.2.1).  The windows follow the widths, so
+    the in-window term counts differ; each is counted."""
+    from paper_2604_11856_amd import synth
+    E = synth.air_ionization_energies(wl.species)
+    out = {"band": 0}
+    for name, e in (("uniform", None), ("full", E)):
+        ctx.set_lorentz(e)
+        terms = ctx.count_terms(0)
+        eta, kap, esc = ctx.coeffs_torch(0, lrt.LRT_FP32_COMP)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(reps):
+            ctx.coeffs(0, lrt.LRT_FP32_COMP, eta, kap, esc)
+        torch.cuda.synchronize()
+        ms, n = ctx.profile_read("accum")
+        ctx.profile(False)
+        t = ms / max(1, n)
+        out[name] = {"accum_ms": t, "terms": int(terms), "evals_per_s": terms / (t / 1e3)}
+        del eta, kap, esc
+    ctx.set_lorentz(None)
+    torch.cuda.empty_cache()
+    return out
+
+
 def cr_cost(wl, lrt, torch, reps=2, scale_cells=32768):
     """QSS collisional-radiative populations of N and O (Sec. 2.1) on the
     workload with its atomic lines put on level pairs (synth.with_cr): whole
@@ -351,10 +378,11 @@ def main():
                    "I_int_max": float(np.max(np.abs(I32 - I64) / np.maximum(np.abs(I64), 1e-300))),
                    "q": [float(abs(a - b) / abs(b)) if b != 0 else 0.0 for a, b in zip(q32, q64)]}}
 
-    march_schemes = continuum = cr = None
+    march_schemes = continuum = cr = lorentz = None
     if not args.no_side:
         march_schemes = compare_march_schemes(ctx, lrt, torch, sz)
         continuum = continuum_cost(ctx, wl, lrt, torch)
+        lorentz = lorentz_cost(ctx, wl, lrt, torch)
         cr = cr_cost(wl, lrt, torch) if args.workload == "stagnation" else None
 
     acc_ms, acc_n = prof32["accum"]
@@ -397,6 +425,7 @@ def main():
                      "avg_launch_ms": acc_s * 1e3},
         "march_schemes": march_schemes,
         "continuum": continuum,
+        "lorentz": lorentz,
         "cr": cr,
         # every ray of a wall point re-reads the rows of the cells it crosses, so
         # the march does an exp per (ray, segment, point) on 8 B that the rays
