@@ -55,7 +55,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--workload", default="stagnation", choices=["stagnation", "slab", "axi"])
+    ap.add_argument("--workload", default="stagnation", choices=["stagnation", "slab", "axi", "axi_large"])
+    ap.add_argument("--band", type=int, default=None,
+                    help="time one band alone (coefficients of every cell, then the march of every "
+                         "ray), print its own JSON line and exit")
     ap.add_argument("--cpu-points", type=int, default=1536, help="grid points of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true",
@@ -91,11 +94,69 @@ def workload(name):
     elif name == "slab":
         wl = synth.config_slab()
         desc = "slab: 64 cells x 0.05 cm, 2000 N/O lines, 200,000-point grid 5000-80000 cm^-1, 1 ray"
-    else:
+    elif name == "axi":
         wl = synth.config_axi()
         desc = ("axisymmetric: 256x128 cells, 11 species, 1M lines, 2^20-point grid in 16 bands, "
                 "64 wall points x (16 GL x 16 azimuth) rays")
+    else:
+        wl = synth.config_axi_large()
+        desc = ("large axisymmetric: 512x256 cells, 11 species, 4M-line generator, 2^22-point grid "
+                "in 32 bands of 131072, 256 wall points x (32 GL x 32 azimuth) rays")
     return wl, desc
+
+
+def band_bench(args):
+    """One band of a workload timed alone: the single-precision coefficients of
+    every cell, then the march of every ray through them with the band's
+    trapezoid sum (no per-point intensity kept), HIP events per kernel.  A
+    whole step of the large axisymmetric case is 32 such bands."""
+    import torch
+    from paper_2604_11856_amd import lrt
+    wl, desc = workload(args.workload)
+    ctx = lrt.Context(0).load(wl)
+    sz = ctx.sizes()
+    b = args.band
+    if not 0 <= b < sz["n_bands"]:
+        print("band %d out of range [0, %d)" % (b, sz["n_bands"]), file=sys.stderr)
+        sys.exit(2)
+    n_terms, n_core = ctx.count_terms(b, core=True)
+    nb = ctx.band_len(b)
+    n_seg = sum(len(ctx.ray(r)[0]) for r in range(sz["n_rays"]))
+    eta = torch.empty((sz["n_cells"], nb), dtype=torch.float32, device="cuda:0")
+    kap = torch.empty_like(eta)
+    esc = torch.zeros((sz["n_cells"], 2), dtype=torch.int32, device="cuda:0")
+    I_int = torch.empty((sz["n_rays"],), dtype=torch.float64, device="cuda:0")
+
+    def once():
+        ctx.coeffs(b, lrt.LRT_FP32_COMP, eta, kap, esc)
+        ctx.march(b, lrt.LRT_FP32_COMP, eta, kap, esc, None, I_int)
+
+    for _ in range(args.warmup):
+        once()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        once()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    prof = {k: ctx.profile_read(k) for k in lrt.KERNELS}
+    ctx.profile(False)
+    acc_s = prof["accum"][0] / 1e3 / max(1, prof["accum"][1])
+    mar_s = prof["march"][0] / 1e3 / max(1, prof["march"][1])
+    slots = n_core * SLOTS_CORE + (n_terms - n_core) * SLOTS_WING
+    seg_pts = n_seg * nb
+    print(json.dumps({
+        "metric": "one band alone: Voigt line-pt evals/s, march row GB/s", "workload": desc,
+        "band": b, "band_points": nb, "cells": sz["n_cells"], "rays": sz["n_rays"],
+        "steps": args.steps, "warmup": args.warmup, "ms_per_band": dt * 1e3,
+        "terms": n_terms, "core_fraction": n_core / max(1, n_terms), "evals_per_s": n_terms / dt,
+        "accum_ms": acc_s * 1e3, "accum_frac_of_valu_issue": slots / acc_s / PEAK_LANE_OPS,
+        "march_ms": mar_s * 1e3, "segment_points": seg_pts,
+        "march_row_GB_per_s": seg_pts * 8 / mar_s / 1e9,
+        "march_frac_of_valu_issue": seg_pts * SLOTS_MARCH / mar_s / PEAK_LANE_OPS,
+        "kernels_ms": {k: v[0] / args.steps for k, v in prof.items()}}), flush=True)
+    ctx.close()
 
 
 # Sources of the accumulation kernel; the committed counter summary records
@@ -340,6 +401,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.band is not None:
+        band_bench(args)
+        return
     import torch
     from paper_2604_11856_amd import lrt
 

@@ -21,7 +21,9 @@
 // atomics touch eta, kappa, I or the flux; sums run in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
+#include <cstdint>
 #include <cmath>
 #include <type_traits>
 
@@ -758,11 +760,11 @@ __global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(L
 void accum_f32_kernel(
     DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int32_t *escale,
     const int2 *ranges, int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band,
-    int32_t n_tiles, DevCont ct, float *eta, float *kappa)
+    int32_t n_tiles, uint32_t b0, DevCont ct, float *eta, float *kappa)
 {
     __shared__ RecF32 rec[kStage];
     int tile, c;
-    block_tile_cell(blockIdx.x, gridDim.x, n_cells, n_tiles, tile, c);
+    block_tile_cell(b0 + blockIdx.x, (uint32_t)n_tiles * (uint32_t)n_cells, n_cells, n_tiles, tile, c);
     // the wave index is uniform across the wave: keep it (and every bound
     // derived from it) in scalar registers so slice tests are scalar branches
     const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
@@ -793,11 +795,11 @@ void accum_f32_kernel(
 __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
     DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int2 *ranges,
     int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles,
-    DevCont ct, double *eta, double *kappa)
+    uint32_t b0, DevCont ct, double *eta, double *kappa)
 {
     __shared__ RecF64 rec[kStage];
     int tile, c;
-    block_tile_cell(blockIdx.x, gridDim.x, n_cells, n_tiles, tile, c);
+    block_tile_cell(b0 + blockIdx.x, (uint32_t)n_tiles * (uint32_t)n_cells, n_cells, n_tiles, tile, c);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t kt = k_first + tile * kTilePoints;
     const int32_t kw = kt + wave * 64 * kPPL;
@@ -1075,10 +1077,16 @@ hipError_t launch_accum_f32(const DevLines &L, const DevGrid &g, const CellConst
                             const DevCont &ct, float *eta, float *kappa, hipStream_t st)
 {
     const int32_t n_tiles = (n_band + kTilePoints - 1) / kTilePoints;
-    hipLaunchKernelGGL(accum_f32_kernel, dim3((unsigned)((int64_t)n_tiles * n_cells)),
-                       dim3(kAccumThreads), 0, st, L, g, cc, cs, escale, ranges, n_cells, n_species,
-                       k_first, n_band, n_tiles, ct, eta, kappa);
-    return hipGetLastError();
+    const int64_t n_blocks = (int64_t)n_tiles * n_cells;
+    if (n_blocks > (int64_t)UINT32_MAX) return hipErrorInvalidConfiguration;
+    for (int64_t b0 = 0; b0 < n_blocks; b0 += kMaxLaunchBlocks) {
+        hipLaunchKernelGGL(accum_f32_kernel, dim3((unsigned)std::min(kMaxLaunchBlocks, n_blocks - b0)),
+                           dim3(kAccumThreads), 0, st, L, g, cc, cs, escale, ranges, n_cells, n_species,
+                           k_first, n_band, n_tiles, (uint32_t)b0, ct, eta, kappa);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_accum_f64(const DevLines &L, const DevGrid &g, const CellConst *cc,
@@ -1087,10 +1095,16 @@ hipError_t launch_accum_f64(const DevLines &L, const DevGrid &g, const CellConst
                             double *eta, double *kappa, hipStream_t st)
 {
     const int32_t n_tiles = (n_band + kTilePoints - 1) / kTilePoints;
-    hipLaunchKernelGGL(accum_f64_kernel, dim3((unsigned)((int64_t)n_tiles * n_cells)),
-                       dim3(kAccumThreads), 0, st, L, g, cc, cs, ranges, n_cells, n_species, k_first,
-                       n_band, n_tiles, ct, eta, kappa);
-    return hipGetLastError();
+    const int64_t n_blocks = (int64_t)n_tiles * n_cells;
+    if (n_blocks > (int64_t)UINT32_MAX) return hipErrorInvalidConfiguration;
+    for (int64_t b0 = 0; b0 < n_blocks; b0 += kMaxLaunchBlocks) {
+        hipLaunchKernelGGL(accum_f64_kernel, dim3((unsigned)std::min(kMaxLaunchBlocks, n_blocks - b0)),
+                           dim3(kAccumThreads), 0, st, L, g, cc, cs, ranges, n_cells, n_species, k_first,
+                           n_band, n_tiles, (uint32_t)b0, ct, eta, kappa);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_count(const DevLines &L, const DevGrid &g, const CellConst *cc,

@@ -43,6 +43,12 @@ constexpr int kStage = kAccumThreads;
 
 // March tile: 256 threads x 4 points.
 constexpr int kMarchThreads = 256;
+
+// Workgroups per launch of a kernel whose grid can be large (the accumulation
+// over cells x tiles, the march over rays x chunks): a dispatch counts at most
+// 2^32 - 1 work-items, so such grids go in launches of 2^23 workgroups of 256
+// (a multiple of the 8 XCDs, so every launch starts on XCD 0 as one launch would).
+constexpr int64_t kMaxLaunchBlocks = int64_t(1) << 23;
 #ifndef LRT_MARCH_PPT
 #define LRT_MARCH_PPT 4
 #endif

@@ -4,7 +4,9 @@
 // deterministic sums of per-block partials and of ray fluxes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <type_traits>
 
 #include "lrt_device.h"
@@ -108,25 +110,25 @@ __device__ __forceinline__ void load_row(const T *eta, const T *kap, int64_t row
 // axisymmetric case) come from that XCD's L2.  Measured against ray-fastest
 // items with a contiguous ray range per XCD: 8.6 vs 11.2 ms on the 17 slab
 // rays of the stagnation line, 100.6 vs 107.5 ms on 8192 axisymmetric rays.
-// A bijection of [0, n_rays n_chunks) for any sizes.
-__device__ __forceinline__ void march_item(int32_t n_rays, int32_t n_chunks, int &ray, int &chunk)
+// A bijection of [0, n_rays n_chunks) for any sizes; b is the workgroup's
+// index in the whole grid (launch offset b0 + blockIdx.x).
+__device__ __forceinline__ void march_item(uint32_t b, int32_t n_rays, int32_t n_chunks, int &ray, int &chunk)
 {
-    const int b = blockIdx.x;
-    const int n = n_rays * n_chunks, x = b % kXCDs, i = b / kXCDs;
-    const int per = n / kXCDs, rem = n % kXCDs;
-    const int gi = x * per + min(x, rem) + i;
-    chunk = gi / n_rays;
-    ray = gi % n_rays;
+    const uint32_t n = (uint32_t)n_rays * (uint32_t)n_chunks, x = b % kXCDs, i = b / kXCDs;
+    const uint32_t per = n / kXCDs, rem = n % kXCDs;
+    const uint32_t gi = x * per + min(x, rem) + i;
+    chunk = (int)(gi / (uint32_t)n_rays);
+    ray = (int)(gi % (uint32_t)n_rays);
 }
 
 template <bool FP32, bool LINEAR>
 __global__ __launch_bounds__(kMarchThreads) void march_kernel(
     DevRays rays, DevGrid g, int32_t k_first, int32_t n_band, const void *eta_v,
     const void *kappa_v, const int32_t *escale, const double *T_far, double *I_out,
-    double *partials, int32_t n_chunks, int32_t aligned16)
+    double *partials, int32_t n_chunks, int32_t aligned16, uint32_t b0)
 {
     int ray, chunk;
-    march_item(rays.n_rays, n_chunks, ray, chunk);
+    march_item(b0 + blockIdx.x, rays.n_rays, n_chunks, ray, chunk);
     const int32_t kb = chunk * kMarchPoints + threadIdx.x * kMarchPPT;   // band-relative
     const int64_t m0 = rays.off[ray], m1 = rays.off[ray + 1];
     double I[kMarchPPT];
@@ -280,18 +282,24 @@ hipError_t launch_march(bool fp32, bool linear, const DevRays &rays, const DevGr
                         double *partials, int32_t n_chunks, hipStream_t st)
 {
     if (rays.n_rays == 0) return hipSuccess;
-    dim3 grid((unsigned)((int64_t)rays.n_rays * n_chunks));
+    const int64_t n_blocks = (int64_t)rays.n_rays * n_chunks;
+    if (n_blocks > (int64_t)UINT32_MAX) return hipErrorInvalidConfiguration;
     const int32_t al = ((((uintptr_t)eta) | ((uintptr_t)kappa)) & 15) == 0;
+    for (int64_t b0 = 0; b0 < n_blocks; b0 += kMaxLaunchBlocks) {
+        const dim3 grid((unsigned)std::min(kMaxLaunchBlocks, n_blocks - b0));
 #define LRT_MARCH(F, LIN)                                                                          \
     hipLaunchKernelGGL((march_kernel<F, LIN>), grid, dim3(kMarchThreads), 0, st, rays, g, k_first, \
-                       n_band, eta, kappa, escale, T_far, I_out, partials, n_chunks, al)
-    if (fp32) {
-        if (linear) LRT_MARCH(true, true); else LRT_MARCH(true, false);
-    } else {
-        if (linear) LRT_MARCH(false, true); else LRT_MARCH(false, false);
-    }
+                       n_band, eta, kappa, escale, T_far, I_out, partials, n_chunks, al, (uint32_t)b0)
+        if (fp32) {
+            if (linear) LRT_MARCH(true, true); else LRT_MARCH(true, false);
+        } else {
+            if (linear) LRT_MARCH(false, true); else LRT_MARCH(false, false);
+        }
 #undef LRT_MARCH
-    return hipGetLastError();
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_reduce_rows(const double *partials, int32_t n_rows, int32_t n_cols, double *out,

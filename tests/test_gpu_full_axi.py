@@ -159,3 +159,60 @@ def test_axisymmetric_large_full_size(torch_dev):
     wl = synth.config_axi_large()
     wl = dataclasses.replace(wl, grid=dataclasses.replace(wl.grid, band_points=8192))
     check_config(wl, 300, 8, 16, "large axisymmetric", torch_dev, march_points=16)
+
+
+def test_axisymmetric_large_own_bands(torch_dev):
+    """The 512 x 256-cell case at its own 131,072-point bands, in single
+    precision (its FP64 eta / kappa of one such band would need 275 GB).
+    Those grids exceed one dispatch's work-item count: 33.5M accumulation
+    workgroups and 16.8M march workgroups go in several launches each.
+    Checked: eta / kappa at 48 cells x sampled points against the oracle, and
+    every ray's band integral against the sum of the same points computed as
+    16 bands of 8,192 points (one launch each; that path is checked against
+    the oracle above)."""
+    torch = torch_dev
+    wl = synth.config_axi_large()
+    band = 16
+    rng = np.random.Generator(np.random.PCG64(5))
+    ctx = lrt.Context(0).load(wl)
+    sz = ctx.sizes()
+    nb = ctx.band_len(band)
+    k0 = band * wl.grid.band_points
+    assert nb == 131072
+    assert sz["n_cells"] * (nb // 512) > 2 ** 23 and sz["n_rays"] * (nb // 1024) > 2 ** 23
+    say("large case, own bands: %d cells, %d rays, band %d = [%d, %d)"
+        % (sz["n_cells"], sz["n_rays"], band, k0, k0 + nb))
+    cs = np.sort(rng.choice(wl.cells.n, 48, replace=False))
+    ks = band_points(rng, k0, nb, 8)
+    sub = subset_cells(wl.cells, cs)
+    e_ref, k_ref, _ = O.coeffs(wl.species, wl.lines, sub, wl.grid, ks)
+    m_ref = knife_mask(wl, sub, ks)
+    eta, kap, esc = ctx.coeffs_torch(band, lrt.LRT_FP32_COMP)
+    ct = torch.as_tensor(cs, device="cuda:0")
+    kt = torch.as_tensor(ks - k0, device="cuda:0")
+    e, k = lrt.scaled_to_f64(eta[ct][:, kt], kap[ct][:, kt], esc[ct])
+    ee, ek = normwise(e, e_ref, m_ref), normwise(k, k_ref, m_ref)
+    say("  eta %.3e kappa %.3e at %d cells x %d points (knife edges %d)"
+        % (ee, ek, cs.size, ks.size, int(m_ref.sum())))
+    assert ee <= 1e-5 and ek <= 1e-5
+    I_int = torch.empty((sz["n_rays"],), dtype=torch.float64, device="cuda:0")
+    ctx.march(band, lrt.LRT_FP32_COMP, eta, kap, esc, None, I_int)
+    big = I_int.cpu().numpy()
+    del eta, kap, esc, I_int
+    torch.cuda.empty_cache()
+    ctx.close()
+
+    wl2 = dataclasses.replace(wl, grid=dataclasses.replace(wl.grid, band_points=8192))
+    ctx2 = lrt.Context(0).load(wl2)
+    acc = np.zeros(sz["n_rays"])
+    for b in range(k0 // 8192, (k0 + nb) // 8192):
+        eta, kap, esc = ctx2.coeffs_torch(b, lrt.LRT_FP32_COMP)
+        Ii = torch.empty((sz["n_rays"],), dtype=torch.float64, device="cuda:0")
+        ctx2.march(b, lrt.LRT_FP32_COMP, eta, kap, esc, None, Ii)
+        acc += Ii.cpu().numpy()
+        del eta, kap, esc, Ii
+    torch.cuda.empty_cache()
+    ctx2.close()
+    rel = float(np.max(np.abs(big - acc)) / np.max(np.abs(acc)))
+    say("  band integral of %d rays: one 131,072-point band vs 16 x 8,192: %.3e" % (big.size, rel))
+    assert np.all(np.isfinite(big)) and np.max(acc) > 0 and rel <= 1e-5
