@@ -379,6 +379,8 @@ lrt_status lrt_get_ray(const lrt_ctx *ctx, int64_t r, int64_t cap, int32_t *cell
  * LRT_FP32_COMP, escale (device, [n_cells][2] int32) receives per cell the
  * power-of-two scale of eta and of kappa: value = stored * 2^escale (0 when
  * the cell is representable unscaled); escale may be NULL for LRT_FP64.
+ * Large grids are launched in pieces; the band's 512-point tiles times the
+ * cells must stay below 2^32 (LRT_E_DEVICE otherwise).
  * Stream-ordered.  Errors: LRT_E_STATE (species, lines, grid or cells
  * missing), LRT_E_ARG (band out of range, NULL buffer, unknown precision). */
 lrt_status lrt_coeffs(lrt_ctx *ctx, int64_t band, lrt_precision prec, void *eta, void *kappa,
@@ -392,6 +394,8 @@ lrt_status lrt_coeffs(lrt_ctx *ctx, int64_t band, lrt_precision prec, void *eta,
  * tau = kappa ds, F(t) = (1 - e^-t)/t, F(0) = 1.  I_out (device, [n_rays][band_len] doubles) receives the wall
  * intensity, or pass NULL; I_int_out (device, [n_rays] doubles) receives the
  * band's trapezoid sum with global-index weights (h/2 at grid ends, h inside).
+ * The rays times the band's 1024-point chunks must stay below 2^32
+ * (LRT_E_DEVICE otherwise).
  * Stream-ordered.  Errors: LRT_E_STATE (no rays, cells/rays mismatch),
  * LRT_E_ARG. */
 lrt_status lrt_march(lrt_ctx *ctx, int64_t band, lrt_precision prec, const void *eta,
