@@ -471,7 +471,8 @@ __device__ __forceinline__ uint32_t slice_modes(int32_t klo, int32_t khi, int32_
 }
 
 struct __align__(16) RecF64 {
-    int32_t klo, khi, k0, pad;
+    int32_t klo, khi, k0;
+    uint32_t mode;          // slice masks: in, edge, x^2.25 window, Gaussian window
     double frac0, inv2g, r, se, sk, pad2;
 };
 
@@ -792,6 +793,60 @@ void accum_f32_kernel(
     }
 }
 
+// Windows of the double-precision exponentials, in units of gamma_V: beyond
+// |dnu| = 33 gamma_V (x = 16.5) e^{-2.772 x^2} is exactly zero in double
+// precision, beyond 57 gamma_V (x = 28.5) so is e^{-0.4 x^2.25}; the point
+// windows carry one point of margin on each side.
+constexpr double kF64GaussHalfWidth = 33.0;
+constexpr double kF64WexpHalfWidth = 57.0;
+
+// Order in which the double-precision kernel walks the staged lines:
+//   0: every staged line on every wave, each lane testing its own point
+//      against the window
+//   1: as the single-precision kernel: slice masks at staging, one ballot per
+//      (slice, flag) per block of 64 lines, groups of 8 lines, and the
+//      exponentials by wave-uniform slice windows (bitwise the same sums)
+#ifndef LRT_F64_WALK
+#define LRT_F64_WALK 1
+#endif
+
+// The terms of one staged line (bit t of the block masks) on this wave's
+// slices of points kk[j], added to the sums.
+template <typename Mask>
+__device__ __forceinline__ void line_terms_f64(const RecF64 &qr, int t, const int32_t (&kk)[kPPL], double h,
+                                               const Mask (&m_in)[kPPL], const Mask (&m_w)[kPPL],
+                                               const Mask (&m_g)[kPPL], const Mask (&m_edge)[kPPL],
+                                               double (&se)[kPPL], double (&sk)[kPPL])
+{
+    const RecF64 q = qr;
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        if (!((m_in[j] >> t) & 1u)) continue;
+        const double x = fabs(fma((double)(kk[j] - q.k0), h, -q.frac0)) * q.inv2g;
+        const double u = x * x;
+        const double p = u * (x > 0.0 ? sqrt_newton(sqrt_newton(x)) : 0.0);
+        const double d1 = 1.0 + 4.0 * u, d2 = 1.0 + 0.1 * p;
+        const double w = 0.016 * q.r * (1.0 - q.r);
+        double P = (q.r * d2 - w * d1) / (d1 * d2);
+        // exponentials by slice window (a lane beyond its term's bound adds an
+        // exact zero, as the lane-wise form skips it)
+        if ((m_g[j] >> t) & 1u) {
+            asm volatile("");
+            P += (1.0 - q.r) * exp(-2.772 * u);
+        }
+        if ((m_w[j] >> t) & 1u) {
+            asm volatile("");
+            P += w * exp(-0.4 * p);
+        }
+        if ((m_edge[j] >> t) & 1u) {
+            asm volatile("");
+            P = (kk[j] >= q.klo && kk[j] <= q.khi) ? P : 0.0;
+        }
+        se[j] += q.se * P;
+        sk[j] += q.sk * P;
+    }
+}
+
 __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
     DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int2 *ranges,
     int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles,
@@ -800,7 +855,7 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
     __shared__ RecF64 rec[kStage];
     int tile, c;
     block_tile_cell(b0 + blockIdx.x, (uint32_t)n_tiles * (uint32_t)n_cells, n_cells, n_tiles, tile, c);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
     const int32_t kt = k_first + tile * kTilePoints;
     const int32_t kw = kt + wave * 64 * kPPL;
     const int32_t kend = k_first + n_band;
@@ -812,7 +867,14 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
     double se[kPPL], sk[kPPL];
 #pragma unroll
     for (int j = 0; j < kPPL; ++j) se[j] = sk[j] = 0.0;
+#if LRT_F64_WALK == 0
     const int32_t kw_last = kw + 64 * kPPL - 1;
+#else
+    const uint32_t wshift = (uint32_t)(wave * kPPL);
+    int32_t kk[kPPL];
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) kk[j] = kw + 64 * j + lane;
+#endif
 
     for (int base = rg.x; base < rg.y; base += kStage) {
         const int64_t i = (int64_t)base + threadIdx.x;
@@ -820,7 +882,7 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
         rr.klo = 1;
         rr.khi = 0;
         rr.k0 = 0;
-        rr.pad = 0;
+        rr.mode = 0;
         rr.frac0 = rr.inv2g = rr.r = rr.se = rr.sk = rr.pad2 = 0.0;
         if (i < rg.y) {
             PairF64 p;
@@ -833,11 +895,24 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
                 rr.r = p.r;
                 rr.se = p.se;
                 rr.sk = p.sk;
+#if LRT_F64_WALK != 0
+                // windows of the two exponentials, one point of margin each side
+                const double nu0 = L.nu0[i], gV = 0.5 / p.inv2g;
+                const double wg = kF64GaussHalfWidth * gV, ww = kF64WexpHalfWidth * gV;
+                const int32_t glo = (int32_t)fmax(ceil((nu0 - wg - g.nu_min) * g.inv_h) - 1.0, (double)p.klo);
+                const int32_t ghi = (int32_t)fmin(floor((nu0 + wg - g.nu_min) * g.inv_h) + 1.0, (double)p.khi);
+                const int32_t wlo = (int32_t)fmax(ceil((nu0 - ww - g.nu_min) * g.inv_h) - 1.0, (double)p.klo);
+                const int32_t whi = (int32_t)fmin(floor((nu0 + ww - g.nu_min) * g.inv_h) + 1.0, (double)p.khi);
+                const uint32_t m = slice_modes(p.klo - kt, p.khi - kt, wlo - kt, whi - kt);
+                const uint32_t gm = slice_run(max(glo, p.klo) - kt, min(ghi, p.khi) - kt) & m & 0xffu;
+                rr.mode = m | (gm << 24);
+#endif
             }
         }
         rec[threadIdx.x] = rr;
         __syncthreads();
         const int n = min(kStage, rg.y - base);
+#if LRT_F64_WALK == 0
         for (int l = 0; l < n; ++l) {
             const RecF64 q = rec[l];
             if (q.khi < kw || q.klo > kw_last) continue;
@@ -855,16 +930,49 @@ __global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
                 }
             }
         }
+#else
+        for (int l0 = 0; l0 < n; l0 += kBlock) {
+            uint32_t mb = 0;
+            if (lane < kBlock && l0 + lane < n) mb = rec[l0 + lane].mode >> wshift;
+            const BlockMask todo = (BlockMask)__ballot((mb & ((1u << kPPL) - 1u)) != 0);
+            BlockMask m_in[kPPL], m_edge[kPPL], m_w[kPPL], m_g[kPPL];
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                m_in[j] = (BlockMask)__ballot(mb & (1u << j));
+                m_edge[j] = (BlockMask)__ballot(mb & (1u << (8 + j)));
+                m_w[j] = (BlockMask)__ballot(mb & (1u << (16 + j)));
+                m_g[j] = (BlockMask)__ballot(mb & (1u << (24 + j)));
+            }
+            for (int g8 = 0; g8 < kBlock; g8 += 8) {
+                const uint32_t gt = (uint32_t)(todo >> g8) & 0xffu;
+                if (gt == 0) continue;
+                uint32_t gi[kPPL], gw[kPPL], gg[kPPL], ge[kPPL];
+#pragma unroll
+                for (int j = 0; j < kPPL; ++j) {
+                    gi[j] = (uint32_t)(m_in[j] >> g8);
+                    gw[j] = (uint32_t)(m_w[j] >> g8);
+                    gg[j] = (uint32_t)(m_g[j] >> g8);
+                    ge[j] = (uint32_t)(m_edge[j] >> g8);
+                }
+                uint32_t off = (uint32_t)((l0 + g8) * (int)sizeof(RecF64));
+                asm volatile("" : "+v"(off));
+                const RecF64 *rg8 = (const RecF64 *)((const char *)rec + off);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if ((gt >> u) & 1u) line_terms_f64(rg8[u], u, kk, g.h, gi, gw, gg, ge, se, sk);
+            }
+        }
+#endif
         __syncthreads();
     }
 #pragma unroll
     for (int j = 0; j < kPPL; ++j) {
-        const int32_t kk = kw + 64 * j + lane;
-        if (kk < kend) {
-            const int64_t o = (int64_t)c * n_band + (kk - k_first);
+        const int32_t kq = kw + 64 * j + lane;
+        if (kq < kend) {
+            const int64_t o = (int64_t)c * n_band + (kq - k_first);
             if (ct.n_thr >= 0) {   // atomic continuum
                 double ce, ck;
-                continuum_point(ct, c, g.nu_min + (double)kk * g.h, ce, ck);
+                continuum_point(ct, c, g.nu_min + (double)kq * g.h, ce, ck);
                 se[j] += ce;
                 sk[j] += ck;
             }
