@@ -847,7 +847,13 @@ __device__ __forceinline__ void line_terms_f64(const RecF64 &qr, int t, const in
     }
 }
 
-__global__ __launch_bounds__(kAccumThreads) void accum_f64_kernel(
+// Waves per SIMD the double-precision kernel is compiled for (its register
+// budget 512 / waves per lane): measured on the stagnation line, 4 (no limit,
+// 120 registers) 4.88 s, 6 4.65 s, 8 4.79 s per launch.
+#ifndef LRT_F64_WAVES
+#define LRT_F64_WAVES 6
+#endif
+__global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(LRT_F64_WAVES))) void accum_f64_kernel(
     DevLines L, DevGrid g, const CellConst *cc, const CellSpecies *cs, const int2 *ranges,
     int32_t n_cells, int32_t n_species, int32_t k_first, int32_t n_band, int32_t n_tiles,
     uint32_t b0, DevCont ct, double *eta, double *kappa)
