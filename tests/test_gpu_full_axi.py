@@ -216,3 +216,50 @@ def test_axisymmetric_large_own_bands(torch_dev):
     rel = float(np.max(np.abs(big - acc)) / np.max(np.abs(acc)))
     say("  band integral of %d rays: one 131,072-point band vs 16 x 8,192: %.3e" % (big.size, rel))
     assert np.all(np.isfinite(big)) and np.max(acc) > 0 and rel <= 1e-5
+
+
+def test_axisymmetric_large_fp64_band(torch_dev):
+    """The 512 x 256-cell case in double precision at 65,536-point bands (the
+    band size at which its FP64 eta / kappa fit HBM, 137 GB; 16.8M
+    accumulation workgroups, two launches): eta / kappa at 48 cells x sampled
+    points against the oracle within 1e-12, and every ray's band integral
+    against the single-precision form of the same band within 1e-5."""
+    torch = torch_dev
+    wl = synth.config_axi_large()
+    wl = dataclasses.replace(wl, grid=dataclasses.replace(wl.grid, band_points=65536))
+    band = 32
+    rng = np.random.Generator(np.random.PCG64(9))
+    ctx = lrt.Context(0).load(wl)
+    sz = ctx.sizes()
+    nb = ctx.band_len(band)
+    k0 = band * wl.grid.band_points
+    assert nb == 65536 and sz["n_cells"] * (nb // 512) > 2 ** 23
+    say("large case, FP64 at 65,536-point bands: band %d = [%d, %d)" % (band, k0, k0 + nb))
+    cs = np.sort(rng.choice(wl.cells.n, 48, replace=False))
+    ks = band_points(rng, k0, nb, 8)
+    sub = subset_cells(wl.cells, cs)
+    e_ref, k_ref, _ = O.coeffs(wl.species, wl.lines, sub, wl.grid, ks)
+    m_ref = knife_mask(wl, sub, ks)
+    ct = torch.as_tensor(cs, device="cuda:0")
+    kt = torch.as_tensor(ks - k0, device="cuda:0")
+    I_int = {}
+    for prec in (lrt.LRT_FP64, lrt.LRT_FP32_COMP):
+        eta, kap, esc = ctx.coeffs_torch(band, prec)
+        if prec == lrt.LRT_FP64:
+            e, k = eta[ct][:, kt].cpu().numpy(), kap[ct][:, kt].cpu().numpy()
+        else:
+            e, k = lrt.scaled_to_f64(eta[ct][:, kt], kap[ct][:, kt], esc[ct])
+        ee, ek = normwise(e, e_ref, m_ref), normwise(k, k_ref, m_ref)
+        Ii = torch.empty((sz["n_rays"],), dtype=torch.float64, device="cuda:0")
+        ctx.march(band, prec, eta, kap, esc if prec == lrt.LRT_FP32_COMP else None, None, Ii)
+        I_int[prec] = Ii.cpu().numpy()
+        say("  prec %d: eta %.3e kappa %.3e at %d cells x %d points (knife edges %d)"
+            % (prec, ee, ek, cs.size, ks.size, int(m_ref.sum())))
+        assert ee <= TOL[prec] and ek <= TOL[prec]
+        del eta, kap, esc, Ii
+        torch.cuda.empty_cache()
+    ctx.close()
+    a, b = I_int[lrt.LRT_FP32_COMP], I_int[lrt.LRT_FP64]
+    rel = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    say("  band integral of %d rays, FP32-comp vs FP64: %.3e" % (b.size, rel))
+    assert np.all(np.isfinite(b)) and np.max(b) > 0 and rel <= 1e-5
