@@ -452,7 +452,9 @@ typedef struct lrt_server lrt_server;
  * (free) boundary to the observer with path length ds[c] (cm), cell states as
  * in lrt_cells (host pointers, copied at submit), a window of n_window grid
  * points starting at k_first on the context's resident grid, and the species
- * that radiate (bit s of species_mask; 0 = every species with lines).
+ * that radiate (bit s of species_mask; 0 = every species): lines of a species
+ * outside the mask, and the atomic continuum of an atom outside it, are left
+ * out.
  * keep_spectrum != 0 keeps I over the window for lrt_poll / lrt_wait. */
 typedef struct {
     int64_t n_cells;
@@ -482,7 +484,9 @@ typedef struct {
  * time.  Each request is computed by fused kernels (populations, setups,
  * accumulation and march per spectral tile and chunk of cells, then the
  * chunks composed in order), single-precision compensated profile sums, FP64
- * march state and quadrature; no eta/kappa array is stored.  Errors:
+ * march state and quadrature; no eta/kappa array is stored.  The context's
+ * Lorentz model and atomic continuum (lrt_set_lorentz, lrt_set_continuum)
+ * apply; QSS-CR populations and the march variants do not.  Errors:
  * LRT_E_ARG (max_slots < 1, budget < 1 MiB), LRT_E_STATE (missing set_*),
  * LRT_E_OOM, LRT_E_DEVICE. */
 lrt_status lrt_server_start(lrt_ctx *ctx, size_t hbm_budget_bytes, int max_slots, lrt_server **out);

@@ -90,7 +90,7 @@ __global__ void thermo_kernel(DevSpecies sp, DevCells cells, DevWidths wd, doubl
     const double N = cells.N[(int64_t)c * S + s];
     CellSpecies o;
     // species outside a non-zero mask carry no lines (bit s of mask)
-    const bool on = mask == 0 || (s < 64 && ((mask >> s) & 1ull));
+    const bool on = species_on(mask, s);
     o.lnNQ = (on && kind != 0 && N > 0.0 && Q > 0.0) ? log(N) - log(Q) : -INFINITY;
     o.dop = 7.16233e-7 / 2.0 * sqrt(Ttr / sp.mass[s]);
     o.gW = (wd.E_ion && kind == 1 && wd.E_ion[s] > 0.0) ? vdw_width(sp, cells, c, s) : 0.0;
@@ -229,7 +229,8 @@ constexpr double kElectronMass = 9.1093837015e-28;   // g
 // for the power-of-two scale.
 __global__ void cont_cells_kernel(const ContThr *thr, int32_t n_thr, const ContRec *rec,
                                   int32_t n_rec, DevCells cells, const CellSpecies *cs, DevCR cr,
-                                  double nu_lo, double nu_hi, double *cum, double *ff, double *lnb)
+                                  uint64_t species_mask, double nu_lo, double nu_hi, double *cum,
+                                  double *ff, double *lnb)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells.n_cells) return;
@@ -244,6 +245,11 @@ __global__ void cont_cells_kernel(const ContThr *thr, int32_t n_thr, const ContR
     for (int j = 0; j < n_thr; ++j) {
         const ContThr t = thr[j];
         const ContRec r = rec[t.rec];
+        if (!species_on(species_mask, r.species)) {   // a species outside the mask radiates nothing
+            cA[j + 1] = a;
+            cB[j + 1] = b;
+            continue;
+        }
         const double Np = cells.N[(int64_t)c * ns + r.ion];
         const int slot = cr.n > 0 ? cr.slot[r.species] : -1;
         // absorption from the level: its QSS-CR population, else Boltzmann
@@ -263,6 +269,7 @@ __global__ void cont_cells_kernel(const ContThr *thr, int32_t n_thr, const ContR
     double f0 = 0.0, f1 = 0.0;
     for (int q = 0; q < n_rec; ++q) {
         const ContRec r = rec[q];
+        if (!species_on(species_mask, r.species)) continue;
         const double w = cells.N[(int64_t)c * ns + r.ion] * ne * 1e-40 * r.z4inv;
         f0 += w * (r.peach[0] + r.peach[1] * exp(-r.peach[2] * T));
         f1 += w * (r.peach[3] + r.peach[4] * exp(-r.peach[5] * T) + r.peach[6] * exp(-r.peach[7] * T));
@@ -417,11 +424,13 @@ __global__ void scale_bound_kernel(DevBins B, const CellConst *cc, const CellSpe
     }
 }
 
-__global__ void scale_finish_kernel(const int32_t *emax, int32_t n, int32_t *escale)
+__global__ void scale_finish_kernel(const int32_t *emax, const double *cont_lnb, int32_t n, int32_t *escale)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    const int e = emax[t];
+    int e = emax[t];
+    if (cont_lnb && cont_lnb[t] > -INFINITY)   // the atomic continuum's own bound: peak < 2^e
+        e = max(e, (int)fmax(-2000.0, fmin(2000.0, ceil(cont_lnb[t] * kLog2e) + 1.0)));
     // keep values unscaled while the largest line peak stays within 2^+-60
     escale[t] = (e == INT_MIN || (e >= -60 && e <= 60)) ? 0 : e;
 }
@@ -1076,6 +1085,16 @@ void serve_kernel(DevLines L, DevGrid g,
             const int ese = R.escale[2 * c + 0], esk = R.escale[2 * c + 1];
             accum_cell_tile_f32(rec, L, g, R.cc[c], R.cs + (int64_t)c * n_species, nullptr, ese, esk,
                                 R.ranges[(int64_t)c * R.n_tiles + w.tile], kt, kw, lane, e, kp);
+            if (R.ct.n_thr >= 0) {
+                // atomic continuum, added in double precision and rounded once
+#pragma unroll
+                for (int j = 0; j < kPPL; ++j) {
+                    double ce, ck;
+                    continuum_point(R.ct, c, g.nu_min + (double)(kt + kw + 64 * j + lane) * g.h, ce, ck);
+                    e[j] = (float)((double)e[j] + ldexp(ce, -ese));
+                    kp[j] = (float)((double)kp[j] + ldexp(ck, -esk));
+                }
+            }
             const double ds = R.ds[c];
             const double dse = ldexp(ds, ese);
             const float dsk = (float)fmin(ldexp(ds, esk), 3.0e38);
@@ -1161,18 +1180,19 @@ hipError_t launch_scale_bound(const DevBins &B, const CellConst *cc, const CellS
 
 hipError_t launch_cont_cells(const ContThr *thr, int32_t n_thr, const ContRec *rec, int32_t n_rec,
                              const DevCells &cells, const CellSpecies *cs, const DevCR &cr,
-                             double nu_lo, double nu_hi, double *cum, double *ff, double *lnb,
-                             hipStream_t st)
+                             uint64_t species_mask, double nu_lo, double nu_hi, double *cum, double *ff,
+                             double *lnb, hipStream_t st)
 {
     if (cells.n_cells == 0) return hipSuccess;
     hipLaunchKernelGGL(cont_cells_kernel, dim3(blocks_for(cells.n_cells, 64)), dim3(64), 0, st, thr,
-                       n_thr, rec, n_rec, cells, cs, cr, nu_lo, nu_hi, cum, ff, lnb);
+                       n_thr, rec, n_rec, cells, cs, cr, species_mask, nu_lo, nu_hi, cum, ff, lnb);
     return hipGetLastError();
 }
 
 hipError_t launch_scale(const DevLines &L, int64_t i0, int64_t i1, const DevGrid &g,
                         const CellConst *cc, const CellSpecies *cs, int32_t n_cells,
-                        int32_t n_species, int32_t *emax, int32_t *escale, hipStream_t st)
+                        int32_t n_species, const double *cont_lnb, int32_t *emax, int32_t *escale,
+                        hipStream_t st)
 {
     // emax must hold INT_MIN on entry (set by a fill kernel of the caller);
     // lines i0 <= i < i1 are scanned
@@ -1181,7 +1201,7 @@ hipError_t launch_scale(const DevLines &L, int64_t i0, int64_t i1, const DevGrid
                            dim3(256), 0, st, L, i0, i1, g, cc, cs, n_cells, n_species, emax);
     }
     hipLaunchKernelGGL(scale_finish_kernel, dim3(blocks_for(2 * n_cells, 256)), dim3(256), 0, st,
-                       emax, 2 * n_cells, escale);
+                       emax, cont_lnb, 2 * n_cells, escale);
     return hipGetLastError();
 }
 

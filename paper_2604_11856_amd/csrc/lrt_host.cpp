@@ -947,7 +947,7 @@ lrt_status prepare(lrt_ctx *c, hipStream_t st, bool need_scale, bool force)
                 (r = ensure(c, c->d_cont_lnb, nc * 2 * sizeof(double))))
                 return r;
             LRT_HIP(c, launch_cont_cells(c->d_cont_thr.as<ContThr>(), c->n_cont_thr, c->d_cont_rec.as<ContRec>(),
-                                         c->n_cont_rec, cells, c->d_cs.as<CellSpecies>(), dev_cr(c),
+                                         c->n_cont_rec, cells, c->d_cs.as<CellSpecies>(), dev_cr(c), 0ull,
                                          c->nu_min, c->nu_max, c->d_cont_cum.as<double>(),
                                          c->d_cont_ff.as<double>(), c->d_cont_lnb.as<double>(), st));
         }

@@ -185,6 +185,12 @@ struct CellConst {
     double cand_G, cand_A;   // line-skip bound: |nu - nu0| <= cand_G + cand_A nu0
 };
 
+// Whether species s radiates under a species mask (bit s; 0: every species).
+__host__ __device__ inline bool species_on(uint64_t mask, int s)
+{
+    return mask == 0 || (s < 64 && ((mask >> s) & 1ull));
+}
+
 // Per (cell, species) constants written by the thermo kernel.
 struct CellSpecies {
     double lnNQ;   // ln(N_s / Q_s), -inf when the species carries no population
@@ -219,6 +225,7 @@ struct ServeReq {
     double *I_out;           // [n_window]
     double *partials;        // [ceil(n_window / 256)]
     double *I_int;           // [1]
+    DevCont ct;              // the request's atomic continuum (n_thr < 0: none)
 };
 
 // One unit of serving work: the cells of one chunk on one tile of a request.
@@ -239,8 +246,8 @@ hipError_t launch_scale_bound(const DevBins &B, const CellConst *cc, const CellS
                               int32_t *escale, hipStream_t st);
 hipError_t launch_cont_cells(const ContThr *thr, int32_t n_thr, const ContRec *rec, int32_t n_rec,
                              const DevCells &cells, const CellSpecies *cs, const DevCR &cr,
-                             double nu_lo, double nu_hi, double *cum, double *ff, double *lnb,
-                             hipStream_t st);
+                             uint64_t species_mask, double nu_lo, double nu_hi, double *cum, double *ff,
+                             double *lnb, hipStream_t st);
 
 // QSS-CR populations of every (cell, atom) (lrt_cr.hip); max_l / max_lev:
 // largest n_model / n_lev over the records.
@@ -248,7 +255,8 @@ hipError_t launch_cr(const DevSpecies &sp, const DevCells &cells, const DevCR &c
                      int32_t max_lev, const CellSpecies *cs, hipStream_t st);
 hipError_t launch_scale(const DevLines &L, int64_t i0, int64_t i1, const DevGrid &g,
                         const CellConst *cc, const CellSpecies *cs, int32_t n_cells,
-                        int32_t n_species, int32_t *emax, int32_t *escale, hipStream_t st);
+                        int32_t n_species, const double *cont_lnb, int32_t *emax, int32_t *escale,
+                        hipStream_t st);
 
 hipError_t launch_accum_f32(const DevLines &L, const DevGrid &g, const CellConst *cc,
                             const CellSpecies *cs, const int32_t *escale, const int2 *ranges,

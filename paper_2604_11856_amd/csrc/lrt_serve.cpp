@@ -125,7 +125,8 @@ struct Epoch {
 
 // Device bytes of one request (inputs, per-cell constants, ranges, chunk
 // transmittance / source, outputs), each sub-buffer 256-byte aligned.
-size_t request_bytes(int64_t nc, int S, int32_t n_window, int32_t &n_tiles, int32_t &n_chunks)
+size_t request_bytes(int64_t nc, int S, int32_t n_window, int32_t n_thr, int32_t &n_tiles,
+                     int32_t &n_chunks)
 {
     n_tiles = (n_window + kTilePoints - 1) / kTilePoints;
     n_chunks = (int32_t)((nc + kChunkCells - 1) / kChunkCells);
@@ -140,6 +141,8 @@ size_t request_bytes(int64_t nc, int S, int32_t n_window, int32_t &n_tiles, int3
     b += align_up((size_t)n_tiles * n_chunks * 2 * kTilePoints * 8);   // T, S
     b += align_up((size_t)n_window * 8);                    // I
     b += align_up(nb * 8) + align_up(8);                    // partials, I_int
+    if (n_thr >= 0)                                         // continuum: cum, ff, lnb
+        b += align_up((size_t)nc * 2 * (n_thr + 1) * 8) + 2 * align_up((size_t)nc * 2 * 8);
     return b;
 }
 
@@ -207,7 +210,8 @@ void lrt_server::release(Req &r)
 bool lrt_server::admit(Req &r)
 {
     const int S = ctx->n_species;
-    const size_t bytes = request_bytes(r.n_cells, S, r.n_window, r.n_tiles, r.n_chunks);
+    const int32_t n_thr = ctx->n_cont_rec > 0 ? ctx->n_cont_thr : -1;
+    const size_t bytes = request_bytes(r.n_cells, S, r.n_window, n_thr, r.n_tiles, r.n_chunks);
     if (free_slots.empty()) return false;
     size_t off;
     if (!arena.alloc(bytes, off)) return false;
@@ -235,6 +239,12 @@ bool lrt_server::admit(Req &r)
     double *I_out = (double *)take((size_t)r.n_window * 8);
     double *partials = (double *)take((size_t)(r.n_window + 255) / 256 * 8);
     double *I_int = (double *)take(8);
+    double *cum = nullptr, *ff = nullptr, *lnb = nullptr;
+    if (n_thr >= 0) {
+        cum = (double *)take((size_t)nc * 2 * (n_thr + 1) * 8);
+        ff = (double *)take((size_t)nc * 2 * 8);
+        lnb = (double *)take((size_t)nc * 2 * 8);
+    }
     hipStream_t st = admit_stream;
     auto ok = [&](hipError_t e, const char *what) {
         if (e != hipSuccess) {
@@ -257,6 +267,17 @@ bool lrt_server::admit(Req &r)
     if (!ok(launch_thermo(ctx->sp, cells, dev_widths(ctx), ctx->M_min, r.mask, cc, cs, st), "thermo") ||
         !ok(launch_ranges(L, g, cc, (int32_t)nc, r.k_first, r.n_window, kTilePoints, ranges, st), "ranges"))
         return true;
+    // the atomic continuum of the species the request lets radiate, over its window
+    DevCont ct{-1, nullptr, nullptr, nullptr, nullptr};
+    if (n_thr >= 0) {
+        const double w_lo = ctx->nu_min + (double)r.k_first * ctx->h;
+        const double w_hi = ctx->nu_min + (double)(r.k_first + r.n_window - 1) * ctx->h;
+        if (!ok(launch_cont_cells(ctx->d_cont_thr.as<ContThr>(), n_thr, ctx->d_cont_rec.as<ContRec>(),
+                                  ctx->n_cont_rec, cells, cs, DevCR{}, r.mask, w_lo, w_hi, cum, ff, lnb, st),
+                "continuum"))
+            return true;
+        ct = DevCont{n_thr, ctx->d_cont_thr.as<ContThr>(), cum, ff, T_v};
+    }
     // lines that can reach the window at all, for the per-cell scale
     double gL_max = 0.0, T_max = 0.0;
     for (int64_t c = 0; c < nc; ++c) {
@@ -271,10 +292,10 @@ bool lrt_server::admit(Req &r)
     const int64_t i0 = std::lower_bound(nu0.begin(), nu0.end(), (nu_a - G) / (1.0 + A)) - nu0.begin();
     const int64_t i1 = std::lower_bound(nu0.begin(), nu0.end(), (nu_b + G) / (1.0 - A)) - nu0.begin();
     if (!ok(launch_fill_i32(emax, INT_MIN, 2 * nc, st), "fill") ||
-        !ok(launch_scale(L, i0, i1, g, cc, cs, (int32_t)nc, S, emax, escale, st), "scale"))
+        !ok(launch_scale(L, i0, i1, g, cc, cs, (int32_t)nc, S, lnb, emax, escale, st), "scale"))
         return true;
     r.dev = ServeReq{(int32_t)nc, r.k_first, r.n_window, r.n_tiles, r.n_chunks, kChunkCells,
-                     cc, cs, escale, ds, ranges, TS, I_out, partials, I_int};
+                     cc, cs, escale, ds, ranges, TS, I_out, partials, I_int, ct};
     if (!ok(hipMemcpyAsync(d_reqs.as<ServeReq>() + r.slot, &r.dev, sizeof(ServeReq),
                            hipMemcpyHostToDevice, st), "upload") ||
         !ok(hipEventCreateWithFlags(&r.prep_ev, hipEventDisableTiming), "event") ||
@@ -500,7 +521,8 @@ lrt_status lrt_submit(lrt_server *s, const lrt_los_request *q, uint64_t *ticket)
                 return fail(nullptr, LRT_E_ARG, "request: cell %lld density %d invalid", (long long)c, sp);
     }
     int32_t nt, nch;
-    const size_t bytes = request_bytes(q->n_cells, S, (int32_t)q->n_window, nt, nch);
+    const int32_t n_thr = ctx->n_cont_rec > 0 ? ctx->n_cont_thr : -1;
+    const size_t bytes = request_bytes(q->n_cells, S, (int32_t)q->n_window, n_thr, nt, nch);
     if (bytes > s->budget)
         return fail(nullptr, LRT_E_BUDGET, "request needs %zu bytes, budget is %zu", bytes, s->budget);
     std::unique_ptr<Req> r(new (std::nothrow) Req());

@@ -4,6 +4,8 @@ Parity bar: the single-precision compensated form within 1e-5 of the FP64
 oracle (spectrum normwise, integral relative).  Each result must be bitwise
 the same alone and in a mix.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -40,9 +42,11 @@ def make_requests(grid, n, seed, max_cells=120, max_win=30000):
                                   min_win=500, max_win=max_win, seed=seed)
 
 
-def oracle_los(wl, req, ks=None):
+def oracle_los(wl, req, ks=None, cont=None):
     """Observer intensity at window points ks (default: the whole window) and,
-    for the whole window, its trapezoid integral (h/2 at both ends)."""
+    for the whole window, its trapezoid integral (h/2 at both ends).  With
+    cont, the atomic continuum of the atoms inside the request's mask is added
+    (their ions at the request's densities)."""
     N = req.cells.N.copy()
     for s in range(N.shape[1]):
         if req.species_mask and not (req.species_mask >> s) & 1:
@@ -52,6 +56,10 @@ def oracle_los(wl, req, ks=None):
     if full:
         ks = np.arange(req.k_first, req.k_first + req.n_window, dtype=np.int64)
     eta, kap, _ = O.coeffs(wl.species, wl.lines, cells, wl.grid, ks)
+    keep = [r for r in (cont or []) if not req.species_mask or (req.species_mask >> r.species) & 1]
+    if keep:
+        ec, kc = O.continuum(wl.species, req.cells, wl.grid, keep, ks)
+        eta, kap = eta + ec, kap + kc
     I = O.march(np.arange(cells.n), req.ds, eta, kap)
     if not full:
         return I, None
@@ -102,6 +110,51 @@ def test_serving_alone_equals_mix_bitwise(resident):
         np.testing.assert_array_equal(a["spectrum"], m["spectrum"])
     say("epochs", srv.info()["epochs"])
     srv.stop()
+
+
+def test_serving_with_atomic_continuum(resident):
+    """The context's atomic continuum (bound-free and free-free of N and O) in
+    every request, for the atoms its mask lets radiate.  The context keeps only
+    the 50 lowest lines, so most windows see the continuum alone: spectra and
+    integrals against the oracle, and bitwise the same alone and in a mix."""
+    wl, _ = resident
+    cont = synth.air_continuum(wl.species)
+    assert cont
+    wl2 = dataclasses.replace(wl, lines=wl.lines.subset(np.arange(50)))
+    ctx = lrt.Context(0)
+    ctx.set_species(wl2.species)
+    ctx.set_lines(wl2.lines)
+    ctx.set_grid(wl2.grid)
+    ctx.set_continuum(cont)
+    reqs = make_requests(wl2.grid, 5, seed=13)
+    top = dataclasses.replace(reqs[0], k_first=wl2.grid.n_points - 12000, n_window=12000, species_mask=0)
+    n_only = dataclasses.replace(top, species_mask=1 << [sp.name for sp in wl2.species].index("N"))
+    reqs += [top, n_only]
+    srv = lrt.Server(ctx, 2 << 30, max_slots=8)
+    alone = []
+    for r in reqs:
+        res = srv.wait(srv.submit(r, keep_spectrum=True), timeout_ms=120000)
+        assert res is not None and res["status"] == 0
+        alone.append(res)
+        I_ref, Iint_ref = oracle_los(wl2, r, cont=cont)
+        if Iint_ref == 0.0:   # nothing radiates in the window (no line, continuum masked)
+            assert res["I_int"] == 0.0 and not np.any(res["spectrum"])
+            say("cells %4d window %6d mask %#x: nothing radiates, result zero"
+                % (r.cells.n, r.n_window, r.species_mask))
+            continue
+        _, Iint_lines = oracle_los(wl2, r)
+        e_spec = normwise(res["spectrum"], I_ref)
+        e_int = abs(res["I_int"] - Iint_ref) / abs(Iint_ref)
+        say("cells %4d window %6d mask %#x: spectrum %.2e integral %.2e (continuum share %.3f)"
+            % (r.cells.n, r.n_window, r.species_mask, e_spec, e_int, 1.0 - Iint_lines / Iint_ref))
+        assert e_spec <= TOL and e_int <= TOL
+    tickets = [srv.submit(r, keep_spectrum=True) for r in reqs]
+    for a, t in zip(alone, tickets):
+        m = srv.wait(t, timeout_ms=120000)
+        assert m["status"] == 0 and a["I_int"] == m["I_int"]
+        np.testing.assert_array_equal(a["spectrum"], m["spectrum"])
+    srv.stop()
+    ctx.close()
 
 
 def test_serving_budget_cancel_and_invalid(resident):
