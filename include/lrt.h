@@ -455,7 +455,10 @@ typedef struct lrt_server lrt_server;
  * that radiate (bit s of species_mask; 0 = every species): lines of a species
  * outside the mask, and the atomic continuum of an atom outside it, are left
  * out.
- * keep_spectrum != 0 keeps I over the window for lrt_poll / lrt_wait. */
+ * keep_spectrum != 0 keeps I over the window for lrt_poll / lrt_wait.  T_far
+ * (K) is the temperature of a solid far boundary whose blackbody intensity
+ * B(nu, T_far) starts the march (Sec. 2.2.3 boundary intensity); 0: a free
+ * boundary (intensity 0). */
 typedef struct {
     int64_t n_cells;
     int n_species;
@@ -463,6 +466,7 @@ typedef struct {
     int64_t k_first, n_window;
     uint64_t species_mask;
     int keep_spectrum;
+    double T_far;
 } lrt_los_request;
 
 /* Result of one request: status (LRT_OK, or the error that ended it;
@@ -493,7 +497,7 @@ lrt_status lrt_server_start(lrt_ctx *ctx, size_t hbm_budget_bytes, int max_slots
 
 /* Copy a request in and queue it; never waits for the GPU.  *ticket receives
  * its handle.  Errors: LRT_E_ARG (invalid cells, ds <= 0, window outside the
- * grid, species count), LRT_E_BUDGET (the request could never fit the budget),
+ * grid, species count, T_far < 0 or non-finite), LRT_E_BUDGET (the request could never fit the budget),
  * LRT_E_STATE (server stopping), LRT_E_DEVICE (server failed). */
 lrt_status lrt_submit(lrt_server *s, const lrt_los_request *req, uint64_t *ticket);
 

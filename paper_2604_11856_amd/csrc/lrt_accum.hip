@@ -1124,7 +1124,8 @@ __global__ __launch_bounds__(256) void serve_combine_kernel(ServeReq R, DevGrid 
     double part = 0.0;
     if (t < R.n_window) {
         const int32_t tile = t / kTilePoints, loc = t % kTilePoints;
-        double I = 0.0;
+        // a solid far boundary starts the march at its blackbody intensity
+        double I = R.T_far > 0.0 ? planck_f64(g.nu_min + (double)(R.k_first + t) * g.h, R.T_far) : 0.0;
         for (int32_t m = 0; m < R.n_chunks; ++m) {
             const double *ts = R.TS + ((int64_t)tile * R.n_chunks + m) * 2 * kTilePoints;
             I = fma(I, ts[loc], ts[kTilePoints + loc]);

@@ -226,6 +226,7 @@ struct ServeReq {
     double *partials;        // [ceil(n_window / 256)]
     double *I_int;           // [1]
     DevCont ct;              // the request's atomic continuum (n_thr < 0: none)
+    double T_far;            // solid far boundary temperature (0: free)
 };
 
 // One unit of serving work: the cells of one chunk on one tile of a request.

@@ -42,11 +42,12 @@ def make_requests(grid, n, seed, max_cells=120, max_win=30000):
                                   min_win=500, max_win=max_win, seed=seed)
 
 
-def oracle_los(wl, req, ks=None, cont=None):
+def oracle_los(wl, req, ks=None, cont=None, T_far=0.0):
     """Observer intensity at window points ks (default: the whole window) and,
     for the whole window, its trapezoid integral (h/2 at both ends).  With
     cont, the atomic continuum of the atoms inside the request's mask is added
-    (their ions at the request's densities)."""
+    (their ions at the request's densities).  T_far > 0: a solid far boundary
+    whose blackbody intensity starts the march."""
     N = req.cells.N.copy()
     for s in range(N.shape[1]):
         if req.species_mask and not (req.species_mask >> s) & 1:
@@ -60,7 +61,8 @@ def oracle_los(wl, req, ks=None, cont=None):
     if keep:
         ec, kc = O.continuum(wl.species, req.cells, wl.grid, keep, ks)
         eta, kap = eta + ec, kap + kc
-    I = O.march(np.arange(cells.n), req.ds, eta, kap)
+    I_far = O.planck_spectrum(wl.grid, ks, T_far) if T_far > 0.0 else None
+    I = O.march(np.arange(cells.n), req.ds, eta, kap, I_far)
     if not full:
         return I, None
     h = O.grid_step(wl.grid)
@@ -155,6 +157,31 @@ def test_serving_with_atomic_continuum(resident):
         np.testing.assert_array_equal(a["spectrum"], m["spectrum"])
     srv.stop()
     ctx.close()
+
+
+def test_serving_far_boundary(resident):
+    """Requests whose line of sight ends on a solid far boundary: the march
+    starts from B(nu, T_far) (Sec. 2.2.3 boundary intensity); spectra and
+    integrals against the oracle, the same request without it unchanged, and a
+    negative T_far refused."""
+    wl, ctx = resident
+    reqs = make_requests(wl.grid, 4, seed=21)
+    srv = lrt.Server(ctx, 2 << 30, max_slots=8)
+    for r, T_far in zip(reqs, (2500.0, 6000.0, 9000.0, 15000.0)):
+        res = srv.wait(srv.submit(r, keep_spectrum=True, T_far=T_far), timeout_ms=120000)
+        free = srv.wait(srv.submit(r, keep_spectrum=True), timeout_ms=120000)
+        assert res["status"] == 0 and free["status"] == 0
+        I_ref, Iint_ref = oracle_los(wl, r, T_far=T_far)
+        I_free, Iint_free = oracle_los(wl, r)
+        e_spec = normwise(res["spectrum"], I_ref)
+        e_int = abs(res["I_int"] - Iint_ref) / abs(Iint_ref)
+        say("cells %4d window %6d T_far %6.0f: spectrum %.2e integral %.2e (wall share %.3f)"
+            % (r.cells.n, r.n_window, T_far, e_spec, e_int, 1.0 - Iint_free / Iint_ref))
+        assert e_spec <= TOL and e_int <= TOL
+        assert abs(free["I_int"] - Iint_free) <= TOL * abs(Iint_free)
+    with pytest.raises(lrt.LrtError):
+        srv.submit(reqs[0], T_far=-1.0)
+    srv.stop()
 
 
 def test_serving_budget_cancel_and_invalid(resident):
