@@ -458,7 +458,10 @@ typedef struct lrt_server lrt_server;
  * keep_spectrum != 0 keeps I over the window for lrt_poll / lrt_wait.  T_far
  * (K) is the temperature of a solid far boundary whose blackbody intensity
  * B(nu, T_far) starts the march (Sec. 2.2.3 boundary intensity); 0: a free
- * boundary (intensity 0). */
+ * boundary (intensity 0).  scheme: the segment scheme of the march
+ * (lrt_march_scheme: LRT_MARCH_CELL or LRT_MARCH_LINEAR_J, as lrt_set_march
+ * describes; the linear-j nodes are the far end, the cell midpoints and the
+ * observer). */
 typedef struct {
     int64_t n_cells;
     int n_species;
@@ -467,6 +470,7 @@ typedef struct {
     uint64_t species_mask;
     int keep_spectrum;
     double T_far;
+    int scheme;
 } lrt_los_request;
 
 /* Result of one request: status (LRT_OK, or the error that ended it;
@@ -491,14 +495,14 @@ typedef struct {
  * march state and quadrature; no eta/kappa array is stored.  The context's
  * Lorentz model and atomic continuum (lrt_set_lorentz, lrt_set_continuum)
  * apply; QSS-CR populations, lrt_set_march and lrt_set_far_temperature do not
- * (a request carries its own far boundary, T_far).  Errors:
+ * (a request carries its own far boundary and segment scheme).  Errors:
  * LRT_E_ARG (max_slots < 1, budget < 1 MiB), LRT_E_STATE (missing set_*),
  * LRT_E_OOM, LRT_E_DEVICE. */
 lrt_status lrt_server_start(lrt_ctx *ctx, size_t hbm_budget_bytes, int max_slots, lrt_server **out);
 
 /* Copy a request in and queue it; never waits for the GPU.  *ticket receives
  * its handle.  Errors: LRT_E_ARG (invalid cells, ds <= 0, window outside the
- * grid, species count, T_far < 0 or non-finite), LRT_E_BUDGET (the request could never fit the budget),
+ * grid, species count, T_far < 0 or non-finite, unknown scheme), LRT_E_BUDGET (the request could never fit the budget),
  * LRT_E_STATE (server stopping), LRT_E_DEVICE (server failed). */
 lrt_status lrt_submit(lrt_server *s, const lrt_los_request *req, uint64_t *ticket);
 

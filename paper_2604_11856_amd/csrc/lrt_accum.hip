@@ -1052,6 +1052,27 @@ __global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, int
 // observer in a fixed order.  Nothing depends on what else shares the epoch.
 // ---------------------------------------------------------------------------
 
+// One linear-j segment of length Ls (cm) from far node (fe, fk) to near node
+// ne (scaled single-precision coefficients with their power-of-two scales),
+// composed into the chunk's transmittance T and source S: I <- I e^-t +
+// Ls (wf fe + wn ne), t = fk Ls.
+__device__ __forceinline__ void linear_j_step(const float (&fe)[kPPL], const float (&fk)[kPPL], int fee, int fek,
+                                              const float (&ne)[kPPL], int nee, double Ls, double (&T)[kPPL],
+                                              double (&S)[kPPL])
+{
+    const double Lf = ldexp(Ls, fee), Ln = ldexp(Ls, nee);
+    const float Lk = (float)fmin(ldexp(Ls, fek), 3.0e38);
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        const float t = fk[j] * Lk;
+        const float ex = __builtin_amdgcn_exp2f(t * (float)(-kLog2e));
+        float wf, wn;
+        linear_j_weights_f32(t, ex, wf, wn);
+        T[j] *= (double)ex;
+        S[j] = fma(S[j], (double)ex, (double)(wf * fe[j]) * Lf + (double)(wn * ne[j]) * Ln);
+    }
+}
+
 __global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(LRT_SERVE_WAVES)))
 void serve_kernel(DevLines L, DevGrid g,
                                                               const ServeReq *reqs,
@@ -1080,7 +1101,14 @@ void serve_kernel(DevLines L, DevGrid g,
             T[j] = 1.0;
             S[j] = 0.0;
         }
-        for (int32_t c = c0; c < c1; ++c) {
+        // linear-j: the chunk owns the segments that end at its cells' midpoint
+        // nodes (the first from the far end, the last chunk's also to the
+        // observer), so it starts one cell early for its first far node
+        float pe[kPPL], pk[kPPL];
+        int pee = 0, pek = 0;
+        double pds = 0.0;
+        const int32_t cs0 = (R.linear && c0 > 0) ? c0 - 1 : c0;
+        for (int32_t c = cs0; c < c1; ++c) {
             float e[kPPL], kp[kPPL];
             const int ese = R.escale[2 * c + 0], esk = R.escale[2 * c + 1];
             accum_cell_tile_f32(rec, L, g, R.cc[c], R.cs + (int64_t)c * n_species, nullptr, ese, esk,
@@ -1096,16 +1124,35 @@ void serve_kernel(DevLines L, DevGrid g,
                 }
             }
             const double ds = R.ds[c];
-            const double dse = ldexp(ds, ese);
-            const float dsk = (float)fmin(ldexp(ds, esk), 3.0e38);
+            if (!R.linear) {
+                const double dse = ldexp(ds, ese);
+                const float dsk = (float)fmin(ldexp(ds, esk), 3.0e38);
+#pragma unroll
+                for (int j = 0; j < kPPL; ++j) {
+                    double at, em;
+                    segment_f32(e[j], kp[j], dsk, dse, at, em);
+                    T[j] *= at;
+                    S[j] = fma(S[j], at, em);
+                }
+                continue;
+            }
+            if (c >= c0) {
+                if (c == 0)   // far end -> first midpoint, both nodes the first cell's state
+                    linear_j_step(e, kp, ese, esk, e, ese, 0.5 * ds, T, S);
+                else          // midpoint -> midpoint, kappa from the far node
+                    linear_j_step(pe, pk, pee, pek, e, ese, 0.5 * (pds + ds), T, S);
+            }
 #pragma unroll
             for (int j = 0; j < kPPL; ++j) {
-                double at, em;
-                segment_f32(e[j], kp[j], dsk, dse, at, em);
-                T[j] *= at;
-                S[j] = fma(S[j], at, em);
+                pe[j] = e[j];
+                pk[j] = kp[j];
             }
+            pee = ese;
+            pek = esk;
+            pds = ds;
         }
+        if (R.linear && c1 == R.n_cells)   // last midpoint -> observer
+            linear_j_step(pe, pk, pee, pek, pe, pee, 0.5 * pds, T, S);
         double *ts = R.TS + ((int64_t)w.tile * R.n_chunks + w.chunk) * 2 * kTilePoints;
 #pragma unroll
         for (int j = 0; j < kPPL; ++j) {

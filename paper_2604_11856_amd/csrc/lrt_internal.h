@@ -227,6 +227,7 @@ struct ServeReq {
     double *I_int;           // [1]
     DevCont ct;              // the request's atomic continuum (n_thr < 0: none)
     double T_far;            // solid far boundary temperature (0: free)
+    int32_t linear;          // segment scheme: 0 cell-constant, 1 linear-j
 };
 
 // One unit of serving work: the cells of one chunk on one tile of a request.

@@ -16,27 +16,6 @@ namespace lrt {
 
 namespace {
 
-// Weights per unit length of the two nodes of a linear-j segment (Sec. 2.2.3:
-// kappa from the far node, j linear between the nodes) at optical thickness
-// t with e = e^-t: W_near = (1 - f)/t, W_far = (f - e)/t, f = (1 - e)/t, which
-// integrate the transfer equation over the segment.  (The pairing follows the
-// scheme's derivation; as t grows only the node next to the target counts.)
-// For |t| < 0.1 both differences cancel; there the weights come from their
-// Taylor series, W_near = sum (-t)^n/(n+2)!, W_far = sum (-1)^n (n+1) t^n/(n+2)!,
-// whose first omitted terms are below 3e-11.
-__device__ __forceinline__ void linear_j_weights_f32(float t, float e, float &wf, float &wn)
-{
-    const float sn = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, -1.0f / 5040.0f, 1.0f / 720.0f),
-                                                   -1.0f / 120.0f), 1.0f / 24.0f), -1.0f / 6.0f), 0.5f);
-    const float sf = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, -1.0f / 840.0f, 1.0f / 144.0f),
-                                                   -1.0f / 30.0f), 1.0f / 8.0f), -1.0f / 3.0f), 0.5f);
-    const float r = __builtin_amdgcn_rcpf(t);
-    const float f = (1.0f - e) * r;
-    const bool thin = fabsf(t) < 0.1f;
-    wn = thin ? sn : (1.0f - f) * r;
-    wf = thin ? sf : (f - e) * r;
-}
-
 __device__ __forceinline__ void linear_j_weights_f64(double t, double &e, double &wf, double &wn)
 {
     e = exp(-t);

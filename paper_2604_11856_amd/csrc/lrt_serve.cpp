@@ -102,6 +102,7 @@ struct Req {
     uint64_t mask = 0;
     bool keep = false;
     double T_far = 0.0;   // solid far boundary (0: free)
+    int scheme = 0;       // LRT_MARCH_CELL or LRT_MARCH_LINEAR_J
     // layout
     int32_t n_tiles = 0, n_chunks = 0;
     size_t bytes = 0, off = 0;
@@ -296,7 +297,8 @@ bool lrt_server::admit(Req &r)
         !ok(launch_scale(L, i0, i1, g, cc, cs, (int32_t)nc, S, lnb, emax, escale, st), "scale"))
         return true;
     r.dev = ServeReq{(int32_t)nc, r.k_first, r.n_window, r.n_tiles, r.n_chunks, kChunkCells,
-                     cc, cs, escale, ds, ranges, TS, I_out, partials, I_int, ct, r.T_far};
+                     cc, cs, escale, ds, ranges, TS, I_out, partials, I_int, ct, r.T_far,
+                     r.scheme == LRT_MARCH_LINEAR_J ? 1 : 0};
     if (!ok(hipMemcpyAsync(d_reqs.as<ServeReq>() + r.slot, &r.dev, sizeof(ServeReq),
                            hipMemcpyHostToDevice, st), "upload") ||
         !ok(hipEventCreateWithFlags(&r.prep_ev, hipEventDisableTiming), "event") ||
@@ -523,6 +525,8 @@ lrt_status lrt_submit(lrt_server *s, const lrt_los_request *q, uint64_t *ticket)
     }
     if (!(q->T_far >= 0.0) || !std::isfinite(q->T_far))
         return fail(nullptr, LRT_E_ARG, "request: far-boundary temperature %g invalid", q->T_far);
+    if (q->scheme != LRT_MARCH_CELL && q->scheme != LRT_MARCH_LINEAR_J)
+        return fail(nullptr, LRT_E_ARG, "request: unknown segment scheme %d", q->scheme);
     int32_t nt, nch;
     const int32_t n_thr = ctx->n_cont_rec > 0 ? ctx->n_cont_thr : -1;
     const size_t bytes = request_bytes(q->n_cells, S, (int32_t)q->n_window, n_thr, nt, nch);
@@ -542,6 +546,7 @@ lrt_status lrt_submit(lrt_server *s, const lrt_los_request *q, uint64_t *ticket)
     r->mask = q->species_mask;
     r->keep = q->keep_spectrum != 0;
     r->T_far = q->T_far;
+    r->scheme = q->scheme;
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) return fail(nullptr, LRT_E_STATE, "server is stopping");

@@ -82,7 +82,7 @@ class _LosRequest(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_species", C.c_int), ("T_tr", _dp), ("T_v", _dp),
                 ("N", _dp), ("n_e", _dp), ("ds", _dp), ("k_first", C.c_int64),
                 ("n_window", C.c_int64), ("species_mask", C.c_uint64), ("keep_spectrum", C.c_int),
-                ("T_far", C.c_double)]
+                ("T_far", C.c_double), ("scheme", C.c_int)]
 
 
 class _LosResult(C.Structure):
@@ -419,14 +419,16 @@ class Server:
     def _err(self, s):
         raise LrtError(s, self._L.lrt_last_error(None).decode())
 
-    def submit(self, req, keep_spectrum: bool = False, T_far: float = 0.0) -> int:
+    def submit(self, req, keep_spectrum: bool = False, T_far: float = 0.0,
+               scheme: int = 0) -> int:
         """req: synth.LosRequest; T_far > 0: a solid far boundary at that
-        temperature.  Returns the ticket."""
+        temperature; scheme: LRT_MARCH_CELL or LRT_MARCH_LINEAR_J.  Returns the
+        ticket."""
         c = req.cells
         a = [np.ascontiguousarray(x, np.float64) for x in (c.T_tr, c.T_v, c.N, c.n_e, req.ds)]
         q = _LosRequest(a[0].shape[0], a[2].shape[1], _p(a[0]), _p(a[1]), _p(a[2]), _p(a[3]),
                         _p(a[4]), int(req.k_first), int(req.n_window), int(req.species_mask),
-                        1 if keep_spectrum else 0, float(T_far))
+                        1 if keep_spectrum else 0, float(T_far), int(scheme))
         t = C.c_uint64()
         s = self._L.lrt_submit(self.h, C.byref(q), C.byref(t))
         if s != 0:

@@ -42,12 +42,13 @@ def make_requests(grid, n, seed, max_cells=120, max_win=30000):
                                   min_win=500, max_win=max_win, seed=seed)
 
 
-def oracle_los(wl, req, ks=None, cont=None, T_far=0.0):
+def oracle_los(wl, req, ks=None, cont=None, T_far=0.0, linear=False):
     """Observer intensity at window points ks (default: the whole window) and,
     for the whole window, its trapezoid integral (h/2 at both ends).  With
     cont, the atomic continuum of the atoms inside the request's mask is added
     (their ions at the request's densities).  T_far > 0: a solid far boundary
-    whose blackbody intensity starts the march."""
+    whose blackbody intensity starts the march; linear: the linear-j segment
+    scheme."""
     N = req.cells.N.copy()
     for s in range(N.shape[1]):
         if req.species_mask and not (req.species_mask >> s) & 1:
@@ -62,7 +63,8 @@ def oracle_los(wl, req, ks=None, cont=None, T_far=0.0):
         ec, kc = O.continuum(wl.species, req.cells, wl.grid, keep, ks)
         eta, kap = eta + ec, kap + kc
     I_far = O.planck_spectrum(wl.grid, ks, T_far) if T_far > 0.0 else None
-    I = O.march(np.arange(cells.n), req.ds, eta, kap, I_far)
+    march = O.march_linear if linear else O.march
+    I = march(np.arange(cells.n), req.ds, eta, kap, I_far)
     if not full:
         return I, None
     h = O.grid_step(wl.grid)
@@ -181,6 +183,43 @@ def test_serving_far_boundary(resident):
         assert abs(free["I_int"] - Iint_free) <= TOL * abs(Iint_free)
     with pytest.raises(lrt.LrtError):
         srv.submit(reqs[0], T_far=-1.0)
+    srv.stop()
+
+
+def test_serving_linear_j(resident):
+    """Requests marched with the linear-j segment scheme (nodes at the far end,
+    the cell midpoints and the observer; a chunk of cells starts one cell early
+    for its first far node), with and without a far wall: spectra and
+    integrals against the oracle's linear-j march, both schemes bitwise the
+    same alone and mixed, and an unknown scheme refused."""
+    wl, ctx = resident
+    reqs = make_requests(wl.grid, 5, seed=31)
+    assert any(r.cells.n > 64 for r in reqs)
+    srv = lrt.Server(ctx, 2 << 30, max_slots=16)
+    walls = (0.0, 7000.0, 0.0, 12000.0, 0.0)
+    alone = {}
+    for r, T_far in zip(reqs, walls):
+        res = srv.wait(srv.submit(r, keep_spectrum=True, T_far=T_far, scheme=lrt.LRT_MARCH_LINEAR_J),
+                       timeout_ms=120000)
+        assert res["status"] == 0
+        alone[(id(r), 1)] = res
+        I_ref, Iint_ref = oracle_los(wl, r, T_far=T_far, linear=True)
+        _, Iint_cell = oracle_los(wl, r, T_far=T_far)
+        e_spec = normwise(res["spectrum"], I_ref)
+        e_int = abs(res["I_int"] - Iint_ref) / abs(Iint_ref)
+        say("cells %4d window %6d T_far %6.0f linear-j: spectrum %.2e integral %.2e (vs cell scheme %.2e)"
+            % (r.cells.n, r.n_window, T_far, e_spec, e_int, abs(Iint_cell - Iint_ref) / abs(Iint_ref)))
+        assert e_spec <= TOL and e_int <= TOL
+        alone[(id(r), 0)] = srv.wait(srv.submit(r, keep_spectrum=True, T_far=T_far), timeout_ms=120000)
+    tickets = [(r, sc, srv.submit(r, keep_spectrum=True, T_far=T_far, scheme=sc))
+               for r, T_far in zip(reqs, walls) for sc in (1, 0)]
+    for r, sc, t in tickets:
+        m = srv.wait(t, timeout_ms=120000)
+        a = alone[(id(r), sc)]
+        assert m["status"] == 0 and a["I_int"] == m["I_int"]
+        np.testing.assert_array_equal(a["spectrum"], m["spectrum"])
+    with pytest.raises(lrt.LrtError):
+        srv.submit(reqs[0], scheme=2)
     srv.stop()
 
 
