@@ -493,9 +493,12 @@ typedef struct {
  * accumulation and march per spectral tile and chunk of cells, then the
  * chunks composed in order), single-precision compensated profile sums, FP64
  * march state and quadrature; no eta/kappa array is stored.  The context's
- * Lorentz model and atomic continuum (lrt_set_lorentz, lrt_set_continuum)
- * apply; QSS-CR populations, lrt_set_march and lrt_set_far_temperature do not
- * (a request carries its own far boundary and segment scheme).  Errors:
+ * Lorentz model, atomic continuum and QSS-CR data (lrt_set_lorentz,
+ * lrt_set_continuum, lrt_set_cr, lrt_set_line_levels) apply, the CR
+ * populations solved for each request's cells at admission (collision
+ * partners at the request's densities, whatever its species mask);
+ * lrt_set_march and lrt_set_far_temperature do not (a request carries its
+ * own far boundary and segment scheme).  Errors:
  * LRT_E_ARG (max_slots < 1, budget < 1 MiB), LRT_E_STATE (missing set_*),
  * LRT_E_OOM, LRT_E_DEVICE. */
 lrt_status lrt_server_start(lrt_ctx *ctx, size_t hbm_budget_bytes, int max_slots, lrt_server **out);

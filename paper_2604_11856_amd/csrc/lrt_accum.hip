@@ -1111,7 +1111,8 @@ void serve_kernel(DevLines L, DevGrid g,
         for (int32_t c = cs0; c < c1; ++c) {
             float e[kPPL], kp[kPPL];
             const int ese = R.escale[2 * c + 0], esk = R.escale[2 * c + 1];
-            accum_cell_tile_f32(rec, L, g, R.cc[c], R.cs + (int64_t)c * n_species, nullptr, ese, esk,
+            accum_cell_tile_f32(rec, L, g, R.cc[c], R.cs + (int64_t)c * n_species,
+                                R.lnd ? R.lnd + (int64_t)c * R.lnd_stride : nullptr, ese, esk,
                                 R.ranges[(int64_t)c * R.n_tiles + w.tile], kt, kw, lane, e, kp);
             if (R.ct.n_thr >= 0) {
                 // atomic continuum, added in double precision and rounded once

@@ -228,6 +228,8 @@ struct ServeReq {
     DevCont ct;              // the request's atomic continuum (n_thr < 0: none)
     double T_far;            // solid far boundary temperature (0: free)
     int32_t linear;          // segment scheme: 0 cell-constant, 1 linear-j
+    int32_t lnd_stride;      // QSS-CR: entries per cell of lnd
+    const double *lnd;       // QSS-CR: [cell][lnd_stride] ln departures, or NULL
 };
 
 // One unit of serving work: the cells of one chunk on one tile of a request.

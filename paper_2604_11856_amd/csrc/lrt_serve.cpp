@@ -127,7 +127,7 @@ struct Epoch {
 
 // Device bytes of one request (inputs, per-cell constants, ranges, chunk
 // transmittance / source, outputs), each sub-buffer 256-byte aligned.
-size_t request_bytes(int64_t nc, int S, int32_t n_window, int32_t n_thr, int32_t &n_tiles,
+size_t request_bytes(int64_t nc, int S, int32_t n_window, int32_t n_thr, int32_t cr_row, int32_t &n_tiles,
                      int32_t &n_chunks)
 {
     n_tiles = (n_window + kTilePoints - 1) / kTilePoints;
@@ -145,6 +145,8 @@ size_t request_bytes(int64_t nc, int S, int32_t n_window, int32_t n_thr, int32_t
     b += align_up(nb * 8) + align_up(8);                    // partials, I_int
     if (n_thr >= 0)                                         // continuum: cum, ff, lnb
         b += align_up((size_t)nc * 2 * (n_thr + 1) * 8) + 2 * align_up((size_t)nc * 2 * 8);
+    if (cr_row > 0)                                         // QSS-CR: populations, departures
+        b += 2 * align_up((size_t)nc * cr_row * 8);
     return b;
 }
 
@@ -213,7 +215,8 @@ bool lrt_server::admit(Req &r)
 {
     const int S = ctx->n_species;
     const int32_t n_thr = ctx->n_cont_rec > 0 ? ctx->n_cont_thr : -1;
-    const size_t bytes = request_bytes(r.n_cells, S, r.n_window, n_thr, r.n_tiles, r.n_chunks);
+    const int32_t cr_row = ctx->n_cr > 0 ? ctx->n_cr * ctx->cr_LS : 0;
+    const size_t bytes = request_bytes(r.n_cells, S, r.n_window, n_thr, cr_row, r.n_tiles, r.n_chunks);
     if (free_slots.empty()) return false;
     size_t off;
     if (!arena.alloc(bytes, off)) return false;
@@ -247,6 +250,12 @@ bool lrt_server::admit(Req &r)
         ff = (double *)take((size_t)nc * 2 * 8);
         lnb = (double *)take((size_t)nc * 2 * 8);
     }
+    // QSS-CR rows of the request's cells (the context's rate data and records)
+    DevCR crq = dev_cr(ctx);
+    if (cr_row > 0) {
+        crq.pop = (double *)take((size_t)nc * cr_row * 8);
+        crq.lnd = (double *)take((size_t)nc * cr_row * 8);
+    }
     hipStream_t st = admit_stream;
     auto ok = [&](hipError_t e, const char *what) {
         if (e != hipSuccess) {
@@ -262,11 +271,18 @@ bool lrt_server::admit(Req &r)
         !ok(hipMemcpyAsync(ds, r.ds.data(), nc * 8, hipMemcpyHostToDevice, st), "upload") ||
         !ok(hipMemcpyAsync(N, r.N.data(), (size_t)nc * S * 8, hipMemcpyHostToDevice, st), "upload"))
         return true;   // failed and released; counts as handled
+    // lines tied to QSS-CR levels read the request's departure rows
     DevLines L = dev_lines(ctx);
-    L.lev = nullptr;   // a request's cells carry Boltzmann populations (no QSS-CR here)
+    const bool cr_lines = cr_row > 0 && ctx->line_lev_ready;
+    L.lev = cr_lines ? ctx->d_line_lev.as<int32_t>() : nullptr;
+    L.lnd = cr_lines ? crq.lnd : nullptr;
+    L.lnd_stride = cr_lines ? cr_row : 0;
     const DevGrid g = dev_grid(ctx);
     const DevCells cells{(int32_t)nc, S, T_tr, T_v, N, n_e};
+    int32_t max_lev = 0;
+    for (int32_t v : ctx->h_cr_nlev) max_lev = std::max(max_lev, v);
     if (!ok(launch_thermo(ctx->sp, cells, dev_widths(ctx), ctx->M_min, r.mask, cc, cs, st), "thermo") ||
+        (cr_row > 0 && !ok(launch_cr(ctx->sp, cells, crq, ctx->cr_max_l, max_lev, cs, st), "QSS-CR")) ||
         !ok(launch_ranges(L, g, cc, (int32_t)nc, r.k_first, r.n_window, kTilePoints, ranges, st), "ranges"))
         return true;
     // the atomic continuum of the species the request lets radiate, over its window
@@ -275,7 +291,8 @@ bool lrt_server::admit(Req &r)
         const double w_lo = ctx->nu_min + (double)r.k_first * ctx->h;
         const double w_hi = ctx->nu_min + (double)(r.k_first + r.n_window - 1) * ctx->h;
         if (!ok(launch_cont_cells(ctx->d_cont_thr.as<ContThr>(), n_thr, ctx->d_cont_rec.as<ContRec>(),
-                                  ctx->n_cont_rec, cells, cs, DevCR{}, r.mask, w_lo, w_hi, cum, ff, lnb, st),
+                                  ctx->n_cont_rec, cells, cs, cr_row > 0 ? crq : DevCR{}, r.mask, w_lo, w_hi,
+                                  cum, ff, lnb, st),
                 "continuum"))
             return true;
         ct = DevCont{n_thr, ctx->d_cont_thr.as<ContThr>(), cum, ff, T_v};
@@ -298,7 +315,7 @@ bool lrt_server::admit(Req &r)
         return true;
     r.dev = ServeReq{(int32_t)nc, r.k_first, r.n_window, r.n_tiles, r.n_chunks, kChunkCells,
                      cc, cs, escale, ds, ranges, TS, I_out, partials, I_int, ct, r.T_far,
-                     r.scheme == LRT_MARCH_LINEAR_J ? 1 : 0};
+                     r.scheme == LRT_MARCH_LINEAR_J ? 1 : 0, L.lnd_stride, L.lnd};
     if (!ok(hipMemcpyAsync(d_reqs.as<ServeReq>() + r.slot, &r.dev, sizeof(ServeReq),
                            hipMemcpyHostToDevice, st), "upload") ||
         !ok(hipEventCreateWithFlags(&r.prep_ev, hipEventDisableTiming), "event") ||
@@ -350,8 +367,13 @@ bool lrt_server::launch_epoch(Epoch &e)
             return false;
         }
     }
+    // level offsets of the lines tied to QSS-CR levels; each request brings its
+    // own departure rows
     DevLines L = dev_lines(ctx);
-    L.lev = nullptr;   // Boltzmann populations in serving
+    const bool cr_lines = ctx->n_cr > 0 && ctx->line_lev_ready;
+    L.lev = cr_lines ? ctx->d_line_lev.as<int32_t>() : nullptr;
+    L.lnd = nullptr;
+    L.lnd_stride = 0;
     const DevGrid g = dev_grid(ctx);
     hipError_t err = hipMemcpyAsync(e.d_items.p, e.h_items, (size_t)n * sizeof(ServeItem),
                                     hipMemcpyHostToDevice, e.stream);
@@ -529,7 +551,8 @@ lrt_status lrt_submit(lrt_server *s, const lrt_los_request *q, uint64_t *ticket)
         return fail(nullptr, LRT_E_ARG, "request: unknown segment scheme %d", q->scheme);
     int32_t nt, nch;
     const int32_t n_thr = ctx->n_cont_rec > 0 ? ctx->n_cont_thr : -1;
-    const size_t bytes = request_bytes(q->n_cells, S, (int32_t)q->n_window, n_thr, nt, nch);
+    const int32_t cr_row = ctx->n_cr > 0 ? ctx->n_cr * ctx->cr_LS : 0;
+    const size_t bytes = request_bytes(q->n_cells, S, (int32_t)q->n_window, n_thr, cr_row, nt, nch);
     if (bytes > s->budget)
         return fail(nullptr, LRT_E_BUDGET, "request needs %zu bytes, budget is %zu", bytes, s->budget);
     std::unique_ptr<Req> r(new (std::nothrow) Req());

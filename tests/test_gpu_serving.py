@@ -42,13 +42,14 @@ def make_requests(grid, n, seed, max_cells=120, max_win=30000):
                                   min_win=500, max_win=max_win, seed=seed)
 
 
-def oracle_los(wl, req, ks=None, cont=None, T_far=0.0, linear=False):
+def oracle_los(wl, req, ks=None, cont=None, T_far=0.0, linear=False, cr=None, line_levels=None):
     """Observer intensity at window points ks (default: the whole window) and,
     for the whole window, its trapezoid integral (h/2 at both ends).  With
     cont, the atomic continuum of the atoms inside the request's mask is added
     (their ions at the request's densities).  T_far > 0: a solid far boundary
     whose blackbody intensity starts the march; linear: the linear-j segment
-    scheme."""
+    scheme; cr / line_levels: QSS-CR populations (a mask of 0 only, so that
+    the collision partners keep their densities)."""
     N = req.cells.N.copy()
     for s in range(N.shape[1]):
         if req.species_mask and not (req.species_mask >> s) & 1:
@@ -57,7 +58,7 @@ def oracle_los(wl, req, ks=None, cont=None, T_far=0.0, linear=False):
     full = ks is None
     if full:
         ks = np.arange(req.k_first, req.k_first + req.n_window, dtype=np.int64)
-    eta, kap, _ = O.coeffs(wl.species, wl.lines, cells, wl.grid, ks)
+    eta, kap, _ = O.coeffs(wl.species, wl.lines, cells, wl.grid, ks, cr=cr, line_levels=line_levels)
     keep = [r for r in (cont or []) if not req.species_mask or (req.species_mask >> r.species) & 1]
     if keep:
         ec, kc = O.continuum(wl.species, req.cells, wl.grid, keep, ks)
@@ -221,6 +222,44 @@ def test_serving_linear_j(resident):
     with pytest.raises(lrt.LrtError):
         srv.submit(reqs[0], scheme=2)
     srv.stop()
+
+
+def test_serving_qss_cr(resident):
+    """A context with QSS-CR data for N, O and the diatomic molecules, their
+    atomic lines on level pairs and rovibronic lines on electronic states
+    (synth.with_cr): each request solves the CR populations of its own cells
+    at admission, and the lines take them.  Spectra and integrals against the
+    oracle with the same CR model, alone = mixed bitwise."""
+    wl, _ = resident
+    wlc = synth.with_cr(wl)
+    assert wlc.cr.species and np.any(wlc.line_levels[:, 0] >= 0)
+    ctx = lrt.Context(0)
+    ctx.set_species(wlc.species)
+    ctx.set_lines(wlc.lines)
+    ctx.set_grid(wlc.grid)
+    ctx.set_cr(wlc.cr)
+    ctx.set_line_levels(wlc.line_levels)
+    reqs = [dataclasses.replace(r, species_mask=0) for r in make_requests(wlc.grid, 5, seed=41)]
+    srv = lrt.Server(ctx, 2 << 30, max_slots=8)
+    alone = []
+    for r in reqs:
+        res = srv.wait(srv.submit(r, keep_spectrum=True), timeout_ms=120000)
+        assert res["status"] == 0
+        alone.append(res)
+        I_ref, Iint_ref = oracle_los(wlc, r, cr=wlc.cr, line_levels=wlc.line_levels)
+        _, Iint_b = oracle_los(wlc, r)
+        e_spec = normwise(res["spectrum"], I_ref)
+        e_int = abs(res["I_int"] - Iint_ref) / abs(Iint_ref)
+        say("cells %4d window %6d QSS-CR: spectrum %.2e integral %.2e (vs Boltzmann %.2e)"
+            % (r.cells.n, r.n_window, e_spec, e_int, abs(Iint_b - Iint_ref) / abs(Iint_ref)))
+        assert e_spec <= TOL and e_int <= TOL
+    tickets = [srv.submit(r, keep_spectrum=True) for r in reqs]
+    for a, t in zip(alone, tickets):
+        m = srv.wait(t, timeout_ms=120000)
+        assert m["status"] == 0 and a["I_int"] == m["I_int"]
+        np.testing.assert_array_equal(a["spectrum"], m["spectrum"])
+    srv.stop()
+    ctx.close()
 
 
 def test_serving_budget_cancel_and_invalid(resident):
