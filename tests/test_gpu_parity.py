@@ -190,6 +190,39 @@ def test_axisymmetric_small(torch_dev):
     ctx.close()
 
 
+def test_solve_over_bands_equals_band_by_band(torch_dev):
+    """lrt_solve over several ragged bands gives bitwise the per-band
+    lrt_coeffs + lrt_march results summed in band order (its workspace reuse
+    across bands changes nothing); also from a first_band inside the range,
+    whose per-band fluxes equal those of the full solve."""
+    torch = torch_dev
+    wl = synth.axisymmetric(nx=12, nr=6, n_atomic=1500, n_rovib=3000, n_points=8192,
+                            band_points=1500, n_wall=3, n_mu=3, n_phi=5)
+    ctx = lrt.Context(0).load(wl)
+    s = ctx.sizes()
+    nb = s["n_bands"]
+    assert nb == 6 and ctx.band_len(nb - 1) == 692
+    for prec in PRECS:
+        per_band = []
+        for b in range(nb):
+            eta, kap, esc = ctx.coeffs_torch(b, prec)
+            I_b = torch.zeros(s["n_rays"], dtype=torch.float64, device="cuda:0")
+            ctx.march(b, prec, eta, kap, esc if prec == lrt.LRT_FP32_COMP else None, None, I_b)
+            per_band.append(I_b.cpu().numpy())
+        _, I_int, qb = ctx.solve(prec)
+        for first in (0, 3):
+            ref = np.zeros(s["n_rays"])
+            for b in range(first, nb):
+                ref = ref + per_band[b]
+            if first:
+                _, I_int, qb_f = ctx.solve(prec, first_band=first)
+                assert np.array_equal(qb_f[:, first:], qb[:, first:])
+            say("  solve over %d bands from %d prec %d: max |I - band by band| %.3e"
+                % (nb, first, prec, np.max(np.abs(I_int - ref))))
+            assert np.array_equal(I_int, ref)
+    ctx.close()
+
+
 def test_axi_segments_match_oracle(torch_dev):
     """Library traversal vs the oracle's sorted crossings: same cells, same
     lengths (mirror azimuths are traced once with twice the weight)."""

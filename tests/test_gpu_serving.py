@@ -42,14 +42,16 @@ def make_requests(grid, n, seed, max_cells=120, max_win=30000):
                                   min_win=500, max_win=max_win, seed=seed)
 
 
-def oracle_los(wl, req, ks=None, cont=None, T_far=0.0, linear=False, cr=None, line_levels=None):
+def oracle_los(wl, req, ks=None, cont=None, T_far=0.0, linear=False, cr=None, line_levels=None,
+               E_ion=None):
     """Observer intensity at window points ks (default: the whole window) and,
     for the whole window, its trapezoid integral (h/2 at both ends).  With
     cont, the atomic continuum of the atoms inside the request's mask is added
     (their ions at the request's densities).  T_far > 0: a solid far boundary
     whose blackbody intensity starts the march; linear: the linear-j segment
-    scheme; cr / line_levels: QSS-CR populations (a mask of 0 only, so that
-    the collision partners keep their densities)."""
+    scheme; cr / line_levels: QSS-CR populations; E_ion: the full Lorentz
+    width (both of the last two with a mask of 0 only, so that collision
+    partners and perturbers keep their densities)."""
     N = req.cells.N.copy()
     for s in range(N.shape[1]):
         if req.species_mask and not (req.species_mask >> s) & 1:
@@ -58,7 +60,8 @@ def oracle_los(wl, req, ks=None, cont=None, T_far=0.0, linear=False, cr=None, li
     full = ks is None
     if full:
         ks = np.arange(req.k_first, req.k_first + req.n_window, dtype=np.int64)
-    eta, kap, _ = O.coeffs(wl.species, wl.lines, cells, wl.grid, ks, cr=cr, line_levels=line_levels)
+    eta, kap, _ = O.coeffs(wl.species, wl.lines, cells, wl.grid, ks, cr=cr, line_levels=line_levels,
+                           E_ion=E_ion)
     keep = [r for r in (cont or []) if not req.species_mask or (req.species_mask >> r.species) & 1]
     if keep:
         ec, kc = O.continuum(wl.species, req.cells, wl.grid, keep, ks)
@@ -252,6 +255,46 @@ def test_serving_qss_cr(resident):
         e_int = abs(res["I_int"] - Iint_ref) / abs(Iint_ref)
         say("cells %4d window %6d QSS-CR: spectrum %.2e integral %.2e (vs Boltzmann %.2e)"
             % (r.cells.n, r.n_window, e_spec, e_int, abs(Iint_b - Iint_ref) / abs(Iint_ref)))
+        assert e_spec <= TOL and e_int <= TOL
+    tickets = [srv.submit(r, keep_spectrum=True) for r in reqs]
+    for a, t in zip(alone, tickets):
+        m = srv.wait(t, timeout_ms=120000)
+        assert m["status"] == 0 and a["I_int"] == m["I_int"]
+        np.testing.assert_array_equal(a["spectrum"], m["spectrum"])
+    srv.stop()
+    ctx.close()
+
+
+def test_serving_full_lorentz(resident):
+    """A context with the full Lorentz width (natural + Stark + van der Waals
+    per atomic line, electron densities raised to 2e16-2e17 cm^-3 so that the
+    Stark term shows): spectra and integrals against the oracle with the same
+    widths, alone = mixed bitwise."""
+    wl, _ = resident
+    E = synth.air_ionization_energies(wl.species)
+    ctx = lrt.Context(0)
+    ctx.set_species(wl.species)
+    ctx.set_lines(wl.lines)
+    ctx.set_grid(wl.grid)
+    ctx.set_lorentz(E)
+    rng = np.random.default_rng(43)
+    reqs = []
+    for r in make_requests(wl.grid, 5, seed=43):
+        n_e = 10.0 ** rng.uniform(16.3, 17.3, r.cells.n)
+        cells = synth.Cells(r.cells.T_tr, r.cells.T_v, r.cells.N, n_e)
+        reqs.append(dataclasses.replace(r, cells=cells, species_mask=0))
+    srv = lrt.Server(ctx, 2 << 30, max_slots=8)
+    alone = []
+    for r in reqs:
+        res = srv.wait(srv.submit(r, keep_spectrum=True), timeout_ms=120000)
+        assert res["status"] == 0
+        alone.append(res)
+        I_ref, Iint_ref = oracle_los(wl, r, E_ion=E)
+        _, Iint_u = oracle_los(wl, r)
+        e_spec = normwise(res["spectrum"], I_ref)
+        e_int = abs(res["I_int"] - Iint_ref) / abs(Iint_ref)
+        say("cells %4d window %6d full Lorentz: spectrum %.2e integral %.2e (vs uniform law %.2e)"
+            % (r.cells.n, r.n_window, e_spec, e_int, abs(Iint_u - Iint_ref) / abs(Iint_ref)))
         assert e_spec <= TOL and e_int <= TOL
     tickets = [srv.submit(r, keep_spectrum=True) for r in reqs]
     for a, t in zip(alone, tickets):
