@@ -202,6 +202,8 @@ def serving(n_closed, n_open, budget_gb=64, slots=64):
     srv.wait(srv.submit(synth.serving_requests(1, wl.grid.n_points, max_cells=32, max_win=20000,
                                                seed=1)[0]))
     reqs = synth.serving_requests(n_closed, wl.grid.n_points, seed=11859)
+    # (cell, grid point) pairs whose coefficients the closed loop computes and marches
+    cell_points = sum(int(r.cells.n) * int(r.n_window) for r in reqs)
     t0 = time.perf_counter()
     res = [srv.wait(t) for t in [srv.submit(r) for r in reqs]]
     t_closed = time.perf_counter() - t0
@@ -225,7 +227,8 @@ def serving(n_closed, n_open, budget_gb=64, slots=64):
     return {"resident": "1M lines (250k atomic + 750k rovibronic), 2^20-point grid 1000-100000 cm^-1",
             "requests": "cells logU[16, 2048], window logU[1e4, 1e6] points, mixed species subsets",
             "budget_GB": budget_gb, "slots": slots, "all_ok": ok,
-            "closed_loop": {"requests": n_closed, "seconds": t_closed, "solves_per_s": x_sat},
+            "closed_loop": {"requests": n_closed, "seconds": t_closed, "solves_per_s": x_sat,
+                            "cell_points": cell_points, "cell_points_per_s": cell_points / t_closed},
             "open_loop": {"requests": n_open, "rate_hz": rate, "seconds": t_open,
                           "solves_per_s": n_open / t_open,
                           "p50_latency_ms": float(np.percentile(lat, 50)),
