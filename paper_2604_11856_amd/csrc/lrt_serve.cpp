@@ -44,8 +44,8 @@ using Clock = std::chrono::steady_clock;
 constexpr size_t kAlign = 256;
 constexpr int kEpochStreams = 2;
 constexpr int32_t kChunkCells = 32;
-constexpr int kEpochCap = 8192;            // items per epoch at most
-constexpr int64_t kEpochUnits = 64ll << 20; // cell x point units per epoch (target)
+constexpr int kEpochCap = 32768;            // items per epoch at most
+constexpr int64_t kEpochUnits = 512ll << 20; // cell x point units per epoch (target)
 constexpr int kItemsPerTurn = 64;          // round-robin share per request
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
