@@ -98,6 +98,7 @@ struct Req {
     // inputs (host copies)
     int64_t n_cells = 0;
     std::vector<double> T_tr, T_v, N, n_e, ds;
+    std::vector<char> packed;   // the five arrays in their arena layout, one upload
     int32_t k_first = 0, n_window = 0;
     uint64_t mask = 0;
     bool keep = false;
@@ -265,11 +266,17 @@ bool lrt_server::admit(Req &r)
         }
         return true;
     };
-    if (!ok(hipMemcpyAsync(T_tr, r.T_tr.data(), nc * 8, hipMemcpyHostToDevice, st), "upload") ||
-        !ok(hipMemcpyAsync(T_v, r.T_v.data(), nc * 8, hipMemcpyHostToDevice, st), "upload") ||
-        !ok(hipMemcpyAsync(n_e, r.n_e.data(), nc * 8, hipMemcpyHostToDevice, st), "upload") ||
-        !ok(hipMemcpyAsync(ds, r.ds.data(), nc * 8, hipMemcpyHostToDevice, st), "upload") ||
-        !ok(hipMemcpyAsync(N, r.N.data(), (size_t)nc * S * 8, hipMemcpyHostToDevice, st), "upload"))
+    // T_tr, T_v, n_e, ds and N are consecutive in the arena: pack them host-side
+    // in that layout (padding zeroed) and upload once.  Small copies run as blit
+    // kernels beside the persistent serve kernel, each costing admission latency.
+    const size_t span = (size_t)((char *)(N + (size_t)nc * S) - (char *)T_tr);
+    r.packed.assign(span, 0);
+    const std::pair<const double *, const std::vector<double> *> parts[] = {
+        {T_tr, &r.T_tr}, {T_v, &r.T_v}, {n_e, &r.n_e}, {ds, &r.ds}, {N, &r.N}};
+    for (const auto &pt : parts)
+        std::memcpy(r.packed.data() + ((const char *)pt.first - (const char *)T_tr), pt.second->data(),
+                    pt.second->size() * sizeof(double));
+    if (!ok(hipMemcpyAsync(T_tr, r.packed.data(), span, hipMemcpyHostToDevice, st), "upload"))
         return true;   // failed and released; counts as handled
     // lines tied to QSS-CR levels read the request's departure rows
     DevLines L = dev_lines(ctx);
