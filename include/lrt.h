@@ -55,7 +55,7 @@ typedef enum {
     LRT_FP64 = 0,       /* every step in double precision */
     LRT_FP32_COMP = 1   /* populations, widths, windows and quadrature in double;
                            profile evaluation in single precision; at each grid
-                           point lines are summed in blocks of 32 whose partials
+                           point lines are summed in blocks of 64 whose partials
                            are merged with Kahan's compensation; eta/kappa stored
                            as float with a per-cell power-of-two scale */
 } lrt_precision;
@@ -96,14 +96,18 @@ typedef struct {
     const int32_t *species;
 } lrt_lines;
 
-/* Flowfield cell states, host pointers (Sec. 2.3 flowfield interface):
- * T_tr translational-rotational temperature, T_v vibrational =
- * electron-electronic temperature, N[c * n_species + s] number densities,
- * n_e electron number density (Lorentz width). */
+/* Flowfield cell states (Sec. 2.3 flowfield interface, the two-temperature
+ * state of Sec. 2.1): T_tr translational-rotational temperature, T_v
+ * vibrational = electron-electronic temperature, N[c * n_species + s] number
+ * densities, n_e electron number density (Lorentz width).  Structure of
+ * arrays owned by the caller: host pointers (on_device == 0) or device
+ * pointers of the context's HIP device (on_device != 0); read during the call
+ * only. */
 typedef struct {
     int64_t n_cells;
     int n_species;
     const double *T_tr, *T_v, *N, *n_e;
+    int on_device;
 } lrt_cells;
 
 /* Library version as "major.minor.patch". */
@@ -134,16 +138,21 @@ lrt_status lrt_set_species(lrt_ctx *ctx, int n_species, const lrt_species *speci
  * species), LRT_E_OOM. */
 lrt_status lrt_set_lines(lrt_ctx *ctx, const lrt_lines *lines);
 
-/* Uniform spectral grid nu_k = nu_min + k h, h = (nu_max - nu_min) /
- * (n_points - 1), both ends included, processed in bands of band_points
- * points (the last band may be shorter).  Errors: LRT_E_ARG (n_points < 2,
- * nu_max <= nu_min, nu_min <= 0, band_points < 1, n_points >= 2^31). */
+/* Uniform spectral grid of the line-by-line evaluation (Sec. 2.2.1: each
+ * line's profile is evaluated at the nodes of a spectral grid, at the
+ * distance of the node from the line centre; Sec. 2.2.3: the spectral
+ * integral of the wall intensity runs over the same nodes): nu_k = nu_min + k h, h = (nu_max - nu_min) / (n_points - 1), both
+ * ends included, processed in bands of band_points points (the last band may
+ * be shorter).  Errors: LRT_E_ARG (n_points < 2, nu_max <= nu_min,
+ * nu_min <= 0, band_points < 1, n_points >= 2^31). */
 lrt_status lrt_set_grid(lrt_ctx *ctx, double nu_min, double nu_max, int64_t n_points,
                         int64_t band_points);
 
-/* Cell states (copied to device memory, resident).  Errors: LRT_E_ARG
- * (n_species differs from the species table, T <= 0 or non-finite, N < 0,
- * n_e < 0), LRT_E_STATE (no species). */
+/* Cell states (copied to device memory, resident).  Device arrays are
+ * copied on the device and validated there (the call synchronises the
+ * device).  Errors: LRT_E_ARG (n_species differs from the species table,
+ * T <= 0 or non-finite, N < 0, n_e < 0; the context then has no cells),
+ * LRT_E_STATE (no species), LRT_E_DEVICE. */
 lrt_status lrt_set_cells(lrt_ctx *ctx, const lrt_cells *cells);
 
 /* Lorentz width of atomic lines (Sec. 2.2.1 pressure broadening).  With
@@ -175,7 +184,7 @@ lrt_status lrt_set_lorentz(lrt_ctx *ctx, const double *E_ion);
  *     A1 = c1 + c2 e^{-c3 T}, A2 = c4 + c5 e^{-c6 T} + c7 e^{-c8 T},
  *     eta += B(nu, T) times that (the fit's normalisation factor D is 0).
  * sigma0 has one entry per level of the atom (0: no bound-free from it); all
- * c zero: no free-free.  The serving path does not add the continuum. */
+ * c zero: no free-free. */
 typedef struct {
     int32_t species;       /* the atom (an LRT_KIND_ATOM species) */
     int32_t ion;           /* species index of its singly charged ion */
@@ -402,9 +411,12 @@ lrt_status lrt_march(lrt_ctx *ctx, int64_t band, lrt_precision prec, const void 
                      const void *kappa, const int32_t *escale, double *I_out, double *I_int_out,
                      void *stream);
 
-/* The whole path over bands first_band..n_bands-1: per-cell populations and
- * scales (recomputed on every call), coefficients, march, spectral and angular
- * quadrature.  Outputs (host, may be NULL): q[n_wall]
+/* The whole path of Sec. 2.2.3 (steps: populations of every cell, Sec. 2.1;
+ * emission and absorption coefficients on the grid, Sec. 2.2.1; the formal
+ * solution of the transfer equation along every ray; the wall flux integral
+ * over wavenumber and solid angle) over bands first_band..n_bands-1:
+ * per-cell populations and scales (recomputed on every call), coefficients,
+ * march, spectral and angular quadrature.  Outputs (host, may be NULL): q[n_wall]
  * wall flux summed over the processed bands, I_int[n_rays] spectrally
  * integrated intensity per ray, q_band[n_wall][n_bands] per-band flux (bands
  * before first_band are left untouched, so a run resumed at first_band fills

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <climits>
 #include <cstdint>
 #include <cmath>
@@ -1036,6 +1037,22 @@ __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n)
     if (t < n) p[t] = v;
 }
 
+__global__ void check_cells_kernel(DevCells cells, int32_t *flags)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int S = cells.n_species;
+    if (t >= (int64_t)cells.n_cells * (S + 1)) return;
+    const int64_t c = t / (S + 1), s = t % (S + 1);
+    if (s == S) {
+        const double a = cells.T_tr[c], b = cells.T_v[c], e = cells.n_e[c];
+        if (!(a > 0.0 && a <= DBL_MAX && b > 0.0 && b <= DBL_MAX)) atomicOr(&flags[0], 1);
+        if (!(e >= 0.0 && e <= DBL_MAX)) atomicOr(&flags[1], 1);
+    } else {
+        const double n = cells.N[c * S + s];
+        if (!(n >= 0.0 && n <= DBL_MAX)) atomicOr(&flags[1], 1);
+    }
+}
+
 __global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, int64_t n)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1305,6 +1322,14 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_cells(const DevCells &cells, int32_t *flags, hipStream_t st)
+{
+    const int64_t n = (int64_t)cells.n_cells * (cells.n_species + 1);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(check_cells_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, cells, flags);
     return hipGetLastError();
 }
 

@@ -156,7 +156,12 @@ bool traverse_axi(int nx, int nr, double Lx, double R, double rw, double mu, dou
     const double A2 = st * st;          // rho^2(s) = rw^2 + 2 B s + A2 s^2
     const double B = rw * a;
     int ix = 0;
+    // start cell from the same face products the crossings use:
+    // ir dr <= rw < (ir + 1) dr (floor(rw / dr) can be one off when dr is
+    // not a power of two and rw sits on a face)
     int ir = std::min((int)std::floor(rw / dr), nr - 1);
+    while (ir > 0 && rw < ir * dr) --ir;
+    while (ir < nr - 1 && rw >= (ir + 1) * dr) ++ir;
     double s = 0.0;
     const int max_steps = 4 * (nx + 2 * nr) + 16;
     for (int step = 0; step < max_steps; ++step) {
@@ -178,8 +183,11 @@ bool traverse_axi(int nx, int nr, double Lx, double R, double rw, double mu, dou
                 }
             }
             if (dir == 0) {
+                // outward crossing of the outer face: ahead of s, or at s when
+                // the ray starts on it heading outward
                 const double rj = (ir + 1) * dr;
-                if (quad_roots(A2, B, (rw - rj) * (rw + rj), lo, hi) && hi > s) {
+                const bool outward = B + A2 * s > 0.0;
+                if (quad_roots(A2, B, (rw - rj) * (rw + rj), lo, hi) && (hi > s || (hi == s && outward))) {
                     s_r = hi;
                     dir = +1;
                 }
@@ -548,6 +556,44 @@ lrt_status lrt_set_grid(lrt_ctx *c, double nu_min, double nu_max, int64_t n_poin
     return LRT_OK;
 }
 
+}  // extern "C"
+
+// Cells given as device arrays: copied on the device, then validated there
+// (one flag per rule); on failure the context is left without cells.
+static lrt_status set_cells_device(lrt_ctx *c, const lrt_cells *x)
+{
+    const int64_t nc = x->n_cells, S = x->n_species;
+    c->n_cells = 0;
+    lrt_status st;
+    if ((st = upload(c, c->d_T_tr, nullptr, nc * 8)) || (st = upload(c, c->d_T_v, nullptr, nc * 8)) ||
+        (st = upload(c, c->d_N, nullptr, nc * S * 8)) || (st = upload(c, c->d_n_e, nullptr, nc * 8)) ||
+        (st = upload(c, c->d_cc, nullptr, nc * sizeof(CellConst))) ||
+        (st = upload(c, c->d_cs, nullptr, nc * S * sizeof(CellSpecies))) ||
+        (st = upload(c, c->d_emax, nullptr, nc * 2 * sizeof(int32_t))) ||
+        (st = upload(c, c->d_escale, nullptr, nc * 2 * sizeof(int32_t))) ||
+        (st = ensure(c, c->w_count, 16)))
+        return st;
+    LRT_HIP(c, hipMemcpy(c->d_T_tr.p, x->T_tr, nc * 8, hipMemcpyDeviceToDevice));
+    LRT_HIP(c, hipMemcpy(c->d_T_v.p, x->T_v, nc * 8, hipMemcpyDeviceToDevice));
+    LRT_HIP(c, hipMemcpy(c->d_N.p, x->N, nc * S * 8, hipMemcpyDeviceToDevice));
+    LRT_HIP(c, hipMemcpy(c->d_n_e.p, x->n_e, nc * 8, hipMemcpyDeviceToDevice));
+    int32_t *flags = c->w_count.as<int32_t>();
+    LRT_HIP(c, launch_fill_i32(flags, 0, 2, nullptr));
+    const DevCells cells{(int32_t)nc, (int)S, c->d_T_tr.as<double>(), c->d_T_v.as<double>(),
+                         c->d_N.as<double>(), c->d_n_e.as<double>()};
+    LRT_HIP(c, launch_check_cells(cells, flags, nullptr));
+    int32_t h[2] = {0, 0};
+    LRT_HIP(c, hipMemcpy(h, flags, sizeof(h), hipMemcpyDeviceToHost));
+    if (h[0]) return fail(c, LRT_E_ARG, "device cells: temperatures must be positive and finite");
+    if (h[1]) return fail(c, LRT_E_ARG, "device cells: N and n_e must be finite and >= 0");
+    c->n_cells = nc;
+    c->thermo_ready = false;
+    c->scale_ready = false;
+    return LRT_OK;
+}
+
+extern "C" {
+
 lrt_status lrt_set_cells(lrt_ctx *c, const lrt_cells *x)
 {
     if (!c) return LRT_E_ARG;
@@ -559,6 +605,7 @@ lrt_status lrt_set_cells(lrt_ctx *c, const lrt_cells *x)
         return fail(c, LRT_E_ARG, "cells have %d species, table has %d", x->n_species, c->n_species);
     if (!x->T_tr || !x->T_v || !x->N || !x->n_e) return fail(c, LRT_E_ARG, "cell arrays must be non-NULL");
     const int64_t nc = x->n_cells, S = x->n_species;
+    if (x->on_device) return set_cells_device(c, x);
     for (int64_t i = 0; i < nc; ++i) {
         if (!(x->T_tr[i] > 0.0) || !(x->T_v[i] > 0.0) || !std::isfinite(x->T_tr[i]) || !std::isfinite(x->T_v[i]))
             return fail(c, LRT_E_ARG, "cell %lld: temperatures must be positive and finite", (long long)i);

@@ -291,6 +291,10 @@ hipError_t launch_wall_sum(const double *I_int, const double *weight, const int6
 hipError_t launch_add(double *acc, const double *x, int32_t n, hipStream_t st);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+// Cell-state validation on the device: flags[0] |= 1 for a temperature that is
+// not positive and finite, flags[1] |= 1 for a density or n_e that is not
+// finite and >= 0 (flags zeroed by the caller).
+hipError_t launch_check_cells(const DevCells &cells, int32_t *flags, hipStream_t st);
 
 hipError_t launch_serve(const DevLines &L, const DevGrid &g, const ServeReq *reqs,
                         const ServeItem *items, int32_t n_items, int32_t *counter,

@@ -75,7 +75,7 @@ class _CRSpecies(C.Structure):
 
 class _Cells(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_species", C.c_int), ("T_tr", _dp), ("T_v", _dp),
-                ("N", _dp), ("n_e", _dp)]
+                ("N", _dp), ("n_e", _dp), ("on_device", C.c_int)]
 
 
 class _LosRequest(C.Structure):
@@ -226,7 +226,17 @@ class Context:
         T_v = np.ascontiguousarray(cells.T_v, np.float64)
         N = np.ascontiguousarray(cells.N, np.float64)
         ne = np.ascontiguousarray(cells.n_e, np.float64)
-        s = _Cells(T_tr.shape[0], N.shape[1], _p(T_tr), _p(T_v), _p(N), _p(ne))
+        s = _Cells(T_tr.shape[0], N.shape[1], _p(T_tr), _p(T_v), _p(N), _p(ne), 0)
+        self._chk(self._L.lrt_set_cells(self.h, C.byref(s)))
+
+    def set_cells_device(self, T_tr, T_v, N, n_e):
+        """Cell states from contiguous float64 device tensors ([n], [n], [n, S], [n])
+        on the context's device; copied and validated on the device."""
+        for t in (T_tr, T_v, N, n_e):
+            if not (t.is_cuda and t.dtype.itemsize == 8 and t.is_contiguous()):
+                raise ValueError("device cells must be contiguous float64 device tensors")
+        dp = lambda t: C.cast(C.c_void_p(t.data_ptr()), _dp)
+        s = _Cells(int(T_tr.shape[0]), int(N.shape[1]), dp(T_tr), dp(T_v), dp(N), dp(n_e), 1)
         self._chk(self._L.lrt_set_cells(self.h, C.byref(s)))
 
     def set_rays(self, geom):

@@ -66,3 +66,22 @@ def test_fibonacci_rule_matches_oracle():
         assert d1.shape == d0.shape
         np.testing.assert_allclose(d1, d0, rtol=0, atol=1e-15)
         np.testing.assert_allclose(w1, w0, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("R,nr", [(0.3, 20), (0.7, 10), (50.0 / 3.0, 30), (1.0, 7)])
+def test_traversal_wall_points_on_faces_non_dyadic(R, nr):
+    """Wall points at k R / nr on grids whose radial step is not a power of
+    two: the start cell must agree with the face products (r_k = k dr), or an
+    outward ray misses its first face.  Checked against the oracle's sorted
+    crossings for every face, polar node and azimuth.  (A ray along the wall
+    normal from a face point runs on the face itself, where either adjacent
+    cell is correct; it is checked for its length only.)"""
+    g = synth.AxiGeometry(16, nr, 1.0, R, np.arange(nr) * R / nr, 4, 4)
+    mus = list(O.gauss_legendre_01(5)[0]) + [0.3, 0.95]
+    phis = [0.2, 1.3, 2.9, math.pi, 4.0, 5.5, 0.0, math.pi / 2]
+    for rw in g.wall_r:
+        for mu in mus:
+            for phi in phis:
+                _compare(g, float(rw), float(mu), phi)
+        c1, d1 = lrt.trace_axi_ray(g.nx, g.nr, g.Lx, g.R, float(rw), 1.0, 0.0)
+        assert d1.sum() == pytest.approx(g.Lx, rel=1e-14) and np.all(np.diff(c1 // nr) == -1)

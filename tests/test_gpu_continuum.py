@@ -8,6 +8,7 @@ import pytest
 
 import oracle as O
 from paper_2604_11856_amd import lrt, synth
+from parity_util import edge_mask, normwise, say
 
 pytestmark = pytest.mark.gpu
 
@@ -22,31 +23,12 @@ def torch_dev():
     return torch
 
 
-def say(*a):
-    print(*a, flush=True)
-
-
-def normwise(got, ref, mask=None):
-    d = np.abs(np.asarray(got, np.float64) - np.asarray(ref, np.float64))
-    if mask is not None:
-        d = np.where(mask, 0.0, d)
-    return float(np.max(np.max(d, axis=1) / np.max(np.abs(ref), axis=1)))
-
-
 def gpu_coeffs(ctx, band, prec, torch):
     eta, kap, esc = ctx.coeffs_torch(band, prec)
     torch.cuda.synchronize()
     if prec == lrt.LRT_FP32_COMP:
         return lrt.scaled_to_f64(eta, kap, esc)
     return eta.cpu().numpy(), kap.cpu().numpy()
-
-
-def edge_mask(wl, k_first, n):
-    cc, kk = O.knife_edges(wl.species, wl.lines, wl.cells, wl.grid)
-    m = np.zeros((wl.cells.n, n), bool)
-    sel = (kk >= k_first) & (kk < k_first + n)
-    m[cc[sel], kk[sel] - k_first] = True
-    return m
 
 
 def test_continuum_coeffs_all_bands(torch_dev):

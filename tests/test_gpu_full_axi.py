@@ -21,6 +21,7 @@ import pytest
 
 import oracle as O
 from paper_2604_11856_amd import lrt, synth
+from parity_util import knife_mask, normwise, say
 
 pytestmark = pytest.mark.gpu
 
@@ -35,23 +36,6 @@ def torch_dev():
     return torch
 
 
-def say(*a):
-    print(*a, flush=True)
-
-
-def normwise(got, ref, mask=None):
-    got = np.asarray(got, np.float64)
-    ref = np.asarray(ref, np.float64)
-    d = np.abs(got - ref)
-    if mask is not None:
-        d = np.where(mask, 0.0, d)
-    den = np.max(np.abs(ref), axis=-1)
-    num = np.max(d, axis=-1)
-    zero = den == 0
-    assert np.all(num[zero] == 0), "nonzero values where the oracle has none"
-    return float(np.max(num[~zero] / den[~zero])) if np.any(~zero) else 0.0
-
-
 def subset_cells(cells, idx):
     return synth.Cells(cells.T_tr[idx], cells.T_v[idx], np.ascontiguousarray(cells.N[idx]),
                        cells.n_e[idx])
@@ -60,16 +44,6 @@ def subset_cells(cells, idx):
 def band_points(rng, k0, n, n_clusters, cluster=32):
     starts = rng.integers(k0, k0 + n - cluster, n_clusters)
     return np.unique(np.concatenate([np.arange(s, s + cluster) for s in starts])).astype(np.int64)
-
-
-def knife_mask(wl, cells, ks):
-    cc, kk = O.knife_edges(wl.species, wl.lines, cells, wl.grid, near=ks)
-    pos = {int(k): j for j, k in enumerate(ks)}
-    m = np.zeros((cells.n, ks.size), bool)
-    for c, k in zip(cc, kk):
-        if int(k) in pos:
-            m[c, pos[int(k)]] = True
-    return m
 
 
 def check_config(wl, band, n_walls, ray_stride, label, torch, seed=3, march_points=32):

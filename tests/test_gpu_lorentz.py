@@ -7,6 +7,7 @@ import pytest
 
 import oracle as O
 from paper_2604_11856_amd import lrt, synth
+from parity_util import normwise, say
 
 pytestmark = pytest.mark.gpu
 
@@ -19,18 +20,6 @@ def torch_dev():
     import torch
     assert torch.cuda.is_available()
     return torch
-
-
-def say(*a):
-    print(*a, flush=True)
-
-
-def normwise(got, ref, mask=None):
-    d = np.abs(np.asarray(got, np.float64) - np.asarray(ref, np.float64))
-    if mask is not None:
-        d = np.where(mask, 0.0, d)
-    den = np.max(np.abs(ref), axis=1)
-    return float(np.max(np.max(d, axis=1)[den > 0] / den[den > 0]))
 
 
 def stark_workload(n_e):

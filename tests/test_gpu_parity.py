@@ -11,6 +11,7 @@ import pytest
 
 import oracle as O
 from paper_2604_11856_amd import lrt, synth
+from parity_util import edge_mask, normwise, say
 
 pytestmark = pytest.mark.gpu
 
@@ -25,39 +26,12 @@ def torch_dev():
     return torch
 
 
-def say(*a):
-    print(*a, flush=True)
-
-
-def normwise(got, ref, mask=None):
-    """max over rows of max|got - ref| / max|ref| (rows where ref == 0
-    must be exactly zero)."""
-    got = np.asarray(got, np.float64)
-    ref = np.asarray(ref, np.float64)
-    d = np.abs(got - ref)
-    if mask is not None:
-        d = np.where(mask, 0.0, d)
-    den = np.max(np.abs(ref), axis=-1)
-    num = np.max(d, axis=-1)
-    zero = den == 0
-    assert np.all(num[zero] == 0), "nonzero values where the oracle has none"
-    return float(np.max(num[~zero] / den[~zero])) if np.any(~zero) else 0.0
-
-
 def gpu_coeffs(ctx, band, prec, torch):
     eta, kap, esc = ctx.coeffs_torch(band, prec)
     torch.cuda.synchronize()
     if prec == lrt.LRT_FP32_COMP:
         return lrt.scaled_to_f64(eta, kap, esc)
     return eta.cpu().numpy(), kap.cpu().numpy()
-
-
-def edge_mask(wl, k_first, n):
-    cc, kk = O.knife_edges(wl.species, wl.lines, wl.cells, wl.grid)
-    m = np.zeros((wl.cells.n, n), bool)
-    sel = (kk >= k_first) & (kk < k_first + n)
-    m[cc[sel], kk[sel] - k_first] = True
-    return m
 
 
 def check_all_bands(wl, torch, precs=PRECS):
@@ -402,4 +376,43 @@ def test_stagnation_full_size_sampled(torch_dev):
         say("  eta %.3e kappa %.3e (knife-edge points excluded: %d)" % (ee, ek, int(m.sum())))
         assert ee <= TOL[prec] and ek <= TOL[prec]
         torch.cuda.empty_cache()
+    ctx.close()
+
+
+def test_cells_from_device_tensors(torch_dev):
+    """Cell states passed as device tensors (the caller-owned device SoA of
+    the boundary) give bitwise the results of the host upload, in both
+    precisions; invalid device states are rejected with LRT_E_ARG and leave
+    the context without cells."""
+    torch = torch_dev
+    wl = synth.stagnation_line(n_cells=24, n_atomic=400, n_rovib=800, n_points=6000,
+                               band_points=2048, n_mu=3, seed=12)
+    ctx = lrt.Context(0).load(wl)
+    host = {p: ctx.solve(p) for p in PRECS}
+    host_c = {p: gpu_coeffs(ctx, 1, p, torch) for p in PRECS}
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64), device="cuda:0")
+    T_tr, T_v, N, ne = dev(wl.cells.T_tr), dev(wl.cells.T_v), dev(wl.cells.N), dev(wl.cells.n_e)
+    ctx.set_cells_device(T_tr, T_v, N, ne)
+    for p in PRECS:
+        q, I_int, qb = ctx.solve(p)
+        assert np.array_equal(q, host[p][0]) and np.array_equal(I_int, host[p][1])
+        e, k = gpu_coeffs(ctx, 1, p, torch)
+        assert np.array_equal(e, host_c[p][0]) and np.array_equal(k, host_c[p][1])
+    say("device cells: bitwise equal to host cells in both precisions")
+    for bad in ("T", "N", "ne"):
+        t2, n2, e2 = T_tr.clone(), N.clone(), ne.clone()
+        if bad == "T":
+            t2[5] = -1.0
+        elif bad == "N":
+            n2[3, 2] = float("nan")
+        else:
+            e2[0] = -2.0
+        with pytest.raises(lrt.LrtError) as err:
+            ctx.set_cells_device(t2, T_v, n2, e2)
+        assert err.value.status == 1
+        with pytest.raises(lrt.LrtError) as err:
+            ctx.solve(lrt.LRT_FP64)   # no cells after a rejected set
+        assert err.value.status == 6
+    ctx.set_cells_device(T_tr, T_v, N, ne)
+    assert np.array_equal(ctx.solve(lrt.LRT_FP64)[0], host[lrt.LRT_FP64][0])
     ctx.close()

@@ -929,3 +929,123 @@ def test_full_lorentz_sum_vs_bruteforce(seed):
     assert np.array_equal(es, eb[:, ks]) and np.array_equal(kss, kb[:, ks])
     e0, _, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid)
     assert np.max(np.abs(e - e0)) > 0
+
+
+# ---------------------------------------------------------------------------
+# knife edges: the parity exclusion (the +-100 HWHM cut of Sec. 2.2.1 read as
+# integer window bounds; a bound within 1e-9 grid steps of an integer index
+# may move by one point under a last-bit change of the Voigt width)
+# ---------------------------------------------------------------------------
+
+_KE_NU_MIN, _KE_H, _KE_N = 1000.0, 0.0625, (1 << 20) + 1   # h = 2^-4 exactly
+_KE_T, _KE_NE, _KE_MASS = 8000.0, 1e15, 14.0
+
+
+def _ke_bound(nu0, side):
+    """Real-valued grid position of one window bound of a line at nu0, in
+    double precision as the definition reads: (nu0 +- 100 gamma_V - nu_min)/h
+    with gamma_V the Voigt HWHM of its Doppler and uniform Stark widths."""
+    gG = O.doppler_hwhm(nu0, _KE_T, _KE_MASS)
+    gL = O.lorentz_hwhm(_KE_NE, _KE_T)
+    W = 100.0 * O.voigt_hwhm(gL, gG)
+    return ((nu0 + side * W) - _KE_NU_MIN) / _KE_H
+
+
+def _ke_line_at(m, delta, side):
+    """A line centre nu0 (double) whose bound on `side` sits as close as the
+    double grid allows to m + delta grid steps; returns nu0 and the exact
+    offset of that bound from m (a Fraction)."""
+    from fractions import Fraction
+    target = Fraction(m) + Fraction(delta)
+    nu0 = _KE_NU_MIN + m * _KE_H
+    for _ in range(6):   # fixed point: the width depends weakly on nu0
+        nu0 = nu0 - (_ke_bound(nu0, side) - float(target)) * _KE_H
+    best = None
+    for _ in range(400):   # walk nu0 one ulp at a time towards the target
+        b = Fraction(_ke_bound(nu0, side))
+        if best is None or abs(b - target) < abs(best[1] - target):
+            best = (nu0, b)
+        step = math.nextafter(nu0, math.inf if b < target else -math.inf)
+        if (b < target) != (Fraction(_ke_bound(step, side)) < target) and \
+                abs(Fraction(_ke_bound(step, side)) - target) >= abs(b - target):
+            break
+        nu0 = step
+    nu0, b = best
+    return nu0, b - m
+
+
+def _ke_workload(nu0):
+    sp = [synth.Species("N", synth.KIND_ATOM, _KE_MASS, level_E=np.array([0.0, 80000.0]),
+                        level_g=np.array([4.0, 6.0]))]
+    lines = synth.Lines(np.array([nu0]), np.array([1e8]), np.array([90000.0]), np.zeros(1),
+                        np.array([90000.0 - nu0]), np.zeros(1), np.array([6.0]), np.array([4.0]),
+                        np.zeros(1, np.int32))
+    cells = synth.Cells(np.array([_KE_T]), np.array([_KE_T]), np.array([[1e16]]), np.array([_KE_NE]))
+    grid = synth.Grid(_KE_NU_MIN, _KE_NU_MIN + _KE_H * (_KE_N - 1), _KE_N, _KE_N)
+    return sp, lines, cells, grid
+
+
+def _ke_expected(nu0):
+    """Points the exclusion must flag for a one-line, one-cell case: each bound
+    whose exact distance to the nearest integer r is at most 1e-9 grid steps
+    flags r - 1, r, r + 1 (those on the grid), nothing else."""
+    from fractions import Fraction
+    want = set()
+    for side in (-1.0, 1.0):
+        b = Fraction(_ke_bound(nu0, side))
+        r = round(b)
+        if abs(b - r) <= Fraction(1e-9) and -1 <= r <= _KE_N:
+            want |= {k for k in (r - 1, r, r + 1) if 0 <= k < _KE_N}
+    return want
+
+
+@pytest.mark.parametrize("side", [-1.0, 1.0])
+@pytest.mark.parametrize("delta", [0.0, 5e-10, -5e-10, 2e-9, -2e-9, 1e-6, 1e-3, 0.5])
+def test_knife_edges_flag_only_bounds_within_1e9_steps(side, delta):
+    """A window bound placed at integer + delta grid steps (delta exact,
+    bound index ~4.6e5 so that a tolerance relative to the index would be
+    ~5e-4 steps): flagged, with its two neighbours, iff |delta| <= 1e-9."""
+    m = 464_123 if side > 0 else 463_877
+    nu0, off = _ke_line_at(m, delta, side)
+    assert abs(float(off) - delta) < 3e-10, (off, delta)   # placement is as asked
+    sp, lines, cells, grid = _ke_workload(nu0)
+    cc, kk = O.knife_edges(sp, lines, cells, grid)
+    got = set(int(k) for k in kk)
+    assert set(int(c) for c in cc) <= {0}
+    want = _ke_expected(nu0)
+    assert got == want, (delta, side, sorted(got), sorted(want))
+    flagged_here = abs(off) <= 1e-9
+    assert flagged_here == (abs(delta) <= 1e-9)
+    if flagged_here:
+        assert {m - 1, m, m + 1} <= got
+    else:
+        assert not ({m - 1, m, m + 1} & got)
+
+
+def test_knife_edges_at_grid_ends():
+    """Bounds at index -1 and n_points flag only the neighbours that exist on
+    the grid (k = 0 and k = n_points - 1)."""
+    nu0, off = _ke_line_at(-1, 0.0, 1.0)
+    assert off == 0
+    sp, lines, cells, grid = _ke_workload(nu0)
+    _, kk = O.knife_edges(sp, lines, cells, grid)
+    assert set(int(k) for k in kk) == _ke_expected(nu0) and 0 in set(int(k) for k in kk)
+    assert all(0 <= k < _KE_N for k in kk)
+    nu0, off = _ke_line_at(_KE_N, 0.0, -1.0)
+    assert off == 0
+    sp, lines, cells, grid = _ke_workload(nu0)
+    _, kk = O.knife_edges(sp, lines, cells, grid)
+    assert set(int(k) for k in kk) == _ke_expected(nu0) and _KE_N - 1 in set(int(k) for k in kk)
+
+
+def test_knife_edges_rate_on_a_random_list():
+    """On seeded random lines the flagged fraction matches the 2e-9 chance of
+    a bound landing within 1e-9 of an integer: none among 4e4 bounds; and
+    every flagged point of a larger tolerance lies next to such a bound."""
+    wl = synth.stagnation_line(n_cells=4, n_atomic=5000, n_rovib=5000, n_points=1 << 16,
+                               band_points=1 << 16, n_mu=0, seed=5)
+    cc, kk = O.knife_edges(wl.species, wl.lines, wl.cells, wl.grid)
+    assert cc.size == 0
+    cc, kk = O.knife_edges(wl.species, wl.lines, wl.cells, wl.grid, tol=1e-3)
+    # about 2e-3 of 8e4 bounds, three points each
+    assert 0 < cc.size < 3 * 8e4 * 2e-3 * 3
