@@ -425,6 +425,22 @@ lrt_status lrt_march(lrt_ctx *ctx, int64_t band, lrt_precision prec, const void 
 lrt_status lrt_solve(lrt_ctx *ctx, lrt_precision prec, int64_t first_band, double *q,
                      double *I_int, double *q_band, void *stream);
 
+/* The whole path of lrt_solve over an explicit list of n grid-point ranges
+ * [k_first[i], k_first[i] + n_points[i]) instead of the bands (a spectral
+ * window of a coupled solver, or a stratified sample of the spectrum): per-cell
+ * populations and scales once, then per range the coefficients of every cell,
+ * the march of every ray and the flux sums (Sec. 2.2.3 steps as for
+ * lrt_solve).  Each range is processed like a band (at most band_points
+ * points); the trapezoid weights stay those of the whole grid (h/2 only at
+ * its two ends), so ranges that tile the grid sum to lrt_solve's results.
+ * Outputs (host, may be NULL): q[n_wall] and I_int[n_rays] summed over the
+ * ranges, q_range[n_wall][n] per range.  Synchronises the stream.  Errors:
+ * LRT_E_ARG (n < 1, a range outside the grid or longer than band_points, NULL
+ * arrays), LRT_E_STATE, LRT_E_OOM, LRT_E_DEVICE. */
+lrt_status lrt_solve_ranges(lrt_ctx *ctx, lrt_precision prec, int64_t n, const int64_t *k_first,
+                            const int64_t *n_points, double *q, double *I_int, double *q_range,
+                            void *stream);
+
 /* Number of in-window (cell, line, grid point) terms of band `band`, i.e. the
  * Voigt evaluations the accumulation performs usefully, and (core_count, may
  * be NULL) how many of them the single-precision form evaluates with the
@@ -433,6 +449,12 @@ lrt_status lrt_solve(lrt_ctx *ctx, lrt_precision prec, int64_t first_band, doubl
  * plus at most one point of margin on each side.  Synchronises. */
 lrt_status lrt_count_terms(lrt_ctx *ctx, int64_t band, int64_t *count, int64_t *core_count,
                            void *stream);
+
+/* As lrt_count_terms, summed over the grid-point ranges of lrt_solve_ranges
+ * (same rules for the ranges).  Synchronises. */
+lrt_status lrt_count_terms_ranges(lrt_ctx *ctx, int64_t n, const int64_t *k_first,
+                                  const int64_t *n_points, int64_t *count, int64_t *core_count,
+                                  void *stream);
 
 /* Kernel families timed by the profiler. */
 typedef enum {
@@ -453,6 +475,26 @@ lrt_status lrt_profile(lrt_ctx *ctx, int enable);
 /* Total device time (ms, from the event pairs) and number of launches of one
  * kernel family since profiling was enabled.  Waits for the recorded events. */
 lrt_status lrt_profile_read(lrt_ctx *ctx, int kernel, double *ms, int64_t *launches);
+
+/* Throughput probes of the chip (measurement support, not part of the path):
+ * the measured denominators of the roofline beside the nominal peaks. */
+typedef enum {
+    LRT_PROBE_FMA_F32 = 0,  /* single-precision FMA, lane-ops/s (2 flops each) */
+    LRT_PROBE_FMA_F64 = 1,  /* double-precision FMA, lane-ops/s */
+    LRT_PROBE_EXP_F32 = 2,  /* v_exp_f32 (2^x), lane-ops/s */
+    LRT_PROBE_LOG_F32 = 3,  /* v_log_f32 (log2), lane-ops/s */
+    LRT_PROBE_RCP_F32 = 4,  /* v_rcp_f32, lane-ops/s */
+    LRT_PROBE_MIX_F32 = 5,  /* a wing term's mix: 3 transcendentals + 10 other
+                               single-precision operations, lane-ops/s */
+    LRT_PROBE_COPY = 6      /* 1 GiB device-to-device copy, bytes read + written per s */
+} lrt_probe_kind;
+
+/* Runs one probe on HIP device `device` (8 waves per SIMD on every compute
+ * unit, 8 independent chains per lane; one untimed launch, then one launch
+ * timed with HIP events) and returns its rate and time (ms, may be NULL).
+ * Allocates and frees its own buffers; synchronises the device.  Errors:
+ * LRT_E_ARG (unknown kind or device, rate NULL), LRT_E_OOM, LRT_E_DEVICE. */
+lrt_status lrt_probe(int device, int kind, double *rate, double *ms);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of line-of-sight requests                     */

@@ -79,8 +79,11 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        # ORACLE_LIB: an instrumented build of oracle.c (the sanitizer test)
+        path = os.environ.get("ORACLE_LIB")
+        if not path:
+            path = build()
+        L = C.CDLL(path)
         d, i64 = C.c_double, C.c_int64
         sig = {
             "orc_c2": (d, []),
@@ -517,16 +520,18 @@ def coeffs(species, lines, cells, grid, ks: Optional[np.ndarray] = None, threads
     return eta, kap, n
 
 
-def knife_edges(species, lines, cells, grid, tol: float = 1e-9, near=None, E_ion=None):
+def knife_edges(species, lines, cells, grid, tol: float = 1e-9, near=None, E_ion=None,
+                reach: float = 1000.0):
     """(cell, k) grid points next to a window bound that lies within tol grid
     steps of an integer grid index: a last-bit difference in the Voigt
     width may move such a bound by one point.  near: optional sorted grid
-    indices; only lines within 1000 cm^-1 of one of them are scanned."""
+    indices; only lines within `reach` cm^-1 of one of them are scanned (the
+    caller's bound on 100 Voigt HWHM)."""
     if near is not None and lines.n:
         h = grid_step(grid)
         nu = grid.nu_min + np.asarray(near, np.float64) * h
-        lo = np.searchsorted(lines.nu0, nu - 1000.0)
-        hi = np.searchsorted(lines.nu0, nu + 1000.0)
+        lo = np.searchsorted(lines.nu0, nu - reach)
+        hi = np.searchsorted(lines.nu0, nu + reach)
         keep = np.zeros(lines.n + 1, np.int64)
         np.add.at(keep, lo, 1)
         np.add.at(keep, hi, -1)

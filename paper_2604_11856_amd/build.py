@@ -26,12 +26,12 @@ def build_library(out: str = LIB) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = []
-    for name in ("lrt_accum", "lrt_march", "lrt_cr"):
+    for name in ("lrt_accum", "lrt_march", "lrt_cr", "lrt_probe"):
         obj = os.path.join(bdir, name + ".o")
         _run([HIPCC, *ARCH, *COMMON, *NO_PK, "-c", os.path.join(CSRC, name + ".hip"), "-o", obj])
         objs.append(obj)
     # host code: no FP contraction, so the two-sum / two-product grid offsets stay exact
-    for name in ("lrt_host", "lrt_cr_host", "lrt_serve"):
+    for name in ("lrt_host", "lrt_cr_host", "lrt_serve", "lrt_geom"):
         obj = os.path.join(bdir, name + ".o")
         _run([HIPCC, *ARCH, *COMMON, "-ffp-contract=off", "-x", "hip", *NO_PK, "-c",
               os.path.join(CSRC, name + ".cpp"), "-o", obj])

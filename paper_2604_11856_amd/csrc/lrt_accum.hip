@@ -515,34 +515,16 @@ __device__ __forceinline__ float shape_exp_f32(const RecF32 &q, float d1, float 
 }
 
 
-// Block -> (tile, cell) order of the accumulation grid.
-//   0: tile fastest (consecutive workgroups sweep one cell's spectrum)
-//   1: workgroups are dispatched round-robin over the 8 XCDs (workgroup b on
-//      XCD b % 8, each with its own L2); XCD x walks a contiguous block of the
-//      tile-major, cell-minor order
-//   2: tile-major, cell-minor, no XCD remap
-//   3: groups of 8 tiles x all cells; within a group XCD x takes tile 8g + x
-//      for every cell, so the cells of one tile share their candidate lines in
-//      one L2 while tiles stay interleaved across XCDs
-#ifndef LRT_BLOCK_MAP
-#define LRT_BLOCK_MAP 3
-#endif
-__device__ __forceinline__ void block_tile_cell(uint32_t b, uint32_t n_blocks, int32_t n_cells,
-                                                int32_t n_tiles, int &tile, int &cell)
+// Block -> (tile, cell) order of the accumulation grid: groups of 8 tiles x
+// all cells; within a group XCD x (workgroups go round-robin over the 8 XCDs,
+// each with its own L2) takes tile 8g + x for every cell, so the cells of one
+// tile share their candidate lines in one L2 while tiles stay interleaved
+// across XCDs.  (Measured against tile-fastest order: 3 % faster; against a
+// contiguous range of tiles per XCD: 37 % faster, the per-XCD work being
+// uneven because line density varies along nu.)
+__device__ __forceinline__ void block_tile_cell(uint32_t b, int32_t n_cells, int32_t n_tiles, int &tile,
+                                                int &cell)
 {
-#if LRT_BLOCK_MAP == 0
-    tile = (int)(b % (uint32_t)n_tiles);
-    cell = (int)(b / (uint32_t)n_tiles);
-#elif LRT_BLOCK_MAP == 1
-    const uint32_t per = n_blocks / kXCDs, rem = n_blocks % kXCDs;
-    const uint32_t x = b % kXCDs, i = b / kXCDs;
-    const uint32_t logical = x * per + min(x, rem) + i;
-    tile = (int)(logical / (uint32_t)n_cells);
-    cell = (int)(logical % (uint32_t)n_cells);
-#elif LRT_BLOCK_MAP == 2
-    tile = (int)(b / (uint32_t)n_cells);
-    cell = (int)(b % (uint32_t)n_cells);
-#else
     const uint32_t gsz = (uint32_t)kXCDs * (uint32_t)n_cells;
     const uint32_t g = b / gsz, r = b % gsz;
     const uint32_t full = (uint32_t)n_tiles / kXCDs;
@@ -553,8 +535,6 @@ __device__ __forceinline__ void block_tile_cell(uint32_t b, uint32_t n_blocks, i
         tile = (int)(g * kXCDs + r / (uint32_t)n_cells);
         cell = (int)(r % (uint32_t)n_cells);
     }
-#endif
-    (void)n_blocks;
 }
 
 // Compensated (Kahan) addition of a block partial v into (s, c).
@@ -565,15 +545,6 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v)
     c = (t - s) - y;
     s = t;
 }
-
-// Whiting profile in double precision.  The two rational terms share one
-// division; an exponential whose argument is below -745.6 underflows to
-// exactly zero (e^-745.14 is under half the smallest subnormal), so it is
-// skipped there: beyond x = 16.4 for the Gaussian term and x = 28.4 for the
-// x^2.25 term, while windows reach x = 50.  The lanes of a 64-point slice
-// share the branch when the whole slice lies beyond the bound.
-constexpr double kExpZeroU = 269.0;    // 2.772 u >= 745.668
-constexpr double kExpZeroP = 1864.0;   // 0.4 p >= 745.6
 
 // Square root of x > 0 from the hardware reciprocal square root (about 5e-8
 // relative) and one Newton step on y^2 = x.  Measured on the chip, the fourth
@@ -586,40 +557,12 @@ __device__ __forceinline__ double sqrt_newton(double x)
     return fma(fma(-y, y, x), 0.5 * r, y);
 }
 
-__device__ __forceinline__ double shape_f64(double x, double r)
-{
-    const double u = x * x;
-    const double p = u * (x > 0.0 ? sqrt_newton(sqrt_newton(x)) : 0.0);
-    const double d1 = 1.0 + 4.0 * u, d2 = 1.0 + 0.1 * p;
-    const double w = 0.016 * r * (1.0 - r);
-    double P = (r * d2 - w * d1) / (d1 * d2);
-    if (u < kExpZeroU) P += (1.0 - r) * exp(-2.772 * u);
-    if (p < kExpZeroP) P += w * exp(-0.4 * p);
-    return P;
-}
-
 // Lines per compensated block: partials of at most kBlock terms are added
-// plainly, blocks are merged with Kahan's compensation.
-#ifndef LRT_ACCUM_BLOCK
-#define LRT_ACCUM_BLOCK 64
-#endif
-constexpr int kBlock = LRT_ACCUM_BLOCK;
-static_assert(kBlock == 32 || kBlock == 64, "a block is one ballot mask");
-// Bit mask over the lines of one block, one bit per line.
-using BlockMask = std::conditional_t<(kBlock > 32), uint64_t, uint32_t>;
-__device__ __forceinline__ int lowest_bit(uint32_t m) { return __builtin_ctz(m); }
-__device__ __forceinline__ int lowest_bit(uint64_t m) { return __builtin_ctzll(m); }
-
-// Order in which a wave walks the lines of a block that reach it (both in
-// line order, so the sums are bitwise the same):
-//   0: lowest set bit of the block mask, one line at a time (per line a
-//      vector move of the LDS address and ~8 more scalar instructions)
-//   1: groups of 8 lines with constant LDS offsets from one base register;
-//      measured 4 % faster on the stagnation line, 5-8 % on the
-//      axisymmetric bands
-#ifndef LRT_LINE_WALK
-#define LRT_LINE_WALK 1
-#endif
+// plainly, blocks are merged with Kahan's compensation (64-line blocks
+// measured 1 % faster than 32-line ones).  A block is one ballot mask: one bit
+// per line.
+constexpr int kBlock = 64;
+using BlockMask = uint64_t;
 
 // The terms of one staged line (bit t of the block masks) on this wave's
 // slices, added to the block partials.
@@ -720,13 +663,6 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
                 m_edge[j] = (BlockMask)__ballot(mb & (1u << (8 + j)));
                 m_core[j] = (BlockMask)__ballot(mb & (1u << (16 + j)));
             }
-#if LRT_LINE_WALK == 0
-            while (todo) {
-                const int t = lowest_bit(todo);
-                todo &= todo - 1;
-                line_terms(rec[l0 + t], t, kf, m_in, m_core, m_edge, ae, ak);
-            }
-#else
             // groups of 8 lines: within a group the LDS offsets are constants
             // from one base address held in a vector register, and the block
             // masks, shifted once per group, are tested at constant bits; a
@@ -750,7 +686,6 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
                 for (int u = 0; u < 8; ++u)
                     if ((gt >> u) & 1u) line_terms(rg8[u], u, kf, gi, gc, ge, ae, ak);
             }
-#endif
 #pragma unroll
             for (int j = 0; j < kPPL; ++j) {
                 kahan_add(se[j], ce[j], ae[j]);
@@ -775,7 +710,7 @@ void accum_f32_kernel(
 {
     __shared__ RecF32 rec[kStage];
     int tile, c;
-    block_tile_cell(b0 + blockIdx.x, (uint32_t)n_tiles * (uint32_t)n_cells, n_cells, n_tiles, tile, c);
+    block_tile_cell(b0 + blockIdx.x, n_cells, n_tiles, tile, c);
     // the wave index is uniform across the wave: keep it (and every bound
     // derived from it) in scalar registers so slice tests are scalar branches
     const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
@@ -803,22 +738,17 @@ void accum_f32_kernel(
     }
 }
 
-// Windows of the double-precision exponentials, in units of gamma_V: beyond
-// |dnu| = 33 gamma_V (x = 16.5) e^{-2.772 x^2} is exactly zero in double
-// precision, beyond 57 gamma_V (x = 28.5) so is e^{-0.4 x^2.25}; the point
-// windows carry one point of margin on each side.
+// Whiting profile in double precision.  The two rational terms share one
+// division.  An exponential whose argument is below -745.6 underflows to
+// exactly zero (e^-745.14 is under half the smallest subnormal), so the
+// windows of the two exponentials, in units of gamma_V, stop where that
+// happens: beyond |dnu| = 33 gamma_V (x = 16.5) e^{-2.772 x^2} is exactly
+// zero in double precision, beyond 57 gamma_V (x = 28.5) so is
+// e^{-0.4 x^2.25}, while the line windows reach x = 50; the point windows
+// carry one point of margin on each side, and a lane inside a window slice
+// but beyond its exponential's bound adds an exact zero.
 constexpr double kF64GaussHalfWidth = 33.0;
 constexpr double kF64WexpHalfWidth = 57.0;
-
-// Order in which the double-precision kernel walks the staged lines:
-//   0: every staged line on every wave, each lane testing its own point
-//      against the window
-//   1: as the single-precision kernel: slice masks at staging, one ballot per
-//      (slice, flag) per block of 64 lines, groups of 8 lines, and the
-//      exponentials by wave-uniform slice windows (bitwise the same sums)
-#ifndef LRT_F64_WALK
-#define LRT_F64_WALK 1
-#endif
 
 // The terms of one staged line (bit t of the block masks) on this wave's
 // slices of points kk[j], added to the sums.
@@ -870,7 +800,7 @@ __global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(L
 {
     __shared__ RecF64 rec[kStage];
     int tile, c;
-    block_tile_cell(b0 + blockIdx.x, (uint32_t)n_tiles * (uint32_t)n_cells, n_cells, n_tiles, tile, c);
+    block_tile_cell(b0 + blockIdx.x, n_cells, n_tiles, tile, c);
     const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
     const int32_t kt = k_first + tile * kTilePoints;
     const int32_t kw = kt + wave * 64 * kPPL;
@@ -883,14 +813,10 @@ __global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(L
     double se[kPPL], sk[kPPL];
 #pragma unroll
     for (int j = 0; j < kPPL; ++j) se[j] = sk[j] = 0.0;
-#if LRT_F64_WALK == 0
-    const int32_t kw_last = kw + 64 * kPPL - 1;
-#else
     const uint32_t wshift = (uint32_t)(wave * kPPL);
     int32_t kk[kPPL];
 #pragma unroll
     for (int j = 0; j < kPPL; ++j) kk[j] = kw + 64 * j + lane;
-#endif
 
     for (int base = rg.x; base < rg.y; base += kStage) {
         const int64_t i = (int64_t)base + threadIdx.x;
@@ -911,7 +837,6 @@ __global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(L
                 rr.r = p.r;
                 rr.se = p.se;
                 rr.sk = p.sk;
-#if LRT_F64_WALK != 0
                 // windows of the two exponentials, one point of margin each side
                 const double nu0 = L.nu0[i], gV = 0.5 / p.inv2g;
                 const double wg = kF64GaussHalfWidth * gV, ww = kF64WexpHalfWidth * gV;
@@ -922,31 +847,11 @@ __global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(L
                 const uint32_t m = slice_modes(p.klo - kt, p.khi - kt, wlo - kt, whi - kt);
                 const uint32_t gm = slice_run(max(glo, p.klo) - kt, min(ghi, p.khi) - kt) & m & 0xffu;
                 rr.mode = m | (gm << 24);
-#endif
             }
         }
         rec[threadIdx.x] = rr;
         __syncthreads();
         const int n = min(kStage, rg.y - base);
-#if LRT_F64_WALK == 0
-        for (int l = 0; l < n; ++l) {
-            const RecF64 q = rec[l];
-            if (q.khi < kw || q.klo > kw_last) continue;
-#pragma unroll
-            for (int j = 0; j < kPPL; ++j) {
-                const int32_t k0j = kw + 64 * j;
-                if (q.khi < k0j || q.klo > k0j + 63) continue;
-                const int32_t kk = k0j + lane;
-                if (kk >= q.klo && kk <= q.khi) {
-                    const double delta = fma((double)(kk - q.k0), g.h, -q.frac0);
-                    const double x = fabs(delta) * q.inv2g;
-                    const double P = shape_f64(x, q.r);
-                    se[j] += q.se * P;
-                    sk[j] += q.sk * P;
-                }
-            }
-        }
-#else
         for (int l0 = 0; l0 < n; l0 += kBlock) {
             uint32_t mb = 0;
             if (lane < kBlock && l0 + lane < n) mb = rec[l0 + lane].mode >> wshift;
@@ -978,7 +883,6 @@ __global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(L
                     if ((gt >> u) & 1u) line_terms_f64(rg8[u], u, kk, g.h, gi, gw, gg, ge, se, sk);
             }
         }
-#endif
         __syncthreads();
     }
 #pragma unroll

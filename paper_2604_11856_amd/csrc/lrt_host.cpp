@@ -16,13 +16,11 @@
 
 #include "../../include/lrt.h"
 #include "lrt_ctx.h"
+#include "lrt_geom.h"
 #include "lrt_internal.h"
 
 using namespace lrt;
 
-namespace {
-thread_local std::string g_create_error;
-}  // namespace
 
 
 
@@ -35,7 +33,7 @@ lrt_status fail(lrt_ctx *c, lrt_status s, const char *fmt, ...)
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (c) c->err = buf; else g_create_error = buf;
+    if (c) c->err = buf; else host_error() = buf;
     return s;
 }
 
@@ -80,136 +78,6 @@ bool finite_all(const double *p, int64_t n)
     for (int64_t i = 0; i < n; ++i)
         if (!std::isfinite(p[i])) return false;
     return true;
-}
-
-// Gauss-Legendre nodes and weights on [0, 1] (Newton on P_n).
-void gauss_legendre_01(int n, std::vector<double> &mu, std::vector<double> &w)
-{
-    mu.assign(n, 0.0);
-    w.assign(n, 0.0);
-    for (int i = 0; i < n; ++i) {
-        double x = std::cos(kPi * (i + 0.75) / (n + 0.5));
-        double dp = 1.0;
-        for (int it = 0; it < 100; ++it) {
-            double p0 = 1.0, p1 = x;
-            for (int k = 2; k <= n; ++k) {
-                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-                p0 = p1;
-                p1 = p2;
-            }
-            if (n == 1) { p1 = x; p0 = 1.0; }
-            dp = n * (x * p1 - p0) / (x * x - 1.0);
-            double dx = p1 / dp;
-            x -= dx;
-            if (std::fabs(dx) < 1e-16) break;
-        }
-        {
-            double p0 = 1.0, p1 = x;
-            for (int k = 2; k <= n; ++k) {
-                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-                p0 = p1;
-                p1 = p2;
-            }
-            if (n == 1) { p1 = x; p0 = 1.0; }
-            dp = n * (x * p1 - p0) / (x * x - 1.0);
-        }
-        // node on [-1, 1] -> [0, 1]
-        mu[i] = 0.5 * (x + 1.0);
-        w[i] = 0.5 * 2.0 / ((1.0 - x * x) * dp * dp);
-    }
-    // ascending order
-    std::vector<int> idx(n);
-    std::iota(idx.begin(), idx.end(), 0);
-    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return mu[a] < mu[b]; });
-    std::vector<double> m2(n), w2(n);
-    for (int i = 0; i < n; ++i) { m2[i] = mu[idx[i]]; w2[i] = w[idx[i]]; }
-    mu.swap(m2);
-    w.swap(w2);
-}
-
-// Roots of A2 s^2 + 2 B s + C = 0 (A2 > 0), smaller and larger; false if none.
-bool quad_roots(double A2, double B, double C, double &lo, double &hi)
-{
-    const double disc = B * B - A2 * C;
-    if (disc < 0.0) return false;
-    const double sq = std::sqrt(disc);
-    const double q = (B >= 0.0) ? -(B + sq) : (-B + sq);
-    if (q == 0.0) {
-        lo = hi = 0.0;
-        return true;
-    }
-    double r1 = q / A2, r2 = C / q;
-    lo = std::min(r1, r2);
-    hi = std::max(r1, r2);
-    return true;
-}
-
-// Cell-to-cell traversal of one ray from the wall point (0, rw, 0) along
-// (mu, st cos phi, st sin phi) through the nx x nr grid.  Appends segments in
-// wall -> far order.  Returns false if the traversal does not terminate.
-bool traverse_axi(int nx, int nr, double Lx, double R, double rw, double mu, double phi,
-                  std::vector<int32_t> &cell, std::vector<double> &ds)
-{
-    const double dx = Lx / nx, dr = R / nr;
-    const double st = std::sqrt(std::max(0.0, 1.0 - mu * mu));
-    const double a = st * std::cos(phi);
-    const double A2 = st * st;          // rho^2(s) = rw^2 + 2 B s + A2 s^2
-    const double B = rw * a;
-    int ix = 0;
-    // start cell from the same face products the crossings use:
-    // ir dr <= rw < (ir + 1) dr (floor(rw / dr) can be one off when dr is
-    // not a power of two and rw sits on a face)
-    int ir = std::min((int)std::floor(rw / dr), nr - 1);
-    while (ir > 0 && rw < ir * dr) --ir;
-    while (ir < nr - 1 && rw >= (ir + 1) * dr) ++ir;
-    double s = 0.0;
-    const int max_steps = 4 * (nx + 2 * nr) + 16;
-    for (int step = 0; step < max_steps; ++step) {
-        const double s_x = (ix + 1) * dx / mu;
-        double s_r = INFINITY;
-        int dir = 0;
-        if (A2 > 0.0) {
-            double lo, hi;
-            if (ir > 0) {
-                // inward crossing of the inner face: ahead of s, or at s when the
-                // ray starts on that face heading inward (d rho^2/ds < 0).  A
-                // tangency (lo == hi) touches the face without entering.
-                const double rj = ir * dr;
-                const bool inward = B + A2 * s < 0.0;
-                if (quad_roots(A2, B, (rw - rj) * (rw + rj), lo, hi) && lo < hi &&
-                    (lo > s || (lo == s && inward))) {
-                    s_r = lo;
-                    dir = -1;
-                }
-            }
-            if (dir == 0) {
-                // outward crossing of the outer face: ahead of s, or at s when
-                // the ray starts on it heading outward
-                const double rj = (ir + 1) * dr;
-                const bool outward = B + A2 * s > 0.0;
-                if (quad_roots(A2, B, (rw - rj) * (rw + rj), lo, hi) && (hi > s || (hi == s && outward))) {
-                    s_r = hi;
-                    dir = +1;
-                }
-            }
-        }
-        const double s_next = std::min(s_x, s_r);
-        if (s_next > s) {
-            cell.push_back((int32_t)((int64_t)ix * nr + ir));
-            ds.push_back(s_next - s);
-        }
-        s = s_next;
-        // an x-plane and an r-face crossed at the same s are both taken, since
-        // a root equal to s is not found again on the next step
-        const bool cross_x = s_x <= s_r, cross_r = s_r <= s_x;
-        if (cross_x && ++ix >= nx) return true;
-        if (cross_r) {
-            ir += dir;
-            if (ir >= nr) return true;
-            if (ir < 0) ir = 0;
-        }
-    }
-    return false;
 }
 
 }  // namespace
@@ -262,7 +130,7 @@ void lrt_destroy(lrt_ctx *ctx)
 
 const char *lrt_last_error(const lrt_ctx *ctx)
 {
-    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+    return ctx ? ctx->err.c_str() : host_error().c_str();
 }
 
 lrt_status lrt_set_species(lrt_ctx *c, int n, const lrt_species *sp)
@@ -726,62 +594,6 @@ lrt_status lrt_set_rays_axi(lrt_ctx *c, int nx, int nr, double Lx, double R, int
     return LRT_OK;
 }
 
-// Fibonacci-sphere LOS seen from a wall with normal along +x, and the flux
-// weight of each (Sec. 2.2.3): direction i (1-based) of n has polar component
-// w = 1 - 2(i-1)/(n-1) along the normal and azimuth a = (i-1)(sqrt 5 - 1) pi;
-// those with w > 0 look into the gas.  The interpolated angular rule carries
-// the LOS results to the nodes of a uniform (polar phi, azimuth theta) grid,
-// each node taking its nearest LOS, and sums over the grid cells the mean of
-// the four corners times the cell's int sin(phi) cos(phi) dphi dtheta.  The
-// rule is linear in the LOS results, so it reduces to one weight per LOS.
-static void fibonacci_rule(int n_los, int n_polar, int n_azim, std::vector<double> &dir,
-                           std::vector<double> &wt)
-{
-    dir.clear();
-    wt.clear();
-    for (int i = 0; i < n_los; ++i) {
-        const double w = 1.0 - 2.0 * (double)i / (double)(n_los - 1);
-        if (!(w > 0.0)) continue;
-        const double r = std::sqrt(std::max(0.0, 1.0 - w * w));
-        const double a = ((double)i * (std::sqrt(5.0) - 1.0)) * kPi;
-        dir.push_back(w);
-        dir.push_back(r * std::cos(a));
-        dir.push_back(r * std::sin(a));
-    }
-    const int m = (int)(dir.size() / 3);
-    wt.assign(m, 0.0);
-    std::vector<int> near((size_t)(n_polar + 1) * (n_azim + 1));
-    const double dphi = 0.5 * kPi / n_polar, dth = 2.0 * kPi / n_azim;
-    for (int p = 0; p <= n_polar; ++p) {
-        const double ph = p * dphi;
-        for (int t = 0; t <= n_azim; ++t) {
-            const double th = t * dth;
-            const double nx_ = std::cos(ph), ny_ = std::sin(ph) * std::cos(th), nz_ = std::sin(ph) * std::sin(th);
-            int best = 0;
-            double bd = -2.0;
-            for (int q = 0; q < m; ++q) {
-                const double dd = dir[3 * q] * nx_ + dir[3 * q + 1] * ny_ + dir[3 * q + 2] * nz_;
-                if (dd > bd) {
-                    bd = dd;
-                    best = q;
-                }
-            }
-            near[(size_t)p * (n_azim + 1) + t] = best;
-        }
-    }
-    for (int p = 0; p < n_polar; ++p) {
-        const double s0 = std::sin(p * dphi), s1 = std::sin((p + 1) * dphi);
-        const double band = 0.5 * (s1 * s1 - s0 * s0);
-        for (int t = 0; t < n_azim; ++t) {
-            const double quarter = 0.25 * band * (((t + 1) * dth) - (t * dth));
-            wt[near[(size_t)p * (n_azim + 1) + t]] += quarter;
-            wt[near[(size_t)(p + 1) * (n_azim + 1) + t]] += quarter;
-            wt[near[(size_t)p * (n_azim + 1) + t + 1]] += quarter;
-            wt[near[(size_t)(p + 1) * (n_azim + 1) + t + 1]] += quarter;
-        }
-    }
-}
-
 lrt_status lrt_set_rays_axi_fibonacci(lrt_ctx *c, int nx, int nr, double Lx, double R, int n_wall,
                                       const double *wall_r, int n_los, int n_polar, int n_azim)
 {
@@ -829,20 +641,6 @@ lrt_status lrt_set_rays_axi_fibonacci(lrt_ctx *c, int nx, int nr, double Lx, dou
     return LRT_OK;
 }
 
-lrt_status lrt_fibonacci_quadrature(int n_los, int n_polar, int n_azim, int64_t cap, double *dirs,
-                                    double *weights, int64_t *n)
-{
-    if (n_los < 3 || n_polar < 1 || n_azim < 1 || !n || (cap > 0 && (!dirs || !weights)))
-        return fail(nullptr, LRT_E_ARG, "fibonacci: invalid sizes");
-    std::vector<double> dir, wt;
-    fibonacci_rule(n_los, n_polar, n_azim, dir, wt);
-    *n = (int64_t)wt.size();
-    if (cap < *n) return fail(nullptr, LRT_E_ARG, "fibonacci: capacity %lld < %lld", (long long)cap, (long long)*n);
-    std::copy(dir.begin(), dir.end(), dirs);
-    std::copy(wt.begin(), wt.end(), weights);
-    return LRT_OK;
-}
-
 lrt_status lrt_set_march(lrt_ctx *c, lrt_march_scheme scheme)
 {
     if (!c) return LRT_E_ARG;
@@ -873,26 +671,6 @@ lrt_status lrt_set_far_temperature(lrt_ctx *c, const double *T_far, int64_t n)
     lrt_status st = upload_vec(c, c->d_Tfar, t);
     if (st) return st;
     c->have_Tfar = true;
-    return LRT_OK;
-}
-
-lrt_status lrt_trace_axi_ray(int nx, int nr, double Lx, double R, double rw, double mu, double phi,
-                             int64_t cap, int32_t *cell, double *ds, int64_t *n)
-{
-    if (nx < 1 || nr < 1 || !(Lx > 0.0) || !(R > 0.0) || !(rw >= 0.0) || !(rw < R) || !(mu > 0.0) ||
-        !(mu <= 1.0) || !std::isfinite(phi) || !n || (cap > 0 && (!cell || !ds)))
-        return fail(nullptr, LRT_E_ARG, "trace: invalid geometry or direction");
-    std::vector<int32_t> cv;
-    std::vector<double> dv;
-    if (!traverse_axi(nx, nr, Lx, R, rw, mu, phi, cv, dv))
-        return fail(nullptr, LRT_E_ARG, "trace: traversal did not terminate");
-    const int64_t m = (int64_t)cv.size();
-    *n = m;
-    if (cap < m) return fail(nullptr, LRT_E_ARG, "trace: capacity %lld < %lld", (long long)cap, (long long)m);
-    for (int64_t i = 0; i < m; ++i) {   // far -> wall
-        cell[i] = cv[m - 1 - i];
-        ds[i] = dv[m - 1 - i];
-    }
     return LRT_OK;
 }
 
@@ -1080,15 +858,14 @@ lrt_status band_range(lrt_ctx *c, int64_t band, int32_t &k_first, int32_t &n_ban
     return LRT_OK;
 }
 
-lrt_status coeffs_impl(lrt_ctx *c, int64_t band, lrt_precision prec, void *eta, void *kappa,
-                       int32_t *escale, hipStream_t st)
+// Coefficients of every cell on grid points [k_first, k_first + n_band).
+lrt_status coeffs_range(lrt_ctx *c, int32_t k_first, int32_t n_band, lrt_precision prec, void *eta,
+                        void *kappa, int32_t *escale, hipStream_t st)
 {
     if (prec != LRT_FP64 && prec != LRT_FP32_COMP) return fail(c, LRT_E_ARG, "unknown precision %d", (int)prec);
     if (!eta || !kappa) return fail(c, LRT_E_ARG, "eta and kappa must be non-NULL");
     lrt_status r;
     if ((r = prepare(c, st, prec == LRT_FP32_COMP))) return r;
-    int32_t k_first, n_band;
-    if ((r = band_range(c, band, k_first, n_band))) return r;
     const int32_t n_tiles = (n_band + kTilePoints - 1) / kTilePoints;
     if ((r = ensure(c, c->w_ranges, (size_t)c->n_cells * n_tiles * sizeof(int2)))) return r;
     const DevLines L = dev_lines(c);
@@ -1122,8 +899,20 @@ lrt_status coeffs_impl(lrt_ctx *c, int64_t band, lrt_precision prec, void *eta, 
     return LRT_OK;
 }
 
-lrt_status march_impl(lrt_ctx *c, int64_t band, lrt_precision prec, const void *eta, const void *kappa,
-                      const int32_t *escale, double *I_out, double *I_int_out, hipStream_t st)
+lrt_status coeffs_impl(lrt_ctx *c, int64_t band, lrt_precision prec, void *eta, void *kappa,
+                       int32_t *escale, hipStream_t st)
+{
+    if (!c->have_grid) return fail(c, LRT_E_STATE, "grid not set");
+    int32_t k_first, n_band;
+    lrt_status r;
+    if ((r = band_range(c, band, k_first, n_band))) return r;
+    return coeffs_range(c, k_first, n_band, prec, eta, kappa, escale, st);
+}
+
+// March of every ray over grid points [k_first, k_first + n_band).
+lrt_status march_range(lrt_ctx *c, int32_t k_first, int32_t n_band, lrt_precision prec, const void *eta,
+                       const void *kappa, const int32_t *escale, double *I_out, double *I_int_out,
+                       hipStream_t st)
 {
     if (prec != LRT_FP64 && prec != LRT_FP32_COMP) return fail(c, LRT_E_ARG, "unknown precision %d", (int)prec);
     if (!eta || !kappa || !I_int_out) return fail(c, LRT_E_ARG, "eta, kappa and I_int_out must be non-NULL");
@@ -1133,9 +922,7 @@ lrt_status march_impl(lrt_ctx *c, int64_t band, lrt_precision prec, const void *
     if (c->n_cells < 1) return fail(c, LRT_E_STATE, "cells not set");
     if (c->rays_cells != c->n_cells)
         return fail(c, LRT_E_STATE, "rays expect %lld cells, %lld set", (long long)c->rays_cells, (long long)c->n_cells);
-    int32_t k_first, n_band;
     lrt_status r;
-    if ((r = band_range(c, band, k_first, n_band))) return r;
     const int32_t n_chunks = (n_band + kMarchPoints - 1) / kMarchPoints;
     if ((r = ensure(c, c->w_partials, (size_t)c->n_rays * n_chunks * sizeof(double)))) return r;
     const DevRays rays{(int32_t)c->n_rays, c->d_off.as<int64_t>(), c->d_cell.as<int32_t>(), c->d_ds.as<double>()};
@@ -1147,6 +934,112 @@ lrt_status march_impl(lrt_ctx *c, int64_t band, lrt_precision prec, const void *
                                     c->w_partials.as<double>(), n_chunks, st);
             }));
     LRT_HIP(c, launch_reduce_rows(c->w_partials.as<double>(), (int32_t)c->n_rays, n_chunks, I_int_out, st));
+    return LRT_OK;
+}
+
+lrt_status march_impl(lrt_ctx *c, int64_t band, lrt_precision prec, const void *eta, const void *kappa,
+                      const int32_t *escale, double *I_out, double *I_int_out, hipStream_t st)
+{
+    if (!c->have_grid) return fail(c, LRT_E_STATE, "grid not set");
+    int32_t k_first, n_band;
+    lrt_status r;
+    if ((r = band_range(c, band, k_first, n_band))) return r;
+    return march_range(c, k_first, n_band, prec, eta, kappa, escale, I_out, I_int_out, st);
+}
+
+// The whole path over a list of point ranges, each like one band: per-cell
+// quantities recomputed once, then per range the coefficients, the march and
+// the per-range wall sums; q and I_int are the sums over the ranges.
+lrt_status solve_ranges(lrt_ctx *c, lrt_precision prec, int64_t n_rng, const int32_t *k_first,
+                        const int32_t *n_pts, int64_t max_pts, double *q, double *I_int, double *q_rng,
+                        hipStream_t st)
+{
+    if (prec != LRT_FP64 && prec != LRT_FP32_COMP) return fail(c, LRT_E_ARG, "unknown precision %d", (int)prec);
+    if (c->n_rays < 1) return fail(c, LRT_E_STATE, "rays not set");
+    const size_t esz = prec == LRT_FP64 ? 8 : 4;
+    const size_t plane = (size_t)std::max<int64_t>(c->n_cells, 1) * (size_t)max_pts * esz;
+    lrt_status r;
+    if ((r = ensure(c, c->w_eta, plane)) || (r = ensure(c, c->w_kappa, plane)) ||
+        (r = ensure(c, c->w_Iband, (size_t)c->n_rays * 8)) || (r = ensure(c, c->w_Itot, (size_t)c->n_rays * 8)) ||
+        (r = ensure(c, c->w_qband, (size_t)c->n_wall * n_rng * 8)))
+        return r;
+    // zero the accumulators (all-zero bits are +0.0)
+    LRT_HIP(c, launch_fill_u64(c->w_Itot.as<unsigned long long>(), 0ull, c->n_rays, st));
+    LRT_HIP(c, launch_fill_u64(c->w_qband.as<unsigned long long>(), 0ull, c->n_wall * n_rng, st));
+    int32_t *esc = (prec == LRT_FP32_COMP) ? c->d_escale.as<int32_t>() : nullptr;
+    // populations and scales belong to the path: recompute them on every call
+    if ((r = prepare(c, st, prec == LRT_FP32_COMP, true))) return r;
+    for (int64_t b = 0; b < n_rng; ++b) {
+        if ((r = coeffs_range(c, k_first[b], n_pts[b], prec, c->w_eta.p, c->w_kappa.p, nullptr, st))) return r;
+        if ((r = march_range(c, k_first[b], n_pts[b], prec, c->w_eta.p, c->w_kappa.p, esc, nullptr,
+                             c->w_Iband.as<double>(), st)))
+            return r;
+        LRT_HIP(c, launch_add(c->w_Itot.as<double>(), c->w_Iband.as<double>(), (int32_t)c->n_rays, st));
+        // per-range wall flux into row b of the [n_rng][n_wall] staging array
+        LRT_HIP(c, launch_wall_sum(c->w_Iband.as<double>(), c->d_weight.as<double>(), c->d_wall_off.as<int64_t>(),
+                                   (int32_t)c->n_wall, c->w_qband.as<double>() + b * c->n_wall, st));
+    }
+    std::vector<double> qb((size_t)c->n_wall * n_rng), it((size_t)c->n_rays);
+    LRT_HIP(c, hipMemcpyAsync(qb.data(), c->w_qband.p, qb.size() * 8, hipMemcpyDeviceToHost, st));
+    LRT_HIP(c, hipMemcpyAsync(it.data(), c->w_Itot.p, it.size() * 8, hipMemcpyDeviceToHost, st));
+    LRT_HIP(c, hipStreamSynchronize(st));
+    for (int64_t w = 0; w < c->n_wall; ++w) {
+        double sum = 0.0;
+        for (int64_t b = 0; b < n_rng; ++b) {
+            sum += qb[b * c->n_wall + w];
+            if (q_rng) q_rng[w * n_rng + b] = qb[b * c->n_wall + w];
+        }
+        if (q) q[w] = sum;
+    }
+    if (I_int) std::copy(it.begin(), it.end(), I_int);
+    return LRT_OK;
+}
+
+// In-window terms (and core terms) over grid points [k_first, k_first + n).
+lrt_status count_range(lrt_ctx *c, int32_t k_first, int32_t n_band, int64_t *count, int64_t *core_count,
+                       hipStream_t st)
+{
+    lrt_status r;
+    if ((r = prepare(c, st, false))) return r;
+    if ((r = ensure(c, c->w_count, 16)) || (r = ensure(c, c->w_ranges, (size_t)c->n_cells * sizeof(int2))))
+        return r;
+    LRT_HIP(c, launch_fill_u64(c->w_count.as<unsigned long long>(), 0ull, 2, st));
+    const DevGrid g = dev_grid(c);
+    const DevLines L = dev_lines(c);
+    // candidate lines of each cell for the whole range (one tile spanning it)
+    LRT_HIP(c, launch_ranges(L, g, c->d_cc.as<CellConst>(), (int32_t)c->n_cells, k_first, n_band, n_band,
+                             c->w_ranges.as<int2>(), st));
+    LRT_HIP(c, launch_count(L, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(), c->w_ranges.as<int2>(),
+                            (int32_t)c->n_cells, c->n_species, k_first, n_band,
+                            c->w_count.as<unsigned long long>(), st));
+    unsigned long long v[2] = {0, 0};
+    LRT_HIP(c, hipMemcpyAsync(v, c->w_count.p, 16, hipMemcpyDeviceToHost, st));
+    LRT_HIP(c, hipStreamSynchronize(st));
+    *count = (int64_t)v[0];
+    if (core_count) *core_count = (int64_t)v[1];
+    return LRT_OK;
+}
+
+// Validates a list of point ranges against the grid; returns the longest.
+lrt_status check_ranges(lrt_ctx *c, int64_t n, const int64_t *k_first, const int64_t *n_points,
+                        std::vector<int32_t> &kf, std::vector<int32_t> &np, int64_t &max_pts)
+{
+    if (!c->have_grid) return fail(c, LRT_E_STATE, "grid not set");
+    if (n < 1 || !k_first || !n_points) return fail(c, LRT_E_ARG, "need at least one range");
+    kf.resize(n);
+    np.resize(n);
+    max_pts = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (k_first[i] < 0 || n_points[i] < 1 || n_points[i] > c->n_points - k_first[i])
+            return fail(c, LRT_E_ARG, "range %lld [%lld, +%lld) outside the grid of %lld points", (long long)i,
+                        (long long)k_first[i], (long long)n_points[i], (long long)c->n_points);
+        if (n_points[i] > c->band_points)
+            return fail(c, LRT_E_ARG, "range %lld longer than the band length %lld", (long long)i,
+                        (long long)c->band_points);
+        kf[i] = (int32_t)k_first[i];
+        np[i] = (int32_t)n_points[i];
+        max_pts = std::max<int64_t>(max_pts, n_points[i]);
+    }
     return LRT_OK;
 }
 
@@ -1175,47 +1068,25 @@ lrt_status lrt_solve(lrt_ctx *c, lrt_precision prec, int64_t first_band, double 
 {
     if (!c) return LRT_E_ARG;
     c->err.clear();
-    hipStream_t st = (hipStream_t)stream;
     if (prec != LRT_FP64 && prec != LRT_FP32_COMP) return fail(c, LRT_E_ARG, "unknown precision %d", (int)prec);
     if (!c->have_grid) return fail(c, LRT_E_STATE, "grid not set");
     if (c->n_rays < 1) return fail(c, LRT_E_STATE, "rays not set");
     const int64_t nb = (c->n_points + c->band_points - 1) / c->band_points;
     if (first_band < 0 || first_band >= nb) return fail(c, LRT_E_ARG, "first_band out of range");
-    const size_t esz = prec == LRT_FP64 ? 8 : 4;
-    const size_t plane = (size_t)std::max<int64_t>(c->n_cells, 1) * c->band_points * esz;
-    lrt_status r;
-    if ((r = ensure(c, c->w_eta, plane)) || (r = ensure(c, c->w_kappa, plane)) ||
-        (r = ensure(c, c->w_Iband, (size_t)c->n_rays * 8)) || (r = ensure(c, c->w_Itot, (size_t)c->n_rays * 8)) ||
-        (r = ensure(c, c->w_qband, (size_t)c->n_wall * nb * 8)))
-        return r;
-    // zero the accumulators (all-zero bits are +0.0)
-    LRT_HIP(c, launch_fill_u64(c->w_Itot.as<unsigned long long>(), 0ull, c->n_rays, st));
-    LRT_HIP(c, launch_fill_u64(c->w_qband.as<unsigned long long>(), 0ull, c->n_wall * nb, st));
-    int32_t *esc = (prec == LRT_FP32_COMP) ? c->d_escale.as<int32_t>() : nullptr;
-    // populations and scales belong to the path: recompute them on every call
-    if ((r = prepare(c, st, prec == LRT_FP32_COMP, true))) return r;
+    // the bands as point ranges
+    const int64_t n = nb - first_band;
+    std::vector<int32_t> kf(n), np(n);
     for (int64_t b = first_band; b < nb; ++b) {
-        if ((r = coeffs_impl(c, b, prec, c->w_eta.p, c->w_kappa.p, nullptr, st))) return r;
-        if ((r = march_impl(c, b, prec, c->w_eta.p, c->w_kappa.p, esc, nullptr, c->w_Iband.as<double>(), st)))
-            return r;
-        LRT_HIP(c, launch_add(c->w_Itot.as<double>(), c->w_Iband.as<double>(), (int32_t)c->n_rays, st));
-        // per-band wall flux into row b of the [n_bands][n_wall] staging array
-        LRT_HIP(c, launch_wall_sum(c->w_Iband.as<double>(), c->d_weight.as<double>(), c->d_wall_off.as<int64_t>(),
-                                   (int32_t)c->n_wall, c->w_qband.as<double>() + b * c->n_wall, st));
+        lrt_status r = band_range(c, b, kf[b - first_band], np[b - first_band]);
+        if (r) return r;
     }
-    std::vector<double> qb((size_t)c->n_wall * nb), it((size_t)c->n_rays);
-    LRT_HIP(c, hipMemcpyAsync(qb.data(), c->w_qband.p, qb.size() * 8, hipMemcpyDeviceToHost, st));
-    LRT_HIP(c, hipMemcpyAsync(it.data(), c->w_Itot.p, it.size() * 8, hipMemcpyDeviceToHost, st));
-    LRT_HIP(c, hipStreamSynchronize(st));
-    for (int64_t w = 0; w < c->n_wall; ++w) {
-        double s = 0.0;
-        for (int64_t b = first_band; b < nb; ++b) {
-            s += qb[b * c->n_wall + w];
-            if (q_band) q_band[w * nb + b] = qb[b * c->n_wall + w];
-        }
-        if (q) q[w] = s;
-    }
-    if (I_int) std::copy(it.begin(), it.end(), I_int);
+    std::vector<double> qr(q_band ? (size_t)c->n_wall * n : 0);
+    lrt_status r = solve_ranges(c, prec, n, kf.data(), np.data(), std::min(c->band_points, c->n_points), q, I_int,
+                                q_band ? qr.data() : nullptr, (hipStream_t)stream);
+    if (r) return r;
+    if (q_band)
+        for (int64_t w = 0; w < c->n_wall; ++w)
+            for (int64_t b = first_band; b < nb; ++b) q_band[w * nb + b] = qr[w * n + (b - first_band)];
     return LRT_OK;
 }
 
@@ -1225,26 +1096,44 @@ lrt_status lrt_count_terms(lrt_ctx *c, int64_t band, int64_t *count, int64_t *co
     c->err.clear();
     if (!count) return fail(c, LRT_E_ARG, "count must be non-NULL");
     hipStream_t st = (hipStream_t)stream;
-    lrt_status r;
-    if ((r = prepare(c, st, false))) return r;
+    if (!c->have_grid) return fail(c, LRT_E_STATE, "grid not set");
     int32_t k_first, n_band;
+    lrt_status r;
     if ((r = band_range(c, band, k_first, n_band))) return r;
-    if ((r = ensure(c, c->w_count, 16)) || (r = ensure(c, c->w_ranges, (size_t)c->n_cells * sizeof(int2))))
-        return r;
-    LRT_HIP(c, launch_fill_u64(c->w_count.as<unsigned long long>(), 0ull, 2, st));
-    const DevGrid g = dev_grid(c);
-    const DevLines L = dev_lines(c);
-    // candidate lines of each cell for the whole band (one tile spanning it)
-    LRT_HIP(c, launch_ranges(L, g, c->d_cc.as<CellConst>(), (int32_t)c->n_cells, k_first, n_band, n_band,
-                             c->w_ranges.as<int2>(), st));
-    LRT_HIP(c, launch_count(L, g, c->d_cc.as<CellConst>(), c->d_cs.as<CellSpecies>(), c->w_ranges.as<int2>(),
-                            (int32_t)c->n_cells, c->n_species, k_first, n_band,
-                            c->w_count.as<unsigned long long>(), st));
-    unsigned long long v[2] = {0, 0};
-    LRT_HIP(c, hipMemcpyAsync(v, c->w_count.p, 16, hipMemcpyDeviceToHost, st));
-    LRT_HIP(c, hipStreamSynchronize(st));
-    *count = (int64_t)v[0];
-    if (core_count) *core_count = (int64_t)v[1];
+    return count_range(c, k_first, n_band, count, core_count, st);
+}
+
+lrt_status lrt_solve_ranges(lrt_ctx *c, lrt_precision prec, int64_t n, const int64_t *k_first,
+                            const int64_t *n_points, double *q, double *I_int, double *q_range, void *stream)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    std::vector<int32_t> kf, np;
+    int64_t max_pts = 0;
+    lrt_status r;
+    if ((r = check_ranges(c, n, k_first, n_points, kf, np, max_pts))) return r;
+    return solve_ranges(c, prec, n, kf.data(), np.data(), max_pts, q, I_int, q_range, (hipStream_t)stream);
+}
+
+lrt_status lrt_count_terms_ranges(lrt_ctx *c, int64_t n, const int64_t *k_first, const int64_t *n_points,
+                                  int64_t *count, int64_t *core_count, void *stream)
+{
+    if (!c) return LRT_E_ARG;
+    c->err.clear();
+    if (!count) return fail(c, LRT_E_ARG, "count must be non-NULL");
+    std::vector<int32_t> kf, np;
+    int64_t max_pts = 0;
+    lrt_status r;
+    if ((r = check_ranges(c, n, k_first, n_points, kf, np, max_pts))) return r;
+    int64_t tot = 0, tot_core = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t a = 0, b = 0;
+        if ((r = count_range(c, kf[i], np[i], &a, &b, (hipStream_t)stream))) return r;
+        tot += a;
+        tot_core += b;
+    }
+    *count = tot;
+    if (core_count) *core_count = tot_core;
     return LRT_OK;
 }
 

@@ -32,10 +32,11 @@ EXPORTS = ["lrt_version", "lrt_status_string", "lrt_create", "lrt_destroy", "lrt
            "lrt_set_species", "lrt_set_lines", "lrt_set_grid", "lrt_set_cells", "lrt_set_continuum", "lrt_set_lorentz",
            "lrt_set_rays_slab", "lrt_set_rays_axi", "lrt_set_rays_axi_fibonacci",
            "lrt_fibonacci_quadrature", "lrt_set_march", "lrt_set_far_temperature", "lrt_trace_axi_ray", "lrt_get_sizes", "lrt_get_ray",
-           "lrt_coeffs", "lrt_march", "lrt_solve", "lrt_count_terms", "lrt_profile",
+           "lrt_coeffs", "lrt_march", "lrt_solve", "lrt_solve_ranges", "lrt_count_terms",
+           "lrt_count_terms_ranges", "lrt_profile",
            "lrt_profile_read", "lrt_server_start", "lrt_submit", "lrt_poll", "lrt_wait",
            "lrt_cancel", "lrt_server_info", "lrt_server_stop", "lrt_set_cr", "lrt_set_line_levels",
-           "lrt_cr_populations"]
+           "lrt_cr_populations", "lrt_probe"]
 
 KERNELS = {"thermo": 0, "scale": 1, "ranges": 2, "accum": 3, "march": 4, "cr": 5}
 
@@ -130,6 +131,9 @@ def lib():
             "lrt_march": (st, [_vp, C.c_int64, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]),
             "lrt_solve": (st, [_vp, C.c_int, C.c_int64, _dp, _dp, _dp, _vp]),
             "lrt_count_terms": (st, [_vp, C.c_int64, _i64p, _i64p, _vp]),
+            "lrt_solve_ranges": (st, [_vp, C.c_int, C.c_int64, _i64p, _i64p, _dp, _dp, _dp, _vp]),
+            "lrt_probe": (st, [C.c_int, C.c_int, _dp, _dp]),
+            "lrt_count_terms_ranges": (st, [_vp, C.c_int64, _i64p, _i64p, _i64p, _i64p, _vp]),
             "lrt_profile": (st, [_vp, C.c_int]),
             "lrt_profile_read": (st, [_vp, C.c_int, _dp, _i64p]),
             "lrt_server_start": (st, [_vp, C.c_size_t, C.c_int, C.POINTER(_vp)]),
@@ -353,6 +357,15 @@ class Context:
         s = self.sizes()
         return min(s["band_points"], s["n_points"] - band * s["band_points"])
 
+    def segment_count(self) -> int:
+        """Segments of all rays (lrt_get_ray's count query per ray)."""
+        n, w, wall = C.c_int64(), C.c_double(), C.c_int64()
+        tot = 0
+        for r in range(self.sizes()["n_rays"]):
+            self._chk(self._L.lrt_get_ray(self.h, r, 0, None, None, C.byref(n), C.byref(w), C.byref(wall)))
+            tot += n.value
+        return tot
+
     def ray(self, r: int):
         n, w, wall = C.c_int64(), C.c_double(), C.c_int64()
         self._chk(self._L.lrt_get_ray(self.h, r, 0, None, None, C.byref(n), C.byref(w), C.byref(wall)))
@@ -379,6 +392,27 @@ class Context:
         self._chk(self._L.lrt_solve(self.h, precision, first_band, _p(q), _p(I_int), _p(qb),
                                     _stream(stream)))
         return q, I_int, qb
+
+    def solve_ranges(self, precision: int, k_first, n_points, stream=None):
+        """The whole path over grid-point ranges [k_first[i], k_first[i] + n_points[i]):
+        (q [n_wall], I_int [n_rays], q_range [n_wall, n_ranges])."""
+        kf = np.ascontiguousarray(k_first, np.int64)
+        npt = np.ascontiguousarray(n_points, np.int64)
+        s = self.sizes()
+        q = np.zeros(s["n_wall"])
+        I_int = np.zeros(s["n_rays"])
+        qr = np.zeros((s["n_wall"], kf.size))
+        self._chk(self._L.lrt_solve_ranges(self.h, precision, kf.size, _p(kf, _i64p), _p(npt, _i64p),
+                                           _p(q), _p(I_int), _p(qr), _stream(stream)))
+        return q, I_int, qr
+
+    def count_terms_ranges(self, k_first, n_points, stream=None, core: bool = False):
+        kf = np.ascontiguousarray(k_first, np.int64)
+        npt = np.ascontiguousarray(n_points, np.int64)
+        n, nc = C.c_int64(), C.c_int64()
+        self._chk(self._L.lrt_count_terms_ranges(self.h, kf.size, _p(kf, _i64p), _p(npt, _i64p),
+                                                 C.byref(n), C.byref(nc), _stream(stream)))
+        return (n.value, nc.value) if core else n.value
 
     def count_terms(self, band: int, stream=None, core: bool = False):
         """In-window terms of a band; with core=True also those within 25
@@ -529,3 +563,17 @@ def scaled_to_f64(eta, kappa, escale):
     k = kappa.double().cpu().numpy()
     s = escale.cpu().numpy().astype(np.int64)
     return np.ldexp(e, s[:, :1]), np.ldexp(k, s[:, 1:2])
+
+
+PROBES = {"fma_f32": 0, "fma_f64": 1, "exp_f32": 2, "log_f32": 3, "rcp_f32": 4, "mix_f32": 5,
+          "copy": 6}
+
+
+def probe(kind: str, device: int = 0):
+    """(rate, ms) of one throughput probe (lrt_probe): lane-ops/s for the
+    arithmetic kinds, bytes read + written per second for the copy."""
+    rate, ms = C.c_double(), C.c_double()
+    s = lib().lrt_probe(device, PROBES[kind], C.byref(rate), C.byref(ms))
+    if s != 0:
+        raise LrtError(s, "lrt_probe(%s) failed" % kind)
+    return rate.value, ms.value

@@ -65,10 +65,10 @@ def edge_mask(wl, k_first, n, cells=None, E_ion=None):
     return m
 
 
-def knife_mask(wl, cells, ks, E_ion=None):
+def knife_mask(wl, cells, ks, E_ion=None, reach=1000.0):
     """[n_cells, ks.size] mask of the knife-edge points among sampled grid
-    indices ks (sorted)."""
-    cc, kk = O.knife_edges(wl.species, wl.lines, cells, wl.grid, near=ks, E_ion=E_ion)
+    indices ks (sorted); reach bounds 100 Voigt HWHM in cm^-1."""
+    cc, kk = O.knife_edges(wl.species, wl.lines, cells, wl.grid, near=ks, E_ion=E_ion, reach=reach)
     pos = {int(k): j for j, k in enumerate(ks)}
     m = np.zeros((cells.n, ks.size), bool)
     for c, k in zip(cc, kk):

@@ -237,3 +237,59 @@ def test_axisymmetric_large_fp64_band(torch_dev):
     rel = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
     say("  band integral of %d rays, FP32-comp vs FP64: %.3e" % (b.size, rel))
     assert np.all(np.isfinite(b)) and np.max(b) > 0 and rel <= 1e-5
+
+
+def _runs(ks):
+    """Contiguous runs of sorted grid indices as (k_first, n_points) arrays."""
+    cut = np.nonzero(np.diff(ks) != 1)[0] + 1
+    parts = np.split(ks, cut)
+    return (np.array([p[0] for p in parts], np.int64), np.array([p.size for p in parts], np.int64))
+
+
+def test_axisymmetric_large_wall_flux_vs_oracle(torch_dev):
+    """The large axisymmetric configuration at full shape (512 x 256 cells,
+    4M-line generator, 2^22 points, 256 wall points x 1024 directions):
+    q_rad of 8 wall points over two 16-point spectral windows, one in the
+    lowest band and one in the upper half (lrt_solve_ranges; the flux over
+    exactly those points with the whole grid's trapezoid weights), against
+    the oracle's flux over the same points: every one of the 1024 directions
+    of each wall point traced by the oracle's own crossing construction, the
+    oracle's coefficients of every cell they cross, its march and its sums.
+    GPU FP64 within 1e-12, FP32-comp within 1e-5, relative per wall point."""
+    wl = synth.config_axi_large()
+    g = wl.grid
+    rng = np.random.Generator(np.random.PCG64(58))
+    ks = np.unique(np.concatenate([np.arange(s, s + 16) for s in
+                                   (int(rng.integers(1000, 60000)), int(rng.integers(2_200_000, 4_000_000)))]))
+    walls = np.linspace(0, len(wl.geometry.wall_r) - 1, 8).astype(int)
+    # the oracle: its rays, the cells they cross, its coefficients there
+    segs, wts = {}, {}
+    for w in walls:
+        segs[w], wts[w] = O.axi_rays(wl.geometry, int(w))
+    ucells = np.unique(np.concatenate([c for w in walls for c, _ in segs[w]]))
+    usub = subset_cells(wl.cells, ucells)
+    # a bound of 100 Voigt HWHM over the configuration (Doppler at the top
+    # of the grid and the hottest cell, the largest uniform Lorentz width)
+    gG = 7.16233e-7 / 2 * g.nu_max * np.sqrt(max(wl.cells.T_tr.max(), wl.cells.T_v.max()) / 14.0)
+    gL = 1e-16 * wl.cells.n_e.max() * (wl.cells.T_v.max() / 1e4) ** 0.33
+    reach = 150.0 * (gG + gL)
+    edge = knife_mask(wl, usub, ks, reach=reach).any(axis=0)
+    say("large axisymmetric: %d oracle rays over %d cells at %d points (knife-edge columns %d)"
+        % (sum(len(segs[w]) for w in walls), ucells.size, ks.size, int(edge.sum())))
+    ks = ks[~edge]
+    eu, ku, n_terms = O.coeffs(wl.species, wl.lines, usub, g, ks)
+    row = np.full(wl.cells.n, -1, np.int64)
+    row[ucells] = np.arange(ucells.size)
+    wk = O.trapezoid_weights(g, ks)
+    q_ref = np.array([sum(wt * float(O.march(row[c], d, eu, ku) @ wk) for (c, d), wt in zip(segs[w], wts[w]))
+                      for w in walls])
+    say("  oracle: %d terms; q over the sample %s" % (n_terms, np.array2string(q_ref, precision=4)))
+    ctx = lrt.Context(0).load(wl)
+    kf, npt = _runs(ks)
+    for prec in PRECS:
+        q, _, qr = ctx.solve_ranges(prec, kf, npt)
+        e = float(np.max(np.abs(q[walls] - q_ref) / np.abs(q_ref)))
+        say("  prec %d: q at %d wall points, max rel err %.3e" % (prec, walls.size, e))
+        assert np.all(q_ref > 0) and e <= TOL[prec]
+        assert np.allclose(qr.sum(axis=1), q, rtol=1e-14, atol=0)
+    ctx.close()

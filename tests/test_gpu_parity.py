@@ -416,3 +416,38 @@ def test_cells_from_device_tensors(torch_dev):
     ctx.set_cells_device(T_tr, T_v, N, ne)
     assert np.array_equal(ctx.solve(lrt.LRT_FP64)[0], host[lrt.LRT_FP64][0])
     ctx.close()
+
+
+def test_solve_ranges(torch_dev):
+    """lrt_solve_ranges: the bands as ranges give lrt_solve's results bitwise;
+    a range list that tiles the grid differently gives the same flux to
+    rounding; sampled ranges match the oracle's flux over the same points;
+    invalid ranges are rejected."""
+    wl = synth.stagnation_line(n_cells=20, n_atomic=300, n_rovib=600, n_points=9000,
+                               band_points=2500, n_mu=4, seed=21)
+    ctx = lrt.Context(0).load(wl)
+    nb = wl.grid.n_bands
+    kf = np.arange(nb) * wl.grid.band_points
+    npt = np.minimum(wl.grid.band_points, wl.grid.n_points - kf)
+    for prec in PRECS:
+        q, I_int, qb = ctx.solve(prec)
+        q2, I2, qr = ctx.solve_ranges(prec, kf, npt)
+        assert np.array_equal(q, q2) and np.array_equal(I_int, I2) and np.array_equal(qb, qr)
+        kf3 = np.array([0, 1000, 3001, 5000, 7000], np.int64)
+        q3, I3, _ = ctx.solve_ranges(prec, kf3, np.diff(np.append(kf3, wl.grid.n_points)))
+        # FP64 sums every point's lines in line order whatever the ranges; the
+        # single-precision blocks of 64 lines start where a tile's candidates do
+        assert abs(q3[0] - q[0]) <= (1e-13 if prec == lrt.LRT_FP64 else 1e-5) * abs(q[0])
+        # sampled ranges vs the oracle over the same points
+        ks = np.concatenate([np.arange(700, 733), np.arange(4100, 4164), np.arange(8990, 9000)])
+        ref = O.solve_slab(wl, ks)
+        qs, Is, _ = ctx.solve_ranges(prec, [700, 4100, 8990], [33, 64, 10])
+        eq = abs(qs[0] - ref["q"]) / abs(ref["q"])
+        eI = float(np.max(np.abs(Is - ref["I_int"]) / np.abs(ref["I_int"])))
+        say("solve_ranges prec %d: sampled q %.3e, I_int %.3e" % (prec, eq, eI))
+        assert eq <= TOL[prec] and eI <= TOL[prec]
+    for kfb, nbad in (([-1], [5]), ([8999], [2]), ([0], [2501]), ([0], [0])):
+        with pytest.raises(lrt.LrtError) as e:
+            ctx.solve_ranges(lrt.LRT_FP64, kfb, nbad)
+        assert e.value.status == 1
+    ctx.close()
