@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=500,
                     help="requests per open-loop rate (closed loop: 2/5 of it); 0 skips serving")
     ap.add_argument("--peak", action="store_true", help="only run the unit throughput probes and exit")
+    ap.add_argument("--no-full-count", action="store_true",
+                    help="skip the whole-configuration term count (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy 3 times (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -480,6 +482,44 @@ def whole_solve_leg(name, lrt, torch, steps, fp64_steps, side):
     return out
 
 
+def generated_lines_leg(lrt, torch, steps=2):
+    """The stagnation line with its molecular lines generated on the device
+    (lrt_gen_rovib_lines) from the four air band systems (30 x 30 bands each,
+    J up to 150) instead of the stored synthetic list: generation time, the
+    list set from device memory, then whole single-precision solves."""
+    from paper_2604_11856_amd import synth
+    wl = synth.config_stagnation()
+    ctx = lrt.Context(0)
+    ctx.set_species(wl.species)
+    sy = synth.air_band_systems(nv=30, J_max=150)
+    ctx.gen_rovib_lines(sy, wl.grid.nu_min, wl.grid.nu_max)    # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gen = ctx.gen_rovib_lines(sy, wl.grid.nu_min, wl.grid.nu_max)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    atom = np.isin(wl.lines.species, [i for i, sp in enumerate(wl.species) if sp.kind == synth.KIND_ATOM])
+    dev = {k: torch.cat([torch.as_tensor(np.asarray(getattr(wl.lines, k))[atom], dtype=torch.float64,
+                                         device="cuda:0"), gen[k]]) for k in lrt.LINE_FIELDS}
+    dev["species"] = torch.cat([torch.as_tensor(np.asarray(wl.lines.species)[atom], dtype=torch.int32,
+                                                device="cuda:0"), gen["species"]])
+    t0 = time.perf_counter()
+    ctx.set_lines_device(dev)
+    t_set = time.perf_counter() - t0
+    ctx.set_grid(wl.grid)
+    ctx.set_cells(wl.cells)
+    ctx.set_rays(wl.geometry)
+    n_terms = ctx.count_terms(0)
+    dt, (q, _, _), prof = timed(ctx, lrt, torch, lambda: ctx.solve(lrt.LRT_FP32_COMP), steps, 1)
+    out = {"atomic_lines": int(atom.sum()), "generated_lines": int(gen["nu0"].shape[0]),
+           "generation_ms": t_gen * 1e3, "generated_lines_per_s": gen["nu0"].shape[0] / t_gen,
+           "set_lines_from_device_ms": t_set * 1e3, "solve_ms_per_step": dt * 1e3,
+           "evals_per_s": n_terms / dt, "voigt_terms_per_step": n_terms, "q_rad_W_cm2": [float(x) for x in q]}
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_model():
     try:
         for ln in open("/proc/cpuinfo"):
@@ -590,13 +630,17 @@ def main():
         log("fp64 step: %.1f ms" % (dt64 * 1e3))
     # the whole configuration: the slice is 1/256 of the points; the
     # accumulation also scaled by the exact term counts of every band
-    t_full_count = time.perf_counter()
-    n_terms_full = sum(ctx.count_terms(b) for b in range(sz["n_bands"]))
-    log("whole-configuration term count %.3e in %.1f s" % (n_terms_full, time.perf_counter() - t_full_count))
     ratio = sz["n_points"] / n_slice_pts
     acc_step = prof32["accum"][0] / 1e3 / args.steps
     t_full_pts = dt32 * ratio
-    t_full_terms = acc_step * n_terms_full / n_terms + (dt32 - acc_step) * ratio
+    if args.no_full_count:
+        n_terms_full = int(n_terms * ratio)
+        t_full_terms = t_full_pts
+    else:
+        t_full_count = time.perf_counter()
+        n_terms_full = sum(ctx.count_terms(b) for b in range(sz["n_bands"]))
+        log("whole-configuration term count %.3e in %.1f s" % (n_terms_full, time.perf_counter() - t_full_count))
+        t_full_terms = acc_step * n_terms_full / n_terms + (dt32 - acc_step) * ratio
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -656,6 +700,8 @@ def main():
         log("peaks done")
         line["stagnation"] = whole_solve_leg("stagnation", lrt, torch, 3, 1, True)
         log("stagnation leg done")
+        line["stagnation_generated_lines"] = generated_lines_leg(lrt, torch)
+        log("generated-lines leg done")
         line["axisymmetric"] = whole_solve_leg("axi", lrt, torch, 1, 0, False)
         log("axisymmetric leg done")
         if args.serving_requests > 0:

@@ -85,16 +85,56 @@ typedef struct {
     const double *vib_G, *vib_B, *vib_D;
 } lrt_species;
 
-/* Line list, structure of arrays, host pointers, any order (Sec. 2.2.1-2.2.2).
+/* Line list, structure of arrays, any order (Sec. 2.2.1-2.2.2).
  * nu0 > 0 line centre; A >= 0 Einstein coefficient (s^-1); upper / lower level
  * energy split into an electronic+vibrational part (populated at T_v) and a
  * rotational part (populated at T_tr; 0 for atoms); gu, gl >= 1 level
- * degeneracies; species indexes the species table. */
+ * degeneracies; species indexes the species table.  Host pointers
+ * (on_device == 0) or device pointers of the context's device (on_device !=
+ * 0, e.g. the output of lrt_gen_rovib_lines), read during the call only. */
 typedef struct {
     int64_t n;
     const double *nu0, *A, *Eu_ev, *Eu_rot, *El_ev, *El_rot, *gu, *gl;
     const int32_t *species;
+    int on_device;
 } lrt_lines;
+
+/* One electronic band system of a diatomic radiator, upper state u -> lower
+ * state l (Sec. 2.2.2), the input of lrt_gen_rovib_lines.  Per state: |Lambda|,
+ * electronic term T_e and degeneracy factor g_e (a level's degeneracy is
+ * g_e (2J + 1)), vibrational constants w_e, w_e x_e, w_e y_e (vibrational
+ * term E_V = w_e (V + 1/2) - w_e x_e (V + 1/2)^2 + w_e y_e (V + 1/2)^3),
+ * rotational constants B_e, alpha_e, D_e, beta_e (B_v = B_e - alpha_e
+ * (V + 1/2), D_v = D_e + beta_e (V + 1/2)), spin-rotation constant gamma,
+ * all in cm^-1, and nv vibrational levels V = 0..nv-1.  hund: LRT_HUND_A
+ * (rotational term B_v J(J+1) - D_v J^2 (J+1)^2; Hoenl-London factors of
+ * the case (a) table for Lambda_u, Lambda_l with |dLambda| <= 1; levels J >=
+ * Lambda; J_u = 0..J_max with its P, Q and R lines) or LRT_HUND_B (a doublet
+ * Sigma-Sigma system: levels N = J - S, S = +-1/2, term B_v N(N+1) -
+ * D_v N^2 (N+1)^2 + S gamma (N + 1/2 - S); Hoenl-London factors of the case
+ * (b) table in J_l; lower levels N_l = 0..J_max, from each a P and an R line
+ * keeping the spin component and a Q line changing it).  Re2 (host,
+ * [nv_u][nv_l]): the squared rotationless transition moment Re'^2 = Re^2
+ * F_vv of each band in units of e a0.  A line exists when both of its levels
+ * do and its Hoenl-London factor is positive. */
+enum { LRT_HUND_A = 0, LRT_HUND_B = 1 };
+typedef struct {
+    int32_t species;       /* the molecule (an LRT_KIND_MOLECULE species) */
+    int32_t hund;
+    int32_t Lambda_u, Lambda_l;
+    double Te_u, Te_l, g_u, g_l;
+    double we_u, wexe_u, weye_u, Be_u, ae_u, De_u, be_u, gamma_u;
+    double we_l, wexe_l, weye_l, Be_l, ae_l, De_l, be_l, gamma_l;
+    int32_t nv_u, nv_l, J_max;
+    const double *Re2;
+} lrt_band_system;
+
+/* Output arrays of a generated line list (device pointers, caller-owned,
+ * capacity given to the call). */
+typedef struct {
+    double *nu0, *A, *Eu_ev, *Eu_rot, *El_ev, *El_rot, *gu, *gl;
+    int32_t *species;
+} lrt_line_buffers;
 
 /* Flowfield cell states (Sec. 2.3 flowfield interface, the two-temperature
  * state of Sec. 2.1): T_tr translational-rotational temperature, T_v
@@ -132,7 +172,8 @@ const char *lrt_last_error(const lrt_ctx *ctx);
  * molecule / atom without levels, non-finite values. */
 lrt_status lrt_set_species(lrt_ctx *ctx, int n_species, const lrt_species *species);
 
-/* Line list (copied to device memory, sorted by nu0 there, kept resident).
+/* Line list (copied to device memory, sorted by nu0 there, kept resident;
+ * device arrays are copied to the host first, then handled alike).
  * Errors: LRT_E_ARG (nu0 <= 0, A < 0, g < 1, non-finite energy, species index
  * out of range or pointing to a species of kind NONE), LRT_E_STATE (no
  * species), LRT_E_OOM. */
@@ -403,7 +444,7 @@ lrt_status lrt_coeffs(lrt_ctx *ctx, int64_t band, lrt_precision prec, void *eta,
  * tau = kappa ds, F(t) = (1 - e^-t)/t, F(0) = 1.  I_out (device, [n_rays][band_len] doubles) receives the wall
  * intensity, or pass NULL; I_int_out (device, [n_rays] doubles) receives the
  * band's trapezoid sum with global-index weights (h/2 at grid ends, h inside).
- * The rays times the band's 1024-point chunks must stay below 2^32
+ * The rays times the band's 128-point chunks must stay below 2^32
  * (LRT_E_DEVICE otherwise).
  * Stream-ordered.  Errors: LRT_E_STATE (no rays, cells/rays mismatch),
  * LRT_E_ARG. */
@@ -456,6 +497,24 @@ lrt_status lrt_count_terms_ranges(lrt_ctx *ctx, int64_t n, const int64_t *k_firs
                                   const int64_t *n_points, int64_t *count, int64_t *core_count,
                                   void *stream);
 
+/* The rovibronic line list of n band systems on the device (Sec. 2.2.2): for
+ * every line, nu0 = E_u - E_l with E = T_e + E_V + E_rot of its state, the
+ * molecular Einstein coefficient A = 64 pi^4 nu0^3 (e a0 Re')^2 S_JJ /
+ * (3 h (2 J_u + 1)) in CGS (e the elementary charge in statcoulomb, a0 =
+ * 5.291772083e-9 cm), the degeneracies g_e (2J + 1), the energies split into
+ * T_e + E_V (Eu_ev, El_ev) and E_rot (Eu_rot, El_rot), and the species; lines
+ * with nu0 outside [nu_min, nu_max] are dropped.  Order: system, V_u, V_l,
+ * then J_u (case a) or N_l and S_l = +1/2, -1/2 (case b), then the branch P,
+ * Q, R.  Writes at most cap lines into out (device) and the number of lines
+ * to *n_out; cap = 0 (out ignored) only counts them.  Stream-ordered kernels,
+ * then the call synchronises the stream.  Errors: LRT_E_ARG (n < 1, a
+ * species that is not a molecule, nv < 1, J_max < 0, unknown hund, |dLambda|
+ * > 1 in case (a) or Lambda != 0 in case (b), negative or non-finite Re2 or
+ * degeneracy, nu_min >= nu_max, cap > 0 below the line count (*n_out is
+ * then set)), LRT_E_STATE (no species), LRT_E_OOM, LRT_E_DEVICE. */
+lrt_status lrt_gen_rovib_lines(lrt_ctx *ctx, int n, const lrt_band_system *sys, double nu_min, double nu_max,
+                               int64_t cap, const lrt_line_buffers *out, int64_t *n_out, void *stream);
+
 /* Kernel families timed by the profiler. */
 typedef enum {
     LRT_K_THERMO = 0,   /* partition functions, per-cell constants */
@@ -486,7 +545,7 @@ typedef enum {
     LRT_PROBE_RCP_F32 = 4,  /* v_rcp_f32, lane-ops/s */
     LRT_PROBE_MIX_F32 = 5,  /* a wing term's mix: 3 transcendentals + 10 other
                                single-precision operations, lane-ops/s */
-    LRT_PROBE_COPY = 6      /* 1 GiB device-to-device copy, bytes read + written per s */
+    LRT_PROBE_COPY = 6      /* 4 GiB device-to-device copy, bytes read + written per s */
 } lrt_probe_kind;
 
 /* Runs one probe on HIP device `device` (8 waves per SIMD on every compute

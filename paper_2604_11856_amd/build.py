@@ -13,6 +13,14 @@ ARCH = ["--offload-arch=gfx950"]
 # packed FP32 instructions are disabled for every HIP translation unit
 NO_PK = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]
+# The accumulation kernels stage one FP64 (cell, line) setup per thread and
+# round; machine-level loop-invariant code motion hoists the polynomial
+# constants of the double-precision exp/expm1/sinpi out of the round loop,
+# where they no longer fit the register budget and are spilled to scratch and
+# reloaded every round (57 reloads per lane per round, the bulk of the
+# kernel's HBM traffic).  Without that pass they are rebuilt where used; the
+# profile loop's own constants are set outside the loops explicitly.
+EXTRA = {"lrt_accum": ["-mllvm", "-disable-machine-licm"]}
 
 
 def _run(cmd):
@@ -26,9 +34,10 @@ def build_library(out: str = LIB) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = []
-    for name in ("lrt_accum", "lrt_march", "lrt_cr", "lrt_probe"):
+    for name in ("lrt_accum", "lrt_march", "lrt_cr", "lrt_probe", "lrt_rovib"):
         obj = os.path.join(bdir, name + ".o")
-        _run([HIPCC, *ARCH, *COMMON, *NO_PK, "-c", os.path.join(CSRC, name + ".hip"), "-o", obj])
+        _run([HIPCC, *ARCH, *COMMON, *NO_PK, *EXTRA.get(name, []), "-c", os.path.join(CSRC, name + ".hip"),
+              "-o", obj])
         objs.append(obj)
     # host code: no FP contraction, so the two-sum / two-product grid offsets stay exact
     for name in ("lrt_host", "lrt_cr_host", "lrt_serve", "lrt_geom"):

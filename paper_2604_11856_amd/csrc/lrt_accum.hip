@@ -386,7 +386,14 @@ __global__ void scale_bound_kernel(DevBins B, const CellConst *cc, const CellSpe
     const double ln_norm = -log(2.0 * 1.065 * 0.9);
     double ve = -INFINITY, vk = -INFINITY;
     const double *lnd_c = B.lev_off ? B.lnd + (int64_t)c * B.lnd_stride : nullptr;
+    // a spectral window: line centres that can reach it (as ranges_kernel)
+    double ca = -INFINITY, cb = INFINITY;
+    if (B.nu_lo) {
+        ca = (B.win_a - k.cand_G) / (1.0 + k.cand_A);
+        cb = (B.win_b + k.cand_G) / (1.0 - k.cand_A);
+    }
     for (int b = lane; b < B.n; b += 64) {
+        if (B.nu_lo && (B.nu_hi[b] < ca || B.nu_lo[b] > cb)) continue;
         const CellSpecies q = cs[(int64_t)c * n_species + B.species[b]];
         if (!(q.lnNQ > -INFINITY)) continue;
         double v = q.lnNQ + ln_norm - log(q.dop) - k.beta_v * B.Ev[b] - k.beta_tr * B.Er[b];
@@ -490,30 +497,48 @@ struct __align__(16) RecF64 {
 // 1 + 4x^2 = 1 + y^2 is one FMA and x^2.25 = 2^-2.25 |y|^2.25.
 constexpr double kTwoM225 = 0.21022410381342863;   // 2^-2.25
 
+// Constants of the single-precision profile.  The kernels set them once,
+// outside their loops, and an empty asm keeps them in scalar registers: VOP3
+// instructions take no literal on this chip, so a constant rebuilt inside
+// the loop costs a vector move per use.
+struct ShapeConsts {
+    float c225;   // 2.25 (the exponent of |y|)
+    float cw;     // 0.1 * 2^-2.25 (0.1 x^2.25 from |y|^2.25)
+    float cg;     // -2.772/4 log2(e) (the Gaussian exponent from 1 + y^2)
+    float ce;     // -0.4 * 2^-2.25 log2(e) (the other exponent)
+};
+
+__device__ __forceinline__ ShapeConsts shape_consts()
+{
+    ShapeConsts K{2.25f, (float)(0.1 * kTwoM225), (float)(-2.772 / 4.0 * kLog2e),
+                  (float)(-0.4 * kTwoM225 * kLog2e)};
+    asm volatile("" : "+s"(K.c225), "+s"(K.cw), "+s"(K.cg), "+s"(K.ce));
+    return K;
+}
+
 // Rational part r/(1+4x^2) - 0.016 r(1-r)/(1+0.1 x^2.25) over one reciprocal;
 // also returns 1 + y^2 and |y|^2.25 for the exponential part.  (Two
 // reciprocals save two instructions but measured 4 % slower: the
 // transcendental pipe, not the instruction count, then sets the pace.)
-__device__ __forceinline__ float shape_rational_f32(float kf, const RecF32 &q, float &d1, float &p)
+__device__ __forceinline__ float shape_rational_f32(float kf, const RecF32 &q, const ShapeConsts &K, float &d1,
+                                                    float &p)
 {
     const float y = fmaf(kf - q.k0f, q.hg, -q.fg);
     d1 = fmaf(y, y, 1.0f);
-    p = __builtin_amdgcn_exp2f(2.25f * __builtin_amdgcn_logf(fabsf(y)));
-    const float d2 = fmaf(p, (float)(0.1 * kTwoM225), 1.0f);
+    p = __builtin_amdgcn_exp2f(K.c225 * __builtin_amdgcn_logf(fabsf(y)));
+    const float d2 = fmaf(p, K.cw, 1.0f);
     const float num = fmaf(q.r, d2, -(q.aW * d1));
     return num * __builtin_amdgcn_rcpf(d1 * d2);
 }
 
 // Exponential part (1-r) e^{-2.772 x^2} + 0.016 r(1-r) e^{-0.4 x^2.25} added to
 // P, with x^2 = (d1 - 1)/4 folded into the exponent's FMA.
-__device__ __forceinline__ float shape_exp_f32(const RecF32 &q, float d1, float p, float P)
+__device__ __forceinline__ float shape_exp_f32(const RecF32 &q, const ShapeConsts &K, float d1, float p, float P)
 {
-    constexpr float c1 = (float)(-2.772 / 4.0 * kLog2e);
-    const float gs = __builtin_amdgcn_exp2f(fmaf(d1, c1, -c1));
-    const float e = __builtin_amdgcn_exp2f(p * (float)(-0.4 * kTwoM225 * kLog2e));
+    const float gs = __builtin_amdgcn_exp2f(fmaf(d1, K.cg, -K.cg));
+    const float e = __builtin_amdgcn_exp2f(p * K.ce);
     return fmaf(q.aG, gs, fmaf(q.aW, e, P));
 }
-
 
 // Block -> (tile, cell) order of the accumulation grid: groups of 8 tiles x
 // all cells; within a group XCD x (workgroups go round-robin over the 8 XCDs,
@@ -567,7 +592,7 @@ using BlockMask = uint64_t;
 // The terms of one staged line (bit t of the block masks) on this wave's
 // slices, added to the block partials.
 template <typename Mask>
-__device__ __forceinline__ void line_terms(const RecF32 &qr, int t, const float (&kf)[kPPL],
+__device__ __forceinline__ void line_terms(const RecF32 &qr, int t, const float (&kf)[kPPL], const ShapeConsts &K,
                                            const Mask (&m_in)[kPPL], const Mask (&m_core)[kPPL],
                                            const Mask (&m_edge)[kPPL], float (&ae)[kPPL], float (&ak)[kPPL])
 {
@@ -576,14 +601,14 @@ __device__ __forceinline__ void line_terms(const RecF32 &qr, int t, const float 
     for (int j = 0; j < kPPL; ++j) {
         if (!((m_in[j] >> t) & 1u)) continue;      // slice outside the window
         float d1, pw;
-        float P = shape_rational_f32(kf[j], q, d1, pw);
+        float P = shape_rational_f32(kf[j], q, K, d1, pw);
         // Within 25 HWHM of the centre the exponentials contribute;
         // beyond it they are exactly zero in single precision.  Both
         // conditions are wave-uniform; the empty asm keeps them real
         // scalar branches instead of computing both sides and selecting.
         if ((m_core[j] >> t) & 1u) {
             asm volatile("");
-            P = shape_exp_f32(q, d1, pw, P);
+            P = shape_exp_f32(q, K, d1, pw, P);
         }
         // slice crossing a window edge: mask the lanes outside
         if ((m_edge[j] >> t) & 1u) {
@@ -609,6 +634,7 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
 {
     // first slice of this wave (kw = wave * 64 * kPPL)
     const uint32_t wshift = (uint32_t)(kw / 64);
+    const ShapeConsts K = shape_consts();
     float kf[kPPL];
     float se[kPPL], ce[kPPL], sk[kPPL], ck[kPPL], ae[kPPL], ak[kPPL];
 #pragma unroll
@@ -684,7 +710,7 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
                 const RecF32 *rg8 = (const RecF32 *)((const char *)rec + off);
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    if ((gt >> u) & 1u) line_terms(rg8[u], u, kf, gi, gc, ge, ae, ak);
+                    if ((gt >> u) & 1u) line_terms(rg8[u], u, kf, K, gi, gc, ge, ae, ak);
             }
 #pragma unroll
             for (int j = 0; j < kPPL; ++j) {
@@ -975,31 +1001,29 @@ __global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, int
 
 // One linear-j segment of length Ls (cm) from far node (fe, fk) to near node
 // ne (scaled single-precision coefficients with their power-of-two scales),
-// composed into the chunk's transmittance T and source S: I <- I e^-t +
-// Ls (wf fe + wn ne), t = fk Ls.
+// composed into the chunk's transmittance and source at ts[loc],
+// ts[kTilePoints + loc]: I <- I e^-t + Ls (wf fe + wn ne), t = fk Ls.
 __device__ __forceinline__ void linear_j_step(const float (&fe)[kPPL], const float (&fk)[kPPL], int fee, int fek,
-                                              const float (&ne)[kPPL], int nee, double Ls, double (&T)[kPPL],
-                                              double (&S)[kPPL])
+                                              const float (&ne)[kPPL], int nee, double Ls, double *ts,
+                                              int32_t kw, int lane)
 {
     const double Lf = ldexp(Ls, fee), Ln = ldexp(Ls, nee);
     const float Lk = (float)fmin(ldexp(Ls, fek), 3.0e38);
 #pragma unroll
     for (int j = 0; j < kPPL; ++j) {
+        const int32_t loc = kw + 64 * j + lane;
         const float t = fk[j] * Lk;
         const float ex = __builtin_amdgcn_exp2f(t * (float)(-kLog2e));
         float wf, wn;
         linear_j_weights_f32(t, ex, wf, wn);
-        T[j] *= (double)ex;
-        S[j] = fma(S[j], (double)ex, (double)(wf * fe[j]) * Lf + (double)(wn * ne[j]) * Ln);
+        ts[loc] *= (double)ex;
+        ts[kTilePoints + loc] = fma(ts[kTilePoints + loc], (double)ex, (double)(wf * fe[j]) * Lf + (double)(wn * ne[j]) * Ln);
     }
 }
 
 __global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(LRT_SERVE_WAVES)))
-void serve_kernel(DevLines L, DevGrid g,
-                                                              const ServeReq *reqs,
-                                                              const ServeItem *items,
-                                                              int32_t n_items, int32_t *counter,
-                                                              int32_t n_species)
+void serve_kernel(DevLines L, DevGrid g, const ServeReq *reqs, const ServeItem *items, int32_t n_items,
+                  int32_t *counter, int32_t n_species)
 {
     __shared__ RecF32 rec[kStage];
     __shared__ int32_t s_item;
@@ -1012,15 +1036,21 @@ void serve_kernel(DevLines L, DevGrid g,
         __syncthreads();   // every thread has read s_item before it is overwritten
         if (it >= n_items) break;
         const ServeItem w = items[it];
-        const ServeReq R = reqs[w.req];
+        // the request's fields are read where used: held in registers across
+        // the cell loop they would crowd out the accumulation's
+        const ServeReq &R = reqs[w.req];
         const int32_t kt = R.k_first + w.tile * kTilePoints;
         const int32_t c0 = w.chunk * R.chunk_cells;
         const int32_t c1 = min(R.n_cells, c0 + R.chunk_cells);
-        double T[kPPL], S[kPPL];
+        // the chunk's transmittance T and source S per point live in its own
+        // slice of the request's buffer (each lane owns its points), not in
+        // registers across the cells
+        double *ts = R.TS + ((int64_t)w.tile * R.n_chunks + w.chunk) * 2 * kTilePoints;
 #pragma unroll
         for (int j = 0; j < kPPL; ++j) {
-            T[j] = 1.0;
-            S[j] = 0.0;
+            const int32_t loc = kw + 64 * j + lane;
+            ts[loc] = 1.0;
+            ts[kTilePoints + loc] = 0.0;
         }
         // linear-j: the chunk owns the segments that end at its cells' midpoint
         // nodes (the first from the far end, the last chunk's also to the
@@ -1028,7 +1058,8 @@ void serve_kernel(DevLines L, DevGrid g,
         float pe[kPPL], pk[kPPL];
         int pee = 0, pek = 0;
         double pds = 0.0;
-        const int32_t cs0 = (R.linear && c0 > 0) ? c0 - 1 : c0;
+        const bool linear = R.linear != 0;
+        const int32_t cs0 = (linear && c0 > 0) ? c0 - 1 : c0;
         for (int32_t c = cs0; c < c1; ++c) {
             float e[kPPL], kp[kPPL];
             const int ese = R.escale[2 * c + 0], esk = R.escale[2 * c + 1];
@@ -1039,30 +1070,36 @@ void serve_kernel(DevLines L, DevGrid g,
                 // atomic continuum, added in double precision and rounded once
 #pragma unroll
                 for (int j = 0; j < kPPL; ++j) {
+                    // (recomputed per cell: the per-point parts hoisted out of
+                    // the cell loop would be spilled across the accumulation)
+                    int32_t kk = kt + kw + 64 * j + lane;
+                    asm volatile("" : "+v"(kk));
+                    const double nu = g.nu_min + (double)kk * g.h;
                     double ce, ck;
-                    continuum_point(R.ct, c, g.nu_min + (double)(kt + kw + 64 * j + lane) * g.h, ce, ck);
+                    continuum_point(R.ct, c, nu, ce, ck);
                     e[j] = (float)((double)e[j] + ldexp(ce, -ese));
                     kp[j] = (float)((double)kp[j] + ldexp(ck, -esk));
                 }
             }
             const double ds = R.ds[c];
-            if (!R.linear) {
+            if (!linear) {
                 const double dse = ldexp(ds, ese);
                 const float dsk = (float)fmin(ldexp(ds, esk), 3.0e38);
 #pragma unroll
                 for (int j = 0; j < kPPL; ++j) {
+                    const int32_t loc = kw + 64 * j + lane;
                     double at, em;
                     segment_f32(e[j], kp[j], dsk, dse, at, em);
-                    T[j] *= at;
-                    S[j] = fma(S[j], at, em);
+                    ts[loc] *= at;
+                    ts[kTilePoints + loc] = fma(ts[kTilePoints + loc], at, em);
                 }
                 continue;
             }
             if (c >= c0) {
                 if (c == 0)   // far end -> first midpoint, both nodes the first cell's state
-                    linear_j_step(e, kp, ese, esk, e, ese, 0.5 * ds, T, S);
+                    linear_j_step(e, kp, ese, esk, e, ese, 0.5 * ds, ts, kw, lane);
                 else          // midpoint -> midpoint, kappa from the far node
-                    linear_j_step(pe, pk, pee, pek, e, ese, 0.5 * (pds + ds), T, S);
+                    linear_j_step(pe, pk, pee, pek, e, ese, 0.5 * (pds + ds), ts, kw, lane);
             }
 #pragma unroll
             for (int j = 0; j < kPPL; ++j) {
@@ -1073,15 +1110,8 @@ void serve_kernel(DevLines L, DevGrid g,
             pek = esk;
             pds = ds;
         }
-        if (R.linear && c1 == R.n_cells)   // last midpoint -> observer
-            linear_j_step(pe, pk, pee, pek, pe, pee, 0.5 * pds, T, S);
-        double *ts = R.TS + ((int64_t)w.tile * R.n_chunks + w.chunk) * 2 * kTilePoints;
-#pragma unroll
-        for (int j = 0; j < kPPL; ++j) {
-            const int32_t loc = kw + 64 * j + lane;
-            ts[loc] = T[j];
-            ts[kTilePoints + loc] = S[j];
-        }
+        if (linear && c1 == R.n_cells)   // last midpoint -> observer
+            linear_j_step(pe, pk, pee, pek, pe, pee, 0.5 * pds, ts, kw, lane);
     }
 }
 

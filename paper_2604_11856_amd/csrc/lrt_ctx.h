@@ -100,7 +100,7 @@ struct lrt_ctx {
     DBuf d_cc, d_cs;
     bool thermo_ready = false;
     DBuf d_emax, d_escale;
-    DBuf d_bin_sp, d_bin_Ev, d_bin_Er, d_bin_aeta, d_bin_akap;
+    DBuf d_bin_sp, d_bin_Ev, d_bin_Er, d_bin_aeta, d_bin_akap, d_bin_nlo, d_bin_nhi;
     int64_t n_bins = 0;
     bool scale_ready = false;
 
@@ -118,6 +118,7 @@ struct lrt_ctx {
 
     // workspace
     DBuf w_ranges, w_eta, w_kappa, w_partials, w_Iband, w_Itot, w_qband, w_count;
+    DBuf w_gen_sys, w_gen_re2, w_gen_cnt, w_gen_off;   // rovibronic line generation
 
     // profiler: event pairs per kernel family
     bool prof = false;
@@ -179,6 +180,10 @@ inline DevWidths dev_widths(const lrt_ctx *c)
     return DevWidths{c->h_Eion.empty() ? nullptr : c->d_Eion.as<double>(), c->gN_max, c->gS_max};
 }
 lrt_status line_widths(lrt_ctx *c);
+lrt_status band_range(lrt_ctx *c, int64_t band, int32_t &k_first, int32_t &n_band);
+lrt_status march_range(lrt_ctx *c, int32_t k_first, int32_t n_band, lrt_precision prec, const void *eta,
+                       const void *kappa, const int32_t *escale, double *I_out, double *I_int_out,
+                       hipStream_t st, double *partials, int64_t cap);
 inline DevGrid dev_grid(const lrt_ctx *c)
 {
     return DevGrid{c->nu_min, c->h, (int32_t)c->n_points, 1.0 / c->h};

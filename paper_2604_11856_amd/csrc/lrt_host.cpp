@@ -222,17 +222,35 @@ lrt_status lrt_set_species(lrt_ctx *c, int n, const lrt_species *sp)
     return LRT_OK;
 }
 
-lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *L)
+lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *Lin)
 {
     if (!c) return LRT_E_ARG;
     c->err.clear();
     if (c->n_species < 1) return fail(c, LRT_E_STATE, "set species before lines");
-    if (!L || L->n < 0) return fail(c, LRT_E_ARG, "lines NULL or negative count");
-    if (L->n >= INT_MAX) return fail(c, LRT_E_ARG, "at most 2^31-2 lines");
-    const int64_t n = L->n;
-    if (n > 0 && (!L->nu0 || !L->A || !L->Eu_ev || !L->Eu_rot || !L->El_ev || !L->El_rot || !L->gu ||
-                  !L->gl || !L->species))
+    if (!Lin || Lin->n < 0) return fail(c, LRT_E_ARG, "lines NULL or negative count");
+    if (Lin->n >= INT_MAX) return fail(c, LRT_E_ARG, "at most 2^31-2 lines");
+    const int64_t n = Lin->n;
+    if (n > 0 && (!Lin->nu0 || !Lin->A || !Lin->Eu_ev || !Lin->Eu_rot || !Lin->El_ev || !Lin->El_rot || !Lin->gu ||
+                  !Lin->gl || !Lin->species))
         return fail(c, LRT_E_ARG, "line arrays must be non-NULL");
+    // device arrays (a line list generated on the device): host copies, then
+    // the same validation, sort and preparation as host arrays
+    std::vector<double> hd[8];
+    std::vector<int32_t> hs;
+    lrt_lines Lh = *Lin;
+    if (Lin->on_device && n > 0) {
+        const double *src[8] = {Lin->nu0, Lin->A, Lin->Eu_ev, Lin->Eu_rot, Lin->El_ev, Lin->El_rot, Lin->gu, Lin->gl};
+        for (int k = 0; k < 8; ++k) {
+            hd[k].resize(n);
+            LRT_HIP(c, hipMemcpy(hd[k].data(), src[k], n * 8, hipMemcpyDeviceToHost));
+        }
+        hs.resize(n);
+        LRT_HIP(c, hipMemcpy(hs.data(), Lin->species, n * 4, hipMemcpyDeviceToHost));
+        Lh.nu0 = hd[0].data(); Lh.A = hd[1].data(); Lh.Eu_ev = hd[2].data(); Lh.Eu_rot = hd[3].data();
+        Lh.El_ev = hd[4].data(); Lh.El_rot = hd[5].data(); Lh.gu = hd[6].data(); Lh.gl = hd[7].data();
+        Lh.species = hs.data();
+    }
+    const lrt_lines *L = &Lh;
     for (int64_t i = 0; i < n; ++i) {
         if (!(L->nu0[i] > 0.0) || !std::isfinite(L->nu0[i]))
             return fail(c, LRT_E_ARG, "line %lld: nu0 must be positive and finite", (long long)i);
@@ -312,10 +330,22 @@ lrt_status lrt_set_lines(lrt_ctx *c, const lrt_lines *L)
                 return fail(c, LRT_E_ARG, "line %lld: level energy beyond +-8e9 cm^-1", (long long)j);
         }
     }
+    // per bin the range of line centres of its lines (upper and lower
+    // levels): a spectral window's scale bound visits only the bins whose
+    // lines can reach it
+    std::vector<double> b_nlo(b_sp.size(), std::numeric_limits<double>::infinity());
+    std::vector<double> b_nhi(b_sp.size(), -std::numeric_limits<double>::infinity());
+    for (int64_t j = 0; j < n; ++j)
+        for (int32_t b : {bin_u[j], bin_l[j]})
+            if (b >= 0) {
+                b_nlo[b] = std::min(b_nlo[b], nu0[j]);
+                b_nhi[b] = std::max(b_nhi[b], nu0[j]);
+            }
     lrt_status st;
     if ((st = upload_vec(c, c->d_bin_sp, b_sp)) || (st = upload_vec(c, c->d_bin_Ev, b_Ev)) ||
         (st = upload_vec(c, c->d_bin_Er, b_Er)) || (st = upload_vec(c, c->d_bin_aeta, b_aeta)) ||
-        (st = upload_vec(c, c->d_bin_akap, b_akap)))
+        (st = upload_vec(c, c->d_bin_akap, b_akap)) || (st = upload_vec(c, c->d_bin_nlo, b_nlo)) ||
+        (st = upload_vec(c, c->d_bin_nhi, b_nhi)))
         return st;
     c->n_bins = (int64_t)b_sp.size();
     if ((st = upload_vec(c, c->d_nu0, nu0)) || (st = upload_vec(c, c->d_seta0, seta0)) ||
@@ -909,10 +939,13 @@ lrt_status coeffs_impl(lrt_ctx *c, int64_t band, lrt_precision prec, void *eta, 
     return coeffs_range(c, k_first, n_band, prec, eta, kappa, escale, st);
 }
 
-// March of every ray over grid points [k_first, k_first + n_band).
+// March of every ray over grid points [k_first, k_first + n_band).  The
+// per-(ray, chunk) partial sums go to the context's workspace, or to
+// `partials` (capacity `cap` doubles) when the caller brings its own buffer:
+// then nothing is allocated and no launch is profiled.
 lrt_status march_range(lrt_ctx *c, int32_t k_first, int32_t n_band, lrt_precision prec, const void *eta,
                        const void *kappa, const int32_t *escale, double *I_out, double *I_int_out,
-                       hipStream_t st)
+                       hipStream_t st, double *partials, int64_t cap)
 {
     if (prec != LRT_FP64 && prec != LRT_FP32_COMP) return fail(c, LRT_E_ARG, "unknown precision %d", (int)prec);
     if (!eta || !kappa || !I_int_out) return fail(c, LRT_E_ARG, "eta, kappa and I_int_out must be non-NULL");
@@ -924,16 +957,33 @@ lrt_status march_range(lrt_ctx *c, int32_t k_first, int32_t n_band, lrt_precisio
         return fail(c, LRT_E_STATE, "rays expect %lld cells, %lld set", (long long)c->rays_cells, (long long)c->n_cells);
     lrt_status r;
     const int32_t n_chunks = (n_band + kMarchPoints - 1) / kMarchPoints;
-    if ((r = ensure(c, c->w_partials, (size_t)c->n_rays * n_chunks * sizeof(double)))) return r;
-    const DevRays rays{(int32_t)c->n_rays, c->d_off.as<int64_t>(), c->d_cell.as<int32_t>(), c->d_ds.as<double>()};
+    const int64_t need = c->n_rays * (int64_t)n_chunks;
+    if (partials) {
+        if (need > cap)
+            return fail(c, LRT_E_ARG, "the march needs %lld partial sums (rays x %d-point chunks), the buffer holds %lld",
+                        (long long)need, kMarchPoints, (long long)cap);
+    } else {
+        if ((r = ensure(c, c->w_partials, (size_t)need * sizeof(double)))) return r;
+    }
+    double *part = partials ? partials : c->w_partials.as<double>();
+    DevRays rays{(int32_t)c->n_rays, c->d_off.as<int64_t>(), c->d_cell.as<int32_t>(), c->d_ds.as<double>()};
+    // every wall point with the same number of rays: the march may take them
+    // direction-major
+    if (c->n_wall > 0 && c->n_rays % c->n_wall == 0 && (int64_t)c->h_wall_off.size() == c->n_wall + 1) {
+        const int64_t per = c->n_rays / c->n_wall;
+        bool same = true;
+        for (int64_t w = 0; w < c->n_wall && same; ++w) same = c->h_wall_off[w + 1] - c->h_wall_off[w] == per;
+        if (same) rays.per_wall = (int32_t)per;
+    }
     const DevGrid g = dev_grid(c);
-    LRT_HIP(c, timed(c, LRT_K_MARCH, st, [&] {
-                return launch_march(prec == LRT_FP32_COMP, c->march_scheme == LRT_MARCH_LINEAR_J, rays, g,
-                                    k_first, n_band, eta, kappa, escale,
-                                    c->have_Tfar ? c->d_Tfar.as<double>() : nullptr, I_out,
-                                    c->w_partials.as<double>(), n_chunks, st);
-            }));
-    LRT_HIP(c, launch_reduce_rows(c->w_partials.as<double>(), (int32_t)c->n_rays, n_chunks, I_int_out, st));
+    auto go = [&] {
+        return launch_march(prec == LRT_FP32_COMP, c->march_scheme == LRT_MARCH_LINEAR_J, rays, g, k_first, n_band,
+                            eta, kappa, escale, c->have_Tfar ? c->d_Tfar.as<double>() : nullptr, I_out, part,
+                            n_chunks, st);
+    };
+    if (partials) LRT_HIP(c, go());
+    else LRT_HIP(c, timed(c, LRT_K_MARCH, st, go));
+    LRT_HIP(c, launch_reduce_rows(part, (int32_t)c->n_rays, n_chunks, I_int_out, st));
     return LRT_OK;
 }
 
@@ -944,7 +994,7 @@ lrt_status march_impl(lrt_ctx *c, int64_t band, lrt_precision prec, const void *
     int32_t k_first, n_band;
     lrt_status r;
     if ((r = band_range(c, band, k_first, n_band))) return r;
-    return march_range(c, k_first, n_band, prec, eta, kappa, escale, I_out, I_int_out, st);
+    return march_range(c, k_first, n_band, prec, eta, kappa, escale, I_out, I_int_out, st, nullptr, 0);
 }
 
 // The whole path over a list of point ranges, each like one band: per-cell
@@ -972,7 +1022,7 @@ lrt_status solve_ranges(lrt_ctx *c, lrt_precision prec, int64_t n_rng, const int
     for (int64_t b = 0; b < n_rng; ++b) {
         if ((r = coeffs_range(c, k_first[b], n_pts[b], prec, c->w_eta.p, c->w_kappa.p, nullptr, st))) return r;
         if ((r = march_range(c, k_first[b], n_pts[b], prec, c->w_eta.p, c->w_kappa.p, esc, nullptr,
-                             c->w_Iband.as<double>(), st)))
+                             c->w_Iband.as<double>(), st, nullptr, 0)))
             return r;
         LRT_HIP(c, launch_add(c->w_Itot.as<double>(), c->w_Iband.as<double>(), (int32_t)c->n_rays, st));
         // per-range wall flux into row b of the [n_rng][n_wall] staging array

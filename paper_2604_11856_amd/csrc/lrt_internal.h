@@ -41,20 +41,19 @@ constexpr int kTilePoints = kAccumThreads * kPPL;
 // Line records staged in LDS per round: one per thread.
 constexpr int kStage = kAccumThreads;
 
-// March tile: 256 threads x 4 points.
+// March tile: one wave owns one (ray, chunk) item of kMarchPoints = 64 x
+// kMarchPPT consecutive points; a workgroup of kMarchThreads holds the items
+// of kMarchWaves rays on the same chunk.
 constexpr int kMarchThreads = 256;
+constexpr int kMarchWaves = kMarchThreads / 64;
+constexpr int kMarchPPT = 2;
+constexpr int kMarchPoints = 64 * kMarchPPT;
 
 // Workgroups per launch of a kernel whose grid can be large (the accumulation
 // over cells x tiles, the march over rays x chunks): a dispatch counts at most
 // 2^32 - 1 work-items, so such grids go in launches of 2^23 workgroups of 256
 // (a multiple of the 8 XCDs, so every launch starts on XCD 0 as one launch would).
 constexpr int64_t kMaxLaunchBlocks = int64_t(1) << 23;
-#ifndef LRT_MARCH_PPT
-#define LRT_MARCH_PPT 4
-#endif
-constexpr int kMarchPPT = LRT_MARCH_PPT;
-static_assert(kMarchPPT == 1 || kMarchPPT == 2 || kMarchPPT == 4, "march points per thread");
-constexpr int kMarchPoints = kMarchThreads * kMarchPPT;
 
 // Species level tables on the device (flattened).
 struct DevSpecies {
@@ -165,6 +164,11 @@ struct DevBins {
     const int32_t *lev_off = nullptr, *lev = nullptr;
     const double *lnd = nullptr;
     int32_t lnd_stride = 0;
+    // optional window [win_a, win_b] (cm^-1, nu_lo non-NULL): only bins whose
+    // line centres [nu_lo, nu_hi] meet the cell's candidate range of the
+    // window count
+    const double *nu_lo = nullptr, *nu_hi = nullptr;
+    double win_a = 0.0, win_b = 0.0;
 };
 
 struct DevGrid {
@@ -211,6 +215,9 @@ struct DevRays {
     const int64_t *off;     // [n_rays+1] into cell / ds
     const int32_t *cell;
     const double *ds;
+    // rays per wall point when every wall point has that many (wall-major
+    // ray order), else 0: the march then visits the rays direction-major
+    int32_t per_wall = 0;
 };
 
 // One admitted line-of-sight request as the serving kernels see it.

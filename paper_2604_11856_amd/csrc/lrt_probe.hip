@@ -91,7 +91,7 @@ extern "C" lrt_status lrt_probe(int device, int kind, double *rate, double *ms)
     const int blocks = prop.multiProcessorCount * 8;
     const int32_t iters = 16384;
     void *buf = nullptr, *src = nullptr;
-    const int64_t copy_bytes = (int64_t)1 << 30;
+    const int64_t copy_bytes = (int64_t)4 << 30;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     lrt_status st = LRT_OK;
     float t = 0.0f;
@@ -122,7 +122,7 @@ extern "C" lrt_status lrt_probe(int device, int kind, double *rate, double *ms)
                                (double *)buf);
             break;
         default:
-            hipLaunchKernelGGL(probe_copy_kernel, dim3(blocks * 4), dim3(kProbeThreads), 0, nullptr,
+            hipLaunchKernelGGL(probe_copy_kernel, dim3(blocks * 16), dim3(kProbeThreads), 0, nullptr,
                                (const float4 *)src, (float4 *)buf, copy_bytes / 16);
             break;
         }

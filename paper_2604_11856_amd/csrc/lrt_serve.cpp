@@ -6,14 +6,16 @@
 //     arena allocated at start, first-fit, so nothing is allocated or freed
 //     on the device while kernels run); admitted requests get their cell data
 //     uploaded and their per-cell constants, candidate ranges and scales
-//     computed on the admission stream;
+//     computed on the admission stream (the scale from the binned bound of
+//     the line peaks, over the bins whose lines can reach the window);
 //   - epochs: items (request, tile, cell chunk) of every admitted request are
 //     handed out round-robin into bounded epochs, each one launch of the
 //     persistent serving kernel on one of two epoch streams, so new work joins
 //     while earlier epochs run;
 //   - completion: when all items of a request are done, the combine kernel
-//     composes its chunks; the integral (and optionally the spectrum) is
-//     copied back and the slot and memory are released.
+//     composes its chunks on a stream of its own; the integral (and
+//     optionally the spectrum) is copied back and the slot and memory are
+//     released.
 // A request's decomposition depends only on the request itself, so its result
 // is bitwise the same alone and in a mix.
 #include <hip/hip_runtime.h>
@@ -139,7 +141,7 @@ size_t request_bytes(int64_t nc, int S, int32_t n_window, int32_t n_thr, int32_t
     b += align_up((size_t)nc * S * 8);                      // N
     b += align_up(nc * sizeof(CellConst));
     b += align_up((size_t)nc * S * sizeof(CellSpecies));
-    b += 2 * align_up(nc * 2 * sizeof(int32_t));            // emax, escale
+    b += align_up(nc * 2 * sizeof(int32_t));                // escale
     b += align_up((size_t)nc * n_tiles * sizeof(int2));     // ranges
     b += align_up((size_t)n_tiles * n_chunks * 2 * kTilePoints * 8);   // T, S
     b += align_up((size_t)n_window * 8);                    // I
@@ -167,6 +169,7 @@ struct lrt_server {
     DBuf d_arena, d_reqs;
     std::vector<int> free_slots;
     hipStream_t admit_stream = nullptr;
+    hipStream_t done_stream = nullptr;   // combine of finished requests, apart from admissions
     Epoch epochs[kEpochStreams];
 
     std::mutex mu;
@@ -238,7 +241,6 @@ bool lrt_server::admit(Req &r)
     double *N = (double *)take((size_t)nc * S * 8);
     CellConst *cc = (CellConst *)take(nc * sizeof(CellConst));
     CellSpecies *cs = (CellSpecies *)take((size_t)nc * S * sizeof(CellSpecies));
-    int32_t *emax = (int32_t *)take(nc * 2 * sizeof(int32_t));
     int32_t *escale = (int32_t *)take(nc * 2 * sizeof(int32_t));
     int2 *ranges = (int2 *)take((size_t)nc * r.n_tiles * sizeof(int2));
     double *TS = (double *)take((size_t)r.n_tiles * r.n_chunks * 2 * kTilePoints * 8);
@@ -304,22 +306,25 @@ bool lrt_server::admit(Req &r)
             return true;
         ct = DevCont{n_thr, ctx->d_cont_thr.as<ContThr>(), cum, ff, T_v};
     }
-    // lines that can reach the window at all, for the per-cell scale
-    double gL_max = 0.0, T_max = 0.0;
-    for (int64_t c = 0; c < nc; ++c) {
-        gL_max = std::max(gL_max, 1e-16 * r.n_e[c] * std::pow(r.T_v[c] / 1e4, 0.33));
-        T_max = std::max(T_max, r.T_tr[c]);
+    // per-cell power-of-two scale: the upper bound of the line peaks over the
+    // level-energy bins whose lines can reach the window (and the continuum's
+    // own bound), as the batch path bounds every line
+    {
+        DevBins B{(int32_t)ctx->n_bins, ctx->d_bin_sp.as<int32_t>(), ctx->d_bin_Ev.as<double>(),
+                  ctx->d_bin_Er.as<double>(), ctx->d_bin_aeta.as<double>(), ctx->d_bin_akap.as<double>()};
+        if (cr_lines) {
+            B.lev_off = ctx->d_bin_lev_off.as<int32_t>();
+            B.lev = ctx->d_bin_lev.as<int32_t>();
+            B.lnd = crq.lnd;
+            B.lnd_stride = cr_row;
+        }
+        B.nu_lo = ctx->d_bin_nlo.as<double>();
+        B.nu_hi = ctx->d_bin_nhi.as<double>();
+        B.win_a = ctx->nu_min + (double)r.k_first * ctx->h - ctx->h;
+        B.win_b = ctx->nu_min + (double)(r.k_first + r.n_window - 1) * ctx->h + ctx->h;
+        if (!ok(launch_scale_bound(B, cc, cs, lnb, (int32_t)nc, S, escale, st), "scale"))
+            return true;
     }
-    const double G = 100.0 * gL_max * (1.0 + 1e-6) + ctx->h;
-    const double A = 100.0 * (7.16233e-7 / 2.0) * std::sqrt(T_max / ctx->M_min) * (1.0 + 1e-6);
-    const double nu_a = ctx->nu_min + (double)r.k_first * ctx->h;
-    const double nu_b = ctx->nu_min + (double)(r.k_first + r.n_window - 1) * ctx->h;
-    const auto &nu0 = ctx->h_nu0;
-    const int64_t i0 = std::lower_bound(nu0.begin(), nu0.end(), (nu_a - G) / (1.0 + A)) - nu0.begin();
-    const int64_t i1 = std::lower_bound(nu0.begin(), nu0.end(), (nu_b + G) / (1.0 - A)) - nu0.begin();
-    if (!ok(launch_fill_i32(emax, INT_MIN, 2 * nc, st), "fill") ||
-        !ok(launch_scale(L, i0, i1, g, cc, cs, (int32_t)nc, S, lnb, emax, escale, st), "scale"))
-        return true;
     r.dev = ServeReq{(int32_t)nc, r.k_first, r.n_window, r.n_tiles, r.n_chunks, kChunkCells,
                      cc, cs, escale, ds, ranges, TS, I_out, partials, I_int, ct, r.T_far,
                      r.scheme == LRT_MARCH_LINEAR_J ? 1 : 0, L.lnd_stride, L.lnd};
@@ -424,9 +429,11 @@ void lrt_server::run()
             Req &r = *reqs[t];
             if (r.state != ST_ADMITTED || r.items_done < r.items_total) continue;
             const DevGrid g = dev_grid(ctx);
-            hipError_t err = launch_serve_combine(r.dev, g, admit_stream);
+            // (its own stream: a finished request does not queue behind the
+            // uploads and per-cell kernels of requests being admitted)
+            hipError_t err = launch_serve_combine(r.dev, g, done_stream);
             if (err == hipSuccess) err = hipEventCreateWithFlags(&r.comb_ev, hipEventDisableTiming);
-            if (err == hipSuccess) err = hipEventRecord(r.comb_ev, admit_stream);
+            if (err == hipSuccess) err = hipEventRecord(r.comb_ev, done_stream);
             if (err != hipSuccess) {
                 fatal = std::string("combine: ") + hipGetErrorString(err);
                 break;
@@ -517,6 +524,7 @@ lrt_status lrt_server_start(lrt_ctx *ctx, size_t budget, int max_slots, lrt_serv
     if ((st = upload(ctx, s->d_reqs, nullptr, (size_t)max_slots * sizeof(ServeReq)))) return st;
     for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     LRT_HIP(ctx, hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking));
+    LRT_HIP(ctx, hipStreamCreateWithFlags(&s->done_stream, hipStreamNonBlocking));
     for (auto &e : s->epochs) {
         LRT_HIP(ctx, hipStreamCreateWithFlags(&e.stream, hipStreamNonBlocking));
         LRT_HIP(ctx, hipEventCreateWithFlags(&e.done, hipEventDisableTiming));
@@ -674,6 +682,7 @@ lrt_status lrt_server_stop(lrt_server *s)
         if (e.stream) (void)hipStreamDestroy(e.stream);
     }
     if (s->admit_stream) (void)hipStreamDestroy(s->admit_stream);
+    if (s->done_stream) (void)hipStreamDestroy(s->done_stream);
     const std::string msg = s->fatal;
     delete s;
     if (!ok) return fail(nullptr, LRT_E_DEVICE, "server failed: %s", msg.c_str());

@@ -36,7 +36,7 @@ EXPORTS = ["lrt_version", "lrt_status_string", "lrt_create", "lrt_destroy", "lrt
            "lrt_count_terms_ranges", "lrt_profile",
            "lrt_profile_read", "lrt_server_start", "lrt_submit", "lrt_poll", "lrt_wait",
            "lrt_cancel", "lrt_server_info", "lrt_server_stop", "lrt_set_cr", "lrt_set_line_levels",
-           "lrt_cr_populations", "lrt_probe"]
+           "lrt_cr_populations", "lrt_probe", "lrt_gen_rovib_lines"]
 
 KERNELS = {"thermo": 0, "scale": 1, "ranges": 2, "accum": 3, "march": 4, "cr": 5}
 
@@ -56,7 +56,24 @@ class _Species(C.Structure):
 
 class _Lines(C.Structure):
     _fields_ = [("n", C.c_int64), ("nu0", _dp), ("A", _dp), ("Eu_ev", _dp), ("Eu_rot", _dp),
-                ("El_ev", _dp), ("El_rot", _dp), ("gu", _dp), ("gl", _dp), ("species", _i32p)]
+                ("El_ev", _dp), ("El_rot", _dp), ("gu", _dp), ("gl", _dp), ("species", _i32p),
+                ("on_device", C.c_int)]
+
+
+class _BandSystem(C.Structure):
+    _fields_ = [("species", C.c_int32), ("hund", C.c_int32), ("Lambda_u", C.c_int32), ("Lambda_l", C.c_int32),
+                *[(k, C.c_double) for k in ("Te_u", "Te_l", "g_u", "g_l",
+                                            "we_u", "wexe_u", "weye_u", "Be_u", "ae_u", "De_u", "be_u", "gamma_u",
+                                            "we_l", "wexe_l", "weye_l", "Be_l", "ae_l", "De_l", "be_l", "gamma_l")],
+                ("nv_u", C.c_int32), ("nv_l", C.c_int32), ("J_max", C.c_int32), ("Re2", _dp)]
+
+
+class _LineBuffers(C.Structure):
+    _fields_ = [(k, _dp) for k in ("nu0", "A", "Eu_ev", "Eu_rot", "El_ev", "El_rot", "gu", "gl")] + \
+        [("species", _i32p)]
+
+
+LINE_FIELDS = ("nu0", "A", "Eu_ev", "Eu_rot", "El_ev", "El_rot", "gu", "gl")
 
 
 class _Continuum(C.Structure):
@@ -133,6 +150,8 @@ def lib():
             "lrt_count_terms": (st, [_vp, C.c_int64, _i64p, _i64p, _vp]),
             "lrt_solve_ranges": (st, [_vp, C.c_int, C.c_int64, _i64p, _i64p, _dp, _dp, _dp, _vp]),
             "lrt_probe": (st, [C.c_int, C.c_int, _dp, _dp]),
+            "lrt_gen_rovib_lines": (st, [_vp, C.c_int, C.POINTER(_BandSystem), C.c_double, C.c_double,
+                                         C.c_int64, C.POINTER(_LineBuffers), _i64p, _vp]),
             "lrt_count_terms_ranges": (st, [_vp, C.c_int64, _i64p, _i64p, _i64p, _i64p, _vp]),
             "lrt_profile": (st, [_vp, C.c_int]),
             "lrt_profile_read": (st, [_vp, C.c_int, _dp, _i64p]),
@@ -218,8 +237,47 @@ class Context:
              for k in ("nu0", "A", "Eu_ev", "Eu_rot", "El_ev", "El_rot", "gu", "gl")}
         sp = np.ascontiguousarray(lines.species, np.int32)
         s = _Lines(lines.n, _p(a["nu0"]), _p(a["A"]), _p(a["Eu_ev"]), _p(a["Eu_rot"]),
-                   _p(a["El_ev"]), _p(a["El_rot"]), _p(a["gu"]), _p(a["gl"]), _p(sp, _i32p))
+                   _p(a["El_ev"]), _p(a["El_rot"]), _p(a["gu"]), _p(a["gl"]), _p(sp, _i32p), 0)
         self._chk(self._L.lrt_set_lines(self.h, C.byref(s)))
+
+    def set_lines_device(self, t):
+        """Line list from contiguous device tensors: t maps LINE_FIELDS to
+        float64 and "species" to int32 tensors of one length."""
+        n = int(t["nu0"].shape[0])
+        dp = lambda x: C.cast(C.c_void_p(x.data_ptr()), _dp)
+        for k in LINE_FIELDS + ("species",):
+            if not (t[k].is_cuda and t[k].is_contiguous() and int(t[k].shape[0]) == n):
+                raise ValueError("device lines: %s must be a contiguous device tensor of length %d" % (k, n))
+        s = _Lines(n, *[dp(t[k]) for k in LINE_FIELDS], C.cast(C.c_void_p(t["species"].data_ptr()), _i32p), 1)
+        self._chk(self._L.lrt_set_lines(self.h, C.byref(s)))
+
+    def gen_rovib_lines(self, systems, nu_min: float, nu_max: float, device="cuda:0", stream=None):
+        """Rovibronic lines of synth.BandSystem records generated on the device
+        (lrt_gen_rovib_lines): dict of device tensors (LINE_FIELDS float64,
+        "species" int32), in the generator's order."""
+        import torch
+        arr = (_BandSystem * len(systems))()
+        keep = []
+        for i, b in enumerate(systems):
+            re2 = np.ascontiguousarray(b.Re2, np.float64)
+            keep.append(re2)
+            arr[i] = _BandSystem(b.species, b.hund, b.Lambda_u, b.Lambda_l,
+                                 *[float(getattr(b, k)) for k in (
+                                     "Te_u", "Te_l", "g_u", "g_l", "we_u", "wexe_u", "weye_u", "Be_u", "ae_u",
+                                     "De_u", "be_u", "gamma_u", "we_l", "wexe_l", "weye_l", "Be_l", "ae_l",
+                                     "De_l", "be_l", "gamma_l")],
+                                 b.nv_u, b.nv_l, b.J_max, _p(re2))
+        n = C.c_int64()
+        self._chk(self._L.lrt_gen_rovib_lines(self.h, len(systems), arr, float(nu_min), float(nu_max), 0, None,
+                                              C.byref(n), _stream(stream)))
+        out = {k: torch.empty(max(1, n.value), dtype=torch.float64, device=device) for k in LINE_FIELDS}
+        out["species"] = torch.empty(max(1, n.value), dtype=torch.int32, device=device)
+        bufs = _LineBuffers(*[C.cast(C.c_void_p(out[k].data_ptr()), _dp) for k in LINE_FIELDS],
+                            C.cast(C.c_void_p(out["species"].data_ptr()), _i32p))
+        if n.value:
+            self._chk(self._L.lrt_gen_rovib_lines(self.h, len(systems), arr, float(nu_min), float(nu_max), n.value,
+                                                  C.byref(bufs), C.byref(n), _stream(stream)))
+        return {k: v[:n.value] for k, v in out.items()}
 
     def set_grid(self, grid):
         self._chk(self._L.lrt_set_grid(self.h, float(grid.nu_min), float(grid.nu_max),

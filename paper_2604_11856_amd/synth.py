@@ -208,6 +208,48 @@ class CRModel:
 
 
 @dataclasses.dataclass
+class BandSystem:
+    """Molecular constants of one electronic band system (upper state u ->
+    lower state l) of a diatomic radiator, the input of the rovibronic line
+    generator: coupling case (0: Hund (a), 1: Hund (b) doublet), |Lambda| of
+    each state, electronic terms T_e and degeneracy factors g_e (cm^-1, a
+    level's degeneracy being g_e (2J + 1)), vibrational constants w_e,
+    w_e x_e, w_e y_e, rotational constants B_e, alpha_e, D_e, beta_e and the
+    spin-rotation constant gamma of each state (cm^-1), vibrational levels
+    V = 0..nv-1 of each state, the rotational extent J_max, and per
+    (V_u, V_l) band the squared rotationless transition moment Re'^2 (in
+    units of e a0, row-major [nv_u][nv_l])."""
+    species: int
+    hund: int
+    Lambda_u: int
+    Lambda_l: int
+    Te_u: float
+    Te_l: float
+    g_u: float
+    g_l: float
+    we_u: float
+    wexe_u: float
+    weye_u: float
+    Be_u: float
+    ae_u: float
+    De_u: float
+    be_u: float
+    gamma_u: float
+    we_l: float
+    wexe_l: float
+    weye_l: float
+    Be_l: float
+    ae_l: float
+    De_l: float
+    be_l: float
+    gamma_l: float
+    nv_u: int
+    nv_l: int
+    J_max: int
+    Re2: np.ndarray
+
+
+@dataclasses.dataclass
 class Workload:
     name: str
     species: List[Species]
@@ -555,6 +597,32 @@ def rovib_lines(rng, sp: Species, sp_index: int, n_target: int,
     d = {k: np.concatenate(v)[:n_target] for k, v in out.items()}
     d["species"] = np.full(d["nu0"].shape[0], sp_index, np.int32)
     return d
+
+
+def air_band_systems(seed: int = 11866, nv: int = 16, J_max: int = 150) -> List[BandSystem]:
+    """Four seeded band systems, one per diatomic radiator of the air species
+    list, near the magnitudes of the real ones: N2 (a Pi - Pi system, Hund
+    (a)), N2+ (a doublet Sigma - Sigma system, Hund (b)), NO (a Sigma - Pi
+    system, Hund (a), dLambda = -1) and O2 (a Sigma - Sigma system, Hund
+    (a)).  Re'^2 ~ logU(1e-3, 1) per band."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    spec = [("N2", 0, 1, 1, 88000.0, 59600.0), ("N2+", 1, 0, 0, 25500.0, 0.0),
+            ("NO", 0, 0, 1, 44000.0, 0.0), ("O2", 0, 0, 0, 49800.0, 0.0)]
+    out = []
+    for name, hund, lu, ll, Tu, Tl in spec:
+        we = rng.uniform(1000.0, 2400.0, 2)
+        Be = rng.uniform(1.4, 2.0, 2)
+        out.append(BandSystem(
+            species=AIR11.index(name), hund=hund, Lambda_u=lu, Lambda_l=ll, Te_u=Tu, Te_l=Tl,
+            g_u=float(2 - (lu == 0)), g_l=float(2 - (ll == 0)),
+            we_u=float(we[0]), wexe_u=float(we[0] / rng.uniform(60.0, 120.0)), weye_u=float(rng.uniform(-0.5, 0.5)),
+            Be_u=float(Be[0]), ae_u=float(rng.uniform(0.01, 0.03)), De_u=float(rng.uniform(4e-6, 8e-6)),
+            be_u=float(rng.uniform(-1e-7, 1e-7)), gamma_u=float(rng.uniform(0.005, 0.03) if hund else 0.0),
+            we_l=float(we[1]), wexe_l=float(we[1] / rng.uniform(60.0, 120.0)), weye_l=float(rng.uniform(-0.5, 0.5)),
+            Be_l=float(Be[1]), ae_l=float(rng.uniform(0.01, 0.03)), De_l=float(rng.uniform(4e-6, 8e-6)),
+            be_l=float(rng.uniform(-1e-7, 1e-7)), gamma_l=float(rng.uniform(0.005, 0.03) if hund else 0.0),
+            nv_u=nv, nv_l=nv, J_max=J_max, Re2=_log_uniform(rng, 1e-3, 1.0, nv * nv)))
+    return out
 
 
 def merge_sorted(parts: List[Dict[str, np.ndarray]]) -> Lines:
