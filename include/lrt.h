@@ -444,7 +444,7 @@ lrt_status lrt_coeffs(lrt_ctx *ctx, int64_t band, lrt_precision prec, void *eta,
  * tau = kappa ds, F(t) = (1 - e^-t)/t, F(0) = 1.  I_out (device, [n_rays][band_len] doubles) receives the wall
  * intensity, or pass NULL; I_int_out (device, [n_rays] doubles) receives the
  * band's trapezoid sum with global-index weights (h/2 at grid ends, h inside).
- * The rays times the band's 128-point chunks must stay below 2^32
+ * The rays times the band's 1024-point chunks must stay below 2^32
  * (LRT_E_DEVICE otherwise).
  * Stream-ordered.  Errors: LRT_E_STATE (no rays, cells/rays mismatch),
  * LRT_E_ARG. */

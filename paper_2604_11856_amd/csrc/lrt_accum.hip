@@ -1011,7 +1011,8 @@ __device__ __forceinline__ void linear_j_step(const float (&fe)[kPPL], const flo
     const float Lk = (float)fmin(ldexp(Ls, fek), 3.0e38);
 #pragma unroll
     for (int j = 0; j < kPPL; ++j) {
-        const int32_t loc = kw + 64 * j + lane;
+        int32_t loc = kw + 64 * j + lane;
+        asm volatile("" : "+v"(loc));   // recomputed here, not held across the accumulation
         const float t = fk[j] * Lk;
         const float ex = __builtin_amdgcn_exp2f(t * (float)(-kLog2e));
         float wf, wn;
@@ -1032,7 +1033,7 @@ void serve_kernel(DevLines L, DevGrid g, const ServeReq *reqs, const ServeItem *
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int32_t it = s_item;
+        const int32_t it = uniform_i(s_item);   // one item per workgroup: scalar loads of its fields
         __syncthreads();   // every thread has read s_item before it is overwritten
         if (it >= n_items) break;
         const ServeItem w = items[it];
@@ -1087,7 +1088,8 @@ void serve_kernel(DevLines L, DevGrid g, const ServeReq *reqs, const ServeItem *
                 const float dsk = (float)fmin(ldexp(ds, esk), 3.0e38);
 #pragma unroll
                 for (int j = 0; j < kPPL; ++j) {
-                    const int32_t loc = kw + 64 * j + lane;
+                    int32_t loc = kw + 64 * j + lane;
+                    asm volatile("" : "+v"(loc));
                     double at, em;
                     segment_f32(e[j], kp[j], dsk, dse, at, em);
                     ts[loc] *= at;

@@ -21,8 +21,10 @@ constexpr double kPi = 3.14159265358979323846;
 // accumulation kernels are compiled for LRT_ACCUM_WAVES waves per SIMD
 // (register budget 512 / waves per lane).  Measured on the 400-cell, 2.2M-line
 // stagnation case: 2 points per lane at 8 waves per SIMD beats 4 points at 4
-// waves by 22% (1385 ms vs 1785 ms per launch) although the staging code then
-// spills a few registers around each round.
+// waves by 22% (1385 ms vs 1785 ms per launch).  At 8 waves the FP64 staging
+// code fits the 64-register budget only if the compiler's machine-level loop
+// invariant motion is off (it hoists FP64 constants into registers that then
+// spill); the build passes that option for the accumulation's unit.
 #ifndef LRT_ACCUM_PPL
 #define LRT_ACCUM_PPL 2
 #endif
@@ -41,13 +43,14 @@ constexpr int kTilePoints = kAccumThreads * kPPL;
 // Line records staged in LDS per round: one per thread.
 constexpr int kStage = kAccumThreads;
 
-// March tile: one wave owns one (ray, chunk) item of kMarchPoints = 64 x
-// kMarchPPT consecutive points; a workgroup of kMarchThreads holds the items
-// of kMarchWaves rays on the same chunk.
+// March tile: one workgroup of 256 threads owns one (ray, chunk) item of
+// kMarchPoints = 1024 consecutive points, 4 per thread.  (One wave per
+// (ray, 128-point chunk) item, with the whole chip on one chunk at a time,
+// halved the march's memory traffic but took 1.2-2x longer: the per-segment
+// work is then spread over 128 points instead of 1024.)
 constexpr int kMarchThreads = 256;
-constexpr int kMarchWaves = kMarchThreads / 64;
-constexpr int kMarchPPT = 2;
-constexpr int kMarchPoints = 64 * kMarchPPT;
+constexpr int kMarchPPT = 4;
+constexpr int kMarchPoints = kMarchThreads * kMarchPPT;
 
 // Workgroups per launch of a kernel whose grid can be large (the accumulation
 // over cells x tiles, the march over rays x chunks): a dispatch counts at most

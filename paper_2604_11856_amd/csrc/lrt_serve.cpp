@@ -535,7 +535,7 @@ lrt_status lrt_server_start(lrt_ctx *ctx, size_t budget, int max_slots, lrt_serv
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess)
-        s->n_groups = std::max(1, prop.multiProcessorCount * 4);
+        s->n_groups = std::max(1, prop.multiProcessorCount * 8);   // 8 waves per SIMD, as the kernel is built for
     lrt_server *raw = s.release();
     raw->th = std::thread([raw] { raw->run(); });
     *out = raw;
