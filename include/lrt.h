@@ -452,6 +452,19 @@ lrt_status lrt_march(lrt_ctx *ctx, int64_t band, lrt_precision prec, const void 
                      const void *kappa, const int32_t *escale, double *I_out, double *I_int_out,
                      void *stream);
 
+/* lrt_march for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same arguments, kernels and results as lrt_march, but the per-(ray, chunk)
+ * partial sums of the spectral trapezoid go to a static device array of the
+ * library (2^23 doubles, 64 MiB, held on each device the library runs on
+ * until the process ends) instead of a workspace the context allocates; no
+ * launch is profiled.  Calls that overlap on one device share that array and
+ * race.  Errors: as lrt_march, and LRT_E_ARG when the rays times the band's
+ * 1024-point chunks exceed 2^23. */
+lrt_status lrt_march_noalloc(lrt_ctx *ctx, int64_t band, lrt_precision prec, const void *eta,
+                             const void *kappa, const int32_t *escale, double *I_out, double *I_int_out,
+                             void *stream);
+
 /* The whole path of Sec. 2.2.3 (steps: populations of every cell, Sec. 2.1;
  * emission and absorption coefficients on the grid, Sec. 2.2.1; the formal
  * solution of the transfer equation along every ray; the wall flux integral

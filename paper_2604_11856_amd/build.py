@@ -34,7 +34,7 @@ def build_library(out: str = LIB) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = []
-    for name in ("lrt_accum", "lrt_march", "lrt_cr", "lrt_probe", "lrt_rovib"):
+    for name in ("lrt_accum", "lrt_march", "lrt_cr", "lrt_probe", "lrt_rovib", "lrt_noalloc"):
         obj = os.path.join(bdir, name + ".o")
         _run([HIPCC, *ARCH, *COMMON, *NO_PK, *EXTRA.get(name, []), "-c", os.path.join(CSRC, name + ".hip"),
               "-o", obj])

@@ -184,6 +184,9 @@ lrt_status band_range(lrt_ctx *c, int64_t band, int32_t &k_first, int32_t &n_ban
 lrt_status march_range(lrt_ctx *c, int32_t k_first, int32_t n_band, lrt_precision prec, const void *eta,
                        const void *kappa, const int32_t *escale, double *I_out, double *I_int_out,
                        hipStream_t st, double *partials, int64_t cap);
+// Device address of the static scratch array on `device` (current device),
+// looked up once per device; lrt_march_noalloc's buffer.
+hipError_t noalloc_scratch_init(int device);
 inline DevGrid dev_grid(const lrt_ctx *c)
 {
     return DevGrid{c->nu_min, c->h, (int32_t)c->n_points, 1.0 / c->h};

@@ -114,6 +114,9 @@ lrt_status lrt_create(int device, lrt_ctx **out)
     if (device < 0 || device >= n) return fail(nullptr, LRT_E_ARG, "device %d out of range (%d devices)", device, n);
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail(nullptr, LRT_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    // the static scratch of lrt_march_noalloc: its address on this device
+    e = noalloc_scratch_init(device);
+    if (e != hipSuccess) return fail(nullptr, LRT_E_DEVICE, "scratch address: %s", hipGetErrorString(e));
     lrt_ctx *c = new (std::nothrow) lrt_ctx();
     if (!c) return fail(nullptr, LRT_E_OOM, "context allocation failed");
     c->device = device;

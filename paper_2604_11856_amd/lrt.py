@@ -36,7 +36,7 @@ EXPORTS = ["lrt_version", "lrt_status_string", "lrt_create", "lrt_destroy", "lrt
            "lrt_count_terms_ranges", "lrt_profile",
            "lrt_profile_read", "lrt_server_start", "lrt_submit", "lrt_poll", "lrt_wait",
            "lrt_cancel", "lrt_server_info", "lrt_server_stop", "lrt_set_cr", "lrt_set_line_levels",
-           "lrt_cr_populations", "lrt_probe", "lrt_gen_rovib_lines"]
+           "lrt_cr_populations", "lrt_probe", "lrt_gen_rovib_lines", "lrt_march_noalloc"]
 
 KERNELS = {"thermo": 0, "scale": 1, "ranges": 2, "accum": 3, "march": 4, "cr": 5}
 
@@ -150,6 +150,7 @@ def lib():
             "lrt_count_terms": (st, [_vp, C.c_int64, _i64p, _i64p, _vp]),
             "lrt_solve_ranges": (st, [_vp, C.c_int, C.c_int64, _i64p, _i64p, _dp, _dp, _dp, _vp]),
             "lrt_probe": (st, [C.c_int, C.c_int, _dp, _dp]),
+            "lrt_march_noalloc": (st, [_vp, C.c_int64, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]),
             "lrt_gen_rovib_lines": (st, [_vp, C.c_int, C.POINTER(_BandSystem), C.c_double, C.c_double,
                                          C.c_int64, C.POINTER(_LineBuffers), _i64p, _vp]),
             "lrt_count_terms_ranges": (st, [_vp, C.c_int64, _i64p, _i64p, _i64p, _i64p, _vp]),
@@ -441,6 +442,12 @@ class Context:
     def march(self, band: int, precision: int, eta, kappa, escale, I_out, I_int_out, stream=None):
         self._chk(self._L.lrt_march(self.h, band, precision, _ptr(eta), _ptr(kappa),
                                     _ptr(escale), _ptr(I_out), _ptr(I_int_out), _stream(stream)))
+
+    def march_noalloc(self, band: int, precision: int, eta, kappa, escale, I_out, I_int_out, stream=None):
+        """lrt_march_noalloc: lrt_march with the library's static scratch
+        instead of an allocated workspace."""
+        self._chk(self._L.lrt_march_noalloc(self.h, band, precision, _ptr(eta), _ptr(kappa),
+                                            _ptr(escale), _ptr(I_out), _ptr(I_int_out), _stream(stream)))
 
     def solve(self, precision: int, first_band: int = 0, stream=None):
         s = self.sizes()
