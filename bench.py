@@ -208,15 +208,23 @@ def band_bench(args):
     ctx.close()
 
 
-# Sources of the accumulation kernel; the committed counter summary records
-# their sha256 (in this order).
+# Sources of the accumulation and march kernels; a committed counter summary
+# records the sha256 of its kernel's sources (in this order).
 ACCUM_SOURCES = ("lrt_accum.hip", "lrt_device.h", "lrt_internal.h")
+MARCH_SOURCES = ("lrt_march.hip", "lrt_device.h", "lrt_internal.h")
 
 
-def counter_traffic(summary):
-    """HBM bytes per accumulation launch from a committed counter summary,
-    provided it was taken with the current kernel sources; otherwise None."""
+def sources_sha256(sources):
     import hashlib
+    h = hashlib.sha256()
+    for f in sources:
+        h.update(open(os.path.join(ROOT, "paper_2604_11856_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def counter_summary(summary, sources):
+    """The machine-readable fields of a committed counter summary, provided it
+    was taken with the current kernel sources; otherwise None."""
     path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
@@ -225,12 +233,16 @@ def counter_traffic(summary):
         if ":" in ln:
             k, v = ln.split(":", 1)
             fields[k.strip().strip("-* ")] = v.strip()
-    h = hashlib.sha256()
-    for f in ACCUM_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2604_11856_amd", "csrc", f), "rb").read())
-    if fields.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernel_source_sha256") != sources_sha256(sources) or "traffic_bytes_per_launch" not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return fields
+
+
+def counter_traffic(summary, sources=ACCUM_SOURCES):
+    """HBM bytes per launch from a committed counter summary taken with the
+    current kernel sources; otherwise None."""
+    f = counter_summary(summary, sources)
+    return None if f is None else float(f["traffic_bytes_per_launch"])
 
 
 def serving(n_open, budget_gb=64, slots=64):
@@ -609,6 +621,7 @@ def main():
     kf, npt = slice_ranges(sz["n_points"])
     n_slice_pts = int(npt.sum())
     n_terms, n_core = ctx.count_terms_ranges(kf, npt, core=True)
+    terms_per_range = [int(ctx.count_terms_ranges(kf[j:j + 1], npt[j:j + 1])) for j in range(SLICE_RANGES)]
     n_seg = ctx.segment_count()
     log("slice: %d terms, %d segments" % (n_terms, n_seg))
 
@@ -651,6 +664,7 @@ def main():
     slots_per_launch = (n_core * SLOTS_CORE + (n_terms - n_core) * SLOTS_WING) / SLICE_RANGES
     mar_launch_s = prof32["march"][0] / 1e3 / max(1, prof32["march"][1])
     march_bytes_per_launch = n_seg * RANGE_POINTS * 8.0
+    march_traffic = counter_traffic("march_f32_axi_large_slice_pmc.md", MARCH_SOURCES)
     line = {
         "metric": METRIC,
         "value": n_terms / dt32,
@@ -669,7 +683,7 @@ def main():
                    "cells": sz["n_cells"], "lines": wl.lines.n, "grid_points": sz["n_points"],
                    "slice_ranges": [[int(a), int(b)] for a, b in zip(kf, npt)],
                    "traced_rays": sz["n_rays"], "wall_points": sz["n_wall"], "segments": n_seg,
-                   "voigt_terms_per_step": n_terms},
+                   "voigt_terms_per_step": n_terms, "voigt_terms_per_range": terms_per_range},
         "whole_config_extrapolated": {
             "ms_by_points": t_full_pts * 1e3, "ms_by_terms": t_full_terms * 1e3,
             "voigt_terms": n_terms_full, "q_rad_solves_per_s": sz["n_wall"] / t_full_terms,
@@ -691,7 +705,9 @@ def main():
         "march_roofline": {"bound": "hbm", "kernel": "march_f32",
                            "achieved": march_bytes_per_launch / mar_launch_s / 1e9, "peak": HBM_PEAK / 1e9,
                            "unit": "GB/s", "frac": march_bytes_per_launch / mar_launch_s / HBM_PEAK,
-                           "traffic": None, "row_bytes_per_launch": march_bytes_per_launch,
+                           "traffic": march_traffic, "row_bytes_per_launch": march_bytes_per_launch,
+                           "hbm_GB_per_s_from_counters": (march_traffic / mar_launch_s / 1e9
+                                                          if march_traffic else None),
                            "avg_launch_ms": mar_launch_s * 1e3},
         "p50_latency_ms": None, "p99_latency_ms": None,
     }
