@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=500,
                     help="requests per open-loop rate (closed loop: 2/5 of it); 0 skips serving")
     ap.add_argument("--peak", action="store_true", help="only run the unit throughput probes and exit")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only run the serving stream (--serving-requests per open-loop rate) and exit")
     ap.add_argument("--no-full-count", action="store_true",
                     help="skip the whole-configuration term count (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -475,7 +477,8 @@ def whole_solve_leg(name, lrt, torch, steps, fp64_steps, side):
     n_terms = sum(c[0] for c in counts)
     dt, (q, I, _), prof = timed(ctx, lrt, torch, lambda: ctx.solve(lrt.LRT_FP32_COMP), steps, 1)
     out = {"workload": desc, "steps": steps, "ms_per_step": dt * 1e3, "evals_per_s": n_terms / dt,
-           "voigt_terms_per_step": n_terms, "q_rad_solves_per_s": sz["n_wall"] / dt,
+           "voigt_terms_per_step": n_terms, "terms_per_band": [int(c[0]) for c in counts],
+           "core_terms_per_band": [int(c[1]) for c in counts], "q_rad_solves_per_s": sz["n_wall"] / dt,
            "los_solves_per_s": sz["n_rays"] / dt,
            "accum_ms_per_step": prof["accum"][0] / steps, "march_ms_per_step": prof["march"][0] / steps}
     if fp64_steps > 0:
@@ -600,6 +603,9 @@ def main():
         return
     if args.band is not None:
         band_bench(args)
+        return
+    if args.serving_only:
+        print(json.dumps({"metric": "serving stream", "serving": serving(max(1, args.serving_requests))}), flush=True)
         return
     import torch
     from paper_2604_11856_amd import lrt
