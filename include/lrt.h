@@ -615,7 +615,8 @@ typedef struct {
  * (ctx cells and rays are not used; ctx must not be used for other calls until
  * lrt_server_stop).  hbm_budget_bytes of device memory are allocated once and
  * shared by admitted requests; at most max_slots requests are admitted at a
- * time.  Each request is computed by fused kernels (populations, setups,
+ * time (each slot also holds 8 bytes of pinned host memory, where the device
+ * writes the request's integral).  Each request is computed by fused kernels (populations, setups,
  * accumulation and march per spectral tile and chunk of cells, then the
  * chunks composed in order), single-precision compensated profile sums, FP64
  * march state and quadrature; no eta/kappa array is stored.  The context's

@@ -13,8 +13,8 @@
 //               then every lane accumulates the Whiting-Voigt profile of each
 //               staged line at its own grid points (Sec. 2.2.1)
 //   count       per (cell, candidate line): in-window and core term counts
-//   serve       persistent serving kernel (profiles + march of request chunks)
-//               and the chunk combine
+//   serve       serving kernel: profiles + march of request chunks, one
+//               workgroup per item, and the composition of finished tiles
 // The march of the path and its reductions live in lrt_march.hip.
 //
 // Everything is output-stationary: each output element has one owner, so no
@@ -990,13 +990,16 @@ __global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, int
 }
 
 // ---------------------------------------------------------------------------
-// a7: serving.  A persistent workgroup pulls (request, tile, chunk) items from
-// an epoch's list through an atomic counter until the list is exhausted; every
-// workgroup exits then.  An item accumulates eta/kappa of each cell of its
-// chunk on its tile (in LDS / registers, never stored) and marches through them
-// at once, producing the chunk's transmittance T and source S per point:
-// I_out = I_in T + S.  The combine kernel then composes the chunks far ->
-// observer in a fixed order.  Nothing depends on what else shares the epoch.
+// a7: serving.  One workgroup per (request, tile, chunk) item of an epoch's
+// list, so workgroups retire all through an epoch and work on other streams
+// (admissions, result copies) finds free slots without waiting for the epoch.
+// An item accumulates eta/kappa of each cell of its chunk on its tile (in LDS /
+// registers, never stored) and marches through them at once, producing the
+// chunk's transmittance T and source S per point: I_out = I_in T + S.  The
+// workgroup that completes the last chunk of a tile composes the tile's chunks
+// far -> observer, and the one that completes the last tile sums the tiles:
+// every sum runs in a fixed order, so nothing depends on what else shares the
+// epoch or on the order in which items finish.
 // ---------------------------------------------------------------------------
 
 // One linear-j segment of length Ls (cm) from far node (fe, fk) to near node
@@ -1022,21 +1025,50 @@ __device__ __forceinline__ void linear_j_step(const float (&fe)[kPPL], const flo
     }
 }
 
+// Compose the chunks of the tile's points far -> observer (I <- I T + S in
+// chunk order, from the far boundary's blackbody intensity when there is
+// one), write I and the tile's trapezoid sum (h/2 at both window ends) in a
+// fixed order: each thread's points, the wave's lanes by xor-shuffles, then
+// the waves in order.  Called by the whole workgroup.
+__device__ __forceinline__ void serve_compose_tile(const ServeReq &R, const DevGrid &g, int32_t tile, int32_t kw,
+                                                   int lane, double *s_part)
+{
+    double part = 0.0;
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        const int32_t loc = kw + 64 * j + lane;
+        const int32_t t = tile * kTilePoints + loc;
+        if (t < R.n_window) {
+            double I = R.T_far > 0.0 ? planck_f64(g.nu_min + (double)(R.k_first + t) * g.h, R.T_far) : 0.0;
+            for (int32_t m = 0; m < R.n_chunks; ++m) {
+                const double *ts = R.TS + ((int64_t)tile * R.n_chunks + m) * 2 * kTilePoints;
+                I = fma(I, ts[loc], ts[kTilePoints + loc]);
+            }
+            R.I_out[t] = I;
+            const double w = (t == 0 || t == R.n_window - 1) ? 0.5 * g.h : g.h;
+            part = fma(w, I, part);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (lane == 0) s_part[kw / (64 * kPPL)] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int wv = 0; wv < kAccumThreads / 64; ++wv) sum += s_part[wv];
+        R.tile_part[tile] = sum;
+    }
+}
+
 __global__ __launch_bounds__(kAccumThreads) __attribute__((amdgpu_waves_per_eu(LRT_SERVE_WAVES)))
-void serve_kernel(DevLines L, DevGrid g, const ServeReq *reqs, const ServeItem *items, int32_t n_items,
-                  int32_t *counter, int32_t n_species)
+void serve_kernel(DevLines L, DevGrid g, const ServeReq *reqs, const ServeItem *items, int32_t n_species)
 {
     __shared__ RecF32 rec[kStage];
-    __shared__ int32_t s_item;
+    __shared__ int32_t s_last;
+    __shared__ double s_part[kAccumThreads / 64];
     const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
     const int32_t kw = wave * 64 * kPPL;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-        __syncthreads();
-        const int32_t it = uniform_i(s_item);   // one item per workgroup: scalar loads of its fields
-        __syncthreads();   // every thread has read s_item before it is overwritten
-        if (it >= n_items) break;
-        const ServeItem w = items[it];
+    {
+        const ServeItem w = items[blockIdx.x];
         // the request's fields are read where used: held in registers across
         // the cell loop they would crowd out the accumulation's
         const ServeReq &R = reqs[w.req];
@@ -1114,33 +1146,32 @@ void serve_kernel(DevLines L, DevGrid g, const ServeReq *reqs, const ServeItem *
         }
         if (linear && c1 == R.n_cells)   // last midpoint -> observer
             linear_j_step(pe, pk, pee, pek, pe, pee, 0.5 * pds, ts, kw, lane);
+        // publish this chunk's T and S; the workgroup that brings the tile's
+        // count to n_chunks composes the tile (device-scope fences around the
+        // counter: the chunks may have run on other XCDs)
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) s_last = atomicAdd(R.done + w.tile, 1) == R.n_chunks - 1;
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+        serve_compose_tile(R, g, w.tile, kw, lane, s_part);
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) s_last = atomicAdd(R.done + R.n_tiles, 1) == R.n_tiles - 1;
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+        if (threadIdx.x == 0) {
+            double sum = 0.0;
+            for (int32_t t = 0; t < R.n_tiles; ++t) sum += R.tile_part[t];
+            *R.I_int = sum;
+            *R.I_int_host = sum;
+        }
     }
 }
 
-// Compose the chunks of every window point far -> observer, write I and the
-// window's trapezoid partials (h/2 at both window ends).
-__global__ __launch_bounds__(256) void serve_combine_kernel(ServeReq R, DevGrid g)
-{
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    double part = 0.0;
-    if (t < R.n_window) {
-        const int32_t tile = t / kTilePoints, loc = t % kTilePoints;
-        // a solid far boundary starts the march at its blackbody intensity
-        double I = R.T_far > 0.0 ? planck_f64(g.nu_min + (double)(R.k_first + t) * g.h, R.T_far) : 0.0;
-        for (int32_t m = 0; m < R.n_chunks; ++m) {
-            const double *ts = R.TS + ((int64_t)tile * R.n_chunks + m) * 2 * kTilePoints;
-            I = fma(I, ts[loc], ts[kTilePoints + loc]);
-        }
-        R.I_out[t] = I;
-        const double w = (t == 0 || t == R.n_window - 1) ? 0.5 * g.h : g.h;
-        part = w * I;
-    }
-    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-    __shared__ double wsum[4];
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
-    __syncthreads();
-    if (threadIdx.x == 0) R.partials[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
-}
+
 
 
 }  // namespace
@@ -1278,24 +1309,12 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
 
 
 hipError_t launch_serve(const DevLines &L, const DevGrid &g, const ServeReq *reqs,
-                        const ServeItem *items, int32_t n_items, int32_t *counter,
-                        int32_t n_species, int32_t n_groups, hipStream_t st)
+                        const ServeItem *items, int32_t n_items, int32_t n_species, hipStream_t st)
 {
-    // counter must hold 0 on entry; every workgroup leaves once it draws an
-    // index >= n_items
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(serve_kernel, dim3((unsigned)max(1, min(n_groups, n_items))),
-                       dim3(kAccumThreads), 0, st, L, g, reqs, items, n_items, counter, n_species);
+    hipLaunchKernelGGL(serve_kernel, dim3((unsigned)n_items), dim3(kAccumThreads), 0, st, L, g, reqs, items,
+                       n_species);
     return hipGetLastError();
-}
-
-hipError_t launch_serve_combine(const ServeReq &R, const DevGrid &g, hipStream_t st)
-{
-    const unsigned nb = blocks_for(R.n_window, 256);
-    hipLaunchKernelGGL(serve_combine_kernel, dim3(nb), dim3(256), 0, st, R, g);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_reduce_rows(R.partials, 1, (int32_t)nb, R.I_int, st);
 }
 
 }  // namespace lrt

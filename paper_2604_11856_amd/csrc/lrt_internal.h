@@ -233,8 +233,10 @@ struct ServeReq {
     const int2 *ranges;      // [cell][tile]
     double *TS;              // [tile][chunk][2][kTilePoints]: transmittance, source
     double *I_out;           // [n_window]
-    double *partials;        // [ceil(n_window / 256)]
+    int32_t *done;           // [n_tiles + 1]: chunks composed per tile, then tiles composed
+    double *tile_part;       // [n_tiles]: trapezoid sum of each tile's points
     double *I_int;           // [1]
+    double *I_int_host;      // the request's slot in pinned host memory
     DevCont ct;              // the request's atomic continuum (n_thr < 0: none)
     double T_far;            // solid far boundary temperature (0: free)
     int32_t linear;          // segment scheme: 0 cell-constant, 1 linear-j
@@ -307,10 +309,7 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 hipError_t launch_check_cells(const DevCells &cells, int32_t *flags, hipStream_t st);
 
 hipError_t launch_serve(const DevLines &L, const DevGrid &g, const ServeReq *reqs,
-                        const ServeItem *items, int32_t n_items, int32_t *counter,
-                        int32_t n_species, int32_t n_groups, hipStream_t st);
-
-hipError_t launch_serve_combine(const ServeReq &req_host, const DevGrid &g, hipStream_t st);
+                        const ServeItem *items, int32_t n_items, int32_t n_species, hipStream_t st);
 
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st);
 

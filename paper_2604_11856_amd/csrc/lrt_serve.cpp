@@ -10,12 +10,14 @@
 //     the line peaks, over the bins whose lines can reach the window);
 //   - epochs: items (request, tile, cell chunk) of every admitted request are
 //     handed out round-robin into bounded epochs, each one launch of the
-//     persistent serving kernel on one of two epoch streams, so new work joins
-//     while earlier epochs run;
-//   - completion: when all items of a request are done, the combine kernel
-//     composes its chunks on a stream of its own; the integral (and
-//     optionally the spectrum) is copied back and the slot and memory are
-//     released.
+//     serving kernel (one workgroup per item) on one of two epoch streams, so
+//     new work joins while earlier epochs run, and workgroups retire all
+//     through an epoch, leaving slots for the admission kernels and copies;
+//   - completion: the workgroup that finishes a tile's last chunk composes
+//     the tile, the one that finishes the last tile writes the integral into
+//     the request's slot of pinned host memory; once every item of a request
+//     is done the scheduler reads it (and optionally copies the spectrum back)
+//     and releases the slot and memory.
 // A request's decomposition depends only on the request itself, so its result
 // is bitwise the same alone and in a mix.
 #include <hip/hip_runtime.h>
@@ -90,7 +92,7 @@ struct Arena {
     }
 };
 
-enum State { ST_PENDING, ST_ADMITTED, ST_COMBINING, ST_DONE };
+enum State { ST_PENDING, ST_ADMITTED, ST_DONE };
 
 struct Req {
     uint64_t ticket = 0;
@@ -111,7 +113,7 @@ struct Req {
     size_t bytes = 0, off = 0;
     int slot = -1;
     int64_t items_total = 0, items_issued = 0, items_done = 0;
-    hipEvent_t prep_ev = nullptr, comb_ev = nullptr;
+    hipEvent_t prep_ev = nullptr;
     ServeReq dev{};
     // timing and results
     Clock::time_point t_submit, t_admit, t_done;
@@ -124,7 +126,7 @@ struct Epoch {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     ServeItem *h_items = nullptr;   // pinned
-    DBuf d_items, d_counter;
+    DBuf d_items;
     std::vector<std::pair<uint64_t, int64_t>> credit;   // ticket -> items
 };
 
@@ -145,7 +147,8 @@ size_t request_bytes(int64_t nc, int S, int32_t n_window, int32_t n_thr, int32_t
     b += align_up((size_t)nc * n_tiles * sizeof(int2));     // ranges
     b += align_up((size_t)n_tiles * n_chunks * 2 * kTilePoints * 8);   // T, S
     b += align_up((size_t)n_window * 8);                    // I
-    b += align_up(nb * 8) + align_up(8);                    // partials, I_int
+    b += align_up((size_t)(n_tiles + 1) * 4);               // done counters
+    b += align_up((size_t)n_tiles * 8) + align_up(8);       // tile sums, I_int
     if (n_thr >= 0)                                         // continuum: cum, ff, lnb
         b += align_up((size_t)nc * 2 * (n_thr + 1) * 8) + 2 * align_up((size_t)nc * 2 * 8);
     if (cr_row > 0)                                         // QSS-CR: populations, departures
@@ -164,12 +167,11 @@ struct lrt_server {
     lrt_ctx *ctx = nullptr;
     size_t budget = 0;
     int max_slots = 0;
-    int n_groups = 1024;
     Arena arena;
     DBuf d_arena, d_reqs;
     std::vector<int> free_slots;
     hipStream_t admit_stream = nullptr;
-    hipStream_t done_stream = nullptr;   // combine of finished requests, apart from admissions
+    double *h_I_int = nullptr;   // pinned, one per slot: the integral written by the serving kernel
     Epoch epochs[kEpochStreams];
 
     std::mutex mu;
@@ -211,8 +213,7 @@ void lrt_server::release(Req &r)
         r.bytes = 0;
     }
     if (r.prep_ev) (void)hipEventDestroy(r.prep_ev);
-    if (r.comb_ev) (void)hipEventDestroy(r.comb_ev);
-    r.prep_ev = r.comb_ev = nullptr;
+    r.prep_ev = nullptr;
 }
 
 bool lrt_server::admit(Req &r)
@@ -245,7 +246,8 @@ bool lrt_server::admit(Req &r)
     int2 *ranges = (int2 *)take((size_t)nc * r.n_tiles * sizeof(int2));
     double *TS = (double *)take((size_t)r.n_tiles * r.n_chunks * 2 * kTilePoints * 8);
     double *I_out = (double *)take((size_t)r.n_window * 8);
-    double *partials = (double *)take((size_t)(r.n_window + 255) / 256 * 8);
+    int32_t *done = (int32_t *)take((size_t)(r.n_tiles + 1) * 4);
+    double *tile_part = (double *)take((size_t)r.n_tiles * 8);
     double *I_int = (double *)take(8);
     double *cum = nullptr, *ff = nullptr, *lnb = nullptr;
     if (n_thr >= 0) {
@@ -325,8 +327,9 @@ bool lrt_server::admit(Req &r)
         if (!ok(launch_scale_bound(B, cc, cs, lnb, (int32_t)nc, S, escale, st), "scale"))
             return true;
     }
+    if (!ok(launch_fill_i32(done, 0, (int64_t)r.n_tiles + 1, st), "counters")) return true;
     r.dev = ServeReq{(int32_t)nc, r.k_first, r.n_window, r.n_tiles, r.n_chunks, kChunkCells,
-                     cc, cs, escale, ds, ranges, TS, I_out, partials, I_int, ct, r.T_far,
+                     cc, cs, escale, ds, ranges, TS, I_out, done, tile_part, I_int, h_I_int + r.slot, ct, r.T_far,
                      r.scheme == LRT_MARCH_LINEAR_J ? 1 : 0, L.lnd_stride, L.lnd};
     if (!ok(hipMemcpyAsync(d_reqs.as<ServeReq>() + r.slot, &r.dev, sizeof(ServeReq),
                            hipMemcpyHostToDevice, st), "upload") ||
@@ -389,10 +392,8 @@ bool lrt_server::launch_epoch(Epoch &e)
     const DevGrid g = dev_grid(ctx);
     hipError_t err = hipMemcpyAsync(e.d_items.p, e.h_items, (size_t)n * sizeof(ServeItem),
                                     hipMemcpyHostToDevice, e.stream);
-    if (err == hipSuccess) err = launch_fill_i32(e.d_counter.as<int32_t>(), 0, 1, e.stream);
     if (err == hipSuccess)
-        err = launch_serve(L, g, d_reqs.as<ServeReq>(), e.d_items.as<ServeItem>(), n,
-                           e.d_counter.as<int32_t>(), ctx->n_species, n_groups, e.stream);
+        err = launch_serve(L, g, d_reqs.as<ServeReq>(), e.d_items.as<ServeItem>(), n, ctx->n_species, e.stream);
     if (err == hipSuccess) err = hipEventRecord(e.done, e.stream);
     if (err != hipSuccess) {
         fatal = std::string("epoch launch: ") + hipGetErrorString(err);
@@ -424,39 +425,23 @@ void lrt_server::run()
             progress = true;
         }
         if (!fatal.empty()) break;
-        // 2) requests with every item done: compose the chunks
-        for (uint64_t t : admitted) {
-            Req &r = *reqs[t];
-            if (r.state != ST_ADMITTED || r.items_done < r.items_total) continue;
-            const DevGrid g = dev_grid(ctx);
-            // (its own stream: a finished request does not queue behind the
-            // uploads and per-cell kernels of requests being admitted)
-            hipError_t err = launch_serve_combine(r.dev, g, done_stream);
-            if (err == hipSuccess) err = hipEventCreateWithFlags(&r.comb_ev, hipEventDisableTiming);
-            if (err == hipSuccess) err = hipEventRecord(r.comb_ev, done_stream);
-            if (err != hipSuccess) {
-                fatal = std::string("combine: ") + hipGetErrorString(err);
-                break;
-            }
-            r.state = ST_COMBINING;
-            progress = true;
-        }
-        if (!fatal.empty()) break;
-        // 3) composed requests: results to the host, resources back
+        // 2) requests with every item done: the serving kernel has composed
+        //    them and written the integral to the slot's pinned host word
         for (size_t a = 0; a < admitted.size();) {
             Req &r = *reqs[admitted[a]];
-            if (r.state != ST_COMBINING || hipEventQuery(r.comb_ev) != hipSuccess) {
+            if (r.state != ST_ADMITTED || r.items_done < r.items_total) {
                 ++a;
                 continue;
             }
-            hipError_t err = hipMemcpy(&r.I_int, r.dev.I_int, 8, hipMemcpyDeviceToHost);
-            if (err == hipSuccess && r.keep) {
+            r.I_int = h_I_int[r.slot];
+            if (r.keep) {
                 r.spectrum.resize(r.n_window);
-                err = hipMemcpy(r.spectrum.data(), r.dev.I_out, (size_t)r.n_window * 8, hipMemcpyDeviceToHost);
-            }
-            if (err != hipSuccess) {
-                fatal = std::string("result copy: ") + hipGetErrorString(err);
-                break;
+                const hipError_t err = hipMemcpy(r.spectrum.data(), r.dev.I_out, (size_t)r.n_window * 8,
+                                                 hipMemcpyDeviceToHost);
+                if (err != hipSuccess) {
+                    fatal = std::string("result copy: ") + hipGetErrorString(err);
+                    break;
+                }
             }
             r.state = ST_DONE;
             r.t_done = Clock::now();
@@ -467,7 +452,7 @@ void lrt_server::run()
             cv_done.notify_all();
         }
         if (!fatal.empty()) break;
-        // 4) admission: FIFO with skip-ahead
+        // 3) admission: FIFO with skip-ahead
         for (auto it = pending.begin(); it != pending.end();) {
             Req &r = *reqs[*it];
             if (admit(r)) {
@@ -478,7 +463,7 @@ void lrt_server::run()
             }
             if (free_slots.empty()) break;
         }
-        // 5) keep the epoch streams fed
+        // 4) keep the epoch streams fed
         for (auto &e : epochs) {
             if (!e.busy && launch_epoch(e)) progress = true;
             if (!fatal.empty()) break;
@@ -524,18 +509,13 @@ lrt_status lrt_server_start(lrt_ctx *ctx, size_t budget, int max_slots, lrt_serv
     if ((st = upload(ctx, s->d_reqs, nullptr, (size_t)max_slots * sizeof(ServeReq)))) return st;
     for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     LRT_HIP(ctx, hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking));
-    LRT_HIP(ctx, hipStreamCreateWithFlags(&s->done_stream, hipStreamNonBlocking));
+    LRT_HIP(ctx, hipHostMalloc((void **)&s->h_I_int, (size_t)max_slots * 8, hipHostMallocDefault));
     for (auto &e : s->epochs) {
         LRT_HIP(ctx, hipStreamCreateWithFlags(&e.stream, hipStreamNonBlocking));
         LRT_HIP(ctx, hipEventCreateWithFlags(&e.done, hipEventDisableTiming));
         LRT_HIP(ctx, hipHostMalloc((void **)&e.h_items, kEpochCap * sizeof(ServeItem), hipHostMallocDefault));
-        if ((st = upload(ctx, e.d_items, nullptr, kEpochCap * sizeof(ServeItem))) ||
-            (st = upload(ctx, e.d_counter, nullptr, 64)))
-            return st;
+        if ((st = upload(ctx, e.d_items, nullptr, kEpochCap * sizeof(ServeItem)))) return st;
     }
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess)
-        s->n_groups = std::max(1, prop.multiProcessorCount * 8);   // 8 waves per SIMD, as the kernel is built for
     lrt_server *raw = s.release();
     raw->th = std::thread([raw] { raw->run(); });
     *out = raw;
@@ -682,7 +662,7 @@ lrt_status lrt_server_stop(lrt_server *s)
         if (e.stream) (void)hipStreamDestroy(e.stream);
     }
     if (s->admit_stream) (void)hipStreamDestroy(s->admit_stream);
-    if (s->done_stream) (void)hipStreamDestroy(s->done_stream);
+    if (s->h_I_int) (void)hipHostFree(s->h_I_int);
     const std::string msg = s->fatal;
     delete s;
     if (!ok) return fail(nullptr, LRT_E_DEVICE, "server failed: %s", msg.c_str());
