@@ -459,8 +459,8 @@ __global__ void scale_finish_kernel(const int32_t *emax, const double *cont_lnb,
 // bit masks and needs no vector work for control flow.
 constexpr int kSlices = kTilePoints / 64;
 struct __align__(16) RecF32 {
-    float k0f, hg, fg, r;           // centre index (tile-relative), h/gV, frac0/gV, gL/gV
-    float aG, aW, se, sk;           // 1-r, 0.016 r (1-r), scaled strengths
+    float k0f, hg, fg, qw;          // centre index (tile-relative), h/gV, frac0/gV, 0.016 r (1-r) / s
+    float qg, pad0, se, sk;         // (1-r) / s, -, strengths times s and the cell's scale
     float klo, khi;                 // window, tile-relative, clamped to [-1, tile] (edge masks)
     uint32_t mode, pad;
 };
@@ -516,10 +516,14 @@ __device__ __forceinline__ ShapeConsts shape_consts()
     return K;
 }
 
-// Rational part r/(1+4x^2) - 0.016 r(1-r)/(1+0.1 x^2.25) over one reciprocal;
-// also returns 1 + y^2 and |y|^2.25 for the exponential part.  (Two
-// reciprocals save two instructions but measured 4 % slower: the
-// transcendental pipe, not the instruction count, then sets the pace.)
+// The profile divided by s = r = gL/gV (the staged strengths carry the
+// factor s back): rational part [1/(1+4x^2) - 0.016 (1-r)/(1+0.1 x^2.25)]
+// over one reciprocal, whose numerator (1+0.1 x^2.25) - 0.016 (1-r)(1+4x^2)
+// is one FMA; also returns 1 + y^2 and |y|^2.25 for the exponential part.
+// A line with r below kRScaleMin is staged with s = kRScaleMin instead, which
+// adds a Lorentzian of at most kRScaleMin of the line's own peak.  (Two
+// reciprocals save instructions but measured 4 % slower: the transcendental
+// pipe, not the instruction count, then sets the pace.)
 __device__ __forceinline__ float shape_rational_f32(float kf, const RecF32 &q, const ShapeConsts &K, float &d1,
                                                     float &p)
 {
@@ -527,17 +531,20 @@ __device__ __forceinline__ float shape_rational_f32(float kf, const RecF32 &q, c
     d1 = fmaf(y, y, 1.0f);
     p = __builtin_amdgcn_exp2f(K.c225 * __builtin_amdgcn_logf(fabsf(y)));
     const float d2 = fmaf(p, K.cw, 1.0f);
-    const float num = fmaf(q.r, d2, -(q.aW * d1));
+    const float num = fmaf(-q.qw, d1, d2);
     return num * __builtin_amdgcn_rcpf(d1 * d2);
 }
 
-// Exponential part (1-r) e^{-2.772 x^2} + 0.016 r(1-r) e^{-0.4 x^2.25} added to
-// P, with x^2 = (d1 - 1)/4 folded into the exponent's FMA.
+// Smallest normalisation s of the staged profile (2^-40).
+constexpr double kRScaleMin = 9.094947017729282e-13;
+
+// Exponential part [(1-r) e^{-2.772 x^2} + 0.016 r(1-r) e^{-0.4 x^2.25}] / s
+// added to P, with x^2 = (d1 - 1)/4 folded into the exponent's FMA.
 __device__ __forceinline__ float shape_exp_f32(const RecF32 &q, const ShapeConsts &K, float d1, float p, float P)
 {
     const float gs = __builtin_amdgcn_exp2f(fmaf(d1, K.cg, -K.cg));
     const float e = __builtin_amdgcn_exp2f(p * K.ce);
-    return fmaf(q.aG, gs, fmaf(q.aW, e, P));
+    return fmaf(q.qg, gs, fmaf(q.qw, e, P));
 }
 
 // Block -> (tile, cell) order of the accumulation grid: groups of 8 tiles x
@@ -651,7 +658,7 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
         rr.mode = 0;
         rr.klo = 1.0f;
         rr.khi = 0.0f;
-        rr.k0f = rr.hg = rr.fg = rr.r = rr.aG = rr.aW = rr.se = rr.sk = 0.0f;
+        rr.k0f = rr.hg = rr.fg = rr.qw = rr.qg = rr.pad0 = rr.se = rr.sk = 0.0f;
         rr.pad = 0;
         if (i < rg.y) {
             PairF64 p;
@@ -664,11 +671,12 @@ __device__ __forceinline__ void accum_cell_tile_f32(RecF32 *rec, const DevLines 
                 rr.k0f = (float)(L.k0[i] - kt);
                 rr.hg = (float)(2.0 * g.h * p.inv2g);
                 rr.fg = (float)(2.0 * L.frac0[i] * p.inv2g);
-                rr.r = (float)p.r;
-                rr.aG = (float)(1.0 - p.r);
-                rr.aW = (float)(0.016 * p.r * (1.0 - p.r));
-                rr.se = (float)ldexp(p.se, -ese);
-                rr.sk = (float)ldexp(p.sk, -esk);
+                // profile divided by s = r, strengths times s
+                const double sc = fmax(p.r, kRScaleMin), isc = 1.0 / sc;
+                rr.qw = (float)(0.016 * p.r * (1.0 - p.r) * isc);
+                rr.qg = (float)((1.0 - p.r) * isc);
+                rr.se = (float)ldexp(p.se * sc, -ese);
+                rr.sk = (float)ldexp(p.sk * sc, -esk);
             }
         }
         rec[threadIdx.x] = rr;
