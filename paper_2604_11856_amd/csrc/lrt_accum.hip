@@ -1,9 +1,10 @@
 // gfx950 kernels of the line-by-line path (arXiv 2604.11856): populations,
 // line setups and the line-to-grid accumulation.
 //
-//   thermo      per (cell, species): partition function, ln(N/Q), Doppler
-//               coefficient; per cell: beta's, Lorentz HWHM, line-skip bound
-//               (Sec. 2.1 Boltzmann populations, Sec. 2.2.1 widths); the
+//   thermo      per (cell, species): atomic partition function, ln(N/Q),
+//               Doppler coefficient; per cell: beta's, Lorentz HWHM, line-skip
+//               bound (Sec. 2.1 Boltzmann populations, Sec. 2.2.1 widths);
+//               molq: ln(N/Q) of the molecules, one wave per (cell, species); the
 //               QSS-CR populations of selected atoms come from lrt_cr.hip
 //               and enter the line setup as departures from Boltzmann
 //   ranges      per (cell, tile): index range of the nu0-sorted lines that
@@ -73,26 +74,13 @@ __global__ void thermo_kernel(DevSpecies sp, DevCells cells, DevWidths wd, doubl
     if (kind == 1) {
         for (int64_t j = sp.lev_off[s]; j < sp.lev_off[s + 1]; ++j)
             Q += sp.lev_g[j] * exp(-bv * sp.lev_E[j]);
-    } else if (kind == 2) {
-        for (int64_t e = sp.el_off[s]; e < sp.el_off[s + 1]; ++e) {
-            double qvr = 0.0;
-            for (int64_t v = sp.vib_off[e]; v < sp.vib_off[e + 1]; ++v) {
-                const double B = sp.vib_B[v], D = sp.vib_D[v];
-                double qr = 0.0;
-                for (int J = 0; J <= sp.el_Jmax[e]; ++J) {
-                    const double jj = (double)J * (J + 1.0);
-                    qr += (2.0 * J + 1.0) * exp(-br * (B * jj - D * jj * jj));
-                }
-                qvr += exp(-bv * sp.vib_G[v]) * qr;
-            }
-            Q += sp.el_g[e] * exp(-bv * sp.el_T[e]) * qvr;
-        }
     }
     const double N = cells.N[(int64_t)c * S + s];
     CellSpecies o;
-    // species outside a non-zero mask carry no lines (bit s of mask)
+    // species outside a non-zero mask carry no lines (bit s of mask); a
+    // molecule's ln(N/Q) comes from molq_kernel, launched next
     const bool on = species_on(mask, s);
-    o.lnNQ = (on && kind != 0 && N > 0.0 && Q > 0.0) ? log(N) - log(Q) : -INFINITY;
+    o.lnNQ = (on && kind == 1 && N > 0.0 && Q > 0.0) ? log(N) - log(Q) : -INFINITY;
     o.dop = 7.16233e-7 / 2.0 * sqrt(Ttr / sp.mass[s]);
     o.gW = (wd.E_ion && kind == 1 && wd.E_ion[s] > 0.0) ? vdw_width(sp, cells, c, s) : 0.0;
     cs[t] = o;
@@ -110,6 +98,41 @@ __global__ void thermo_kernel(DevSpecies sp, DevCells cells, DevWidths wd, doubl
         k.cand_G = 100.0 * (wd.gN_max + wd.gS_max * k.gL + gWmax) * (1.0 + 1e-6);
         k.cand_A = 100.0 * (7.16233e-7 / 2.0) * sqrt(Ttr / M_min) * (1.0 + 1e-6);
         cc[c] = k;
+    }
+}
+
+// ln(N/Q) of a molecule (Sec. 2.1 molecular Boltzmann relation), one wave per
+// (cell, species): Q = sum_e g_e e^{-beta_v T_e} sum_v e^{-beta_v G_v}
+// sum_J (2J+1) e^{-beta_tr (B_v J(J+1) - D_v J^2(J+1)^2)}, lane l taking the
+// J = l (mod 64) terms of every (e, v), then the lanes summed in a fixed
+// butterfly order.  Waves of other species leave at once.
+__global__ __launch_bounds__(64) void molq_kernel(DevSpecies sp, DevCells cells, uint64_t mask, CellSpecies *cs)
+{
+    const int S = cells.n_species;
+    const int64_t t = blockIdx.x;
+    const int c = (int)(t / S), s = (int)(t % S);
+    if (sp.kind[s] != 2) return;
+    const int lane = threadIdx.x;
+    const double bv = kC2 / cells.T_v[c], br = kC2 / cells.T_tr[c];
+    double Q = 0.0;
+    for (int64_t e = sp.el_off[s]; e < sp.el_off[s + 1]; ++e) {
+        double qvr = 0.0;
+        const int Jmax = sp.el_Jmax[e];
+        for (int64_t v = sp.vib_off[e]; v < sp.vib_off[e + 1]; ++v) {
+            const double B = sp.vib_B[v], D = sp.vib_D[v];
+            double qr = 0.0;
+            for (int J = lane; J <= Jmax; J += 64) {
+                const double jj = (double)J * (J + 1.0);
+                qr += (2.0 * J + 1.0) * exp(-br * (B * jj - D * jj * jj));
+            }
+            qvr += exp(-bv * sp.vib_G[v]) * qr;
+        }
+        Q += sp.el_g[e] * exp(-bv * sp.el_T[e]) * qvr;
+    }
+    for (int o = 32; o > 0; o >>= 1) Q += __shfl_xor(Q, o);
+    if (lane == 0) {
+        const double N = cells.N[(int64_t)c * S + s];
+        cs[t].lnNQ = (species_on(mask, s) && N > 0.0 && Q > 0.0) ? log(N) - log(Q) : -INFINITY;
     }
 }
 
@@ -1195,6 +1218,10 @@ hipError_t launch_thermo(const DevSpecies &sp, const DevCells &cells, const DevW
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(thermo_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, st, sp, cells, wd, M_min,
                        species_mask, cc, cs);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (n > (int64_t)UINT32_MAX) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(molq_kernel, dim3((unsigned)n), dim3(64), 0, st, sp, cells, species_mask, cs);
     return hipGetLastError();
 }
 
