@@ -43,14 +43,19 @@ constexpr int kTilePoints = kAccumThreads * kPPL;
 // Line records staged in LDS per round: one per thread.
 constexpr int kStage = kAccumThreads;
 
-// March tile: one workgroup of 256 threads owns one (ray, chunk) item of
-// kMarchPoints = 1024 consecutive points, 4 per thread.  (One wave per
-// (ray, 128-point chunk) item, with the whole chip on one chunk at a time,
-// halved the march's memory traffic but took 1.2-2x longer: the per-segment
-// work is then spread over 128 points instead of 1024.)
+// March tile: one workgroup of 256 threads owns one (ray group, chunk) item:
+// each of its 4 waves marches one ray of the group over the chunk's
+// kMarchPoints = 256 consecutive points, 4 per lane.  The waves share no
+// state, so a group's rays may have different segment counts.  (One
+// workgroup per (ray, 1024-point chunk), 4 points per thread, took 4.8 %
+// longer on 131,072 rays: a 1024-point row of every cell is 8 KB, a 256-point
+// one 2 KB, so four times as many rows stay in L2 while a chunk's rays run.
+// One wave per (ray, 128-point chunk) took 1.2-2x longer: the per-segment
+// work is then spread over 128 points.)
 constexpr int kMarchThreads = 256;
 constexpr int kMarchPPT = 4;
-constexpr int kMarchPoints = kMarchThreads * kMarchPPT;
+constexpr int kMarchRays = kMarchThreads / 64;        // rays per workgroup, one per wave
+constexpr int kMarchPoints = 64 * kMarchPPT;          // points per chunk
 
 // Workgroups per launch of a kernel whose grid can be large (the accumulation
 // over cells x tiles, the march over rays x chunks): a dispatch counts at most

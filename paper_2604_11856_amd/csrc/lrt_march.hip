@@ -74,8 +74,9 @@ __device__ __forceinline__ void load_row(const T *eta, const T *kap, int64_t row
 //     ds_M-1/2, and each segment uses the far node's kappa.
 // T_far (NULL: all free) gives per ray the temperature of a solid far
 // boundary (0: free), whose blackbody intensity starts the march.
-// The (ray, chunk) item of workgroup b (b: index in the whole grid, launch
-// offset b0 + blockIdx.x).  Workgroups go round-robin to the 8 XCDs (b % 8),
+// The (ray, chunk) of wave `wave` of workgroup b (b: index in the whole grid,
+// launch offset b0 + blockIdx.x): the workgroup owns (ray group, chunk), its
+// waves the group's rays.  Workgroups go round-robin to the 8 XCDs (b % 8),
 // each with its own L2: XCD x takes a contiguous range of the chunk-major
 // items, so every ray of a spectral chunk runs on one XCD and the rows the
 // rays share come from that XCD's L2.  When every wall point has the same
@@ -84,15 +85,20 @@ __device__ __forceinline__ void load_row(const T *eta, const T *kap, int64_t row
 // points, which cross nearly the same cells.  (Measured against ray-fastest
 // items with a contiguous ray range per XCD: 8.6 vs 11.2 ms on the 17 slab
 // rays of the stagnation line, 100.6 vs 107.5 ms on 8192 axisymmetric rays.)
-// A bijection of [0, n_rays n_chunks) for any sizes.
-__device__ __forceinline__ void march_item(uint32_t b, const DevRays &rays, int32_t n_chunks, int &ray, int &chunk)
+// A bijection onto [0, n_rays) x [0, n_chunks) for any sizes (ray = -1 for
+// the waves past the last ray).
+__device__ __forceinline__ void march_item(uint32_t b, int32_t wave, const DevRays &rays, int32_t n_chunks,
+                                           int &ray, int &chunk)
 {
-    const uint32_t n = (uint32_t)rays.n_rays * (uint32_t)n_chunks, x = b % kXCDs, i = b / kXCDs;
+    const uint32_t n_groups = ((uint32_t)rays.n_rays + kMarchRays - 1) / kMarchRays;
+    const uint32_t n = n_groups * (uint32_t)n_chunks, x = b % kXCDs, i = b / kXCDs;
     const uint32_t per = n / kXCDs, rem = n % kXCDs;
     const uint32_t gi = x * per + min(x, rem) + i;
-    chunk = (int)(gi / (uint32_t)rays.n_rays);
-    const int32_t q = (int32_t)(gi % (uint32_t)rays.n_rays);
-    if (rays.per_wall > 0) {
+    chunk = (int)(gi / n_groups);
+    const int32_t q = (int32_t)(gi % n_groups) * kMarchRays + wave;
+    if (q >= rays.n_rays) {
+        ray = -1;   // past the last ray: this wave has nothing to do
+    } else if (rays.per_wall > 0) {
         const int32_t n_wall = rays.n_rays / rays.per_wall;
         ray = (q % n_wall) * rays.per_wall + q / n_wall;   // direction-major
     } else {
@@ -106,9 +112,11 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
     const void *kappa_v, const int32_t *escale, const double *T_far, double *I_out,
     double *partials, int32_t n_chunks, int32_t aligned16, uint32_t b0)
 {
+    const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
     int ray, chunk;
-    march_item(b0 + blockIdx.x, rays, n_chunks, ray, chunk);
-    const int32_t kb = chunk * kMarchPoints + threadIdx.x * kMarchPPT;   // band-relative
+    march_item(b0 + blockIdx.x, wave, rays, n_chunks, ray, chunk);
+    if (ray < 0) return;
+    const int32_t kb = chunk * kMarchPoints + lane * kMarchPPT;   // band-relative
     const int64_t m0 = rays.off[ray], m1 = rays.off[ray + 1];
     double I[kMarchPPT];
     const double Tw = T_far ? T_far[ray] : 0.0;
@@ -216,16 +224,9 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
             if (I_out) I_out[(int64_t)ray * n_band + kl] = I[j];
         }
     }
-    // block sum in a fixed order: waves reduce by xor-shuffles, then wave 0
+    // the wave's sum in a fixed order (xor-shuffles)
     for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-    __shared__ double wsum[kMarchThreads / 64];
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < kMarchThreads / 64; ++w) s += wsum[w];
-        partials[(int64_t)ray * n_chunks + chunk] = s;
-    }
+    if (lane == 0) partials[(int64_t)ray * n_chunks + chunk] = part;
 }
 
 __global__ void reduce_rows_kernel(const double *p, int32_t n_rows, int32_t n_cols, double *out)
@@ -261,7 +262,7 @@ hipError_t launch_march(bool fp32, bool linear, const DevRays &rays, const DevGr
                         double *partials, int32_t n_chunks, hipStream_t st)
 {
     if (rays.n_rays == 0) return hipSuccess;
-    const int64_t n_blocks = (int64_t)rays.n_rays * n_chunks;
+    const int64_t n_blocks = ((int64_t)rays.n_rays + kMarchRays - 1) / kMarchRays * n_chunks;
     if (n_blocks > (int64_t)UINT32_MAX) return hipErrorInvalidConfiguration;
     const int32_t al = ((((uintptr_t)eta) | ((uintptr_t)kappa)) & 15) == 0;
     for (int64_t b0 = 0; b0 < n_blocks; b0 += kMaxLaunchBlocks) {

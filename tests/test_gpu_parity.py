@@ -347,8 +347,10 @@ def test_invalid_arguments(torch_dev):
 
 def test_stagnation_full_size_sampled(torch_dev):
     """400 cells, 2.2M lines (200k atomic + 2M rovibronic), 2^21 points, the
-    launch configuration the benchmark times: eta/kappa of every cell at 512
-    sampled grid points against the oracle evaluated point by point."""
+    whole-solve launch configuration of the stagnation line: eta/kappa of every
+    cell at 512 sampled grid points against the oracle evaluated point by
+    point, and the wall intensity of all 17 rays at those points against the
+    oracle's march through the oracle's coefficients."""
     torch = torch_dev
     wl = synth.stagnation_line()
     ks = synth.sample_points(wl.grid, wl.lines, 512, seed=5)
@@ -360,14 +362,23 @@ def test_stagnation_full_size_sampled(torch_dev):
     for c, k in zip(cc, kk):
         if int(k) in pos:
             m[c, pos[int(k)]] = True
+    rays, _, _ = O.slab_rays(wl.geometry)
+    I_ref = np.array([O.march(c, ds, e_ref, k_ref) for c, ds in rays])
+    mI = np.broadcast_to(m.any(axis=0), I_ref.shape)
     ctx = lrt.Context(0).load(wl)
     kt = torch.as_tensor(ks, device="cuda:0")
     for prec in PRECS:
         say("stagnation full prec", prec)
         eta, kap, esc = ctx.coeffs_torch(0, prec)
+        I = torch.zeros((len(rays), wl.grid.n_points), dtype=torch.float64, device="cuda:0")
+        Ii = torch.zeros(len(rays), dtype=torch.float64, device="cuda:0")
+        ctx.march(0, prec, eta, kap, esc if prec == lrt.LRT_FP32_COMP else None, I, Ii)
+        Is = I[:, kt].cpu().numpy()
         es, ksmp = eta[:, kt], kap[:, kt]
-        del eta, kap
+        del eta, kap, I
         torch.cuda.synchronize()
+        eI = normwise(Is, I_ref, mI, label="wall intensity, 17 rays")
+        assert eI <= TOL[prec]
         if prec == lrt.LRT_FP32_COMP:
             e, k = lrt.scaled_to_f64(es, ksmp, esc)
         else:
