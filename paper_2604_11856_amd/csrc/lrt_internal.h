@@ -45,15 +45,16 @@ constexpr int kStage = kAccumThreads;
 
 // March tile: one workgroup of 256 threads owns one (ray group, chunk) item:
 // each of its 4 waves marches one ray of the group over the chunk's
-// kMarchPoints = 256 consecutive points, 4 per lane.  The waves share no
-// state, so a group's rays may have different segment counts.  (One
-// workgroup per (ray, 1024-point chunk), 4 points per thread, took 4.8 %
-// longer on 131,072 rays: a 1024-point row of every cell is 8 KB, a 256-point
-// one 2 KB, so four times as many rows stay in L2 while a chunk's rays run.
-// One wave per (ray, 128-point chunk) took 1.2-2x longer: the per-segment
-// work is then spread over 128 points.)
+// kMarchPoints = 128 consecutive points, 2 per lane.  The waves share no
+// state, so a group's rays may have different segment counts.  Smaller
+// chunks keep more cell rows in L2 while a chunk's rays run (a row is
+// 8 B per point) at more per-segment work per point.  March time per step of
+// the large axisymmetric slice (131,072 rays, 16 x 1,024 points), by chunk
+// points / rays per workgroup: 1024 / 1 (4 points per lane): 826 ms;
+// 256 / 1: 794; 256 / 2: 794; 256 / 4: 712; 256 / 8: 717; 128 / 4: 641-651;
+// 128 / 8: 656; 64 / 4: 909; 64 / 8: 928.
 constexpr int kMarchThreads = 256;
-constexpr int kMarchPPT = 4;
+constexpr int kMarchPPT = 2;
 constexpr int kMarchRays = kMarchThreads / 64;        // rays per workgroup, one per wave
 constexpr int kMarchPoints = 64 * kMarchPPT;          // points per chunk
 

@@ -42,19 +42,22 @@ __device__ __forceinline__ void linear_j_weights_f64(double t, double &e, double
     wf = b;
 }
 
-// One row (the kMarchPPT = 4 consecutive points of a thread) of eta and kappa.
+// One row (the kMarchPPT consecutive points of a lane) of eta and kappa.
 template <typename T>
 __device__ __forceinline__ void load_row(const T *eta, const T *kap, int64_t row, int32_t kb,
                                          int32_t n_band, bool vec, T (&ev)[kMarchPPT],
                                          T (&kv)[kMarchPPT])
 {
-    static_assert(kMarchPPT == 4, "one float4 per array and thread");
     if constexpr (sizeof(T) == 4) {
-        if (vec) {
-            const float4 a = *(const float4 *)(eta + row);
-            const float4 b = *(const float4 *)(kap + row);
-            ev[0] = a.x; ev[1] = a.y; ev[2] = a.z; ev[3] = a.w;
-            kv[0] = b.x; kv[1] = b.y; kv[2] = b.z; kv[3] = b.w;
+        if (vec) {   // one vector load per array and lane
+            typedef float VecF __attribute__((ext_vector_type(kMarchPPT)));
+            const VecF a = *(const VecF *)(eta + row);
+            const VecF b = *(const VecF *)(kap + row);
+#pragma unroll
+            for (int j = 0; j < kMarchPPT; ++j) {
+                ev[j] = a[j];
+                kv[j] = b[j];
+            }
             return;
         }
     }
