@@ -444,8 +444,10 @@ lrt_status lrt_coeffs(lrt_ctx *ctx, int64_t band, lrt_precision prec, void *eta,
  * tau = kappa ds, F(t) = (1 - e^-t)/t, F(0) = 1.  I_out (device, [n_rays][band_len] doubles) receives the wall
  * intensity, or pass NULL; I_int_out (device, [n_rays] doubles) receives the
  * band's trapezoid sum with global-index weights (h/2 at grid ends, h inside).
- * The rays over 4 times the band's 128-point chunks must stay below 2^32
- * (LRT_E_DEVICE otherwise).
+ * The march works on chunks of 128 grid points when the rays cross each
+ * cell at least 128 times on average (segments / cells), else of 256; the
+ * rays over 4 times the band's chunks must stay below 2^32 (LRT_E_DEVICE
+ * otherwise).
  * Stream-ordered.  Errors: LRT_E_STATE (no rays, cells/rays mismatch),
  * LRT_E_ARG. */
 lrt_status lrt_march(lrt_ctx *ctx, int64_t band, lrt_precision prec, const void *eta,
@@ -460,7 +462,7 @@ lrt_status lrt_march(lrt_ctx *ctx, int64_t band, lrt_precision prec, const void 
  * until the process ends) instead of a workspace the context allocates; no
  * launch is profiled.  Calls that overlap on one device share that array and
  * race.  Errors: as lrt_march, and LRT_E_ARG when the rays times the band's
- * 128-point chunks exceed 2^23. */
+ * chunks (as lrt_march describes) exceed 2^23. */
 lrt_status lrt_march_noalloc(lrt_ctx *ctx, int64_t band, lrt_precision prec, const void *eta,
                              const void *kappa, const int32_t *escale, double *I_out, double *I_int_out,
                              void *stream);

@@ -959,12 +959,13 @@ lrt_status march_range(lrt_ctx *c, int32_t k_first, int32_t n_band, lrt_precisio
     if (c->rays_cells != c->n_cells)
         return fail(c, LRT_E_STATE, "rays expect %lld cells, %lld set", (long long)c->rays_cells, (long long)c->n_cells);
     lrt_status r;
-    const int32_t n_chunks = (n_band + kMarchPoints - 1) / kMarchPoints;
+    const int32_t ppt = march_points_per_lane(c->h_off.back(), c->n_cells), chunk_points = 64 * ppt;
+    const int32_t n_chunks = (n_band + chunk_points - 1) / chunk_points;
     const int64_t need = c->n_rays * (int64_t)n_chunks;
     if (partials) {
         if (need > cap)
             return fail(c, LRT_E_ARG, "the march needs %lld partial sums (rays x %d-point chunks), the buffer holds %lld",
-                        (long long)need, kMarchPoints, (long long)cap);
+                        (long long)need, chunk_points, (long long)cap);
     } else {
         if ((r = ensure(c, c->w_partials, (size_t)need * sizeof(double)))) return r;
     }
@@ -980,7 +981,7 @@ lrt_status march_range(lrt_ctx *c, int32_t k_first, int32_t n_band, lrt_precisio
     }
     const DevGrid g = dev_grid(c);
     auto go = [&] {
-        return launch_march(prec == LRT_FP32_COMP, c->march_scheme == LRT_MARCH_LINEAR_J, rays, g, k_first, n_band,
+        return launch_march(prec == LRT_FP32_COMP, c->march_scheme == LRT_MARCH_LINEAR_J, ppt, rays, g, k_first, n_band,
                             eta, kappa, escale, c->have_Tfar ? c->d_Tfar.as<double>() : nullptr, I_out, part,
                             n_chunks, st);
     };

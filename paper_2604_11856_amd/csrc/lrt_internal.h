@@ -43,20 +43,27 @@ constexpr int kTilePoints = kAccumThreads * kPPL;
 // Line records staged in LDS per round: one per thread.
 constexpr int kStage = kAccumThreads;
 
-// March tile: one workgroup of 256 threads owns one (ray group, chunk) item:
-// each of its 4 waves marches one ray of the group over the chunk's
-// kMarchPoints = 128 consecutive points, 2 per lane.  The waves share no
-// state, so a group's rays may have different segment counts.  Smaller
-// chunks keep more cell rows in L2 while a chunk's rays run (a row is
-// 8 B per point) at more per-segment work per point.  March time per step of
-// the large axisymmetric slice (131,072 rays, 16 x 1,024 points), by chunk
-// points / rays per workgroup: 1024 / 1 (4 points per lane): 826 ms;
-// 256 / 1: 794; 256 / 2: 794; 256 / 4: 712; 256 / 8: 717; 128 / 4: 641-651;
-// 128 / 8: 656; 64 / 4: 909; 64 / 8: 928.
+// March tile: one workgroup of 4 waves; each wave marches one ray over one
+// chunk of 64 x PPT consecutive points, PPT per lane, and the waves share no
+// state.  Smaller chunks keep more cell rows in L2 while a chunk's rays run
+// (a row is 8 B per point), at more per-segment work per point, so the tile
+// follows how often the rays cross a cell: from kMarchReuseNarrow segments per
+// cell on, 128-point chunks (PPT 2) and 4 rays per workgroup; below, 256-point
+// chunks (PPT 4) and 4 consecutive chunks of one ray per workgroup.  March time per step of the large
+// axisymmetric slice (131,072 rays, 391 segments per cell), by chunk points /
+// rays per workgroup: 1024 / 1 (4 points per lane): 826 ms; 256 / 1: 794;
+// 256 / 2: 794; 256 / 4: 712; 256 / 8: 717; 128 / 4: 641-651; 128 / 8: 656;
+// 64 / 4: 909; 64 / 8: 928.  On the 256 x 128-cell case (8,192 rays, few
+// segments per cell), per band: 128 / 4: 97 ms; 256 / 4: 88 ms; 256-point
+// chunks, 4 of one ray per workgroup: 84 ms.
 constexpr int kMarchThreads = 256;
-constexpr int kMarchPPT = 2;
-constexpr int kMarchRays = kMarchThreads / 64;        // rays per workgroup, one per wave
-constexpr int kMarchPoints = 64 * kMarchPPT;          // points per chunk
+constexpr int64_t kMarchReuseNarrow = 128;
+
+// Points per lane of the march for a ray set with n_seg segments over n_cells cells.
+inline int32_t march_points_per_lane(int64_t n_seg, int64_t n_cells)
+{
+    return n_seg >= kMarchReuseNarrow * n_cells ? 2 : 4;
+}
 
 // Workgroups per launch of a kernel whose grid can be large (the accumulation
 // over cells x tiles, the march over rays x chunks): a dispatch counts at most
@@ -295,7 +302,7 @@ hipError_t launch_count(const DevLines &L, const DevGrid &g, const CellConst *cc
                         int32_t n_species, int32_t k_first, int32_t n_band,
                         unsigned long long *count, hipStream_t st);
 
-hipError_t launch_march(bool fp32, bool linear, const DevRays &rays, const DevGrid &g,
+hipError_t launch_march(bool fp32, bool linear, int32_t ppt, const DevRays &rays, const DevGrid &g,
                         int32_t k_first, int32_t n_band, const void *eta, const void *kappa,
                         const int32_t *escale, const double *T_far, double *I_out,
                         double *partials, int32_t n_chunks, hipStream_t st);

@@ -42,19 +42,18 @@ __device__ __forceinline__ void linear_j_weights_f64(double t, double &e, double
     wf = b;
 }
 
-// One row (the kMarchPPT consecutive points of a lane) of eta and kappa.
-template <typename T>
+// One row (the PPT consecutive points of a lane) of eta and kappa.
+template <int PPT, typename T>
 __device__ __forceinline__ void load_row(const T *eta, const T *kap, int64_t row, int32_t kb,
-                                         int32_t n_band, bool vec, T (&ev)[kMarchPPT],
-                                         T (&kv)[kMarchPPT])
+                                         int32_t n_band, bool vec, T (&ev)[PPT], T (&kv)[PPT])
 {
     if constexpr (sizeof(T) == 4) {
         if (vec) {   // one vector load per array and lane
-            typedef float VecF __attribute__((ext_vector_type(kMarchPPT)));
+            typedef float VecF __attribute__((ext_vector_type(PPT)));
             const VecF a = *(const VecF *)(eta + row);
             const VecF b = *(const VecF *)(kap + row);
 #pragma unroll
-            for (int j = 0; j < kMarchPPT; ++j) {
+            for (int j = 0; j < PPT; ++j) {
                 ev[j] = a[j];
                 kv[j] = b[j];
             }
@@ -62,14 +61,14 @@ __device__ __forceinline__ void load_row(const T *eta, const T *kap, int64_t row
         }
     }
 #pragma unroll
-    for (int j = 0; j < kMarchPPT; ++j) {
+    for (int j = 0; j < PPT; ++j) {
         const bool ok = kb + j < n_band;
         ev[j] = ok ? eta[row + j] : (T)0;
         kv[j] = ok ? kap[row + j] : (T)0;
     }
 }
 
-// March of one (ray, chunk of kMarchPoints points), far -> target.
+// March of one (ray, chunk of 64 x PPT points), far -> target.
 //   LINEAR = false: cell-constant segments, I <- I e^-tau + eta ds F(tau).
 //   LINEAR = true: linear-j segments between LOS nodes at the far end of the
 //     ray, the midpoint of every cell segment and the target; a node takes its
@@ -78,29 +77,32 @@ __device__ __forceinline__ void load_row(const T *eta, const T *kap, int64_t row
 // T_far (NULL: all free) gives per ray the temperature of a solid far
 // boundary (0: free), whose blackbody intensity starts the march.
 // The (ray, chunk) of wave `wave` of workgroup b (b: index in the whole grid,
-// launch offset b0 + blockIdx.x): the workgroup owns (ray group, chunk), its
-// waves the group's rays.  Workgroups go round-robin to the 8 XCDs (b % 8),
-// each with its own L2: XCD x takes a contiguous range of the chunk-major
-// items, so every ray of a spectral chunk runs on one XCD and the rows the
-// rays share come from that XCD's L2.  When every wall point has the same
-// rays (per_wall > 0) a chunk's rays are taken direction-major: the rays an
-// XCD runs together are then nearly parallel lines from neighbouring wall
-// points, which cross nearly the same cells.  (Measured against ray-fastest
-// items with a contiguous ray range per XCD: 8.6 vs 11.2 ms on the 17 slab
-// rays of the stagnation line, 100.6 vs 107.5 ms on 8192 axisymmetric rays.)
-// A bijection onto [0, n_rays) x [0, n_chunks) for any sizes (ray = -1 for
-// the waves past the last ray).
+// launch offset b0 + blockIdx.x): the workgroup owns RAYS rays x (4 / RAYS)
+// consecutive chunks, one (ray, chunk) per wave.  Workgroups go round-robin to
+// the 8 XCDs (b % 8), each with its own L2: XCD x takes a contiguous range of
+// the chunk-major items, so every ray of a spectral chunk runs on one XCD and
+// the rows the rays share come from that XCD's L2.  When every wall point has
+// the same rays (per_wall > 0) a chunk's rays are taken direction-major: the
+// rays an XCD runs together are then nearly parallel lines from neighbouring
+// wall points, which cross nearly the same cells.  (Measured against
+// ray-fastest items with a contiguous ray range per XCD: 8.6 vs 11.2 ms on the
+// 17 slab rays of the stagnation line, 100.6 vs 107.5 ms on 8192 axisymmetric
+// rays.)  A bijection onto [0, n_rays) x [0, n_chunks) for any sizes (ray = -1
+// for the waves past the last ray or chunk).
+template <int RAYS>
 __device__ __forceinline__ void march_item(uint32_t b, int32_t wave, const DevRays &rays, int32_t n_chunks,
                                            int &ray, int &chunk)
 {
-    const uint32_t n_groups = ((uint32_t)rays.n_rays + kMarchRays - 1) / kMarchRays;
-    const uint32_t n = n_groups * (uint32_t)n_chunks, x = b % kXCDs, i = b / kXCDs;
+    constexpr int CHUNKS = kMarchThreads / 64 / RAYS;
+    const uint32_t n_groups = ((uint32_t)rays.n_rays + RAYS - 1) / RAYS;
+    const uint32_t n_cgroups = ((uint32_t)n_chunks + CHUNKS - 1) / CHUNKS;
+    const uint32_t n = n_groups * n_cgroups, x = b % kXCDs, i = b / kXCDs;
     const uint32_t per = n / kXCDs, rem = n % kXCDs;
     const uint32_t gi = x * per + min(x, rem) + i;
-    chunk = (int)(gi / n_groups);
-    const int32_t q = (int32_t)(gi % n_groups) * kMarchRays + wave;
-    if (q >= rays.n_rays) {
-        ray = -1;   // past the last ray: this wave has nothing to do
+    chunk = (int)(gi / n_groups) * CHUNKS + wave / RAYS;
+    const int32_t q = (int32_t)(gi % n_groups) * RAYS + wave % RAYS;
+    if (q >= rays.n_rays || chunk >= n_chunks) {
+        ray = -1;   // past the last ray or chunk: this wave has nothing to do
     } else if (rays.per_wall > 0) {
         const int32_t n_wall = rays.n_rays / rays.per_wall;
         ray = (q % n_wall) * rays.per_wall + q / n_wall;   // direction-major
@@ -109,7 +111,7 @@ __device__ __forceinline__ void march_item(uint32_t b, int32_t wave, const DevRa
     }
 }
 
-template <bool FP32, bool LINEAR>
+template <bool FP32, bool LINEAR, int PPT, int RAYS>
 __global__ __launch_bounds__(kMarchThreads) void march_kernel(
     DevRays rays, DevGrid g, int32_t k_first, int32_t n_band, const void *eta_v,
     const void *kappa_v, const int32_t *escale, const double *T_far, double *I_out,
@@ -117,21 +119,21 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
 {
     const int lane = threadIdx.x & 63, wave = uniform_i(threadIdx.x >> 6);
     int ray, chunk;
-    march_item(b0 + blockIdx.x, wave, rays, n_chunks, ray, chunk);
+    march_item<RAYS>(b0 + blockIdx.x, wave, rays, n_chunks, ray, chunk);
     if (ray < 0) return;
-    const int32_t kb = chunk * kMarchPoints + lane * kMarchPPT;   // band-relative
+    const int32_t kb = chunk * (64 * PPT) + lane * PPT;   // band-relative
     const int64_t m0 = rays.off[ray], m1 = rays.off[ray + 1];
-    double I[kMarchPPT];
+    double I[PPT];
     const double Tw = T_far ? T_far[ray] : 0.0;
 #pragma unroll
-    for (int j = 0; j < kMarchPPT; ++j) {
+    for (int j = 0; j < PPT; ++j) {
         I[j] = 0.0;
         if (Tw > 0.0 && kb + j < n_band) I[j] = planck_f64(g.nu_min + (double)(k_first + kb + j) * g.h, Tw);
     }
-    // vector loads only when every row start is aligned to kMarchPPT floats
-    // (16-byte aligned bases, n_band a multiple of kMarchPPT) and the
+    // vector loads only when every row start is aligned to PPT floats
+    // (16-byte aligned bases, n_band a multiple of PPT) and the
     // thread's points are all inside the band
-    const bool vec = aligned16 && (kb + kMarchPPT <= n_band) && (n_band % kMarchPPT) == 0;
+    const bool vec = aligned16 && (kb + PPT <= n_band) && (n_band % PPT) == 0;
     using T = std::conditional_t<FP32, float, double>;
     const T *eta = (const T *)eta_v;
     const T *kap = (const T *)kappa_v;
@@ -141,20 +143,20 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
             const int32_t c = rays.cell[m];
             const double ds = rays.ds[m];
             const int64_t row = (int64_t)c * n_band + kb;
-            T ev[kMarchPPT], kv[kMarchPPT];
-            load_row<T>(eta, kap, row, kb, n_band, vec, ev, kv);
+            T ev[PPT], kv[PPT];
+            load_row<PPT, T>(eta, kap, row, kb, n_band, vec, ev, kv);
             if constexpr (FP32) {
                 const double dse = ldexp(ds, escale[2 * c + 0]);
                 const float dsk = (float)fmin(ldexp(ds, escale[2 * c + 1]), 3.0e38);
 #pragma unroll
-                for (int j = 0; j < kMarchPPT; ++j) {
+                for (int j = 0; j < PPT; ++j) {
                     double at, em;
                     segment_f32(ev[j], kv[j], dsk, dse, at, em);
                     I[j] = fma(I[j], at, em);
                 }
             } else {
 #pragma unroll
-                for (int j = 0; j < kMarchPPT; ++j) {
+                for (int j = 0; j < PPT; ++j) {
                     if (kb + j < n_band) {
                         const double tau = kv[j] * ds;
                         const double em = expm1(-tau);
@@ -166,17 +168,17 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
         }
     } else {
         // previous node (the far node of the next segment)
-        T pe[kMarchPPT], pk[kMarchPPT];
+        T pe[PPT], pk[PPT];
         int32_t pee = 0, pek = 0;
         double pds = 0.0;
         // one linear-j segment of length L from node (fe, fk) to node (ne_)
-        auto segment = [&](const T (&fe)[kMarchPPT], const T (&fk)[kMarchPPT], int32_t fee,
-                           int32_t fek, const T (&ne_)[kMarchPPT], int32_t nee, double L) {
+        auto segment = [&](const T (&fe)[PPT], const T (&fk)[PPT], int32_t fee,
+                           int32_t fek, const T (&ne_)[PPT], int32_t nee, double L) {
             if constexpr (FP32) {
                 const double Lf = ldexp(L, fee), Ln = ldexp(L, nee);
                 const float Lk = (float)fmin(ldexp(L, fek), 3.0e38);
 #pragma unroll
-                for (int j = 0; j < kMarchPPT; ++j) {
+                for (int j = 0; j < PPT; ++j) {
                     const float t = fk[j] * Lk;
                     const float e = __builtin_amdgcn_exp2f(t * (float)(-kLog2e));
                     float wf, wn;
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
                 }
             } else {
 #pragma unroll
-                for (int j = 0; j < kMarchPPT; ++j) {
+                for (int j = 0; j < PPT; ++j) {
                     if (kb + j < n_band) {
                         double e, wf, wn;
                         linear_j_weights_f64(fk[j] * L, e, wf, wn);
@@ -197,15 +199,15 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
         for (int64_t m = m0; m < m1; ++m) {
             const int32_t c = rays.cell[m];
             const double ds = rays.ds[m];
-            T ev[kMarchPPT], kv[kMarchPPT];
-            load_row<T>(eta, kap, (int64_t)c * n_band + kb, kb, n_band, vec, ev, kv);
+            T ev[PPT], kv[PPT];
+            load_row<PPT, T>(eta, kap, (int64_t)c * n_band + kb, kb, n_band, vec, ev, kv);
             const int32_t ee = FP32 ? escale[2 * c + 0] : 0, ek = FP32 ? escale[2 * c + 1] : 0;
             if (m == m0)
                 segment(ev, kv, ee, ek, ev, ee, 0.5 * ds);             // far end -> first midpoint
             else
                 segment(pe, pk, pee, pek, ev, ee, 0.5 * (pds + ds));   // midpoint -> midpoint
 #pragma unroll
-            for (int j = 0; j < kMarchPPT; ++j) {
+            for (int j = 0; j < PPT; ++j) {
                 pe[j] = ev[j];
                 pk[j] = kv[j];
             }
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
     // outputs: I and the trapezoid partial with global-index weights
     double part = 0.0;
 #pragma unroll
-    for (int j = 0; j < kMarchPPT; ++j) {
+    for (int j = 0; j < PPT; ++j) {
         const int32_t kl = kb + j;
         if (kl < n_band) {
             const int32_t kg = k_first + kl;
@@ -259,25 +261,32 @@ __global__ void add_kernel(double *acc, const double *x, int32_t n)
 
 }  // namespace
 
-hipError_t launch_march(bool fp32, bool linear, const DevRays &rays, const DevGrid &g,
+hipError_t launch_march(bool fp32, bool linear, int32_t ppt, const DevRays &rays, const DevGrid &g,
                         int32_t k_first, int32_t n_band, const void *eta, const void *kappa,
                         const int32_t *escale, const double *T_far, double *I_out,
                         double *partials, int32_t n_chunks, hipStream_t st)
 {
     if (rays.n_rays == 0) return hipSuccess;
-    const int64_t n_blocks = ((int64_t)rays.n_rays + kMarchRays - 1) / kMarchRays * n_chunks;
+    if (ppt != 2 && ppt != 4) return hipErrorInvalidValue;
+    // 128-point chunks: 4 rays per workgroup; 256-point chunks: 4 chunks of one ray
+    const int64_t waves = kMarchThreads / 64, n_rays = rays.n_rays;
+    const int64_t n_blocks = ppt == 2 ? (n_rays + waves - 1) / waves * n_chunks
+                                      : n_rays * ((n_chunks + waves - 1) / waves);
     if (n_blocks > (int64_t)UINT32_MAX) return hipErrorInvalidConfiguration;
     const int32_t al = ((((uintptr_t)eta) | ((uintptr_t)kappa)) & 15) == 0;
     for (int64_t b0 = 0; b0 < n_blocks; b0 += kMaxLaunchBlocks) {
         const dim3 grid((unsigned)std::min(kMaxLaunchBlocks, n_blocks - b0));
-#define LRT_MARCH(F, LIN)                                                                          \
-    hipLaunchKernelGGL((march_kernel<F, LIN>), grid, dim3(kMarchThreads), 0, st, rays, g, k_first, \
+#define LRT_MARCH(F, LIN, P, R)                                                                          \
+    hipLaunchKernelGGL((march_kernel<F, LIN, P, R>), grid, dim3(kMarchThreads), 0, st, rays, g, k_first, \
                        n_band, eta, kappa, escale, T_far, I_out, partials, n_chunks, al, (uint32_t)b0)
+#define LRT_MARCH_P(F, LIN) \
+    if (ppt == 2) LRT_MARCH(F, LIN, 2, 4); else LRT_MARCH(F, LIN, 4, 1)
         if (fp32) {
-            if (linear) LRT_MARCH(true, true); else LRT_MARCH(true, false);
+            if (linear) LRT_MARCH_P(true, true); else LRT_MARCH_P(true, false);
         } else {
-            if (linear) LRT_MARCH(false, true); else LRT_MARCH(false, false);
+            if (linear) LRT_MARCH_P(false, true); else LRT_MARCH_P(false, false);
         }
+#undef LRT_MARCH_P
 #undef LRT_MARCH
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -19,7 +19,7 @@ namespace lrt {
 
 namespace {
 
-// 2^23 doubles (64 MiB): rays x 128-point chunks of one band at most.
+// 2^23 doubles (64 MiB): rays x march chunks of one band at most.
 constexpr int64_t kScratchDoubles = int64_t(1) << 23;
 constexpr int kMaxDevices = 64;
 

@@ -54,7 +54,7 @@ def test_noalloc_march_matches_march(torch_dev):
 
 
 def test_noalloc_rejects_oversize(torch_dev):
-    """Rays x 128-point chunks above 2^23: a clear error, nothing launched."""
+    """Rays x march chunks above 2^23: a clear error, nothing launched."""
     torch = torch_dev
     wl = synth.stagnation_line(n_cells=1, n_atomic=10, n_rovib=0, n_points=(1 << 19) + 7, band_points=1 << 19,
                                n_mu=16400, seed=33)
