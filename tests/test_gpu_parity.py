@@ -129,6 +129,45 @@ def test_slab_solve_bands(band_points, torch_dev):
     ctx.close()
 
 
+def test_slab_many_rays_ray_groups(torch_dev):
+    """131 slab rays over 8 cells: the rays cross each cell 131 times, so the
+    march takes 4 rays per workgroup on 128-point chunks, with the last group
+    one ray short; ragged bands and a ragged grid end.  Every ray's band
+    integral and the flux against the oracle, and the ray intensities of one
+    band against lrt_march per ray."""
+    wl = synth.slab_equilibrium(n_cells=8, n_lines_per_species=60, n_points=3001, band_points=1000,
+                                n_mu=130, seed=31)
+    ref = O.solve_slab(wl)
+    ctx = lrt.Context(0).load(wl)
+    sz = ctx.sizes()
+    assert sz["n_rays"] == 131
+    for prec in PRECS:
+        q, I_int, _ = ctx.solve(prec)
+        eI = np.max(np.abs(I_int - ref["I_int"]) / np.abs(ref["I_int"]))
+        eq = abs(q[0] - ref["q"]) / abs(ref["q"])
+        say("  131 rays prec %d: I_int %.3e q %.3e" % (prec, eI, eq))
+        assert eI <= TOL[prec] and eq <= TOL[prec]
+    # the last band (1 point) and the first: every ray's intensity against the
+    # oracle's march through the oracle's coefficients
+    torch = torch_dev
+    for band in (0, sz["n_bands"] - 1):
+        n = ctx.band_len(band)
+        ks = np.arange(band * sz["band_points"], band * sz["band_points"] + n)
+        e_ref, k_ref, _ = O.coeffs(wl.species, wl.lines, wl.cells, wl.grid, ks)
+        rays, _, _ = O.slab_rays(wl.geometry)
+        I_ref = np.array([O.march(c, ds, e_ref, k_ref) for c, ds in rays])
+        mI = np.broadcast_to(edge_mask(wl, int(ks[0]), n).any(axis=0), I_ref.shape)
+        for prec in PRECS:
+            eta, kap, esc = ctx.coeffs_torch(band, prec)
+            I = torch.zeros((sz["n_rays"], n), dtype=torch.float64, device="cuda:0")
+            Ii = torch.zeros(sz["n_rays"], dtype=torch.float64, device="cuda:0")
+            ctx.march(band, prec, eta, kap, esc, I, Ii)
+            torch.cuda.synchronize()
+            eI = normwise(I.cpu().numpy(), I_ref, mI, label="band %d prec %d, 131 rays" % (band, prec))
+            assert eI <= TOL[prec]
+    ctx.close()
+
+
 def test_stagnation_small(torch_dev):
     """Two-temperature stagnation-line shape with atomic and rovibronic lines,
     several ragged bands."""
