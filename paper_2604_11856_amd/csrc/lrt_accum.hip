@@ -1147,14 +1147,15 @@ void serve_kernel(DevLines L, DevGrid g, const ServeReq *reqs, const ServeItem *
             }
             const double ds = R.ds[c];
             if (!linear) {
-                const double dse = ldexp(ds, ese);
-                const float dsk = (float)fmin(ldexp(ds, esk), 3.0e38);
+                float dsu;
+                double dsl;
+                segment_scales(ds, ese, esk, dsu, dsl);
 #pragma unroll
                 for (int j = 0; j < kPPL; ++j) {
                     int32_t loc = kw + 64 * j + lane;
                     asm volatile("" : "+v"(loc));
                     double at, em;
-                    segment_f32(e[j], kp[j], dsk, dse, at, em);
+                    segment_f32(e[j], kp[j], dsu, dsl, at, em);
                     ts[loc] *= at;
                     ts[kTilePoints + loc] = fma(ts[kTilePoints + loc], at, em);
                 }

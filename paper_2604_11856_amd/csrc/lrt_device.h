@@ -10,6 +10,7 @@
 namespace lrt {
 
 constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
 // XCDs of the chip: workgroup ids go round-robin over them, each has its own L2.
 constexpr int kXCDs = 8;
 
@@ -23,28 +24,43 @@ static __device__ __forceinline__ double planck_f64(double nu, double T)
     return 1e-7 * 2.0 * kPlanck * kLight * kLight * nu * nu * nu / expm1(kC2 * nu / T);
 }
 
-// F(t) = (1 - e^-t)/t from e = e^-t; Taylor for |t| < 0.1 avoids the
-// cancellation in 1 - e (relative error of the direct form ~ 6e-8 / |t|).
-static __device__ __forceinline__ float fexp_f32(float t, float e)
+// F(t) = (1 - e^-t)/t of a segment, evaluated as H = F ln2 in u = t log2(e)
+// (so e^-t = 2^-u is one hardware exponential, and the caller's emission
+// factor carries the 1/ln2): the direct form (1 - e)/u, or for |t| < 0.1,
+// where 1 - e cancels (relative error ~6e-8/|t|), the Taylor series
+// F = sum_n (-t)^n/(n+1)! through t^4 (first omitted term below 1.4e-8
+// relative) rewritten in u: H = sum_n (-1)^n ln2^(n+1) u^n/(n+1)!.
+static __device__ __forceinline__ float fexp_u_f32(float u, float e)
 {
-    const float poly = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, -1.0f / 720.0f, 1.0f / 120.0f),
-                                                   -1.0f / 24.0f), 1.0f / 6.0f), -0.5f), 1.0f);
-    const float direct = (1.0f - e) * __builtin_amdgcn_rcpf(t);
-    return fabsf(t) < 0.1f ? poly : direct;
+    constexpr double l = kLn2, l2 = l * l, l3 = l2 * l;
+    const float poly = fmaf(u, fmaf(u, fmaf(u, fmaf(u, (float)(l3 * l2 / 120.0), (float)(-l2 * l2 / 24.0)),
+                                            (float)(l3 / 6.0)), (float)(-l2 / 2.0)), (float)l);
+    const float direct = (1.0f - e) * __builtin_amdgcn_rcpf(u);
+    return fabsf(u) < (float)(0.1 * kLog2e) ? poly : direct;
 }
 
 // One cell-constant segment on scaled single-precision coefficients:
 // tau = kappa ds; returns e^-tau (as the attenuation factor) and the emitted
-// term eta ds F(tau) in double precision.  dsk = ds 2^esk (as float),
-// dse = ds 2^ese.
-static __device__ __forceinline__ void segment_f32(float eta_s, float kap_s, float dsk, double dse,
+// term eta ds F(tau) in double precision.  dsu = ds log2(e) 2^esk (as float,
+// so u = kappa dsu = tau log2(e)), dsl = ds log2(e) 2^ese.
+static __device__ __forceinline__ void segment_f32(float eta_s, float kap_s, float dsu, double dsl,
                                             double &atten, double &emit)
 {
-    const float tau = kap_s * dsk;
-    const float e = __builtin_amdgcn_exp2f(tau * (float)(-kLog2e));
-    const float F = fexp_f32(tau, e);
+    const float u = kap_s * dsu;
+    const float e = __builtin_amdgcn_exp2f(-u);
+    const float H = fexp_u_f32(u, e);
     atten = (double)e;
-    emit = (double)(eta_s * F) * dse;
+    emit = (double)(eta_s * H) * dsl;
+}
+
+// The per-segment factors of segment_f32 from ds and the cell's scales (dsu
+// clamped below float overflow, so that kappa = 0 gives u = 0).
+static __device__ __forceinline__ void segment_scales(double ds, int32_t ese, int32_t esk, float &dsu,
+                                               double &dsl)
+{
+    const double d = ds * kLog2e;
+    dsu = (float)fmin(ldexp(d, esk), 3.0e38);
+    dsl = ldexp(d, ese);
 }
 
 // Weights per unit length of the two nodes of a linear-j segment (Sec. 2.2.3:

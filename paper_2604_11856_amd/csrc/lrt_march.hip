@@ -42,16 +42,18 @@ __device__ __forceinline__ void linear_j_weights_f64(double t, double &e, double
     wf = b;
 }
 
-// One row (the PPT consecutive points of a lane) of eta and kappa.
+// One row (the PPT consecutive points kb.. of a lane) of eta and kappa, from
+// the row bases of the segment's cell (the same for the whole wave, so the
+// loads take a scalar base and the lane's 32-bit byte offset ob = kb sizeof(T)).
 template <int PPT, typename T>
-__device__ __forceinline__ void load_row(const T *eta, const T *kap, int64_t row, int32_t kb,
-                                         int32_t n_band, bool vec, T (&ev)[PPT], T (&kv)[PPT])
+__device__ __forceinline__ void load_row(const T *erow, const T *krow, uint32_t kb, uint32_t ob, int32_t n_band,
+                                         bool vec, T (&ev)[PPT], T (&kv)[PPT])
 {
     if constexpr (sizeof(T) == 4) {
         if (vec) {   // one vector load per array and lane
             typedef float VecF __attribute__((ext_vector_type(PPT)));
-            const VecF a = *(const VecF *)(eta + row);
-            const VecF b = *(const VecF *)(kap + row);
+            const VecF a = *(const VecF *)((const char *)erow + ob);
+            const VecF b = *(const VecF *)((const char *)krow + ob);
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
                 ev[j] = a[j];
@@ -62,9 +64,9 @@ __device__ __forceinline__ void load_row(const T *eta, const T *kap, int64_t row
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const bool ok = kb + j < n_band;
-        ev[j] = ok ? eta[row + j] : (T)0;
-        kv[j] = ok ? kap[row + j] : (T)0;
+        const bool ok = (int32_t)kb + j < n_band;
+        ev[j] = ok ? erow[kb + j] : (T)0;
+        kv[j] = ok ? krow[kb + j] : (T)0;
     }
 }
 
@@ -131,41 +133,54 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
         if (Tw > 0.0 && kb + j < n_band) I[j] = planck_f64(g.nu_min + (double)(k_first + kb + j) * g.h, Tw);
     }
     // vector loads only when every row start is aligned to PPT floats
-    // (16-byte aligned bases, n_band a multiple of PPT) and the
-    // thread's points are all inside the band
-    const bool vec = aligned16 && (kb + PPT <= n_band) && (n_band % PPT) == 0;
+    // (16-byte aligned bases, n_band a multiple of PPT) and the wave's
+    // points are all inside the band (a wave-uniform choice)
+    const bool vec = aligned16 && (int64_t)(chunk + 1) * (64 * PPT) <= n_band && (n_band % PPT) == 0;
     using T = std::conditional_t<FP32, float, double>;
     const T *eta = (const T *)eta_v;
     const T *kap = (const T *)kappa_v;
+    const uint32_t ob = (uint32_t)kb * (uint32_t)sizeof(T);   // byte offset of the lane's points in a row
 
     if constexpr (!LINEAR) {
-        for (int64_t m = m0; m < m1; ++m) {
-            const int32_t c = rays.cell[m];
-            const double ds = rays.ds[m];
-            const int64_t row = (int64_t)c * n_band + kb;
-            T ev[PPT], kv[PPT];
-            load_row<PPT, T>(eta, kap, row, kb, n_band, vec, ev, kv);
-            if constexpr (FP32) {
-                const double dse = ldexp(ds, escale[2 * c + 0]);
-                const float dsk = (float)fmin(ldexp(ds, escale[2 * c + 1]), 3.0e38);
+        // the segment loop, with vector or guarded row loads chosen once
+        // outside it; a 32-bit trip count keeps the loop test on the scalar unit
+        const int32_t *cell_m = rays.cell + m0;
+        const double *ds_m = rays.ds + m0;
+        const int32_t n_seg = (int32_t)(m1 - m0);
+        auto cell_march = [&](auto vec_c) {
+            for (int32_t i = 0; i < n_seg; ++i) {
+                const int32_t c = cell_m[i];
+                const double ds = ds_m[i];
+                const int64_t row = (int64_t)c * n_band;
+                T ev[PPT], kv[PPT];
+                load_row<PPT, T>(eta + row, kap + row, (uint32_t)kb, ob, n_band, decltype(vec_c)::value, ev, kv);
+                if constexpr (FP32) {
+                    float dsu;
+                    double dsl;
+                    segment_scales(ds, escale[2 * c + 0], escale[2 * c + 1], dsu, dsl);
 #pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    double at, em;
-                    segment_f32(ev[j], kv[j], dsk, dse, at, em);
-                    I[j] = fma(I[j], at, em);
-                }
-            } else {
+                    for (int j = 0; j < PPT; ++j) {
+                        double at, em;
+                        segment_f32(ev[j], kv[j], dsu, dsl, at, em);
+                        I[j] = fma(I[j], at, em);
+                    }
+                } else {
 #pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    if (kb + j < n_band) {
-                        const double tau = kv[j] * ds;
-                        const double em = expm1(-tau);
-                        const double F = (tau == 0.0) ? 1.0 : -em / tau;
-                        I[j] = I[j] * (1.0 + em) + ev[j] * ds * F;
+                    for (int j = 0; j < PPT; ++j) {
+                        if (kb + j < n_band) {
+                            const double tau = kv[j] * ds;
+                            const double em = expm1(-tau);
+                            const double F = (tau == 0.0) ? 1.0 : -em / tau;
+                            I[j] = I[j] * (1.0 + em) + ev[j] * ds * F;
+                        }
                     }
                 }
             }
-        }
+        };
+        if (vec)
+            cell_march(std::true_type{});
+        else
+            cell_march(std::false_type{});
     } else {
         // previous node (the far node of the next segment)
         T pe[PPT], pk[PPT];
@@ -200,7 +215,8 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
             const int32_t c = rays.cell[m];
             const double ds = rays.ds[m];
             T ev[PPT], kv[PPT];
-            load_row<PPT, T>(eta, kap, (int64_t)c * n_band + kb, kb, n_band, vec, ev, kv);
+            load_row<PPT, T>(eta + (int64_t)c * n_band, kap + (int64_t)c * n_band, (uint32_t)kb, ob, n_band, vec,
+                             ev, kv);
             const int32_t ee = FP32 ? escale[2 * c + 0] : 0, ek = FP32 ? escale[2 * c + 1] : 0;
             if (m == m0)
                 segment(ev, kv, ee, ek, ev, ee, 0.5 * ds);             // far end -> first midpoint
