@@ -148,6 +148,7 @@ __global__ __launch_bounds__(kMarchThreads) void march_kernel(
         const double *ds_m = rays.ds + m0;
         const int32_t n_seg = (int32_t)(m1 - m0);
         auto cell_march = [&](auto vec_c) {
+#pragma unroll 2
             for (int32_t i = 0; i < n_seg; ++i) {
                 const int32_t c = cell_m[i];
                 const double ds = ds_m[i];
