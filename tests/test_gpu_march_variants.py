@@ -157,3 +157,54 @@ def test_march_variant_arguments(torch_dev):
     with pytest.raises(lrt.LrtError):
         ctx.set_far_temperature(-1.0)
     ctx.close()
+
+
+def test_march_optical_depth_range(torch_dev):
+    """The cell-constant march over segment optical depths from 1e-9 to 50,
+    exactly zero, slightly negative, and on both sides of tau = 0.1 (where the
+    single-precision F(tau) switches from its Taylor series to the direct
+    form), with per-cell power-of-two scales from 2^-90 to 2^40: the wall
+    intensity of every ray against the oracle's march through the same
+    coefficients (the scaled floats taken exactly)."""
+    torch = torch_dev
+    wl = synth.slab_equilibrium(n_cells=8, n_lines_per_species=10, n_points=1000, band_points=1000,
+                                n_mu=3, seed=5)
+    ctx = lrt.Context(0).load(wl)
+    sz = ctx.sizes()
+    n, nc = ctx.band_len(0), sz["n_cells"]
+    assert nc == 8 and n == 1000
+    dx = np.asarray(wl.geometry.dx, np.float64)
+    # optical depth of each cell's segment on the wall-normal ray
+    tau = np.geomspace(1e-9, 50.0, n)
+    tau[::97] = 0.0
+    tau[5:11] = 0.1 * (1.0 + np.array([-1e-6, -1e-7, 0.0, 1e-7, 1e-6, 1e-3]))
+    tau[20:23] = [-0.03, -2e-5, -1e-8]
+    mult = np.array([1.0, 0.5, 2.0, 1e-3, 10.0, 1.0, 0.1, 3.0])
+    kap = tau[None, :] * mult[:, None] / dx[:, None]
+    rng = np.random.Generator(np.random.PCG64(77))
+    eta = 10.0 ** rng.uniform(-3, 3, (nc, n))
+    ese = np.array([0, -90, 40, 0, 7, -3, 0, 12])
+    esk = np.array([0, -30, 10, 3, 0, -8, 1, 0])
+    eta_s = (eta * 2.0 ** -ese[:, None]).astype(np.float32)
+    kap_s = (kap * 2.0 ** -esk[:, None]).astype(np.float32)
+    e_ref = eta_s.astype(np.float64) * 2.0 ** ese[:, None]
+    k_ref = kap_s.astype(np.float64) * 2.0 ** esk[:, None]
+    rays, _, _ = O.slab_rays(wl.geometry)
+    I_ref = np.array([O.march(c, ds, e_ref, k_ref) for c, ds in rays])
+    for prec in PRECS:
+        if prec == lrt.LRT_FP32_COMP:
+            eta_d, kap_d = torch.from_numpy(eta_s).cuda(), torch.from_numpy(kap_s).cuda()
+            esc = torch.from_numpy(np.stack([ese, esk], axis=1).astype(np.int32)).cuda()
+        else:
+            eta_d, kap_d, esc = torch.from_numpy(e_ref).cuda(), torch.from_numpy(k_ref).cuda(), None
+        I = torch.zeros((sz["n_rays"], n), dtype=torch.float64, device="cuda:0")
+        Ii = torch.zeros(sz["n_rays"], dtype=torch.float64, device="cuda:0")
+        ctx.march(0, prec, eta_d, kap_d, esc, I, Ii)
+        torch.cuda.synchronize()
+        got = I.cpu().numpy()
+        e = normwise(got, I_ref)
+        big = np.abs(I_ref) >= 1e-3 * np.max(np.abs(I_ref), axis=-1, keepdims=True)
+        pw = float(np.max(np.abs(got - I_ref)[big] / np.abs(I_ref)[big]))
+        say("  optical-depth sweep prec %d: normwise %.3e pointwise %.3e" % (prec, e, pw))
+        assert e <= TOL[prec] and pw <= TOL[prec]
+    ctx.close()
