@@ -144,14 +144,20 @@ struct PairF64 {
     double se, sk;        // eta and kappa per unit profile shape (strength * norm)
     double inv2g, r;      // 1 / (2 gamma_V), gamma_L / gamma_V
     int32_t klo, khi;     // inclusive window, klo > khi when empty
-    int32_t kclo, kchi;   // core: points with |nu_k - nu0| <= 25 gamma_V (x <= 12.5)
+    int32_t kclo, kchi;   // core: points with |nu_k - nu0| <= kCoreHalfWidth gamma_V
 };
 
-// Half-width of the core in units of gamma_V.  Beyond it x = |dnu|/(2 gamma_V)
-// > 12.5, where e^{-2.772 x^2} (< 2^-620) and e^{-0.4 x^2.25} (< 2^-169) are
-// exactly zero in single precision, so the profile reduces to its two
-// rational terms.
-constexpr double kCoreHalfWidth = 25.0;
+// Half-width of the single-precision core in units of gamma_V, where the
+// profile's two exponential terms are evaluated.  Beyond it x = |dnu|/(2
+// gamma_V) > 6, and with the staged normalisation s = max(r, 2^-40) the
+// exponential part (1-r)/s e^{-2.772 x^2} + 0.016 r(1-r)/s e^{-0.4 x^2.25}
+// is below 5.1e-32 + 2.7e-12, while the rational part 1/(1+4x^2) -
+// 0.016(1-r)/(1+0.1 x^2.25) is at least 4.48e-3 (both ratios fall with x):
+// the omitted part is below 2^-30 of the term, under a quarter of the
+// single-precision rounding of the term itself.  (At 25 gamma_V both
+// exponentials are exactly zero in single precision; the narrower core
+// halves the terms that evaluate them.)
+constexpr double kCoreHalfWidth = 12.0;
 
 // The cell's row of ln departures from Boltzmann (QSS-CR populations), or
 // NULL when no line has levels.
