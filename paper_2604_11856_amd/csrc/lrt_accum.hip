@@ -638,8 +638,8 @@ __device__ __forceinline__ void line_terms(const RecF32 &qr, int t, const float 
         if (!((m_in[j] >> t) & 1u)) continue;      // slice outside the window
         float d1, pw;
         float P = shape_rational_f32(kf[j], q, K, d1, pw);
-        // Within 25 HWHM of the centre the exponentials contribute;
-        // beyond it they are exactly zero in single precision.  Both
+        // Within kCoreHalfWidth gamma_V of the centre the exponentials
+        // contribute; beyond it they are below 2^-30 of the term.  Both
         // conditions are wave-uniform; the empty asm keeps them real
         // scalar branches instead of computing both sides and selecting.
         if ((m_core[j] >> t) & 1u) {
